@@ -1,0 +1,170 @@
+/*
+ * swx.h -- MI355X (gfx950) Smith-Waterman-Gotoh alignment library, C ABI.
+ *
+ * What it computes (paper: "SSW Library: An SIMD Smith-Waterman C/C++ Library
+ * for Use in Genomic Applications"; Introduction and method section
+ * "Algorithm and implementation"): the optimal local alignment of a query
+ * against a reference under a substitution matrix and affine gaps,
+ *
+ *   H(i,j) = max(0, H(i-1,j-1) + S(q_i, r_j), E(i,j), F(i,j))
+ *   E(i,j) = max(E(i,j-1) - e, H(i,j-1) - o)   gap consuming reference (D)
+ *   F(i,j) = max(F(i-1,j) - e, H(i-1,j) - o)   gap consuming query     (I)
+ *
+ * so a gap of length k costs o + (k-1)*e.  The Results section's API
+ * description fixes the outputs: the optimal score, its end and begin on the
+ * query and the reference, the detailed alignment (CIGAR), and the score and
+ * end of the best suboptimal alignment, obtained as in the method section:
+ * a per-column "max" array gives the end, a reversed pass from the end gives
+ * the begin, a banded pass between begin and end gives the CIGAR, and the max
+ * array with the primary alignment's region masked gives the second score.
+ *
+ * Ties (the paper leaves them open; every build of this library resolves them
+ * the same way, so results are deterministic and independent of lane width,
+ * batching or scheduling):
+ *   end     smallest reference position, then smallest query position, among
+ *           cells scoring score1;
+ *   begin   among begins from which an alignment reaches that end with score
+ *           score1: largest reference position, then largest query position;
+ *   CIGAR   traceback of the global 3-state DP on [begin, end] preferring
+ *           M, then D, then I, and inside a gap "open" before "extend";
+ *   score2  largest max-array value outside columns
+ *           [ref_begin1 - mask_len, ref_end1 + mask_len]; ref_end2 is its
+ *           smallest column; mask_len < 0 selects max(qlen/2, 15).
+ *   score1 == 0 means "no alignment": every coordinate is -1.
+ *
+ * Conventions: sequences are int8 symbol codes in [0, n); the matrix is
+ * row-major n x n int8 indexed [query symbol][reference symbol]; gap_open and
+ * gap_extend are positive magnitudes with gap_open >= gap_extend >= 0.
+ * Coordinates are 0-based and inclusive.  CIGAR words are (length << 4) | op
+ * with op 0 = M, 1 = I (consumes query), 2 = D (consumes reference), as in SAM.
+ *
+ * Errors: every call returns SWX_OK (0) or a negative status; no exception
+ * crosses the ABI.  swx_last_error() returns a message for the calling
+ * thread's last failure.  Inputs are validated before any alignment work; a
+ * rejected call leaves outputs untouched.
+ *
+ * Threads: a context serialises its own calls; use one context per thread for
+ * concurrency.  Profiles are immutable after creation and may be shared by
+ * threads that use the same context.
+ */
+#ifndef SWX_H
+#define SWX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define SWX_OK         0
+#define SWX_EINVAL    -1   /* bad argument: null pointer, symbol >= n, o < e, n > 32, ... */
+#define SWX_ENOMEM    -2   /* host or device allocation failed */
+#define SWX_EDEVICE   -3   /* a HIP call failed (message in swx_last_error) */
+#define SWX_EBUSY     -4   /* serving: admission refused (non-blocking submit) */
+#define SWX_EOVERFLOW -5   /* a score could exceed the 32-bit lanes (query*max score >= 2^26) */
+#define SWX_ERANGE    -6   /* caller's CIGAR arena too small; cigar_used holds the size needed */
+#define SWX_EINTERNAL -7   /* an internal consistency check failed (a bug: please report) */
+
+/* ---- flags --------------------------------------------------------------- */
+#define SWX_BEGIN   1u     /* compute read_begin1 / ref_begin1 (reversed pass) */
+#define SWX_CIGAR   2u     /* compute the CIGAR (banded pass); implies SWX_BEGIN */
+#define SWX_SCORE2  4u     /* compute score2 / ref_end2; implies SWX_BEGIN */
+#define SWX_ALL     7u
+
+#define SWX_MEM_HOST   0u  /* buffers are host memory */
+#define SWX_MEM_DEVICE 1u  /* buffers are device memory of the context's GPU */
+
+typedef struct swx_ctx swx_ctx;
+typedef struct swx_profile swx_profile;
+
+/* One alignment result (56 bytes).  In batch output, cigar_off indexes the
+ * batch's CIGAR arena; cigar_len is the number of CIGAR words. */
+typedef struct {
+  int32_t score1, score2;
+  int32_t read_begin1, read_end1;
+  int64_t ref_begin1, ref_end1, ref_end2;
+  int64_t cigar_off;
+  int32_t cigar_len;
+  int32_t lane_bits;   /* lane width that produced the result (16 or 32); diagnostic only */
+} swx_rec;
+
+/* Single-pair result: the record plus a CIGAR owned by the result
+ * (release with swx_result_free). */
+typedef struct {
+  swx_rec rec;
+  uint32_t *cigar;
+} swx_result;
+
+/* ---- context --------------------------------------------------------------
+ * device: HIP device ordinal.  The context owns a stream and a device memory
+ * pool that grows on demand and is reused across calls. */
+int swx_ctx_create(int device, swx_ctx **out);
+int swx_ctx_destroy(swx_ctx *ctx);
+
+/* ---- profiles (method section: the query profile built once per query) ----
+ * query: host codes [qlen], qlen >= 1.  matrix: host n x n, 1 <= n <= 32.
+ * The profile copies everything it needs; the caller keeps ownership of its
+ * buffers.  Errors: SWX_EINVAL (nulls, qlen < 1, n out of range, symbol >= n,
+ * gap_open < gap_extend, gap_extend < 0, gap_open > 32767). */
+int swx_profile_create(swx_ctx *ctx, const int8_t *query, int32_t qlen, const int8_t *matrix,
+                       int32_t n, int32_t gap_open, int32_t gap_extend, swx_profile **out);
+int swx_profile_destroy(swx_profile *p);
+
+/* ---- one pair --------------------------------------------------------------
+ * ref: [rlen] codes in host memory, or device memory when flags has
+ * SWX_REF_DEVICE.  rlen == 0 is valid and yields "no alignment".  Synchronous:
+ * returns when out is filled.  out->cigar is malloc'd by the library (NULL when
+ * the CIGAR was not requested or is empty). */
+#define SWX_REF_DEVICE (1u << 8)
+int swx_align(const swx_profile *p, const int8_t *ref, int64_t rlen, uint32_t flags,
+              int32_t mask_len, swx_result *out);
+void swx_result_free(swx_result *r);
+
+/* ---- many pairs ------------------------------------------------------------
+ * Queries and references are concatenated code arrays with offsets
+ * (qoff[nq+1], roff[nr+1], non-decreasing, within [0, qcat_len] and
+ * [0, rcat_len]); pair k aligns query pair_q[k] against reference pair_r[k].
+ * in_mem says where qcat/qoff/rcat/roff/pair_q/pair_r live; matrix is always
+ * host memory. */
+typedef struct {
+  const int8_t *matrix; int32_t n; int32_t gap_open; int32_t gap_extend;
+  const int8_t *qcat; int64_t qcat_len; const int64_t *qoff; int64_t nq;
+  const int8_t *rcat; int64_t rcat_len; const int64_t *roff; int64_t nr;
+  const int64_t *pair_q; const int64_t *pair_r; int64_t npairs;
+  uint32_t flags;      /* SWX_BEGIN | SWX_CIGAR | SWX_SCORE2 */
+  int32_t mask_len;    /* < 0: max(qlen/2, 15) per pair */
+  uint32_t in_mem;     /* SWX_MEM_HOST or SWX_MEM_DEVICE */
+} swx_batch;
+
+/* Output of a batch.  recs [npairs] and cigar [cigar_cap] are caller-owned and
+ * live in out_mem.  On SWX_ERANGE the records are complete but the CIGARs did
+ * not fit: cigar_used holds the number of words needed. */
+typedef struct {
+  swx_rec *recs;
+  uint32_t *cigar;
+  int64_t cigar_cap;
+  int64_t cigar_used;  /* out */
+  uint32_t out_mem;
+} swx_batch_out;
+
+/* Aligns every pair.  Synchronous with respect to the host. */
+int swx_align_batch(swx_ctx *ctx, const swx_batch *b, swx_batch_out *out);
+
+/* Upper bound on CIGAR words for a batch: sum over pairs of qlen + rlen + 1
+ * (host-memory batches only; returns -1 otherwise). */
+int64_t swx_cigar_bound(const swx_batch *b);
+
+/* ---- diagnostics ------------------------------------------------------------ */
+const char *swx_strerror(int status);
+const char *swx_last_error(void);
+/* Device time in milliseconds of each stage of the last batch on ctx, in the
+ * order: prepare, fill, rerun32, reverse, traceback, score2, records.
+ * Returns the number of stages written (at most cap). */
+int swx_last_stage_ms(const swx_ctx *ctx, double *ms, int cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SWX_H */

@@ -1,0 +1,291 @@
+"""ctypes declarations of the C ABI in include/swx.h, plus a small Context
+wrapper.  Argument marshalling only: no alignment arithmetic happens here."""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libswx.so"
+_lock = threading.Lock()
+_lib = None
+
+SWX_OK = 0
+SWX_BEGIN = 1
+SWX_CIGAR = 2
+SWX_SCORE2 = 4
+SWX_ALL = 7
+SWX_MEM_HOST = 0
+SWX_MEM_DEVICE = 1
+SWX_REF_DEVICE = 1 << 8
+SWX_ERANGE = -6
+
+REC_DTYPE = np.dtype([
+    ("score1", "<i4"), ("score2", "<i4"), ("read_begin1", "<i4"), ("read_end1", "<i4"),
+    ("ref_begin1", "<i8"), ("ref_end1", "<i8"), ("ref_end2", "<i8"), ("cigar_off", "<i8"),
+    ("cigar_len", "<i4"), ("lane_bits", "<i4")])
+assert REC_DTYPE.itemsize == 56
+
+
+class SwxRec(ctypes.Structure):
+    _fields_ = [("score1", ctypes.c_int32), ("score2", ctypes.c_int32),
+                ("read_begin1", ctypes.c_int32), ("read_end1", ctypes.c_int32),
+                ("ref_begin1", ctypes.c_int64), ("ref_end1", ctypes.c_int64),
+                ("ref_end2", ctypes.c_int64), ("cigar_off", ctypes.c_int64),
+                ("cigar_len", ctypes.c_int32), ("lane_bits", ctypes.c_int32)]
+
+
+class SwxResult(ctypes.Structure):
+    _fields_ = [("rec", SwxRec), ("cigar", ctypes.POINTER(ctypes.c_uint32))]
+
+
+class SwxBatch(ctypes.Structure):
+    _fields_ = [("matrix", ctypes.c_void_p), ("n", ctypes.c_int32),
+                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32),
+                ("qcat", ctypes.c_void_p), ("qcat_len", ctypes.c_int64),
+                ("qoff", ctypes.c_void_p), ("nq", ctypes.c_int64),
+                ("rcat", ctypes.c_void_p), ("rcat_len", ctypes.c_int64),
+                ("roff", ctypes.c_void_p), ("nr", ctypes.c_int64),
+                ("pair_q", ctypes.c_void_p), ("pair_r", ctypes.c_void_p),
+                ("npairs", ctypes.c_int64), ("flags", ctypes.c_uint32),
+                ("mask_len", ctypes.c_int32), ("in_mem", ctypes.c_uint32)]
+
+
+class SwxBatchOut(ctypes.Structure):
+    _fields_ = [("recs", ctypes.c_void_p), ("cigar", ctypes.c_void_p),
+                ("cigar_cap", ctypes.c_int64), ("cigar_used", ctypes.c_int64),
+                ("out_mem", ctypes.c_uint32)]
+
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "swx_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "swx_ctx_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "swx_profile_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "swx_profile_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "swx_align": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                 ctypes.c_uint32, ctypes.c_int32, ctypes.POINTER(SwxResult)]),
+    "swx_result_free": (None, [ctypes.POINTER(SwxResult)]),
+    "swx_align_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxBatch),
+                                       ctypes.POINTER(SwxBatchOut)]),
+    "swx_cigar_bound": (ctypes.c_int64, [ctypes.POINTER(SwxBatch)]),
+    "swx_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "swx_last_error": (ctypes.c_char_p, []),
+    "swx_last_stage_ms": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.c_int]),
+}
+EXPORTED = tuple(_SIGS)
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, _LIB_NAME)
+
+
+def lib():
+    """Load libswx.so (built in-tree by build.py).  Raises when it is missing."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            path = lib_path()
+            if not os.path.exists(path):
+                raise RuntimeError(
+                    f"{path} is missing: build it with `python -m paper_1208_6350_amd.build` "
+                    "(there is no CPU fallback)")
+            L = ctypes.CDLL(path)
+            for name, (res, args) in _SIGS.items():
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = L
+    return _lib
+
+
+class SwxError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        detail = lib().swx_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {lib().swx_strerror(status).decode()} ({status}): {detail}")
+
+
+def _check(status: int, where: str):
+    if status != SWX_OK:
+        raise SwxError(status, where)
+
+
+# ---- raw C entry points, same names as the header ---------------------------
+def swx_ctx_create(device: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().swx_ctx_create(int(device), ctypes.byref(h)), "swx_ctx_create")
+    return h.value
+
+
+def swx_ctx_destroy(ctx: int) -> None:
+    _check(lib().swx_ctx_destroy(ctx), "swx_ctx_destroy")
+
+
+def swx_profile_create(ctx: int, query, matrix, gap_open: int, gap_extend: int) -> int:
+    q = np.ascontiguousarray(query, dtype=np.int8)
+    m = np.ascontiguousarray(matrix, dtype=np.int8)
+    h = ctypes.c_void_p()
+    _check(lib().swx_profile_create(ctx, q.ctypes.data, len(q), m.ctypes.data, int(m.shape[0]),
+                                    int(gap_open), int(gap_extend), ctypes.byref(h)),
+           "swx_profile_create")
+    return h.value
+
+
+def swx_profile_destroy(p: int) -> None:
+    _check(lib().swx_profile_destroy(p), "swx_profile_destroy")
+
+
+def decode_cigar(words) -> list:
+    ops = "MID"
+    return [(int(w) >> 4, ops[int(w) & 0xF]) for w in words]
+
+
+def swx_align(profile: int, ref, flags: int = SWX_ALL, mask_len: int = -1):
+    """Align one reference (numpy int8, or a device pointer with its length as a
+    tuple (ptr, rlen) and flags | SWX_REF_DEVICE).  Returns (record dict, cigar list)."""
+    res = SwxResult()
+    if isinstance(ref, tuple):
+        ptr, rlen = ref
+        st = lib().swx_align(profile, ctypes.c_void_p(ptr), int(rlen), int(flags),
+                             int(mask_len), ctypes.byref(res))
+    else:
+        r = np.ascontiguousarray(ref, dtype=np.int8)
+        st = lib().swx_align(profile, r.ctypes.data if len(r) else None, len(r), int(flags),
+                             int(mask_len), ctypes.byref(res))
+    _check(st, "swx_align")
+    rec = {k: getattr(res.rec, k) for k, _ in SwxRec._fields_}
+    cig = [res.cigar[k] for k in range(res.rec.cigar_len)] if res.rec.cigar_len else []
+    lib().swx_result_free(ctypes.byref(res))
+    return rec, decode_cigar(cig)
+
+
+def swx_result_free(res) -> None:
+    lib().swx_result_free(ctypes.byref(res))
+
+
+def swx_strerror(status: int) -> str:
+    return lib().swx_strerror(int(status)).decode()
+
+
+def swx_last_error() -> str:
+    return lib().swx_last_error().decode(errors="replace")
+
+
+def swx_last_stage_ms(ctx: int, cap: int = 8) -> list:
+    buf = (ctypes.c_double * cap)()
+    n = lib().swx_last_stage_ms(ctx, buf, cap)
+    if n < 0:
+        raise SwxError(n, "swx_last_stage_ms")
+    return [buf[k] for k in range(n)]
+
+
+def _ptr(x):
+    """Address of a numpy array or a torch tensor (host or device)."""
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    return x.ctypes.data
+
+
+def _make_batch(matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r, flags, mask_len, in_mem):
+    m = np.ascontiguousarray(matrix, dtype=np.int8)
+    b = SwxBatch()
+    b.matrix = m.ctypes.data
+    b.n = int(m.shape[0])
+    b.gap_open = int(o)
+    b.gap_extend = int(e)
+    b.qcat = _ptr(qcat)
+    b.qcat_len = int(qcat.numel() if hasattr(qcat, "numel") else len(qcat))
+    b.qoff = _ptr(qoff)
+    b.nq = int((qoff.numel() if hasattr(qoff, "numel") else len(qoff)) - 1)
+    b.rcat = _ptr(rcat)
+    b.rcat_len = int(rcat.numel() if hasattr(rcat, "numel") else len(rcat))
+    b.roff = _ptr(roff)
+    b.nr = int((roff.numel() if hasattr(roff, "numel") else len(roff)) - 1)
+    b.pair_q = _ptr(pair_q)
+    b.pair_r = _ptr(pair_r)
+    b.npairs = int(pair_q.numel() if hasattr(pair_q, "numel") else len(pair_q))
+    b.flags = int(flags)
+    b.mask_len = int(mask_len)
+    b.in_mem = int(in_mem)
+    return b, m
+
+
+def swx_cigar_bound(matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r) -> int:
+    arrs = [np.ascontiguousarray(x, dtype=np.int64) for x in (qoff, roff, pair_q, pair_r)]
+    qc = np.ascontiguousarray(qcat, dtype=np.int8)
+    rc = np.ascontiguousarray(rcat, dtype=np.int8)
+    b, _m = _make_batch(matrix, o, e, qc, arrs[0], rc, arrs[1], arrs[2], arrs[3], 0, -1,
+                        SWX_MEM_HOST)
+    return int(lib().swx_cigar_bound(ctypes.byref(b)))
+
+
+def swx_align_batch(ctx: int, matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r,
+                    flags=SWX_ALL, mask_len=-1, in_mem=SWX_MEM_HOST, recs=None, cigar=None,
+                    out_mem=SWX_MEM_HOST):
+    """Raw batch call.  Host-memory inputs are numpy arrays; device-memory
+    inputs are torch tensors.  recs/cigar are caller-owned outputs (numpy
+    structured array of REC_DTYPE and uint32 array on the host, or torch
+    tensors on the device).  Returns (status, cigar_used)."""
+    b, _m = _make_batch(matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r, flags, mask_len,
+                        in_mem)
+    out = SwxBatchOut()
+    out.recs = _ptr(recs)
+    out.cigar = _ptr(cigar)
+    out.cigar_cap = int(cigar.numel() if hasattr(cigar, "numel") else
+                        (len(cigar) if cigar is not None else 0))
+    out.out_mem = int(out_mem)
+    st = lib().swx_align_batch(ctx, ctypes.byref(b), ctypes.byref(out))
+    return st, int(out.cigar_used)
+
+
+class Context:
+    """One library context (device stream + memory pool)."""
+
+    def __init__(self, device: int = 0):
+        self.handle = swx_ctx_create(device)
+
+    def close(self):
+        if self.handle:
+            swx_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stage_ms(self):
+        return swx_last_stage_ms(self.handle)
+
+    def align_pair(self, query, ref, matrix, o, e, flags=SWX_ALL, mask_len=-1):
+        p = swx_profile_create(self.handle, query, matrix, o, e)
+        try:
+            return swx_align(p, ref, flags, mask_len)
+        finally:
+            swx_profile_destroy(p)
+
+    def align_batch(self, matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r,
+                    flags=SWX_ALL, mask_len=-1):
+        """Host-memory batch: returns (records [REC_DTYPE], cigar words)."""
+        qcat = np.ascontiguousarray(qcat, dtype=np.int8)
+        rcat = np.ascontiguousarray(rcat, dtype=np.int8)
+        qoff, roff, pair_q, pair_r = (np.ascontiguousarray(x, dtype=np.int64)
+                                      for x in (qoff, roff, pair_q, pair_r))
+        npairs = len(pair_q)
+        recs = np.zeros(npairs, dtype=REC_DTYPE)
+        cap = swx_cigar_bound(matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r)
+        cig = np.zeros(max(cap, 1), dtype=np.uint32)
+        st, used = swx_align_batch(self.handle, matrix, o, e, qcat, qoff, rcat, roff, pair_q,
+                                   pair_r, flags, mask_len, SWX_MEM_HOST, recs, cig, SWX_MEM_HOST)
+        _check(st, "swx_align_batch")
+        return recs, cig[:used]

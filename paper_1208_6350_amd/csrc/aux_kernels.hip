@@ -1,0 +1,471 @@
+// aux_kernels.hip -- the steps of the method after the forward fill:
+//   * pair views (forward, and reversed prefixes for the begin search),
+//   * the banded global DP and traceback that produce the CIGAR
+//     (method section: "the banded SW (whose band is defined by the beginning
+//     and ending positions) generates the detailed alignment"),
+//   * the suboptimal score from the masked max array (method section, (2);
+//     Figure 1 caption),
+//   * CIGAR compaction and result records.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include "swx_internal.h"
+#include "swx_kernels.h"
+
+namespace swx {
+
+// ---- pair views -----------------------------------------------------------
+__global__ void k_views(int64_t npairs, const int64_t *qoff, const int64_t *roff,
+                        const int64_t *pair_q, const int64_t *pair_r,
+                        int64_t *qstart, int32_t *qlen, int64_t *rstart, int64_t *rlen) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const int64_t qi = pair_q[p], ri = pair_r[p];
+  qstart[p] = qoff[qi];
+  qlen[p] = (int32_t)(qoff[qi + 1] - qoff[qi]);
+  rstart[p] = roff[ri];
+  rlen[p] = roff[ri + 1] - roff[ri];
+}
+
+// Reversed prefixes q[0..qend] and r[0..rend] (read backwards by the fill).
+__global__ void k_rev_views(int64_t npairs, const int64_t *qstart, const int64_t *rstart,
+                            const int32_t *qlen, const int64_t *rlen,
+                            const int32_t *score, const int32_t *qend, const int64_t *rend,
+                            int64_t *rqstart, int32_t *rqlen, int64_t *rrstart, int64_t *rrlen,
+                            int32_t *target, uint8_t *err) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  bool ok = score[p] > 0;
+  if (ok && (qend[p] < 0 || qend[p] >= qlen[p] || rend[p] < 0 || rend[p] >= rlen[p])) {
+    err[p] = 1;   // an end outside the pair: never read past the sequences
+    ok = false;
+  }
+  rqstart[p] = qstart[p];
+  rrstart[p] = rstart[p];
+  rqlen[p] = ok ? qend[p] + 1 : 0;
+  rrlen[p] = ok ? rend[p] + 1 : 0;
+  target[p] = ok ? score[p] : 0;
+}
+
+// ---- banded global DP and traceback (one thread per pair) ------------------
+// Safe band: with m = qend-qbeg+1, w = rend-rbeg+1, D = w - m and
+//   G = floor((smax*(m+w) - 2o + 2e - 2*score1) / (smax + 2e)),
+// every path of score score1 has at most G gap symbols, so it stays on the
+// diagonals min(0,D) - hw .. max(0,D) + hw with hw = floor((G - |D|)/2).
+// Inside the band the DP values on such paths equal the unbanded ones, so the
+// traceback (rule T3: M, then D, then I; open before extend) is the same.
+__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+  return q;
+}
+
+__device__ __forceinline__ void band_of(int64_t m, int64_t w, int64_t score1, int32_t smax,
+                                        int32_t o, int32_t e, int64_t *dlo, int64_t *dhi) {
+  const int64_t D = w - m;
+  const int64_t num = (int64_t)smax * (m + w) - 2 * o + 2 * e - 2 * score1;
+  const int64_t den = (int64_t)smax + 2 * e;
+  const int64_t G = den > 0 ? floor_div(num, den) : (m + w);
+  const int64_t aD = D < 0 ? -D : D;
+  int64_t hw = (G - aD) >= 0 ? (G - aD) / 2 : 0;
+  *dlo = (D < 0 ? D : 0) - hw;
+  *dhi = (D > 0 ? D : 0) + hw;
+}
+
+__device__ __forceinline__ bool coords_ok(int64_t p, const int32_t *qbeg, const int32_t *qend,
+                                          const int64_t *rbeg, const int64_t *rend,
+                                          const int32_t *qlen, const int64_t *rlen) {
+  return qbeg[p] >= 0 && qbeg[p] <= qend[p] && qend[p] < qlen[p] && rbeg[p] >= 0 &&
+         rbeg[p] <= rend[p] && rend[p] < rlen[p];
+}
+
+__global__ void k_band_sizes(int64_t npairs, const int32_t *score, const int32_t *qbeg,
+                             const int32_t *qend, const int64_t *rbeg, const int64_t *rend,
+                             const int32_t *qlen, const int64_t *rlen, int32_t smax, int32_t o, int32_t e, int64_t *dir_size,
+                             int64_t *cig_cap, int64_t *row_cap) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  if (score[p] <= 0 || !coords_ok(p, qbeg, qend, rbeg, rend, qlen, rlen)) {
+    dir_size[p] = 0; cig_cap[p] = 0; row_cap[p] = 0; return;
+  }
+  const int64_t m = qend[p] - qbeg[p] + 1, w = rend[p] - rbeg[p] + 1;
+  int64_t dlo, dhi;
+  band_of(m, w, score[p], smax, o, e, &dlo, &dhi);
+  const int64_t bw = dhi - dlo + 1;
+  dir_size[p] = (m + 1) * bw;
+  cig_cap[p] = m + w + 2;
+  row_cap[p] = bw + 2;
+}
+
+
+
+constexpr int32_t kNegInf = -(1 << 29);
+
+__global__ void k_band_tb(BandArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.npairs) return;
+  const int32_t s1 = a.score[p];
+  if (s1 <= 0) { a.cig_len[p] = 0; return; }
+  if (!coords_ok(p, a.qbeg, a.qend, a.rbeg, a.rend, a.qlen, a.rlen)) {
+    a.cig_len[p] = 0;
+    a.err[p] = 1;
+    return;
+  }
+  const int64_t qb = a.qbeg[p], qe = a.qend[p], rb = a.rbeg[p], re = a.rend[p];
+  const int64_t m = qe - qb + 1, w = re - rb + 1;
+  int64_t dlo, dhi;
+  band_of(m, w, s1, a.smax, a.o, a.e, &dlo, &dhi);
+  const int64_t bw = dhi - dlo + 1;
+  uint8_t *dir = a.dir + a.dir_off[p];
+  int32_t *hrow = a.rowbuf + 2 * a.row_off[p];      // H of the previous row, by band index
+  int32_t *frow = hrow + (bw + 2);                   // F of the previous row
+  const int8_t *q = a.qcat + a.qstart[p] + qb;
+  const int8_t *r = a.rcat + a.rstart[p] + rb;
+  const int32_t o = a.o, e = a.e;
+  // band index k = j - i - dlo; row i covers j in [max(0, i+dlo), min(w, i+dhi)]
+  // row 0
+  for (int64_t k = 0; k < bw; ++k) { hrow[k] = kNegInf; frow[k] = kNegInf; }
+  {
+    int32_t ev = kNegInf;
+    const int64_t jhi = dhi < w ? dhi : w;
+    for (int64_t j = 0; j <= jhi; ++j) {
+      const int64_t k = j - dlo;
+      if (j == 0) { hrow[k] = 0; dir[k] = 0; continue; }
+      const int32_t open = hrow[k - 1] - o, ext = ev - e;
+      ev = open > ext ? open : ext;
+      hrow[k] = ev;
+      dir[k] = (uint8_t)(1 | (open >= ext ? 4 : 0));
+    }
+  }
+  for (int64_t i = 1; i <= m; ++i) {
+    const int64_t jlo = (i + dlo) > 0 ? (i + dlo) : 0;
+    const int64_t jhi = (i + dhi) < w ? (i + dhi) : w;
+    uint8_t *drow = dir + i * bw;
+    int32_t ev = kNegInf;        // E(i, j-1)
+    int32_t hleft = kNegInf;     // H(i, j-1)
+    // the previous row's entries are read at band index k (diag) and k+1 (up);
+    // they are overwritten in place at index k after use
+    for (int64_t j = jlo; j <= jhi; ++j) {
+      const int64_t k = j - i - dlo;
+      const int32_t hup = (k + 1 < bw) ? hrow[k + 1] : kNegInf;
+      const int32_t fup = (k + 1 < bw) ? frow[k + 1] : kNegInf;
+      const int32_t hdg = hrow[k];
+      const int32_t fopen = hup - o, fext = fup - e;
+      const int32_t fij = fopen > fext ? fopen : fext;
+      int32_t h, c;
+      if (j == 0) {
+        h = fij;
+        c = 2 | (fopen >= fext ? 8 : 0);
+        ev = kNegInf;
+      } else {
+        const int32_t eopen = hleft - o, eext = ev - e;
+        const int32_t eij = eopen > eext ? eopen : eext;
+        const int32_t diag = hdg + a.matrix[q[i - 1] * a.n + r[j - 1]];
+        h = diag;
+        if (eij > h) h = eij;
+        if (fij > h) h = fij;
+        c = (h == diag) ? 0 : (h == eij ? 1 : 2);
+        if (eopen >= eext) c |= 4;
+        if (fopen >= fext) c |= 8;
+        ev = eij;
+      }
+      drow[k] = (uint8_t)c;
+      hrow[k] = h;
+      frow[k] = fij;
+      hleft = h;
+    }
+    // cells of the previous row outside this row's range must not leak
+    // into the next row: the next row reads indices k and k+1 for its j
+    for (int64_t k = 0; k < bw; ++k) {
+      const int64_t j = i + dlo + k;
+      if (j < jlo || j > jhi) { hrow[k] = kNegInf; frow[k] = kNegInf; }
+    }
+  }
+  // global optimum check: H(m, w)
+  const int32_t hend = hrow[w - m - dlo];
+  if (hend != s1) a.err[p] = 1;
+  // traceback from (m, w) in state H, runs written end -> begin then reversed
+  uint32_t *out = a.cig + a.cig_off[p];
+  int32_t nruns = 0;
+  int64_t i = m, j = w;
+  int state = 0;
+  uint32_t cur_op = 0xFF, cur_len = 0;
+  int64_t guard = 2 * (m + w) + 4;
+  while ((i > 0 || j > 0) && guard-- > 0) {
+    const int64_t k = j - i - dlo;
+    if (k < 0 || k >= bw) { a.err[p] = 1; break; }
+    const uint8_t c = dir[i * bw + k];
+    uint32_t op = 0xFF;
+    if (state == 0) {
+      const int src = c & 3;
+      if (src == 0 && i > 0 && j > 0) { op = 0; --i; --j; }
+      else if (src == 1) state = 1;
+      else state = 2;
+    } else if (state == 1) {
+      op = 2;
+      state = (c & 4) ? 0 : 1;
+      --j;
+    } else {
+      op = 1;
+      state = (c & 8) ? 0 : 2;
+      --i;
+    }
+    if (op != 0xFF) {
+      if (op == cur_op) ++cur_len;
+      else {
+        if (cur_len) out[nruns++] = (cur_len << 4) | cur_op;
+        cur_op = op; cur_len = 1;
+      }
+    }
+  }
+  if (cur_len) out[nruns++] = (cur_len << 4) | cur_op;
+  for (int32_t x = 0, y = nruns - 1; x < y; ++x, --y) {
+    uint32_t t = out[x]; out[x] = out[y]; out[y] = t;
+  }
+  a.cig_len[p] = nruns;
+}
+
+// ---- CIGAR compaction -----------------------------------------------------
+__global__ void k_cigar_compact(int64_t npairs, const uint32_t *src, const int64_t *src_off,
+                                const int32_t *len, const int64_t *dst_off, uint32_t *dst) {
+  const int64_t p = blockIdx.x;
+  if (p >= npairs) return;
+  const int32_t n = len[p];
+  for (int32_t k = threadIdx.x; k < n; k += blockDim.x) dst[dst_off[p] + k] = src[src_off[p] + k];
+}
+
+// ---- score2 on inter tasks (max array = final CM plane) -------------------
+
+
+__global__ __launch_bounds__(256) void k_score2_inter(Score2InterArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t tid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (tid >= a.ntasks) return;
+  const InterTask tk = a.tasks[tid];
+  const uint32_t *bC = a.bnd + tk.bnd_off + 2 * (int64_t)tk.rp * 64;
+  for (int h = 0; h < a.halves; ++h) {
+    const int s = lane + 64 * h;
+    if (s >= tk.nslots) continue;
+    const int64_t p = a.slot_pair[tk.slot_base + s];
+    if (p < 0) continue;
+    int32_t best = 0;
+    int64_t at = -1;
+    if (a.score1[p] > 0) {
+      const int64_t lr = a.rlen[p];
+      const int64_t padr = tk.rp - lr;
+      int64_t m = a.mask_len;
+      if (m < 0) { m = a.qlen[p] / 2; if (m < 15) m = 15; }
+      const int64_t lo = a.rbeg[p] - m, hi = a.rend[p] + m;
+      for (int64_t j = 0; j < lr; ++j) {
+        if (j >= lo && j <= hi) continue;
+        const uint32_t wv = bC[(j + padr) * 64 + lane];
+        const int32_t v = (a.halves == 2) ? (int32_t)(h ? (wv >> 16) : (wv & 0xFFFFu)) : (int32_t)wv;
+        if (v > best) { best = v; at = j; }
+      }
+    }
+    a.score2[p] = best;
+    a.rend2[p] = best > 0 ? at : -1;
+  }
+}
+
+// score2 on a plain per-pair max array (long pairs)
+__global__ void k_score2_plain(int64_t p, const int32_t *maxcol, int64_t lr, const int32_t *score1,
+                               const int64_t *rbeg, const int64_t *rend, int32_t mask_len,
+                               const int32_t *qlen, int32_t *score2, int64_t *rend2) {
+  __shared__ int32_t sv[256];
+  __shared__ int64_t sj[256];
+  int32_t best = 0;
+  int64_t at = INT64_MAX;
+  if (score1[p] > 0) {
+    int64_t m = mask_len;
+    if (m < 0) { m = qlen[p] / 2; if (m < 15) m = 15; }
+    const int64_t lo = rbeg[p] - m, hi = rend[p] + m;
+    for (int64_t j = threadIdx.x; j < lr; j += blockDim.x) {
+      if (j >= lo && j <= hi) continue;
+      const int32_t v = maxcol[j];
+      if (v > best) { best = v; at = j; }
+    }
+  }
+  sv[threadIdx.x] = best;
+  sj[threadIdx.x] = at;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      const int32_t v2 = sv[threadIdx.x + off];
+      const int64_t j2 = sj[threadIdx.x + off];
+      if (v2 > sv[threadIdx.x] || (v2 == sv[threadIdx.x] && j2 < sj[threadIdx.x])) {
+        sv[threadIdx.x] = v2; sj[threadIdx.x] = j2;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    score2[p] = sv[0];
+    rend2[p] = sv[0] > 0 ? sj[0] : -1;
+  }
+}
+
+// ---- result records -------------------------------------------------------
+__global__ void k_records(int64_t npairs, const int32_t *score1, const int32_t *score2,
+                          const int32_t *qbeg, const int32_t *qend, const int64_t *rbeg,
+                          const int64_t *rend, const int64_t *rend2, const int64_t *cig_off,
+                          const int32_t *cig_len, const uint8_t *lane_bits, uint32_t flags,
+                          swx_rec_dev *recs) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  swx_rec_dev r;
+  const bool ok = score1[p] > 0;
+  const bool beg = (flags & 1u) && ok;
+  r.score1 = score1[p];
+  r.score2 = (ok && (flags & 4u)) ? score2[p] : 0;
+  r.read_begin1 = beg ? qbeg[p] : -1;
+  r.read_end1 = ok ? qend[p] : -1;
+  r.ref_begin1 = beg ? rbeg[p] : -1;
+  r.ref_end1 = ok ? rend[p] : -1;
+  r.ref_end2 = (ok && (flags & 4u)) ? rend2[p] : -1;
+  r.cigar_off = (ok && (flags & 2u)) ? cig_off[p] : 0;
+  r.cigar_len = (ok && (flags & 2u)) ? cig_len[p] : 0;
+  r.lane_bits = lane_bits[p];
+  recs[p] = r;
+}
+
+// begin coordinates from the reversed pass: begin = end - reversed end
+__global__ void k_begins(int64_t npairs, const int32_t *score1, const int32_t *qend,
+                         const int64_t *rend, const int32_t *rscore, const int32_t *rqend,
+                         const int64_t *rrend, int32_t *qbeg, int64_t *rbeg, uint8_t *err) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  if (score1[p] <= 0) { qbeg[p] = -1; rbeg[p] = -1; return; }
+  if (rscore[p] != score1[p]) err[p] = 1;
+  qbeg[p] = qend[p] - rqend[p];
+  rbeg[p] = rend[p] - rrend[p];
+}
+
+// ---- input validation -------------------------------------------------------
+__global__ void k_validate(ValidateArgs a) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  uint32_t bad = 0;
+  for (int64_t k = tid; k <= a.nq; k += stride) {
+    const int64_t v = a.qoff[k];
+    if (v < 0 || v > a.qcat_len || (k > 0 && a.qoff[k - 1] > v)) bad |= 1u;
+  }
+  for (int64_t k = tid; k <= a.nr; k += stride) {
+    const int64_t v = a.roff[k];
+    if (v < 0 || v > a.rcat_len || (k > 0 && a.roff[k - 1] > v)) bad |= 1u;
+  }
+  for (int64_t k = tid; k < a.npairs; k += stride) {
+    if (a.pair_q[k] < 0 || a.pair_q[k] >= a.nq || a.pair_r[k] < 0 || a.pair_r[k] >= a.nr) bad |= 2u;
+  }
+  for (int64_t k = tid; k < a.qcat_len; k += stride) {
+    const int8_t c = a.qcat[k];
+    if (c < 0 || c >= a.n) bad |= 4u;
+  }
+  for (int64_t k = tid; k < a.rcat_len; k += stride) {
+    const int8_t c = a.rcat[k];
+    if (c < 0 || c >= a.n) bad |= 8u;
+  }
+  if (bad) atomicOr(a.bad, bad);
+}
+
+// ---- launchers --------------------------------------------------------------
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_validate(const ValidateArgs &a, hipStream_t st) {
+  const int64_t work = a.qcat_len + a.rcat_len + a.npairs + a.nq + a.nr + 2;
+  int64_t blocks = (work + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_validate, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, void *tmp,
+                                 size_t *tmp_bytes, hipStream_t st) {
+  return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, in, out, (int)n, st);
+}
+
+hipError_t launch_views(int64_t npairs, const int64_t *qoff, const int64_t *roff,
+                        const int64_t *pair_q, const int64_t *pair_r, int64_t *qstart,
+                        int32_t *qlen, int64_t *rstart, int64_t *rlen, hipStream_t st) {
+  if (!npairs) return hipSuccess;
+  hipLaunchKernelGGL(k_views, dim3(blocks_for(npairs, 256)), dim3(256), 0, st, npairs, qoff, roff,
+                     pair_q, pair_r, qstart, qlen, rstart, rlen);
+  return hipGetLastError();
+}
+
+hipError_t launch_rev_views(int64_t npairs, const int64_t *qstart, const int64_t *rstart,
+                            const int32_t *qlen, const int64_t *rlen,
+                            const int32_t *score, const int32_t *qend, const int64_t *rend,
+                            int64_t *rqstart, int32_t *rqlen, int64_t *rrstart, int64_t *rrlen,
+                            int32_t *target, uint8_t *err, hipStream_t st) {
+  if (!npairs) return hipSuccess;
+  hipLaunchKernelGGL(k_rev_views, dim3(blocks_for(npairs, 256)), dim3(256), 0, st, npairs, qstart,
+                     rstart, qlen, rlen, score, qend, rend, rqstart, rqlen, rrstart, rrlen, target,
+                     err);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_sizes(int64_t npairs, const int32_t *score, const int32_t *qbeg,
+                             const int32_t *qend, const int64_t *rbeg, const int64_t *rend,
+                             const int32_t *qlen, const int64_t *rlen,
+                             int32_t smax, int32_t o, int32_t e, int64_t *dir_size,
+                             int64_t *cig_cap, int64_t *row_cap, hipStream_t st) {
+  if (!npairs) return hipSuccess;
+  hipLaunchKernelGGL(k_band_sizes, dim3(blocks_for(npairs, 256)), dim3(256), 0, st, npairs, score,
+                     qbeg, qend, rbeg, rend, qlen, rlen, smax, o, e, dir_size, cig_cap, row_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_tb(const BandArgs &a, hipStream_t st) {
+  if (!a.npairs) return hipSuccess;
+  hipLaunchKernelGGL(k_band_tb, dim3(blocks_for(a.npairs, 64)), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_cigar_compact(int64_t npairs, const uint32_t *src, const int64_t *src_off,
+                                const int32_t *len, const int64_t *dst_off, uint32_t *dst,
+                                hipStream_t st) {
+  if (!npairs) return hipSuccess;
+  hipLaunchKernelGGL(k_cigar_compact, dim3((unsigned)npairs), dim3(64), 0, st, npairs, src,
+                     src_off, len, dst_off, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_score2_inter(const Score2InterArgs &a, hipStream_t st) {
+  if (!a.ntasks) return hipSuccess;
+  hipLaunchKernelGGL(k_score2_inter, dim3(blocks_for(a.ntasks, 4)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_score2_plain(int64_t p, const int32_t *maxcol, int64_t lr, const int32_t *score1,
+                               const int64_t *rbeg, const int64_t *rend, int32_t mask_len,
+                               const int32_t *qlen, int32_t *score2, int64_t *rend2,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_score2_plain, dim3(1), dim3(256), 0, st, p, maxcol, lr, score1, rbeg, rend,
+                     mask_len, qlen, score2, rend2);
+  return hipGetLastError();
+}
+
+hipError_t launch_records(int64_t npairs, const int32_t *score1, const int32_t *score2,
+                          const int32_t *qbeg, const int32_t *qend, const int64_t *rbeg,
+                          const int64_t *rend, const int64_t *rend2, const int64_t *cig_off,
+                          const int32_t *cig_len, const uint8_t *lane_bits, uint32_t flags,
+                          swx_rec_dev *recs, hipStream_t st) {
+  if (!npairs) return hipSuccess;
+  hipLaunchKernelGGL(k_records, dim3(blocks_for(npairs, 256)), dim3(256), 0, st, npairs, score1,
+                     score2, qbeg, qend, rbeg, rend, rend2, cig_off, cig_len, lane_bits, flags,
+                     recs);
+  return hipGetLastError();
+}
+
+hipError_t launch_begins(int64_t npairs, const int32_t *score1, const int32_t *qend,
+                         const int64_t *rend, const int32_t *rscore, const int32_t *rqend,
+                         const int64_t *rrend, int32_t *qbeg, int64_t *rbeg, uint8_t *err,
+                         hipStream_t st) {
+  if (!npairs) return hipSuccess;
+  hipLaunchKernelGGL(k_begins, dim3(blocks_for(npairs, 256)), dim3(256), 0, st, npairs, score1,
+                     qend, rend, rscore, rqend, rrend, qbeg, rbeg, err);
+  return hipGetLastError();
+}
+
+}  // namespace swx

@@ -1,0 +1,181 @@
+"""GPU parity: the HIP path against the CPU oracle, bit-exact in every field
+(score1, score2, begins, ends, ref_end2) and in the CIGAR, on seeded inputs.
+
+Every test here calls the library through the C ABI (ctypes)."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1208_6350_amd as swx
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = swx.Context(0)
+    yield c
+    c.close()
+
+
+def run_both(ctx, b: W.Batch, flags=swx.SWX_ALL, mask_len=-1, nthreads=8):
+    _say(f"[parity] {b.name}: {b.npairs} pairs, flags={flags}, mask_len={mask_len}")
+    recs, cig = ctx.align_batch(b.matrix, b.gap_open, b.gap_extend, b.qcat, b.qoff, b.rcat,
+                                b.roff, b.pair_q, b.pair_r, flags, mask_len)
+    ref, rcig, rcoff = oracle.align_many(b.qcat, b.qoff, b.rcat, b.roff, b.pair_q, b.pair_r,
+                                         b.matrix, b.gap_open, b.gap_extend, flags, mask_len,
+                                         nthreads=nthreads)
+    return recs, cig, ref, rcig, rcoff
+
+
+FIELDS = ["score1", "score2", "read_begin1", "read_end1", "ref_begin1", "ref_end1", "ref_end2"]
+
+
+def assert_parity(ctx, b, flags=swx.SWX_ALL, mask_len=-1):
+    recs, cig, ref, rcig, rcoff = run_both(ctx, b, flags, mask_len)
+    bad = []
+    for k, f in enumerate(FIELDS):
+        got = recs[f].astype(np.int64)
+        exp = ref[:, k]
+        if f == "score2" and not (flags & swx.SWX_SCORE2):
+            exp = np.zeros_like(exp)
+        if f == "ref_end2" and not (flags & swx.SWX_SCORE2):
+            exp = np.full_like(exp, -1)
+        if f in ("read_begin1", "ref_begin1") and not (flags & 7):
+            exp = np.where(ref[:, 0] > 0, -1, exp)
+        mism = np.nonzero(got != exp)[0]
+        if len(mism):
+            p = int(mism[0])
+            bad.append(f"{f}: {len(mism)} mismatches, first pair {p}: gpu {got[p]} oracle {exp[p]}")
+    assert not bad, "; ".join(bad)
+    if flags & swx.SWX_CIGAR:
+        for p in range(b.npairs):
+            g = cig[recs["cigar_off"][p]:recs["cigar_off"][p] + recs["cigar_len"][p]]
+            e = rcig[rcoff[p]:rcoff[p] + ref[p, 7]]
+            if not np.array_equal(g, e):
+                raise AssertionError(f"CIGAR mismatch at pair {p}: gpu {swx.decode_cigar(g)} "
+                                     f"oracle {swx.decode_cigar(e)}")
+    else:
+        assert (recs["cigar_len"] == 0).all()
+    return recs
+
+
+def test_random_dna_small(ctx):
+    b = W.random_pairs(101, 300, (1, 90), (0, 260))
+    recs = assert_parity(ctx, b)
+    assert (recs["score1"] > 0).sum() > 200
+
+
+def test_random_dna_gap_settings(ctx):
+    for seed, (o, e) in enumerate([(2, 1), (5, 2), (1, 1), (4, 3), (6, 0), (0, 0)]):
+        b = W.random_pairs(200 + seed, 150, (1, 70), (1, 200), o=o, e=e)
+        assert_parity(ctx, b)
+
+
+def test_random_protein_general_profile(ctx):
+    b = W.random_pairs(301, 200, (1, 100), (1, 300), alphabet=24, o=11, e=1)
+    assert_parity(ctx, b)
+
+
+def test_asymmetric_matrix_five_symbols(ctx):
+    g = np.random.Generator(np.random.PCG64(7))
+    mat = g.integers(-5, 6, size=(5, 5)).astype(np.int8)
+    b = W.random_pairs(302, 150, (1, 60), (1, 150), alphabet=5, matrix=mat, o=3, e=1)
+    assert_parity(ctx, b)
+
+
+def test_flags_and_mask(ctx):
+    b = W.random_pairs(303, 120, (5, 80), (20, 300))
+    for flags in (0, swx.SWX_BEGIN, swx.SWX_CIGAR, swx.SWX_SCORE2):
+        assert_parity(ctx, b, flags=flags)
+    for m in (0, 3, 40):
+        assert_parity(ctx, b, mask_len=m)
+
+
+def test_edge_cases(ctx):
+    mat = W.dna_matrix()
+    qs = [np.array([0], np.int8), np.array([1, 2, 3], np.int8), np.array([2] * 40, np.int8),
+          np.array([0, 1], np.int8), np.arange(64, dtype=np.int8) % 4]
+    rs = [np.array([0], np.int8), np.zeros(0, np.int8), np.array([2] * 70, np.int8),
+          np.array([3, 3, 3], np.int8), np.arange(64, dtype=np.int8) % 4]
+    b = W.from_lists("edges", mat, 3, 1, qs, rs)
+    assert_parity(ctx, b)
+    neg = np.full((4, 4), -1, np.int8)
+    b2 = W.from_lists("no-positive", neg, 3, 1, qs, rs)
+    recs = assert_parity(ctx, b2)
+    assert (recs["score1"] == 0).all() and (recs["ref_end1"] == -1).all()
+
+
+def test_lane_width_threshold(ctx):
+    """Scores around the 16-bit limit (2047): the saturated pairs are re-run
+    on 32-bit lanes and every result must equal the oracle's."""
+    g = np.random.Generator(np.random.PCG64(11))
+    mat = W.dna_matrix(8, -8)
+    qs, rs = [], []
+    for L in (250, 255, 256, 257, 258, 300, 40):
+        ref = g.integers(0, 4, size=L + 100).astype(np.int8)
+        qs.append(ref[50:50 + L].copy())
+        rs.append(ref)
+    b = W.from_lists("threshold", mat, 10, 2, qs, rs)
+    recs = assert_parity(ctx, b)
+    assert set(recs["lane_bits"]) == {16, 32}
+
+
+def test_many_tasks_ragged(ctx):
+    b = W.random_pairs(404, 700, (1, 200), (1, 500))
+    assert_parity(ctx, b)
+
+
+def test_config1_single_pair(ctx):
+    b = W.config1()
+    assert_parity(ctx, b)
+    # the single-pair entry point gives the same record
+    rec, cig = ctx.align_pair(b.query(0), b.ref(0), b.matrix, b.gap_open, b.gap_extend)
+    a = oracle.align(b.query(0), b.ref(0), b.matrix, b.gap_open, b.gap_extend)
+    assert (rec["score1"], rec["score2"], rec["read_begin1"], rec["read_end1"], rec["ref_begin1"],
+            rec["ref_end1"], rec["ref_end2"]) == (a.score1, a.score2, a.read_begin1,
+                                                  a.read_end1, a.ref_begin1, a.ref_end1,
+                                                  a.ref_end2)
+    assert cig == a.cigar
+
+
+def test_config4_sample(ctx):
+    b = W.config4(npairs=3000)
+    assert_parity(ctx, b)
+
+
+def test_config3_sample(ctx):
+    full = W.config3(ntargets=600)
+    assert_parity(ctx, full)
+
+
+def test_batch_equals_single(ctx):
+    """Each pair aligned inside a batch equals the same pair aligned alone."""
+    b = W.random_pairs(505, 40, (5, 120), (10, 300))
+    recs, cig = ctx.align_batch(b.matrix, b.gap_open, b.gap_extend, b.qcat, b.qoff, b.rcat,
+                                b.roff, b.pair_q, b.pair_r)
+    for p in range(b.npairs):
+        rec, c1 = ctx.align_pair(b.query(p), b.ref(p), b.matrix, b.gap_open, b.gap_extend)
+        for f in FIELDS:
+            assert rec[f] == recs[f][p], (p, f)
+        assert c1 == swx.decode_cigar(cig[recs["cigar_off"][p]:recs["cigar_off"][p] +
+                                          recs["cigar_len"][p]])
+
+
+def test_invalid_symbols_rejected(ctx):
+    b = W.random_pairs(606, 5, (3, 10), (3, 10))
+    b.rcat[2] = 9
+    with pytest.raises(swx.SwxError) as ei:
+        ctx.align_batch(b.matrix, b.gap_open, b.gap_extend, b.qcat, b.qoff, b.rcat, b.roff,
+                        b.pair_q, b.pair_r)
+    assert ei.value.status == -1
