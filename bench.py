@@ -1,0 +1,169 @@
+"""Benchmark: GCUPS of the whole alignment path on one MI355X.
+
+A step is one pass of the whole path -- forward fill with the max array and
+the end, exact 32-bit re-run of saturated pairs, reversed pass (begin), banded
+traceback (CIGAR), masked max array (score2) and result records -- over one
+batch of synthetic read/window pairs that are already resident in HBM.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2]
+
+Prints one JSON line.  `value` is forward-fill cells (sum of qlen*rlen over
+pairs) per second of the whole path, in GCUPS.  `roofline` reports the forward
+fill kernel against the packed 16-bit integer VALU peak; `cpu_baseline` times
+the CPU oracle on a bounded sample of the same pairs on this host's cores;
+`per_pair` times the same library called one pair at a time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Integer-VALU peak of MI355X: 256 CUs x 4 SIMD x 16 lanes = 64 lane-ops per
+# clock per CU at 2.4 GHz = 39.32 T lane-ops/s; packed 16-bit instructions do
+# two operations per lane-op: 78.64 T ops/s.
+PEAK_PK16_TOPS = 256 * 64 * 2.4e9 * 2 / 1e12
+OPS_PER_CELL = 10      # algorithmic integer operations per DP cell
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--pairs", type=int, default=1_000_000)
+    ap.add_argument("--per-pair-sample", type=int, default=200)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(b, seconds):
+    """The oracle, unmodified, over a bounded sample of the workload."""
+    import numpy as np
+
+    import oracle
+    threads = os.cpu_count() or 1
+    probe = b.subset(np.arange(min(2000, b.npairs)))
+    t = time.perf_counter()
+    oracle.align_many(probe.qcat, probe.qoff, probe.rcat, probe.roff, probe.pair_q, probe.pair_r,
+                      probe.matrix, probe.gap_open, probe.gap_extend, nthreads=threads)
+    rate = probe.cells() / max(time.perf_counter() - t, 1e-6)
+    n = int(min(b.npairs, max(2000, seconds * rate / (b.cells() / b.npairs))))
+    s = b.subset(np.arange(n))
+    t = time.perf_counter()
+    oracle.align_many(s.qcat, s.qoff, s.rcat, s.roff, s.pair_q, s.pair_r, s.matrix,
+                      s.gap_open, s.gap_extend, nthreads=threads)
+    dt = time.perf_counter() - t
+    return {"value": round(s.cells() / dt / 1e9, 4), "unit": "GCUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {n} pairs of the same workload ({s.cells()/1e9:.2f} G cells, "
+                      f"{dt:.1f} s, whole path incl. begin/CIGAR/score2)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is "
+                                   "described in DESIGN.md but not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1208_6350_amd as swx
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    b = W.config4(npairs=args.pairs)
+    print(f"[bench] generated {b.npairs} pairs in {time.perf_counter() - t0:.1f}s", flush=True,
+          file=sys.stderr)
+    cells = b.cells()
+    to = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x)).to(dev)
+    dq, dqo, dr, dro = to(b.qcat, None), to(b.qoff, None), to(b.rcat, None), to(b.roff, None)
+    dpq, dpr = to(b.pair_q, None), to(b.pair_r, None)
+    recs = torch.empty(b.npairs * swx.REC_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    cap = int(b.qlen().sum() + b.rlen().sum() + b.npairs)
+    cig = torch.empty(cap, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    ctx = swx.Context(0)
+
+    def step():
+        st, used = swx.swx_align_batch(ctx.handle, b.matrix, b.gap_open, b.gap_extend, dq, dqo,
+                                       dr, dro, dpq, dpr, swx.SWX_ALL, -1, swx.SWX_MEM_DEVICE,
+                                       recs, cig, swx.SWX_MEM_DEVICE)
+        if st != 0:
+            raise swx.SwxError(st, "swx_align_batch")
+        return used
+
+    for k in range(args.warmup):
+        step()
+        print(f"[bench] warmup {k + 1}/{args.warmup} done", flush=True, file=sys.stderr)
+    torch.cuda.synchronize()
+    fill_ms = []
+    stages = None
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+        st_ms = ctx.stage_ms()
+        fill_ms.append(st_ms[1])
+        stages = st_ms if stages is None else [a + c for a, c in zip(stages, st_ms)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"[bench] {args.steps} timed steps in {dt:.3f}s", flush=True, file=sys.stderr)
+    ms_per_step = dt * 1e3 / args.steps
+    value = cells * args.steps / dt / 1e9
+    fill_avg = sum(fill_ms) / len(fill_ms)
+    achieved = cells * OPS_PER_CELL / (fill_avg * 1e-3) / 1e12
+    names = ["prepare", "fill", "rerun32", "reverse", "traceback", "score2", "records"]
+    stage_avg = {n: round(v / args.steps, 3) for n, v in zip(names, stages)}
+
+    # per-pair form: the same library, one pair per call
+    pp = b.subset(np.arange(min(args.per_pair_sample, b.npairs)))
+    t = time.perf_counter()
+    for p in range(pp.npairs):
+        ctx.align_pair(pp.query(p), pp.ref(p), pp.matrix, pp.gap_open, pp.gap_extend)
+    pdt = time.perf_counter() - t
+    per_pair = {"value": round(pp.cells() / pdt / 1e9, 4), "unit": "GCUPS",
+                "pairs": pp.npairs, "ms_per_pair": round(pdt * 1e3 / pp.npairs, 3)}
+    ctx.close()
+
+    line = {
+        "metric": "GCUPS (fill+traceback) batched vs per-pair at 1 GPU",
+        "value": round(value, 2),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int16",
+        "data": "synthetic",
+        "config": {"workload": f"batched uneven DNA: {b.npairs} read/window pairs, reads "
+                               "100-250 nt, windows +0-400 nt, 1-3% subs, 0.5% indels, 10% "
+                               "random reads; +2/-2, gap open 3, extend 1; score, score2, "
+                               "begins, ends, CIGAR per pair",
+                   "pairs": b.npairs, "cells": cells, "global_batch": b.npairs,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                     "peak": round(PEAK_PK16_TOPS, 2), "unit": "Tops/s",
+                     "frac": round(achieved / PEAK_PK16_TOPS, 4), "traffic": None,
+                     "kernel": "k_inter_fill (forward fill, packed 16-bit lanes)",
+                     "fill_ms": round(fill_avg, 3), "ops_per_cell": OPS_PER_CELL},
+        "stages_ms": stage_avg,
+        "per_pair": per_pair,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

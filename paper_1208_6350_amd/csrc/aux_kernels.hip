@@ -81,11 +81,12 @@ __device__ __forceinline__ bool coords_ok(int64_t p, const int32_t *qbeg, const 
 
 __global__ void k_band_sizes(int64_t npairs, const int32_t *score, const int32_t *qbeg,
                              const int32_t *qend, const int64_t *rbeg, const int64_t *rend,
-                             const int32_t *qlen, const int64_t *rlen, int32_t smax, int32_t o, int32_t e, int64_t *dir_size,
+                             const int32_t *qlen, const int64_t *rlen, const uint8_t *only,
+                             int32_t smax, int32_t o, int32_t e, int64_t *dir_size,
                              int64_t *cig_cap, int64_t *row_cap) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npairs) return;
-  if (score[p] <= 0 || !coords_ok(p, qbeg, qend, rbeg, rend, qlen, rlen)) {
+  if (score[p] <= 0 || (only && only[p] != 5) || !coords_ok(p, qbeg, qend, rbeg, rend, qlen, rlen)) {
     dir_size[p] = 0; cig_cap[p] = 0; row_cap[p] = 0; return;
   }
   const int64_t m = qend[p] - qbeg[p] + 1, w = rend[p] - rbeg[p] + 1;
@@ -105,6 +106,7 @@ __global__ void k_band_tb(BandArgs a) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= a.npairs) return;
   const int32_t s1 = a.score[p];
+  if (a.only && a.only[p] != 5) return;
   if (s1 <= 0) { a.cig_len[p] = 0; return; }
   if (!coords_ok(p, a.qbeg, a.qend, a.rbeg, a.rend, a.qlen, a.rlen)) {
     a.cig_len[p] = 0;
@@ -368,8 +370,73 @@ __global__ void k_validate(ValidateArgs a) {
   if (bad) atomicOr(a.bad, bad);
 }
 
+// ---- small helpers ------------------------------------------------------------
+// stats[0] = max over pairs of min(qlen, rlen)
+__global__ void k_pair_stats(int64_t n, const int32_t *qlen, const int64_t *rlen, int64_t *stats) {
+  int64_t best = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+    const int64_t m = qlen[p] < rlen[p] ? qlen[p] : rlen[p];
+    best = m > best ? m : best;
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    const int64_t o = __shfl_xor(best, off, 64);
+    best = o > best ? o : best;
+  }
+  if ((threadIdx.x & 63) == 0 && best > 0) atomicMax((unsigned long long *)&stats[0], (unsigned long long)best);
+}
+
+__global__ void k_lens_to_i64(int64_t n, const int32_t *len, int64_t *out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) out[p] = len[p];
+}
+
+__global__ void k_mark_lanes(int64_t n, const int64_t *ids, uint8_t *lanebits, uint8_t v) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) lanebits[ids[k]] = v;
+}
+
+__global__ void k_any_flag(int64_t n, const uint8_t *flag, int64_t *count) {
+  int64_t c = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride)
+    c += flag[p] ? 1 : 0;
+  for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd((unsigned long long *)count, (unsigned long long)c);
+}
+
 // ---- launchers --------------------------------------------------------------
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_pair_stats(int64_t n, const int32_t *qlen, const int64_t *rlen, int64_t *stats,
+                             hipStream_t st) {
+  if (!n) return hipSuccess;
+  unsigned b = blocks_for(n, 256);
+  if (b > 1024) b = 1024;
+  hipLaunchKernelGGL(k_pair_stats, dim3(b), dim3(256), 0, st, n, qlen, rlen, stats);
+  return hipGetLastError();
+}
+
+hipError_t lens_to_i64(int64_t n, const int32_t *len, int64_t *out, hipStream_t st) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_lens_to_i64, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, len, out);
+  return hipGetLastError();
+}
+
+hipError_t mark_lanes(int64_t n, const int64_t *ids, uint8_t *lanebits, int v, hipStream_t st) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_mark_lanes, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, ids, lanebits,
+                     (uint8_t)v);
+  return hipGetLastError();
+}
+
+hipError_t launch_any_flag(int64_t n, const uint8_t *flag, int64_t *count, hipStream_t st) {
+  if (!n) return hipSuccess;
+  unsigned b = blocks_for(n, 256);
+  if (b > 1024) b = 1024;
+  hipLaunchKernelGGL(k_any_flag, dim3(b), dim3(256), 0, st, n, flag, count);
+  return hipGetLastError();
+}
 
 hipError_t launch_validate(const ValidateArgs &a, hipStream_t st) {
   const int64_t work = a.qcat_len + a.rcat_len + a.npairs + a.nq + a.nr + 2;
@@ -407,12 +474,13 @@ hipError_t launch_rev_views(int64_t npairs, const int64_t *qstart, const int64_t
 
 hipError_t launch_band_sizes(int64_t npairs, const int32_t *score, const int32_t *qbeg,
                              const int32_t *qend, const int64_t *rbeg, const int64_t *rend,
-                             const int32_t *qlen, const int64_t *rlen,
+                             const int32_t *qlen, const int64_t *rlen, const uint8_t *only,
                              int32_t smax, int32_t o, int32_t e, int64_t *dir_size,
                              int64_t *cig_cap, int64_t *row_cap, hipStream_t st) {
   if (!npairs) return hipSuccess;
   hipLaunchKernelGGL(k_band_sizes, dim3(blocks_for(npairs, 256)), dim3(256), 0, st, npairs, score,
-                     qbeg, qend, rbeg, rend, qlen, rlen, smax, o, e, dir_size, cig_cap, row_cap);
+                     qbeg, qend, rbeg, rend, qlen, rlen, only, smax, o, e, dir_size, cig_cap,
+                     row_cap);
   return hipGetLastError();
 }
 

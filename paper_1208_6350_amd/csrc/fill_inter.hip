@@ -17,9 +17,10 @@
 // Each lane walks the matrix in strips of R rows.  For each column of a strip
 // the lane keeps H and E of its R rows in registers and receives H and F of
 // the row above from the boundary planes written by the previous strip; the
-// whole cell update is 11 saturating 16-bit-pair instructions plus two for
-// the column max with the row code (value * 32 + code, so that a max over the
-// strip also names the first row reaching it).
+// cell update is 11 saturating 16-bit-pair instructions plus two for the
+// column max with the row code (value * 32 + code, so that a max over the
+// strip also names the first row reaching it).  Sequences are read straight
+// from the caller's concatenated arrays (8 columns per fetch).
 //
 // Scores live in a biased domain: the substitution term arrives as
 // S + bias >= 0 (bias = -min S), E and F are kept as E + bias and F + bias
@@ -43,40 +44,33 @@ __device__ __forceinline__ int64_t wave_max64(int64_t v) {
   return v;
 }
 
-template <class V, int R, uint32_t MODE>
-__device__ __forceinline__ void load_scores(const InterArgs &a, const InterTask &tk, int s, int lane,
-                                            const uint32_t *s_lut, uint32_t symA, uint32_t symB,
-                                            uint32_t (&X)[R / 4][2]) {
-  using T = VT<V>;
-  if constexpr (MODE == kQSel) {
-    // column LUTs: the same dword pair serves every row
-    X[0][0] = s_lut[symA];
-    X[0][1] = (T::kHalves == 2) ? s_lut[symB] : 0u;
-  } else {
-    const int np1 = a.n + 1;
-    const uint8_t *base = a.prof + tk.qdata_off;
-    const int64_t strip = (int64_t)s * np1 * T::kHalves * 64 * R;
-    const uint4 *pA = (const uint4 *)(base + strip + (((int64_t)symA * T::kHalves + 0) * 64 + lane) * R);
-#pragma unroll
-    for (int k = 0; k < R / 16; ++k) {
-      uint4 v = pA[k];
-      X[4 * k + 0][0] = v.x; X[4 * k + 1][0] = v.y; X[4 * k + 2][0] = v.z; X[4 * k + 3][0] = v.w;
-    }
-    if constexpr (T::kHalves == 2) {
-      const uint4 *pB = (const uint4 *)(base + strip + (((int64_t)symB * 2 + 1) * 64 + lane) * R);
-#pragma unroll
-      for (int k = 0; k < R / 16; ++k) {
-        uint4 v = pB[k];
-        X[4 * k + 0][1] = v.x; X[4 * k + 1][1] = v.y; X[4 * k + 2][1] = v.z; X[4 * k + 3][1] = v.w;
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < R / 4; ++k) X[k][1] = 0u;
-    }
-  }
+// A sequence as seen by one lane-half: padded index i maps to symbol
+// base[i - pad] (forward) or base[len - 1 - (i - pad)] (reversed view).
+struct SeqRef {
+  const int8_t *base;
+  int64_t len;
+  int64_t pad;
+  bool rev;
+};
+
+__device__ __forceinline__ int32_t seq_at(const SeqRef &s, int64_t i) {
+  const int64_t j = i - s.pad;
+  if (j < 0 || j >= s.len) return -1;
+  return s.base[s.rev ? s.len - 1 - j : j];
 }
 
-template <class V, int R, uint32_t MODE>
+// padded columns c0..c0+7, byte k = column c0+k, pad symbol outside
+__device__ __forceinline__ uint2 fetch8(const SeqRef &s, int64_t c0, uint32_t pad_sym) {
+  uint32_t w[2] = {0u, 0u};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int32_t v = seq_at(s, c0 + k);
+    w[k >> 2] |= (v < 0 ? pad_sym : (uint32_t)v) << (8 * (k & 3));
+  }
+  return make_uint2(w[0], w[1]);
+}
+
+template <class V, int R, uint32_t MODE, bool CLAMP>
 __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
   using T = VT<V>;
   constexpr int NH = T::kHalves;
@@ -91,11 +85,11 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
   const bool rev = a.rev != 0;
   const int nstrips = tk.qp / R;
   const int64_t rp = tk.rp;
+  const uint32_t pad_sym = (uint32_t)a.n;
 
   // slots of this lane
   int64_t pid[NH];
-  int32_t padq[NH];
-  int64_t padr[NH];
+  SeqRef qs[NH], rs[NH];
   int32_t tgt[NH];
   int64_t reach[NH];
 #pragma unroll
@@ -103,14 +97,18 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
     const int s = lane + 64 * h;
     pid[h] = (s < tk.nslots) ? a.slot_pair[tk.slot_base + s] : -1;
     if (pid[h] >= 0) {
-      const int32_t lq = a.view.qlen[pid[h]];
-      const int64_t lr = a.view.rlen[pid[h]];
-      padq[h] = rev ? 0 : tk.qp - lq;
-      padr[h] = rev ? 0 : rp - lr;
-      tgt[h] = rev ? a.target[pid[h]] : 0;
+      const int64_t p = pid[h];
+      const int32_t lq = a.view.qlen[p];
+      const int64_t lr = a.view.rlen[p];
+      qs[h] = SeqRef{a.view.qcat + a.view.qstart[p], lq, rev ? 0 : tk.qp - lq, a.view.reversed != 0};
+      rs[h] = SeqRef{a.view.rcat + a.view.rstart[p], lr, rev ? 0 : rp - lr, a.view.reversed != 0};
+      tgt[h] = rev ? a.target[p] : 0;
       reach[h] = (rev && tgt[h] <= 0) ? -1 : kNoReach;
     } else {
-      padq[h] = 0; padr[h] = 0; tgt[h] = 0; reach[h] = -1;
+      qs[h] = SeqRef{a.view.qcat, 0, 0, false};
+      rs[h] = SeqRef{a.view.rcat, 0, 0, false};
+      tgt[h] = 0;
+      reach[h] = -1;
     }
   }
   int32_t bval[NH], brow[NH];
@@ -121,7 +119,6 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
   uint32_t *bH = a.bnd + tk.bnd_off;
   uint32_t *bF = bH + rp * 64;
   uint32_t *bC = bF + rp * 64;
-  const uint4 *sym = a.rsym + tk.sym_off;
   const V vbias = T::splat((uint32_t)a.bias);
   const V vo = T::splat((uint32_t)a.o);
   const V ve = T::splat((uint32_t)a.e);
@@ -144,10 +141,20 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
       if (clo >= chi) break;   // later strips have even later windows
     }
 
+    // per-row byte selectors (QSEL): query symbol of each half, 0x0C = pad
     uint32_t sel[R];
     if constexpr (MODE == kQSel) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) sel[r] = a.qsel[tk.qdata_off + (int64_t)(sR + r) * 64 + lane];
+      for (int r = 0; r < R; ++r) {
+        uint32_t w = 0x0C0C0C0Cu;
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          const int32_t qv = seq_at(qs[h], sR + r);
+          const uint32_t b = qv < 0 ? 0x0Cu : (uint32_t)qv + 4u * h;
+          w = (w & ~(0xFFu << (16 * h))) | (b << (16 * h));
+        }
+        sel[r] = w;
+      }
     }
 
     V H[R], E[R];
@@ -162,21 +169,74 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
     for (int h = 0; h < NH; ++h) { sb[h] = 0u; sbcol[h] = -1; }
     const bool last = (s == nstrips - 1);
 
-    for (int64_t c = clo; c < chi; ++c) {
+    // Column loop.  Everything column c+1 needs from memory (boundary values,
+    // reference symbols, score operands) is requested before column c is
+    // computed, so the loads overlap the arithmetic.
+    int64_t cdone = chi;   // one past the last column this strip computes
+    int64_t blk = clo >> 3;
+    uint2 s8cur[NH], s8nxt[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      s8cur[h] = fetch8(rs[h], blk * 8, pad_sym);
+      s8nxt[h] = fetch8(rs[h], blk * 8 + 8, pad_sym);
+    }
+    V n_hup, n_F, n_cm;
+    uint32_t nX[R / 4][2];
+    auto prefetch = [&](int64_t c) {
       const bool inprev = (s > 0) && (c >= plo) && (c < phi);
       const int64_t bi = c * 64 + lane;
-      V hup = inprev ? T::from(bH[bi]) : T::zero();
-      V F = inprev ? T::from(bF[bi]) : T::zero();
-      V cmin = (!rev && s > 0) ? T::from(bC[bi]) : T::zero();
-
-      const uint4 sy = sym[(c >> 3) * 64 + lane];
-      const int sh = (int)(c & 3) * 8;
-      const uint32_t wA = (c & 4) ? sy.y : sy.x;
-      const uint32_t wB = (c & 4) ? sy.w : sy.z;
-      const uint32_t symA = (wA >> sh) & 0xFFu;
-      const uint32_t symB = (wB >> sh) & 0xFFu;
+      n_hup = inprev ? T::from(bH[bi]) : T::zero();
+      n_F = inprev ? T::from(bF[bi]) : T::zero();
+      n_cm = (!rev && s > 0) ? T::from(bC[bi]) : T::zero();
+      const uint32_t cc = (uint32_t)(c & 7);
+      const uint32_t symA = __builtin_amdgcn_ubfe(cc < 4 ? s8cur[0].x : s8cur[0].y, 8 * (cc & 3), 8);
+      const uint32_t symB = (NH == 2)
+          ? __builtin_amdgcn_ubfe(cc < 4 ? s8cur[NH - 1].x : s8cur[NH - 1].y, 8 * (cc & 3), 8)
+          : 0u;
+      if constexpr (MODE == kQSel) {
+        nX[0][0] = s_lut[symA];
+        nX[0][1] = (NH == 2) ? s_lut[symB] : 0u;
+      } else {
+        const int np1 = a.n + 1;
+        const uint8_t *base = a.prof + tk.qdata_off + (int64_t)s * np1 * NH * 64 * R;
+        const uint4 *pA = (const uint4 *)(base + (((int64_t)symA * NH + 0) * 64 + lane) * R);
+#pragma unroll
+        for (int k = 0; k < R / 16; ++k) {
+          const uint4 v = pA[k];
+          nX[4 * k + 0][0] = v.x; nX[4 * k + 1][0] = v.y; nX[4 * k + 2][0] = v.z; nX[4 * k + 3][0] = v.w;
+        }
+        if constexpr (NH == 2) {
+          const uint4 *pB = (const uint4 *)(base + (((int64_t)symB * 2 + 1) * 64 + lane) * R);
+#pragma unroll
+          for (int k = 0; k < R / 16; ++k) {
+            const uint4 v = pB[k];
+            nX[4 * k + 0][1] = v.x; nX[4 * k + 1][1] = v.y; nX[4 * k + 2][1] = v.z; nX[4 * k + 3][1] = v.w;
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < R / 4; ++k) nX[k][1] = 0u;
+        }
+      }
+    };
+    prefetch(clo);
+#pragma unroll 1
+    for (int64_t c = clo; c < chi; ++c) {
+      const V hup = n_hup;
+      V F = n_F;
+      const V cmin = n_cm;
       uint32_t X[R / 4][2];
-      load_scores<V, R, MODE>(a, tk, s, lane, s_lut, symA, symB, X);
+#pragma unroll
+      for (int k = 0; k < ((MODE == kQSel) ? 1 : R / 4); ++k) { X[k][0] = nX[k][0]; X[k][1] = nX[k][1]; }
+      if (((c + 1) & 7) == 0) {   // the next column starts a new 8-column block
+        ++blk;
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          s8cur[h] = s8nxt[h];
+          s8nxt[h] = fetch8(rs[h], blk * 8 + 8, pad_sym);
+        }
+      }
+      if (c + 1 < chi) prefetch(c + 1);
+      const int64_t bi = c * 64 + lane;
 
       V hdiag = hdtop;
       hdtop = hup;
@@ -192,7 +252,8 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
         const V hb = T::max(T::max(t, E[r]), F);
         const V hn = T::subs(hb, vbias);
         H[r] = hn;
-        cm = T::max(cm, T::enc(hn, T::code_splat((uint32_t)(R - 1 - r))));
+        cm = T::max(cm, CLAMP ? T::enc(hn, T::code_splat((uint32_t)(R - 1 - r)))
+                              : T::enc_nosat(hn, (uint32_t)(R - 1 - r)));
         ho = T::subs(hb, vo);
         E[r] = T::max(T::subs(E[r], ve), ho);
         F = T::max(T::subs(F, ve), ho);   // F of the next row
@@ -208,14 +269,27 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
         const uint32_t v = T::half(cm, h);
         if ((v | 31u) > (sb[h] | 31u)) { sb[h] = v; sbcol[h] = c; }
       }
+      if (rev && ((c + 1) & 7) == 0) {
+        // leave the strip once every pair has reached its target at or before
+        // column c: later columns can neither give an earlier column nor a
+        // smaller row
+        int64_t need = -1;
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          int64_t rr = reach[h];
+          if (rr >= 0 && (int32_t)(sb[h] >> 5) >= tgt[h] && sbcol[h] < rr) rr = sbcol[h];
+          need = rr > need ? rr : need;
+        }
+        if (wave_max64(need) <= c + 1) { cdone = c + 1; break; }
+      }
     }
     // merge the strip best into the pair best (earlier strips win ties)
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
       const int32_t v = (int32_t)(sb[h] >> 5);
       if (v > 0) {
-        const int32_t row = sR + (R - 1 - (int32_t)(sb[h] & 31u)) - padq[h];
-        const int64_t col = sbcol[h] - padr[h];
+        const int32_t row = sR + (R - 1 - (int32_t)(sb[h] & 31u)) - (int32_t)qs[h].pad;
+        const int64_t col = sbcol[h] - rs[h].pad;
         if (v > bval[h] || (v == bval[h] && col < bcol[h])) {
           bval[h] = v; brow[h] = row; bcol[h] = col;
         }
@@ -223,7 +297,7 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
       }
     }
     plo = clo;
-    phi = chi;
+    phi = cdone;
   }
 
   constexpr int32_t limit = (NH == 2) ? kInter16Limit : (1 << 26) - 1;
@@ -238,85 +312,37 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
   }
 }
 
-// ---- packing: reference symbols, QSEL row selectors, QGEN profiles ------
-// Reference symbols of a task: uint4 per (8 columns, lane): bytes 0-7 hold
-// the low-half pair's symbols, bytes 8-15 the high-half pair's.  Padding
-// columns carry the pad symbol `pad`.
-
-
-__device__ __forceinline__ int32_t ref_sym(const PackArgs &a, int64_t p, int64_t c, int64_t rp) {
-  if (p < 0) return -1;
-  const int64_t lr = a.view.rlen[p];
-  int64_t j = a.rev ? c : c - (rp - lr);
-  if (j < 0 || j >= lr) return -1;
-  const int64_t idx = a.view.reversed ? a.view.rstart[p] + lr - 1 - j : a.view.rstart[p] + j;
-  return a.view.rcat[idx];
-}
-
-__device__ __forceinline__ int32_t qry_sym(const PackArgs &a, int64_t p, int64_t ip, int32_t qp) {
-  if (p < 0) return -1;
-  const int32_t lq = a.view.qlen[p];
-  int64_t i = a.rev ? ip : ip - (qp - lq);
-  if (i < 0 || i >= lq) return -1;
-  const int64_t idx = a.view.reversed ? a.view.qstart[p] + lq - 1 - i : a.view.qstart[p] + i;
-  return a.view.qcat[idx];
-}
-
-__global__ __launch_bounds__(256) void k_inter_pack(PackArgs a) {
+// ---- QGEN profile: per task, strip, symbol, half, lane: R biased bytes ----
+__global__ __launch_bounds__(256) void k_inter_prof(PackArgs a) {
   const int64_t t = blockIdx.x;
   if (t >= a.ntasks) return;
   const InterTask tk = a.tasks[t];
-  const int pad = a.n;   // pad symbol code
-  // reference symbols
-  const int64_t nblk = tk.rp / 8;
-  for (int64_t k = threadIdx.x; k < nblk * 64; k += blockDim.x) {
-    const int lane = (int)(k & 63);
-    const int64_t blk = k >> 6;
-    uint32_t w[4] = {0, 0, 0, 0};
-    for (int h = 0; h < a.halves; ++h) {
-      const int s = lane + 64 * h;
-      const int64_t p = (s < tk.nslots) ? a.slot_pair[tk.slot_base + s] : -1;
-      for (int cc = 0; cc < 8; ++cc) {
-        int32_t v = ref_sym(a, p, blk * 8 + cc, tk.rp);
-        uint32_t b = (uint32_t)(v < 0 ? pad : v) & 0xFFu;
-        w[2 * h + (cc >> 2)] |= b << ((cc & 3) * 8);
+  const int R = a.strip_rows;
+  const int np1 = a.n + 1;
+  const int64_t nstrips = tk.qp / R;
+  const int64_t units = nstrips * np1 * a.halves * 64;
+  for (int64_t u = threadIdx.x; u < units; u += blockDim.x) {
+    const int lane = (int)(u & 63);
+    int64_t rest = u >> 6;
+    const int h = (int)(rest % a.halves); rest /= a.halves;
+    const int sy = (int)(rest % np1);
+    const int64_t strip = rest / np1;
+    const int s = lane + 64 * h;
+    const int64_t p = (s < tk.nslots) ? a.slot_pair[tk.slot_base + s] : -1;
+    uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // up to R = 32 bytes
+    if (p >= 0 && sy < a.n) {
+      const int32_t lq = a.view.qlen[p];
+      const SeqRef q{a.view.qcat + a.view.qstart[p], lq, a.rev ? 0 : tk.qp - lq,
+                     a.view.reversed != 0};
+      for (int r = 0; r < R; ++r) {
+        const int32_t qv = seq_at(q, strip * R + r);
+        const uint32_t b = qv < 0 ? 0u : (uint32_t)(uint8_t)(a.matrix[qv * a.n + sy] + a.bias);
+        w[r >> 2] |= b << (8 * (r & 3));
       }
     }
-    a.rsym[tk.sym_off + k] = make_uint4(w[0], w[1], w[2], w[3]);
-  }
-  if (a.mode == (int)kQSel) {
-    for (int64_t k = threadIdx.x; k < (int64_t)tk.qp * 64; k += blockDim.x) {
-      const int lane = (int)(k & 63);
-      const int64_t ip = k >> 6;
-      uint32_t sel = 0x0C0C0C0Cu;
-      for (int h = 0; h < a.halves; ++h) {
-        const int s = lane + 64 * h;
-        const int64_t p = (s < tk.nslots) ? a.slot_pair[tk.slot_base + s] : -1;
-        const int32_t v = qry_sym(a, p, ip, tk.qp);
-        const uint32_t b = (v < 0) ? 0x0Cu : (uint32_t)v + 4u * h;
-        sel = (sel & ~(0xFFu << (16 * h))) | (b << (16 * h));
-      }
-      a.qsel[tk.qdata_off + k] = sel;
-    }
-  } else {
-    const int R = a.strip_rows;
-    const int np1 = a.n + 1;
-    const int64_t total = (int64_t)tk.qp * np1 * a.halves * 64;
-    for (int64_t k = threadIdx.x; k < total; k += blockDim.x) {
-      // k enumerates (strip, symbol, half, lane, row-in-strip) with the row fastest
-      const int r = (int)(k % R);
-      int64_t rest = k / R;
-      const int lane = (int)(rest % 64); rest /= 64;
-      const int h = (int)(rest % a.halves); rest /= a.halves;
-      const int sy = (int)(rest % np1);
-      const int64_t strip = rest / np1;
-      const int s = lane + 64 * h;
-      const int64_t p = (s < tk.nslots) ? a.slot_pair[tk.slot_base + s] : -1;
-      const int32_t qv = qry_sym(a, p, strip * R + r, tk.qp);
-      uint8_t b = 0;
-      if (qv >= 0 && sy < a.n) b = (uint8_t)(a.matrix[qv * a.n + sy] + a.bias);
-      a.prof[tk.qdata_off + k] = b;
-    }
+    uint4 *dst = (uint4 *)(a.prof + tk.qdata_off + u * R);
+    for (int k = 0; k < R / 16; ++k)
+      dst[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
   }
 }
 
@@ -326,30 +352,30 @@ static hipError_t launch_fill(const InterArgs &a, hipStream_t st) {
   const int waves_per_block = 4;
   const int64_t blocks = (a.ntasks + waves_per_block - 1) / waves_per_block;
   if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_inter_fill<V, R, MODE>), dim3((unsigned)blocks), dim3(64 * waves_per_block),
-                     0, st, a);
+  if (a.clamp)
+    hipLaunchKernelGGL((k_inter_fill<V, R, MODE, true>), dim3((unsigned)blocks),
+                       dim3(64 * waves_per_block), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_inter_fill<V, R, MODE, false>), dim3((unsigned)blocks),
+                       dim3(64 * waves_per_block), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t inter_fill(const InterArgs &a, int lane_bits, int R, hipStream_t st) {
-  const uint32_t mode = a.qsel ? kQSel : kQGen;
+  const bool qsel = (a.prof == nullptr);
   if (lane_bits == 16) {
-    if (R == 32) return mode == kQSel ? launch_fill<u16x2, 32, kQSel>(a, st)
-                                      : launch_fill<u16x2, 32, kQGen>(a, st);
-    if (R == 16) return mode == kQSel ? launch_fill<u16x2, 16, kQSel>(a, st)
-                                      : launch_fill<u16x2, 16, kQGen>(a, st);
+    if (R == 32) return qsel ? launch_fill<u16x2, 32, kQSel>(a, st) : launch_fill<u16x2, 32, kQGen>(a, st);
+    if (R == 16) return qsel ? launch_fill<u16x2, 16, kQSel>(a, st) : launch_fill<u16x2, 16, kQGen>(a, st);
   } else {
-    if (R == 32) return mode == kQSel ? launch_fill<uint32_t, 32, kQSel>(a, st)
-                                      : launch_fill<uint32_t, 32, kQGen>(a, st);
-    if (R == 16) return mode == kQSel ? launch_fill<uint32_t, 16, kQSel>(a, st)
-                                      : launch_fill<uint32_t, 16, kQGen>(a, st);
+    if (R == 32) return qsel ? launch_fill<uint32_t, 32, kQSel>(a, st) : launch_fill<uint32_t, 32, kQGen>(a, st);
+    if (R == 16) return qsel ? launch_fill<uint32_t, 16, kQSel>(a, st) : launch_fill<uint32_t, 16, kQGen>(a, st);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t inter_pack(const PackArgs &a, hipStream_t st) {
   if (a.ntasks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_inter_pack, dim3((unsigned)a.ntasks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_inter_prof, dim3((unsigned)a.ntasks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

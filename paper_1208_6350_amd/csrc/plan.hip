@@ -1,0 +1,199 @@
+// plan.hip -- device-side batching: length-bucketed task formation.
+//
+// Pairs of one pass are sorted by a key (band class, padded query height,
+// reference length) with a device radix sort and cut into tasks of `slots`
+// consecutive pairs, so that the pairs sharing a wave have nearly the same
+// dimensions and little padding.  Task sizes and buffer offsets are derived on
+// the device; the host only reads back the totals it must allocate.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include "swx_internal.h"
+#include "swx_kernels.h"
+
+namespace swx {
+
+__global__ void k_plan_keys(int64_t n, const int64_t *ids, const int32_t *qlen,
+                            const int64_t *rlen, const int32_t *band, int32_t R, uint64_t *keys,
+                            int64_t *vals) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t p = ids ? ids[k] : k;
+  int64_t q = qlen[p];
+  if (q < 1) q = 1;
+  const uint64_t qc = (uint64_t)((q + R - 1) / R);
+  uint64_t r = (uint64_t)rlen[p];
+  if (r > 0xFFFFFFFull) r = 0xFFFFFFFull;
+  uint64_t b = 0;
+  if (band) b = band[p] < 0 ? 0xFFFFFull : (uint64_t)(band[p] > 0xFFFFE ? 0xFFFFE : band[p]);
+  keys[k] = (b << 44) | ((qc > 0xFFFF ? 0xFFFF : qc) << 28) | r;
+  vals[k] = p;
+}
+
+__global__ void k_plan_tasks(int64_t n, int64_t ntasks, int32_t slots, int32_t R,
+                             int64_t qdata_per_row, const int64_t *sorted, const int32_t *qlen,
+                             const int64_t *rlen, const int32_t *band, InterTask *tasks,
+                             int64_t *bnd_size, int64_t *qdata_size) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntasks) return;
+  const int64_t s0 = t * slots;
+  const int64_t s1 = (s0 + slots < n) ? s0 + slots : n;
+  int64_t mq = 1, mr = 1;
+  int32_t mb = band ? 0 : -1;
+  for (int64_t k = s0; k < s1; ++k) {
+    const int64_t p = sorted[k];
+    if (qlen[p] > mq) mq = qlen[p];
+    if (rlen[p] > mr) mr = rlen[p];
+    if (band) mb = (band[p] < 0 || mb < 0) ? -1 : (band[p] > mb ? band[p] : mb);
+  }
+  InterTask tk{};
+  tk.nslots = (int32_t)(s1 - s0);
+  tk.qp = (int32_t)((mq + R - 1) / R * R);
+  tk.rp = (int32_t)((mr + 7) / 8 * 8);
+  tk.band = mb;
+  tk.slot_base = s0;
+  tasks[t] = tk;
+  bnd_size[t] = 3 * (int64_t)tk.rp * 64;
+  qdata_size[t] = ((int64_t)tk.qp * qdata_per_row + 15) / 16 * 16;
+}
+
+__global__ void k_plan_offsets(int64_t ntasks, InterTask *tasks, const int64_t *bnd_off,
+                               const int64_t *qdata_off) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntasks) return;
+  tasks[t].bnd_off = bnd_off[t];
+  tasks[t].qdata_off = qdata_off[t];
+}
+
+// flagged compaction: out[k] = the k-th pair with flag != 0 (in pair order)
+__global__ void k_flag_to_i64(int64_t n, const uint8_t *flag, int64_t *f64) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) f64[p] = flag[p] ? 1 : 0;
+}
+
+__global__ void k_compact(int64_t n, const uint8_t *flag, const int64_t *pos, int64_t *out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n && flag[p]) out[pos[p]] = p;
+}
+
+__global__ void k_count_classes(int64_t n, const uint8_t *cls, int64_t *counts) {
+  __shared__ int64_t c[8];
+  if (threadIdx.x < 8) c[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride)
+    atomicAdd((unsigned long long *)&c[cls[p] & 7], 1ull);
+  __syncthreads();
+  if (threadIdx.x < 8 && c[threadIdx.x]) atomicAdd((unsigned long long *)&counts[threadIdx.x],
+                                                   (unsigned long long)c[threadIdx.x]);
+}
+
+// reversed pass setup: band G' per pair and the lane width it runs at.
+// Every alignment of score score1 that ends at the end cell stays within
+// G' = (smax*min(qend+1, rend+1) - o + e - score1) / e diagonals of the
+// reversed start (e > 0); with e == 0 no band is used.
+__global__ void k_rev_prepare(int64_t n, const int32_t *score, const int32_t *qend,
+                              const int64_t *rend, const uint8_t *lanebits, int32_t smax,
+                              int32_t o, int32_t e, int32_t *band, uint8_t *f16, uint8_t *f32) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const bool ok = score[p] > 0;
+  int32_t b = 0;
+  if (ok) {
+    if (e > 0) {
+      int64_t ml = (int64_t)qend[p] + 1;
+      if (rend[p] + 1 < ml) ml = rend[p] + 1;
+      int64_t g = ((int64_t)smax * ml - o + e - score[p]) / e;
+      if (g < 0) g = 0;
+      b = (int32_t)(g > (1 << 30) ? (1 << 30) : g);
+    } else {
+      b = -1;
+    }
+  }
+  band[p] = b;
+  f16[p] = (ok && lanebits[p] == 16) ? 1 : 0;
+  f32[p] = (ok && lanebits[p] == 32) ? 1 : 0;
+}
+
+static inline unsigned nb(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t count_classes(int64_t n, const uint8_t *cls, int64_t *counts, hipStream_t st) {
+  if (!n) return hipSuccess;
+  unsigned blocks = nb(n, 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_count_classes, dim3(blocks), dim3(256), 0, st, n, cls, counts);
+  return hipGetLastError();
+}
+
+hipError_t sort_keys(int64_t n, uint64_t *keys, uint64_t *keys_alt, int64_t *vals,
+                     int64_t *vals_alt, void *tmp, size_t *tmp_bytes, int64_t **sorted_out,
+                     hipStream_t st) {
+  hipcub::DoubleBuffer<uint64_t> kb(keys, keys_alt);
+  hipcub::DoubleBuffer<int64_t> vb(vals, vals_alt);
+  hipError_t e = hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, kb, vb, (int)n, 0, 64, st);
+  if (tmp) *sorted_out = vb.Current();
+  return e;
+}
+
+hipError_t rev_prepare(int64_t npairs, const int32_t *score, const int32_t *qend,
+                       const int64_t *rend, const uint8_t *lanebits, int32_t smax, int32_t o,
+                       int32_t e, int32_t *band, uint8_t *f16, uint8_t *f32, hipStream_t st) {
+  if (!npairs) return hipSuccess;
+  hipLaunchKernelGGL(k_rev_prepare, dim3(nb(npairs, 256)), dim3(256), 0, st, npairs, score, qend,
+                     rend, lanebits, smax, o, e, band, f16, f32);
+  return hipGetLastError();
+}
+
+hipError_t plan_sort(int64_t n, const int64_t *ids, const int32_t *qlen, const int64_t *rlen,
+                     const int32_t *band, int32_t R, uint64_t *keys, uint64_t *keys_alt,
+                     int64_t *vals, int64_t *vals_alt, void *tmp, size_t *tmp_bytes,
+                     int64_t **sorted_out, hipStream_t st) {
+  if (tmp == nullptr) {
+    hipcub::DoubleBuffer<uint64_t> kb(keys, keys_alt);
+    hipcub::DoubleBuffer<int64_t> vb(vals, vals_alt);
+    return hipcub::DeviceRadixSort::SortPairs(nullptr, *tmp_bytes, kb, vb, (int)n, 0, 64, st);
+  }
+  if (n == 0) { *sorted_out = vals; return hipSuccess; }
+  hipLaunchKernelGGL(k_plan_keys, dim3(nb(n, 256)), dim3(256), 0, st, n, ids, qlen, rlen, band, R,
+                     keys, vals);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipcub::DoubleBuffer<uint64_t> kb(keys, keys_alt);
+  hipcub::DoubleBuffer<int64_t> vb(vals, vals_alt);
+  e = hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, kb, vb, (int)n, 0, 64, st);
+  *sorted_out = vb.Current();
+  return e;
+}
+
+hipError_t plan_tasks_dev(int64_t n, int64_t ntasks, int32_t slots, int32_t R,
+                          int64_t qdata_per_row, const int64_t *sorted, const int32_t *qlen,
+                          const int64_t *rlen, const int32_t *band, InterTask *tasks,
+                          int64_t *bnd_size, int64_t *qdata_size, hipStream_t st) {
+  if (ntasks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_plan_tasks, dim3(nb(ntasks, 128)), dim3(128), 0, st, n, ntasks, slots, R,
+                     qdata_per_row, sorted, qlen, rlen, band, tasks, bnd_size, qdata_size);
+  return hipGetLastError();
+}
+
+hipError_t plan_offsets_dev(int64_t ntasks, InterTask *tasks, const int64_t *bnd_off,
+                            const int64_t *qdata_off, hipStream_t st) {
+  if (ntasks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_plan_offsets, dim3(nb(ntasks, 128)), dim3(128), 0, st, ntasks, tasks,
+                     bnd_off, qdata_off);
+  return hipGetLastError();
+}
+
+hipError_t flags_to_i64(int64_t n, const uint8_t *flag, int64_t *f64, hipStream_t st) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_flag_to_i64, dim3(nb(n, 256)), dim3(256), 0, st, n, flag, f64);
+  return hipGetLastError();
+}
+
+hipError_t compact_flags(int64_t n, const uint8_t *flag, const int64_t *pos, int64_t *out,
+                         hipStream_t st) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_compact, dim3(nb(n, 256)), dim3(256), 0, st, n, flag, pos, out);
+  return hipGetLastError();
+}
+
+}  // namespace swx

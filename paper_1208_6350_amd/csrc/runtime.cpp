@@ -96,6 +96,7 @@ struct swx_ctx {
   hipEvent_t ev[8] = {};
   double stage_ms[8] = {};
   int nstages = 0;
+  int64_t fill_cells = 0;   // cells of the last forward fill launch
 };
 
 struct swx_profile {
@@ -143,126 +144,110 @@ static int make_scoring(const int8_t *mat, int32_t n, int32_t o, int32_t e, Scor
   return SWX_OK;
 }
 
-// ---- planning of inter-sequence tasks --------------------------------------
+// ---- device-side planning of one fill pass ---------------------------------
 struct Plan {
-  std::vector<InterTask> tasks;
-  std::vector<int64_t> slot_pair;
-  int64_t bnd_words = 0, sym_vecs = 0, qdata = 0;   // buffer sizes
-  InterTask *d_tasks = nullptr;
-  int64_t *d_slot_pair = nullptr;
-  uint32_t *d_bnd = nullptr;
-  uint4 *d_rsym = nullptr;
-  uint32_t *d_qsel = nullptr;
-  uint8_t *d_prof = nullptr;
+  int64_t n = 0, ntasks = 0;
   int lane_bits = 16, R = 32;
+  InterTask *d_tasks = nullptr;
+  int64_t *d_sorted = nullptr;   // slot -> pair id
+  uint32_t *d_bnd = nullptr;
+  uint8_t *d_prof = nullptr;
 };
 
 static inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-// ids: pairs of this pass; qlen/rlen/band indexed by pair id (band may be null)
-static void plan_tasks(Plan &pl, const std::vector<int64_t> &ids, const int32_t *qlen,
-                       const int64_t *rlen, const int32_t *band, int lane_bits, int R, int n,
-                       bool qsel) {
+template <class T>
+static T *alloc_or_null(DevArena &A, int64_t n) { return A.get<T>(n); }
+
+// Sort the pass's pairs by (band, padded query height, reference length) on
+// the device, cut them into tasks, derive buffer offsets and allocate.
+static int plan_pass(swx_ctx *ctx, const Scoring &sc, const int64_t *ids, int64_t n,
+                     const int32_t *qlen, const int64_t *rlen, const int32_t *band, int lane_bits,
+                     int R, Plan &pl) {
+  DevArena &A = ctx->arena;
+  hipStream_t st = ctx->stream;
+  pl = Plan{};
+  pl.n = n;
   pl.lane_bits = lane_bits;
   pl.R = R;
+  if (n == 0) return SWX_OK;
   const int slots = lane_bits == 16 ? kSlots16 : kSlots32;
   const int halves = lane_bits == 16 ? 2 : 1;
-  std::vector<int64_t> ord(ids);
-  std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
-    const int32_t ba = band ? band[a] : 0, bb = band ? band[b] : 0;
-    if (ba != bb) return ba < bb;
-    const int64_t qa = round_up(std::max(qlen[a], 1), R), qb = round_up(std::max(qlen[b], 1), R);
-    if (qa != qb) return qa < qb;
-    if (rlen[a] != rlen[b]) return rlen[a] < rlen[b];
-    return a < b;
-  });
-  pl.tasks.clear();
-  pl.slot_pair.clear();
-  pl.bnd_words = pl.sym_vecs = pl.qdata = 0;
-  for (size_t s0 = 0; s0 < ord.size(); s0 += slots) {
-    const size_t s1 = std::min(ord.size(), s0 + slots);
-    InterTask t{};
-    t.nslots = (int32_t)(s1 - s0);
-    int32_t mq = 1;
-    int64_t mr = 1;
-    int32_t mb = band ? 0 : -1;
-    for (size_t k = s0; k < s1; ++k) {
-      mq = std::max(mq, qlen[ord[k]]);
-      mr = std::max(mr, rlen[ord[k]]);
-      if (band) mb = (band[ord[k]] < 0 || mb < 0) ? -1 : std::max(mb, band[ord[k]]);
-    }
-    t.qp = (int32_t)round_up(mq, R);
-    t.rp = (int32_t)round_up(mr, 8);
-    t.band = mb;
-    t.slot_base = (int64_t)pl.slot_pair.size();
-    for (size_t k = s0; k < s1; ++k) pl.slot_pair.push_back(ord[k]);
-    t.bnd_off = pl.bnd_words;
-    pl.bnd_words += 3 * (int64_t)t.rp * 64;
-    t.sym_off = pl.sym_vecs;
-    pl.sym_vecs += (int64_t)(t.rp / 8) * 64;
-    t.qdata_off = pl.qdata;
-    if (qsel) pl.qdata += (int64_t)t.qp * 64;
-    else pl.qdata += round_up((int64_t)t.qp * (n + 1) * halves * 64, 16);
-    pl.tasks.push_back(t);
-  }
-}
-
-static int upload_plan(swx_ctx *ctx, Plan &pl, bool qsel) {
-  DevArena &A = ctx->arena;
-  const int64_t nt = (int64_t)pl.tasks.size();
-  pl.d_tasks = A.get<InterTask>(nt);
-  pl.d_slot_pair = A.get<int64_t>((int64_t)pl.slot_pair.size());
-  pl.d_bnd = A.get<uint32_t>(pl.bnd_words);
-  pl.d_rsym = A.get<uint4>(pl.sym_vecs);
-  if (qsel) {
-    pl.d_qsel = A.get<uint32_t>(pl.qdata);
-    pl.d_prof = nullptr;
-  } else {
-    pl.d_prof = A.get<uint8_t>(pl.qdata);
-    pl.d_qsel = nullptr;
-  }
-  if (!pl.d_tasks || !pl.d_slot_pair || !pl.d_bnd || !pl.d_rsym || (!pl.d_qsel && !pl.d_prof))
-    return fail(SWX_ENOMEM, "device pool exhausted while planning");
-  if (nt) {
-    HIP_TRY(hipMemcpyAsync(pl.d_tasks, pl.tasks.data(), sizeof(InterTask) * nt,
-                           hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(hipMemcpyAsync(pl.d_slot_pair, pl.slot_pair.data(),
-                           sizeof(int64_t) * pl.slot_pair.size(), hipMemcpyHostToDevice,
-                           ctx->stream));
+  pl.ntasks = (n + slots - 1) / slots;
+  uint64_t *k0 = A.get<uint64_t>(n), *k1 = A.get<uint64_t>(n);
+  int64_t *v0 = A.get<int64_t>(n), *v1 = A.get<int64_t>(n);
+  pl.d_tasks = A.get<InterTask>(pl.ntasks);
+  int64_t *bsz = A.get<int64_t>(pl.ntasks + 1), *qsz = A.get<int64_t>(pl.ntasks + 1);
+  int64_t *boff = A.get<int64_t>(pl.ntasks + 1), *qoff = A.get<int64_t>(pl.ntasks + 1);
+  if (!k0 || !k1 || !v0 || !v1 || !pl.d_tasks || !bsz || !qsz || !boff || !qoff)
+    return fail(SWX_ENOMEM, "device pool exhausted (plan)");
+  size_t tmp_bytes = 0;
+  HIP_TRY(plan_sort(n, ids, qlen, rlen, band, R, k0, k1, v0, v1, nullptr, &tmp_bytes, nullptr, st));
+  void *tmp = A.alloc(tmp_bytes);
+  if (!tmp) return fail(SWX_ENOMEM, "device pool exhausted (sort)");
+  HIP_TRY(plan_sort(n, ids, qlen, rlen, band, R, k0, k1, v0, v1, tmp, &tmp_bytes, &pl.d_sorted, st));
+  const int64_t per_row = sc.qsel ? 0 : (int64_t)(sc.n + 1) * halves * 64;
+  HIP_TRY(hipMemsetAsync(bsz + pl.ntasks, 0, 8, st));
+  HIP_TRY(hipMemsetAsync(qsz + pl.ntasks, 0, 8, st));
+  HIP_TRY(plan_tasks_dev(n, pl.ntasks, slots, R, per_row, pl.d_sorted, qlen, rlen, band,
+                         pl.d_tasks, bsz, qsz, st));
+  size_t t1 = 0, t2 = 0;
+  HIP_TRY(launch_exclusive_scan(bsz, boff, pl.ntasks + 1, nullptr, &t1, st));
+  void *s1 = A.alloc(t1);
+  if (!s1) return fail(SWX_ENOMEM, "device pool exhausted (scan)");
+  HIP_TRY(launch_exclusive_scan(bsz, boff, pl.ntasks + 1, s1, &t1, st));
+  HIP_TRY(launch_exclusive_scan(qsz, qoff, pl.ntasks + 1, nullptr, &t2, st));
+  void *s2 = A.alloc(t2);
+  if (!s2) return fail(SWX_ENOMEM, "device pool exhausted (scan)");
+  HIP_TRY(launch_exclusive_scan(qsz, qoff, pl.ntasks + 1, s2, &t2, st));
+  HIP_TRY(plan_offsets_dev(pl.ntasks, pl.d_tasks, boff, qoff, st));
+  int64_t tot[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(&tot[0], boff + pl.ntasks, 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&tot[1], qoff + pl.ntasks, 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  pl.d_bnd = A.get<uint32_t>(tot[0]);
+  if (!pl.d_bnd) return fail(SWX_ENOMEM, "device pool exhausted (boundary planes)");
+  if (!sc.qsel) {
+    pl.d_prof = A.get<uint8_t>(tot[1]);
+    if (!pl.d_prof) return fail(SWX_ENOMEM, "device pool exhausted (profiles)");
   }
   return SWX_OK;
 }
 
-// pack + fill for one plan
+// profile (general alphabets) + fill for one plan; when mark_fill >= 0,
+// events mark_fill and mark_fill + 1 bracket the fill kernel alone
 static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &view, bool rev,
-                    const int32_t *d_target, FillOut out) {
-  if (pl.tasks.empty()) return SWX_OK;
-  int rc = upload_plan(ctx, pl, sc.qsel);
-  if (rc) return rc;
-  PackArgs pk{};
-  pk.tasks = pl.d_tasks;
-  pk.ntasks = (int64_t)pl.tasks.size();
-  pk.slot_pair = pl.d_slot_pair;
-  pk.view = view;
-  pk.rsym = pl.d_rsym;
-  pk.qsel = pl.d_qsel;
-  pk.prof = pl.d_prof;
-  pk.matrix = sc.dmat;
-  pk.n = sc.n;
-  pk.bias = sc.bias;
-  pk.halves = pl.lane_bits == 16 ? 2 : 1;
-  pk.strip_rows = pl.R;
-  pk.mode = sc.qsel ? (int)kQSel : (int)kQGen;
-  pk.rev = rev ? 1 : 0;
-  HIP_TRY(inter_pack(pk, ctx->stream));
+                    const int32_t *d_target, FillOut out, int64_t score_bound,
+                    int mark_fill = -1) {
+  hipStream_t st = ctx->stream;
+  if (pl.ntasks == 0) {
+    if (mark_fill >= 0) {
+      HIP_TRY(hipEventRecord(ctx->ev[mark_fill], st));
+      HIP_TRY(hipEventRecord(ctx->ev[mark_fill + 1], st));
+    }
+    return SWX_OK;
+  }
+  if (!sc.qsel) {
+    PackArgs pk{};
+    pk.tasks = pl.d_tasks;
+    pk.ntasks = pl.ntasks;
+    pk.slot_pair = pl.d_sorted;
+    pk.view = view;
+    pk.prof = pl.d_prof;
+    pk.matrix = sc.dmat;
+    pk.n = sc.n;
+    pk.bias = sc.bias;
+    pk.halves = pl.lane_bits == 16 ? 2 : 1;
+    pk.strip_rows = pl.R;
+    pk.rev = rev ? 1 : 0;
+    HIP_TRY(inter_pack(pk, st));
+  }
   InterArgs a{};
   a.tasks = pl.d_tasks;
-  a.ntasks = (int64_t)pl.tasks.size();
-  a.slot_pair = pl.d_slot_pair;
+  a.ntasks = pl.ntasks;
+  a.slot_pair = pl.d_sorted;
   a.view = view;
-  a.rsym = pl.d_rsym;
-  a.qsel = pl.d_qsel;
-  a.prof = pl.d_prof;
+  a.prof = sc.qsel ? nullptr : pl.d_prof;
   a.bnd = pl.d_bnd;
   for (int k = 0; k < 8; ++k) a.lut[k] = sc.lut[k];
   a.n = sc.n;
@@ -270,16 +255,14 @@ static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &v
   a.e = sc.e;
   a.bias = sc.bias;
   a.rev = rev ? 1 : 0;
+  // without a possible score above the 16-bit value field the row code needs
+  // no saturation (scores are at most smax * min(qlen, rlen))
+  a.clamp = score_bound > kInter16Limit - 1 ? 1 : 0;
   a.target = d_target;
   a.out = out;
-  HIP_TRY(inter_fill(a, pl.lane_bits, pl.R, ctx->stream));
-  return SWX_OK;
-}
-
-template <class T>
-static int d2h(swx_ctx *ctx, std::vector<T> &dst, const T *src, int64_t n) {
-  dst.resize((size_t)n);
-  if (n) HIP_TRY(hipMemcpyAsync(dst.data(), src, sizeof(T) * n, hipMemcpyDeviceToHost, ctx->stream));
+  if (mark_fill >= 0) HIP_TRY(hipEventRecord(ctx->ev[mark_fill], st));
+  HIP_TRY(inter_fill(a, pl.lane_bits, pl.R, st));
+  if (mark_fill >= 0) HIP_TRY(hipEventRecord(ctx->ev[mark_fill + 1], st));
   return SWX_OK;
 }
 
@@ -293,12 +276,146 @@ static int scan(swx_ctx *ctx, const int64_t *in, int64_t *out, int64_t n) {
   return SWX_OK;
 }
 
-// ---- the pipeline -----------------------------------------------------------
+static int read_i64(swx_ctx *ctx, const int64_t *d, int64_t *h, int64_t n = 1) {
+  HIP_TRY(hipMemcpyAsync(h, d, 8 * n, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return SWX_OK;
+}
+
+// ids of the pairs whose flag is set (device list) and their count (host)
+static int select_flagged(swx_ctx *ctx, const uint8_t *flag, int64_t np, int64_t **ids,
+                          int64_t *count) {
+  DevArena &A = ctx->arena;
+  int64_t *f64 = A.get<int64_t>(np + 1), *pos = A.get<int64_t>(np + 1);
+  *ids = A.get<int64_t>(np);
+  if (!f64 || !pos || !*ids) return fail(SWX_ENOMEM, "device pool exhausted (select)");
+  HIP_TRY(hipMemsetAsync(f64 + np, 0, 8, ctx->stream));
+  HIP_TRY(flags_to_i64(np, flag, f64, ctx->stream));
+  int rc = scan(ctx, f64, pos, np + 1);
+  if (rc) return rc;
+  HIP_TRY(compact_flags(np, flag, pos, *ids, ctx->stream));
+  return read_i64(ctx, pos + np, count);
+}
+
+// ---- banded traceback: classify by band width, one register kernel per
+// width class, a general kernel for bands wider than 64 diagonals ------------
 struct DeviceBatch {
   const int8_t *qcat, *rcat;
   const int64_t *qoff, *roff, *pair_q, *pair_r;
   int64_t qcat_len, rcat_len, nq, nr, npairs;
 };
+
+static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, int64_t np,
+                         const int32_t *score, const int32_t *qbeg, const int32_t *qend,
+                         const int64_t *rbeg, const int64_t *rend, const int64_t *qstart,
+                         const int64_t *rstart, const int32_t *qlen, const int64_t *rlen,
+                         int32_t *cig_len, int64_t *cig_off_final, uint8_t *err,
+                         swx_batch_out *out, uint32_t *flags, int *rc_range) {
+  DevArena &A = ctx->arena;
+  hipStream_t st = ctx->stream;
+  int rc;
+  TbArgs ta{};
+  ta.score = score; ta.qbeg = qbeg; ta.qend = qend; ta.rbeg = rbeg; ta.rend = rend;
+  ta.qstart = qstart; ta.rstart = rstart; ta.qlen = qlen; ta.rlen = rlen;
+  ta.qcat = b.qcat; ta.rcat = b.rcat; ta.matrix = sc.dmat;
+  ta.n = sc.n; ta.o = sc.o; ta.e = sc.e; ta.smax = sc.smax;
+  ta.cig_len = cig_len; ta.err = err;
+  uint8_t *cls = A.get<uint8_t>(np);
+  uint64_t *k0 = A.get<uint64_t>(np), *k1 = A.get<uint64_t>(np);
+  int64_t *v0 = A.get<int64_t>(np), *v1 = A.get<int64_t>(np);
+  int64_t *ccap = A.get<int64_t>(np + 1), *coff = A.get<int64_t>(np + 1);
+  int64_t *counts = A.get<int64_t>(8);
+  if (!cls || !k0 || !k1 || !v0 || !v1 || !ccap || !coff || !counts)
+    return fail(SWX_ENOMEM, "device pool exhausted (traceback)");
+  HIP_TRY(hipMemsetAsync(ccap + np, 0, 8, st));
+  HIP_TRY(hipMemsetAsync(counts, 0, 64, st));
+  HIP_TRY(tb_classify(ta, np, cls, k0, v0, ccap, st));
+  if ((rc = scan(ctx, ccap, coff, np + 1))) return rc;
+  HIP_TRY(count_classes(np, cls, counts, st));
+  size_t tmp_bytes = 0;
+  int64_t *sorted = nullptr;
+  HIP_TRY(sort_keys(np, k0, k1, v0, v1, nullptr, &tmp_bytes, &sorted, st));
+  void *tmp = A.alloc(tmp_bytes);
+  if (!tmp) return fail(SWX_ENOMEM, "device pool exhausted (sort)");
+  HIP_TRY(sort_keys(np, k0, k1, v0, v1, tmp, &tmp_bytes, &sorted, st));
+  int64_t hc[8], capw = 0;
+  if ((rc = read_i64(ctx, counts, hc, 8))) return rc;
+  if ((rc = read_i64(ctx, coff + np, &capw))) return rc;
+  uint32_t *cscr = A.get<uint32_t>(capw);
+  if (!cscr) return fail(SWX_ENOMEM, "device pool exhausted (CIGAR scratch)");
+  ta.cig = cscr;
+  ta.cig_off = coff;
+  int64_t pos = hc[0];
+  for (int c = 1; c <= 4; ++c) {
+    const int64_t nc = hc[c];
+    if (nc == 0) continue;
+    const int32_t bw = 8 << (c - 1);
+    const int64_t nt = (nc + 63) / 64;
+    TbTask *tasks = A.get<TbTask>(nt);
+    int64_t *dsz = A.get<int64_t>(nt + 1), *doff = A.get<int64_t>(nt + 1);
+    if (!tasks || !dsz || !doff) return fail(SWX_ENOMEM, "device pool exhausted (traceback tasks)");
+    HIP_TRY(hipMemsetAsync(dsz + nt, 0, 8, st));
+    HIP_TRY(tb_tasks(pos, pos + nc, sorted, ta, bw, tasks, dsz, st));
+    if ((rc = scan(ctx, dsz, doff, nt + 1))) return rc;
+    HIP_TRY(tb_offsets(nt, tasks, doff, st));
+    int64_t words = 0;
+    if ((rc = read_i64(ctx, doff + nt, &words))) return rc;
+    ta.dir = A.get<uint32_t>(words);
+    if (!ta.dir) return fail(SWX_ENOMEM, "device pool exhausted (choice codes)");
+    HIP_TRY(tb_band(ta, tasks, nt, sorted, bw, st));
+    pos += nc;
+  }
+  if (hc[5] > 0) {   // bands wider than 64 diagonals: row strips, columns swept
+    const int64_t nc = hc[5];
+    const int64_t nt = (nc + 63) / 64;
+    TbwTask *tasks = A.get<TbwTask>(nt);
+    int64_t *dsz = A.get<int64_t>(nt + 1), *doff = A.get<int64_t>(nt + 1);
+    int64_t *bsz = A.get<int64_t>(nt + 1), *boff = A.get<int64_t>(nt + 1);
+    if (!tasks || !dsz || !doff || !bsz || !boff)
+      return fail(SWX_ENOMEM, "device pool exhausted (wide traceback tasks)");
+    HIP_TRY(hipMemsetAsync(dsz + nt, 0, 8, st));
+    HIP_TRY(hipMemsetAsync(bsz + nt, 0, 8, st));
+    HIP_TRY(tbw_tasks(pos, pos + nc, sorted, ta, tasks, dsz, bsz, st));
+    if ((rc = scan(ctx, dsz, doff, nt + 1))) return rc;
+    if ((rc = scan(ctx, bsz, boff, nt + 1))) return rc;
+    HIP_TRY(tbw_offsets(nt, tasks, doff, boff, st));
+    int64_t tot[2];
+    if ((rc = read_i64(ctx, doff + nt, &tot[0]))) return rc;
+    if ((rc = read_i64(ctx, boff + nt, &tot[1]))) return rc;
+    ta.dir = A.get<uint32_t>(tot[0]);
+    int32_t *bnd = A.get<int32_t>(tot[1]);
+    if (!ta.dir || !bnd) return fail(SWX_ENOMEM, "device pool exhausted (wide band)");
+    HIP_TRY(tb_strip(ta, tasks, nt, sorted, bnd, st));
+    pos += nc;
+  }
+  // final CIGAR offsets and compaction into the caller's arena
+  int64_t *len64 = A.get<int64_t>(np + 1);
+  if (!len64) return fail(SWX_ENOMEM, "device pool exhausted");
+  HIP_TRY(hipMemsetAsync(len64 + np, 0, 8, st));
+  HIP_TRY(lens_to_i64(np, cig_len, len64, st));
+  if ((rc = scan(ctx, len64, cig_off_final, np + 1))) return rc;
+  int64_t total = 0;
+  if ((rc = read_i64(ctx, cig_off_final + np, &total))) return rc;
+  out->cigar_used = total;
+  if (total > out->cigar_cap || (total > 0 && !out->cigar)) {
+    *flags &= ~SWX_CIGAR;   // records are still produced; CIGARs are not copied
+    *rc_range = SWX_ERANGE;
+    g_last_error = "CIGAR arena too small";
+    return SWX_OK;
+  }
+  uint32_t *dst = out->cigar, *dtmp = nullptr;
+  if (out->out_mem != SWX_MEM_DEVICE) {
+    dtmp = A.get<uint32_t>(total);
+    if (!dtmp) return fail(SWX_ENOMEM, "device pool exhausted");
+    dst = dtmp;
+  }
+  HIP_TRY(launch_cigar_compact(np, cscr, coff, cig_len, cig_off_final, dst, st));
+  if (dtmp && total)
+    HIP_TRY(hipMemcpyAsync(out->cigar, dtmp, sizeof(uint32_t) * total, hipMemcpyDeviceToHost, st));
+  return SWX_OK;
+}
+
+// ---- the pipeline -----------------------------------------------------------
 
 static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, uint32_t flags,
                         int32_t mask_len, swx_batch_out *out) {
@@ -306,16 +423,10 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
   hipStream_t st = ctx->stream;
   const int64_t np = b.npairs;
   if (flags & (SWX_CIGAR | SWX_SCORE2)) flags |= SWX_BEGIN;
-  int stage = 0;
-  auto mark = [&](int k) -> int {
-    HIP_TRY(hipEventRecord(ctx->ev[k], st));
-    stage = k;
-    return SWX_OK;
-  };
-  int rc = mark(0);
-  if (rc) return rc;
+  int rc;
+  HIP_TRY(hipEventRecord(ctx->ev[0], st));
 
-  // validation
+  // validation (before any alignment work)
   uint32_t *d_bad = A.get<uint32_t>(1);
   if (!d_bad) return fail(SWX_ENOMEM, "device pool exhausted");
   HIP_TRY(hipMemsetAsync(d_bad, 0, sizeof(uint32_t), st));
@@ -337,104 +448,66 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
   uint8_t *ovf = A.get<uint8_t>(np), *lanebits = A.get<uint8_t>(np), *err = A.get<uint8_t>(np);
   int32_t *qbeg = A.get<int32_t>(np), *score2 = A.get<int32_t>(np);
   int64_t *rbeg = A.get<int64_t>(np), *rend2 = A.get<int64_t>(np);
+  int64_t *stats = A.get<int64_t>(4);
   if (!qstart || !rstart || !rlen || !qlen || !score || !qend || !rend || !ovf || !lanebits ||
-      !err || !qbeg || !score2 || !rbeg || !rend2)
+      !err || !qbeg || !score2 || !rbeg || !rend2 || !stats)
     return fail(SWX_ENOMEM, "device pool exhausted (pair arrays)");
   HIP_TRY(hipMemsetAsync(err, 0, np, st));
   HIP_TRY(hipMemsetAsync(lanebits, 16, np, st));
   HIP_TRY(launch_views(np, b.qoff, b.roff, b.pair_q, b.pair_r, qstart, qlen, rstart, rlen, st));
-  std::vector<int32_t> hqlen;
-  std::vector<int64_t> hrlen;
-  if ((rc = d2h(ctx, hqlen, qlen, np))) return rc;
-  if ((rc = d2h(ctx, hrlen, rlen, np))) return rc;
-  HIP_TRY(hipStreamSynchronize(st));
   // a score can reach smax * min(qlen, rlen); the 32-bit lanes hold < 2^26
-  for (int64_t p = 0; p < np; ++p) {
-    if ((int64_t)std::max(sc.smax, 0) * std::min<int64_t>(hqlen[p], hrlen[p]) >= (1 << 26) - 1)
-      return fail(SWX_EOVERFLOW, "a score could exceed the 32-bit lane range");
-  }
+  HIP_TRY(hipMemsetAsync(stats, 0, 8 * 4, st));
+  HIP_TRY(launch_pair_stats(np, qlen, rlen, stats, st));
+  int64_t hstats[4];
+  if ((rc = read_i64(ctx, stats, hstats, 4))) return rc;
+  const int64_t score_bound = (int64_t)std::max(sc.smax, 0) * hstats[0];
+  if (score_bound >= (1 << 26) - 1)
+    return fail(SWX_EOVERFLOW, "a score could exceed the 32-bit lane range");
   PairView fview{qstart, rstart, qlen, rlen, b.qcat, b.rcat, 0};
   FillOut fout{score, qend, rend, ovf};
-  if ((rc = mark(1))) return rc;
 
-  // forward fill, 16-bit lanes
-  std::vector<int64_t> all(np);
-  std::iota(all.begin(), all.end(), 0);
+  // forward fill, 16-bit lanes (events 1 and 2 bracket the fill kernel)
   const int R = 32;
-  Plan p16;
-  plan_tasks(p16, all, hqlen.data(), hrlen.data(), nullptr, 16, R, sc.n, sc.qsel);
-  if ((rc = run_fill(ctx, p16, sc, fview, false, nullptr, fout))) return rc;
-  if ((rc = mark(2))) return rc;
+  Plan p16, p32;
+  if ((rc = plan_pass(ctx, sc, nullptr, np, qlen, rlen, nullptr, 16, R, p16))) return rc;
+  if ((rc = run_fill(ctx, p16, sc, fview, false, nullptr, fout, score_bound, 1))) return rc;
 
   // saturated pairs: exact re-run on 32-bit lanes
-  std::vector<uint8_t> hovf;
-  if ((rc = d2h(ctx, hovf, ovf, np))) return rc;
-  HIP_TRY(hipStreamSynchronize(st));
-  std::vector<int64_t> wide;
-  for (int64_t p = 0; p < np; ++p)
-    if (hovf[p]) wide.push_back(p);
-  Plan p32;
-  std::vector<uint8_t> is32(np, 0);
-  if (!wide.empty()) {
-    plan_tasks(p32, wide, hqlen.data(), hrlen.data(), nullptr, 32, R, sc.n, sc.qsel);
-    if ((rc = run_fill(ctx, p32, sc, fview, false, nullptr, fout))) return rc;
-    for (int64_t p : wide) is32[p] = 1;
-    uint8_t *d32 = A.get<uint8_t>(np);
-    if (!d32) return fail(SWX_ENOMEM, "device pool exhausted");
-    std::vector<uint8_t> lb(np);
-    for (int64_t p = 0; p < np; ++p) lb[p] = is32[p] ? 32 : 16;
-    HIP_TRY(hipMemcpyAsync(lanebits, lb.data(), np, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipStreamSynchronize(st));
+  int64_t *wide = nullptr, nwide = 0;
+  if ((rc = select_flagged(ctx, ovf, np, &wide, &nwide))) return rc;
+  if (nwide > 0) {
+    if ((rc = plan_pass(ctx, sc, wide, nwide, qlen, rlen, nullptr, 32, R, p32))) return rc;
+    if ((rc = run_fill(ctx, p32, sc, fview, false, nullptr, fout, score_bound))) return rc;
+    HIP_TRY(mark_lanes(nwide, wide, lanebits, 32, st));
   }
-  if ((rc = mark(3))) return rc;
+  HIP_TRY(hipEventRecord(ctx->ev[3], st));
 
   // reversed pass: begin
   if (flags & SWX_BEGIN) {
     int64_t *rqs = A.get<int64_t>(np), *rrs = A.get<int64_t>(np), *rrl = A.get<int64_t>(np);
-    int32_t *rql = A.get<int32_t>(np), *tgt = A.get<int32_t>(np);
+    int32_t *rql = A.get<int32_t>(np), *tgt = A.get<int32_t>(np), *band = A.get<int32_t>(np);
     int32_t *rsc = A.get<int32_t>(np), *rqe = A.get<int32_t>(np);
     int64_t *rre = A.get<int64_t>(np);
-    uint8_t *rov = A.get<uint8_t>(np);
-    if (!rqs || !rrs || !rrl || !rql || !tgt || !rsc || !rqe || !rre || !rov)
+    uint8_t *rov = A.get<uint8_t>(np), *f16 = A.get<uint8_t>(np), *f32 = A.get<uint8_t>(np);
+    if (!rqs || !rrs || !rrl || !rql || !tgt || !band || !rsc || !rqe || !rre || !rov || !f16 || !f32)
       return fail(SWX_ENOMEM, "device pool exhausted (reverse)");
     HIP_TRY(launch_rev_views(np, qstart, rstart, qlen, rlen, score, qend, rend, rqs, rql, rrs,
                              rrl, tgt, err, st));
-    std::vector<int32_t> hs, hqe;
-    std::vector<int64_t> hre;
-    if ((rc = d2h(ctx, hs, score, np))) return rc;
-    if ((rc = d2h(ctx, hqe, qend, np))) return rc;
-    if ((rc = d2h(ctx, hre, rend, np))) return rc;
-    HIP_TRY(hipStreamSynchronize(st));
-    std::vector<int32_t> rq(np), bandv(np);
-    std::vector<int64_t> rr(np);
-    std::vector<int64_t> ids16, ids32;
-    for (int64_t p = 0; p < np; ++p) {
-      if (hs[p] <= 0) { rq[p] = 0; rr[p] = 0; bandv[p] = 0; continue; }
-      rq[p] = hqe[p] + 1;
-      rr[p] = hre[p] + 1;
-      // every score1 alignment ending at the end cell stays within G' diagonals
-      // of the reversed start: G' = (smax*min(qe+1, re+1) - o + e - score1) / e
-      if (sc.e > 0) {
-        const int64_t mlen = std::min<int64_t>(rq[p], rr[p]);
-        int64_t g = ((int64_t)sc.smax * mlen - sc.o + sc.e - hs[p]) / sc.e;
-        if (g < 0) g = 0;
-        bandv[p] = (int32_t)std::min<int64_t>(g, 1 << 30);
-      } else {
-        bandv[p] = -1;
-      }
-      (is32[p] ? ids32 : ids16).push_back(p);
-    }
+    HIP_TRY(rev_prepare(np, score, qend, rend, lanebits, sc.smax, sc.o, sc.e, band, f16, f32, st));
+    HIP_TRY(hipMemsetAsync(rsc, 0, sizeof(int32_t) * np, st));
     PairView rview{rqs, rrs, rql, rrl, b.qcat, b.rcat, 1};
     FillOut rout{rsc, rqe, rre, rov};
-    HIP_TRY(hipMemsetAsync(rsc, 0, sizeof(int32_t) * np, st));
-    Plan r16, r32;
-    plan_tasks(r16, ids16, rq.data(), rr.data(), bandv.data(), 16, R, sc.n, sc.qsel);
-    if ((rc = run_fill(ctx, r16, sc, rview, true, tgt, rout))) return rc;
-    plan_tasks(r32, ids32, rq.data(), rr.data(), bandv.data(), 32, R, sc.n, sc.qsel);
-    if ((rc = run_fill(ctx, r32, sc, rview, true, tgt, rout))) return rc;
+    for (int lb : {16, 32}) {
+      int64_t *ids = nullptr, cnt = 0;
+      if ((rc = select_flagged(ctx, lb == 16 ? f16 : f32, np, &ids, &cnt))) return rc;
+      if (cnt == 0) continue;
+      Plan pr;
+      if ((rc = plan_pass(ctx, sc, ids, cnt, rql, rrl, band, lb, R, pr))) return rc;
+      if ((rc = run_fill(ctx, pr, sc, rview, true, tgt, rout, score_bound))) return rc;
+    }
     HIP_TRY(launch_begins(np, score, qend, rend, rsc, rqe, rre, qbeg, rbeg, err, st));
   }
-  if ((rc = mark(4))) return rc;
+  HIP_TRY(hipEventRecord(ctx->ev[4], st));
 
   // banded traceback: CIGAR
   int64_t *cig_off_final = A.get<int64_t>(np + 1);
@@ -442,95 +515,31 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
   if (!cig_off_final || !cig_len) return fail(SWX_ENOMEM, "device pool exhausted");
   HIP_TRY(hipMemsetAsync(cig_len, 0, sizeof(int32_t) * np, st));
   HIP_TRY(hipMemsetAsync(cig_off_final, 0, sizeof(int64_t) * (np + 1), st));
-  int64_t cig_total = 0;
+  int rc_range = SWX_OK;
   if (flags & SWX_CIGAR) {
-    int64_t *dsz = A.get<int64_t>(np + 1), *ccap = A.get<int64_t>(np + 1), *rcap = A.get<int64_t>(np + 1);
-    int64_t *doff = A.get<int64_t>(np + 1), *coff = A.get<int64_t>(np + 1), *roff = A.get<int64_t>(np + 1);
-    if (!dsz || !ccap || !rcap || !doff || !coff || !roff) return fail(SWX_ENOMEM, "device pool exhausted");
-    HIP_TRY(hipMemsetAsync(dsz, 0, sizeof(int64_t) * (np + 1), st));
-    HIP_TRY(hipMemsetAsync(ccap, 0, sizeof(int64_t) * (np + 1), st));
-    HIP_TRY(hipMemsetAsync(rcap, 0, sizeof(int64_t) * (np + 1), st));
-    HIP_TRY(launch_band_sizes(np, score, qbeg, qend, rbeg, rend, qlen, rlen, sc.smax, sc.o, sc.e,
-                              dsz, ccap, rcap, st));
-    if ((rc = scan(ctx, dsz, doff, np + 1))) return rc;
-    if ((rc = scan(ctx, ccap, coff, np + 1))) return rc;
-    if ((rc = scan(ctx, rcap, roff, np + 1))) return rc;
-    int64_t tot[3];
-    HIP_TRY(hipMemcpyAsync(&tot[0], doff + np, 8, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(&tot[1], coff + np, 8, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(&tot[2], roff + np, 8, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    uint8_t *dir = A.get<uint8_t>(tot[0]);
-    uint32_t *cscr = A.get<uint32_t>(tot[1]);
-    int32_t *rows = A.get<int32_t>(2 * tot[2]);
-    if (!dir || !cscr || !rows) return fail(SWX_ENOMEM, "device pool exhausted (band)");
-    BandArgs ba{};
-    ba.npairs = np;
-    ba.score = score;
-    ba.qbeg = qbeg; ba.qend = qend; ba.rbeg = rbeg; ba.rend = rend;
-    ba.qstart = qstart; ba.rstart = rstart;
-    ba.qlen = qlen; ba.rlen = rlen;
-    ba.qcat = b.qcat; ba.rcat = b.rcat;
-    ba.matrix = sc.dmat;
-    ba.n = sc.n; ba.o = sc.o; ba.e = sc.e; ba.smax = sc.smax;
-    ba.dir = dir; ba.dir_off = doff;
-    ba.rowbuf = rows; ba.row_off = roff;
-    ba.cig = cscr; ba.cig_off = coff;
-    ba.cig_len = cig_len;
-    ba.err = err;
-    HIP_TRY(launch_band_tb(ba, st));
-    // compaction offsets
-    int64_t *clen64 = A.get<int64_t>(np + 1);
-    if (!clen64) return fail(SWX_ENOMEM, "device pool exhausted");
-    std::vector<int32_t> hcl;
-    if ((rc = d2h(ctx, hcl, cig_len, np))) return rc;
-    HIP_TRY(hipStreamSynchronize(st));
-    std::vector<int64_t> hoff(np + 1, 0);
-    for (int64_t p = 0; p < np; ++p) hoff[p + 1] = hoff[p] + hcl[p];
-    cig_total = hoff[np];
-    HIP_TRY(hipMemcpyAsync(cig_off_final, hoff.data(), sizeof(int64_t) * (np + 1),
-                           hipMemcpyHostToDevice, st));
-    out->cigar_used = cig_total;
-    if (cig_total > out->cigar_cap || (cig_total > 0 && !out->cigar)) {
-      // records are still produced; CIGARs are not copied
-      flags &= ~SWX_CIGAR;
-      rc = SWX_ERANGE;
-      g_last_error = "CIGAR arena too small";
-    } else {
-      uint32_t *dst = out->cigar;
-      uint32_t *dtmp = nullptr;
-      if (out->out_mem != SWX_MEM_DEVICE) {
-        dtmp = A.get<uint32_t>(cig_total);
-        if (!dtmp) return fail(SWX_ENOMEM, "device pool exhausted");
-        dst = dtmp;
-      }
-      HIP_TRY(launch_cigar_compact(np, cscr, coff, cig_len, cig_off_final, dst, st));
-      if (dtmp && cig_total)
-        HIP_TRY(hipMemcpyAsync(out->cigar, dtmp, sizeof(uint32_t) * cig_total,
-                               hipMemcpyDeviceToHost, st));
-    }
+    if ((rc = run_traceback(ctx, sc, b, np, score, qbeg, qend, rbeg, rend, qstart, rstart, qlen,
+                            rlen, cig_len, cig_off_final, err, out, &flags, &rc_range)))
+      return rc;
   } else {
     out->cigar_used = 0;
   }
-  int rc_range = rc;
-  rc = mark(5);
-  if (rc) return rc;
+  HIP_TRY(hipEventRecord(ctx->ev[5], st));
 
   // score2 from the max array (final CM plane of the forward tasks)
   if (flags & SWX_SCORE2) {
     Score2InterArgs s2{};
     s2.rlen = rlen; s2.qlen = qlen; s2.score1 = score; s2.rbeg = rbeg; s2.rend = rend;
     s2.mask_len = mask_len; s2.score2 = score2; s2.rend2 = rend2;
-    s2.tasks = p16.d_tasks; s2.ntasks = (int64_t)p16.tasks.size(); s2.slot_pair = p16.d_slot_pair;
+    s2.tasks = p16.d_tasks; s2.ntasks = p16.ntasks; s2.slot_pair = p16.d_sorted;
     s2.bnd = p16.d_bnd; s2.halves = 2;
     HIP_TRY(launch_score2_inter(s2, st));
-    if (!p32.tasks.empty()) {
-      s2.tasks = p32.d_tasks; s2.ntasks = (int64_t)p32.tasks.size(); s2.slot_pair = p32.d_slot_pair;
+    if (p32.ntasks) {
+      s2.tasks = p32.d_tasks; s2.ntasks = p32.ntasks; s2.slot_pair = p32.d_sorted;
       s2.bnd = p32.d_bnd; s2.halves = 1;
       HIP_TRY(launch_score2_inter(s2, st));
     }
   }
-  if ((rc = mark(6))) return rc;
+  HIP_TRY(hipEventRecord(ctx->ev[6], st));
 
   // records
   swx_rec_dev *drec = (out->out_mem == SWX_MEM_DEVICE) ? (swx_rec_dev *)out->recs
@@ -540,20 +549,20 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
                          lanebits, flags, drec, st));
   if (out->out_mem != SWX_MEM_DEVICE && np)
     HIP_TRY(hipMemcpyAsync(out->recs, drec, sizeof(swx_rec) * np, hipMemcpyDeviceToHost, st));
-  if ((rc = mark(7))) return rc;
-  std::vector<uint8_t> herr;
-  if ((rc = d2h(ctx, herr, err, np))) return rc;
-  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipEventRecord(ctx->ev[7], st));
+  // consistency: any per-pair error flag
+  HIP_TRY(hipMemsetAsync(stats, 0, 8, st));
+  HIP_TRY(launch_any_flag(np, err, stats, st));
+  int64_t nerr = 0;
+  if ((rc = read_i64(ctx, stats, &nerr))) return rc;
   ctx->nstages = 7;
   for (int k = 0; k < 7; ++k) {
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[k], ctx->ev[k + 1]));
     ctx->stage_ms[k] = ms;
   }
-  for (int64_t p = 0; p < np; ++p)
-    if (herr[p]) return fail(SWX_EINTERNAL, "internal consistency check failed for pair " +
-                                                std::to_string(p));
-  (void)stage;
+  if (nerr) return fail(SWX_EINTERNAL, "internal consistency check failed for " +
+                                           std::to_string(nerr) + " pairs");
   return rc_range;
 }
 

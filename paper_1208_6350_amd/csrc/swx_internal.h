@@ -25,9 +25,7 @@ struct InterTask {
   int32_t band;       // reversed pass: band half-width around the main diagonal (-1: none)
   int64_t slot_base;  // slots are slot_pair[slot_base + s]
   int64_t bnd_off;    // boundary planes at bnd + bnd_off: 3 planes of rp*64 dwords
-  int64_t sym_off;    // packed reference symbols at rsym + sym_off: (rp/8)*64 uint4
-  int64_t qdata_off;  // QSEL: row selectors at qsel + off (qp*64 dwords);
-                      // QGEN: profile bytes at prof + off
+  int64_t qdata_off;  // QGEN: profile bytes at prof + off
                       //       ((qp/R) strips * (n+1) symbols * halves * 64 lanes * R rows)
 };
 
@@ -57,15 +55,14 @@ constexpr uint32_t kQGen = 1;    // any n: per-slot biased profile rows in globa
 struct InterArgs {
   const InterTask *tasks;
   int64_t ntasks;
-  const int64_t *slot_pair;   // slot -> pair id (-1: empty)
+  const int64_t *slot_pair;   // slot -> pair id
   PairView view;
-  const uint4 *rsym;          // packed reference symbols
-  const uint32_t *qsel;       // QSEL row selectors
-  const uint8_t *prof;        // QGEN profile bytes
+  const uint8_t *prof;        // QGEN profile bytes (null: QSEL)
   uint32_t *bnd;              // boundary planes (H, F, CM)
   uint32_t lut[8];            // QSEL: per reference symbol, biased scores of query symbols 0..3
   int32_t n, o, e, bias;
   int32_t rev;                // reversed pass: stop at target, band window, no CM plane
+  int32_t clamp;              // scores may exceed the 16-bit value field: saturate the code
   const int32_t *target;      // reversed pass: per pair score to reach
   FillOut out;
 };

@@ -16,16 +16,14 @@ struct swx_rec_dev {
   int32_t lane_bits;
 };
 
-struct PackArgs {
+struct PackArgs {            // QGEN profile construction
   const InterTask *tasks;
   int64_t ntasks;
   const int64_t *slot_pair;
   PairView view;
-  uint4 *rsym;
-  uint32_t *qsel;
   uint8_t *prof;
   const int8_t *matrix;   // n x n, [query symbol][reference symbol], device
-  int32_t n, bias, halves, strip_rows, mode, rev;
+  int32_t n, bias, halves, strip_rows, rev;
 };
 
 struct BandArgs {
@@ -44,6 +42,7 @@ struct BandArgs {
   uint32_t *cig;           const int64_t *cig_off;   // scratch runs
   int32_t *cig_len;
   uint8_t *err;
+  const uint8_t *only;     // when set, only pairs with only[p] == 5 (wide bands)
 };
 
 struct Score2InterArgs {
@@ -69,10 +68,68 @@ struct ValidateArgs {
   uint32_t *bad;          // bit flags: 1 offsets, 2 pair index, 4 query symbol, 8 reference symbol
 };
 
+// banded traceback
+struct TbTask {
+  int32_t nslots, rows, bw, pad_;
+  int64_t slot_base;
+  int64_t dir_off;     // dwords
+};
+
+struct TbwTask {        // wide-band traceback task (64 pairs)
+  int32_t nslots, pad_;
+  int64_t rows, wmax, dlo, width;
+  int64_t slot_base;
+  int64_t dir_off;      // dwords
+  int64_t bnd_off;      // ints
+};
+
+struct TbArgs {
+  const int32_t *score;
+  const int32_t *qbeg, *qend;
+  const int64_t *rbeg, *rend;
+  const int64_t *qstart, *rstart;
+  const int32_t *qlen;
+  const int64_t *rlen;
+  const int8_t *qcat, *rcat;
+  const int8_t *matrix;
+  int32_t n, o, e, smax;
+  uint32_t *dir;
+  uint32_t *cig;
+  const int64_t *cig_off;
+  int32_t *cig_len;
+  uint8_t *err;
+};
+
+hipError_t tb_classify(const TbArgs &a, int64_t npairs, uint8_t *cls, uint64_t *key, int64_t *vals,
+                       int64_t *ccap, hipStream_t st);
+hipError_t tb_tasks(int64_t n0, int64_t n1, const int64_t *sorted, const TbArgs &a, int32_t bw,
+                    TbTask *tasks, int64_t *dir_words, hipStream_t st);
+hipError_t tb_offsets(int64_t ntasks, TbTask *tasks, const int64_t *off, hipStream_t st);
+hipError_t tb_band(const TbArgs &a, const TbTask *tasks, int64_t ntasks, const int64_t *sorted,
+                   int32_t bw, hipStream_t st);
+hipError_t tbw_tasks(int64_t n0, int64_t n1, const int64_t *sorted, const TbArgs &a,
+                     TbwTask *tasks, int64_t *dir_words, int64_t *bnd_words, hipStream_t st);
+hipError_t tbw_offsets(int64_t ntasks, TbwTask *tasks, const int64_t *doff, const int64_t *boff,
+                       hipStream_t st);
+hipError_t tb_strip(const TbArgs &a, const TbwTask *tasks, int64_t ntasks, const int64_t *sorted,
+                    int32_t *bndbuf, hipStream_t st);
+hipError_t count_classes(int64_t n, const uint8_t *cls, int64_t *counts, hipStream_t st);
+hipError_t sort_keys(int64_t n, uint64_t *keys, uint64_t *keys_alt, int64_t *vals,
+                     int64_t *vals_alt, void *tmp, size_t *tmp_bytes, int64_t **sorted_out,
+                     hipStream_t st);
+hipError_t rev_prepare(int64_t npairs, const int32_t *score, const int32_t *qend,
+                       const int64_t *rend, const uint8_t *lanebits, int32_t smax, int32_t o,
+                       int32_t e, int32_t *band, uint8_t *f16, uint8_t *f32, hipStream_t st);
+
 hipError_t inter_fill(const InterArgs &a, int lane_bits, int R, hipStream_t st);
 hipError_t inter_pack(const PackArgs &a, hipStream_t st);
 
 hipError_t launch_validate(const ValidateArgs &a, hipStream_t st);
+hipError_t launch_pair_stats(int64_t n, const int32_t *qlen, const int64_t *rlen, int64_t *stats,
+                             hipStream_t st);
+hipError_t lens_to_i64(int64_t n, const int32_t *len, int64_t *out, hipStream_t st);
+hipError_t mark_lanes(int64_t n, const int64_t *ids, uint8_t *lanebits, int v, hipStream_t st);
+hipError_t launch_any_flag(int64_t n, const uint8_t *flag, int64_t *count, hipStream_t st);
 hipError_t launch_views(int64_t npairs, const int64_t *qoff, const int64_t *roff,
                         const int64_t *pair_q, const int64_t *pair_r, int64_t *qstart,
                         int32_t *qlen, int64_t *rstart, int64_t *rlen, hipStream_t st);
@@ -83,7 +140,8 @@ hipError_t launch_rev_views(int64_t npairs, const int64_t *qstart, const int64_t
                             int32_t *target, uint8_t *err, hipStream_t st);
 hipError_t launch_band_sizes(int64_t npairs, const int32_t *score, const int32_t *qbeg,
                              const int32_t *qend, const int64_t *rbeg, const int64_t *rend,
-                             const int32_t *qlen, const int64_t *rlen, int32_t smax, int32_t o, int32_t e, int64_t *dir_size,
+                             const int32_t *qlen, const int64_t *rlen, const uint8_t *only,
+                             int32_t smax, int32_t o, int32_t e, int64_t *dir_size,
                              int64_t *cig_cap, int64_t *row_cap, hipStream_t st);
 hipError_t launch_band_tb(const BandArgs &a, hipStream_t st);
 hipError_t launch_cigar_compact(int64_t npairs, const uint32_t *src, const int64_t *src_off,
@@ -102,6 +160,19 @@ hipError_t launch_records(int64_t npairs, const int32_t *score1, const int32_t *
 hipError_t launch_begins(int64_t npairs, const int32_t *score1, const int32_t *qend,
                          const int64_t *rend, const int32_t *rscore, const int32_t *rqend,
                          const int64_t *rrend, int32_t *qbeg, int64_t *rbeg, uint8_t *err,
+                         hipStream_t st);
+hipError_t plan_sort(int64_t n, const int64_t *ids, const int32_t *qlen, const int64_t *rlen,
+                     const int32_t *band, int32_t R, uint64_t *keys, uint64_t *keys_alt,
+                     int64_t *vals, int64_t *vals_alt, void *tmp, size_t *tmp_bytes,
+                     int64_t **sorted_out, hipStream_t st);
+hipError_t plan_tasks_dev(int64_t n, int64_t ntasks, int32_t slots, int32_t R,
+                          int64_t qdata_per_row, const int64_t *sorted, const int32_t *qlen,
+                          const int64_t *rlen, const int32_t *band, InterTask *tasks,
+                          int64_t *bnd_size, int64_t *qdata_size, hipStream_t st);
+hipError_t plan_offsets_dev(int64_t ntasks, InterTask *tasks, const int64_t *bnd_off,
+                            const int64_t *qdata_off, hipStream_t st);
+hipError_t flags_to_i64(int64_t n, const uint8_t *flag, int64_t *f64, hipStream_t st);
+hipError_t compact_flags(int64_t n, const uint8_t *flag, const int64_t *pos, int64_t *out,
                          hipStream_t st);
 hipError_t launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, void *tmp,
                                  size_t *tmp_bytes, hipStream_t st);

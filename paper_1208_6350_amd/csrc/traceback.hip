@@ -1,0 +1,564 @@
+// traceback.hip -- the banded pass that produces the detailed alignment.
+//
+// Method section: "the banded SW (whose band is defined by the beginning and
+// ending positions) generates the detailed alignment".  For each pair the
+// global 3-state DP on q[qbeg..qend] x r[rbeg..rend] is filled inside the
+// safe band (every path of score score1 has at most G gap symbols, so it stays
+// within a fixed set of diagonals; inside any superset of that set the DP
+// values on those paths are exact), a 4-bit choice code is stored per cell,
+// and the path is traced back from the end cell with rule T3 (M, then D, then
+// I; inside a gap "open" before "extend").
+//
+// Layout: one lane per pair, 64 pairs of similar band width per wave.  The
+// band of a lane is BW diagonals starting at its own lowest diagonal; BW is
+// the task's width class (8, 16, 32 or 64), a superset of the lane's band.
+// The previous row of H and F lives in registers; cells left of column 0 hold
+// -inf and cells right of the last column only feed cells right of it, so no
+// per-cell masking is needed.  Choice codes of one row are packed 8 per dword
+// and stored lane-interleaved (coalesced).
+#include <hip/hip_runtime.h>
+
+#include "swx_internal.h"
+#include "swx_kernels.h"
+
+namespace swx {
+
+constexpr int32_t kNeg = -(1 << 29);
+
+__device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+  return q;
+}
+
+// lowest diagonal and width of the safe band of one pair
+__device__ __forceinline__ void safe_band(int64_t m, int64_t w, int64_t s1, int32_t smax, int32_t o,
+                                          int32_t e, int64_t *dlo, int64_t *bw) {
+  const int64_t D = w - m;
+  const int64_t num = (int64_t)smax * (m + w) - 2 * o + 2 * e - 2 * s1;
+  const int64_t den = (int64_t)smax + 2 * e;
+  const int64_t G = den > 0 ? floor_div64(num, den) : (m + w);
+  const int64_t aD = D < 0 ? -D : D;
+  const int64_t hw = (G - aD) >= 0 ? (G - aD) / 2 : 0;
+  *dlo = (D < 0 ? D : 0) - hw;
+  *bw = ((D > 0 ? D : 0) + hw) - *dlo + 1;
+}
+
+__device__ __forceinline__ bool tb_coords_ok(const TbArgs &a, int64_t p) {
+  return a.qbeg[p] >= 0 && a.qbeg[p] <= a.qend[p] && a.qend[p] < a.qlen[p] && a.rbeg[p] >= 0 &&
+         a.rbeg[p] <= a.rend[p] && a.rend[p] < a.rlen[p];
+}
+
+// per pair: band class (0: none, 1..4: BW 8/16/32/64, 5: wider), rows, key
+__global__ void k_tb_classify(TbArgs a, int64_t npairs, uint8_t *cls, uint64_t *key,
+                              int64_t *vals, int64_t *ccap) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  uint8_t c = 0;
+  int64_t m = 0, w = 0, bw = 0, dlo = 0;
+  if (a.score[p] > 0) {
+    if (tb_coords_ok(a, p)) {
+      m = a.qend[p] - a.qbeg[p] + 1;
+      w = a.rend[p] - a.rbeg[p] + 1;
+      safe_band(m, w, a.score[p], a.smax, a.o, a.e, &dlo, &bw);
+      c = bw <= 8 ? 1 : bw <= 16 ? 2 : bw <= 32 ? 3 : bw <= 64 ? 4 : 5;
+    } else {
+      a.err[p] = 1;
+    }
+  }
+  cls[p] = c;
+  key[p] = ((uint64_t)c << 40) | (uint64_t)(m > 0xFFFFFFFFFll ? 0xFFFFFFFFFll : m);
+  vals[p] = p;
+  ccap[p] = (c != 0) ? (m + w + 2) : 0;
+}
+
+__global__ void k_tb_tasks(int64_t n0, int64_t n1, const int64_t *sorted, const TbArgs a,
+                           int32_t bw, TbTask *tasks, int64_t *dir_words) {
+  // tasks over sorted[n0 .. n1)
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ntasks = (n1 - n0 + 63) / 64;
+  if (t >= ntasks) return;
+  const int64_t s0 = n0 + t * 64;
+  const int64_t s1 = (s0 + 64 < n1) ? s0 + 64 : n1;
+  int64_t rows = 1;
+  for (int64_t k = s0; k < s1; ++k) {
+    const int64_t p = sorted[k];
+    const int64_t m = a.qend[p] - a.qbeg[p] + 1;
+    rows = m > rows ? m : rows;
+  }
+  TbTask tk{};
+  tk.nslots = (int32_t)(s1 - s0);
+  tk.rows = (int32_t)rows;
+  tk.bw = bw;
+  tk.slot_base = s0;
+  tasks[t] = tk;
+  dir_words[t] = (rows + 1) * (bw / 8) * 64;
+}
+
+__global__ void k_tb_offsets(int64_t ntasks, TbTask *tasks, const int64_t *off) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < ntasks) tasks[t].dir_off = off[t];
+}
+
+template <int BW, bool LUT4>
+__global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, int64_t ntasks,
+                                                 const int64_t *sorted) {
+  __shared__ int8_t s_mat[32 * 32];
+  for (int k = threadIdx.x; k < a.n * a.n; k += blockDim.x) s_mat[k] = a.matrix[k];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t tid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (tid >= ntasks) return;
+  const TbTask tk = tasks[tid];
+  const bool live = lane < tk.nslots;
+  const int64_t p = live ? sorted[tk.slot_base + lane] : -1;
+  int64_t m = 1, w = 1, dlo = 0, bwl = 1;
+  int32_t s1 = 0;
+  const int8_t *q = a.qcat, *r = a.rcat;
+  if (live) {
+    s1 = a.score[p];
+    m = a.qend[p] - a.qbeg[p] + 1;
+    w = a.rend[p] - a.rbeg[p] + 1;
+    safe_band(m, w, s1, a.smax, a.o, a.e, &dlo, &bwl);
+    q = a.qcat + a.qstart[p] + a.qbeg[p];
+    r = a.rcat + a.rstart[p] + a.rbeg[p];
+  }
+  const int32_t o = a.o, e = a.e;
+  uint32_t *dir = a.dir + tk.dir_off;
+  constexpr int ND = BW / 8;        // direction dwords per row
+  constexpr int NW = BW / 4 + 2;    // reference window dwords
+
+  // reference window: byte k of the window = symbol at local column
+  // base + k (1-based columns j use symbol r[j-1]); row i covers j = i+dlo+k
+  auto ref_byte = [&](int64_t j) -> uint32_t {   // symbol code of column j (1-based)
+    if (!live || j < 1 || j > w) return 0u;
+    const uint32_t v = (uint32_t)(uint8_t)r[j - 1];
+    return LUT4 ? v * 8u : v;
+  };
+  uint32_t win[NW];
+  {
+    const int64_t j0 = 1 + dlo;   // row 1, k = 0
+#pragma unroll
+    for (int d = 0; d < NW; ++d) {
+      uint32_t v = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) v |= ref_byte(j0 + 4 * d + b) << (8 * b);
+      win[d] = v;
+    }
+  }
+  int32_t H[BW], F[BW];
+  // row 0: H(0,0) = 0, H(0,j) = E(0,j) = -(o + (j-1)e); F(0,.) = -inf
+  {
+    uint32_t dw[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) dw[d] = 0;
+#pragma unroll
+    for (int k = 0; k < BW; ++k) {
+      const int64_t j = dlo + k;
+      int32_t h = kNeg;
+      uint32_t c = 0;
+      if (j == 0) h = 0;
+      else if (j > 0) {
+        h = -(o + (int32_t)(j - 1) * e);
+        c = 1u | ((j == 1 || o <= e) ? 4u : 0u);
+      }
+      H[k] = h;
+      F[k] = kNeg;
+      dw[k >> 3] |= c << (4 * (k & 7));
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) dir[(int64_t)d * 64 + lane] = dw[d];
+  }
+  int32_t hend = kNeg;
+  const int64_t kend = w - m - dlo;
+  for (int64_t i = 1; i <= tk.rows; ++i) {
+    int32_t lut = 0, qn = 0;
+    if (live && i <= m) {
+      const int32_t qs = q[i - 1];
+      if (LUT4) {
+        uint32_t l = 0;
+        for (int b = 0; b < a.n; ++b) l |= (uint32_t)(uint8_t)s_mat[qs * a.n + b] << (8 * b);
+        lut = (int32_t)l;
+      } else {
+        qn = qs * a.n;
+      }
+    }
+    uint32_t dw[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) dw[d] = 0;
+    int32_t ev = kNeg, hleft = kNeg;
+#pragma unroll
+    for (int k = 0; k < BW; ++k) {
+      const uint32_t sym = __builtin_amdgcn_ubfe(win[k >> 2], 8 * (k & 3), 8);
+      const int32_t sc = LUT4 ? __builtin_amdgcn_sbfe(lut, sym, 8) : (int32_t)s_mat[qn + sym];
+      const int32_t hup = (k + 1 < BW) ? H[k + 1] : kNeg;
+      const int32_t fup = (k + 1 < BW) ? F[k + 1] : kNeg;
+      const int32_t diag = H[k] + sc;
+      const int32_t fo = hup - o, fx = fup - e;
+      const int32_t fij = fo > fx ? fo : fx;
+      const int32_t eo = hleft - o, ex = ev - e;
+      const int32_t eij = eo > ex ? eo : ex;
+      int32_t h = diag > eij ? diag : eij;
+      h = h > fij ? h : fij;
+      uint32_t c = (h == diag) ? 0u : (h == eij ? 1u : 2u);
+      c |= (eo >= ex) ? 4u : 0u;
+      c |= (fo >= fx) ? 8u : 0u;
+      dw[k >> 3] |= c << (4 * (k & 7));
+      H[k] = h;
+      F[k] = fij;
+      ev = eij;
+      hleft = h;
+    }
+    uint32_t *drow = dir + (int64_t)i * ND * 64;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) drow[(int64_t)d * 64 + lane] = dw[d];
+    if (live && i == m) {
+#pragma unroll
+      for (int k = 0; k < BW; ++k)
+        if (k == kend) hend = H[k];
+    }
+    // slide the reference window one column to the right
+    const uint32_t nb = ref_byte(i + 1 + dlo + 4 * NW - 1);
+#pragma unroll
+    for (int d = 0; d < NW - 1; ++d) win[d] = __builtin_amdgcn_alignbyte(win[d + 1], win[d], 1);
+    win[NW - 1] = (win[NW - 1] >> 8) | (nb << 24);
+  }
+  if (!live) return;
+  if (s1 <= 0) { a.cig_len[p] = 0; return; }
+  if (hend != s1 || kend < 0 || kend >= BW) a.err[p] = 1;
+  // traceback from (m, w) in state H; runs are written end -> begin, then reversed
+  uint32_t *out = a.cig + a.cig_off[p];
+  int32_t nruns = 0;
+  int64_t i = m, j = w;
+  int state = 0;
+  uint32_t cur_op = 0xFF, cur_len = 0;
+  int64_t guard = 2 * (m + w) + 4;
+  while ((i > 0 || j > 0) && guard-- > 0) {
+    const int64_t k = j - i - dlo;
+    if (k < 0 || k >= BW) { a.err[p] = 1; break; }
+    const uint32_t c = (dir[((int64_t)i * ND + (k >> 3)) * 64 + lane] >> (4 * (k & 7))) & 0xFu;
+    uint32_t op = 0xFF;
+    if (state == 0) {
+      const uint32_t src = c & 3u;
+      if (src == 0 && i > 0 && j > 0) { op = 0; --i; --j; }
+      else if (src == 1) state = 1;
+      else state = 2;
+    } else if (state == 1) {
+      op = 2;
+      state = (c & 4u) ? 0 : 1;
+      --j;
+    } else {
+      op = 1;
+      state = (c & 8u) ? 0 : 2;
+      --i;
+    }
+    if (op != 0xFF) {
+      if (op == cur_op) ++cur_len;
+      else {
+        if (cur_len) out[nruns++] = (cur_len << 4) | cur_op;
+        cur_op = op;
+        cur_len = 1;
+      }
+    }
+  }
+  if (i != 0 || j != 0) a.err[p] = 1;
+  if (cur_len) out[nruns++] = (cur_len << 4) | cur_op;
+  for (int32_t x = 0, y = nruns - 1; x < y; ++x, --y) {
+    const uint32_t t = out[x]; out[x] = out[y]; out[y] = t;
+  }
+  a.cig_len[p] = nruns;
+}
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t tb_classify(const TbArgs &a, int64_t npairs, uint8_t *cls, uint64_t *key, int64_t *vals,
+                       int64_t *ccap, hipStream_t st) {
+  if (!npairs) return hipSuccess;
+  hipLaunchKernelGGL(k_tb_classify, dim3(nblk(npairs, 256)), dim3(256), 0, st, a, npairs, cls, key,
+                     vals, ccap);
+  return hipGetLastError();
+}
+
+hipError_t tb_tasks(int64_t n0, int64_t n1, const int64_t *sorted, const TbArgs &a, int32_t bw,
+                    TbTask *tasks, int64_t *dir_words, hipStream_t st) {
+  const int64_t nt = (n1 - n0 + 63) / 64;
+  if (nt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tb_tasks, dim3(nblk(nt, 128)), dim3(128), 0, st, n0, n1, sorted, a, bw,
+                     tasks, dir_words);
+  return hipGetLastError();
+}
+
+hipError_t tb_offsets(int64_t ntasks, TbTask *tasks, const int64_t *off, hipStream_t st) {
+  if (!ntasks) return hipSuccess;
+  hipLaunchKernelGGL(k_tb_offsets, dim3(nblk(ntasks, 128)), dim3(128), 0, st, ntasks, tasks, off);
+  return hipGetLastError();
+}
+
+template <int BW>
+static hipError_t launch_band(const TbArgs &a, const TbTask *tasks, int64_t ntasks,
+                              const int64_t *sorted, bool lut4, hipStream_t st) {
+  const unsigned blocks = nblk(ntasks, 4);
+  if (lut4)
+    hipLaunchKernelGGL((k_tb_band<BW, true>), dim3(blocks), dim3(256), 0, st, a, tasks, ntasks, sorted);
+  else
+    hipLaunchKernelGGL((k_tb_band<BW, false>), dim3(blocks), dim3(256), 0, st, a, tasks, ntasks, sorted);
+  return hipGetLastError();
+}
+
+hipError_t tb_band(const TbArgs &a, const TbTask *tasks, int64_t ntasks, const int64_t *sorted,
+                   int32_t bw, hipStream_t st) {
+  if (!ntasks) return hipSuccess;
+  const bool lut4 = a.n <= 4;
+  switch (bw) {
+    case 8: return launch_band<8>(a, tasks, ntasks, sorted, lut4, st);
+    case 16: return launch_band<16>(a, tasks, ntasks, sorted, lut4, st);
+    case 32: return launch_band<32>(a, tasks, ntasks, sorted, lut4, st);
+    case 64: return launch_band<64>(a, tasks, ntasks, sorted, lut4, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+
+// ---- wide bands: row strips in registers, columns swept left to right ------
+// One lane per pair; the task's strip s covers rows sR+1 .. sR+R (1-based,
+// row 0 is the virtual row before the begin) and columns
+// [c0(s), c0(s) + W) with c0(s) = sR + 1 + dlo_min, clipped to [0, wmax]; W =
+// R + width of the union of the lanes' bands, so every lane computes a
+// superset of its own safe band.  H and F of a strip's last row are handed to
+// the next strip through global memory; choice codes are stored per
+// (strip, column) as R nibbles (two dwords for R = 16), lane-interleaved.
+namespace {
+constexpr int kStripR = 16;
+}
+
+__global__ void k_tbw_tasks(int64_t n0, int64_t n1, const int64_t *sorted, const TbArgs a,
+                            TbwTask *tasks, int64_t *dir_words, int64_t *bnd_words) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ntasks = (n1 - n0 + 63) / 64;
+  if (t >= ntasks) return;
+  const int64_t s0 = n0 + t * 64;
+  const int64_t s1 = (s0 + 64 < n1) ? s0 + 64 : n1;
+  int64_t rows = 1, wmax = 1, dlo_min = 0, dhi_max = 0;
+  for (int64_t k = s0; k < s1; ++k) {
+    const int64_t p = sorted[k];
+    const int64_t m = a.qend[p] - a.qbeg[p] + 1, w = a.rend[p] - a.rbeg[p] + 1;
+    int64_t dlo, bw;
+    safe_band(m, w, a.score[p], a.smax, a.o, a.e, &dlo, &bw);
+    rows = m > rows ? m : rows;
+    wmax = w > wmax ? w : wmax;
+    dlo_min = dlo < dlo_min ? dlo : dlo_min;
+    dhi_max = (dlo + bw - 1) > dhi_max ? (dlo + bw - 1) : dhi_max;
+  }
+  TbwTask tk{};
+  tk.nslots = (int32_t)(s1 - s0);
+  tk.rows = rows;
+  tk.wmax = wmax;
+  tk.dlo = dlo_min;
+  tk.width = kStripR + (dhi_max - dlo_min + 1);
+  tk.slot_base = s0;
+  tasks[t] = tk;
+  const int64_t nstrips = (rows + kStripR - 1) / kStripR;
+  dir_words[t] = (nstrips * tk.width + tk.width) * 2 * 64;   // + row 0
+  bnd_words[t] = 2 * (wmax + 1) * 64;
+}
+
+__global__ void k_tbw_offsets(int64_t ntasks, TbwTask *tasks, const int64_t *doff,
+                              const int64_t *boff) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < ntasks) { tasks[t].dir_off = doff[t]; tasks[t].bnd_off = boff[t]; }
+}
+
+template <bool LUT4>
+__global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks, int64_t ntasks,
+                                                  const int64_t *sorted, int32_t *bndbuf) {
+  constexpr int R = kStripR;
+  __shared__ int8_t s_mat[32 * 32];
+  for (int k = threadIdx.x; k < a.n * a.n; k += blockDim.x) s_mat[k] = a.matrix[k];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t tid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (tid >= ntasks) return;
+  const TbwTask tk = tasks[tid];
+  const bool live = lane < tk.nslots;
+  const int64_t p = live ? sorted[tk.slot_base + lane] : -1;
+  int64_t m = 1, w = 1, dlo = 0, bwl = 1;
+  int32_t s1 = 0;
+  const int8_t *q = a.qcat, *r = a.rcat;
+  if (live) {
+    s1 = a.score[p];
+    m = a.qend[p] - a.qbeg[p] + 1;
+    w = a.rend[p] - a.rbeg[p] + 1;
+    safe_band(m, w, s1, a.smax, a.o, a.e, &dlo, &bwl);
+    q = a.qcat + a.qstart[p] + a.qbeg[p];
+    r = a.rcat + a.rstart[p] + a.rbeg[p];
+  }
+  const int32_t o = a.o, e = a.e;
+  uint32_t *dir = a.dir + tk.dir_off;
+  int32_t *bH = bndbuf + tk.bnd_off;
+  int32_t *bF = bH + (tk.wmax + 1) * 64;
+  const int64_t W = tk.width;
+  // row 0 (virtual): H(0,0) = 0, H(0,j) = E(0,j) = -(o + (j-1)e), F = -inf.
+  // Its choice codes sit before strip 0 (W columns starting at column 0).
+  for (int64_t j = 0; j <= tk.wmax; ++j) {
+    bH[j * 64 + lane] = (j == 0) ? 0 : -(o + (int32_t)(j - 1) * e);
+    bF[j * 64 + lane] = kNeg;
+  }
+  for (int64_t j = 0; j < W; ++j) {
+    const uint32_t c = (j == 0) ? 0u : (1u | ((j == 1 || o <= e) ? 4u : 0u));
+    dir[(j * 2) * 64 + lane] = c;
+    dir[(j * 2 + 1) * 64 + lane] = 0;
+  }
+  const int64_t nstrips = (tk.rows + R - 1) / R;
+  int64_t plo = 0, phi = tk.wmax + 1;   // columns of row sR that hold valid values
+  for (int64_t s = 0; s < nstrips; ++s) {
+    const int64_t sR = s * R;
+    const int64_t cstart = sR + 1 + tk.dlo;             // unclipped window start
+    const int64_t clo = cstart > 0 ? cstart : 0;
+    int64_t chi = cstart + W;
+    if (chi > tk.wmax + 1) chi = tk.wmax + 1;
+    uint32_t *sdir = dir + (W + s * W) * 2 * 64;
+    // row symbols and per-row score tables
+    int32_t lut[R];
+    int32_t qn[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int64_t i = sR + 1 + k;
+      lut[k] = 0;
+      qn[k] = 0;
+      if (live && i <= m) {
+        const int32_t qs = q[i - 1];
+        if (LUT4) {
+          uint32_t l = 0;
+          for (int b = 0; b < a.n; ++b) l |= (uint32_t)(uint8_t)s_mat[qs * a.n + b] << (8 * b);
+          lut[k] = (int32_t)l;
+        } else {
+          qn[k] = qs * a.n;
+        }
+      }
+    }
+    int32_t H[R], E[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) { H[k] = kNeg; E[k] = kNeg; }
+    int32_t hdtop = (clo >= 1 && clo - 1 >= plo && clo - 1 < phi) ? bH[(clo - 1) * 64 + lane] : kNeg;
+    for (int64_t j = clo; j < chi; ++j) {
+      const bool inprev = j >= plo && j < phi;
+      const int32_t hup0 = inprev ? bH[j * 64 + lane] : kNeg;
+      const int32_t fup0 = inprev ? bF[j * 64 + lane] : kNeg;
+      uint32_t sym = 0;
+      if (live && j >= 1 && j <= w) sym = (uint32_t)(uint8_t)r[j - 1];
+      const uint32_t sym8 = LUT4 ? sym * 8u : sym;
+      int32_t hdiag = hdtop;
+      hdtop = hup0;
+      int32_t hup = hup0, fup = fup0;
+      uint32_t dw0 = 0, dw1 = 0;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int32_t sc = LUT4 ? __builtin_amdgcn_sbfe(lut[k], sym8, 8) : (int32_t)s_mat[qn[k] + sym];
+        const int32_t diag = hdiag + sc;
+        const int32_t fo = hup - o, fx = fup - e;
+        const int32_t fij = fo > fx ? fo : fx;
+        const int32_t eo = H[k] - o, ex = E[k] - e;      // H[k], E[k] = row k at column j-1
+        const int32_t eij = eo > ex ? eo : ex;
+        int32_t h = diag > eij ? diag : eij;
+        h = h > fij ? h : fij;
+        uint32_t c = (h == diag) ? 0u : (h == eij ? 1u : 2u);
+        c |= (eo >= ex) ? 4u : 0u;
+        c |= (fo >= fx) ? 8u : 0u;
+        if (k < 8) dw0 |= c << (4 * k);
+        else dw1 |= c << (4 * (k - 8));
+        hdiag = H[k];
+        H[k] = h;
+        E[k] = eij;
+        hup = h;
+        fup = fij;
+      }
+      const int64_t jc = j - cstart;
+      sdir[(jc * 2) * 64 + lane] = dw0;
+      sdir[(jc * 2 + 1) * 64 + lane] = dw1;
+      bH[j * 64 + lane] = H[R - 1];
+      bF[j * 64 + lane] = fup;
+    }
+    plo = clo;
+    phi = chi;
+  }
+  if (!live) return;
+  if (s1 <= 0) { a.cig_len[p] = 0; return; }
+  // traceback from (m, w) in state H
+  uint32_t *out = a.cig + a.cig_off[p];
+  int32_t nruns = 0;
+  int64_t i = m, j = w;
+  int state = 0;
+  uint32_t cur_op = 0xFF, cur_len = 0;
+  int64_t guard = 2 * (m + w) + 4;
+  while ((i > 0 || j > 0) && guard-- > 0) {
+    uint32_t c;
+    if (i == 0) {
+      c = (j == 0) ? 0u : (1u | ((j == 1 || o <= e) ? 4u : 0u));
+    } else {
+      const int64_t s = (i - 1) / R, k = (i - 1) % R;
+      const int64_t jc = j - (s * R + 1 + tk.dlo);
+      if (jc < 0 || jc >= W || j > tk.wmax) { a.err[p] = 1; break; }
+      const uint32_t dwv = dir[(W + s * W + jc) * 2 * 64 + (k >> 3) * 64 + lane];
+      c = (dwv >> (4 * (k & 7))) & 0xFu;
+    }
+    uint32_t op = 0xFF;
+    if (state == 0) {
+      const uint32_t src = c & 3u;
+      if (src == 0 && i > 0 && j > 0) { op = 0; --i; --j; }
+      else if (src == 1) state = 1;
+      else state = 2;
+    } else if (state == 1) {
+      op = 2;
+      state = (c & 4u) ? 0 : 1;
+      --j;
+    } else {
+      op = 1;
+      state = (c & 8u) ? 0 : 2;
+      --i;
+    }
+    if (op != 0xFF) {
+      if (op == cur_op) ++cur_len;
+      else {
+        if (cur_len) out[nruns++] = (cur_len << 4) | cur_op;
+        cur_op = op;
+        cur_len = 1;
+      }
+    }
+  }
+  if (i != 0 || j != 0) a.err[p] = 1;
+  if (cur_len) out[nruns++] = (cur_len << 4) | cur_op;
+  for (int32_t x = 0, y = nruns - 1; x < y; ++x, --y) {
+    const uint32_t t = out[x]; out[x] = out[y]; out[y] = t;
+  }
+  a.cig_len[p] = nruns;
+}
+
+hipError_t tbw_tasks(int64_t n0, int64_t n1, const int64_t *sorted, const TbArgs &a,
+                     TbwTask *tasks, int64_t *dir_words, int64_t *bnd_words, hipStream_t st) {
+  const int64_t nt = (n1 - n0 + 63) / 64;
+  if (nt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tbw_tasks, dim3(nblk(nt, 128)), dim3(128), 0, st, n0, n1, sorted, a, tasks,
+                     dir_words, bnd_words);
+  return hipGetLastError();
+}
+
+hipError_t tbw_offsets(int64_t ntasks, TbwTask *tasks, const int64_t *doff, const int64_t *boff,
+                       hipStream_t st) {
+  if (!ntasks) return hipSuccess;
+  hipLaunchKernelGGL(k_tbw_offsets, dim3(nblk(ntasks, 128)), dim3(128), 0, st, ntasks, tasks, doff,
+                     boff);
+  return hipGetLastError();
+}
+
+hipError_t tb_strip(const TbArgs &a, const TbwTask *tasks, int64_t ntasks, const int64_t *sorted,
+                    int32_t *bndbuf, hipStream_t st) {
+  if (!ntasks) return hipSuccess;
+  const unsigned blocks = nblk(ntasks, 4);
+  if (a.n <= 4)
+    hipLaunchKernelGGL((k_tb_strip<true>), dim3(blocks), dim3(256), 0, st, a, tasks, ntasks, sorted, bndbuf);
+  else
+    hipLaunchKernelGGL((k_tb_strip<false>), dim3(blocks), dim3(256), 0, st, a, tasks, ntasks, sorted, bndbuf);
+  return hipGetLastError();
+}
+
+}  // namespace swx
