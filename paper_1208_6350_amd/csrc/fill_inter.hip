@@ -46,6 +46,8 @@ __device__ __forceinline__ int64_t wave_max64(int64_t v) {
 
 // A sequence as seen by one lane-half: padded index i maps to symbol
 // base[i - pad] (forward) or base[len - 1 - (i - pad)] (reversed view).
+// base is always readable at index 0 (a dummy buffer for empty slots), so
+// every access below is a plain load from a clamped index.
 struct SeqRef {
   const int8_t *base;
   int64_t len;
@@ -53,10 +55,17 @@ struct SeqRef {
   bool rev;
 };
 
+__device__ __forceinline__ SeqRef make_seq(const int8_t *base, int64_t len, int64_t pad, bool rev,
+                                           const int8_t *dummy) {
+  return SeqRef{len > 0 ? base : dummy, len, pad, rev};
+}
+
 __device__ __forceinline__ int32_t seq_at(const SeqRef &s, int64_t i) {
   const int64_t j = i - s.pad;
-  if (j < 0 || j >= s.len) return -1;
-  return s.base[s.rev ? s.len - 1 - j : j];
+  const bool ok = (uint64_t)j < (uint64_t)s.len;
+  const int64_t idx = ok ? (s.rev ? s.len - 1 - j : j) : 0;
+  const int32_t v = s.base[idx];
+  return ok ? v : -1;
 }
 
 // padded columns c0..c0+7, byte k = column c0+k, pad symbol outside
@@ -70,8 +79,10 @@ __device__ __forceinline__ uint2 fetch8(const SeqRef &s, int64_t c0, uint32_t pa
   return make_uint2(w[0], w[1]);
 }
 
-template <class V, int R, uint32_t MODE, bool CLAMP>
-__global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
+// Register budget: 256 VGPRs per lane, two waves per SIMD.
+template <class V, int R, uint32_t MODE, bool CLAMP, bool REV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_inter_fill(
+    InterArgs a) {
   using T = VT<V>;
   constexpr int NH = T::kHalves;
   __shared__ uint32_t s_lut[8];
@@ -82,7 +93,7 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
   const int64_t tid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (tid >= a.ntasks) return;
   const InterTask tk = a.tasks[tid];
-  const bool rev = a.rev != 0;
+  constexpr bool rev = REV;
   const int nstrips = tk.qp / R;
   const int64_t rp = tk.rp;
   const uint32_t pad_sym = (uint32_t)a.n;
@@ -100,13 +111,15 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
       const int64_t p = pid[h];
       const int32_t lq = a.view.qlen[p];
       const int64_t lr = a.view.rlen[p];
-      qs[h] = SeqRef{a.view.qcat + a.view.qstart[p], lq, rev ? 0 : tk.qp - lq, a.view.reversed != 0};
-      rs[h] = SeqRef{a.view.rcat + a.view.rstart[p], lr, rev ? 0 : rp - lr, a.view.reversed != 0};
+      qs[h] = make_seq(a.view.qcat + a.view.qstart[p], lq, rev ? 0 : tk.qp - lq,
+                       a.view.reversed != 0, a.dummy);
+      rs[h] = make_seq(a.view.rcat + a.view.rstart[p], lr, rev ? 0 : rp - lr,
+                       a.view.reversed != 0, a.dummy);
       tgt[h] = rev ? a.target[p] : 0;
       reach[h] = (rev && tgt[h] <= 0) ? -1 : kNoReach;
     } else {
-      qs[h] = SeqRef{a.view.qcat, 0, 0, false};
-      rs[h] = SeqRef{a.view.rcat, 0, 0, false};
+      qs[h] = SeqRef{a.dummy, 0, 0, false};
+      rs[h] = SeqRef{a.dummy, 0, 0, false};
       tgt[h] = 0;
       reach[h] = -1;
     }
@@ -120,6 +133,11 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
   uint32_t *bF = bH + rp * 64;
   uint32_t *bC = bF + rp * 64;
   const V vbias = T::splat((uint32_t)a.bias);
+  const uint32_t code_top = (uint32_t)a.code_top;   // R - 1, opaque to the compiler
+  // the row-code multiplier (32 in each half) in a VGPR the compiler cannot
+  // see through, so value * 32 + code stays one v_pk_mad_u16
+  uint32_t mul32;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(mul32) : "s"(0x00200020u));
   const V vo = T::splat((uint32_t)a.o);
   const V ve = T::splat((uint32_t)a.e);
 
@@ -163,10 +181,11 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
     V hdtop = T::zero();
     if (s > 0 && clo >= 1 && clo - 1 >= plo && clo - 1 < phi)
       hdtop = T::from(bH[(clo - 1) * 64 + lane]);
-    uint32_t sb[NH];
-    int64_t sbcol[NH];
+    uint32_t sb[NH];      // encoded strip best (value * 32 + row code)
+    uint32_t sbk[NH];     // sb | 31: its value part, for the strict comparison
+    int32_t sbcol[NH];
 #pragma unroll
-    for (int h = 0; h < NH; ++h) { sb[h] = 0u; sbcol[h] = -1; }
+    for (int h = 0; h < NH; ++h) { sb[h] = 0u; sbk[h] = 31u; sbcol[h] = -1; }
     const bool last = (s == nstrips - 1);
 
     // Column loop.  Everything column c+1 needs from memory (boundary values,
@@ -183,7 +202,9 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
     V n_hup, n_F, n_cm;
     uint32_t nX[R / 4][2];
     auto prefetch = [&](int64_t c) {
-      const bool inprev = (s > 0) && (c >= plo) && (c < phi);
+      // forward strips all span every column, so only the first strip lacks a
+      // row above; reversed strips use column windows
+      const bool inprev = rev ? ((s > 0) && (c >= plo) && (c < phi)) : (s > 0);
       const int64_t bi = c * 64 + lane;
       n_hup = inprev ? T::from(bH[bi]) : T::zero();
       n_F = inprev ? T::from(bF[bi]) : T::zero();
@@ -222,6 +243,7 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
 #pragma unroll 1
     for (int64_t c = clo; c < chi; ++c) {
       const V hup = n_hup;
+      const V hdiag_in = hdtop;
       V F = n_F;
       const V cmin = n_cm;
       uint32_t X[R / 4][2];
@@ -238,22 +260,27 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
       if (c + 1 < chi) prefetch(c + 1);
       const int64_t bi = c * 64 + lane;
 
-      V hdiag = hdtop;
+      // rows: the part of each cell that does not depend on the F chain
+      // (diagonal + substitution, max with E) is computed one row ahead
       hdtop = hup;
       V cm = T::zero();
       V ho = T::zero();
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
+      auto score_of = [&](int r) -> V {
         uint32_t sraw;
         if constexpr (MODE == kQSel) sraw = perm(X[0][1], X[0][0], sel[r]);
         else sraw = perm(X[r >> 2][1], X[r >> 2][0], T::sel_const(r & 3));
-        const V t = T::add(hdiag, T::from(sraw));
-        hdiag = H[r];
-        const V hb = T::max(T::max(t, E[r]), F);
+        return T::from(sraw);
+      };
+      V u_next = T::max(T::add(hdiag_in, score_of(0)), E[0]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const V u = u_next;
+        if (r + 1 < R) u_next = T::max(T::add(H[r], score_of(r + 1)), E[r + 1]);
+        const V hb = T::max(u, F);
         const V hn = T::subs(hb, vbias);
         H[r] = hn;
-        cm = T::max(cm, CLAMP ? T::enc(hn, T::code_splat((uint32_t)(R - 1 - r)))
-                              : T::enc_nosat(hn, (uint32_t)(R - 1 - r)));
+        const uint32_t code = code_top - (uint32_t)r;
+        cm = T::max(cm, CLAMP ? T::enc(hn, T::code_splat(code)) : T::enc_nosat(hn, code, mul32));
         ho = T::subs(hb, vo);
         E[r] = T::max(T::subs(E[r], ve), ho);
         F = T::max(T::subs(F, ve), ho);   // F of the next row
@@ -267,7 +294,11 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
 #pragma unroll
       for (int h = 0; h < NH; ++h) {
         const uint32_t v = T::half(cm, h);
-        if ((v | 31u) > (sb[h] | 31u)) { sb[h] = v; sbcol[h] = c; }
+        const uint32_t vk = v | 31u;
+        const bool imp = vk > sbk[h];
+        sb[h] = imp ? v : sb[h];
+        sbk[h] = imp ? vk : sbk[h];
+        sbcol[h] = imp ? (int32_t)c : sbcol[h];
       }
       if (rev && ((c + 1) & 7) == 0) {
         // leave the strip once every pair has reached its target at or before
@@ -289,7 +320,7 @@ __global__ __launch_bounds__(256) void k_inter_fill(InterArgs a) {
       const int32_t v = (int32_t)(sb[h] >> 5);
       if (v > 0) {
         const int32_t row = sR + (R - 1 - (int32_t)(sb[h] & 31u)) - (int32_t)qs[h].pad;
-        const int64_t col = sbcol[h] - rs[h].pad;
+        const int64_t col = (int64_t)sbcol[h] - rs[h].pad;
         if (v > bval[h] || (v == bval[h] && col < bcol[h])) {
           bval[h] = v; brow[h] = row; bcol[h] = col;
         }
@@ -332,8 +363,8 @@ __global__ __launch_bounds__(256) void k_inter_prof(PackArgs a) {
     uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // up to R = 32 bytes
     if (p >= 0 && sy < a.n) {
       const int32_t lq = a.view.qlen[p];
-      const SeqRef q{a.view.qcat + a.view.qstart[p], lq, a.rev ? 0 : tk.qp - lq,
-                     a.view.reversed != 0};
+      const SeqRef q = make_seq(a.view.qcat + a.view.qstart[p], lq, a.rev ? 0 : tk.qp - lq,
+                                a.view.reversed != 0, a.matrix);
       for (int r = 0; r < R; ++r) {
         const int32_t qv = seq_at(q, strip * R + r);
         const uint32_t b = qv < 0 ? 0u : (uint32_t)(uint8_t)(a.matrix[qv * a.n + sy] + a.bias);
@@ -352,12 +383,14 @@ static hipError_t launch_fill(const InterArgs &a, hipStream_t st) {
   const int waves_per_block = 4;
   const int64_t blocks = (a.ntasks + waves_per_block - 1) / waves_per_block;
   if (blocks == 0) return hipSuccess;
-  if (a.clamp)
-    hipLaunchKernelGGL((k_inter_fill<V, R, MODE, true>), dim3((unsigned)blocks),
-                       dim3(64 * waves_per_block), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_inter_fill<V, R, MODE, false>), dim3((unsigned)blocks),
-                       dim3(64 * waves_per_block), 0, st, a);
+  const dim3 g((unsigned)blocks), b(64 * waves_per_block);
+  if (a.rev) {
+    if (a.clamp) hipLaunchKernelGGL((k_inter_fill<V, R, MODE, true, true>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_inter_fill<V, R, MODE, false, true>), g, b, 0, st, a);
+  } else {
+    if (a.clamp) hipLaunchKernelGGL((k_inter_fill<V, R, MODE, true, false>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_inter_fill<V, R, MODE, false, false>), g, b, 0, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -39,8 +39,8 @@ template <> struct VT<u16x2> {
   }
   // value * 32 + code without saturation: only for pairs whose scores
   // cannot exceed the 11-bit value field (checked before launch)
-  static __device__ __forceinline__ u16x2 enc_nosat(u16x2 h, uint32_t code) {
-    return h * (u16x2){32, 32} + (u16x2){(unsigned short)code, (unsigned short)code};
+  static __device__ __forceinline__ u16x2 enc_nosat(u16x2 h, uint32_t code, uint32_t mul32) {
+    return h * from(mul32) + (u16x2){(unsigned short)code, (unsigned short)code};
   }
   static __device__ __forceinline__ u16x2 shr5(u16x2 v) { return v >> (u16x2){5, 5}; }
   static __device__ __forceinline__ uint32_t half(u16x2 v, int k) {
@@ -68,7 +68,9 @@ template <> struct VT<uint32_t> {
   }
   static __device__ __forceinline__ uint32_t max(uint32_t a, uint32_t b) { return a > b ? a : b; }
   static __device__ __forceinline__ uint32_t enc(uint32_t h, uint32_t code) { return h * 32u + code; }
-  static __device__ __forceinline__ uint32_t enc_nosat(uint32_t h, uint32_t code) { return h * 32u + code; }
+  static __device__ __forceinline__ uint32_t enc_nosat(uint32_t h, uint32_t code, uint32_t) {
+    return h * 32u + code;
+  }
   static __device__ __forceinline__ uint32_t shr5(uint32_t v) { return v >> 5; }
   static __device__ __forceinline__ uint32_t half(uint32_t v, int) { return v; }
   static constexpr uint32_t sel_const(int k) { return (uint32_t)k | 0x0C0C0C00u; }

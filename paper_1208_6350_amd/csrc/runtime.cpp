@@ -258,6 +258,8 @@ static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &v
   // without a possible score above the 16-bit value field the row code needs
   // no saturation (scores are at most smax * min(qlen, rlen))
   a.clamp = score_bound > kInter16Limit - 1 ? 1 : 0;
+  a.code_top = pl.R - 1;
+  a.dummy = sc.dmat;   // any readable device bytes
   a.target = d_target;
   a.out = out;
   if (mark_fill >= 0) HIP_TRY(hipEventRecord(ctx->ev[mark_fill], st));

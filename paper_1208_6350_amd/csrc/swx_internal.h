@@ -63,6 +63,8 @@ struct InterArgs {
   int32_t n, o, e, bias;
   int32_t rev;                // reversed pass: stop at target, band window, no CM plane
   int32_t clamp;              // scores may exceed the 16-bit value field: saturate the code
+  int32_t code_top;           // row code of the first strip row (strip height - 1)
+  const int8_t *dummy;        // readable bytes for empty slots
   const int32_t *target;      // reversed pass: per pair score to reach
   FillOut out;
 };
