@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256) void k_score2_inter(Score2InterArgs a) {
       const int64_t lo = a.rbeg[p] - m, hi = a.rend[p] + m;
       for (int64_t j = 0; j < lr; ++j) {
         if (j >= lo && j <= hi) continue;
-        const uint32_t wv = bC[(j + padr) * 64 + lane];
+        const uint32_t wv = bC[bnd_index(j + padr, lane)];
         const int32_t v = (a.halves == 2) ? (int32_t)(h ? (wv >> 16) : (wv & 0xFFFFu)) : (int32_t)wv;
         if (v > best) { best = v; at = j; }
       }

@@ -19,8 +19,9 @@
 // the row above from the boundary planes written by the previous strip; the
 // cell update is 11 saturating 16-bit-pair instructions plus two for the
 // column max with the row code (value * 32 + code, so that a max over the
-// strip also names the first row reaching it).  Sequences are read straight
-// from the caller's concatenated arrays (8 columns per fetch).
+// strip also names the first row reaching it).  Boundary planes and the
+// reference symbols (packed per task by k_inter_rsym, padding included) move
+// in groups of 4 columns: one 16-byte word per lane and plane.
 //
 // Scores live in a biased domain: the substitution term arrives as
 // S + bias >= 0 (bias = -min S), E and F are kept as E + bias and F + bias
@@ -68,15 +69,8 @@ __device__ __forceinline__ int32_t seq_at(const SeqRef &s, int64_t i) {
   return ok ? v : -1;
 }
 
-// padded columns c0..c0+7, byte k = column c0+k, pad symbol outside
-__device__ __forceinline__ uint2 fetch8(const SeqRef &s, int64_t c0, uint32_t pad_sym) {
-  uint32_t w[2] = {0u, 0u};
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int32_t v = seq_at(s, c0 + k);
-    w[k >> 2] |= (v < 0 ? pad_sym : (uint32_t)v) << (8 * (k & 3));
-  }
-  return make_uint2(w[0], w[1]);
+__device__ __forceinline__ uint32_t word_of(const uint4 &v, int k) {
+  return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
 }
 
 // Register budget: 256 VGPRs per lane, two waves per SIMD.
@@ -90,17 +84,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   __syncthreads();
 
   const int lane = threadIdx.x & 63;
-  const int64_t tid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  // the wave index is uniform across the wave: say so, so that the task and
+  // everything derived from it (bounds, plane addresses) live in SGPRs
+  const int64_t tid = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                      __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   if (tid >= a.ntasks) return;
   const InterTask tk = a.tasks[tid];
   constexpr bool rev = REV;
   const int nstrips = tk.qp / R;
   const int64_t rp = tk.rp;
-  const uint32_t pad_sym = (uint32_t)a.n;
 
   // slots of this lane
   int64_t pid[NH];
-  SeqRef qs[NH], rs[NH];
+  SeqRef qs[NH];
+  int64_t rpad[NH];
   int32_t tgt[NH];
   int64_t reach[NH];
 #pragma unroll
@@ -110,16 +107,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     if (pid[h] >= 0) {
       const int64_t p = pid[h];
       const int32_t lq = a.view.qlen[p];
-      const int64_t lr = a.view.rlen[p];
       qs[h] = make_seq(a.view.qcat + a.view.qstart[p], lq, rev ? 0 : tk.qp - lq,
                        a.view.reversed != 0, a.dummy);
-      rs[h] = make_seq(a.view.rcat + a.view.rstart[p], lr, rev ? 0 : rp - lr,
-                       a.view.reversed != 0, a.dummy);
+      rpad[h] = rev ? 0 : rp - a.view.rlen[p];
       tgt[h] = rev ? a.target[p] : 0;
       reach[h] = (rev && tgt[h] <= 0) ? -1 : kNoReach;
     } else {
       qs[h] = SeqRef{a.dummy, 0, 0, false};
-      rs[h] = SeqRef{a.dummy, 0, 0, false};
+      rpad[h] = 0;
       tgt[h] = 0;
       reach[h] = -1;
     }
@@ -129,9 +124,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
   for (int h = 0; h < NH; ++h) { bval[h] = 0; brow[h] = -1; bcol[h] = -1; }
 
-  uint32_t *bH = a.bnd + tk.bnd_off;
-  uint32_t *bF = bH + rp * 64;
-  uint32_t *bC = bF + rp * 64;
+  // boundary planes: [rp/4][64] 16-byte words each
+  uint4 *bH = reinterpret_cast<uint4 *>(a.bnd + tk.bnd_off);
+  uint4 *bF = bH + rp * 16;
+  uint4 *bC = bF + rp * 16;
+  const uint2 *rsym = a.rsym + rsym_offset(tk.bnd_off);
   const V vbias = T::splat((uint32_t)a.bias);
   const uint32_t code_top = (uint32_t)a.code_top;   // R - 1, opaque to the compiler
   // the row-code multiplier (32 in each half) in a VGPR the compiler cannot
@@ -140,8 +137,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   asm volatile("v_mov_b32 %0, %1" : "=v"(mul32) : "s"(0x00200020u));
   const V vo = T::splat((uint32_t)a.o);
   const V ve = T::splat((uint32_t)a.e);
+  const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
 
-  int64_t plo = 0, phi = 0;  // column window of the previous strip
+  int64_t plo = 0, phi = 0;  // column window of the previous strip (multiples of 4)
   for (int s = 0; s < nstrips; ++s) {
     const int sR = s * R;
     int64_t clo = 0, chi = rp;
@@ -156,6 +154,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       for (int h = 0; h < NH; ++h) bound = bound > reach[h] ? bound : reach[h];
       bound = wave_max64(bound);
       if (bound < kNoReach && bound + 1 < chi) chi = bound + 1;
+      // whole column groups: a wider window only adds cells whose values are
+      // lower bounds of the true ones (an exact band stays exact)
+      clo &= ~(int64_t)3;
+      chi = (chi + 3) & ~(int64_t)3;
+      if (chi > rp) chi = rp;
       if (clo >= chi) break;   // later strips have even later windows
     }
 
@@ -180,7 +183,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int r = 0; r < R; ++r) { H[r] = T::zero(); E[r] = T::zero(); }
     V hdtop = T::zero();
     if (s > 0 && clo >= 1 && clo - 1 >= plo && clo - 1 < phi)
-      hdtop = T::from(bH[(clo - 1) * 64 + lane]);
+      hdtop = T::from(reinterpret_cast<const uint32_t *>(bH)[bnd_index(clo - 1, lane)]);
     uint32_t sb[NH];      // encoded strip best (value * 32 + row code)
     uint32_t sbk[NH];     // sb | 31: its value part, for the strict comparison
     int32_t sbcol[NH];
@@ -188,122 +191,140 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int h = 0; h < NH; ++h) { sb[h] = 0u; sbk[h] = 31u; sbcol[h] = -1; }
     const bool last = (s == nstrips - 1);
 
-    // Column loop.  Everything column c+1 needs from memory (boundary values,
-    // reference symbols, score operands) is requested before column c is
-    // computed, so the loads overlap the arithmetic.
+    // Column groups of 4.  The boundary words and reference symbols of group
+    // g+1 are requested before group g is computed, so the loads overlap four
+    // columns of arithmetic.
     int64_t cdone = chi;   // one past the last column this strip computes
-    int64_t blk = clo >> 3;
-    uint2 s8cur[NH], s8nxt[NH];
-#pragma unroll
-    for (int h = 0; h < NH; ++h) {
-      s8cur[h] = fetch8(rs[h], blk * 8, pad_sym);
-      s8nxt[h] = fetch8(rs[h], blk * 8 + 8, pad_sym);
-    }
-    V n_hup, n_F, n_cm;
-    uint32_t nX[R / 4][2];
-    auto prefetch = [&](int64_t c) {
+    const int64_t g0 = clo >> 2, g1 = chi >> 2;
+    uint4 nh, nf, nc;
+    uint2 nsy;
+    auto fetch_group = [&](int64_t g) {
       // forward strips all span every column, so only the first strip lacks a
       // row above; reversed strips use column windows
-      const bool inprev = rev ? ((s > 0) && (c >= plo) && (c < phi)) : (s > 0);
-      const int64_t bi = c * 64 + lane;
-      n_hup = inprev ? T::from(bH[bi]) : T::zero();
-      n_F = inprev ? T::from(bF[bi]) : T::zero();
-      n_cm = (!rev && s > 0) ? T::from(bC[bi]) : T::zero();
-      const uint32_t cc = (uint32_t)(c & 7);
-      const uint32_t symA = __builtin_amdgcn_ubfe(cc < 4 ? s8cur[0].x : s8cur[0].y, 8 * (cc & 3), 8);
-      const uint32_t symB = (NH == 2)
-          ? __builtin_amdgcn_ubfe(cc < 4 ? s8cur[NH - 1].x : s8cur[NH - 1].y, 8 * (cc & 3), 8)
-          : 0u;
-      if constexpr (MODE == kQSel) {
-        nX[0][0] = s_lut[symA];
-        nX[0][1] = (NH == 2) ? s_lut[symB] : 0u;
-      } else {
-        const int np1 = a.n + 1;
-        const uint8_t *base = a.prof + tk.qdata_off + (int64_t)s * np1 * NH * 64 * R;
-        const uint4 *pA = (const uint4 *)(base + (((int64_t)symA * NH + 0) * 64 + lane) * R);
+      const bool inprev = rev ? ((s > 0) && (4 * g >= plo) && (4 * g < phi)) : (s > 0);
+      const int64_t gi = g * 64 + lane;
+      nsy = rsym[gi];
+      nh = inprev ? bH[gi] : zero4;
+      nf = inprev ? bF[gi] : zero4;
+      nc = (!rev && s > 0) ? bC[gi] : zero4;
+    };
+    // QGEN: profile words of the next column, one column ahead
+    uint32_t nX[R / 4][2];
+    auto fetch_prof = [&](uint32_t symA, uint32_t symB) {
+      const int np1 = a.n + 1;
+      const uint8_t *base = a.prof + tk.qdata_off + (int64_t)s * np1 * NH * 64 * R;
+      const uint4 *pA = (const uint4 *)(base + (((int64_t)symA * NH + 0) * 64 + lane) * R);
+#pragma unroll
+      for (int k = 0; k < R / 16; ++k) {
+        const uint4 v = pA[k];
+        nX[4 * k + 0][0] = v.x; nX[4 * k + 1][0] = v.y; nX[4 * k + 2][0] = v.z; nX[4 * k + 3][0] = v.w;
+      }
+      if constexpr (NH == 2) {
+        const uint4 *pB = (const uint4 *)(base + (((int64_t)symB * 2 + 1) * 64 + lane) * R);
 #pragma unroll
         for (int k = 0; k < R / 16; ++k) {
-          const uint4 v = pA[k];
-          nX[4 * k + 0][0] = v.x; nX[4 * k + 1][0] = v.y; nX[4 * k + 2][0] = v.z; nX[4 * k + 3][0] = v.w;
+          const uint4 v = pB[k];
+          nX[4 * k + 0][1] = v.x; nX[4 * k + 1][1] = v.y; nX[4 * k + 2][1] = v.z; nX[4 * k + 3][1] = v.w;
         }
-        if constexpr (NH == 2) {
-          const uint4 *pB = (const uint4 *)(base + (((int64_t)symB * 2 + 1) * 64 + lane) * R);
+      } else {
 #pragma unroll
-          for (int k = 0; k < R / 16; ++k) {
-            const uint4 v = pB[k];
-            nX[4 * k + 0][1] = v.x; nX[4 * k + 1][1] = v.y; nX[4 * k + 2][1] = v.z; nX[4 * k + 3][1] = v.w;
-          }
-        } else {
-#pragma unroll
-          for (int k = 0; k < R / 4; ++k) nX[k][1] = 0u;
-        }
+        for (int k = 0; k < R / 4; ++k) nX[k][1] = 0u;
       }
     };
-    prefetch(clo);
+    fetch_group(g0);
+    if constexpr (MODE == kQGen) fetch_prof(nsy.x & 0xFFu, nsy.y & 0xFFu);
+
 #pragma unroll 1
-    for (int64_t c = clo; c < chi; ++c) {
-      const V hup = n_hup;
-      const V hdiag_in = hdtop;
-      V F = n_F;
-      const V cmin = n_cm;
-      uint32_t X[R / 4][2];
+    for (int64_t g = g0; g < g1; ++g) {
+      const uint4 ch = nh, cf = nf, cc = nc;
+      const uint2 sy = nsy;
+      if (g + 1 < g1) fetch_group(g + 1);
+      uint32_t lx[4][2];   // QSEL: LUT words of the group's 4 columns
+      if constexpr (MODE == kQSel) {
 #pragma unroll
-      for (int k = 0; k < ((MODE == kQSel) ? 1 : R / 4); ++k) { X[k][0] = nX[k][0]; X[k][1] = nX[k][1]; }
-      if (((c + 1) & 7) == 0) {   // the next column starts a new 8-column block
-        ++blk;
-#pragma unroll
-        for (int h = 0; h < NH; ++h) {
-          s8cur[h] = s8nxt[h];
-          s8nxt[h] = fetch8(rs[h], blk * 8 + 8, pad_sym);
+        for (int k = 0; k < 4; ++k) {
+          lx[k][0] = s_lut[__builtin_amdgcn_ubfe(sy.x, 8 * k, 8)];
+          lx[k][1] = (NH == 2) ? s_lut[__builtin_amdgcn_ubfe(sy.y, 8 * k, 8)] : 0u;
         }
       }
-      if (c + 1 < chi) prefetch(c + 1);
-      const int64_t bi = c * 64 + lane;
+      uint32_t oh[4], of[4], oc[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        // keep the scheduler from hoisting later columns' score operands
+        // (independent of the recurrence) into this one: they would take
+        // R registers per column
+        __builtin_amdgcn_sched_barrier(0);
+        const int64_t c = 4 * g + k;
+        uint32_t X[R / 4][2];
+        if constexpr (MODE == kQGen) {
+#pragma unroll
+          for (int i = 0; i < R / 4; ++i) { X[i][0] = nX[i][0]; X[i][1] = nX[i][1]; }
+          if (k < 3) {
+            fetch_prof(__builtin_amdgcn_ubfe(sy.x, 8 * (k + 1), 8),
+                       __builtin_amdgcn_ubfe(sy.y, 8 * (k + 1), 8));
+          } else if (g + 1 < g1) {
+            fetch_prof(nsy.x & 0xFFu, nsy.y & 0xFFu);
+          }
+        } else {
+          X[0][0] = lx[k][0];
+          X[0][1] = lx[k][1];
+        }
+        const V hup = T::from(word_of(ch, k));
+        const V hdiag_in = hdtop;
+        V F = T::from(word_of(cf, k));
+        const V cmin = T::from(word_of(cc, k));
 
-      // rows: the part of each cell that does not depend on the F chain
-      // (diagonal + substitution, max with E) is computed one row ahead
-      hdtop = hup;
-      V cm = T::zero();
-      V ho = T::zero();
-      auto score_of = [&](int r) -> V {
-        uint32_t sraw;
-        if constexpr (MODE == kQSel) sraw = perm(X[0][1], X[0][0], sel[r]);
-        else sraw = perm(X[r >> 2][1], X[r >> 2][0], T::sel_const(r & 3));
-        return T::from(sraw);
-      };
-      V u_next = T::max(T::add(hdiag_in, score_of(0)), E[0]);
+        // rows: the part of each cell that does not depend on the F chain
+        // (diagonal + substitution, max with E) is computed one row ahead
+        hdtop = hup;
+        V cm = T::zero();
+        V ho = T::zero();
+        auto score_of = [&](int r) -> V {
+          uint32_t sraw;
+          if constexpr (MODE == kQSel) sraw = perm(X[0][1], X[0][0], sel[r]);
+          else sraw = perm(X[r >> 2][1], X[r >> 2][0], T::sel_const(r & 3));
+          return T::from(sraw);
+        };
+        V u_next = T::max(T::add(hdiag_in, score_of(0)), E[0]);
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const V u = u_next;
-        if (r + 1 < R) u_next = T::max(T::add(H[r], score_of(r + 1)), E[r + 1]);
-        const V hb = T::max(u, F);
-        const V hn = T::subs(hb, vbias);
-        H[r] = hn;
-        const uint32_t code = code_top - (uint32_t)r;
-        cm = T::max(cm, CLAMP ? T::enc(hn, T::code_splat(code)) : T::enc_nosat(hn, code, mul32));
-        ho = T::subs(hb, vo);
-        E[r] = T::max(T::subs(E[r], ve), ho);
-        F = T::max(T::subs(F, ve), ho);   // F of the next row
-      }
-      if (!last || rev) {
-        bH[bi] = T::bits(H[R - 1]);
-        bF[bi] = T::bits(F);
-      }
-      if (!rev) bC[bi] = T::bits(T::max(cmin, T::shr5(cm)));
-      // strip best: first column reaching the strip's largest value
+        for (int r = 0; r < R; ++r) {
+          const V u = u_next;
+          if (r + 1 < R) u_next = T::max(T::add(H[r], score_of(r + 1)), E[r + 1]);
+          const V hb = T::max(u, F);
+          const V hn = T::subs(hb, vbias);
+          H[r] = hn;
+          const uint32_t code = code_top - (uint32_t)r;
+          cm = T::max(cm, CLAMP ? T::enc(hn, T::code_splat(code)) : T::enc_nosat(hn, code, mul32));
+          ho = T::subs(hb, vo);
+          E[r] = T::max(T::subs(E[r], ve), ho);
+          F = T::max(T::subs(F, ve), ho);   // F of the next row
+        }
+        oh[k] = T::bits(H[R - 1]);
+        of[k] = T::bits(F);
+        oc[k] = T::bits(T::max(cmin, T::shr5(cm)));
+        // strip best: first column reaching the strip's largest value
 #pragma unroll
-      for (int h = 0; h < NH; ++h) {
-        const uint32_t v = T::half(cm, h);
-        const uint32_t vk = v | 31u;
-        const bool imp = vk > sbk[h];
-        sb[h] = imp ? v : sb[h];
-        sbk[h] = imp ? vk : sbk[h];
-        sbcol[h] = imp ? (int32_t)c : sbcol[h];
+        for (int h = 0; h < NH; ++h) {
+          const uint32_t v = T::half(cm, h);
+          const uint32_t vk = v | 31u;
+          const bool imp = vk > sbk[h];
+          sb[h] = imp ? v : sb[h];
+          sbk[h] = imp ? vk : sbk[h];
+          sbcol[h] = imp ? (int32_t)c : sbcol[h];
+        }
       }
-      if (rev && ((c + 1) & 7) == 0) {
+      const int64_t gi = g * 64 + lane;
+      // the last forward strip has no reader for H and F: it overwrites the
+      // first group's words instead (they stay in L2).  A store that is
+      // skipped instead costs registers: the compiler splits the loop.
+      const int64_t ghf = (last && !rev) ? (int64_t)lane : gi;
+      bH[ghf] = make_uint4(oh[0], oh[1], oh[2], oh[3]);
+      bF[ghf] = make_uint4(of[0], of[1], of[2], of[3]);
+      if (!rev) bC[gi] = make_uint4(oc[0], oc[1], oc[2], oc[3]);
+      if (rev && (g & 1)) {
         // leave the strip once every pair has reached its target at or before
-        // column c: later columns can neither give an earlier column nor a
-        // smaller row
+        // the group's last column: later columns can neither give an earlier
+        // column nor a smaller row
         int64_t need = -1;
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
@@ -311,7 +332,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
           if (rr >= 0 && (int32_t)(sb[h] >> 5) >= tgt[h] && sbcol[h] < rr) rr = sbcol[h];
           need = rr > need ? rr : need;
         }
-        if (wave_max64(need) <= c + 1) { cdone = c + 1; break; }
+        if (wave_max64(need) <= 4 * g + 4) { cdone = 4 * g + 4; break; }
       }
     }
     // merge the strip best into the pair best (earlier strips win ties)
@@ -320,7 +341,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       const int32_t v = (int32_t)(sb[h] >> 5);
       if (v > 0) {
         const int32_t row = sR + (R - 1 - (int32_t)(sb[h] & 31u)) - (int32_t)qs[h].pad;
-        const int64_t col = (int64_t)sbcol[h] - rs[h].pad;
+        const int64_t col = (int64_t)sbcol[h] - rpad[h];
         if (v > bval[h] || (v == bval[h] && col < bcol[h])) {
           bval[h] = v; brow[h] = row; bcol[h] = col;
         }
@@ -340,6 +361,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     a.out.qend[p] = bval[h] > 0 ? brow[h] : -1;
     a.out.rend[p] = bval[h] > 0 ? bcol[h] : -1;
     a.out.overflow[p] = (bval[h] >= limit) ? 1 : 0;
+  }
+}
+
+// ---- packed reference symbols: per task, column group, lane -------------
+// Thread (lane, phase) of a 256-thread block writes groups phase, phase + 4,
+// ... of its lane, so a wave writes one contiguous 512-byte run per step.
+__global__ __launch_bounds__(256) void k_inter_rsym(PackArgs a) {
+  const int64_t t = blockIdx.x;
+  if (t >= a.ntasks) return;
+  const InterTask tk = a.tasks[t];
+  const int lane = threadIdx.x & 63;
+  const int phase = threadIdx.x >> 6;
+  const uint32_t pad4 = (uint32_t)a.n * 0x01010101u;
+  SeqRef r[2];
+  bool live[2] = {false, false};
+  for (int h = 0; h < a.halves; ++h) {
+    const int s = lane + 64 * h;
+    const int64_t p = (s < tk.nslots) ? a.slot_pair[tk.slot_base + s] : -1;
+    if (p >= 0) {
+      const int64_t lr = a.view.rlen[p];
+      r[h] = make_seq(a.view.rcat + a.view.rstart[p], lr, a.rev ? 0 : tk.rp - lr,
+                      a.view.reversed != 0, a.matrix);
+      live[h] = true;
+    }
+  }
+  uint2 *dst = a.rsym + rsym_offset(tk.bnd_off);
+  const int64_t ng = tk.rp / 4;
+  for (int64_t g = phase; g < ng; g += 4) {
+    uint32_t w[2] = {pad4, pad4};
+    for (int h = 0; h < 2; ++h) {
+      if (!live[h]) continue;
+      uint32_t x = 0;
+      for (int k = 0; k < 4; ++k) {
+        const int32_t v = seq_at(r[h], 4 * g + k);
+        x |= (v < 0 ? (uint32_t)a.n : (uint32_t)v) << (8 * k);
+      }
+      w[h] = x;
+    }
+    dst[g * 64 + lane] = make_uint2(w[0], w[1]);
   }
 }
 
@@ -404,6 +464,12 @@ hipError_t inter_fill(const InterArgs &a, int lane_bits, int R, hipStream_t st) 
     if (R == 16) return qsel ? launch_fill<uint32_t, 16, kQSel>(a, st) : launch_fill<uint32_t, 16, kQGen>(a, st);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t inter_pack_ref(const PackArgs &a, hipStream_t st) {
+  if (a.ntasks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_inter_rsym, dim3((unsigned)a.ntasks), dim3(256), 0, st, a);
+  return hipGetLastError();
 }
 
 hipError_t inter_pack(const PackArgs &a, hipStream_t st) {

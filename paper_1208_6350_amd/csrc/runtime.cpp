@@ -151,6 +151,7 @@ struct Plan {
   InterTask *d_tasks = nullptr;
   int64_t *d_sorted = nullptr;   // slot -> pair id
   uint32_t *d_bnd = nullptr;
+  uint2 *d_rsym = nullptr;       // packed reference symbols
   uint8_t *d_prof = nullptr;
 };
 
@@ -206,7 +207,8 @@ static int plan_pass(swx_ctx *ctx, const Scoring &sc, const int64_t *ids, int64_
   HIP_TRY(hipMemcpyAsync(&tot[1], qoff + pl.ntasks, 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   pl.d_bnd = A.get<uint32_t>(tot[0]);
-  if (!pl.d_bnd) return fail(SWX_ENOMEM, "device pool exhausted (boundary planes)");
+  pl.d_rsym = A.get<uint2>(rsym_offset(tot[0]));
+  if (!pl.d_bnd || !pl.d_rsym) return fail(SWX_ENOMEM, "device pool exhausted (boundary planes)");
   if (!sc.qsel) {
     pl.d_prof = A.get<uint8_t>(tot[1]);
     if (!pl.d_prof) return fail(SWX_ENOMEM, "device pool exhausted (profiles)");
@@ -227,21 +229,21 @@ static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &v
     }
     return SWX_OK;
   }
-  if (!sc.qsel) {
-    PackArgs pk{};
-    pk.tasks = pl.d_tasks;
-    pk.ntasks = pl.ntasks;
-    pk.slot_pair = pl.d_sorted;
-    pk.view = view;
-    pk.prof = pl.d_prof;
-    pk.matrix = sc.dmat;
-    pk.n = sc.n;
-    pk.bias = sc.bias;
-    pk.halves = pl.lane_bits == 16 ? 2 : 1;
-    pk.strip_rows = pl.R;
-    pk.rev = rev ? 1 : 0;
-    HIP_TRY(inter_pack(pk, st));
-  }
+  PackArgs pk{};
+  pk.tasks = pl.d_tasks;
+  pk.ntasks = pl.ntasks;
+  pk.slot_pair = pl.d_sorted;
+  pk.view = view;
+  pk.prof = pl.d_prof;
+  pk.rsym = pl.d_rsym;
+  pk.matrix = sc.dmat;
+  pk.n = sc.n;
+  pk.bias = sc.bias;
+  pk.halves = pl.lane_bits == 16 ? 2 : 1;
+  pk.strip_rows = pl.R;
+  pk.rev = rev ? 1 : 0;
+  HIP_TRY(inter_pack_ref(pk, st));
+  if (!sc.qsel) HIP_TRY(inter_pack(pk, st));
   InterArgs a{};
   a.tasks = pl.d_tasks;
   a.ntasks = pl.ntasks;
@@ -249,6 +251,7 @@ static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &v
   a.view = view;
   a.prof = sc.qsel ? nullptr : pl.d_prof;
   a.bnd = pl.d_bnd;
+  a.rsym = pl.d_rsym;
   for (int k = 0; k < 8; ++k) a.lut[k] = sc.lut[k];
   a.n = sc.n;
   a.o = sc.o;

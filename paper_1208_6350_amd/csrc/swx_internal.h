@@ -6,6 +6,7 @@
 // their last symbol backwards, which is how the reversed pass of the method
 // section (begin position search) is run without copying sequences.
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace swx {
@@ -24,7 +25,8 @@ struct InterTask {
   int32_t rp;         // padded columns (multiple of 8)
   int32_t band;       // reversed pass: band half-width around the main diagonal (-1: none)
   int64_t slot_base;  // slots are slot_pair[slot_base + s]
-  int64_t bnd_off;    // boundary planes at bnd + bnd_off: 3 planes of rp*64 dwords
+  int64_t bnd_off;    // boundary planes at bnd + bnd_off: 3 planes of rp*64 dwords;
+                      // packed reference symbols at rsym + rsym_offset(bnd_off)
   int64_t qdata_off;  // QGEN: profile bytes at prof + off
                       //       ((qp/R) strips * (n+1) symbols * halves * 64 lanes * R rows)
 };
@@ -48,6 +50,21 @@ struct FillOut {
   uint8_t *overflow;   // 1 when the lane width saturated: re-run wider
 };
 
+// Boundary plane layout.  Each plane (H of the strip's last row, F below it,
+// column max) holds, per group of 4 columns, one 16-byte word per lane:
+// dword (c & 3) of word [c / 4][lane].  A wave moves 4 columns of one plane
+// with a single coalesced 1 KiB access.
+__host__ __device__ inline int64_t bnd_index(int64_t c, int lane) {
+  return (((c >> 2) * kWave + lane) << 2) + (c & 3);
+}
+
+// Packed reference symbols of a task, [rp/4][64 lanes] of 8 bytes: byte k of
+// .x is the symbol of half 0 at column 4*g + k, .y the same for half 1 (the
+// padding symbol n outside the pair).  A task's boundary planes take
+// 192*rp dwords and its packed symbols 16*rp words, so the symbol offset is
+// the plane offset / 12.
+__host__ __device__ inline int64_t rsym_offset(int64_t bnd_off) { return bnd_off / 12; }
+
 constexpr uint32_t kQSel = 0;    // n <= 4: per-row byte selectors + per-column LUT
 constexpr uint32_t kQGen = 1;    // any n: per-slot biased profile rows in global memory
 
@@ -59,6 +76,7 @@ struct InterArgs {
   PairView view;
   const uint8_t *prof;        // QGEN profile bytes (null: QSEL)
   uint32_t *bnd;              // boundary planes (H, F, CM)
+  const uint2 *rsym;          // packed reference symbols
   uint32_t lut[8];            // QSEL: per reference symbol, biased scores of query symbols 0..3
   int32_t n, o, e, bias;
   int32_t rev;                // reversed pass: stop at target, band window, no CM plane

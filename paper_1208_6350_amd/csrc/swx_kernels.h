@@ -22,6 +22,7 @@ struct PackArgs {            // QGEN profile construction
   const int64_t *slot_pair;
   PairView view;
   uint8_t *prof;
+  uint2 *rsym;            // packed reference symbols (k_inter_rsym)
   const int8_t *matrix;   // n x n, [query symbol][reference symbol], device
   int32_t n, bias, halves, strip_rows, rev;
 };
@@ -123,6 +124,7 @@ hipError_t rev_prepare(int64_t npairs, const int32_t *score, const int32_t *qend
 
 hipError_t inter_fill(const InterArgs &a, int lane_bits, int R, hipStream_t st);
 hipError_t inter_pack(const PackArgs &a, hipStream_t st);
+hipError_t inter_pack_ref(const PackArgs &a, hipStream_t st);
 
 hipError_t launch_validate(const ValidateArgs &a, hipStream_t st);
 hipError_t launch_pair_stats(int64_t n, const int32_t *qlen, const int64_t *rlen, int64_t *stats,
