@@ -40,7 +40,46 @@ def parse():
     ap.add_argument("--per-pair-sample", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the timed steps, copy a device buffer of this many MiB once "
+                         "(a plain copy kernel of known size for calibrating byte counters)")
     return ap.parse_args()
+
+
+# Sources whose change invalidates a recorded HBM traffic figure of the fill.
+FILL_SOURCES = ["paper_1208_6350_amd/csrc/fill_inter.hip", "paper_1208_6350_amd/csrc/lanes.h",
+                "paper_1208_6350_amd/csrc/swx_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_inter_fill_traffic.md")
+
+
+def fill_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in FILL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(pairs):
+    """HBM bytes per forward-fill launch from the committed counter summary,
+    or None when the summary is missing, for another workload size, or was
+    taken on a different version of the fill kernel."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    try:
+        if vals.get("fill_source_sha256") != fill_source_hash() or int(vals["pairs"]) != pairs:
+            return None
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(b, seconds):
@@ -91,6 +130,15 @@ def main():
     cap = int(b.qlen().sum() + b.rlen().sum() + b.npairs)
     cig = torch.empty(cap, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
+    if args.copy_probe_mib > 0:
+        nbytes = args.copy_probe_mib << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy probe: {nbytes} bytes read and written", flush=True, file=sys.stderr)
+        del src, dst
     ctx = swx.Context(0)
 
     def step():
@@ -156,7 +204,8 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(PEAK_PK16_TOPS, 2), "unit": "Tops/s",
-                     "frac": round(achieved / PEAK_PK16_TOPS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_PK16_TOPS, 4),
+                     "traffic": recorded_traffic(b.npairs),
                      "kernel": "k_inter_fill (forward fill, packed 16-bit lanes)",
                      "fill_ms": round(fill_avg, 3), "ops_per_cell": OPS_PER_CELL},
         "stages_ms": stage_avg,

@@ -365,41 +365,60 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 }
 
 // ---- packed reference symbols: per task, column group, lane -------------
-// Thread (lane, phase) of a 256-thread block writes groups phase, phase + 4,
-// ... of its lane, so a wave writes one contiguous 512-byte run per step.
+// One block per task.  The reference bytes of a chunk of 256 columns are read
+// pair by pair (consecutive threads read consecutive bytes of one sequence,
+// so the reads coalesce) into an LDS tile [slot][column], then written out
+// transposed as the [group][lane] words the fill reads.  The tile row stride
+// of 260 bytes keeps the transposed dword reads free of bank conflicts.
+constexpr int kRsymChunk = 256;
+constexpr int kRsymStride = kRsymChunk + 4;
+
 __global__ __launch_bounds__(256) void k_inter_rsym(PackArgs a) {
+  __shared__ uint8_t tile[kSlots16 * kRsymStride];
+  __shared__ const int8_t *s_base[kSlots16];
+  __shared__ int64_t s_len[kSlots16], s_pad[kSlots16];
   const int64_t t = blockIdx.x;
   if (t >= a.ntasks) return;
   const InterTask tk = a.tasks[t];
-  const int lane = threadIdx.x & 63;
-  const int phase = threadIdx.x >> 6;
-  const uint32_t pad4 = (uint32_t)a.n * 0x01010101u;
-  SeqRef r[2];
-  bool live[2] = {false, false};
-  for (int h = 0; h < a.halves; ++h) {
-    const int s = lane + 64 * h;
+  const int nslots = a.halves * 64;
+  for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
     const int64_t p = (s < tk.nslots) ? a.slot_pair[tk.slot_base + s] : -1;
     if (p >= 0) {
       const int64_t lr = a.view.rlen[p];
-      r[h] = make_seq(a.view.rcat + a.view.rstart[p], lr, a.rev ? 0 : tk.rp - lr,
-                      a.view.reversed != 0, a.matrix);
-      live[h] = true;
+      s_base[s] = a.view.rcat + a.view.rstart[p];
+      s_len[s] = lr;
+      s_pad[s] = a.rev ? 0 : tk.rp - lr;
+    } else {
+      s_base[s] = nullptr;
+      s_len[s] = 0;
+      s_pad[s] = 0;
     }
   }
+  __syncthreads();
+  const bool reversed = a.view.reversed != 0;
+  const uint8_t pad_sym = (uint8_t)a.n;
   uint2 *dst = a.rsym + rsym_offset(tk.bnd_off);
-  const int64_t ng = tk.rp / 4;
-  for (int64_t g = phase; g < ng; g += 4) {
-    uint32_t w[2] = {pad4, pad4};
-    for (int h = 0; h < 2; ++h) {
-      if (!live[h]) continue;
-      uint32_t x = 0;
-      for (int k = 0; k < 4; ++k) {
-        const int32_t v = seq_at(r[h], 4 * g + k);
-        x |= (v < 0 ? (uint32_t)a.n : (uint32_t)v) << (8 * k);
-      }
-      w[h] = x;
+  for (int64_t c0 = 0; c0 < tk.rp; c0 += kRsymChunk) {
+    const int64_t c = c0 + threadIdx.x;
+    for (int s = 0; s < nslots; ++s) {
+      const int64_t j = c - s_pad[s];
+      const int64_t len = s_len[s];
+      uint8_t v = pad_sym;
+      if (j >= 0 && j < len) v = (uint8_t)s_base[s][reversed ? len - 1 - j : j];
+      tile[s * kRsymStride + threadIdx.x] = v;
     }
-    dst[g * 64 + lane] = make_uint2(w[0], w[1]);
+    __syncthreads();
+    int64_t ng = (tk.rp - c0) / 4;
+    if (ng > kRsymChunk / 4) ng = kRsymChunk / 4;
+    for (int u = threadIdx.x; u < ng * 64; u += blockDim.x) {
+      const int g = u >> 6, lane = u & 63;
+      const uint32_t x = *reinterpret_cast<const uint32_t *>(&tile[lane * kRsymStride + 4 * g]);
+      const uint32_t y = (a.halves == 2)
+          ? *reinterpret_cast<const uint32_t *>(&tile[(lane + 64) * kRsymStride + 4 * g])
+          : (uint32_t)pad_sym * 0x01010101u;
+      dst[(c0 / 4 + g) * 64 + lane] = make_uint2(x, y);
+    }
+    __syncthreads();
   }
 }
 
