@@ -156,6 +156,28 @@ int swx_align_batch(swx_ctx *ctx, const swx_batch *b, swx_batch_out *out);
  * (host-memory batches only; returns -1 otherwise). */
 int64_t swx_cigar_bound(const swx_batch *b);
 
+/* ---- launch configuration ---------------------------------------------------
+ * Knobs that move work between kernels.  Results never depend on them: every
+ * setting computes the same alignments (rules above), only faster or slower.
+ *   long_cells, long_rlen  a pair with qlen * rlen > long_cells or
+ *                          rlen > long_rlen takes the intra-sequence path
+ *                          (one pair spread over a wave, reference cut into
+ *                          column chunks); others are batched, one pair per
+ *                          16-bit lane half.  Both >= 0.
+ *   intra_jobs             target number of column chunks over all long pairs
+ *                          of one call, >= 1.
+ *   fill_rows              query rows per strip of the batched fill: 16 or 32.
+ * Errors: SWX_EINVAL for null pointers or values out of range (ctx unchanged). */
+typedef struct {
+  int64_t long_cells;
+  int64_t long_rlen;
+  int64_t intra_jobs;
+  int32_t fill_rows;
+  int32_t reserved;    /* must be 0 */
+} swx_tuning;
+int swx_get_tuning(const swx_ctx *ctx, swx_tuning *out);
+int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t);
+
 /* ---- diagnostics ------------------------------------------------------------ */
 const char *swx_strerror(int status);
 const char *swx_last_error(void);

@@ -60,6 +60,12 @@ class SwxBatchOut(ctypes.Structure):
                 ("out_mem", ctypes.c_uint32)]
 
 
+class SwxTuning(ctypes.Structure):
+    _fields_ = [("long_cells", ctypes.c_int64), ("long_rlen", ctypes.c_int64),
+                ("intra_jobs", ctypes.c_int64), ("fill_rows", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 # name -> (restype, argtypes)
 _SIGS = {
     "swx_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
@@ -78,6 +84,8 @@ _SIGS = {
     "swx_last_error": (ctypes.c_char_p, []),
     "swx_last_stage_ms": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                          ctypes.c_int]),
+    "swx_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxTuning)]),
+    "swx_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxTuning)]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -186,6 +194,23 @@ def swx_last_stage_ms(ctx: int, cap: int = 8) -> list:
     return [buf[k] for k in range(n)]
 
 
+def swx_get_tuning(ctx: int) -> dict:
+    t = SwxTuning()
+    _check(lib().swx_get_tuning(ctx, ctypes.byref(t)), "swx_get_tuning")
+    return {k: getattr(t, k) for k, _ in SwxTuning._fields_ if k != "reserved"}
+
+
+def swx_set_tuning(ctx: int, **changes) -> None:
+    """Change some knobs of the launch configuration, keeping the others."""
+    cur = swx_get_tuning(ctx)
+    unknown = set(changes) - set(cur)
+    if unknown:
+        raise KeyError(f"unknown tuning keys {sorted(unknown)}")
+    cur.update(changes)
+    t = SwxTuning(**cur, reserved=0)
+    _check(lib().swx_set_tuning(ctx, ctypes.byref(t)), "swx_set_tuning")
+
+
 def _ptr(x):
     """Address of a numpy array or a torch tensor (host or device)."""
     if x is None:
@@ -266,6 +291,12 @@ class Context:
 
     def stage_ms(self):
         return swx_last_stage_ms(self.handle)
+
+    def tuning(self) -> dict:
+        return swx_get_tuning(self.handle)
+
+    def set_tuning(self, **changes) -> None:
+        swx_set_tuning(self.handle, **changes)
 
     def align_pair(self, query, ref, matrix, o, e, flags=SWX_ALL, mask_len=-1):
         p = swx_profile_create(self.handle, query, matrix, o, e)

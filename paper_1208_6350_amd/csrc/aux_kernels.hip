@@ -536,4 +536,59 @@ hipError_t launch_begins(int64_t npairs, const int32_t *score1, const int32_t *q
   return hipGetLastError();
 }
 
+// ---- long/short split and small gathers for the intra-sequence path -------
+__global__ void k_split_long(int64_t n, const int32_t *qlen, const int64_t *rlen, int64_t cells_thr,
+                             int64_t rlen_thr, uint8_t *is_long, uint8_t *is_short) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const bool lg = (int64_t)qlen[p] * rlen[p] > cells_thr || rlen[p] > rlen_thr;
+  is_long[p] = lg ? 1 : 0;
+  is_short[p] = lg ? 0 : 1;
+}
+
+// out[6k + f]: qlen, rlen, score, qend, rend, band of pair ids[k] (0 for null arrays)
+__global__ void k_gather_pairs(int64_t n, const int64_t *ids, const int32_t *qlen,
+                               const int64_t *rlen, const int32_t *score, const int32_t *qend,
+                               const int64_t *rend, const int32_t *band, int64_t *out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t p = ids[k];
+  out[6 * k + 0] = qlen ? qlen[p] : 0;
+  out[6 * k + 1] = rlen ? rlen[p] : 0;
+  out[6 * k + 2] = score ? score[p] : 0;
+  out[6 * k + 3] = qend ? qend[p] : 0;
+  out[6 * k + 4] = rend ? rend[p] : 0;
+  out[6 * k + 5] = band ? band[p] : 0;
+}
+
+__global__ void k_clear_flags(int64_t n, const int64_t *ids, uint8_t *f1, uint8_t *f2) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  f1[ids[k]] = 0;
+  f2[ids[k]] = 0;
+}
+
+hipError_t split_long(int64_t n, const int32_t *qlen, const int64_t *rlen, int64_t cells_thr,
+                      int64_t rlen_thr, uint8_t *is_long, uint8_t *is_short, hipStream_t st) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_split_long, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, qlen, rlen,
+                     cells_thr, rlen_thr, is_long, is_short);
+  return hipGetLastError();
+}
+
+hipError_t gather_pairs(int64_t n, const int64_t *ids, const int32_t *qlen, const int64_t *rlen,
+                        const int32_t *score, const int32_t *qend, const int64_t *rend,
+                        const int32_t *band, int64_t *out, hipStream_t st) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_pairs, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, ids, qlen,
+                     rlen, score, qend, rend, band, out);
+  return hipGetLastError();
+}
+
+hipError_t clear_flags(int64_t n, const int64_t *ids, uint8_t *f1, uint8_t *f2, hipStream_t st) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_clear_flags, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, ids, f1, f2);
+  return hipGetLastError();
+}
+
 }  // namespace swx

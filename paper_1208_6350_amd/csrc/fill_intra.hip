@@ -1,0 +1,341 @@
+// fill_intra.hip -- intra-sequence Smith-Waterman-Gotoh fill for long pairs.
+//
+// Same recurrences as the inter-sequence fill (paper, Introduction and method
+// section "Algorithm and implementation"), but one pair is spread over the
+// 64 lanes of a wave: lane k owns RL consecutive query rows of a strip of
+// 64*RL rows and computes column c - k at step c.  Per step a lane receives
+// from the lane above, through a one-lane DPP shift, the H leaving that lane's
+// last row, the F entering its own first row, the running column max and the
+// reference symbol; lane 0 receives them from the previous strip's hand-over
+// row (or zeros) and from a 64-column buffer refilled every 64 steps.  The
+// column max leaves lane 63 and is collected, 64 columns at a time, into a
+// register for one coalesced store.
+//
+// Forward pass: the max array of the method section, as one word per column,
+// value << kbits | (2^kbits - 1 - padded row), so that the max over rows and
+// strips also names the first row reaching the value.  The end (rule T1)
+// comes from a reduction over the max array (k_intra_end).
+// Reversed pass: stops at the first reversed column whose max reaches the
+// target score and reports the smallest row there (the begin, rule T2).
+//
+// All lanes are 32-bit, biased like the inter-sequence kernel: scores arrive
+// as S + bias >= 0, E and F are kept biased and floored at 0, and one
+// saturating subtraction of the bias yields H with its zero floor.
+#include <hip/hip_runtime.h>
+
+#include "lanes.h"
+#include "swx_internal.h"
+#include "swx_kernels.h"
+
+namespace swx {
+
+constexpr int kDppWaveShr1 = 0x138;   // DPP control: lane k reads lane k - 1
+
+// value of src from the lane above; lane 0 takes `top`
+__device__ __forceinline__ uint32_t from_above(uint32_t src, uint32_t top) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)top, (int)src, kDppWaveShr1, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, int lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+// vec with lane `at` replaced by the (uniform) v
+__device__ __forceinline__ uint32_t set_lane(uint32_t vec, int at, uint32_t v) {
+  return ((int)threadIdx.x == at) ? v : vec;
+}
+
+template <int RL, bool REV>
+__global__ __launch_bounds__(64) void k_intra_fill(IntraArgs a) {
+  extern __shared__ uint4 s_prof4[];   // [(n + 1) symbols][64 lanes][RL bytes]
+  __shared__ int8_t s_mat[32 * 32];
+  uint8_t *s_prof = reinterpret_cast<uint8_t *>(s_prof4);
+  constexpr int SH = 64 * RL;
+  const int lane = threadIdx.x;
+  const IntraJob jb = a.jobs[blockIdx.x];
+  const int64_t p = jb.pair;
+  const int32_t Lq = a.view.qlen[p];
+  const int64_t Lr = a.view.rlen[p];
+  const int8_t *qs = a.view.qcat + a.view.qstart[p];
+  const int8_t *rs = a.view.rcat + a.view.rstart[p];
+  const bool rv = a.view.reversed != 0;
+  const int n = a.n;
+  for (int i = lane; i < n * n; i += 64) s_mat[i] = a.matrix[i];
+  __syncthreads();
+
+  const int64_t qp = ((int64_t)Lq + SH - 1) / SH * SH;
+  const int nstrips = (int)(qp / SH);
+  const int64_t qpad = REV ? 0 : qp - Lq;   // forward: padding rows on top
+  const int kb = jb.kbits;
+  const uint32_t M = (1u << kb) - 1u;
+  const int32_t tgt = REV ? a.target[p] : 0;
+  uint32_t *bndH = a.bnd + jb.bnd_off;
+  uint32_t *bndF = bndH + (jb.c1 - jb.cw);
+  uint32_t *mc = a.maxcol + jb.mc_off;
+  const uint32_t vbias = (uint32_t)a.bias, vo = (uint32_t)a.o, ve = (uint32_t)a.e;
+  using T = VT<uint32_t>;
+
+  int64_t best_col = -1;    // reversed pass: first column reaching the target
+  int32_t best_row = -1;
+  int64_t plo = 0, phi = 0;  // window of the previous strip
+  for (int s = 0; s < nstrips; ++s) {
+    // column window of this strip
+    int64_t clo = jb.cw, chi = jb.c1;
+    if (REV) {
+      if (jb.band >= 0) {
+        const int64_t l = (int64_t)s * SH - jb.band;
+        if (l > clo) clo = l;
+        const int64_t h = (int64_t)s * SH + SH + jb.band;
+        if (h < chi) chi = h;
+      }
+      if (best_col >= 0 && best_col < chi) chi = best_col;   // only strictly earlier columns
+      if (clo >= chi) break;
+    }
+
+    // strip profile: biased scores of this lane's RL rows against every symbol
+    {
+      int32_t qv[RL];
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int64_t i = (int64_t)s * SH + lane * RL + r - qpad;
+        qv[r] = (i >= 0 && i < Lq) ? (int32_t)qs[rv ? Lq - 1 - i : i] : -1;
+      }
+      for (int sy = 0; sy <= n; ++sy) {
+        uint32_t w[RL / 4];
+#pragma unroll
+        for (int k = 0; k < RL / 4; ++k) w[k] = 0u;
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+          const uint32_t b = (qv[r] >= 0 && sy < n) ? (uint32_t)(uint8_t)(s_mat[qv[r] * n + sy] + a.bias) : 0u;
+          w[r >> 2] |= b << (8 * (r & 3));
+        }
+        uint4 *dst = reinterpret_cast<uint4 *>(s_prof + ((int64_t)sy * 64 + lane) * RL);
+#pragma unroll
+        for (int k = 0; k < RL / 16; ++k)
+          dst[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+      }
+    }
+    __syncthreads();
+
+    // code offset of this lane's rows: code = M - padded row
+    const uint32_t DL = M - (uint32_t)((int64_t)s * SH + lane * RL + RL - 1);
+    const bool hand_over = (s + 1 < nstrips);
+
+    uint32_t H[RL], E[RL];
+#pragma unroll
+    for (int r = 0; r < RL; ++r) { H[r] = 0u; E[r] = 0u; }
+    uint32_t hup_prev = 0u;
+    if (lane == 0 && s > 0 && clo >= 1 && clo - 1 >= plo && clo - 1 < phi) hup_prev = bndH[clo - 1 - jb.cw];
+    uint32_t hout = 0u, fout = 0u, cmout = 0u, sym = (uint32_t)n;
+    uint32_t symbuf = 0u, hbuf = 0u, fbuf = 0u;
+    uint32_t obH = 0u, obF = 0u, obC = 0u;
+    const int64_t nsteps = (chi - clo) + 63;
+    int64_t cdone = chi;
+
+    // store the lane-63 outputs of columns [cbase, cbase + cnt)
+    auto flush = [&](int64_t cbase, int cnt) {
+      if (lane < cnt) {
+        const int64_t col = cbase + lane;
+        if (hand_over) {
+          bndH[col - jb.cw] = obH;
+          bndF[col - jb.cw] = obF;
+        }
+        if (!REV && col >= jb.c0 && col < jb.c1) {
+          uint32_t v = obC;
+          if (s > 0) { const uint32_t old = mc[col]; v = old > v ? old : v; }
+          mc[col] = v;
+        }
+      }
+    };
+
+#pragma unroll 1
+    for (int64_t t = 0; t < nsteps; ++t) {
+      const int tm = (int)(t & 63);
+      if (tm == 0) {
+        // inputs of lane 0 for the next 64 steps
+        const int64_t c = clo + t + lane;
+        const bool in = c < chi;
+        symbuf = in ? (uint32_t)(uint8_t)rs[rv ? Lr - 1 - c : c] : (uint32_t)n;
+        const bool prev = in && s > 0 && c >= plo && c < phi;
+        hbuf = prev ? bndH[c - jb.cw] : 0u;
+        fbuf = prev ? bndF[c - jb.cw] : 0u;
+      }
+      const uint32_t hup = from_above(hout, lane_value(hbuf, tm));
+      uint32_t F = from_above(fout, lane_value(fbuf, tm));
+      const uint32_t cmin = from_above(cmout, 0u);
+      sym = from_above(sym, lane_value(symbuf, tm));
+
+      uint32_t X[RL / 4];
+      {
+        const uint4 *src = reinterpret_cast<const uint4 *>(s_prof + ((int64_t)sym * 64 + lane) * RL);
+#pragma unroll
+        for (int k = 0; k < RL / 16; ++k) {
+          const uint4 v = src[k];
+          X[4 * k] = v.x; X[4 * k + 1] = v.y; X[4 * k + 2] = v.z; X[4 * k + 3] = v.w;
+        }
+      }
+      uint32_t cm = 0u;
+      uint32_t u_next = T::max(hup_prev + __builtin_amdgcn_ubfe(X[0], 0, 8), E[0]);
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const uint32_t u = u_next;
+        if (r + 1 < RL)
+          u_next = T::max(H[r] + __builtin_amdgcn_ubfe(X[(r + 1) >> 2], 8 * ((r + 1) & 3), 8), E[r + 1]);
+        const uint32_t hb = T::max(u, F);
+        const uint32_t hn = T::subs(hb, vbias);
+        H[r] = hn;
+        const uint32_t enc = (hn << kb) + (uint32_t)(RL - 1 - r);
+        cm = cm > enc ? cm : enc;
+        const uint32_t ho = T::subs(hb, vo);
+        E[r] = T::max(T::subs(E[r], ve), ho);
+        F = T::max(T::subs(F, ve), ho);
+      }
+      hup_prev = hup;
+      hout = H[RL - 1];
+      fout = F;
+      const uint32_t cml = cm + DL;
+      cmout = cmin > cml ? cmin : cml;
+
+      if (t >= 63) {
+        const int j = (int)((t - 63) & 63);
+        const int64_t col = clo + t - 63;
+        const uint32_t oc = lane_value(cmout, 63);
+        obH = set_lane(obH, j, lane_value(hout, 63));
+        obF = set_lane(obF, j, lane_value(fout, 63));
+        obC = set_lane(obC, j, oc);
+        if (REV && tgt > 0 && (int32_t)(oc >> kb) >= tgt) {
+          best_col = col;
+          best_row = (int32_t)(M - (oc & M));
+          flush(col - j, j + 1);
+          cdone = col + 1;
+          break;
+        }
+        if (j == 63 || t == nsteps - 1) flush(col - j, j + 1);
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    plo = clo;
+    phi = cdone;
+  }
+
+  if (REV && lane == 0) {
+    const bool hit = best_col >= 0;
+    a.out.score[p] = hit ? tgt : 0;
+    a.out.qend[p] = hit ? best_row : -1;
+    a.out.rend[p] = hit ? best_col : -1;
+    a.out.overflow[p] = 0;
+  }
+}
+
+// ---- end of the best alignment from the max array (rule T1) ---------------
+__device__ __forceinline__ void better(int32_t &bv, int64_t &bj, int32_t v, int64_t j) {
+  if (v > bv || (v == bv && j < bj)) { bv = v; bj = j; }
+}
+
+__device__ void block_best(int32_t &bv, int64_t &bj) {
+  __shared__ int32_t sv[256];
+  __shared__ int64_t sj[256];
+  sv[threadIdx.x] = bv;
+  sj[threadIdx.x] = bj;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      int32_t v = sv[threadIdx.x];
+      int64_t j = sj[threadIdx.x];
+      better(v, j, sv[threadIdx.x + w], sj[threadIdx.x + w]);
+      sv[threadIdx.x] = v;
+      sj[threadIdx.x] = j;
+    }
+    __syncthreads();
+  }
+  bv = sv[0];
+  bj = sj[0];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_intra_end(IntraPairArgs a) {
+  const IntraPair ip = a.pairs[blockIdx.x];
+  const int64_t p = ip.pair;
+  const int64_t Lr = a.rlen[p];
+  const uint32_t *mc = a.maxcol + ip.mc_off;
+  int32_t bv = 0;
+  int64_t bj = INT64_MAX;
+  for (int64_t j = threadIdx.x; j < Lr; j += blockDim.x) {
+    const int32_t v = (int32_t)(mc[j] >> ip.kbits);
+    if (v > bv) { bv = v; bj = j; }
+  }
+  block_best(bv, bj);
+  if (threadIdx.x == 0) {
+    const uint32_t M = (1u << ip.kbits) - 1u;
+    if (bv > 0) {
+      const int64_t qp = ((int64_t)a.qlen[p] + ip.sh - 1) / ip.sh * ip.sh;
+      a.score[p] = bv;
+      a.qend[p] = (int32_t)((int64_t)(M - (mc[bj] & M)) - (qp - a.qlen[p]));
+      a.rend[p] = bj;
+    } else {
+      a.score[p] = 0;
+      a.qend[p] = -1;
+      a.rend[p] = -1;
+    }
+    a.overflow[p] = 0;
+  }
+}
+
+// ---- score2 from the max array (rule T4) ------------------------------------
+__global__ __launch_bounds__(256) void k_intra_score2(IntraPairArgs a) {
+  const IntraPair ip = a.pairs[blockIdx.x];
+  const int64_t p = ip.pair;
+  const int64_t Lr = a.rlen[p];
+  const uint32_t *mc = a.maxcol + ip.mc_off;
+  int32_t bv = 0;
+  int64_t bj = INT64_MAX;
+  if (a.score[p] > 0) {
+    int64_t m = a.mask_len;
+    if (m < 0) { m = a.qlen[p] / 2; if (m < 15) m = 15; }
+    const int64_t lo = a.rbeg[p] - m, hi = a.rend[p] + m;
+    for (int64_t j = threadIdx.x; j < Lr; j += blockDim.x) {
+      if (j >= lo && j <= hi) continue;
+      const int32_t v = (int32_t)(mc[j] >> ip.kbits);
+      if (v > bv) { bv = v; bj = j; }
+    }
+  }
+  block_best(bv, bj);
+  if (threadIdx.x == 0) {
+    a.score2[p] = bv;
+    a.rend2[p] = bv > 0 ? bj : -1;
+  }
+}
+
+// ---- launchers ----------------------------------------------------------------
+size_t intra_lds_bytes(int n, int RL) { return (size_t)(n + 1) * 64 * RL; }
+
+hipError_t intra_fill(const IntraArgs &a, int RL, bool rev, hipStream_t st) {
+  if (a.njobs == 0) return hipSuccess;
+  const dim3 g((unsigned)a.njobs), b(64);
+  const size_t lds = intra_lds_bytes(a.n, RL);
+  if (RL == 16) {
+    if (rev) hipLaunchKernelGGL((k_intra_fill<16, true>), g, b, lds, st, a);
+    else hipLaunchKernelGGL((k_intra_fill<16, false>), g, b, lds, st, a);
+  } else if (RL == 32) {
+    if (rev) hipLaunchKernelGGL((k_intra_fill<32, true>), g, b, lds, st, a);
+    else hipLaunchKernelGGL((k_intra_fill<32, false>), g, b, lds, st, a);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t intra_end(const IntraPairArgs &a, int64_t npairs, hipStream_t st) {
+  if (npairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_intra_end, dim3((unsigned)npairs), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t intra_score2(const IntraPairArgs &a, int64_t npairs, hipStream_t st) {
+  if (npairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_intra_score2, dim3((unsigned)npairs), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace swx

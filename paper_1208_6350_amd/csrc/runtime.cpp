@@ -97,6 +97,11 @@ struct swx_ctx {
   double stage_ms[8] = {};
   int nstages = 0;
   int64_t fill_cells = 0;   // cells of the last forward fill launch
+  // routing of long pairs to the intra-sequence path and its launch shape
+  int64_t long_cells = int64_t(1) << 22;   // qlen * rlen above this ...
+  int64_t long_rlen = int64_t(1) << 16;    // ... or a reference longer than this
+  int64_t intra_jobs = 2048;               // target column chunks over all long pairs
+  int32_t fill_rows = 32;                  // strip height of the batched fill
 };
 
 struct swx_profile {
@@ -422,6 +427,185 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
 
 // ---- the pipeline -----------------------------------------------------------
 
+// ---- long pairs: intra-sequence path ----------------------------------------
+struct LongPath {
+  int64_t nlong = 0, nshort = 0;
+  int64_t *d_long = nullptr;    // long pair ids (device)
+  int64_t *d_short = nullptr;   // short pair ids (device; null: every pair is short)
+  std::vector<int64_t> ids;     // long pair ids (host)
+  std::vector<int64_t> info;    // gather_pairs fields per long pair
+  std::vector<IntraPair> pairs;
+  IntraPair *d_pairs = nullptr;
+  uint32_t *d_maxcol = nullptr;
+};
+
+static int pick_rl(int64_t rows, int n) {
+  return (rows > 1024 && intra_lds_bytes(n, 32) <= 65536) ? 32 : 16;
+}
+
+static int code_bits(int64_t rows_padded) {
+  int k = 1;
+  while ((int64_t(1) << k) < rows_padded) ++k;
+  return k;
+}
+
+static int gather_info(swx_ctx *ctx, int64_t n, const int64_t *d_ids, const int32_t *qlen,
+                       const int64_t *rlen, const int32_t *score, const int32_t *qend,
+                       const int64_t *rend, const int32_t *band, std::vector<int64_t> &info) {
+  int64_t *d = ctx->arena.get<int64_t>(6 * n);
+  if (!d) return fail(SWX_ENOMEM, "device pool exhausted (gather)");
+  HIP_TRY(gather_pairs(n, d_ids, qlen, rlen, score, qend, rend, band, d, ctx->stream));
+  info.resize(6 * n);
+  return read_i64(ctx, d, info.data(), 6 * n);
+}
+
+static int split_pairs(swx_ctx *ctx, int64_t np, const int32_t *qlen, const int64_t *rlen,
+                       LongPath &lp) {
+  DevArena &A = ctx->arena;
+  uint8_t *fl = A.get<uint8_t>(np), *fs = A.get<uint8_t>(np);
+  if (!fl || !fs) return fail(SWX_ENOMEM, "device pool exhausted (split)");
+  HIP_TRY(split_long(np, qlen, rlen, ctx->long_cells, ctx->long_rlen, fl, fs, ctx->stream));
+  int rc;
+  if ((rc = select_flagged(ctx, fl, np, &lp.d_long, &lp.nlong))) return rc;
+  lp.nshort = np - lp.nlong;
+  if (lp.nlong == 0) return SWX_OK;
+  if ((rc = select_flagged(ctx, fs, np, &lp.d_short, &lp.nshort))) return rc;
+  lp.ids.resize(lp.nlong);
+  if ((rc = read_i64(ctx, lp.d_long, lp.ids.data(), lp.nlong))) return rc;
+  return gather_info(ctx, lp.nlong, lp.d_long, qlen, rlen, nullptr, nullptr, nullptr, nullptr,
+                     lp.info);
+}
+
+// Upload jobs (RL = 16 first, then RL = 32) and launch them.
+static int launch_intra_jobs(swx_ctx *ctx, std::vector<IntraJob> jobs[2], IntraArgs a,
+                             int64_t bnd_words, bool rev) {
+  DevArena &A = ctx->arena;
+  const int64_t n16 = (int64_t)jobs[0].size(), n32 = (int64_t)jobs[1].size();
+  if (n16 + n32 == 0) return SWX_OK;
+  IntraJob *dj = A.get<IntraJob>(n16 + n32);
+  a.bnd = A.get<uint32_t>(bnd_words > 0 ? bnd_words : 1);
+  if (!dj || !a.bnd) return fail(SWX_ENOMEM, "device pool exhausted (intra jobs)");
+  std::vector<IntraJob> all(jobs[0]);
+  all.insert(all.end(), jobs[1].begin(), jobs[1].end());
+  HIP_TRY(hipMemcpyAsync(dj, all.data(), sizeof(IntraJob) * all.size(), hipMemcpyHostToDevice,
+                         ctx->stream));
+  if (n16) {
+    a.jobs = dj; a.njobs = n16;
+    HIP_TRY(intra_fill(a, 16, rev, ctx->stream));
+  }
+  if (n32) {
+    a.jobs = dj + n16; a.njobs = n32;
+    HIP_TRY(intra_fill(a, 32, rev, ctx->stream));
+  }
+  // the host job table must outlive the copy
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return SWX_OK;
+}
+
+// Forward pass of the long pairs: column chunks with a warm-up overlap, the
+// encoded max array per pair, then the end (T1) of each pair.
+static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, const PairView &view,
+                             const FillOut &out) {
+  DevArena &A = ctx->arena;
+  int64_t total_r = 0;
+  for (int64_t k = 0; k < lp.nlong; ++k) total_r += std::max<int64_t>(lp.info[6 * k + 1], 1);
+  std::vector<IntraJob> jobs[2];
+  lp.pairs.clear();
+  int64_t mc_words = 0, bnd_words = 0;
+  for (int64_t k = 0; k < lp.nlong; ++k) {
+    const int64_t p = lp.ids[k], Lq = lp.info[6 * k], Lr = lp.info[6 * k + 1];
+    const int RL = pick_rl(Lq, sc.n);
+    const int64_t SH = 64 * RL;
+    const int64_t qp = (Lq + SH - 1) / SH * SH;
+    const int kb = code_bits(qp);
+    const int64_t bound = (int64_t)std::max(sc.smax, 0) * std::min(Lq, Lr);
+    if (kb > 30 || bound >= (int64_t(1) << (32 - kb)))
+      return fail(SWX_EOVERFLOW, "long pair: score range and query length exceed the max-array word");
+    IntraPair ip{p, mc_words, kb, (int32_t)SH};
+    lp.pairs.push_back(ip);
+    if (Lr > 0) {
+      // widest span of a positive-scoring path: the warm-up of every chunk
+      int64_t W = Lr;
+      if (sc.e > 0) W = Lq + std::max<int64_t>((int64_t)sc.smax * Lq - sc.o, 0) / sc.e + 1;
+      const int64_t want = std::max<int64_t>(1, ctx->intra_jobs * Lr / std::max<int64_t>(total_r, 1));
+      int64_t C = (Lr + want - 1) / want;
+      C = std::max<int64_t>(C, std::max<int64_t>(256, W / 2));
+      if (W >= Lr) C = Lr;
+      const bool multi = qp > SH;
+      for (int64_t c0 = 0; c0 < Lr; c0 += C) {
+        IntraJob jb{};
+        jb.pair = p;
+        jb.c0 = c0;
+        jb.c1 = std::min(Lr, c0 + C);
+        jb.cw = std::max<int64_t>(0, c0 - W);
+        jb.mc_off = mc_words;
+        jb.bnd_off = bnd_words;
+        jb.kbits = kb;
+        jb.band = -1;
+        if (multi) bnd_words += 2 * (jb.c1 - jb.cw);
+        jobs[RL == 32].push_back(jb);
+      }
+    }
+    mc_words += Lr;
+  }
+  lp.d_maxcol = A.get<uint32_t>(std::max<int64_t>(mc_words, 1));
+  lp.d_pairs = A.get<IntraPair>(lp.nlong);
+  if (!lp.d_maxcol || !lp.d_pairs) return fail(SWX_ENOMEM, "device pool exhausted (max array)");
+  HIP_TRY(hipMemcpyAsync(lp.d_pairs, lp.pairs.data(), sizeof(IntraPair) * lp.nlong,
+                         hipMemcpyHostToDevice, ctx->stream));
+  IntraArgs a{};
+  a.view = view;
+  a.matrix = sc.dmat;
+  a.n = sc.n; a.o = sc.o; a.e = sc.e; a.bias = sc.bias;
+  a.maxcol = lp.d_maxcol;
+  int rc;
+  if ((rc = launch_intra_jobs(ctx, jobs, a, bnd_words, false))) return rc;
+  IntraPairArgs e{};
+  e.pairs = lp.d_pairs; e.maxcol = lp.d_maxcol; e.qlen = view.qlen; e.rlen = view.rlen;
+  e.score = out.score; e.qend = out.qend; e.rend = out.rend; e.overflow = out.overflow;
+  HIP_TRY(intra_end(e, lp.nlong, ctx->stream));
+  return SWX_OK;
+}
+
+// Reversed pass of the long pairs with a positive score: one job per pair.
+static int run_intra_reverse(swx_ctx *ctx, const Scoring &sc, LongPath &lp, const PairView &rview,
+                             const int32_t *score, const int32_t *qend, const int64_t *rend,
+                             const int32_t *band, const int32_t *tgt, const FillOut &rout) {
+  std::vector<int64_t> info;
+  int rc;
+  if ((rc = gather_info(ctx, lp.nlong, lp.d_long, nullptr, nullptr, score, qend, rend, band, info)))
+    return rc;
+  std::vector<IntraJob> jobs[2];
+  int64_t bnd_words = 0;
+  for (int64_t k = 0; k < lp.nlong; ++k) {
+    if (info[6 * k + 2] <= 0) continue;
+    const int64_t rows = info[6 * k + 3] + 1, cols = info[6 * k + 4] + 1;
+    const int RL = pick_rl(rows, sc.n);
+    const int64_t SH = 64 * RL;
+    const int64_t qp = (rows + SH - 1) / SH * SH;
+    const int kb = code_bits(qp);
+    if (kb > 30 || info[6 * k + 2] >= (int64_t(1) << (32 - kb)))
+      return fail(SWX_EOVERFLOW, "long pair: score range and query length exceed the max-array word");
+    IntraJob jb{};
+    jb.pair = lp.ids[k];
+    jb.cw = 0; jb.c0 = 0; jb.c1 = cols;
+    jb.mc_off = 0;
+    jb.bnd_off = bnd_words;
+    jb.kbits = kb;
+    jb.band = (int32_t)info[6 * k + 5];
+    if (qp > SH) bnd_words += 2 * cols;
+    jobs[RL == 32].push_back(jb);
+  }
+  IntraArgs a{};
+  a.view = rview;
+  a.matrix = sc.dmat;
+  a.n = sc.n; a.o = sc.o; a.e = sc.e; a.bias = sc.bias;
+  a.maxcol = nullptr;
+  a.target = tgt;
+  a.out = rout;
+  return launch_intra_jobs(ctx, jobs, a, bnd_words, true);
+}
+
 static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, uint32_t flags,
                         int32_t mask_len, swx_batch_out *out) {
   DevArena &A = ctx->arena;
@@ -471,11 +655,20 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
   PairView fview{qstart, rstart, qlen, rlen, b.qcat, b.rcat, 0};
   FillOut fout{score, qend, rend, ovf};
 
-  // forward fill, 16-bit lanes (events 1 and 2 bracket the fill kernel)
-  const int R = 32;
+  // long pairs take the intra-sequence path, the rest the batched one
+  LongPath lp;
+  if ((rc = split_pairs(ctx, np, qlen, rlen, lp))) return rc;
+
+  // forward fill, 16-bit lanes (events 1 and 2 bracket the fill kernels)
+  const int R = ctx->fill_rows;
   Plan p16, p32;
-  if ((rc = plan_pass(ctx, sc, nullptr, np, qlen, rlen, nullptr, 16, R, p16))) return rc;
+  if ((rc = plan_pass(ctx, sc, lp.d_short, lp.nshort, qlen, rlen, nullptr, 16, R, p16))) return rc;
   if ((rc = run_fill(ctx, p16, sc, fview, false, nullptr, fout, score_bound, 1))) return rc;
+  if (lp.nlong > 0) {
+    if ((rc = run_intra_forward(ctx, sc, lp, fview, fout))) return rc;
+    HIP_TRY(hipEventRecord(ctx->ev[2], st));
+    HIP_TRY(mark_lanes(lp.nlong, lp.d_long, lanebits, 32, st));
+  }
 
   // saturated pairs: exact re-run on 32-bit lanes
   int64_t *wide = nullptr, nwide = 0;
@@ -499,6 +692,7 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
     HIP_TRY(launch_rev_views(np, qstart, rstart, qlen, rlen, score, qend, rend, rqs, rql, rrs,
                              rrl, tgt, err, st));
     HIP_TRY(rev_prepare(np, score, qend, rend, lanebits, sc.smax, sc.o, sc.e, band, f16, f32, st));
+    if (lp.nlong > 0) HIP_TRY(clear_flags(lp.nlong, lp.d_long, f16, f32, st));
     HIP_TRY(hipMemsetAsync(rsc, 0, sizeof(int32_t) * np, st));
     PairView rview{rqs, rrs, rql, rrl, b.qcat, b.rcat, 1};
     FillOut rout{rsc, rqe, rre, rov};
@@ -510,6 +704,9 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
       if ((rc = plan_pass(ctx, sc, ids, cnt, rql, rrl, band, lb, R, pr))) return rc;
       if ((rc = run_fill(ctx, pr, sc, rview, true, tgt, rout, score_bound))) return rc;
     }
+    if (lp.nlong > 0 &&
+        (rc = run_intra_reverse(ctx, sc, lp, rview, score, qend, rend, band, tgt, rout)))
+      return rc;
     HIP_TRY(launch_begins(np, score, qend, rend, rsc, rqe, rre, qbeg, rbeg, err, st));
   }
   HIP_TRY(hipEventRecord(ctx->ev[4], st));
@@ -542,6 +739,13 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
       s2.tasks = p32.d_tasks; s2.ntasks = p32.ntasks; s2.slot_pair = p32.d_sorted;
       s2.bnd = p32.d_bnd; s2.halves = 1;
       HIP_TRY(launch_score2_inter(s2, st));
+    }
+    if (lp.nlong > 0) {
+      IntraPairArgs e{};
+      e.pairs = lp.d_pairs; e.maxcol = lp.d_maxcol; e.qlen = qlen; e.rlen = rlen;
+      e.score = score; e.qend = qend; e.rend = rend; e.rbeg = rbeg;
+      e.mask_len = mask_len; e.score2 = score2; e.rend2 = rend2;
+      HIP_TRY(intra_score2(e, lp.nlong, st));
     }
   }
   HIP_TRY(hipEventRecord(ctx->ev[6], st));
@@ -595,6 +799,30 @@ const char *swx_strerror(int status) {
 }
 
 const char *swx_last_error(void) { return g_last_error.c_str(); }
+
+int swx_get_tuning(const swx_ctx *ctx, swx_tuning *out) {
+  if (!ctx || !out) return fail(SWX_EINVAL, "null argument");
+  swx_tuning t{};
+  t.long_cells = ctx->long_cells;
+  t.long_rlen = ctx->long_rlen;
+  t.intra_jobs = ctx->intra_jobs;
+  t.fill_rows = ctx->fill_rows;
+  *out = t;
+  return SWX_OK;
+}
+
+int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t) {
+  if (!ctx || !t) return fail(SWX_EINVAL, "null argument");
+  if (t->long_cells < 0 || t->long_rlen < 0 || t->intra_jobs < 1 || t->reserved != 0 ||
+      (t->fill_rows != 16 && t->fill_rows != 32))
+    return fail(SWX_EINVAL, "tuning value out of range");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->long_cells = t->long_cells;
+  ctx->long_rlen = t->long_rlen;
+  ctx->intra_jobs = t->intra_jobs;
+  ctx->fill_rows = t->fill_rows;
+  return SWX_OK;
+}
 
 int swx_ctx_create(int device, swx_ctx **out) {
   if (!out) return fail(SWX_EINVAL, "out is null");

@@ -91,26 +91,36 @@ struct InterArgs {
 // 5-bit row code (value * 32 + code <= 65535).
 constexpr int kInter16Limit = 2047;
 
-// ---- intra-sequence fill (long references) -------------------------------
-// One wave per job; a job is one or two column chunks of one pair (two with
-// 16-bit lanes: low half = chunk A, high half = chunk B).  Lanes hold R rows
-// each; a pass covers 64*R rows; longer queries take several passes with the
-// bottom row handed over through global memory.
+// ---- intra-sequence fill (long pairs) ------------------------------------
+// One wave per job.  Lane k holds rows [k*RL, (k+1)*RL) of a strip of 64*RL
+// query rows and computes column c - k at step c (a wavefront over lanes):
+// the H and F leaving a lane's last row and the running column max move one
+// lane down per step.  Queries taller than a strip take several strips, the
+// strip's last row handed over through global memory.  A long reference is
+// cut into jobs owning columns [c0, c1); each job starts from zero boundaries
+// at cw <= c0, early enough that every positive value in the owned columns is
+// exact (no positive-scoring path spans more than Lq + (smax*Lq - o)/e
+// columns).
 struct IntraJob {
-  int64_t pair;        // pair id
-  int64_t c0[2];       // first computed column of each chunk (-1: unused half)
-  int64_t own0[2];     // first owned column (maxcol written from here)
-  int64_t c1[2];       // one past the last column
-  int64_t mc_base;     // maxcol array of the pair: mc + mc_base (int32 per column)
-  int64_t hand_off;    // pass hand-over buffer (3 planes of ncols_max dwords), or -1
-  int32_t target;      // reversed pass: stop once this score is reached (0: none)
-  int32_t pad_;
+  int64_t pair;      // pair id
+  int64_t cw;        // first computed column
+  int64_t c0, c1;    // owned columns: max array entries are written for these
+  int64_t mc_off;    // forward: the pair's max array at maxcol + mc_off, [rlen] words
+  int64_t bnd_off;   // strip hand-over rows at bnd + bnd_off: H then F, (c1 - cw) words each
+  int32_t kbits;     // row-code bits: max array word = value << kbits | (2^kbits - 1 - row)
+  int32_t band;      // reversed pass: drift band half-width (-1: none)
 };
 
-struct IntraBest {      // per job and half: lexicographic best (score, -col, -row)
-  int32_t score;
-  int32_t row;
-  int64_t col;
+struct IntraArgs {
+  const IntraJob *jobs;
+  int64_t njobs;
+  PairView view;
+  const int8_t *matrix;      // device n x n
+  int32_t n, o, e, bias;
+  uint32_t *maxcol;          // forward: encoded column maxima
+  uint32_t *bnd;             // strip hand-over rows
+  const int32_t *target;     // reversed pass: score to reach, per pair
+  FillOut out;               // reversed pass: reached score, reversed row and column
 };
 
 }  // namespace swx

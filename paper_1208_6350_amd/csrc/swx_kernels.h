@@ -123,6 +123,38 @@ hipError_t rev_prepare(int64_t npairs, const int32_t *score, const int32_t *qend
                        int32_t e, int32_t *band, uint8_t *f16, uint8_t *f32, hipStream_t st);
 
 hipError_t inter_fill(const InterArgs &a, int lane_bits, int R, hipStream_t st);
+
+// intra-sequence path (long pairs)
+struct IntraPair {         // one long pair's forward max array
+  int64_t pair;
+  int64_t mc_off;          // words at maxcol + mc_off, [rlen]
+  int32_t kbits;           // row-code bits
+  int32_t sh;              // strip height of its forward jobs (padding rows = roundup(qlen, sh) - qlen)
+};
+struct IntraPairArgs {
+  const IntraPair *pairs;
+  const uint32_t *maxcol;
+  const int32_t *qlen;
+  const int64_t *rlen;
+  int32_t *score;          // score1 (written by the end kernel, read by score2)
+  int32_t *qend;
+  int64_t *rend;
+  uint8_t *overflow;
+  const int64_t *rbeg;     // score2: begin of the primary alignment
+  int32_t mask_len;
+  int32_t *score2;
+  int64_t *rend2;
+};
+size_t intra_lds_bytes(int n, int RL);
+hipError_t intra_fill(const IntraArgs &a, int RL, bool rev, hipStream_t st);
+hipError_t intra_end(const IntraPairArgs &a, int64_t npairs, hipStream_t st);
+hipError_t intra_score2(const IntraPairArgs &a, int64_t npairs, hipStream_t st);
+hipError_t split_long(int64_t n, const int32_t *qlen, const int64_t *rlen, int64_t cells_thr,
+                      int64_t rlen_thr, uint8_t *is_long, uint8_t *is_short, hipStream_t st);
+hipError_t gather_pairs(int64_t n, const int64_t *ids, const int32_t *qlen, const int64_t *rlen,
+                        const int32_t *score, const int32_t *qend, const int64_t *rend,
+                        const int32_t *band, int64_t *out, hipStream_t st);
+hipError_t clear_flags(int64_t n, const int64_t *ids, uint8_t *f1, uint8_t *f2, hipStream_t st);
 hipError_t inter_pack(const PackArgs &a, hipStream_t st);
 hipError_t inter_pack_ref(const PackArgs &a, hipStream_t st);
 
