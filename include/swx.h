@@ -163,7 +163,10 @@ int64_t swx_cigar_bound(const swx_batch *b);
  *                          rlen > long_rlen takes the intra-sequence path
  *                          (one pair spread over a wave, reference cut into
  *                          column chunks); others are batched, one pair per
- *                          16-bit lane half.  Both >= 0.
+ *                          16-bit lane half.  long_cells = -1 (the default)
+ *                          derives the threshold from each call: twice the
+ *                          call's cells per lane half of a full GPU, at least
+ *                          2048.  long_cells >= -1, long_rlen >= 0.
  *   intra_jobs             target number of column chunks over all long pairs
  *                          of one call, >= 1.
  *   fill_rows              query rows per strip of the batched fill: 16 or 32.

@@ -371,19 +371,24 @@ __global__ void k_validate(ValidateArgs a) {
 }
 
 // ---- small helpers ------------------------------------------------------------
-// stats[0] = max over pairs of min(qlen, rlen)
+// stats[0] = max over pairs of min(qlen, rlen); stats[1] = sum of qlen * rlen
 __global__ void k_pair_stats(int64_t n, const int32_t *qlen, const int64_t *rlen, int64_t *stats) {
-  int64_t best = 0;
+  int64_t best = 0, cells = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
     const int64_t m = qlen[p] < rlen[p] ? qlen[p] : rlen[p];
     best = m > best ? m : best;
+    cells += (int64_t)qlen[p] * rlen[p];
   }
   for (int off = 32; off >= 1; off >>= 1) {
     const int64_t o = __shfl_xor(best, off, 64);
     best = o > best ? o : best;
+    cells += __shfl_xor(cells, off, 64);
   }
-  if ((threadIdx.x & 63) == 0 && best > 0) atomicMax((unsigned long long *)&stats[0], (unsigned long long)best);
+  if ((threadIdx.x & 63) == 0) {
+    if (best > 0) atomicMax((unsigned long long *)&stats[0], (unsigned long long)best);
+    if (cells > 0) atomicAdd((unsigned long long *)&stats[1], (unsigned long long)cells);
+  }
 }
 
 __global__ void k_lens_to_i64(int64_t n, const int32_t *len, int64_t *out) {

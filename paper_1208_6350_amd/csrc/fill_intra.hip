@@ -45,6 +45,36 @@ __device__ __forceinline__ uint32_t set_lane(uint32_t vec, int at, uint32_t v) {
   return ((int)threadIdx.x == at) ? v : vec;
 }
 
+// RL bytes (RL a multiple of 4) of the LDS profile as RL/4 words
+template <int RL>
+__device__ __forceinline__ void lds_load_words(const uint8_t *src, uint32_t (&w)[RL / 4]) {
+  if constexpr (RL % 16 == 0) {
+#pragma unroll
+    for (int k = 0; k < RL / 16; ++k) {
+      const uint4 v = reinterpret_cast<const uint4 *>(src)[k];
+      w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
+    }
+  } else if constexpr (RL == 8) {
+    const uint2 v = *reinterpret_cast<const uint2 *>(src);
+    w[0] = v.x; w[1] = v.y;
+  } else {
+    w[0] = *reinterpret_cast<const uint32_t *>(src);
+  }
+}
+
+template <int RL>
+__device__ __forceinline__ void lds_store_words(uint8_t *dst, const uint32_t (&w)[RL / 4]) {
+  if constexpr (RL % 16 == 0) {
+#pragma unroll
+    for (int k = 0; k < RL / 16; ++k)
+      reinterpret_cast<uint4 *>(dst)[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+  } else if constexpr (RL == 8) {
+    *reinterpret_cast<uint2 *>(dst) = make_uint2(w[0], w[1]);
+  } else {
+    *reinterpret_cast<uint32_t *>(dst) = w[0];
+  }
+}
+
 template <int RL, bool REV>
 __global__ __launch_bounds__(64) void k_intra_fill(IntraArgs a) {
   extern __shared__ uint4 s_prof4[];   // [(n + 1) symbols][64 lanes][RL bytes]
@@ -109,10 +139,7 @@ __global__ __launch_bounds__(64) void k_intra_fill(IntraArgs a) {
           const uint32_t b = (qv[r] >= 0 && sy < n) ? (uint32_t)(uint8_t)(s_mat[qv[r] * n + sy] + a.bias) : 0u;
           w[r >> 2] |= b << (8 * (r & 3));
         }
-        uint4 *dst = reinterpret_cast<uint4 *>(s_prof + ((int64_t)sy * 64 + lane) * RL);
-#pragma unroll
-        for (int k = 0; k < RL / 16; ++k)
-          dst[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+        lds_store_words<RL>(s_prof + ((int64_t)sy * 64 + lane) * RL, w);
       }
     }
     __syncthreads();
@@ -166,14 +193,7 @@ __global__ __launch_bounds__(64) void k_intra_fill(IntraArgs a) {
       sym = from_above(sym, lane_value(symbuf, tm));
 
       uint32_t X[RL / 4];
-      {
-        const uint4 *src = reinterpret_cast<const uint4 *>(s_prof + ((int64_t)sym * 64 + lane) * RL);
-#pragma unroll
-        for (int k = 0; k < RL / 16; ++k) {
-          const uint4 v = src[k];
-          X[4 * k] = v.x; X[4 * k + 1] = v.y; X[4 * k + 2] = v.z; X[4 * k + 3] = v.w;
-        }
-      }
+      lds_load_words<RL>(s_prof + ((int64_t)sym * 64 + lane) * RL, X);
       uint32_t cm = 0u;
       uint32_t u_next = T::max(hup_prev + __builtin_amdgcn_ubfe(X[0], 0, 8), E[0]);
 #pragma unroll
@@ -228,7 +248,13 @@ __global__ __launch_bounds__(64) void k_intra_fill(IntraArgs a) {
   }
 }
 
-// ---- end of the best alignment from the max array (rule T1) ---------------
+// ---- end of the best alignment and score2 from the max array --------------
+// Two phases: blocks (slice, pair) reduce a slice of one pair's max array to
+// its best (value, column) -- the largest value, then the smallest column --
+// and one block per pair reduces the slices.  T1 takes every column; T4
+// skips the masked columns around the primary alignment.
+constexpr int kSlices = 64;
+
 __device__ __forceinline__ void better(int32_t &bv, int64_t &bj, int32_t v, int64_t j) {
   if (v > bv || (v == bv && j < bj)) { bv = v; bj = j; }
 }
@@ -254,47 +280,28 @@ __device__ void block_best(int32_t &bv, int64_t &bj) {
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_intra_end(IntraPairArgs a) {
-  const IntraPair ip = a.pairs[blockIdx.x];
+// mode 0: T1 over all columns; mode 1: T4 outside the mask
+__global__ __launch_bounds__(256) void k_intra_slices(IntraPairArgs a, int mode) {
+  const IntraPair ip = a.pairs[blockIdx.y];
   const int64_t p = ip.pair;
   const int64_t Lr = a.rlen[p];
   const uint32_t *mc = a.maxcol + ip.mc_off;
-  int32_t bv = 0;
-  int64_t bj = INT64_MAX;
-  for (int64_t j = threadIdx.x; j < Lr; j += blockDim.x) {
-    const int32_t v = (int32_t)(mc[j] >> ip.kbits);
-    if (v > bv) { bv = v; bj = j; }
-  }
-  block_best(bv, bj);
-  if (threadIdx.x == 0) {
-    const uint32_t M = (1u << ip.kbits) - 1u;
-    if (bv > 0) {
-      const int64_t qp = ((int64_t)a.qlen[p] + ip.sh - 1) / ip.sh * ip.sh;
-      a.score[p] = bv;
-      a.qend[p] = (int32_t)((int64_t)(M - (mc[bj] & M)) - (qp - a.qlen[p]));
-      a.rend[p] = bj;
-    } else {
-      a.score[p] = 0;
-      a.qend[p] = -1;
-      a.rend[p] = -1;
-    }
-    a.overflow[p] = 0;
-  }
-}
-
-// ---- score2 from the max array (rule T4) ------------------------------------
-__global__ __launch_bounds__(256) void k_intra_score2(IntraPairArgs a) {
-  const IntraPair ip = a.pairs[blockIdx.x];
-  const int64_t p = ip.pair;
-  const int64_t Lr = a.rlen[p];
-  const uint32_t *mc = a.maxcol + ip.mc_off;
-  int32_t bv = 0;
-  int64_t bj = INT64_MAX;
-  if (a.score[p] > 0) {
+  int64_t lo = 1, hi = 0;   // masked columns [lo, hi]
+  bool skip = false;
+  if (mode == 1) {
+    skip = a.score[p] <= 0;
     int64_t m = a.mask_len;
     if (m < 0) { m = a.qlen[p] / 2; if (m < 15) m = 15; }
-    const int64_t lo = a.rbeg[p] - m, hi = a.rend[p] + m;
-    for (int64_t j = threadIdx.x; j < Lr; j += blockDim.x) {
+    lo = a.rbeg[p] - m;
+    hi = a.rend[p] + m;
+  }
+  const int64_t per = (Lr + kSlices - 1) / kSlices;
+  const int64_t j0 = (int64_t)blockIdx.x * per;
+  const int64_t j1 = (j0 + per < Lr) ? j0 + per : Lr;
+  int32_t bv = 0;
+  int64_t bj = INT64_MAX;
+  if (!skip) {
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
       if (j >= lo && j <= hi) continue;
       const int32_t v = (int32_t)(mc[j] >> ip.kbits);
       if (v > bv) { bv = v; bj = j; }
@@ -302,6 +309,35 @@ __global__ __launch_bounds__(256) void k_intra_score2(IntraPairArgs a) {
   }
   block_best(bv, bj);
   if (threadIdx.x == 0) {
+    a.part_v[(int64_t)blockIdx.y * kSlices + blockIdx.x] = bv;
+    a.part_j[(int64_t)blockIdx.y * kSlices + blockIdx.x] = bj;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_intra_finish(IntraPairArgs a, int mode) {
+  const IntraPair ip = a.pairs[blockIdx.x];
+  const int64_t p = ip.pair;
+  if (threadIdx.x != 0) return;
+  int32_t bv = 0;
+  int64_t bj = INT64_MAX;
+  for (int k = 0; k < kSlices; ++k)
+    better(bv, bj, a.part_v[(int64_t)blockIdx.x * kSlices + k],
+           a.part_j[(int64_t)blockIdx.x * kSlices + k]);
+  if (mode == 0) {
+    const uint32_t M = (1u << ip.kbits) - 1u;
+    if (bv > 0) {
+      const int64_t qp = ((int64_t)a.qlen[p] + ip.sh - 1) / ip.sh * ip.sh;
+      const uint32_t w = a.maxcol[ip.mc_off + bj];
+      a.score[p] = bv;
+      a.qend[p] = (int32_t)((int64_t)(M - (w & M)) - (qp - a.qlen[p]));
+      a.rend[p] = bj;
+    } else {
+      a.score[p] = 0;
+      a.qend[p] = -1;
+      a.rend[p] = -1;
+    }
+    a.overflow[p] = 0;
+  } else {
     a.score2[p] = bv;
     a.rend2[p] = bv > 0 ? bj : -1;
   }
@@ -310,32 +346,49 @@ __global__ __launch_bounds__(256) void k_intra_score2(IntraPairArgs a) {
 // ---- launchers ----------------------------------------------------------------
 size_t intra_lds_bytes(int n, int RL) { return (size_t)(n + 1) * 64 * RL; }
 
-hipError_t intra_fill(const IntraArgs &a, int RL, bool rev, hipStream_t st) {
-  if (a.njobs == 0) return hipSuccess;
+template <int RL>
+static void launch_rl(const IntraArgs &a, bool rev, hipStream_t st) {
   const dim3 g((unsigned)a.njobs), b(64);
   const size_t lds = intra_lds_bytes(a.n, RL);
-  if (RL == 16) {
-    if (rev) hipLaunchKernelGGL((k_intra_fill<16, true>), g, b, lds, st, a);
-    else hipLaunchKernelGGL((k_intra_fill<16, false>), g, b, lds, st, a);
-  } else if (RL == 32) {
-    if (rev) hipLaunchKernelGGL((k_intra_fill<32, true>), g, b, lds, st, a);
-    else hipLaunchKernelGGL((k_intra_fill<32, false>), g, b, lds, st, a);
-  } else {
-    return hipErrorInvalidValue;
+  if (rev) hipLaunchKernelGGL((k_intra_fill<RL, true>), g, b, lds, st, a);
+  else hipLaunchKernelGGL((k_intra_fill<RL, false>), g, b, lds, st, a);
+}
+
+hipError_t intra_fill(const IntraArgs &a, int RL, bool rev, hipStream_t st) {
+  if (a.njobs == 0) return hipSuccess;
+  switch (RL) {
+    case 4: launch_rl<4>(a, rev, st); break;
+    case 8: launch_rl<8>(a, rev, st); break;
+    case 16: launch_rl<16>(a, rev, st); break;
+    case 32: launch_rl<32>(a, rev, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int intra_slices() { return kSlices; }
+
+static hipError_t reduce(const IntraPairArgs &a, int64_t npairs, int mode, hipStream_t st) {
+  for (int64_t b0 = 0; b0 < npairs; b0 += 65535) {
+    const int64_t nb = (npairs - b0 < 65535) ? npairs - b0 : 65535;
+    IntraPairArgs s = a;
+    s.pairs = a.pairs + b0;
+    s.part_v = a.part_v + b0 * kSlices;
+    s.part_j = a.part_j + b0 * kSlices;
+    hipLaunchKernelGGL(k_intra_slices, dim3(kSlices, (unsigned)nb), dim3(256), 0, st, s, mode);
+    hipLaunchKernelGGL(k_intra_finish, dim3((unsigned)nb), dim3(64), 0, st, s, mode);
   }
   return hipGetLastError();
 }
 
 hipError_t intra_end(const IntraPairArgs &a, int64_t npairs, hipStream_t st) {
   if (npairs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_intra_end, dim3((unsigned)npairs), dim3(256), 0, st, a);
-  return hipGetLastError();
+  return reduce(a, npairs, 0, st);
 }
 
 hipError_t intra_score2(const IntraPairArgs &a, int64_t npairs, hipStream_t st) {
   if (npairs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_intra_score2, dim3((unsigned)npairs), dim3(256), 0, st, a);
-  return hipGetLastError();
+  return reduce(a, npairs, 1, st);
 }
 
 }  // namespace swx

@@ -98,7 +98,7 @@ struct swx_ctx {
   int nstages = 0;
   int64_t fill_cells = 0;   // cells of the last forward fill launch
   // routing of long pairs to the intra-sequence path and its launch shape
-  int64_t long_cells = int64_t(1) << 22;   // qlen * rlen above this ...
+  int64_t long_cells = -1;                 // qlen * rlen above this (-1: from the batch) ...
   int64_t long_rlen = int64_t(1) << 16;    // ... or a reference longer than this
   int64_t intra_jobs = 2048;               // target column chunks over all long pairs
   int32_t fill_rows = 32;                  // strip height of the batched fill
@@ -437,10 +437,33 @@ struct LongPath {
   std::vector<IntraPair> pairs;
   IntraPair *d_pairs = nullptr;
   uint32_t *d_maxcol = nullptr;
+  int32_t *d_part_v = nullptr;  // partial bests of the max-array reductions
+  int64_t *d_part_j = nullptr;
 };
 
+// Rows per lane of the intra kernel: the fewest instruction slots per column,
+// counting padded rows and about 20 instructions of per-step overhead.
 static int pick_rl(int64_t rows, int n) {
-  return (rows > 1024 && intra_lds_bytes(n, 32) <= 65536) ? 32 : 16;
+  int best = 4;
+  int64_t best_cost = INT64_MAX;
+  for (int RL : {4, 8, 16, 32}) {
+    if (intra_lds_bytes(n, RL) > 65536) continue;
+    const int64_t strips = (rows + 64 * RL - 1) / (64 * RL);
+    const int64_t cost = strips * (12 * RL + 20);
+    if (cost < best_cost) { best_cost = cost; best = RL; }
+  }
+  return best;
+}
+
+static int rl_slot(int RL) { return RL == 4 ? 0 : RL == 8 ? 1 : RL == 16 ? 2 : 3; }
+
+// Pairs above this many cells go to the intra-sequence path.  In the batched
+// path a pair occupies one 16-bit lane half for cells * t; a full GPU holds
+// about 2048 waves * 128 halves, so a pair larger than twice the batch's
+// average work per half would finish last -- it is faster spread over a wave.
+static int64_t long_threshold(const swx_ctx *ctx, int64_t total_cells) {
+  if (ctx->long_cells >= 0) return ctx->long_cells;
+  return std::max<int64_t>(2048, 2 * total_cells / (2048 * 128));
 }
 
 static int code_bits(int64_t rows_padded) {
@@ -460,11 +483,12 @@ static int gather_info(swx_ctx *ctx, int64_t n, const int64_t *d_ids, const int3
 }
 
 static int split_pairs(swx_ctx *ctx, int64_t np, const int32_t *qlen, const int64_t *rlen,
-                       LongPath &lp) {
+                       int64_t total_cells, LongPath &lp) {
   DevArena &A = ctx->arena;
   uint8_t *fl = A.get<uint8_t>(np), *fs = A.get<uint8_t>(np);
   if (!fl || !fs) return fail(SWX_ENOMEM, "device pool exhausted (split)");
-  HIP_TRY(split_long(np, qlen, rlen, ctx->long_cells, ctx->long_rlen, fl, fs, ctx->stream));
+  HIP_TRY(split_long(np, qlen, rlen, long_threshold(ctx, total_cells), ctx->long_rlen, fl, fs,
+                     ctx->stream));
   int rc;
   if ((rc = select_flagged(ctx, fl, np, &lp.d_long, &lp.nlong))) return rc;
   lp.nshort = np - lp.nlong;
@@ -476,26 +500,26 @@ static int split_pairs(swx_ctx *ctx, int64_t np, const int32_t *qlen, const int6
                      lp.info);
 }
 
-// Upload jobs (RL = 16 first, then RL = 32) and launch them.
-static int launch_intra_jobs(swx_ctx *ctx, std::vector<IntraJob> jobs[2], IntraArgs a,
+// Upload jobs (grouped by rows per lane: 4, 8, 16, 32) and launch them.
+static int launch_intra_jobs(swx_ctx *ctx, std::vector<IntraJob> jobs[4], IntraArgs a,
                              int64_t bnd_words, bool rev) {
   DevArena &A = ctx->arena;
-  const int64_t n16 = (int64_t)jobs[0].size(), n32 = (int64_t)jobs[1].size();
-  if (n16 + n32 == 0) return SWX_OK;
-  IntraJob *dj = A.get<IntraJob>(n16 + n32);
+  std::vector<IntraJob> all;
+  for (int g = 0; g < 4; ++g) all.insert(all.end(), jobs[g].begin(), jobs[g].end());
+  if (all.empty()) return SWX_OK;
+  IntraJob *dj = A.get<IntraJob>((int64_t)all.size());
   a.bnd = A.get<uint32_t>(bnd_words > 0 ? bnd_words : 1);
   if (!dj || !a.bnd) return fail(SWX_ENOMEM, "device pool exhausted (intra jobs)");
-  std::vector<IntraJob> all(jobs[0]);
-  all.insert(all.end(), jobs[1].begin(), jobs[1].end());
   HIP_TRY(hipMemcpyAsync(dj, all.data(), sizeof(IntraJob) * all.size(), hipMemcpyHostToDevice,
                          ctx->stream));
-  if (n16) {
-    a.jobs = dj; a.njobs = n16;
-    HIP_TRY(intra_fill(a, 16, rev, ctx->stream));
-  }
-  if (n32) {
-    a.jobs = dj + n16; a.njobs = n32;
-    HIP_TRY(intra_fill(a, 32, rev, ctx->stream));
+  int64_t off = 0;
+  const int rls[4] = {4, 8, 16, 32};
+  for (int g = 0; g < 4; ++g) {
+    if (jobs[g].empty()) continue;
+    a.jobs = dj + off;
+    a.njobs = (int64_t)jobs[g].size();
+    HIP_TRY(intra_fill(a, rls[g], rev, ctx->stream));
+    off += a.njobs;
   }
   // the host job table must outlive the copy
   HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -509,7 +533,7 @@ static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
   DevArena &A = ctx->arena;
   int64_t total_r = 0;
   for (int64_t k = 0; k < lp.nlong; ++k) total_r += std::max<int64_t>(lp.info[6 * k + 1], 1);
-  std::vector<IntraJob> jobs[2];
+  std::vector<IntraJob> jobs[4];
   lp.pairs.clear();
   int64_t mc_words = 0, bnd_words = 0;
   for (int64_t k = 0; k < lp.nlong; ++k) {
@@ -543,14 +567,17 @@ static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
         jb.kbits = kb;
         jb.band = -1;
         if (multi) bnd_words += 2 * (jb.c1 - jb.cw);
-        jobs[RL == 32].push_back(jb);
+        jobs[rl_slot(RL)].push_back(jb);
       }
     }
     mc_words += Lr;
   }
   lp.d_maxcol = A.get<uint32_t>(std::max<int64_t>(mc_words, 1));
   lp.d_pairs = A.get<IntraPair>(lp.nlong);
-  if (!lp.d_maxcol || !lp.d_pairs) return fail(SWX_ENOMEM, "device pool exhausted (max array)");
+  lp.d_part_v = A.get<int32_t>(lp.nlong * intra_slices());
+  lp.d_part_j = A.get<int64_t>(lp.nlong * intra_slices());
+  if (!lp.d_maxcol || !lp.d_pairs || !lp.d_part_v || !lp.d_part_j)
+    return fail(SWX_ENOMEM, "device pool exhausted (max array)");
   HIP_TRY(hipMemcpyAsync(lp.d_pairs, lp.pairs.data(), sizeof(IntraPair) * lp.nlong,
                          hipMemcpyHostToDevice, ctx->stream));
   IntraArgs a{};
@@ -563,6 +590,7 @@ static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
   IntraPairArgs e{};
   e.pairs = lp.d_pairs; e.maxcol = lp.d_maxcol; e.qlen = view.qlen; e.rlen = view.rlen;
   e.score = out.score; e.qend = out.qend; e.rend = out.rend; e.overflow = out.overflow;
+  e.part_v = lp.d_part_v; e.part_j = lp.d_part_j;
   HIP_TRY(intra_end(e, lp.nlong, ctx->stream));
   return SWX_OK;
 }
@@ -575,7 +603,7 @@ static int run_intra_reverse(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
   int rc;
   if ((rc = gather_info(ctx, lp.nlong, lp.d_long, nullptr, nullptr, score, qend, rend, band, info)))
     return rc;
-  std::vector<IntraJob> jobs[2];
+  std::vector<IntraJob> jobs[4];
   int64_t bnd_words = 0;
   for (int64_t k = 0; k < lp.nlong; ++k) {
     if (info[6 * k + 2] <= 0) continue;
@@ -594,7 +622,7 @@ static int run_intra_reverse(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
     jb.kbits = kb;
     jb.band = (int32_t)info[6 * k + 5];
     if (qp > SH) bnd_words += 2 * cols;
-    jobs[RL == 32].push_back(jb);
+    jobs[rl_slot(RL)].push_back(jb);
   }
   IntraArgs a{};
   a.view = rview;
@@ -657,7 +685,7 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
 
   // long pairs take the intra-sequence path, the rest the batched one
   LongPath lp;
-  if ((rc = split_pairs(ctx, np, qlen, rlen, lp))) return rc;
+  if ((rc = split_pairs(ctx, np, qlen, rlen, hstats[1], lp))) return rc;
 
   // forward fill, 16-bit lanes (events 1 and 2 bracket the fill kernels)
   const int R = ctx->fill_rows;
@@ -745,6 +773,7 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
       e.pairs = lp.d_pairs; e.maxcol = lp.d_maxcol; e.qlen = qlen; e.rlen = rlen;
       e.score = score; e.qend = qend; e.rend = rend; e.rbeg = rbeg;
       e.mask_len = mask_len; e.score2 = score2; e.rend2 = rend2;
+      e.part_v = lp.d_part_v; e.part_j = lp.d_part_j;
       HIP_TRY(intra_score2(e, lp.nlong, st));
     }
   }
@@ -813,7 +842,7 @@ int swx_get_tuning(const swx_ctx *ctx, swx_tuning *out) {
 
 int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t) {
   if (!ctx || !t) return fail(SWX_EINVAL, "null argument");
-  if (t->long_cells < 0 || t->long_rlen < 0 || t->intra_jobs < 1 || t->reserved != 0 ||
+  if (t->long_cells < -1 || t->long_rlen < 0 || t->intra_jobs < 1 || t->reserved != 0 ||
       (t->fill_rows != 16 && t->fill_rows != 32))
     return fail(SWX_EINVAL, "tuning value out of range");
   std::lock_guard<std::mutex> g(ctx->mu);

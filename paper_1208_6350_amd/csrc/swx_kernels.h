@@ -144,8 +144,11 @@ struct IntraPairArgs {
   int32_t mask_len;
   int32_t *score2;
   int64_t *rend2;
+  int32_t *part_v;         // per (pair, slice) partial bests: intra_slices() per pair
+  int64_t *part_j;
 };
 size_t intra_lds_bytes(int n, int RL);
+int intra_slices();
 hipError_t intra_fill(const IntraArgs &a, int RL, bool rev, hipStream_t st);
 hipError_t intra_end(const IntraPairArgs &a, int64_t npairs, hipStream_t st);
 hipError_t intra_score2(const IntraPairArgs &a, int64_t npairs, hipStream_t st);

@@ -79,7 +79,8 @@ def test_tuning_invariance(ctx):
     records and CIGARs."""
     b = W.random_pairs(761, 150, (1, 700), (0, 3000))
     base = None
-    for tune in ({}, {"fill_rows": 16}, {"long_cells": 0, "long_rlen": 0, "intra_jobs": 1},
+    for tune in ({}, {"long_cells": -1}, {"fill_rows": 16},
+                 {"long_cells": 0, "long_rlen": 0, "intra_jobs": 1},
                  {"long_cells": 0, "long_rlen": 0, "intra_jobs": 5000},
                  {"long_cells": 100_000, "long_rlen": 1000, "fill_rows": 16}):
         ctx.set_tuning(**{"long_cells": 1 << 22, "long_rlen": 1 << 16, "intra_jobs": 2048,
@@ -97,7 +98,7 @@ def test_tuning_invariance(ctx):
 
 
 def test_tuning_rejects_bad_values(ctx):
-    for bad in ({"fill_rows": 24}, {"intra_jobs": 0}, {"long_cells": -1}):
+    for bad in ({"fill_rows": 24}, {"intra_jobs": 0}, {"long_cells": -2}, {"long_rlen": -1}):
         with pytest.raises(swx.SwxError) as ei:
             ctx.set_tuning(**bad)
         assert ei.value.status == -1

@@ -21,9 +21,19 @@ def _say(msg):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def ctx():
+# Every parity test runs three times: with the default routing, with every
+# pair forced onto the batched (one pair per lane half) path, and with every
+# pair forced onto the intra-sequence (one pair per wave) path.
+PATHS = {"auto": {"long_cells": -1},
+         "batched": {"long_cells": 1 << 62, "long_rlen": 1 << 62},
+         "intra": {"long_cells": 0, "long_rlen": 0, "intra_jobs": 256}}
+
+
+@pytest.fixture(scope="module", params=list(PATHS))
+def ctx(request):
     c = swx.Context(0)
+    c.set_tuning(**PATHS[request.param])
+    c.path = request.param
     yield c
     c.close()
 
@@ -128,7 +138,8 @@ def test_lane_width_threshold(ctx):
         rs.append(ref)
     b = W.from_lists("threshold", mat, 10, 2, qs, rs)
     recs = assert_parity(ctx, b)
-    assert set(recs["lane_bits"]) == {16, 32}
+    if ctx.path == "batched":
+        assert set(recs["lane_bits"]) == {16, 32}
 
 
 def test_many_tasks_ragged(ctx):
