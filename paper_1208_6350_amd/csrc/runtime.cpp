@@ -315,6 +315,10 @@ struct DeviceBatch {
   int64_t qcat_len, rcat_len, nq, nr, npairs;
 };
 
+static int gather_info(swx_ctx *ctx, int64_t n, const int64_t *d_ids, const int32_t *qlen,
+                       const int64_t *rlen, const int32_t *score, const int32_t *qend,
+                       const int64_t *rend, const int32_t *band, std::vector<int64_t> &info);
+
 static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, int64_t np,
                          const int32_t *score, const int32_t *qbeg, const int32_t *qend,
                          const int64_t *rbeg, const int64_t *rend, const int64_t *qstart,
@@ -396,6 +400,41 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
     int32_t *bnd = A.get<int32_t>(tot[1]);
     if (!ta.dir || !bnd) return fail(SWX_ENOMEM, "device pool exhausted (wide band)");
     HIP_TRY(tb_strip(ta, tasks, nt, sorted, bnd, st));
+    pos += nc;
+  }
+  if (hc[6] > 0) {   // long pairs with wide bands: one pair per wave
+    const int64_t nc = hc[6];
+    std::vector<int64_t> info;
+    // gather_pairs fields: qbeg, rbeg, score, qend, rend
+    if ((rc = gather_info(ctx, nc, sorted + pos, qbeg, rbeg, score, qend, rend, nullptr, info)))
+      return rc;
+    std::vector<int64_t> ids(nc);
+    if ((rc = read_i64(ctx, sorted + pos, ids.data(), nc))) return rc;
+    std::vector<TbWaveJob> jobs(nc);
+    int64_t dwords = 0, bwords = 0;
+    for (int64_t k = 0; k < nc; ++k) {
+      TbWaveJob &jb = jobs[k];
+      jb.pair = ids[k];
+      jb.m = info[6 * k + 3] - info[6 * k + 0] + 1;
+      jb.w = info[6 * k + 4] - info[6 * k + 1] + 1;
+      safe_band(jb.m, jb.w, info[6 * k + 2], sc.smax, sc.o, sc.e, &jb.dlo, &jb.bw);
+      jb.dir_off = dwords;
+      jb.bnd_off = bwords;
+      const int64_t SH = 64 * kTbRL, nstrips = (jb.m + SH - 1) / SH;
+      for (int64_t st_ = 0; st_ < nstrips; ++st_) {
+        int64_t clo, chi;
+        tbw_window(st_, jb.dlo, jb.bw, jb.w, &clo, &chi);
+        dwords += ((chi - clo) + 63) * 64;
+      }
+      bwords += 2 * (jb.w + 1);
+    }
+    TbWaveJob *dj = A.get<TbWaveJob>(nc);
+    uint2 *dirw = A.get<uint2>(std::max<int64_t>(dwords, 1));
+    int32_t *bnd = A.get<int32_t>(std::max<int64_t>(bwords, 1));
+    if (!dj || !dirw || !bnd) return fail(SWX_ENOMEM, "device pool exhausted (wave traceback)");
+    HIP_TRY(hipMemcpyAsync(dj, jobs.data(), sizeof(TbWaveJob) * nc, hipMemcpyHostToDevice, st));
+    HIP_TRY(tb_wave(ta, dj, nc, dirw, bnd, st));
+    HIP_TRY(hipStreamSynchronize(st));   // the host job table must outlive the copy
     pos += nc;
   }
   // final CIGAR offsets and compaction into the caller's arena

@@ -84,6 +84,59 @@ struct TbwTask {        // wide-band traceback task (64 pairs)
   int64_t bnd_off;      // ints
 };
 
+// Safe band of the banded pass (method section: the band is set by the
+// begin and the end).  m x w rectangle, score s1: every path of score s1 has
+// at most G = floor((smax*(m+w) - 2o + 2e - 2*s1) / (smax + 2e)) gap symbols,
+// so it stays on diagonals j - i in [min(0,D) - hw, max(0,D) + hw] with
+// D = w - m and hw = floor((G - |D|) / 2).  Returns the lowest diagonal and
+// the number of diagonals.
+__host__ __device__ inline int64_t floor_div64(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+  return q;
+}
+
+__host__ __device__ inline void safe_band(int64_t m, int64_t w, int64_t s1, int32_t smax, int32_t o,
+                                          int32_t e, int64_t *dlo, int64_t *bw) {
+  const int64_t D = w - m;
+  const int64_t num = (int64_t)smax * (m + w) - 2 * o + 2 * e - 2 * s1;
+  const int64_t den = (int64_t)smax + 2 * e;
+  const int64_t G = den > 0 ? floor_div64(num, den) : (m + w);
+  const int64_t aD = D < 0 ? -D : D;
+  const int64_t hw = (G - aD) >= 0 ? (G - aD) / 2 : 0;
+  *dlo = (D < 0 ? D : 0) - hw;
+  *bw = ((D > 0 ? D : 0) + hw) - *dlo + 1;
+}
+
+// Bands wider than 64 diagonals with more cells than this take the
+// wave-parallel traceback (one pair per wave) instead of one pair per lane.
+constexpr int64_t kWaveTbCells = int64_t(1) << 18;
+
+// Wave-parallel traceback of one pair: rows in strips of 64 * kTbRL, lane k
+// holding kTbRL rows, columns swept as a wavefront; choice codes stored per
+// (strip, step, lane) as kTbRL nibbles.
+constexpr int kTbRL = 16;
+struct TbWaveJob {
+  int64_t pair;
+  int64_t m, w;          // rectangle: query rows qbeg..qend, reference columns rbeg..rend
+  int64_t dlo, bw;       // safe band (diagonals j - i, 1-based coordinates)
+  int64_t dir_off;       // uint2 words of choice codes
+  int64_t bnd_off;       // ints of the strip hand-over rows (H then F, w + 1 each)
+};
+
+// column window [clo, chi) of strip s (rows s*SH+1 .. (s+1)*SH, 1-based;
+// column 0 is the virtual column left of the rectangle)
+__host__ __device__ inline void tbw_window(int64_t s, int64_t dlo, int64_t bw, int64_t w,
+                                           int64_t *clo, int64_t *chi) {
+  const int64_t SH = 64 * kTbRL;
+  int64_t lo = s * SH + 1 + dlo;
+  if (lo < 0) lo = 0;
+  int64_t hi = (s + 1) * SH + dlo + bw;
+  if (hi > w + 1) hi = w + 1;
+  *clo = lo;
+  *chi = hi > lo ? hi : lo;
+}
+
 struct TbArgs {
   const int32_t *score;
   const int32_t *qbeg, *qend;
@@ -114,6 +167,8 @@ hipError_t tbw_offsets(int64_t ntasks, TbwTask *tasks, const int64_t *doff, cons
                        hipStream_t st);
 hipError_t tb_strip(const TbArgs &a, const TbwTask *tasks, int64_t ntasks, const int64_t *sorted,
                     int32_t *bndbuf, hipStream_t st);
+hipError_t tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, uint2 *dirw,
+                   int32_t *bnd, hipStream_t st);
 hipError_t count_classes(int64_t n, const uint8_t *cls, int64_t *counts, hipStream_t st);
 hipError_t sort_keys(int64_t n, uint64_t *keys, uint64_t *keys_alt, int64_t *vals,
                      int64_t *vals_alt, void *tmp, size_t *tmp_bytes, int64_t **sorted_out,

@@ -25,25 +25,6 @@ namespace swx {
 
 constexpr int32_t kNeg = -(1 << 29);
 
-__device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b) {
-  int64_t q = a / b;
-  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
-  return q;
-}
-
-// lowest diagonal and width of the safe band of one pair
-__device__ __forceinline__ void safe_band(int64_t m, int64_t w, int64_t s1, int32_t smax, int32_t o,
-                                          int32_t e, int64_t *dlo, int64_t *bw) {
-  const int64_t D = w - m;
-  const int64_t num = (int64_t)smax * (m + w) - 2 * o + 2 * e - 2 * s1;
-  const int64_t den = (int64_t)smax + 2 * e;
-  const int64_t G = den > 0 ? floor_div64(num, den) : (m + w);
-  const int64_t aD = D < 0 ? -D : D;
-  const int64_t hw = (G - aD) >= 0 ? (G - aD) / 2 : 0;
-  *dlo = (D < 0 ? D : 0) - hw;
-  *bw = ((D > 0 ? D : 0) + hw) - *dlo + 1;
-}
-
 __device__ __forceinline__ bool tb_coords_ok(const TbArgs &a, int64_t p) {
   return a.qbeg[p] >= 0 && a.qbeg[p] <= a.qend[p] && a.qend[p] < a.qlen[p] && a.rbeg[p] >= 0 &&
          a.rbeg[p] <= a.rend[p] && a.rend[p] < a.rlen[p];
@@ -61,7 +42,8 @@ __global__ void k_tb_classify(TbArgs a, int64_t npairs, uint8_t *cls, uint64_t *
       m = a.qend[p] - a.qbeg[p] + 1;
       w = a.rend[p] - a.rbeg[p] + 1;
       safe_band(m, w, a.score[p], a.smax, a.o, a.e, &dlo, &bw);
-      c = bw <= 8 ? 1 : bw <= 16 ? 2 : bw <= 32 ? 3 : bw <= 64 ? 4 : 5;
+      c = bw <= 8 ? 1 : bw <= 16 ? 2 : bw <= 32 ? 3 : bw <= 64 ? 4
+          : (m * bw > kWaveTbCells ? 6 : 5);
     } else {
       a.err[p] = 1;
     }
@@ -531,6 +513,236 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
     const uint32_t t = out[x]; out[x] = out[y]; out[y] = t;
   }
   a.cig_len[p] = nruns;
+}
+
+// ---- wave-parallel traceback (long pairs with wide bands) -------------------
+// One pair per wave.  Lane k holds rows [k*RL+1, (k+1)*RL] of a strip of
+// 64*RL rows and computes column c - k at step c; the H and F leaving a lane's
+// last row move one lane down per step through a DPP shift, as in the
+// intra-sequence fill.  Each step stores the lane's RL choice codes (same
+// 4-bit code as the per-lane kernels) as one 8-byte word at [step][lane], so
+// a strip's codes are written with coalesced 512-byte stores.  The walk then
+// runs on the whole wave with uniform state, pulling 64 steps x 64 lanes of
+// codes (32 KiB) at a time into LDS: the walk only moves to smaller steps
+// and lanes inside a strip, so each tile serves at least 32 moves.
+__device__ __forceinline__ int32_t tb_from_above(int32_t src, int32_t top) {
+  return __builtin_amdgcn_update_dpp(top, src, 0x138, 0xF, 0xF, false);   // wave_shr:1
+}
+
+__device__ __forceinline__ uint32_t row0_code(int64_t j, int32_t o, int32_t e) {
+  return (j == 0) ? 0u : (1u | ((j == 1 || o <= e) ? 4u : 0u));
+}
+
+__global__ __launch_bounds__(64) void k_tb_wave(TbArgs a, const TbWaveJob *jobs, uint2 *dirw,
+                                                int32_t *bndbuf) {
+  constexpr int RL = kTbRL;
+  constexpr int64_t SH = 64 * RL;
+  extern __shared__ uint4 s_dyn[];             // profile: [(n+1)][64][RL] score bytes
+  __shared__ uint2 s_tile[64 * 64];
+  __shared__ int8_t s_mat[32 * 32];
+  int8_t *s_prof = reinterpret_cast<int8_t *>(s_dyn);
+  const int lane = threadIdx.x;
+  const TbWaveJob jb = jobs[blockIdx.x];
+  const int64_t p = jb.pair, m = jb.m, w = jb.w;
+  const int n = a.n;
+  const int32_t o = a.o, e = a.e;
+  for (int k = lane; k < n * n; k += 64) s_mat[k] = a.matrix[k];
+  const int8_t *q = a.qcat + a.qstart[p] + a.qbeg[p];
+  const int8_t *r = a.rcat + a.rstart[p] + a.rbeg[p];
+  int32_t *bH = bndbuf + jb.bnd_off;
+  int32_t *bF = bH + (w + 1);
+  // virtual row 0: H(0,0) = 0, H(0,j) = -(o + (j-1)e), F(0,j) = -inf
+  for (int64_t j = lane; j <= w; j += 64) {
+    bH[j] = (j == 0) ? 0 : -(o + (int32_t)(j - 1) * e);
+    bF[j] = kNeg;
+  }
+  __threadfence_block();
+  __syncthreads();
+
+  const int64_t nstrips = (m + SH - 1) / SH;
+  int64_t dcur = jb.dir_off;
+  int64_t plo = 0, phi = w + 1;
+  for (int64_t s = 0; s < nstrips; ++s) {
+    int64_t clo, chi;
+    tbw_window(s, jb.dlo, jb.bw, w, &clo, &chi);
+    // profile of this lane's rows (signed scores; padding rows score 0)
+    {
+      int32_t qv[RL];
+#pragma unroll
+      for (int k = 0; k < RL; ++k) {
+        const int64_t i = s * SH + lane * RL + k + 1;
+        qv[k] = (i <= m) ? (int32_t)q[i - 1] : -1;
+      }
+      for (int sy = 0; sy <= n; ++sy) {
+        uint32_t wv[RL / 4];
+#pragma unroll
+        for (int k = 0; k < RL / 4; ++k) wv[k] = 0u;
+#pragma unroll
+        for (int k = 0; k < RL; ++k) {
+          const uint32_t b = (qv[k] >= 0 && sy < n) ? (uint32_t)(uint8_t)s_mat[qv[k] * n + sy] : 0u;
+          wv[k >> 2] |= b << (8 * (k & 3));
+        }
+        uint4 *dst = reinterpret_cast<uint4 *>(s_prof + ((int64_t)sy * 64 + lane) * RL);
+        *dst = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+      }
+    }
+    __syncthreads();
+    int32_t H[RL], E[RL];
+#pragma unroll
+    for (int k = 0; k < RL; ++k) { H[k] = kNeg; E[k] = kNeg; }
+    int32_t hup_prev = kNeg;
+    if (lane == 0 && clo >= 1 && clo - 1 >= plo && clo - 1 < phi) hup_prev = bH[clo - 1];
+    int32_t hout = kNeg, fout = kNeg;
+    uint32_t sym = (uint32_t)n;
+    int32_t symbuf = 0, hbuf = kNeg, fbuf = kNeg;
+    int32_t obH = 0, obF = 0;
+    const int64_t nsteps = (chi - clo) + 63;
+    const bool hand_over = (s + 1 < nstrips);
+#pragma unroll 1
+    for (int64_t t = 0; t < nsteps; ++t) {
+      const int tm = (int)(t & 63);
+      if (tm == 0) {
+        const int64_t c = clo + t + lane;
+        const bool in = c < chi;
+        symbuf = (in && c >= 1) ? (int32_t)(uint8_t)r[c - 1] : n;
+        const bool prev = in && c >= plo && c < phi;
+        hbuf = prev ? bH[c] : kNeg;
+        fbuf = prev ? bF[c] : kNeg;
+      }
+      const int32_t hup = tb_from_above(hout, __builtin_amdgcn_readlane(hbuf, tm));
+      int32_t fup = tb_from_above(fout, __builtin_amdgcn_readlane(fbuf, tm));
+      sym = (uint32_t)tb_from_above((int32_t)sym, __builtin_amdgcn_readlane(symbuf, tm));
+      const uint4 X = *reinterpret_cast<const uint4 *>(s_prof + ((int64_t)sym * 64 + lane) * RL);
+      const uint32_t Xw[4] = {X.x, X.y, X.z, X.w};
+      int32_t hdiag = hup_prev;
+      int32_t hcur = hup;
+      uint32_t dw0 = 0u, dw1 = 0u;
+#pragma unroll
+      for (int k = 0; k < RL; ++k) {
+        const int32_t sc = __builtin_amdgcn_sbfe((int32_t)Xw[k >> 2], 8 * (k & 3), 8);
+        const int32_t diag = hdiag + sc;
+        const int32_t fo = hcur - o, fx = fup - e;
+        const int32_t fij = fo > fx ? fo : fx;
+        const int32_t eo = H[k] - o, ex = E[k] - e;
+        const int32_t eij = eo > ex ? eo : ex;
+        int32_t h = diag > eij ? diag : eij;
+        h = h > fij ? h : fij;
+        uint32_t c = (h == diag) ? 0u : (h == eij ? 1u : 2u);
+        c |= (eo >= ex) ? 4u : 0u;
+        c |= (fo >= fx) ? 8u : 0u;
+        if (k < 8) dw0 |= c << (4 * k);
+        else dw1 |= c << (4 * (k - 8));
+        hdiag = H[k];
+        H[k] = h;
+        E[k] = eij;
+        hcur = h;
+        fup = fij;
+      }
+      hup_prev = hup;
+      hout = H[RL - 1];
+      fout = fup;
+      dirw[dcur + t * 64 + lane] = make_uint2(dw0, dw1);
+      if (hand_over && t >= 63) {
+        const int jj = (int)((t - 63) & 63);
+        const int32_t vh = __builtin_amdgcn_readlane(hout, 63);
+        const int32_t vf = __builtin_amdgcn_readlane(fout, 63);
+        obH = (lane == jj) ? vh : obH;
+        obF = (lane == jj) ? vf : obF;
+        if (jj == 63 || t == nsteps - 1) {
+          const int64_t col = clo + (t - 63) - jj + lane;
+          if (lane <= jj) { bH[col] = obH; bF[col] = obF; }
+        }
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    dcur += nsteps * 64;
+    plo = clo;
+    phi = chi;
+  }
+
+  // ---- walk back from (m, w) in state H (rule T3), uniform on the wave ------
+  const int64_t cap_end = dcur;
+  uint32_t *out = a.cig + a.cig_off[p];
+  int32_t nruns = 0;
+  int64_t i = m, j = w;
+  int state = 0;
+  uint32_t cur_op = 0xFF, cur_len = 0;
+  int64_t guard = 2 * (m + w) + 4;
+  int64_t ws = nstrips;          // strip whose codes start at wbase
+  int64_t wbase = cap_end, wclo = 0, wchi = 0;
+  int64_t tile_s = -1, tile_lo = 0, tile_hi = -1;
+  bool bad = false;
+  while ((i > 0 || j > 0) && guard-- > 0) {
+    uint32_t c;
+    if (i == 0) {
+      c = row0_code(j, o, e);
+    } else {
+      const int64_t s = (i - 1) / SH;
+      while (ws > s) {   // step the strip cursor up (the walk only moves up)
+        --ws;
+        tbw_window(ws, jb.dlo, jb.bw, w, &wclo, &wchi);
+        wbase -= ((wchi - wclo) + 63) * 64;
+      }
+      if (j < wclo || j >= wchi) { bad = true; break; }
+      const int64_t x = (i - 1) - s * SH;
+      const int L = (int)(x / RL), rr = (int)(x % RL);
+      const int64_t t = (j - wclo) + L;
+      if (s != tile_s || t < tile_lo || t > tile_hi) {
+        tile_s = s;
+        tile_hi = t;
+        tile_lo = t >= 63 ? t - 63 : 0;
+        __syncthreads();
+        for (int k = 0; k < 64; ++k) {
+          const int64_t tt = tile_lo + k;
+          if (tt <= tile_hi) s_tile[k * 64 + lane] = dirw[wbase + tt * 64 + lane];
+        }
+        __syncthreads();
+      }
+      const uint2 dv = s_tile[(t - tile_lo) * 64 + L];
+      c = ((rr < 8 ? dv.x : dv.y) >> (4 * (rr & 7))) & 0xFu;
+    }
+    uint32_t op = 0xFF;
+    if (state == 0) {
+      const uint32_t src = c & 3u;
+      if (src == 0 && i > 0 && j > 0) { op = 0; --i; --j; }
+      else if (src == 1) state = 1;
+      else state = 2;
+    } else if (state == 1) {
+      op = 2;
+      state = (c & 4u) ? 0 : 1;
+      --j;
+    } else {
+      op = 1;
+      state = (c & 8u) ? 0 : 2;
+      --i;
+    }
+    if (op != 0xFF) {
+      if (op == cur_op) {
+        ++cur_len;
+      } else {
+        if (cur_len && lane == 0) out[nruns] = (cur_len << 4) | cur_op;
+        if (cur_len) ++nruns;
+        cur_op = op;
+        cur_len = 1;
+      }
+    }
+  }
+  if (lane != 0) return;
+  if (bad || i != 0 || j != 0) a.err[p] = 1;
+  if (cur_len) out[nruns++] = (cur_len << 4) | cur_op;
+  for (int32_t x = 0, y = nruns - 1; x < y; ++x, --y) {
+    const uint32_t t = out[x]; out[x] = out[y]; out[y] = t;
+  }
+  a.cig_len[p] = nruns;
+}
+
+hipError_t tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, uint2 *dirw,
+                   int32_t *bnd, hipStream_t st) {
+  if (njobs == 0) return hipSuccess;
+  const size_t lds = (size_t)(a.n + 1) * 64 * kTbRL;
+  hipLaunchKernelGGL(k_tb_wave, dim3((unsigned)njobs), dim3(64), lds, st, a, jobs, dirw, bnd);
+  return hipGetLastError();
 }
 
 hipError_t tbw_tasks(int64_t n0, int64_t n1, const int64_t *sorted, const TbArgs &a,
