@@ -181,6 +181,81 @@ typedef struct {
 int swx_get_tuning(const swx_ctx *ctx, swx_tuning *out);
 int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t);
 
+/* ---- serving ------------------------------------------------------------------
+ * A request loop for a stream of alignment requests under one scoring scheme
+ * (the paper's use in read mappers and search servers: many independent
+ * queries against references, results as they complete).
+ *   - Queries can be registered once (swx_server_register_query) and stay on
+ *     the device for the server's lifetime; requests then name them by id.
+ *   - Admission: every request carries an estimate of the device memory its
+ *     work takes (sequences, boundary rows, max array, profile and traceback
+ *     band); requests leave the queue only while the estimates of the work in
+ *     flight stay within mem_budget (a request above the whole budget runs
+ *     alone).
+ *   - Continuous batching: each of `workers` worker threads owns a context
+ *     (own HIP stream and device pool); a free worker takes every queued
+ *     request that fits (up to max_batch) as one batch, so requests arriving
+ *     while batches run join the next batch and batches overlap on the GPU.
+ *   - A request's result never depends on the batch it ran in.
+ * Timestamps are CLOCK_MONOTONIC nanoseconds. */
+typedef struct swx_server swx_server;
+
+typedef struct {
+  int device;
+  const int8_t *matrix; int32_t n; int32_t gap_open; int32_t gap_extend;   /* copied */
+  int64_t mem_budget;   /* bytes; <= 0: 4 GiB */
+  int32_t max_pending;  /* submit accepts no more while this many wait; <= 0: 2^20 */
+  int32_t workers;      /* concurrent batches (1..8); <= 0: 2 */
+  int32_t max_batch;    /* requests per batch; <= 0: 65536 */
+  uint32_t flags;       /* SWX_BEGIN | SWX_CIGAR | SWX_SCORE2 for every request */
+  int32_t mask_len;     /* as for swx_align_batch */
+} swx_server_cfg;
+
+typedef struct {
+  int64_t query_id;     /* >= 0: a registered query; < 0: query[qlen] below (copied) */
+  const int8_t *query; int32_t qlen;
+  const int8_t *ref; int64_t rlen;   /* host codes, copied at submit; rlen may be 0 */
+  uint64_t tag;         /* returned unchanged in the completion */
+} swx_request;
+
+typedef struct {
+  uint64_t ticket, tag;
+  int32_t status;       /* SWX_OK or the batch's error */
+  int32_t batch_size;   /* requests in the batch this one ran in */
+  swx_rec rec;          /* cigar_off is 0: the CIGAR is below */
+  uint32_t *cigar;      /* rec.cigar_len words, malloc'd: release with swx_completion_free */
+  int64_t t_submit_ns, t_start_ns, t_done_ns;
+} swx_completion;
+
+typedef struct {
+  int64_t submitted, deferred;     /* requests accepted / refused with SWX_EBUSY */
+  int64_t admitted, completed;     /* taken into a batch / finished */
+  int64_t batches, max_batch_seen;
+  int64_t pending;                 /* waiting now */
+  int64_t inflight_bytes, peak_inflight_bytes;
+} swx_server_stats;
+
+/* Errors: SWX_EINVAL (nulls, bad scoring, flags), SWX_EDEVICE, SWX_ENOMEM. */
+int swx_server_create(const swx_server_cfg *cfg, swx_server **out);
+/* Uploads a query once; *query_id names it in later requests.  SWX_EINVAL for
+ * qlen < 1 or a symbol >= n. */
+int swx_server_register_query(swx_server *s, const int8_t *query, int32_t qlen, int64_t *query_id);
+/* Queues nreq requests in order; tickets[k] names request k.  All requests
+ * are validated first (SWX_EINVAL: none queued).  When the queue is full the
+ * first *naccepted are queued and SWX_EBUSY is returned. */
+int swx_server_submit(swx_server *s, const swx_request *rq, int32_t nreq, uint64_t *tickets,
+                      int32_t *naccepted);
+/* Moves up to max finished completions into done (waiting up to timeout_us
+ * for the first one when none is ready); *ndone says how many. */
+int swx_server_poll(swx_server *s, swx_completion *done, int32_t max, int32_t timeout_us,
+                    int32_t *ndone);
+/* Releases the CIGARs of n completions (their cigar pointers become NULL). */
+void swx_completion_free(swx_completion *c, int32_t n);
+int swx_server_stats_get(swx_server *s, swx_server_stats *out);
+/* Finishes every queued request, then releases the server (completions not
+ * polled are dropped). */
+int swx_server_destroy(swx_server *s);
+
 /* ---- diagnostics ------------------------------------------------------------ */
 const char *swx_strerror(int status);
 const char *swx_last_error(void);

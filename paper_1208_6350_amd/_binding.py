@@ -66,6 +66,28 @@ class SwxTuning(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class SwxServerCfg(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("matrix", ctypes.c_void_p), ("n", ctypes.c_int32),
+                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32),
+                ("mem_budget", ctypes.c_int64), ("max_pending", ctypes.c_int32),
+                ("workers", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("mask_len", ctypes.c_int32)]
+
+
+class SwxServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in
+                ("submitted", "deferred", "admitted", "completed", "batches", "max_batch_seen",
+                 "pending", "inflight_bytes", "peak_inflight_bytes")]
+
+
+REQ_DTYPE = np.dtype([("query_id", "<i8"), ("query", "<u8"), ("qlen", "<i4"), ("_pad", "<i4"),
+                      ("ref", "<u8"), ("rlen", "<i8"), ("tag", "<u8")])
+assert REQ_DTYPE.itemsize == 48
+COMPLETION_DTYPE = np.dtype([("ticket", "<u8"), ("tag", "<u8"), ("status", "<i4"),
+                             ("batch_size", "<i4"), ("rec", REC_DTYPE), ("cigar", "<u8"),
+                             ("t_submit_ns", "<i8"), ("t_start_ns", "<i8"), ("t_done_ns", "<i8")])
+assert COMPLETION_DTYPE.itemsize == 112
+
 # name -> (restype, argtypes)
 _SIGS = {
     "swx_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
@@ -85,6 +107,17 @@ _SIGS = {
     "swx_last_stage_ms": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                          ctypes.c_int]),
     "swx_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxTuning)]),
+    "swx_server_create": (ctypes.c_int, [ctypes.POINTER(SwxServerCfg),
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "swx_server_register_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                                 ctypes.POINTER(ctypes.c_int64)]),
+    "swx_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "swx_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "swx_completion_free": (None, [ctypes.c_void_p, ctypes.c_int32]),
+    "swx_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxServerStats)]),
+    "swx_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "swx_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxTuning)]),
 }
 EXPORTED = tuple(_SIGS)
@@ -320,3 +353,99 @@ class Context:
                                    pair_r, flags, mask_len, SWX_MEM_HOST, recs, cig, SWX_MEM_HOST)
         _check(st, "swx_align_batch")
         return recs, cig[:used]
+
+
+# ---- serving ------------------------------------------------------------------
+SWX_EBUSY = -4
+
+
+class Server:
+    """Request loop (swx_server_*): resident queries, footprint admission,
+    continuous batching.  Requests are submitted as REQ_DTYPE arrays whose
+    pointers refer to host code arrays the caller keeps alive until submit
+    returns (the library copies them)."""
+
+    def __init__(self, matrix, o, e, device=0, mem_budget=0, max_pending=0, workers=0,
+                 max_batch=0, flags=SWX_ALL, mask_len=-1):
+        self._m = np.ascontiguousarray(matrix, dtype=np.int8)
+        cfg = SwxServerCfg(device=device, matrix=self._m.ctypes.data, n=self._m.shape[0],
+                           gap_open=o, gap_extend=e, mem_budget=mem_budget,
+                           max_pending=max_pending, workers=workers, max_batch=max_batch,
+                           flags=flags, mask_len=mask_len)
+        h = ctypes.c_void_p()
+        _check(lib().swx_server_create(ctypes.byref(cfg), ctypes.byref(h)), "swx_server_create")
+        self.handle = h.value
+
+    def register_query(self, query) -> int:
+        q = np.ascontiguousarray(query, dtype=np.int8)
+        qid = ctypes.c_int64()
+        _check(lib().swx_server_register_query(self.handle, q.ctypes.data, len(q),
+                                               ctypes.byref(qid)), "swx_server_register_query")
+        return qid.value
+
+    def submit(self, reqs: np.ndarray):
+        """Submit a REQ_DTYPE array.  Returns (status, tickets of the accepted prefix)."""
+        reqs = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
+        tickets = np.zeros(len(reqs), dtype=np.uint64)
+        acc = ctypes.c_int32()
+        st = lib().swx_server_submit(self.handle, reqs.ctypes.data, len(reqs),
+                                     tickets.ctypes.data, ctypes.byref(acc))
+        if st not in (SWX_OK, SWX_EBUSY):
+            raise SwxError(st, "swx_server_submit")
+        return st, tickets[:acc.value]
+
+    def poll(self, max_n=4096, timeout_us=0, keep_cigar=False):
+        """Finished completions as a COMPLETION_DTYPE array (and, with
+        keep_cigar, a list of CIGAR word arrays).  CIGAR memory is released."""
+        buf = np.zeros(max_n, dtype=COMPLETION_DTYPE)
+        nd = ctypes.c_int32()
+        _check(lib().swx_server_poll(self.handle, buf.ctypes.data, max_n, int(timeout_us),
+                                     ctypes.byref(nd)), "swx_server_poll")
+        out = buf[:nd.value].copy()
+        cigs = None
+        if keep_cigar:
+            cigs = []
+            for c in out:
+                n = int(c["rec"]["cigar_len"])
+                if n and c["cigar"]:
+                    arr = (ctypes.c_uint32 * n).from_address(int(c["cigar"]))
+                    cigs.append(np.frombuffer(arr, dtype=np.uint32).copy())
+                else:
+                    cigs.append(np.zeros(0, dtype=np.uint32))
+        lib().swx_completion_free(buf.ctypes.data, nd.value)
+        return (out, cigs) if keep_cigar else out
+
+    def stats(self) -> dict:
+        t = SwxServerStats()
+        _check(lib().swx_server_stats_get(self.handle, ctypes.byref(t)), "swx_server_stats_get")
+        return {k: getattr(t, k) for k, _ in SwxServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(lib().swx_server_destroy(self.handle), "swx_server_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_requests(qcat, qoff, rcat, roff, pair_q, pair_r, tags=None, query_ids=None):
+    """REQ_DTYPE array for pairs over concatenated host arrays (which must stay
+    alive until submit returns)."""
+    qcat = np.ascontiguousarray(qcat, dtype=np.int8)
+    rcat = np.ascontiguousarray(rcat, dtype=np.int8)
+    pair_q = np.asarray(pair_q, dtype=np.int64)
+    pair_r = np.asarray(pair_r, dtype=np.int64)
+    qoff = np.asarray(qoff, dtype=np.int64)
+    roff = np.asarray(roff, dtype=np.int64)
+    r = np.zeros(len(pair_q), dtype=REQ_DTYPE)
+    r["query_id"] = -1 if query_ids is None else query_ids
+    r["query"] = qcat.ctypes.data + qoff[pair_q]
+    r["qlen"] = qoff[pair_q + 1] - qoff[pair_q]
+    r["ref"] = rcat.ctypes.data + roff[pair_r]
+    r["rlen"] = roff[pair_r + 1] - roff[pair_r]
+    r["tag"] = np.arange(len(pair_q)) if tags is None else tags
+    return r

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/swx.h"
+#include "runtime_internal.h"
 #include "swx_internal.h"
 #include "swx_kernels.h"
 
@@ -842,6 +843,9 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
                                            std::to_string(nerr) + " pairs");
   return rc_range;
 }
+
+int internal_fail(int code, const char *msg) { return fail(code, msg); }
+hipStream_t internal_stream(swx_ctx *ctx) { return ctx->stream; }
 
 }  // namespace swx
 
