@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--per-pair-sample", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=1e5,
+                    help="offered load of the serving phase, requests per second")
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the timed steps, copy a device buffer of this many MiB once "
                          "(a plain copy kernel of known size for calibrating byte counters)")
@@ -103,6 +107,74 @@ def cpu_baseline(b, seconds):
             "kind": "oracle",
             "sample": f"first {n} pairs of the same workload ({s.cells()/1e9:.2f} G cells, "
                       f"{dt:.1f} s, whole path incl. begin/CIGAR/score2)"}
+
+
+def serving_phase(rate, seconds, warmup=0.25, pool_short=20_000, pool_long=200, workers=8,
+                  mem_budget=32 << 30):
+    """Open-loop Poisson replay of the serving workload through swx_server_*:
+    90% 150-nt reads vs 1-kb windows, 10% 10-kb reads vs 20-kb windows.
+    Latency = completion time - scheduled arrival (so queueing behind an
+    overloaded server counts).  Requests arriving in the first `warmup`
+    seconds are served but not measured."""
+    import numpy as np
+
+    import paper_1208_6350_amd as swx
+    import workloads as W
+    pool = W.config5_pool(n_short=pool_short, n_long=pool_long)
+    is_long = pool.meta["is_long"]
+    g = W.rng_for(105)
+    t_arr, which = W.poisson_schedule(g, rate, warmup + seconds, pool.npairs, is_long, 0.10)
+    n = len(which)
+    reqs = swx.make_requests(pool.qcat, pool.qoff, pool.rcat, pool.roff, pool.pair_q[which],
+                             pool.pair_r[which], tags=np.arange(n))
+    cells = (pool.qlen()[which].astype(np.int64) * pool.rlen()[which])
+    lng = is_long[which]
+    srv = swx.Server(pool.matrix, pool.gap_open, pool.gap_extend, workers=workers,
+                     mem_budget=mem_budget)
+    done_ns = np.zeros(n, dtype=np.int64)
+    bsize = np.zeros(n, dtype=np.int64)
+    t0 = time.monotonic_ns() + 20_000_000
+    arr_ns = t0 + (t_arr * 1e9).astype(np.int64)
+    sub, got, busy = 0, 0, 0
+    limit = t0 + int((warmup + seconds + 120) * 1e9)
+    while got < n and time.monotonic_ns() < limit:
+        now = time.monotonic_ns()
+        k = int(np.searchsorted(arr_ns, now, side="right"))
+        if k > sub:
+            st, tk = srv.submit(reqs[sub:k])
+            busy += (k - sub) - len(tk)
+            sub += len(tk)
+        out = srv.poll(65536, timeout_us=200)
+        if len(out):
+            tags = out["tag"].astype(np.int64)
+            done_ns[tags] = out["t_done_ns"]
+            bsize[tags] = out["batch_size"]
+            got += len(out)
+            if (out["status"] != 0).any():
+                raise RuntimeError("serving request failed")
+    stats = srv.stats()
+    srv.close()
+    if got < n:
+        raise RuntimeError(f"serving phase did not finish: {got}/{n}")
+    meas = t_arr >= warmup
+    lat_ms = (done_ns - arr_ns) / 1e6
+
+    def pct(mask):
+        if not mask.any():
+            return None
+        return {"p50_ms": round(float(np.percentile(lat_ms[mask], 50)), 3),
+                "p99_ms": round(float(np.percentile(lat_ms[mask], 99)), 3),
+                "n": int(mask.sum())}
+    wall = (done_ns[meas].max() - arr_ns[meas].min()) / 1e9
+    return {"offered_per_s": rate, "seconds": seconds, "requests": int(meas.sum()),
+            "offered_gcups": round(float(cells.mean()) * rate / 1e9, 1),
+            "sustained_gcups": round(float(cells[meas].sum()) / wall / 1e9, 1),
+            "latency_all": pct(meas), "latency_short": pct(meas & ~lng),
+            "latency_long": pct(meas & lng),
+            "batches": stats["batches"], "max_batch": stats["max_batch_seen"],
+            "mean_batch": round(float(bsize[meas].mean()), 1), "deferred_busy": busy,
+            "workers": workers, "mem_budget_gib": mem_budget / 2**30,
+            "pool": f"{pool_short} short + {pool_long} long requests"}
 
 
 def main():
@@ -211,6 +283,9 @@ def main():
         "stages_ms": stage_avg,
         "per_pair": per_pair,
     }
+    if not args.no_serve:
+        print("[bench] serving phase", flush=True, file=sys.stderr)
+        line["serving"] = serving_phase(args.serve_rate, args.serve_seconds)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds)
     print(json.dumps(line), flush=True)

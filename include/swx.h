@@ -194,8 +194,11 @@ int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t);
  *     alone).
  *   - Continuous batching: each of `workers` worker threads owns a context
  *     (own HIP stream and device pool); a free worker takes every queued
- *     request that fits (up to max_batch) as one batch, so requests arriving
- *     while batches run join the next batch and batches overlap on the GPU.
+ *     request of one size class that fits (up to max_batch) as one batch, so
+ *     requests arriving while batches run join the next batch and batches
+ *     overlap on the GPU.  With two or more workers, worker 0 serves only
+ *     short requests and the others prefer long ones (qlen * rlen >
+ *     long_cells), so short requests do not wait behind long batches.
  *   - A request's result never depends on the batch it ran in.
  * Timestamps are CLOCK_MONOTONIC nanoseconds. */
 typedef struct swx_server swx_server;
@@ -205,10 +208,11 @@ typedef struct {
   const int8_t *matrix; int32_t n; int32_t gap_open; int32_t gap_extend;   /* copied */
   int64_t mem_budget;   /* bytes; <= 0: 4 GiB */
   int32_t max_pending;  /* submit accepts no more while this many wait; <= 0: 2^20 */
-  int32_t workers;      /* concurrent batches (1..8); <= 0: 2 */
+  int32_t workers;      /* concurrent batches (1..16); <= 0: 2 */
   int32_t max_batch;    /* requests per batch; <= 0: 65536 */
   uint32_t flags;       /* SWX_BEGIN | SWX_CIGAR | SWX_SCORE2 for every request */
   int32_t mask_len;     /* as for swx_align_batch */
+  int64_t long_cells;   /* qlen * rlen above this: long class; <= 0: 2^22 */
 } swx_server_cfg;
 
 typedef struct {

@@ -71,7 +71,8 @@ class SwxServerCfg(ctypes.Structure):
                 ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32),
                 ("mem_budget", ctypes.c_int64), ("max_pending", ctypes.c_int32),
                 ("workers", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("mask_len", ctypes.c_int32)]
+                ("flags", ctypes.c_uint32), ("mask_len", ctypes.c_int32),
+                ("long_cells", ctypes.c_int64)]
 
 
 class SwxServerStats(ctypes.Structure):
@@ -366,12 +367,12 @@ class Server:
     returns (the library copies them)."""
 
     def __init__(self, matrix, o, e, device=0, mem_budget=0, max_pending=0, workers=0,
-                 max_batch=0, flags=SWX_ALL, mask_len=-1):
+                 max_batch=0, flags=SWX_ALL, mask_len=-1, long_cells=0):
         self._m = np.ascontiguousarray(matrix, dtype=np.int8)
         cfg = SwxServerCfg(device=device, matrix=self._m.ctypes.data, n=self._m.shape[0],
                            gap_open=o, gap_extend=e, mem_budget=mem_budget,
                            max_pending=max_pending, workers=workers, max_batch=max_batch,
-                           flags=flags, mask_len=mask_len)
+                           flags=flags, mask_len=mask_len, long_cells=long_cells)
         h = ctypes.c_void_p()
         _check(lib().swx_server_create(ctypes.byref(cfg), ctypes.byref(h)), "swx_server_create")
         self.handle = h.value

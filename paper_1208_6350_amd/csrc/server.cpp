@@ -2,10 +2,12 @@
 // continuous batching on top of the batch path.
 //
 // Requests (a query -- registered once and kept on the device, or inline --
-// and a reference) are queued by swx_server_submit.  Each of `workers` worker
-// threads owns a library context (its own HIP stream and device pool); when a
-// worker is free it takes every queued request that fits the device-memory
-// budget (up to max_batch), runs them as one batch and posts completions.
+// and a reference) are queued by swx_server_submit, short and long ones
+// (query x reference cells above long_cells) in separate FIFO queues.  Each of
+// `workers` worker threads owns a library context (its own HIP stream and
+// device pool); when a worker is free it takes every queued request of one
+// class that fits the device-memory budget (up to max_batch), runs them as one
+// batch and posts completions.
 // Requests that arrive while batches run are picked up by the next free
 // worker, so several batches of mixed sizes overlap on the GPU.  A request's
 // results do not depend on the batch it lands in (the batch path is exact and
@@ -35,6 +37,7 @@ int64_t now_ns() {
 
 struct Req {
   uint64_t ticket = 0, tag = 0;
+  int cls = 0;                    // 0 short, 1 long (cells above the server's threshold)
   int64_t query_id = -1;          // registered query, or -1 (inline: qdata)
   std::vector<int8_t> qdata;
   std::vector<int8_t> rdata;
@@ -90,7 +93,7 @@ struct swx_server {
   std::mutex mu;
   std::condition_variable cv_work;   // workers: pending work or stop
   std::condition_variable cv_done;   // pollers: completions
-  std::deque<Req> pending;
+  std::deque<Req> pending[2];        // [0] short, [1] long requests, FIFO each
   std::deque<swx_completion> done;
   std::vector<RegQuery> queries;
   int64_t inflight_bytes = 0;
@@ -235,6 +238,17 @@ void run_batch(swx_server *s, swx_ctx *ctx, std::vector<Req> &batch, Staging &st
   s->cv_work.notify_all();
 }
 
+// Worker 0 serves only short requests, so a short request never waits behind
+// a batch of long ones; the other workers prefer long requests and take short
+// ones when no long request is admissible.
+int pick_class(const swx_server *s, int w) {
+  if (w == 0 && s->cfg.workers > 1)
+    return (!s->pending[0].empty() && admissible(s, s->pending[0].front(), 0)) ? 0 : -1;
+  for (int c : {1, 0})
+    if (!s->pending[c].empty() && admissible(s, s->pending[c].front(), 0)) return c;
+  return -1;
+}
+
 void worker_main(swx_server *s, int w) {
   swx_ctx *ctx = s->ctxs[w];
   Staging stg;
@@ -244,16 +258,18 @@ void worker_main(swx_server *s, int w) {
     {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv_work.wait(lk, [&] {
-        return (s->stop && s->pending.empty()) ||
-               (!s->pending.empty() && admissible(s, s->pending.front(), 0));
+        return (s->stop && s->pending[0].empty() && s->pending[1].empty()) ||
+               pick_class(s, w) >= 0;
       });
-      if (s->pending.empty()) break;   // stopping and drained
+      const int c = pick_class(s, w);
+      if (c < 0) break;   // stopping, and nothing left for this worker
+      std::deque<Req> &q = s->pending[c];
       int64_t fp = 0;
-      while (!s->pending.empty() && (int64_t)batch.size() < s->cfg.max_batch &&
-             admissible(s, s->pending.front(), fp)) {
-        fp += s->pending.front().footprint;
-        batch.push_back(std::move(s->pending.front()));
-        s->pending.pop_front();
+      while (!q.empty() && (int64_t)batch.size() < s->cfg.max_batch &&
+             admissible(s, q.front(), fp)) {
+        fp += q.front().footprint;
+        batch.push_back(std::move(q.front()));
+        q.pop_front();
       }
       s->inflight_bytes += fp;
       s->stats.admitted += (int64_t)batch.size();
@@ -281,8 +297,9 @@ int swx_server_create(const swx_server_cfg *cfg, swx_server **out) {
   if (s->cfg.mem_budget <= 0) s->cfg.mem_budget = int64_t(4) << 30;
   if (s->cfg.max_pending <= 0) s->cfg.max_pending = 1 << 20;
   if (s->cfg.workers <= 0) s->cfg.workers = 2;
-  if (s->cfg.workers > 8) s->cfg.workers = 8;
+  if (s->cfg.workers > 16) s->cfg.workers = 16;
   if (s->cfg.max_batch <= 0) s->cfg.max_batch = 1 << 16;
+  if (s->cfg.long_cells <= 0) s->cfg.long_cells = int64_t(1) << 22;
   s->matrix.assign(cfg->matrix, cfg->matrix + (size_t)cfg->n * cfg->n);
   s->cfg.matrix = s->matrix.data();
   for (int w = 0; w < s->cfg.workers; ++w) {
@@ -362,16 +379,17 @@ int swx_server_submit(swx_server *s, const swx_request *rq, int32_t nreq, uint64
     }
     if (r.rlen > 0) q.rdata.assign(r.ref, r.ref + r.rlen);
     q.footprint = footprint(ql, r.rlen, s->cfg.n);
+    q.cls = ql * r.rlen > s->cfg.long_cells ? 1 : 0;
     q.t_submit = t;
     reqs.push_back(std::move(q));
   }
   std::lock_guard<std::mutex> g(s->mu);
   int32_t acc = 0;
   for (Req &q : reqs) {
-    if ((int64_t)s->pending.size() >= s->cfg.max_pending) break;
+    if ((int64_t)(s->pending[0].size() + s->pending[1].size()) >= s->cfg.max_pending) break;
     q.ticket = s->next_ticket++;
     tickets[acc++] = q.ticket;
-    s->pending.push_back(std::move(q));
+    s->pending[q.cls].push_back(std::move(q));
   }
   *naccepted = acc;
   s->stats.submitted += acc;
@@ -409,7 +427,7 @@ int swx_server_stats_get(swx_server *s, swx_server_stats *out) {
   if (!s || !out) return swx::internal_fail(SWX_EINVAL, "null argument");
   std::lock_guard<std::mutex> g(s->mu);
   *out = s->stats;
-  out->pending = (int64_t)s->pending.size();
+  out->pending = (int64_t)(s->pending[0].size() + s->pending[1].size());
   out->inflight_bytes = s->inflight_bytes;
   return SWX_OK;
 }
