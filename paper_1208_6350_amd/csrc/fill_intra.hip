@@ -40,9 +40,9 @@ __device__ __forceinline__ uint32_t lane_value(uint32_t v, int lane) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
 }
 
-// vec with lane `at` replaced by the (uniform) v
+// vec with lane `at` of the wave replaced by the (uniform) v
 __device__ __forceinline__ uint32_t set_lane(uint32_t vec, int at, uint32_t v) {
-  return ((int)threadIdx.x == at) ? v : vec;
+  return ((int)(threadIdx.x & 63) == at) ? v : vec;
 }
 
 // RL bytes (RL a multiple of 4) of the LDS profile as RL/4 words
@@ -75,13 +75,35 @@ __device__ __forceinline__ void lds_store_words(uint8_t *dst, const uint32_t (&w
   }
 }
 
+// Strips of one job run on the waves of one workgroup: wave w takes strips
+// w, w + NW, w + 2*NW, ...  Strip s reads the hand-over row of strip s - 1
+// (global memory, one row per boundary) only after strip s - 1 has published,
+// through a progress counter in LDS, that those columns are written.  Every
+// strip depends only on the one above, the waves of a workgroup are resident
+// together, and no strip ever waits on a later one, so the waits always end;
+// a spin limit still bounds them (exceeding it flags the pair as failed).
+constexpr int kMaxStrips = 256;
+constexpr int kMaxWaves = 8;
+constexpr int64_t kSpinLimit = int64_t(1) << 26;
+
+__device__ __forceinline__ void lds_wave_sync() {
+  __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <int RL, bool REV>
-__global__ __launch_bounds__(64) void k_intra_fill(IntraArgs a) {
-  extern __shared__ uint4 s_prof4[];   // [(n + 1) symbols][64 lanes][RL bytes]
+__global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
+  extern __shared__ uint4 s_dyn[];            // per wave: [(n + 1) symbols][64 lanes][RL bytes]
   __shared__ int8_t s_mat[32 * 32];
-  uint8_t *s_prof = reinterpret_cast<uint8_t *>(s_prof4);
+  __shared__ int32_t s_prog[kMaxStrips];      // columns published by strip s (from its window start)
+  __shared__ int32_t s_done[kMaxStrips];      // strip s finished (s_prog is final)
+  __shared__ int64_t s_rcol[kMaxStrips];      // reversed pass: first column of strip s reaching the target
+  __shared__ int32_t s_rrow[kMaxStrips];
+  __shared__ unsigned long long s_best;       // reversed pass: smallest such column so far (~0: none)
   constexpr int SH = 64 * RL;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int NW = blockDim.x >> 6;
   const IntraJob jb = a.jobs[blockIdx.x];
   const int64_t p = jb.pair;
   const int32_t Lq = a.view.qlen[p];
@@ -90,36 +112,63 @@ __global__ __launch_bounds__(64) void k_intra_fill(IntraArgs a) {
   const int8_t *rs = a.view.rcat + a.view.rstart[p];
   const bool rv = a.view.reversed != 0;
   const int n = a.n;
-  for (int i = lane; i < n * n; i += 64) s_mat[i] = a.matrix[i];
-  __syncthreads();
-
   const int64_t qp = ((int64_t)Lq + SH - 1) / SH * SH;
   const int nstrips = (int)(qp / SH);
+  for (int i = threadIdx.x; i < n * n; i += blockDim.x) s_mat[i] = a.matrix[i];
+  for (int i = threadIdx.x; i < nstrips && i < kMaxStrips; i += blockDim.x) {
+    s_prog[i] = 0;
+    s_done[i] = 0;
+    s_rcol[i] = -1;
+    s_rrow[i] = -1;
+  }
+  if (threadIdx.x == 0) s_best = ~0ull;
+  __syncthreads();
+
   const int64_t qpad = REV ? 0 : qp - Lq;   // forward: padding rows on top
   const int kb = jb.kbits;
   const uint32_t M = (1u << kb) - 1u;
   const int32_t tgt = REV ? a.target[p] : 0;
-  uint32_t *bndH = a.bnd + jb.bnd_off;
-  uint32_t *bndF = bndH + (jb.c1 - jb.cw);
+  const int64_t width = jb.c1 - jb.cw;
   uint32_t *mc = a.maxcol + jb.mc_off;
   const uint32_t vbias = (uint32_t)a.bias, vo = (uint32_t)a.o, ve = (uint32_t)a.e;
+  uint8_t *s_prof = reinterpret_cast<uint8_t *>(s_dyn) + (size_t)wave * (n + 1) * 64 * RL;
   using T = VT<uint32_t>;
 
-  int64_t best_col = -1;    // reversed pass: first column reaching the target
-  int32_t best_row = -1;
-  int64_t plo = 0, phi = 0;  // window of the previous strip
-  for (int s = 0; s < nstrips; ++s) {
-    // column window of this strip
-    int64_t clo = jb.cw, chi = jb.c1;
-    if (REV) {
-      if (jb.band >= 0) {
-        const int64_t l = (int64_t)s * SH - jb.band;
-        if (l > clo) clo = l;
-        const int64_t h = (int64_t)s * SH + SH + jb.band;
-        if (h < chi) chi = h;
+  // column window of strip s (the reversed pass bands it)
+  auto window = [&](int s, int64_t &clo, int64_t &chi) {
+    clo = jb.cw;
+    chi = jb.c1;
+    if (REV && jb.band >= 0) {
+      const int64_t l = (int64_t)s * SH - jb.band;
+      if (l > clo) clo = l;
+      const int64_t h = (int64_t)s * SH + SH + jb.band;
+      if (h < chi) chi = h;
+    }
+    if (chi < clo) chi = clo;
+  };
+
+  for (int s = wave; s < nstrips; s += NW) {
+    int64_t clo, chi, plo = 0, phi = 0;
+    window(s, clo, chi);
+    if (s > 0) window(s - 1, plo, phi);
+    uint32_t *bndH = a.bnd + jb.bnd_off + 2 * width * (int64_t)s;   // this strip's hand-over row
+    uint32_t *bndF = bndH + width;
+    uint32_t *inH = bndH - 2 * width;                              // the row of strip s - 1
+    uint32_t *inF = inH + width;
+    const bool hand_over = (s + 1 < nstrips);
+    int32_t published = 0;
+    auto publish = [&](int32_t ncols, bool fin) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if (lane == 0) {
+        __hip_atomic_store(&s_prog[s], ncols, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (fin) __hip_atomic_store(&s_done[s], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
-      if (best_col >= 0 && best_col < chi) chi = best_col;   // only strictly earlier columns
-      if (clo >= chi) break;
+    };
+    // the reversed pass skips a strip that cannot hold an earlier column
+    if (REV && __hip_atomic_load(&s_best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <=
+                   (unsigned long long)clo) {
+      publish(0, true);
+      continue;
     }
 
     // strip profile: biased scores of this lane's RL rows against every symbol
@@ -142,17 +191,36 @@ __global__ __launch_bounds__(64) void k_intra_fill(IntraArgs a) {
         lds_store_words<RL>(s_prof + ((int64_t)sy * 64 + lane) * RL, w);
       }
     }
-    __syncthreads();
+    lds_wave_sync();
 
     // code offset of this lane's rows: code = M - padded row
     const uint32_t DL = M - (uint32_t)((int64_t)s * SH + lane * RL + RL - 1);
-    const bool hand_over = (s + 1 < nstrips);
+    // wait until strip s - 1 has published `need` columns (or finished);
+    // returns the columns available
+    int32_t avail = 0;
+    bool spin_fail = false;
+    auto wait_for = [&](int32_t need) {
+      if (s == 0) return;
+      int64_t spins = 0;
+      for (;;) {
+        const int32_t done = __hip_atomic_load(&s_done[s - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        avail = __hip_atomic_load(&s_prog[s - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (done || avail >= need) break;
+        if (++spins > kSpinLimit) { spin_fail = true; break; }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    };
 
     uint32_t H[RL], E[RL];
 #pragma unroll
     for (int r = 0; r < RL; ++r) { H[r] = 0u; E[r] = 0u; }
     uint32_t hup_prev = 0u;
-    if (lane == 0 && s > 0 && clo >= 1 && clo - 1 >= plo && clo - 1 < phi) hup_prev = bndH[clo - 1 - jb.cw];
+    if (s > 0 && clo >= 1 && clo - 1 >= plo && clo - 1 < phi) {
+      wait_for((int32_t)(clo - plo));
+      if (lane == 0 && clo - 1 < plo + avail)
+        hup_prev = __hip_atomic_load(&inH[clo - 1 - jb.cw], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     uint32_t hout = 0u, fout = 0u, cmout = 0u, sym = (uint32_t)n;
     uint32_t symbuf = 0u, hbuf = 0u, fbuf = 0u;
     uint32_t obH = 0u, obF = 0u, obC = 0u;
@@ -167,25 +235,31 @@ __global__ __launch_bounds__(64) void k_intra_fill(IntraArgs a) {
           bndH[col - jb.cw] = obH;
           bndF[col - jb.cw] = obF;
         }
-        if (!REV && col >= jb.c0 && col < jb.c1) {
-          uint32_t v = obC;
-          if (s > 0) { const uint32_t old = mc[col]; v = old > v ? old : v; }
-          mc[col] = v;
-        }
+        if (!REV && col >= jb.c0 && col < jb.c1) atomicMax(&mc[col], obC);
       }
+      if (hand_over) publish((int32_t)(cbase + cnt - clo), false);
     };
 
 #pragma unroll 1
     for (int64_t t = 0; t < nsteps; ++t) {
       const int tm = (int)(t & 63);
       if (tm == 0) {
+        if (REV && t >= 63 &&
+            (unsigned long long)(clo + t - 63) >=
+                __hip_atomic_load(&s_best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+          cdone = clo + t - 63;   // an earlier strip already reached the target at or before here
+          break;
+        }
         // inputs of lane 0 for the next 64 steps
+        const int64_t cend = (clo + t + 64 < phi) ? clo + t + 64 : phi;
+        if (s > 0 && cend > plo) wait_for((int32_t)(cend - plo));
         const int64_t c = clo + t + lane;
         const bool in = c < chi;
         symbuf = in ? (uint32_t)(uint8_t)rs[rv ? Lr - 1 - c : c] : (uint32_t)n;
-        const bool prev = in && s > 0 && c >= plo && c < phi;
-        hbuf = prev ? bndH[c - jb.cw] : 0u;
-        fbuf = prev ? bndF[c - jb.cw] : 0u;
+        const bool prev = in && s > 0 && c >= plo && c < plo + avail && c < phi;
+        // read past the CU's L1 (another wave of this workgroup wrote them)
+        hbuf = prev ? __hip_atomic_load(&inH[c - jb.cw], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        fbuf = prev ? __hip_atomic_load(&inF[c - jb.cw], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
       }
       const uint32_t hup = from_above(hout, lane_value(hbuf, tm));
       uint32_t F = from_above(fout, lane_value(fbuf, tm));
@@ -224,26 +298,34 @@ __global__ __launch_bounds__(64) void k_intra_fill(IntraArgs a) {
         obF = set_lane(obF, j, lane_value(fout, 63));
         obC = set_lane(obC, j, oc);
         if (REV && tgt > 0 && (int32_t)(oc >> kb) >= tgt) {
-          best_col = col;
-          best_row = (int32_t)(M - (oc & M));
           flush(col - j, j + 1);
           cdone = col + 1;
+          if (lane == 0) {
+            s_rcol[s] = col;
+            s_rrow[s] = (int32_t)(M - (oc & M));
+            atomicMin(&s_best, (unsigned long long)col);
+          }
           break;
         }
         if (j == 63 || t == nsteps - 1) flush(col - j, j + 1);
       }
     }
-    __threadfence_block();
-    __syncthreads();
-    plo = clo;
-    phi = cdone;
+    publish((int32_t)(cdone - clo), true);
+    if (spin_fail && lane == 0) a.err[p] = 1;   // reported as an internal failure
   }
+  __syncthreads();
 
-  if (REV && lane == 0) {
-    const bool hit = best_col >= 0;
+  if (REV && threadIdx.x == 0) {
+    // first column reaching the target; on a tie the earlier strip (smaller row)
+    int64_t bc = -1;
+    int32_t br = -1;
+    for (int s = 0; s < nstrips && s < kMaxStrips; ++s) {
+      if (s_rcol[s] >= 0 && (bc < 0 || s_rcol[s] < bc)) { bc = s_rcol[s]; br = s_rrow[s]; }
+    }
+    const bool hit = bc >= 0;
     a.out.score[p] = hit ? tgt : 0;
-    a.out.qend[p] = hit ? best_row : -1;
-    a.out.rend[p] = hit ? best_col : -1;
+    a.out.qend[p] = hit ? br : -1;
+    a.out.rend[p] = hit ? bc : -1;
     a.out.overflow[p] = 0;
   }
 }
@@ -347,24 +429,29 @@ __global__ __launch_bounds__(64) void k_intra_finish(IntraPairArgs a, int mode) 
 size_t intra_lds_bytes(int n, int RL) { return (size_t)(n + 1) * 64 * RL; }
 
 template <int RL>
-static void launch_rl(const IntraArgs &a, bool rev, hipStream_t st) {
-  const dim3 g((unsigned)a.njobs), b(64);
-  const size_t lds = intra_lds_bytes(a.n, RL);
+static void launch_rl(const IntraArgs &a, int waves, bool rev, hipStream_t st) {
+  const dim3 g((unsigned)a.njobs), b(64 * waves);
+  const size_t lds = intra_lds_bytes(a.n, RL) * waves;
   if (rev) hipLaunchKernelGGL((k_intra_fill<RL, true>), g, b, lds, st, a);
   else hipLaunchKernelGGL((k_intra_fill<RL, false>), g, b, lds, st, a);
 }
 
-hipError_t intra_fill(const IntraArgs &a, int RL, bool rev, hipStream_t st) {
+hipError_t intra_fill(const IntraArgs &a, int RL, int waves, bool rev, hipStream_t st) {
   if (a.njobs == 0) return hipSuccess;
+  if (waves < 1 || waves > kMaxWaves) return hipErrorInvalidValue;
   switch (RL) {
-    case 4: launch_rl<4>(a, rev, st); break;
-    case 8: launch_rl<8>(a, rev, st); break;
-    case 16: launch_rl<16>(a, rev, st); break;
-    case 32: launch_rl<32>(a, rev, st); break;
+    case 4: launch_rl<4>(a, waves, rev, st); break;
+    case 8: launch_rl<8>(a, waves, rev, st); break;
+    case 16: launch_rl<16>(a, waves, rev, st); break;
+    case 32: launch_rl<32>(a, waves, rev, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
+
+int intra_max_strips() { return kMaxStrips; }
+int intra_max_waves() { return kMaxWaves; }
+size_t intra_static_lds() { return 32 * 32 + kMaxStrips * (4 + 4 + 8 + 4) + 8; }
 
 int intra_slices() { return kSlices; }
 

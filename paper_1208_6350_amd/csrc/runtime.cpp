@@ -487,7 +487,7 @@ static int pick_rl(int64_t rows, int n) {
   int best = 4;
   int64_t best_cost = INT64_MAX;
   for (int RL : {4, 8, 16, 32}) {
-    if (intra_lds_bytes(n, RL) > 65536) continue;
+    if (intra_lds_bytes(n, RL) + intra_static_lds() > 65536) continue;
     const int64_t strips = (rows + 64 * RL - 1) / (64 * RL);
     const int64_t cost = strips * (12 * RL + 20);
     if (cost < best_cost) { best_cost = cost; best = RL; }
@@ -540,12 +540,22 @@ static int split_pairs(swx_ctx *ctx, int64_t np, const int32_t *qlen, const int6
                      lp.info);
 }
 
-// Upload jobs (grouped by rows per lane: 4, 8, 16, 32) and launch them.
-static int launch_intra_jobs(swx_ctx *ctx, std::vector<IntraJob> jobs[4], IntraArgs a,
+// Waves per workgroup of an intra job: one per strip, within the LDS budget
+// (a profile of (n + 1) * 64 * RL bytes per wave) and the kernel's maximum.
+static int intra_waves(int64_t nstrips, int n, int RL) {
+  const int64_t per = (int64_t)intra_lds_bytes(n, RL);
+  const int64_t room = (65536 - (int64_t)intra_static_lds()) / per;
+  int64_t w = std::min<int64_t>({nstrips, (int64_t)intra_max_waves(), room});
+  return (int)std::max<int64_t>(w, 1);
+}
+
+// Upload jobs (grouped by rows per lane and waves) and launch them.
+static int launch_intra_jobs(swx_ctx *ctx, std::vector<IntraJob> jobs[4][9], IntraArgs a,
                              int64_t bnd_words, bool rev) {
   DevArena &A = ctx->arena;
   std::vector<IntraJob> all;
-  for (int g = 0; g < 4; ++g) all.insert(all.end(), jobs[g].begin(), jobs[g].end());
+  for (int g = 0; g < 4; ++g)
+    for (int w = 0; w <= 8; ++w) all.insert(all.end(), jobs[g][w].begin(), jobs[g][w].end());
   if (all.empty()) return SWX_OK;
   IntraJob *dj = A.get<IntraJob>((int64_t)all.size());
   a.bnd = A.get<uint32_t>(bnd_words > 0 ? bnd_words : 1);
@@ -555,11 +565,13 @@ static int launch_intra_jobs(swx_ctx *ctx, std::vector<IntraJob> jobs[4], IntraA
   int64_t off = 0;
   const int rls[4] = {4, 8, 16, 32};
   for (int g = 0; g < 4; ++g) {
-    if (jobs[g].empty()) continue;
-    a.jobs = dj + off;
-    a.njobs = (int64_t)jobs[g].size();
-    HIP_TRY(intra_fill(a, rls[g], rev, ctx->stream));
-    off += a.njobs;
+    for (int w = 1; w <= 8; ++w) {
+      if (jobs[g][w].empty()) continue;
+      a.jobs = dj + off;
+      a.njobs = (int64_t)jobs[g][w].size();
+      HIP_TRY(intra_fill(a, rls[g], w, rev, ctx->stream));
+      off += a.njobs;
+    }
   }
   // the host job table must outlive the copy
   HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -569,11 +581,11 @@ static int launch_intra_jobs(swx_ctx *ctx, std::vector<IntraJob> jobs[4], IntraA
 // Forward pass of the long pairs: column chunks with a warm-up overlap, the
 // encoded max array per pair, then the end (T1) of each pair.
 static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, const PairView &view,
-                             const FillOut &out) {
+                             const FillOut &out, uint8_t *err) {
   DevArena &A = ctx->arena;
   int64_t total_r = 0;
   for (int64_t k = 0; k < lp.nlong; ++k) total_r += std::max<int64_t>(lp.info[6 * k + 1], 1);
-  std::vector<IntraJob> jobs[4];
+  std::vector<IntraJob> jobs[4][9];
   lp.pairs.clear();
   int64_t mc_words = 0, bnd_words = 0;
   for (int64_t k = 0; k < lp.nlong; ++k) {
@@ -595,7 +607,10 @@ static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
       int64_t C = (Lr + want - 1) / want;
       C = std::max<int64_t>(C, std::max<int64_t>(256, W / 2));
       if (W >= Lr) C = Lr;
-      const bool multi = qp > SH;
+      const int64_t nstrips = qp / SH;
+      if (nstrips > intra_max_strips())
+        return fail(SWX_EINVAL, "query too long for the intra-sequence path");
+      const int waves = intra_waves(nstrips, sc.n, RL);
       for (int64_t c0 = 0; c0 < Lr; c0 += C) {
         IntraJob jb{};
         jb.pair = p;
@@ -606,13 +621,15 @@ static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
         jb.bnd_off = bnd_words;
         jb.kbits = kb;
         jb.band = -1;
-        if (multi) bnd_words += 2 * (jb.c1 - jb.cw);
-        jobs[rl_slot(RL)].push_back(jb);
+        bnd_words += 2 * (jb.c1 - jb.cw) * (nstrips - 1);
+        jobs[rl_slot(RL)][waves].push_back(jb);
       }
     }
     mc_words += Lr;
   }
   lp.d_maxcol = A.get<uint32_t>(std::max<int64_t>(mc_words, 1));
+  if (lp.d_maxcol && mc_words > 0)
+    HIP_TRY(hipMemsetAsync(lp.d_maxcol, 0, sizeof(uint32_t) * mc_words, ctx->stream));
   lp.d_pairs = A.get<IntraPair>(lp.nlong);
   lp.d_part_v = A.get<int32_t>(lp.nlong * intra_slices());
   lp.d_part_j = A.get<int64_t>(lp.nlong * intra_slices());
@@ -625,6 +642,7 @@ static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
   a.matrix = sc.dmat;
   a.n = sc.n; a.o = sc.o; a.e = sc.e; a.bias = sc.bias;
   a.maxcol = lp.d_maxcol;
+  a.err = err;
   int rc;
   if ((rc = launch_intra_jobs(ctx, jobs, a, bnd_words, false))) return rc;
   IntraPairArgs e{};
@@ -638,12 +656,13 @@ static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
 // Reversed pass of the long pairs with a positive score: one job per pair.
 static int run_intra_reverse(swx_ctx *ctx, const Scoring &sc, LongPath &lp, const PairView &rview,
                              const int32_t *score, const int32_t *qend, const int64_t *rend,
-                             const int32_t *band, const int32_t *tgt, const FillOut &rout) {
+                             const int32_t *band, const int32_t *tgt, const FillOut &rout,
+                             uint8_t *err) {
   std::vector<int64_t> info;
   int rc;
   if ((rc = gather_info(ctx, lp.nlong, lp.d_long, nullptr, nullptr, score, qend, rend, band, info)))
     return rc;
-  std::vector<IntraJob> jobs[4];
+  std::vector<IntraJob> jobs[4][9];
   int64_t bnd_words = 0;
   for (int64_t k = 0; k < lp.nlong; ++k) {
     if (info[6 * k + 2] <= 0) continue;
@@ -654,6 +673,9 @@ static int run_intra_reverse(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
     const int kb = code_bits(qp);
     if (kb > 30 || info[6 * k + 2] >= (int64_t(1) << (32 - kb)))
       return fail(SWX_EOVERFLOW, "long pair: score range and query length exceed the max-array word");
+    const int64_t nstrips = qp / SH;
+    if (nstrips > intra_max_strips())
+      return fail(SWX_EINVAL, "query too long for the intra-sequence path");
     IntraJob jb{};
     jb.pair = lp.ids[k];
     jb.cw = 0; jb.c0 = 0; jb.c1 = cols;
@@ -661,8 +683,8 @@ static int run_intra_reverse(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
     jb.bnd_off = bnd_words;
     jb.kbits = kb;
     jb.band = (int32_t)info[6 * k + 5];
-    if (qp > SH) bnd_words += 2 * cols;
-    jobs[rl_slot(RL)].push_back(jb);
+    bnd_words += 2 * cols * (nstrips - 1);
+    jobs[rl_slot(RL)][intra_waves(nstrips, sc.n, RL)].push_back(jb);
   }
   IntraArgs a{};
   a.view = rview;
@@ -671,6 +693,7 @@ static int run_intra_reverse(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
   a.maxcol = nullptr;
   a.target = tgt;
   a.out = rout;
+  a.err = err;
   return launch_intra_jobs(ctx, jobs, a, bnd_words, true);
 }
 
@@ -733,7 +756,7 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
   if ((rc = plan_pass(ctx, sc, lp.d_short, lp.nshort, qlen, rlen, nullptr, 16, R, p16))) return rc;
   if ((rc = run_fill(ctx, p16, sc, fview, false, nullptr, fout, score_bound, 1))) return rc;
   if (lp.nlong > 0) {
-    if ((rc = run_intra_forward(ctx, sc, lp, fview, fout))) return rc;
+    if ((rc = run_intra_forward(ctx, sc, lp, fview, fout, err))) return rc;
     HIP_TRY(hipEventRecord(ctx->ev[2], st));
     HIP_TRY(mark_lanes(lp.nlong, lp.d_long, lanebits, 32, st));
   }
@@ -773,7 +796,7 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
       if ((rc = run_fill(ctx, pr, sc, rview, true, tgt, rout, score_bound))) return rc;
     }
     if (lp.nlong > 0 &&
-        (rc = run_intra_reverse(ctx, sc, lp, rview, score, qend, rend, band, tgt, rout)))
+        (rc = run_intra_reverse(ctx, sc, lp, rview, score, qend, rend, band, tgt, rout, err)))
       return rc;
     HIP_TRY(launch_begins(np, score, qend, rend, rsc, rqe, rre, qbeg, rbeg, err, st));
   }

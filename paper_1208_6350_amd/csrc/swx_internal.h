@@ -106,10 +106,13 @@ struct IntraJob {
   int64_t cw;        // first computed column
   int64_t c0, c1;    // owned columns: max array entries are written for these
   int64_t mc_off;    // forward: the pair's max array at maxcol + mc_off, [rlen] words
-  int64_t bnd_off;   // strip hand-over rows at bnd + bnd_off: H then F, (c1 - cw) words each
+  int64_t bnd_off;   // hand-over rows at bnd + bnd_off: per strip boundary, H then F, (c1 - cw) words each
   int32_t kbits;     // row-code bits: max array word = value << kbits | (2^kbits - 1 - row)
   int32_t band;      // reversed pass: drift band half-width (-1: none)
 };
+// The strips of a job run on the waves of one workgroup (wave w: strips w,
+// w + NW, ...), strip s consuming strip s - 1's hand-over row as soon as the
+// columns it needs are published.
 
 struct IntraArgs {
   const IntraJob *jobs;
@@ -121,6 +124,7 @@ struct IntraArgs {
   uint32_t *bnd;             // strip hand-over rows
   const int32_t *target;     // reversed pass: score to reach, per pair
   FillOut out;               // reversed pass: reached score, reversed row and column
+  uint8_t *err;              // per pair: set when an internal check fails
 };
 
 }  // namespace swx

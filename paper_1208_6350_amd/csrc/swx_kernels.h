@@ -204,7 +204,10 @@ struct IntraPairArgs {
 };
 size_t intra_lds_bytes(int n, int RL);
 int intra_slices();
-hipError_t intra_fill(const IntraArgs &a, int RL, bool rev, hipStream_t st);
+hipError_t intra_fill(const IntraArgs &a, int RL, int waves, bool rev, hipStream_t st);
+int intra_max_strips();
+int intra_max_waves();
+size_t intra_static_lds();
 hipError_t intra_end(const IntraPairArgs &a, int64_t npairs, hipStream_t st);
 hipError_t intra_score2(const IntraPairArgs &a, int64_t npairs, hipStream_t st);
 hipError_t split_long(int64_t n, const int32_t *qlen, const int64_t *rlen, int64_t cells_thr,
