@@ -412,6 +412,7 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
     std::vector<int64_t> ids(nc);
     if ((rc = read_i64(ctx, sorted + pos, ids.data(), nc))) return rc;
     std::vector<TbWaveJob> jobs(nc);
+    std::vector<int> waves(nc);
     int64_t dwords = 0, bwords = 0;
     for (int64_t k = 0; k < nc; ++k) {
       TbWaveJob &jb = jobs[k];
@@ -422,19 +423,33 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
       jb.dir_off = dwords;
       jb.bnd_off = bwords;
       const int64_t SH = 64 * kTbRL, nstrips = (jb.m + SH - 1) / SH;
+      if (nstrips > tb_wave_max_strips())
+        return fail(SWX_EINVAL, "alignment too long for the wave traceback");
       for (int64_t st_ = 0; st_ < nstrips; ++st_) {
         int64_t clo, chi;
         tbw_window(st_, jb.dlo, jb.bw, jb.w, &clo, &chi);
         dwords += ((chi - clo) + 63) * 64;
       }
-      bwords += 2 * (jb.w + 1);
+      bwords += 2 * (jb.w + 1) * (nstrips + 1);
+      waves[k] = tb_wave_waves(jb.m, sc.n);
     }
+    // launch groups of equal workgroup size
+    std::vector<int64_t> order(nc);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return waves[x] < waves[y]; });
+    std::vector<TbWaveJob> sorted_jobs(nc);
+    for (int64_t k = 0; k < nc; ++k) sorted_jobs[k] = jobs[order[k]];
     TbWaveJob *dj = A.get<TbWaveJob>(nc);
     uint2 *dirw = A.get<uint2>(std::max<int64_t>(dwords, 1));
     int32_t *bnd = A.get<int32_t>(std::max<int64_t>(bwords, 1));
     if (!dj || !dirw || !bnd) return fail(SWX_ENOMEM, "device pool exhausted (wave traceback)");
-    HIP_TRY(hipMemcpyAsync(dj, jobs.data(), sizeof(TbWaveJob) * nc, hipMemcpyHostToDevice, st));
-    HIP_TRY(tb_wave(ta, dj, nc, dirw, bnd, st));
+    HIP_TRY(hipMemcpyAsync(dj, sorted_jobs.data(), sizeof(TbWaveJob) * nc, hipMemcpyHostToDevice, st));
+    for (int64_t k0 = 0; k0 < nc;) {
+      int64_t k1 = k0;
+      while (k1 < nc && waves[order[k1]] == waves[order[k0]]) ++k1;
+      HIP_TRY(tb_wave(ta, dj + k0, k1 - k0, waves[order[k0]], dirw, bnd, st));
+      k0 = k1;
+    }
     HIP_TRY(hipStreamSynchronize(st));   // the host job table must outlive the copy
     pos += nc;
   }

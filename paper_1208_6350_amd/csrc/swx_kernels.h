@@ -121,7 +121,8 @@ struct TbWaveJob {
   int64_t m, w;          // rectangle: query rows qbeg..qend, reference columns rbeg..rend
   int64_t dlo, bw;       // safe band (diagonals j - i, 1-based coordinates)
   int64_t dir_off;       // uint2 words of choice codes
-  int64_t bnd_off;       // ints of the strip hand-over rows (H then F, w + 1 each)
+  int64_t bnd_off;       // ints of the hand-over rows: per strip boundary (and the
+                         // virtual top row) H then F, w + 1 each
 };
 
 // column window [clo, chi) of strip s (rows s*SH+1 .. (s+1)*SH, 1-based;
@@ -167,8 +168,10 @@ hipError_t tbw_offsets(int64_t ntasks, TbwTask *tasks, const int64_t *doff, cons
                        hipStream_t st);
 hipError_t tb_strip(const TbArgs &a, const TbwTask *tasks, int64_t ntasks, const int64_t *sorted,
                     int32_t *bndbuf, hipStream_t st);
-hipError_t tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, uint2 *dirw,
+hipError_t tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, int waves, uint2 *dirw,
                    int32_t *bnd, hipStream_t st);
+int tb_wave_waves(int64_t m, int n);   // waves per workgroup for a pair of m rows
+int tb_wave_max_strips();
 hipError_t count_classes(int64_t n, const uint8_t *cls, int64_t *counts, hipStream_t st);
 hipError_t sort_keys(int64_t n, uint64_t *keys, uint64_t *keys_alt, int64_t *vals,
                      int64_t *vals_alt, void *tmp, size_t *tmp_bytes, int64_t **sorted_out,

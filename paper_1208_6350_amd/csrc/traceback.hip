@@ -18,6 +18,8 @@
 // and stored lane-interleaved (coalesced).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "swx_internal.h"
 #include "swx_kernels.h"
 
@@ -533,38 +535,90 @@ __device__ __forceinline__ uint32_t row0_code(int64_t j, int32_t o, int32_t e) {
   return (j == 0) ? 0u : (1u | ((j == 1 || o <= e) ? 4u : 0u));
 }
 
-__global__ __launch_bounds__(64) void k_tb_wave(TbArgs a, const TbWaveJob *jobs, uint2 *dirw,
-                                                int32_t *bndbuf) {
+constexpr int kTbMaxStrips = 256;
+constexpr int kTbMaxWaves = 8;
+constexpr int64_t kTbSpinLimit = int64_t(1) << 26;
+
+__global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const TbWaveJob *jobs,
+                                                              uint2 *dirw, int32_t *bndbuf) {
   constexpr int RL = kTbRL;
   constexpr int64_t SH = 64 * RL;
-  extern __shared__ uint4 s_dyn[];             // profile: [(n+1)][64][RL] score bytes
+  extern __shared__ uint4 s_dyn[];             // per wave: profile [(n+1)][64][RL] score bytes
   __shared__ uint2 s_tile[64 * 64];
   __shared__ int8_t s_mat[32 * 32];
-  int8_t *s_prof = reinterpret_cast<int8_t *>(s_dyn);
-  const int lane = threadIdx.x;
+  __shared__ int32_t s_prog[kTbMaxStrips];     // columns of strip s's last row published
+  __shared__ int32_t s_done[kTbMaxStrips];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int NW = blockDim.x >> 6;
   const TbWaveJob jb = jobs[blockIdx.x];
   const int64_t p = jb.pair, m = jb.m, w = jb.w;
   const int n = a.n;
   const int32_t o = a.o, e = a.e;
-  for (int k = lane; k < n * n; k += 64) s_mat[k] = a.matrix[k];
+  const int64_t nstrips = (m + SH - 1) / SH;
+  for (int k = threadIdx.x; k < n * n; k += blockDim.x) s_mat[k] = a.matrix[k];
+  for (int k = threadIdx.x; k < nstrips && k < kTbMaxStrips; k += blockDim.x) {
+    s_prog[k] = 0;
+    s_done[k] = 0;
+  }
   const int8_t *q = a.qcat + a.qstart[p] + a.qbeg[p];
   const int8_t *r = a.rcat + a.rstart[p] + a.rbeg[p];
-  int32_t *bH = bndbuf + jb.bnd_off;
-  int32_t *bF = bH + (w + 1);
-  // virtual row 0: H(0,0) = 0, H(0,j) = -(o + (j-1)e), F(0,j) = -inf
-  for (int64_t j = lane; j <= w; j += 64) {
-    bH[j] = (j == 0) ? 0 : -(o + (int32_t)(j - 1) * e);
-    bF[j] = kNeg;
+  // hand-over rows: row 0 is the virtual top row H(0,0) = 0,
+  // H(0,j) = -(o + (j-1)e), F(0,j) = -inf; row s + 1 is strip s's last row
+  int32_t *bnd0 = bndbuf + jb.bnd_off;
+  for (int64_t j = threadIdx.x; j <= w; j += blockDim.x) {
+    bnd0[j] = (j == 0) ? 0 : -(o + (int32_t)(j - 1) * e);
+    bnd0[(w + 1) + j] = kNeg;
   }
   __threadfence_block();
   __syncthreads();
+  int8_t *s_prof = reinterpret_cast<int8_t *>(s_dyn) + (size_t)wave * (n + 1) * 64 * RL;
+  bool spin_fail = false;
 
-  const int64_t nstrips = (m + SH - 1) / SH;
-  int64_t dcur = jb.dir_off;
-  int64_t plo = 0, phi = w + 1;
-  for (int64_t s = 0; s < nstrips; ++s) {
-    int64_t clo, chi;
+  // choice codes of strip s start after those of strips 0..s-1
+  auto strip_base = [&](int64_t s) {
+    int64_t off = jb.dir_off;
+    for (int64_t k = 0; k < s; ++k) {
+      int64_t lo, hi;
+      tbw_window(k, jb.dlo, jb.bw, w, &lo, &hi);
+      off += ((hi - lo) + 63) * 64;
+    }
+    return off;
+  };
+
+  for (int64_t s = wave; s < nstrips; s += NW) {
+    int64_t clo, chi, plo = 0, phi = w + 1;
     tbw_window(s, jb.dlo, jb.bw, w, &clo, &chi);
+    if (s > 0) tbw_window(s - 1, jb.dlo, jb.bw, w, &plo, &phi);
+    const int32_t *inH = bnd0 + 2 * (w + 1) * s;    // the row above this strip
+    const int32_t *inF = inH + (w + 1);
+    int32_t *outH = bnd0 + 2 * (w + 1) * (s + 1);   // this strip's last row
+    int32_t *outF = outH + (w + 1);
+    const bool hand_over = (s + 1 < nstrips);
+    const int64_t dbase = strip_base(s);
+    auto publish = [&](int32_t ncols, bool fin) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if (lane == 0) {
+        __hip_atomic_store(&s_prog[s], ncols, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (fin) __hip_atomic_store(&s_done[s], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    };
+    int32_t avail = (s == 0) ? (int32_t)(w + 1) : 0;
+    auto wait_for = [&](int32_t need) {
+      if (s == 0) return;
+      int64_t spins = 0;
+      for (;;) {
+        const int32_t done = __hip_atomic_load(&s_done[s - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        avail = __hip_atomic_load(&s_prog[s - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (done || avail >= need) break;
+        if (++spins > kTbSpinLimit) { spin_fail = true; break; }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    };
+    auto rd = [](const int32_t *ptr) {   // past the L1: another wave wrote it
+      return __hip_atomic_load(ptr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
     // profile of this lane's rows (signed scores; padding rows score 0)
     {
       int32_t qv[RL];
@@ -586,28 +640,33 @@ __global__ __launch_bounds__(64) void k_tb_wave(TbArgs a, const TbWaveJob *jobs,
         *dst = make_uint4(wv[0], wv[1], wv[2], wv[3]);
       }
     }
-    __syncthreads();
+    __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
     int32_t H[RL], E[RL];
 #pragma unroll
     for (int k = 0; k < RL; ++k) { H[k] = kNeg; E[k] = kNeg; }
     int32_t hup_prev = kNeg;
-    if (lane == 0 && clo >= 1 && clo - 1 >= plo && clo - 1 < phi) hup_prev = bH[clo - 1];
+    if (clo >= 1 && clo - 1 >= plo && clo - 1 < phi) {
+      wait_for((int32_t)(clo - plo));
+      if (lane == 0 && clo - 1 < plo + avail) hup_prev = rd(&inH[clo - 1]);
+    }
     int32_t hout = kNeg, fout = kNeg;
     uint32_t sym = (uint32_t)n;
     int32_t symbuf = 0, hbuf = kNeg, fbuf = kNeg;
     int32_t obH = 0, obF = 0;
     const int64_t nsteps = (chi - clo) + 63;
-    const bool hand_over = (s + 1 < nstrips);
 #pragma unroll 1
     for (int64_t t = 0; t < nsteps; ++t) {
       const int tm = (int)(t & 63);
       if (tm == 0) {
+        const int64_t cend = (clo + t + 64 < phi) ? clo + t + 64 : phi;
+        if (cend > plo) wait_for((int32_t)(cend - plo));
         const int64_t c = clo + t + lane;
         const bool in = c < chi;
         symbuf = (in && c >= 1) ? (int32_t)(uint8_t)r[c - 1] : n;
-        const bool prev = in && c >= plo && c < phi;
-        hbuf = prev ? bH[c] : kNeg;
-        fbuf = prev ? bF[c] : kNeg;
+        const bool prev = in && c >= plo && c < phi && c < plo + avail;
+        hbuf = prev ? rd(&inH[c]) : kNeg;
+        fbuf = prev ? rd(&inF[c]) : kNeg;
       }
       const int32_t hup = tb_from_above(hout, __builtin_amdgcn_readlane(hbuf, tm));
       int32_t fup = tb_from_above(fout, __builtin_amdgcn_readlane(fbuf, tm));
@@ -641,7 +700,7 @@ __global__ __launch_bounds__(64) void k_tb_wave(TbArgs a, const TbWaveJob *jobs,
       hup_prev = hup;
       hout = H[RL - 1];
       fout = fup;
-      dirw[dcur + t * 64 + lane] = make_uint2(dw0, dw1);
+      dirw[dbase + t * 64 + lane] = make_uint2(dw0, dw1);
       if (hand_over && t >= 63) {
         const int jj = (int)((t - 63) & 63);
         const int32_t vh = __builtin_amdgcn_readlane(hout, 63);
@@ -649,17 +708,19 @@ __global__ __launch_bounds__(64) void k_tb_wave(TbArgs a, const TbWaveJob *jobs,
         obH = (lane == jj) ? vh : obH;
         obF = (lane == jj) ? vf : obF;
         if (jj == 63 || t == nsteps - 1) {
-          const int64_t col = clo + (t - 63) - jj + lane;
-          if (lane <= jj) { bH[col] = obH; bF[col] = obF; }
+          const int64_t cb = clo + (t - 63) - jj;
+          if (lane <= jj) { outH[cb + lane] = obH; outF[cb + lane] = obF; }
+          publish((int32_t)(cb + jj + 1 - clo), false);
         }
       }
     }
-    __threadfence_block();
-    __syncthreads();
-    dcur += nsteps * 64;
-    plo = clo;
-    phi = chi;
+    publish((int32_t)(chi - clo), true);
   }
+  __threadfence_block();
+  __syncthreads();
+  if (wave != 0) return;
+  if (spin_fail) a.err[p] = 1;
+  const int64_t dcur = strip_base(nstrips);
 
   // ---- walk back from (m, w) in state H (rule T3), uniform on the wave ------
   const int64_t cap_end = dcur;
@@ -692,12 +753,18 @@ __global__ __launch_bounds__(64) void k_tb_wave(TbArgs a, const TbWaveJob *jobs,
         tile_s = s;
         tile_hi = t;
         tile_lo = t >= 63 ? t - 63 : 0;
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
         for (int k = 0; k < 64; ++k) {
           const int64_t tt = tile_lo + k;
-          if (tt <= tile_hi) s_tile[k * 64 + lane] = dirw[wbase + tt * 64 + lane];
+          if (tt <= tile_hi) {   // past the L1: other waves of the workgroup wrote these codes
+            const unsigned long long v = __hip_atomic_load(
+                reinterpret_cast<unsigned long long *>(&dirw[wbase + tt * 64 + lane]), __ATOMIC_RELAXED,
+                __HIP_MEMORY_SCOPE_AGENT);
+            s_tile[k * 64 + lane] = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+          }
         }
-        __syncthreads();
+        __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+        __builtin_amdgcn_wave_barrier();
       }
       const uint2 dv = s_tile[(t - tile_lo) * 64 + L];
       c = ((rr < 8 ? dv.x : dv.y) >> (4 * (rr & 7))) & 0xFu;
@@ -737,11 +804,23 @@ __global__ __launch_bounds__(64) void k_tb_wave(TbArgs a, const TbWaveJob *jobs,
   a.cig_len[p] = nruns;
 }
 
-hipError_t tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, uint2 *dirw,
+int tb_wave_waves(int64_t m, int n) {
+  const int64_t nstrips = (m + 64 * kTbRL - 1) / (64 * kTbRL);
+  const int64_t per = (int64_t)(n + 1) * 64 * kTbRL;
+  const int64_t stat = 64 * 64 * 8 + 32 * 32 + kTbMaxStrips * 8;
+  const int64_t room = (65536 - stat) / per;
+  int64_t wv = std::min<int64_t>(std::min<int64_t>(nstrips, kTbMaxWaves), room);
+  return (int)(wv < 1 ? 1 : wv);
+}
+
+int tb_wave_max_strips() { return kTbMaxStrips; }
+
+hipError_t tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, int waves, uint2 *dirw,
                    int32_t *bnd, hipStream_t st) {
   if (njobs == 0) return hipSuccess;
-  const size_t lds = (size_t)(a.n + 1) * 64 * kTbRL;
-  hipLaunchKernelGGL(k_tb_wave, dim3((unsigned)njobs), dim3(64), lds, st, a, jobs, dirw, bnd);
+  if (waves < 1 || waves > kTbMaxWaves) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(a.n + 1) * 64 * kTbRL * waves;
+  hipLaunchKernelGGL(k_tb_wave, dim3((unsigned)njobs), dim3(64 * waves), lds, st, a, jobs, dirw, bnd);
   return hipGetLastError();
 }
 
