@@ -44,6 +44,8 @@ def parse():
                     help="offered load of the serving phase, requests per second")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner (default: tune on a 100k-pair sample first)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the timed steps, copy a device buffer of this many MiB once "
                          "(a plain copy kernel of known size for calibrating byte counters)")
@@ -212,6 +214,13 @@ def main():
         print(f"[bench] copy probe: {nbytes} bytes read and written", flush=True, file=sys.stderr)
         del src, dst
     ctx = swx.Context(0)
+    tuning = None
+    if not args.no_autotune:
+        t = time.perf_counter()
+        tuning, _ = ctx.autotune(b.matrix, b.gap_open, b.gap_extend, dq, dqo, dr, dro, dpq, dpr,
+                                 max_pairs=100_000, in_mem=swx.SWX_MEM_DEVICE)
+        print(f"[bench] autotuned in {time.perf_counter() - t:.1f}s: {tuning}", flush=True,
+              file=sys.stderr)
 
     def step():
         st, used = swx.swx_align_batch(ctx.handle, b.matrix, b.gap_open, b.gap_extend, dq, dqo,
@@ -281,6 +290,7 @@ def main():
                      "kernel": "k_inter_fill (forward fill, packed 16-bit lanes)",
                      "fill_ms": round(fill_avg, 3), "ops_per_cell": OPS_PER_CELL},
         "stages_ms": stage_avg,
+        "tuning": tuning,
         "per_pair": per_pair,
     }
     if not args.no_serve:

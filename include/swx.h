@@ -181,6 +181,18 @@ typedef struct {
 int swx_get_tuning(const swx_ctx *ctx, swx_tuning *out);
 int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t);
 
+/* Autotuner: runs the first min(npairs, max_pairs) pairs of b under candidate
+ * settings of each knob in turn (fill_rows, then long_cells, then intra_jobs;
+ * each timed as the best of two runs after a warm-up, a change kept only if
+ * at least 3% faster), installs the fastest in ctx and returns it in *out.
+ * cache_path (may be NULL) names a text file of one JSON object per line,
+ * keyed by the device architecture and a coarse workload signature (n, gaps,
+ * log2 of the sample size and of its cells); a matching entry is installed
+ * without timing (*from_cache = 1), a new result is appended.  Errors: those
+ * of swx_align_batch; SWX_EINVAL for max_pairs < 1 or null pointers. */
+int swx_autotune(swx_ctx *ctx, const swx_batch *b, int64_t max_pairs, const char *cache_path,
+                 swx_tuning *out, int32_t *from_cache);
+
 /* ---- serving ------------------------------------------------------------------
  * A request loop for a stream of alignment requests under one scoring scheme
  * (the paper's use in read mappers and search servers: many independent
@@ -190,8 +202,8 @@ int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t);
  *   - Admission: every request carries an estimate of the device memory its
  *     work takes (sequences, boundary rows, max array, profile and traceback
  *     band); requests leave the queue only while the estimates of the work in
- *     flight stay within mem_budget (a request above the whole budget runs
- *     alone).
+ *     flight stay within mem_budget, long requests within 3/4 of it so that
+ *     short ones always find room (a request above its share runs alone).
  *   - Continuous batching: each of `workers` worker threads owns a context
  *     (own HIP stream and device pool); a free worker takes every queued
  *     request of one size class that fits (up to max_batch) as one batch, so

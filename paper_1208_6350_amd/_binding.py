@@ -108,6 +108,9 @@ _SIGS = {
     "swx_last_stage_ms": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                          ctypes.c_int]),
     "swx_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxTuning)]),
+    "swx_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxBatch), ctypes.c_int64,
+                                    ctypes.c_char_p, ctypes.POINTER(SwxTuning),
+                                    ctypes.POINTER(ctypes.c_int32)]),
     "swx_server_create": (ctypes.c_int, [ctypes.POINTER(SwxServerCfg),
                                          ctypes.POINTER(ctypes.c_void_p)]),
     "swx_server_register_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
@@ -325,6 +328,25 @@ class Context:
 
     def stage_ms(self):
         return swx_last_stage_ms(self.handle)
+
+    def autotune(self, matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r, max_pairs=65536,
+                 cache_path=None, in_mem=SWX_MEM_HOST):
+        """Times the launch configurations on a sample of the batch (numpy
+        arrays on the host, or torch tensors on the device with in_mem =
+        SWX_MEM_DEVICE) and installs the fastest.  Returns (tuning, from_cache)."""
+        if in_mem == SWX_MEM_HOST:
+            qcat = np.ascontiguousarray(qcat, dtype=np.int8)
+            rcat = np.ascontiguousarray(rcat, dtype=np.int8)
+            qoff, roff, pair_q, pair_r = (np.ascontiguousarray(x, dtype=np.int64)
+                                          for x in (qoff, roff, pair_q, pair_r))
+        b, _m = _make_batch(matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r, SWX_ALL, -1,
+                            in_mem)
+        t = SwxTuning()
+        fc = ctypes.c_int32()
+        path = cache_path.encode() if cache_path else None
+        _check(lib().swx_autotune(self.handle, ctypes.byref(b), int(max_pairs), path,
+                                  ctypes.byref(t), ctypes.byref(fc)), "swx_autotune")
+        return {k: getattr(t, k) for k, _ in SwxTuning._fields_ if k != "reserved"}, bool(fc.value)
 
     def tuning(self) -> dict:
         return swx_get_tuning(self.handle)

@@ -884,6 +884,7 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
 
 int internal_fail(int code, const char *msg) { return fail(code, msg); }
 hipStream_t internal_stream(swx_ctx *ctx) { return ctx->stream; }
+int internal_device(const swx_ctx *ctx) { return ctx->device; }
 
 }  // namespace swx
 

@@ -10,4 +10,6 @@ namespace swx {
 int internal_fail(int code, const char *msg);
 // the context's stream (work queued on it runs before the context's next call)
 hipStream_t internal_stream(swx_ctx *ctx);
+// the context's HIP device ordinal
+int internal_device(const swx_ctx *ctx);
 }  // namespace swx

@@ -97,6 +97,7 @@ struct swx_server {
   std::deque<swx_completion> done;
   std::vector<RegQuery> queries;
   int64_t inflight_bytes = 0;
+  int64_t inflight_long = 0;         // part of inflight_bytes held by long requests
   uint64_t next_ticket = 1;
   bool stop = false;
   swx_server_stats stats{};
@@ -115,10 +116,12 @@ int64_t footprint(int64_t qlen, int64_t rlen, int32_t n) {
   return 64 * (qlen + rlen) + (int64_t)(n + 1) * qlen + qlen * band / 2 + 4096;
 }
 
+// Long requests may hold at most 3/4 of the budget, so short ones always find
+// room; a request larger than its share still runs once nothing else does.
 bool admissible(const swx_server *s, const Req &r, int64_t extra) {
-  // a request larger than the whole budget still runs once nothing else does
-  return s->inflight_bytes + extra + r.footprint <= s->cfg.mem_budget ||
-         (s->inflight_bytes == 0 && extra == 0);
+  if (s->inflight_bytes == 0 && extra == 0) return true;
+  if (s->inflight_bytes + extra + r.footprint > s->cfg.mem_budget) return false;
+  return r.cls == 0 || s->inflight_long + extra + r.footprint <= s->cfg.mem_budget / 4 * 3;
 }
 
 void run_batch(swx_server *s, swx_ctx *ctx, std::vector<Req> &batch, Staging &stg) {
@@ -230,6 +233,7 @@ void run_batch(swx_server *s, swx_ctx *ctx, std::vector<Req> &batch, Staging &st
   for (const Req &r : batch) fp += r.footprint;
   std::lock_guard<std::mutex> g(s->mu);
   s->inflight_bytes -= fp;
+  if (nb > 0 && batch[0].cls == 1) s->inflight_long -= fp;
   s->stats.batches += 1;
   s->stats.completed += nb;
   if (nb > s->stats.max_batch_seen) s->stats.max_batch_seen = nb;
@@ -272,6 +276,7 @@ void worker_main(swx_server *s, int w) {
         q.pop_front();
       }
       s->inflight_bytes += fp;
+      if (c == 1) s->inflight_long += fp;
       s->stats.admitted += (int64_t)batch.size();
       if (s->inflight_bytes > s->stats.peak_inflight_bytes)
         s->stats.peak_inflight_bytes = s->inflight_bytes;

@@ -127,3 +127,25 @@ def test_config5_long_requests(ctx):
     b = pool.subset(sel)
     _say(f"[long] config5 long requests: {b.npairs}")
     assert_parity(ctx, b)
+
+
+def test_autotune_keeps_results_and_caches(ctx, tmp_path):
+    """The autotuner only changes speed: results after tuning equal those
+    before, and a second call with the same kind of work reads the cache."""
+    b = W.random_pairs(771, 300, (1, 500), (0, 2500))
+    recs0, cig0 = ctx.align_batch(b.matrix, b.gap_open, b.gap_extend, b.qcat, b.qoff, b.rcat,
+                                  b.roff, b.pair_q, b.pair_r)
+    cache = str(tmp_path / "tune.jsonl")
+    t1, fc1 = ctx.autotune(b.matrix, b.gap_open, b.gap_extend, b.qcat, b.qoff, b.rcat, b.roff,
+                           b.pair_q, b.pair_r, max_pairs=200, cache_path=cache)
+    _say(f"[tune] {t1}")
+    assert not fc1 and t1["fill_rows"] in (16, 32) and t1 == ctx.tuning()
+    recs1, cig1 = ctx.align_batch(b.matrix, b.gap_open, b.gap_extend, b.qcat, b.qoff, b.rcat,
+                                  b.roff, b.pair_q, b.pair_r)
+    for f in FIELDS + ["cigar_off", "cigar_len"]:   # lane_bits is diagnostic only
+        assert np.array_equal(recs0[f], recs1[f]), f
+    assert np.array_equal(cig0, cig1)
+    ctx.set_tuning(fill_rows=16 if t1["fill_rows"] == 32 else 32)
+    t2, fc2 = ctx.autotune(b.matrix, b.gap_open, b.gap_extend, b.qcat, b.qoff, b.rcat, b.roff,
+                           b.pair_q, b.pair_r, max_pairs=200, cache_path=cache)
+    assert fc2 and t2 == t1 and ctx.tuning() == t1
