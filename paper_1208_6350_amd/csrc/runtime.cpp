@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -103,6 +104,11 @@ struct swx_ctx {
   int64_t long_rlen = int64_t(1) << 16;    // ... or a reference longer than this
   int64_t intra_jobs = 2048;               // target column chunks over all long pairs
   int32_t fill_rows = 32;                  // strip height of the batched fill
+  // side streams (default priority) for independent kernels of one stage
+  static constexpr int kAux = 4;
+  hipStream_t aux[kAux] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kAux] = {};
 };
 
 struct swx_profile {
@@ -316,6 +322,39 @@ struct DeviceBatch {
   int64_t qcat_len, rcat_len, nq, nr, npairs;
 };
 
+// Runs independent launches side by side: each goes to a side stream that
+// first waits for everything queued on the main stream, and the main stream
+// then waits for all of them.  Launches come with a cost estimate and are
+// placed longest first on the least loaded of two side streams (the device
+// gives a process few hardware queues; more streams would share them).
+struct SideLaunch {
+  double cost;
+  std::function<hipError_t(hipStream_t)> fn;
+};
+
+static int run_side_by_side(swx_ctx *ctx, std::vector<SideLaunch> &ls) {
+  if (ls.empty()) return SWX_OK;
+  if (ls.size() == 1) {
+    HIP_TRY(ls[0].fn(ctx->stream));
+    return SWX_OK;
+  }
+  std::stable_sort(ls.begin(), ls.end(), [](const SideLaunch &x, const SideLaunch &y) { return x.cost > y.cost; });
+  constexpr int na = 2;
+  HIP_TRY(hipEventRecord(ctx->fork_ev, ctx->stream));
+  for (int k = 0; k < na; ++k) HIP_TRY(hipStreamWaitEvent(ctx->aux[k], ctx->fork_ev, 0));
+  double load[na] = {0, 0};
+  for (auto &l : ls) {
+    const int k = load[0] <= load[1] ? 0 : 1;
+    load[k] += l.cost;
+    HIP_TRY(l.fn(ctx->aux[k]));
+  }
+  for (int k = 0; k < na; ++k) {
+    HIP_TRY(hipEventRecord(ctx->join_ev[k], ctx->aux[k]));
+    HIP_TRY(hipStreamWaitEvent(ctx->stream, ctx->join_ev[k], 0));
+  }
+  return SWX_OK;
+}
+
 static int gather_info(swx_ctx *ctx, int64_t n, const int64_t *d_ids, const int32_t *qlen,
                        const int64_t *rlen, const int32_t *score, const int32_t *qend,
                        const int64_t *rend, const int32_t *band, std::vector<int64_t> &info);
@@ -360,8 +399,11 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
   if (!cscr) return fail(SWX_ENOMEM, "device pool exhausted (CIGAR scratch)");
   ta.cig = cscr;
   ta.cig_off = coff;
+  // plan every class first (host reads of sizes), then launch the classes'
+  // kernels side by side: the small classes would not fill the GPU alone
+  std::vector<SideLaunch> launches;
   int64_t pos = hc[0];
-  for (int c = 1; c <= 4; ++c) {
+  for (int c = 1; c <= 3; ++c) {
     const int64_t nc = hc[c];
     if (nc == 0) continue;
     const int32_t bw = 8 << (c - 1);
@@ -375,9 +417,10 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
     HIP_TRY(tb_offsets(nt, tasks, doff, st));
     int64_t words = 0;
     if ((rc = read_i64(ctx, doff + nt, &words))) return rc;
-    ta.dir = A.get<uint32_t>(words);
-    if (!ta.dir) return fail(SWX_ENOMEM, "device pool exhausted (choice codes)");
-    HIP_TRY(tb_band(ta, tasks, nt, sorted, bw, st));
+    TbArgs tc = ta;
+    tc.dir = A.get<uint32_t>(words);
+    if (!tc.dir) return fail(SWX_ENOMEM, "device pool exhausted (choice codes)");
+    launches.push_back({(double)words * 8, [=](hipStream_t s_) { return tb_band(tc, tasks, nt, sorted, bw, s_); }});
     pos += nc;
   }
   if (hc[5] > 0) {   // bands wider than 64 diagonals: row strips, columns swept
@@ -397,10 +440,11 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
     int64_t tot[2];
     if ((rc = read_i64(ctx, doff + nt, &tot[0]))) return rc;
     if ((rc = read_i64(ctx, boff + nt, &tot[1]))) return rc;
-    ta.dir = A.get<uint32_t>(tot[0]);
+    TbArgs tc = ta;
+    tc.dir = A.get<uint32_t>(tot[0]);
     int32_t *bnd = A.get<int32_t>(tot[1]);
-    if (!ta.dir || !bnd) return fail(SWX_ENOMEM, "device pool exhausted (wide band)");
-    HIP_TRY(tb_strip(ta, tasks, nt, sorted, bnd, st));
+    if (!tc.dir || !bnd) return fail(SWX_ENOMEM, "device pool exhausted (wide band)");
+    launches.push_back({(double)tot[0] * 8, [=](hipStream_t s_) { return tb_strip(tc, tasks, nt, sorted, bnd, s_); }});
     pos += nc;
   }
   if (hc[6] > 0) {   // long pairs with wide bands: one pair per wave
@@ -444,15 +488,19 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
     int32_t *bnd = A.get<int32_t>(std::max<int64_t>(bwords, 1));
     if (!dj || !dirw || !bnd) return fail(SWX_ENOMEM, "device pool exhausted (wave traceback)");
     HIP_TRY(hipMemcpyAsync(dj, sorted_jobs.data(), sizeof(TbWaveJob) * nc, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));   // the host job table must outlive the copy
     for (int64_t k0 = 0; k0 < nc;) {
       int64_t k1 = k0;
       while (k1 < nc && waves[order[k1]] == waves[order[k0]]) ++k1;
-      HIP_TRY(tb_wave(ta, dj + k0, k1 - k0, waves[order[k0]], dirw, bnd, st));
+      const int wv = waves[order[k0]];
+      const TbWaveJob *jp = dj + k0;
+      const int64_t cnt = k1 - k0;
+      launches.push_back({(double)dwords * 16, [=](hipStream_t s_) { return tb_wave(ta, jp, cnt, wv, dirw, bnd, s_); }});
       k0 = k1;
     }
-    HIP_TRY(hipStreamSynchronize(st));   // the host job table must outlive the copy
     pos += nc;
   }
+  if ((rc = run_side_by_side(ctx, launches))) return rc;
   // final CIGAR offsets and compaction into the caller's arena
   int64_t *len64 = A.get<int64_t>(np + 1);
   if (!len64) return fail(SWX_ENOMEM, "device pool exhausted");
@@ -955,6 +1003,14 @@ int swx_ctx_create(int device, swx_ctx **out) {
       return fail(SWX_EDEVICE, "could not create events");
     }
   }
+  bool ok = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess;
+  for (int k = 0; k < swx_ctx::kAux && ok; ++k)
+    ok = hipStreamCreate(&c->aux[k]) == hipSuccess &&
+         hipEventCreateWithFlags(&c->join_ev[k], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    delete c;
+    return fail(SWX_EDEVICE, "could not create side streams");
+  }
   *out = c;
   return SWX_OK;
 }
@@ -968,6 +1024,14 @@ int swx_ctx_destroy(swx_ctx *ctx) {
     ctx->arena.release();
     for (auto &e : ctx->ev)
       if (e) (void)hipEventDestroy(e);
+    for (int k = 0; k < swx_ctx::kAux; ++k) {
+      if (ctx->aux[k]) {
+        (void)hipStreamSynchronize(ctx->aux[k]);
+        (void)hipStreamDestroy(ctx->aux[k]);
+      }
+      if (ctx->join_ev[k]) (void)hipEventDestroy(ctx->join_ev[k]);
+    }
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
     (void)hipStreamDestroy(ctx->stream);
   }
   delete ctx;

@@ -44,8 +44,9 @@ __global__ void k_tb_classify(TbArgs a, int64_t npairs, uint8_t *cls, uint64_t *
       m = a.qend[p] - a.qbeg[p] + 1;
       w = a.rend[p] - a.rbeg[p] + 1;
       safe_band(m, w, a.score[p], a.smax, a.o, a.e, &dlo, &bw);
-      c = bw <= 8 ? 1 : bw <= 16 ? 2 : bw <= 32 ? 3 : bw <= 64 ? 4
-          : (m * bw > kWaveTbCells ? 6 : 5);
+      // bands wider than 32 go to the strip kernel (a 64-wide band in one
+      // lane's registers spills and leaves too few waves)
+      c = bw <= 8 ? 1 : bw <= 16 ? 2 : bw <= 32 ? 3 : (m * bw > kWaveTbCells ? 6 : 5);
     } else {
       a.err[p] = 1;
     }
@@ -88,7 +89,15 @@ template <int BW, bool LUT4>
 __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, int64_t ntasks,
                                                  const int64_t *sorted) {
   __shared__ int8_t s_mat[32 * 32];
+  __shared__ uint32_t s_lut4[32];   // LUT4: scores of query symbol x against reference 0..3
+  constexpr int kRB = BW <= 16 ? 16 : (BW <= 32 ? 8 : 4);
+  __shared__ uint32_t s_walk[4 * kRB * (BW / 8) * 64];   // walk cache: per wave, row, dword, lane
   for (int k = threadIdx.x; k < a.n * a.n; k += blockDim.x) s_mat[k] = a.matrix[k];
+  if (LUT4 && (int)threadIdx.x < a.n) {
+    uint32_t l = 0;
+    for (int b = 0; b < a.n; ++b) l |= (uint32_t)(uint8_t)a.matrix[threadIdx.x * a.n + b] << (8 * b);
+    s_lut4[threadIdx.x] = l;
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int64_t tid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -155,57 +164,72 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
   }
   int32_t hend = kNeg;
   const int64_t kend = w - m - dlo;
-  for (int64_t i = 1; i <= tk.rows; ++i) {
-    int32_t lut = 0, qn = 0;
-    if (live && i <= m) {
-      const int32_t qs = q[i - 1];
-      if (LUT4) {
-        uint32_t l = 0;
-        for (int b = 0; b < a.n; ++b) l |= (uint32_t)(uint8_t)s_mat[qs * a.n + b] << (8 * b);
-        lut = (int32_t)l;
-      } else {
-        qn = qs * a.n;
+  // Rows go in blocks of UB: the query symbols and the window's next
+  // reference bytes of block b+1 are requested while block b is computed.
+  constexpr int UB = BW <= 16 ? 8 : (BW <= 32 ? 4 : 2);
+  auto load_block = [&](int64_t i0, uint32_t (&qo)[UB], uint32_t (&no)[UB]) {
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int64_t i = i0 + u;
+      qo[u] = (live && i <= m) ? (uint32_t)(uint8_t)q[i - 1] : 0xFFu;
+      no[u] = ref_byte(i + 1 + dlo + 4 * NW - 1);
+    }
+  };
+  uint32_t qb[UB], nbb[UB];
+  load_block(1, qb, nbb);
+  for (int64_t i0 = 1; i0 <= tk.rows; i0 += UB) {
+    uint32_t qn[UB], nn[UB];
+    load_block(i0 + UB, qn, nn);
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int64_t i = i0 + u;
+      if (i > tk.rows) break;
+      int32_t lut = 0, qrow = 0;
+      if (qb[u] != 0xFFu) {
+        if (LUT4) lut = (int32_t)s_lut4[qb[u]];
+        else qrow = (int32_t)qb[u] * a.n;
       }
+      uint32_t dw[ND];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) dw[d] = 0;
+      int32_t ev = kNeg, hleft = kNeg;
+#pragma unroll
+      for (int k = 0; k < BW; ++k) {
+        const uint32_t sym = __builtin_amdgcn_ubfe(win[k >> 2], 8 * (k & 3), 8);
+        const int32_t sc = LUT4 ? __builtin_amdgcn_sbfe(lut, sym, 8) : (int32_t)s_mat[qrow + sym];
+        const int32_t hup = (k + 1 < BW) ? H[k + 1] : kNeg;
+        const int32_t fup = (k + 1 < BW) ? F[k + 1] : kNeg;
+        const int32_t diag = H[k] + sc;
+        const int32_t fo = hup - o, fx = fup - e;
+        const int32_t fij = fo > fx ? fo : fx;
+        const int32_t eo = hleft - o, ex = ev - e;
+        const int32_t eij = eo > ex ? eo : ex;
+        int32_t h = diag > eij ? diag : eij;
+        h = h > fij ? h : fij;
+        uint32_t c = (h == diag) ? 0u : (h == eij ? 1u : 2u);
+        c |= (eo >= ex) ? 4u : 0u;
+        c |= (fo >= fx) ? 8u : 0u;
+        dw[k >> 3] |= c << (4 * (k & 7));
+        H[k] = h;
+        F[k] = fij;
+        ev = eij;
+        hleft = h;
+      }
+      uint32_t *drow = dir + (int64_t)i * ND * 64;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) drow[(int64_t)d * 64 + lane] = dw[d];
+      if (live && i == m) {
+#pragma unroll
+        for (int k = 0; k < BW; ++k)
+          if (k == kend) hend = H[k];
+      }
+      // slide the reference window one column to the right
+#pragma unroll
+      for (int d = 0; d < NW - 1; ++d) win[d] = __builtin_amdgcn_alignbyte(win[d + 1], win[d], 1);
+      win[NW - 1] = (win[NW - 1] >> 8) | (nbb[u] << 24);
     }
-    uint32_t dw[ND];
 #pragma unroll
-    for (int d = 0; d < ND; ++d) dw[d] = 0;
-    int32_t ev = kNeg, hleft = kNeg;
-#pragma unroll
-    for (int k = 0; k < BW; ++k) {
-      const uint32_t sym = __builtin_amdgcn_ubfe(win[k >> 2], 8 * (k & 3), 8);
-      const int32_t sc = LUT4 ? __builtin_amdgcn_sbfe(lut, sym, 8) : (int32_t)s_mat[qn + sym];
-      const int32_t hup = (k + 1 < BW) ? H[k + 1] : kNeg;
-      const int32_t fup = (k + 1 < BW) ? F[k + 1] : kNeg;
-      const int32_t diag = H[k] + sc;
-      const int32_t fo = hup - o, fx = fup - e;
-      const int32_t fij = fo > fx ? fo : fx;
-      const int32_t eo = hleft - o, ex = ev - e;
-      const int32_t eij = eo > ex ? eo : ex;
-      int32_t h = diag > eij ? diag : eij;
-      h = h > fij ? h : fij;
-      uint32_t c = (h == diag) ? 0u : (h == eij ? 1u : 2u);
-      c |= (eo >= ex) ? 4u : 0u;
-      c |= (fo >= fx) ? 8u : 0u;
-      dw[k >> 3] |= c << (4 * (k & 7));
-      H[k] = h;
-      F[k] = fij;
-      ev = eij;
-      hleft = h;
-    }
-    uint32_t *drow = dir + (int64_t)i * ND * 64;
-#pragma unroll
-    for (int d = 0; d < ND; ++d) drow[(int64_t)d * 64 + lane] = dw[d];
-    if (live && i == m) {
-#pragma unroll
-      for (int k = 0; k < BW; ++k)
-        if (k == kend) hend = H[k];
-    }
-    // slide the reference window one column to the right
-    const uint32_t nb = ref_byte(i + 1 + dlo + 4 * NW - 1);
-#pragma unroll
-    for (int d = 0; d < NW - 1; ++d) win[d] = __builtin_amdgcn_alignbyte(win[d + 1], win[d], 1);
-    win[NW - 1] = (win[NW - 1] >> 8) | (nb << 24);
+    for (int u = 0; u < UB; ++u) { qb[u] = qn[u]; nbb[u] = nn[u]; }
   }
   if (!live) return;
   if (s1 <= 0) { a.cig_len[p] = 0; return; }
@@ -217,10 +241,28 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
   int state = 0;
   uint32_t cur_op = 0xFF, cur_len = 0;
   int64_t guard = 2 * (m + w) + 4;
+  // the walk only moves up (and left): RB rows of choice codes at a time are
+  // pulled into this lane's LDS slots with independent loads, instead of one
+  // dependent global load per step
+  constexpr int RB = BW <= 16 ? 16 : (BW <= 32 ? 8 : 4);
+  const int wv = (int)(threadIdx.x >> 6);
+  int64_t blk_hi = -1;   // rows (blk_hi - RB, blk_hi] are cached
   while ((i > 0 || j > 0) && guard-- > 0) {
     const int64_t k = j - i - dlo;
     if (k < 0 || k >= BW) { a.err[p] = 1; break; }
-    const uint32_t c = (dir[((int64_t)i * ND + (k >> 3)) * 64 + lane] >> (4 * (k & 7))) & 0xFu;
+    if (i > blk_hi || i <= blk_hi - RB) {
+      blk_hi = i;
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) {
+        const int64_t row = i - rr;
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+          s_walk[((wv * RB + rr) * ND + d) * 64 + lane] =
+              row >= 0 ? dir[((int64_t)row * ND + d) * 64 + lane] : 0u;
+      }
+    }
+    const uint32_t c =
+        (s_walk[((wv * RB + (int)(blk_hi - i)) * ND + (int)(k >> 3)) * 64 + lane] >> (4 * (k & 7))) & 0xFu;
     uint32_t op = 0xFF;
     if (state == 0) {
       const uint32_t src = c & 3u;
@@ -297,7 +339,6 @@ hipError_t tb_band(const TbArgs &a, const TbTask *tasks, int64_t ntasks, const i
     case 8: return launch_band<8>(a, tasks, ntasks, sorted, lut4, st);
     case 16: return launch_band<16>(a, tasks, ntasks, sorted, lut4, st);
     case 32: return launch_band<32>(a, tasks, ntasks, sorted, lut4, st);
-    case 64: return launch_band<64>(a, tasks, ntasks, sorted, lut4, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -356,7 +397,9 @@ template <bool LUT4>
 __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks, int64_t ntasks,
                                                   const int64_t *sorted, int32_t *bndbuf) {
   constexpr int R = kStripR;
+  constexpr int kCB = 16;   // walk cache: columns per lane
   __shared__ int8_t s_mat[32 * 32];
+  __shared__ uint32_t s_walk[4 * kCB * 2 * 64];
   for (int k = threadIdx.x; k < a.n * a.n; k += blockDim.x) s_mat[k] = a.matrix[k];
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -424,12 +467,20 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
 #pragma unroll
     for (int k = 0; k < R; ++k) { H[k] = kNeg; E[k] = kNeg; }
     int32_t hdtop = (clo >= 1 && clo - 1 >= plo && clo - 1 < phi) ? bH[(clo - 1) * 64 + lane] : kNeg;
-    for (int64_t j = clo; j < chi; ++j) {
+    // the row above, the reference symbol: requested one column ahead
+    auto fetch = [&](int64_t j, int32_t &h, int32_t &f, uint32_t &sy) {
       const bool inprev = j >= plo && j < phi;
-      const int32_t hup0 = inprev ? bH[j * 64 + lane] : kNeg;
-      const int32_t fup0 = inprev ? bF[j * 64 + lane] : kNeg;
-      uint32_t sym = 0;
-      if (live && j >= 1 && j <= w) sym = (uint32_t)(uint8_t)r[j - 1];
+      h = inprev ? bH[j * 64 + lane] : kNeg;
+      f = inprev ? bF[j * 64 + lane] : kNeg;
+      sy = (live && j >= 1 && j <= w) ? (uint32_t)(uint8_t)r[j - 1] : 0u;
+    };
+    int32_t n_h = kNeg, n_f = kNeg;
+    uint32_t n_sy = 0;
+    if (clo < chi) fetch(clo, n_h, n_f, n_sy);
+    for (int64_t j = clo; j < chi; ++j) {
+      const int32_t hup0 = n_h, fup0 = n_f;
+      const uint32_t sym = n_sy;
+      if (j + 1 < chi) fetch(j + 1, n_h, n_f, n_sy);
       const uint32_t sym8 = LUT4 ? sym * 8u : sym;
       int32_t hdiag = hdtop;
       hdtop = hup0;
@@ -474,6 +525,8 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
   int state = 0;
   uint32_t cur_op = 0xFF, cur_len = 0;
   int64_t guard = 2 * (m + w) + 4;
+  const int wv = (int)(threadIdx.x >> 6);
+  int64_t cache_s = -1, cache_hi = -1;
   while ((i > 0 || j > 0) && guard-- > 0) {
     uint32_t c;
     if (i == 0) {
@@ -482,7 +535,21 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
       const int64_t s = (i - 1) / R, k = (i - 1) % R;
       const int64_t jc = j - (s * R + 1 + tk.dlo);
       if (jc < 0 || jc >= W || j > tk.wmax) { a.err[p] = 1; break; }
-      const uint32_t dwv = dir[(W + s * W + jc) * 2 * 64 + (k >> 3) * 64 + lane];
+      // the walk only moves up and left: CB columns of this strip's codes at a
+      // time are pulled into the lane's LDS slots with independent loads
+      if (s != cache_s || jc > cache_hi || jc <= cache_hi - kCB) {
+        cache_s = s;
+        cache_hi = jc;
+#pragma unroll
+        for (int cc = 0; cc < kCB; ++cc) {
+          const int64_t jj = jc - cc;
+#pragma unroll
+          for (int d = 0; d < 2; ++d)
+            s_walk[((wv * kCB + cc) * 2 + d) * 64 + lane] =
+                jj >= 0 ? dir[(W + s * W + jj) * 2 * 64 + d * 64 + lane] : 0u;
+        }
+      }
+      const uint32_t dwv = s_walk[((wv * kCB + (int)(cache_hi - jc)) * 2 + (int)(k >> 3)) * 64 + lane];
       c = (dwv >> (4 * (k & 7))) & 0xFu;
     }
     uint32_t op = 0xFF;
