@@ -169,7 +169,9 @@ int64_t swx_cigar_bound(const swx_batch *b);
  *                          2048.  long_cells >= -1, long_rlen >= 0.
  *   intra_jobs             target number of column chunks over all long pairs
  *                          of one call, >= 1.
- *   fill_rows              query rows per strip of the batched fill: 16 or 32.
+ *   fill_rows              query rows per strip of the batched fill: 16, 24 or
+ *                          32 (24 applies to alphabets of at most 4 symbols;
+ *                          others use 32 instead).
  * Errors: SWX_EINVAL for null pointers or values out of range (ctx unchanged). */
 typedef struct {
   int64_t long_cells;

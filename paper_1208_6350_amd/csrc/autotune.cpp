@@ -172,7 +172,8 @@ extern "C" int swx_autotune(swx_ctx *ctx, const swx_batch *b, int64_t max_pairs,
     }
     return SWX_OK;
   };
-  if ((rc = try_knob([](swx_tuning &t, int64_t v) { t.fill_rows = (int32_t)v; }, {16, 32}))) return rc;
+  if ((rc = try_knob([](swx_tuning &t, int64_t v) { t.fill_rows = (int32_t)v; }, {16, 24, 32})))
+    return rc;
   if ((rc = try_knob([](swx_tuning &t, int64_t v) { t.long_cells = v; },
                      {-1, int64_t(1) << 62, 0, int64_t(1) << 20, int64_t(1) << 24})))
     return rc;

@@ -73,9 +73,12 @@ __device__ __forceinline__ uint32_t word_of(const uint4 &v, int k) {
   return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
 }
 
-// Register budget: 256 VGPRs per lane, two waves per SIMD.
+// Register budget: 256 VGPRs per lane (two waves per SIMD) for 32-row strips,
+// 168 (three waves) for shorter strips.
+template <int R> constexpr int fill_waves() { return R >= 32 ? 2 : 3; }
+
 template <class V, int R, uint32_t MODE, bool CLAMP, bool REV>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_inter_fill(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fill_waves<R>()))) void k_inter_fill(
     InterArgs a) {
   using T = VT<V>;
   constexpr int NH = T::kHalves;
@@ -477,9 +480,11 @@ hipError_t inter_fill(const InterArgs &a, int lane_bits, int R, hipStream_t st) 
   const bool qsel = (a.prof == nullptr);
   if (lane_bits == 16) {
     if (R == 32) return qsel ? launch_fill<u16x2, 32, kQSel>(a, st) : launch_fill<u16x2, 32, kQGen>(a, st);
+    if (R == 24 && qsel) return launch_fill<u16x2, 24, kQSel>(a, st);
     if (R == 16) return qsel ? launch_fill<u16x2, 16, kQSel>(a, st) : launch_fill<u16x2, 16, kQGen>(a, st);
   } else {
     if (R == 32) return qsel ? launch_fill<uint32_t, 32, kQSel>(a, st) : launch_fill<uint32_t, 32, kQGen>(a, st);
+    if (R == 24 && qsel) return launch_fill<uint32_t, 24, kQSel>(a, st);
     if (R == 16) return qsel ? launch_fill<uint32_t, 16, kQSel>(a, st) : launch_fill<uint32_t, 16, kQGen>(a, st);
   }
   return hipErrorInvalidValue;

@@ -814,7 +814,8 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
   if ((rc = split_pairs(ctx, np, qlen, rlen, hstats[1], lp))) return rc;
 
   // forward fill, 16-bit lanes (events 1 and 2 bracket the fill kernels)
-  const int R = ctx->fill_rows;
+  // 24-row strips exist for the 4-symbol selector profile only
+  const int R = (ctx->fill_rows == 24 && !sc.qsel) ? 32 : ctx->fill_rows;
   Plan p16, p32;
   if ((rc = plan_pass(ctx, sc, lp.d_short, lp.nshort, qlen, rlen, nullptr, 16, R, p16))) return rc;
   if ((rc = run_fill(ctx, p16, sc, fview, false, nullptr, fout, score_bound, 1))) return rc;
@@ -973,7 +974,7 @@ int swx_get_tuning(const swx_ctx *ctx, swx_tuning *out) {
 int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t) {
   if (!ctx || !t) return fail(SWX_EINVAL, "null argument");
   if (t->long_cells < -1 || t->long_rlen < 0 || t->intra_jobs < 1 || t->reserved != 0 ||
-      (t->fill_rows != 16 && t->fill_rows != 32))
+      (t->fill_rows != 16 && t->fill_rows != 24 && t->fill_rows != 32))
     return fail(SWX_EINVAL, "tuning value out of range");
   std::lock_guard<std::mutex> g(ctx->mu);
   ctx->long_cells = t->long_cells;

@@ -21,10 +21,12 @@ def _say(msg):
     sys.stdout.flush()
 
 
-# Every parity test runs three times: with the default routing, with every
-# pair forced onto the batched (one pair per lane half) path, and with every
-# pair forced onto the intra-sequence (one pair per wave) path.
+# Every parity test runs with the default routing, with every pair forced
+# onto the batched (one pair per lane half) path with 32- and with 24-row
+# strips, and with every pair forced onto the intra-sequence (one pair per
+# wave) path.
 PATHS = {"auto": {"long_cells": -1},
+         "rows24": {"long_cells": 1 << 62, "long_rlen": 1 << 62, "fill_rows": 24},
          "batched": {"long_cells": 1 << 62, "long_rlen": 1 << 62},
          "intra": {"long_cells": 0, "long_rlen": 0, "intra_jobs": 256}}
 
@@ -138,7 +140,7 @@ def test_lane_width_threshold(ctx):
         rs.append(ref)
     b = W.from_lists("threshold", mat, 10, 2, qs, rs)
     recs = assert_parity(ctx, b)
-    if ctx.path == "batched":
+    if ctx.path in ("batched", "rows24"):
         assert set(recs["lane_bits"]) == {16, 32}
 
 
