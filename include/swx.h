@@ -195,6 +195,57 @@ int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t);
 int swx_autotune(swx_ctx *ctx, const swx_batch *b, int64_t max_pairs, const char *cache_path,
                  swx_tuning *out, int32_t *from_cache);
 
+/* ---- graph mode -----------------------------------------------------------------
+ * The batched path (forward fill, 32-bit re-run, reversed pass, banded
+ * traceback, score2, records) captured once as a hipGraph for batches of a
+ * fixed capacity and replayed per batch: no host round trips, no per-call
+ * planning on the host.  Every run aligns exactly max_pairs pairs held in the
+ * graph's own device buffers (swx_graph_io), which the caller fills before
+ * each run (pad unused pair slots with an empty reference: roff[k] ==
+ * roff[k+1]).  Requirements on the contents: qlen <= max_qlen, rlen <=
+ * max_rlen, offsets non-decreasing within the code arrays, codes in [0, n)
+ * over the whole code arrays (create fills them with 0).  Violations of the
+ * validated ones are reported by swx_graph_run as SWX_EINVAL; lengths above
+ * the capacities are the caller's error.  All pairs take the batched path
+ * (no intra-sequence routing).  Results equal swx_align_batch's.
+ * Errors: SWX_EINVAL (capacities < 1, flags), SWX_EOVERFLOW (scores could
+ * exceed the lanes), SWX_ENOMEM, SWX_EDEVICE. */
+typedef struct swx_graph swx_graph;
+
+typedef struct {
+  const int8_t *matrix; int32_t n; int32_t gap_open; int32_t gap_extend;   /* copied */
+  int64_t max_pairs;
+  int32_t max_qlen; int32_t pad_;
+  int64_t max_rlen;
+  int64_t qcat_cap, rcat_cap;   /* code array sizes */
+  int64_t nq_cap, nr_cap;       /* numbers of queries / references (offsets hold cap + 1) */
+  uint32_t flags;               /* SWX_BEGIN | SWX_CIGAR | SWX_SCORE2 */
+  int32_t mask_len;
+} swx_graph_cfg;
+
+typedef struct {   /* device buffers owned by the graph (valid until swx_graph_destroy) */
+  int8_t *qcat; int64_t *qoff; int8_t *rcat; int64_t *roff;   /* inputs, [cap], [cap + 1] */
+  int64_t *pair_q, *pair_r;                                   /* inputs, [max_pairs] */
+  swx_rec *recs;                                              /* output, [max_pairs] */
+  uint32_t *cigar; int64_t cigar_cap;                         /* output CIGAR arena */
+} swx_graph_io;
+
+int swx_graph_create(swx_ctx *ctx, const swx_graph_cfg *cfg, swx_graph **out, swx_graph_io *io);
+/* One replay on the context's stream; returns when the outputs are ready. */
+int swx_graph_run(swx_graph *g);
+/* The same chain issued kernel by kernel without the graph (for checking). */
+int swx_graph_run_eager(swx_graph *g);
+/* Copies a host-memory batch into the graph's input buffers, padding pair
+ * slots past npairs with (query 0, reference nr), an empty reference: needs
+ * npairs <= max_pairs, nq <= nq_cap, nr + 1 <= nr_cap and the code arrays
+ * within their capacities (SWX_EINVAL otherwise). */
+int swx_graph_load(swx_graph *g, const swx_batch *b);
+/* Copies the records of the first npairs pairs, and the CIGAR words they
+ * refer to, from the graph's output buffers to host memory (SWX_ERANGE when
+ * out->cigar_cap is too small; cigar_used says how many words are needed). */
+int swx_graph_read(swx_graph *g, int64_t npairs, swx_batch_out *out);
+int swx_graph_destroy(swx_graph *g);
+
 /* ---- serving ------------------------------------------------------------------
  * A request loop for a stream of alignment requests under one scoring scheme
  * (the paper's use in read mappers and search servers: many independent

@@ -89,6 +89,23 @@ COMPLETION_DTYPE = np.dtype([("ticket", "<u8"), ("tag", "<u8"), ("status", "<i4"
                              ("t_submit_ns", "<i8"), ("t_start_ns", "<i8"), ("t_done_ns", "<i8")])
 assert COMPLETION_DTYPE.itemsize == 112
 
+class SwxGraphCfg(ctypes.Structure):
+    _fields_ = [("matrix", ctypes.c_void_p), ("n", ctypes.c_int32), ("gap_open", ctypes.c_int32),
+                ("gap_extend", ctypes.c_int32), ("max_pairs", ctypes.c_int64),
+                ("max_qlen", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("max_rlen", ctypes.c_int64), ("qcat_cap", ctypes.c_int64),
+                ("rcat_cap", ctypes.c_int64), ("nq_cap", ctypes.c_int64),
+                ("nr_cap", ctypes.c_int64), ("flags", ctypes.c_uint32),
+                ("mask_len", ctypes.c_int32)]
+
+
+class SwxGraphIo(ctypes.Structure):
+    _fields_ = [("qcat", ctypes.c_void_p), ("qoff", ctypes.c_void_p), ("rcat", ctypes.c_void_p),
+                ("roff", ctypes.c_void_p), ("pair_q", ctypes.c_void_p),
+                ("pair_r", ctypes.c_void_p), ("recs", ctypes.c_void_p),
+                ("cigar", ctypes.c_void_p), ("cigar_cap", ctypes.c_int64)]
+
+
 # name -> (restype, argtypes)
 _SIGS = {
     "swx_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
@@ -108,6 +125,13 @@ _SIGS = {
     "swx_last_stage_ms": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                          ctypes.c_int]),
     "swx_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxTuning)]),
+    "swx_graph_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxGraphCfg),
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(SwxGraphIo)]),
+    "swx_graph_run": (ctypes.c_int, [ctypes.c_void_p]),
+    "swx_graph_run_eager": (ctypes.c_int, [ctypes.c_void_p]),
+    "swx_graph_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxBatch)]),
+    "swx_graph_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(SwxBatchOut)]),
+    "swx_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "swx_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxBatch), ctypes.c_int64,
                                     ctypes.c_char_p, ctypes.POINTER(SwxTuning),
                                     ctypes.POINTER(ctypes.c_int32)]),
@@ -376,6 +400,64 @@ class Context:
                                    pair_r, flags, mask_len, SWX_MEM_HOST, recs, cig, SWX_MEM_HOST)
         _check(st, "swx_align_batch")
         return recs, cig[:used]
+
+
+# ---- graph mode ---------------------------------------------------------------
+class Graph:
+    """The batched path captured as one hipGraph for batches of a fixed
+    capacity (swx_graph_*): load a host batch, run (replay), read results."""
+
+    def __init__(self, ctx: "Context", matrix, o, e, max_pairs, max_qlen, max_rlen, qcat_cap,
+                 rcat_cap, nq_cap, nr_cap, flags=SWX_ALL, mask_len=-1):
+        self._m = np.ascontiguousarray(matrix, dtype=np.int8)
+        cfg = SwxGraphCfg(matrix=self._m.ctypes.data, n=self._m.shape[0], gap_open=o,
+                          gap_extend=e, max_pairs=max_pairs, max_qlen=max_qlen, pad_=0,
+                          max_rlen=max_rlen, qcat_cap=qcat_cap, rcat_cap=rcat_cap, nq_cap=nq_cap,
+                          nr_cap=nr_cap, flags=flags, mask_len=mask_len)
+        h = ctypes.c_void_p()
+        self.io = SwxGraphIo()
+        _check(lib().swx_graph_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h),
+                                      ctypes.byref(self.io)), "swx_graph_create")
+        self.handle = h.value
+        self.ctx = ctx
+        self.max_pairs = max_pairs
+        self.npairs = 0
+
+    def load(self, qcat, qoff, rcat, roff, pair_q, pair_r):
+        qcat = np.ascontiguousarray(qcat, dtype=np.int8)
+        rcat = np.ascontiguousarray(rcat, dtype=np.int8)
+        qoff, roff, pair_q, pair_r = (np.ascontiguousarray(x, dtype=np.int64)
+                                      for x in (qoff, roff, pair_q, pair_r))
+        b, _mm = _make_batch(self._m, 0, 0, qcat, qoff, rcat, roff, pair_q, pair_r, 0, -1,
+                             SWX_MEM_HOST)
+        _check(lib().swx_graph_load(self.handle, ctypes.byref(b)), "swx_graph_load")
+        self.npairs = len(pair_q)
+
+    def run(self, eager=False):
+        f = lib().swx_graph_run_eager if eager else lib().swx_graph_run
+        _check(f(self.handle), "swx_graph_run")
+
+    def read(self):
+        recs = np.zeros(self.npairs, dtype=REC_DTYPE)
+        cig = np.zeros(max(int(self.io.cigar_cap), 1), dtype=np.uint32)
+        out = SwxBatchOut()
+        out.recs = recs.ctypes.data
+        out.cigar = cig.ctypes.data
+        out.cigar_cap = len(cig)
+        out.out_mem = SWX_MEM_HOST
+        _check(lib().swx_graph_read(self.handle, self.npairs, ctypes.byref(out)), "swx_graph_read")
+        return recs, cig[:out.cigar_used]
+
+    def close(self):
+        if self.handle:
+            _check(lib().swx_graph_destroy(self.handle), "swx_graph_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- serving ------------------------------------------------------------------

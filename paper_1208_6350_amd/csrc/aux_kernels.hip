@@ -396,8 +396,10 @@ __global__ void k_lens_to_i64(int64_t n, const int32_t *len, int64_t *out) {
   if (p < n) out[p] = len[p];
 }
 
-__global__ void k_mark_lanes(int64_t n, const int64_t *ids, uint8_t *lanebits, uint8_t v) {
+__global__ void k_mark_lanes(int64_t n, const int64_t *n_dev, const int64_t *ids, uint8_t *lanebits,
+                             uint8_t v) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n_dev) n = *n_dev;
   if (k < n) lanebits[ids[k]] = v;
 }
 
@@ -430,8 +432,16 @@ hipError_t lens_to_i64(int64_t n, const int32_t *len, int64_t *out, hipStream_t 
 
 hipError_t mark_lanes(int64_t n, const int64_t *ids, uint8_t *lanebits, int v, hipStream_t st) {
   if (!n) return hipSuccess;
-  hipLaunchKernelGGL(k_mark_lanes, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, ids, lanebits,
-                     (uint8_t)v);
+  hipLaunchKernelGGL(k_mark_lanes, dim3(blocks_for(n, 256)), dim3(256), 0, st, n,
+                     (const int64_t *)nullptr, ids, lanebits, (uint8_t)v);
+  return hipGetLastError();
+}
+
+hipError_t mark_lanes_dev(int64_t cap, const int64_t *n_dev, const int64_t *ids, uint8_t *lanebits,
+                          int v, hipStream_t st) {
+  if (!cap) return hipSuccess;
+  hipLaunchKernelGGL(k_mark_lanes, dim3(blocks_for(cap, 256)), dim3(256), 0, st, cap, n_dev, ids,
+                     lanebits, (uint8_t)v);
   return hipGetLastError();
 }
 

@@ -93,6 +93,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fill_waves<
                       __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   if (tid >= a.ntasks) return;
   const InterTask tk = a.tasks[tid];
+  if (tk.nslots == 0) return;   // an empty task of a fixed-capacity plan
   constexpr bool rev = REV;
   const int nstrips = tk.qp / R;
   const int64_t rp = tk.rp;
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fill_waves<
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
           const int32_t qv = seq_at(qs[h], sR + r);
-          const uint32_t b = qv < 0 ? 0x0Cu : (uint32_t)qv + 4u * h;
+          const uint32_t b = (qv < 0 || qv >= a.n) ? 0x0Cu : (uint32_t)qv + 4u * h;
           w = (w & ~(0xFFu << (16 * h))) | (b << (16 * h));
         }
         sel[r] = w;
@@ -407,7 +408,10 @@ __global__ __launch_bounds__(256) void k_inter_rsym(PackArgs a) {
       const int64_t j = c - s_pad[s];
       const int64_t len = s_len[s];
       uint8_t v = pad_sym;
-      if (j >= 0 && j < len) v = (uint8_t)s_base[s][reversed ? len - 1 - j : j];
+      if (j >= 0 && j < len) {
+        const int8_t c = s_base[s][reversed ? len - 1 - j : j];
+        v = (c >= 0 && c < a.n) ? (uint8_t)c : pad_sym;   // a bad code never indexes a table
+      }
       tile[s * kRsymStride + threadIdx.x] = v;
     }
     __syncthreads();
@@ -449,7 +453,7 @@ __global__ __launch_bounds__(256) void k_inter_prof(PackArgs a) {
                                 a.view.reversed != 0, a.matrix);
       for (int r = 0; r < R; ++r) {
         const int32_t qv = seq_at(q, strip * R + r);
-        const uint32_t b = qv < 0 ? 0u : (uint32_t)(uint8_t)(a.matrix[qv * a.n + sy] + a.bias);
+        const uint32_t b = (qv < 0 || qv >= a.n) ? 0u : (uint32_t)(uint8_t)(a.matrix[qv * a.n + sy] + a.bias);
         w[r >> 2] |= b << (8 * (r & 3));
       }
     }

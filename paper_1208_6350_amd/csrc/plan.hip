@@ -13,11 +13,18 @@
 
 namespace swx {
 
-__global__ void k_plan_keys(int64_t n, const int64_t *ids, const int32_t *qlen,
+// n_dev (may be null): the number of valid ids, read on the device; entries
+// beyond it get the largest key (they sort last and form empty tasks)
+__global__ void k_plan_keys(int64_t n, const int64_t *n_dev, const int64_t *ids, const int32_t *qlen,
                             const int64_t *rlen, const int32_t *band, int32_t R, uint64_t *keys,
                             int64_t *vals) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
+  if (n_dev && k >= *n_dev) {
+    keys[k] = ~0ull;
+    vals[k] = -1;
+    return;
+  }
   const int64_t p = ids ? ids[k] : k;
   int64_t q = qlen[p];
   if (q < 1) q = 1;
@@ -30,14 +37,16 @@ __global__ void k_plan_keys(int64_t n, const int64_t *ids, const int32_t *qlen,
   vals[k] = p;
 }
 
-__global__ void k_plan_tasks(int64_t n, int64_t ntasks, int32_t slots, int32_t R,
-                             int64_t qdata_per_row, const int64_t *sorted, const int32_t *qlen,
-                             const int64_t *rlen, const int32_t *band, InterTask *tasks,
-                             int64_t *bnd_size, int64_t *qdata_size) {
+__global__ void k_plan_tasks(int64_t n, const int64_t *n_dev, int64_t ntasks, int32_t slots,
+                             int32_t R, int64_t qdata_per_row, const int64_t *sorted,
+                             const int32_t *qlen, const int64_t *rlen, const int32_t *band,
+                             InterTask *tasks, int64_t *bnd_size, int64_t *qdata_size) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ntasks) return;
+  if (n_dev) n = *n_dev;
   const int64_t s0 = t * slots;
-  const int64_t s1 = (s0 + slots < n) ? s0 + slots : n;
+  int64_t s1 = (s0 + slots < n) ? s0 + slots : n;
+  if (s1 < s0) s1 = s0;   // a task past the valid ids is empty
   int64_t mq = 1, mr = 1;
   int32_t mb = band ? 0 : -1;
   for (int64_t k = s0; k < s1; ++k) {
@@ -144,18 +153,18 @@ hipError_t rev_prepare(int64_t npairs, const int32_t *score, const int32_t *qend
   return hipGetLastError();
 }
 
-hipError_t plan_sort(int64_t n, const int64_t *ids, const int32_t *qlen, const int64_t *rlen,
-                     const int32_t *band, int32_t R, uint64_t *keys, uint64_t *keys_alt,
-                     int64_t *vals, int64_t *vals_alt, void *tmp, size_t *tmp_bytes,
-                     int64_t **sorted_out, hipStream_t st) {
+hipError_t plan_sort(int64_t n, const int64_t *n_dev, const int64_t *ids, const int32_t *qlen,
+                     const int64_t *rlen, const int32_t *band, int32_t R, uint64_t *keys,
+                     uint64_t *keys_alt, int64_t *vals, int64_t *vals_alt, void *tmp,
+                     size_t *tmp_bytes, int64_t **sorted_out, hipStream_t st) {
   if (tmp == nullptr) {
     hipcub::DoubleBuffer<uint64_t> kb(keys, keys_alt);
     hipcub::DoubleBuffer<int64_t> vb(vals, vals_alt);
     return hipcub::DeviceRadixSort::SortPairs(nullptr, *tmp_bytes, kb, vb, (int)n, 0, 64, st);
   }
   if (n == 0) { *sorted_out = vals; return hipSuccess; }
-  hipLaunchKernelGGL(k_plan_keys, dim3(nb(n, 256)), dim3(256), 0, st, n, ids, qlen, rlen, band, R,
-                     keys, vals);
+  hipLaunchKernelGGL(k_plan_keys, dim3(nb(n, 256)), dim3(256), 0, st, n, n_dev, ids, qlen, rlen,
+                     band, R, keys, vals);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipcub::DoubleBuffer<uint64_t> kb(keys, keys_alt);
@@ -165,13 +174,14 @@ hipError_t plan_sort(int64_t n, const int64_t *ids, const int32_t *qlen, const i
   return e;
 }
 
-hipError_t plan_tasks_dev(int64_t n, int64_t ntasks, int32_t slots, int32_t R,
+hipError_t plan_tasks_dev(int64_t n, const int64_t *n_dev, int64_t ntasks, int32_t slots, int32_t R,
                           int64_t qdata_per_row, const int64_t *sorted, const int32_t *qlen,
                           const int64_t *rlen, const int32_t *band, InterTask *tasks,
                           int64_t *bnd_size, int64_t *qdata_size, hipStream_t st) {
   if (ntasks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_plan_tasks, dim3(nb(ntasks, 128)), dim3(128), 0, st, n, ntasks, slots, R,
-                     qdata_per_row, sorted, qlen, rlen, band, tasks, bnd_size, qdata_size);
+  hipLaunchKernelGGL(k_plan_tasks, dim3(nb(ntasks, 128)), dim3(128), 0, st, n, n_dev, ntasks,
+                     slots, R, qdata_per_row, sorted, qlen, rlen, band, tasks, bnd_size,
+                     qdata_size);
   return hipGetLastError();
 }
 
@@ -193,6 +203,45 @@ hipError_t compact_flags(int64_t n, const uint8_t *flag, const int64_t *pos, int
                          hipStream_t st) {
   if (!n) return hipSuccess;
   hipLaunchKernelGGL(k_compact, dim3(nb(n, 256)), dim3(256), 0, st, n, flag, pos, out);
+  return hipGetLastError();
+}
+
+// ---- plain fills (graph-capturable in place of memset nodes) ------------------
+__global__ void k_fill_u8(int64_t n, uint8_t *p, uint8_t v) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
+__global__ void k_fill_i64(int64_t n, int64_t *p, int64_t v) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
+hipError_t fill_u8(int64_t n, uint8_t *p, uint8_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u8, dim3(nb(n, 256)), dim3(256), 0, st, n, p, v);
+  return hipGetLastError();
+}
+
+hipError_t fill_i64(int64_t n, int64_t *p, int64_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i64, dim3(nb(n, 256)), dim3(256), 0, st, n, p, v);
+  return hipGetLastError();
+}
+
+// ranges[2c], ranges[2c+1]: positions of class c in the class-sorted list
+__global__ void k_class_ranges(const int64_t *counts, int64_t *ranges) {
+  if (threadIdx.x != 0) return;
+  int64_t pos = 0;
+  for (int c = 0; c < 8; ++c) {
+    ranges[2 * c] = pos;
+    pos += counts[c];
+    ranges[2 * c + 1] = pos;
+  }
+}
+
+hipError_t class_ranges(const int64_t *counts, int64_t *ranges, hipStream_t st) {
+  hipLaunchKernelGGL(k_class_ranges, dim3(1), dim3(64), 0, st, counts, ranges);
   return hipGetLastError();
 }
 

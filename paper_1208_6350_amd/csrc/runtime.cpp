@@ -195,14 +195,14 @@ static int plan_pass(swx_ctx *ctx, const Scoring &sc, const int64_t *ids, int64_
   if (!k0 || !k1 || !v0 || !v1 || !pl.d_tasks || !bsz || !qsz || !boff || !qoff)
     return fail(SWX_ENOMEM, "device pool exhausted (plan)");
   size_t tmp_bytes = 0;
-  HIP_TRY(plan_sort(n, ids, qlen, rlen, band, R, k0, k1, v0, v1, nullptr, &tmp_bytes, nullptr, st));
+  HIP_TRY(plan_sort(n, nullptr, ids, qlen, rlen, band, R, k0, k1, v0, v1, nullptr, &tmp_bytes, nullptr, st));
   void *tmp = A.alloc(tmp_bytes);
   if (!tmp) return fail(SWX_ENOMEM, "device pool exhausted (sort)");
-  HIP_TRY(plan_sort(n, ids, qlen, rlen, band, R, k0, k1, v0, v1, tmp, &tmp_bytes, &pl.d_sorted, st));
+  HIP_TRY(plan_sort(n, nullptr, ids, qlen, rlen, band, R, k0, k1, v0, v1, tmp, &tmp_bytes, &pl.d_sorted, st));
   const int64_t per_row = sc.qsel ? 0 : (int64_t)(sc.n + 1) * halves * 64;
   HIP_TRY(hipMemsetAsync(bsz + pl.ntasks, 0, 8, st));
   HIP_TRY(hipMemsetAsync(qsz + pl.ntasks, 0, 8, st));
-  HIP_TRY(plan_tasks_dev(n, pl.ntasks, slots, R, per_row, pl.d_sorted, qlen, rlen, band,
+  HIP_TRY(plan_tasks_dev(n, nullptr, pl.ntasks, slots, R, per_row, pl.d_sorted, qlen, rlen, band,
                          pl.d_tasks, bsz, qsz, st));
   size_t t1 = 0, t2 = 0;
   HIP_TRY(launch_exclusive_scan(bsz, boff, pl.ntasks + 1, nullptr, &t1, st));
@@ -374,6 +374,7 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
   ta.qcat = b.qcat; ta.rcat = b.rcat; ta.matrix = sc.dmat;
   ta.n = sc.n; ta.o = sc.o; ta.e = sc.e; ta.smax = sc.smax;
   ta.cig_len = cig_len; ta.err = err;
+  ta.wave_cells = kWaveTbCells;
   uint8_t *cls = A.get<uint8_t>(np);
   uint64_t *k0 = A.get<uint64_t>(np), *k1 = A.get<uint64_t>(np);
   int64_t *v0 = A.get<int64_t>(np), *v1 = A.get<int64_t>(np);
@@ -931,6 +932,368 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
   return rc_range;
 }
 
+// ============================================================================
+// Fixed-capacity path for hipGraph capture.
+//
+// The same stages as run_pipeline, for batches of exactly B pairs with
+// qlen <= QM and rlen <= RM, with every buffer sized from those capacities
+// when the graph is made and every count that depends on the data (pairs
+// re-run on 32-bit lanes, pairs per reversed pass, pairs per traceback class)
+// kept on the device: plans take their pair count from device memory and
+// form empty tasks past it, kernels skip empty tasks.  Nothing in it waits on
+// the host, so the whole chain is captured once and replayed per batch.
+// Long pairs are not routed to the intra-sequence path here (its job tables
+// are built on the host), and wide bands stay on the strip kernel.
+// ============================================================================
+struct FixedPlan {
+  int lane_bits = 16, R = 32, slots = 128;
+  int64_t cap_n = 0, ntasks = 0;
+  uint64_t *k0 = nullptr, *k1 = nullptr;
+  int64_t *v0 = nullptr, *v1 = nullptr;
+  void *sort_tmp = nullptr;
+  size_t sort_bytes = 0;
+  int64_t *sorted = nullptr;
+  InterTask *tasks = nullptr;
+  int64_t *bsz = nullptr, *boff = nullptr, *qsz = nullptr, *qoff = nullptr;
+  uint32_t *bnd = nullptr;
+  uint2 *rsym = nullptr;
+  uint8_t *prof = nullptr;
+};
+
+struct FixedTb {   // one traceback class
+  int64_t cap_tasks = 0;
+  void *tasks = nullptr;     // TbTask or TbwTask
+  int64_t *dsz = nullptr, *doff = nullptr, *bsz = nullptr, *boff = nullptr;
+  uint32_t *dir = nullptr;
+  int32_t *bnd = nullptr;
+};
+
+struct GraphState {
+  swx_graph_cfg cfg{};
+  std::vector<int8_t> matrix;
+  Scoring sc{};
+  DevArena A;
+  int64_t B = 0, QM = 0, RM = 0;
+  bool clamp = false, need32 = false;
+  // inputs / outputs
+  int8_t *qcat = nullptr, *rcat = nullptr;
+  int64_t *qoff = nullptr, *roff = nullptr, *pair_q = nullptr, *pair_r = nullptr;
+  swx_rec_dev *recs = nullptr;
+  uint32_t *cigar = nullptr;
+  int64_t cigar_cap = 0;
+  // per pair
+  int64_t *qstart, *rstart, *rlen, *rend, *rbeg, *rend2, *rqs, *rrs, *rrl, *rre;
+  int32_t *qlen, *score, *qend, *qbeg, *score2, *rql, *tgt, *band, *rsc, *rqe, *cig_len;
+  uint8_t *ovf, *lanebits, *err, *rov, *f16, *f32, *cls;
+  uint32_t *bad;
+  int64_t *status;            // [0] pairs with an error flag
+  // compaction of flagged pairs
+  int64_t *f64, *pos, *ids;
+  void *scan_tmp = nullptr;
+  size_t scan_bytes = 0;
+  FixedPlan p16, p32, r16, r32;
+  // traceback
+  uint64_t *tk0, *tk1;
+  int64_t *tv0, *tv1, *ccap, *coff, *counts, *ranges, *len64, *cig_off_final;
+  int64_t *tb_sorted = nullptr;
+  void *tb_sort_tmp = nullptr;
+  size_t tb_sort_bytes = 0;
+  FixedTb tb[6];
+  uint32_t *cscr = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static int fixed_scan(GraphState &g, const int64_t *in, int64_t *out, int64_t n, hipStream_t st) {
+  size_t need = 0;
+  HIP_TRY(launch_exclusive_scan(in, out, n, nullptr, &need, st));
+  if (need > g.scan_bytes) return fail(SWX_EINTERNAL, "scan scratch too small");
+  size_t have = g.scan_bytes;
+  HIP_TRY(launch_exclusive_scan(in, out, n, g.scan_tmp, &have, st));
+  return SWX_OK;
+}
+
+// allocate a plan's buffers for up to cap_n pairs (create time)
+static int fixed_plan_alloc(GraphState &g, FixedPlan &pl, int lane_bits, int R) {
+  DevArena &A = g.A;
+  pl.lane_bits = lane_bits;
+  pl.R = R;
+  pl.slots = lane_bits == 16 ? kSlots16 : kSlots32;
+  pl.cap_n = g.B;
+  pl.ntasks = (g.B + pl.slots - 1) / pl.slots;
+  const int halves = lane_bits == 16 ? 2 : 1;
+  pl.k0 = A.get<uint64_t>(g.B); pl.k1 = A.get<uint64_t>(g.B);
+  pl.v0 = A.get<int64_t>(g.B); pl.v1 = A.get<int64_t>(g.B);
+  pl.tasks = A.get<InterTask>(pl.ntasks);
+  pl.bsz = A.get<int64_t>(pl.ntasks + 1); pl.boff = A.get<int64_t>(pl.ntasks + 1);
+  pl.qsz = A.get<int64_t>(pl.ntasks + 1); pl.qoff = A.get<int64_t>(pl.ntasks + 1);
+  const int64_t rp_cap = (g.RM + 7) / 8 * 8 + 8;
+  const int64_t qp_cap = (g.QM + R - 1) / R * R + R;
+  const int64_t bnd_words = pl.ntasks * 3 * 64 * rp_cap;
+  pl.bnd = A.get<uint32_t>(bnd_words);
+  pl.rsym = A.get<uint2>(rsym_offset(bnd_words) + 16);
+  if (!g.sc.qsel) pl.prof = A.get<uint8_t>(pl.ntasks * qp_cap * (g.sc.n + 1) * halves * 64 + 16);
+  size_t sb = 0;
+  HIP_TRY(plan_sort(g.B, nullptr, nullptr, nullptr, nullptr, nullptr, R, pl.k0, pl.k1, pl.v0, pl.v1,
+                    nullptr, &sb, nullptr, nullptr));
+  pl.sort_bytes = sb;
+  pl.sort_tmp = A.alloc(sb);
+  if (!pl.k0 || !pl.k1 || !pl.v0 || !pl.v1 || !pl.tasks || !pl.bsz || !pl.boff || !pl.qsz ||
+      !pl.qoff || !pl.bnd || !pl.rsym || (!g.sc.qsel && !pl.prof) || !pl.sort_tmp)
+    return fail(SWX_ENOMEM, "device pool exhausted (graph plan)");
+  return SWX_OK;
+}
+
+// plan + fill of one pass over ids[0 .. *n_dev) (ids null: all B pairs)
+static int fixed_fill(GraphState &g, FixedPlan &pl, const int64_t *ids, const int64_t *n_dev,
+                      const int32_t *qlen, const int64_t *rlen, const int32_t *band,
+                      const PairView &view, bool rev, const int32_t *target, FillOut out,
+                      hipStream_t st) {
+  size_t sb = pl.sort_bytes;
+  HIP_TRY(plan_sort(pl.cap_n, n_dev, ids, qlen, rlen, band, pl.R, pl.k0, pl.k1, pl.v0, pl.v1,
+                    pl.sort_tmp, &sb, &pl.sorted, st));
+  const int halves = pl.lane_bits == 16 ? 2 : 1;
+  const int64_t per_row = g.sc.qsel ? 0 : (int64_t)(g.sc.n + 1) * halves * 64;
+  HIP_TRY(fill_i64(1, pl.bsz + pl.ntasks, 0, st));
+  HIP_TRY(fill_i64(1, pl.qsz + pl.ntasks, 0, st));
+  HIP_TRY(plan_tasks_dev(pl.cap_n, n_dev, pl.ntasks, pl.slots, pl.R, per_row, pl.sorted, qlen, rlen,
+                         band, pl.tasks, pl.bsz, pl.qsz, st));
+  int rc;
+  if ((rc = fixed_scan(g, pl.bsz, pl.boff, pl.ntasks + 1, st))) return rc;
+  if ((rc = fixed_scan(g, pl.qsz, pl.qoff, pl.ntasks + 1, st))) return rc;
+  HIP_TRY(plan_offsets_dev(pl.ntasks, pl.tasks, pl.boff, pl.qoff, st));
+  PackArgs pk{};
+  pk.tasks = pl.tasks; pk.ntasks = pl.ntasks; pk.slot_pair = pl.sorted; pk.view = view;
+  pk.prof = pl.prof; pk.rsym = pl.rsym; pk.matrix = g.sc.dmat; pk.n = g.sc.n; pk.bias = g.sc.bias;
+  pk.halves = halves; pk.strip_rows = pl.R; pk.rev = rev ? 1 : 0;
+  HIP_TRY(inter_pack_ref(pk, st));
+  if (!g.sc.qsel) HIP_TRY(inter_pack(pk, st));
+  InterArgs a{};
+  a.tasks = pl.tasks; a.ntasks = pl.ntasks; a.slot_pair = pl.sorted; a.view = view;
+  a.prof = g.sc.qsel ? nullptr : pl.prof; a.bnd = pl.bnd; a.rsym = pl.rsym;
+  for (int k = 0; k < 8; ++k) a.lut[k] = g.sc.lut[k];
+  a.n = g.sc.n; a.o = g.sc.o; a.e = g.sc.e; a.bias = g.sc.bias;
+  a.rev = rev ? 1 : 0;
+  a.clamp = g.clamp ? 1 : 0;
+  a.code_top = pl.R - 1;
+  a.dummy = g.sc.dmat;
+  a.target = target;
+  a.out = out;
+  HIP_TRY(inter_fill(a, pl.lane_bits, pl.R, st));
+  return SWX_OK;
+}
+
+// flagged pairs -> ids[0 .. *count) with the count on the device (pos[B])
+static int fixed_select(GraphState &g, const uint8_t *flag, const int64_t **count, hipStream_t st) {
+  HIP_TRY(fill_i64(1, g.f64 + g.B, 0, st));
+  HIP_TRY(flags_to_i64(g.B, flag, g.f64, st));
+  int rc;
+  if ((rc = fixed_scan(g, g.f64, g.pos, g.B + 1, st))) return rc;
+  HIP_TRY(compact_flags(g.B, flag, g.pos, g.ids, st));
+  *count = g.pos + g.B;
+  return SWX_OK;
+}
+
+static int fixed_issue(GraphState &g, hipStream_t st) {
+  const int64_t B = g.B;
+  const uint32_t flags = g.cfg.flags & (SWX_CIGAR | SWX_SCORE2) ? (g.cfg.flags | SWX_BEGIN) : g.cfg.flags;
+  int rc;
+  HIP_TRY(fill_u8(4, (uint8_t *)g.bad, 0, st));
+  HIP_TRY(fill_i64(1, g.status, 0, st));
+  HIP_TRY(fill_u8(B, g.err, 0, st));
+  HIP_TRY(fill_u8(B, g.lanebits, 16, st));
+  ValidateArgs va{g.qcat, g.cfg.qcat_cap, g.qoff, g.cfg.nq_cap, g.rcat, g.cfg.rcat_cap, g.roff,
+                  g.cfg.nr_cap, g.pair_q, g.pair_r, B, g.sc.n, g.bad};
+  HIP_TRY(launch_validate(va, st));
+  HIP_TRY(launch_views(B, g.qoff, g.roff, g.pair_q, g.pair_r, g.qstart, g.qlen, g.rstart, g.rlen, st));
+  PairView fview{g.qstart, g.rstart, g.qlen, g.rlen, g.qcat, g.rcat, 0};
+  FillOut fout{g.score, g.qend, g.rend, g.ovf};
+  if ((rc = fixed_fill(g, g.p16, nullptr, nullptr, g.qlen, g.rlen, nullptr, fview, false, nullptr,
+                       fout, st)))
+    return rc;
+  if (g.need32) {
+    const int64_t *nw = nullptr;
+    if ((rc = fixed_select(g, g.ovf, &nw, st))) return rc;
+    if ((rc = fixed_fill(g, g.p32, g.ids, nw, g.qlen, g.rlen, nullptr, fview, false, nullptr, fout,
+                         st)))
+      return rc;
+    HIP_TRY(mark_lanes_dev(B, nw, g.ids, g.lanebits, 32, st));
+  }
+  if (flags & SWX_BEGIN) {
+    HIP_TRY(launch_rev_views(B, g.qstart, g.rstart, g.qlen, g.rlen, g.score, g.qend, g.rend, g.rqs,
+                             g.rql, g.rrs, g.rrl, g.tgt, g.err, st));
+    HIP_TRY(rev_prepare(B, g.score, g.qend, g.rend, g.lanebits, g.sc.smax, g.sc.o, g.sc.e, g.band,
+                        g.f16, g.f32, st));
+    HIP_TRY(fill_u8(4 * B, (uint8_t *)g.rsc, 0, st));
+    PairView rview{g.rqs, g.rrs, g.rql, g.rrl, g.qcat, g.rcat, 1};
+    FillOut rout{g.rsc, g.rqe, g.rre, g.rov};
+    const int64_t *n16 = nullptr;
+    if ((rc = fixed_select(g, g.f16, &n16, st))) return rc;
+    if ((rc = fixed_fill(g, g.r16, g.ids, n16, g.rql, g.rrl, g.band, rview, true, g.tgt, rout, st)))
+      return rc;
+    if (g.need32) {
+      const int64_t *n32 = nullptr;
+      if ((rc = fixed_select(g, g.f32, &n32, st))) return rc;
+      if ((rc = fixed_fill(g, g.r32, g.ids, n32, g.rql, g.rrl, g.band, rview, true, g.tgt, rout,
+                           st)))
+        return rc;
+    }
+    HIP_TRY(launch_begins(B, g.score, g.qend, g.rend, g.rsc, g.rqe, g.rre, g.qbeg, g.rbeg, g.err, st));
+  }
+  HIP_TRY(fill_u8(4 * B, (uint8_t *)g.cig_len, 0, st));
+  HIP_TRY(fill_i64(B + 1, g.cig_off_final, 0, st));
+  if (flags & SWX_CIGAR) {
+    TbArgs ta{};
+    ta.score = g.score; ta.qbeg = g.qbeg; ta.qend = g.qend; ta.rbeg = g.rbeg; ta.rend = g.rend;
+    ta.qstart = g.qstart; ta.rstart = g.rstart; ta.qlen = g.qlen; ta.rlen = g.rlen;
+    ta.qcat = g.qcat; ta.rcat = g.rcat; ta.matrix = g.sc.dmat;
+    ta.n = g.sc.n; ta.o = g.sc.o; ta.e = g.sc.e; ta.smax = g.sc.smax;
+    ta.cig_len = g.cig_len; ta.err = g.err;
+    ta.wave_cells = INT64_MAX;   // no host-planned wave traceback in a graph
+    ta.cig = g.cscr;
+    ta.cig_off = g.coff;
+    HIP_TRY(fill_i64(1, g.ccap + B, 0, st));
+    HIP_TRY(fill_i64(8, g.counts, 0, st));
+    HIP_TRY(tb_classify(ta, B, g.cls, g.tk0, g.tv0, g.ccap, st));
+    if ((rc = fixed_scan(g, g.ccap, g.coff, B + 1, st))) return rc;
+    HIP_TRY(count_classes(B, g.cls, g.counts, st));
+    size_t sb = g.tb_sort_bytes;
+    HIP_TRY(sort_keys(B, g.tk0, g.tk1, g.tv0, g.tv1, g.tb_sort_tmp, &sb, &g.tb_sorted, st));
+    HIP_TRY(class_ranges(g.counts, g.ranges, st));
+    for (int c = 1; c <= 3; ++c) {
+      FixedTb &t = g.tb[c];
+      const int32_t bw = 8 << (c - 1);
+      TbTask *tasks = (TbTask *)t.tasks;
+      HIP_TRY(fill_i64(1, t.dsz + t.cap_tasks, 0, st));
+      HIP_TRY(tb_tasks_range(g.ranges + 2 * c, t.cap_tasks, g.tb_sorted, ta, bw, tasks, t.dsz, st));
+      if ((rc = fixed_scan(g, t.dsz, t.doff, t.cap_tasks + 1, st))) return rc;
+      HIP_TRY(tb_offsets(t.cap_tasks, tasks, t.doff, st));
+      TbArgs tc = ta;
+      tc.dir = t.dir;
+      HIP_TRY(tb_band(tc, tasks, t.cap_tasks, g.tb_sorted, bw, st));
+    }
+    {
+      FixedTb &t = g.tb[5];
+      TbwTask *tasks = (TbwTask *)t.tasks;
+      HIP_TRY(fill_i64(1, t.dsz + t.cap_tasks, 0, st));
+      HIP_TRY(fill_i64(1, t.bsz + t.cap_tasks, 0, st));
+      HIP_TRY(tbw_tasks_range(g.ranges + 10, t.cap_tasks, g.tb_sorted, ta, tasks, t.dsz, t.bsz, st));
+      if ((rc = fixed_scan(g, t.dsz, t.doff, t.cap_tasks + 1, st))) return rc;
+      if ((rc = fixed_scan(g, t.bsz, t.boff, t.cap_tasks + 1, st))) return rc;
+      HIP_TRY(tbw_offsets(t.cap_tasks, tasks, t.doff, t.boff, st));
+      TbArgs tc = ta;
+      tc.dir = t.dir;
+      HIP_TRY(tb_strip(tc, tasks, t.cap_tasks, g.tb_sorted, t.bnd, st));
+    }
+    HIP_TRY(fill_i64(1, g.len64 + B, 0, st));
+    HIP_TRY(lens_to_i64(B, g.cig_len, g.len64, st));
+    if ((rc = fixed_scan(g, g.len64, g.cig_off_final, B + 1, st))) return rc;
+    HIP_TRY(launch_cigar_compact(B, g.cscr, g.coff, g.cig_len, g.cig_off_final, g.cigar, st));
+  }
+  if (flags & SWX_SCORE2) {
+    Score2InterArgs s2{};
+    s2.rlen = g.rlen; s2.qlen = g.qlen; s2.score1 = g.score; s2.rbeg = g.rbeg; s2.rend = g.rend;
+    s2.mask_len = g.cfg.mask_len; s2.score2 = g.score2; s2.rend2 = g.rend2;
+    s2.tasks = g.p16.tasks; s2.ntasks = g.p16.ntasks; s2.slot_pair = g.p16.sorted;
+    s2.bnd = g.p16.bnd; s2.halves = 2;
+    HIP_TRY(launch_score2_inter(s2, st));
+    if (g.need32) {
+      s2.tasks = g.p32.tasks; s2.ntasks = g.p32.ntasks; s2.slot_pair = g.p32.sorted;
+      s2.bnd = g.p32.bnd; s2.halves = 1;
+      HIP_TRY(launch_score2_inter(s2, st));
+    }
+  }
+  HIP_TRY(launch_records(B, g.score, g.score2, g.qbeg, g.qend, g.rbeg, g.rend, g.rend2,
+                         g.cig_off_final, g.cig_len, g.lanebits, flags, g.recs, st));
+  HIP_TRY(launch_any_flag(B, g.err, g.status, st));
+  return SWX_OK;
+}
+
+static int graph_alloc(GraphState &g) {
+  DevArena &A = g.A;
+  const int64_t B = g.B;
+  g.qcat = A.get<int8_t>(g.cfg.qcat_cap);
+  g.rcat = A.get<int8_t>(g.cfg.rcat_cap);
+  g.qoff = A.get<int64_t>(g.cfg.nq_cap + 1);
+  g.roff = A.get<int64_t>(g.cfg.nr_cap + 1);
+  g.pair_q = A.get<int64_t>(B);
+  g.pair_r = A.get<int64_t>(B);
+  g.recs = A.get<swx_rec_dev>(B);
+  g.cigar_cap = B * (g.QM + g.RM + 2);
+  g.cigar = A.get<uint32_t>(g.cigar_cap);
+  g.cscr = A.get<uint32_t>(g.cigar_cap);
+  for (int64_t **p : {&g.qstart, &g.rstart, &g.rlen, &g.rend, &g.rbeg, &g.rend2, &g.rqs, &g.rrs,
+                      &g.rrl, &g.rre, &g.tv0, &g.tv1})
+    *p = A.get<int64_t>(B);
+  for (int32_t **p : {&g.qlen, &g.score, &g.qend, &g.qbeg, &g.score2, &g.rql, &g.tgt, &g.band,
+                      &g.rsc, &g.rqe, &g.cig_len})
+    *p = A.get<int32_t>(B);
+  for (uint8_t **p : {&g.ovf, &g.lanebits, &g.err, &g.rov, &g.f16, &g.f32, &g.cls})
+    *p = A.get<uint8_t>(B);
+  g.bad = A.get<uint32_t>(1);
+  g.status = A.get<int64_t>(1);
+  g.f64 = A.get<int64_t>(B + 1);
+  g.pos = A.get<int64_t>(B + 1);
+  g.ids = A.get<int64_t>(B);
+  g.tk0 = A.get<uint64_t>(B);
+  g.tk1 = A.get<uint64_t>(B);
+  g.ccap = A.get<int64_t>(B + 1);
+  g.coff = A.get<int64_t>(B + 1);
+  g.counts = A.get<int64_t>(8);
+  g.ranges = A.get<int64_t>(16);
+  g.len64 = A.get<int64_t>(B + 1);
+  g.cig_off_final = A.get<int64_t>(B + 1);
+  int rc;
+  const int R = (g.sc.qsel ? 32 : 32);
+  if ((rc = fixed_plan_alloc(g, g.p16, 16, R))) return rc;
+  if ((rc = fixed_plan_alloc(g, g.r16, 16, R))) return rc;
+  if (g.need32) {
+    if ((rc = fixed_plan_alloc(g, g.p32, 32, R))) return rc;
+    if ((rc = fixed_plan_alloc(g, g.r32, 32, R))) return rc;
+  }
+  // traceback classes: up to every pair in one class
+  const int64_t capT = (B + 63) / 64;
+  for (int c = 1; c <= 3; ++c) {
+    FixedTb &t = g.tb[c];
+    t.cap_tasks = capT;
+    t.tasks = A.get<TbTask>(capT);
+    t.dsz = A.get<int64_t>(capT + 1);
+    t.doff = A.get<int64_t>(capT + 1);
+    t.dir = A.get<uint32_t>(capT * (g.QM + 2) * ((8 << (c - 1)) / 8) * 64);
+    if (!t.tasks || !t.dsz || !t.doff || !t.dir) return fail(SWX_ENOMEM, "device pool exhausted (graph traceback)");
+  }
+  {
+    FixedTb &t = g.tb[5];
+    t.cap_tasks = capT;
+    t.tasks = A.get<TbwTask>(capT);
+    t.dsz = A.get<int64_t>(capT + 1); t.doff = A.get<int64_t>(capT + 1);
+    t.bsz = A.get<int64_t>(capT + 1); t.boff = A.get<int64_t>(capT + 1);
+    // a safe band is at most m + w + 1 diagonals wide; the union over a task's
+    // pairs at most 2 (m + w) + 1
+    const int64_t W = 16 + 2 * (g.QM + g.RM) + 2;
+    const int64_t nstrips = (g.QM + 15) / 16;
+    t.dir = A.get<uint32_t>(capT * (nstrips + 1) * W * 2 * 64);
+    t.bnd = A.get<int32_t>(capT * 2 * (g.RM + 1) * 64);
+    if (!t.tasks || !t.dsz || !t.doff || !t.bsz || !t.boff || !t.dir || !t.bnd)
+      return fail(SWX_ENOMEM, "device pool exhausted (graph traceback)");
+  }
+  size_t sb = 0;
+  HIP_TRY(sort_keys(B, g.tk0, g.tk1, g.tv0, g.tv1, nullptr, &sb, &g.tb_sorted, nullptr));
+  g.tb_sort_bytes = sb;
+  g.tb_sort_tmp = A.alloc(sb);
+  // scan scratch: the largest scan is over B + 1 elements
+  size_t sc1 = 0;
+  HIP_TRY(launch_exclusive_scan(g.f64, g.pos, B + 1, nullptr, &sc1, nullptr));
+  g.scan_bytes = sc1 + 4096;
+  g.scan_tmp = A.alloc(g.scan_bytes);
+  if (!g.qcat || !g.rcat || !g.qoff || !g.roff || !g.pair_q || !g.pair_r || !g.recs || !g.cigar ||
+      !g.cscr || !g.bad || !g.status || !g.f64 || !g.pos || !g.ids || !g.tk0 || !g.tk1 ||
+      !g.ccap || !g.coff || !g.counts || !g.ranges || !g.len64 || !g.cig_off_final ||
+      !g.tb_sort_tmp || !g.scan_tmp)
+    return fail(SWX_ENOMEM, "device pool exhausted (graph)");
+  return SWX_OK;
+}
+
 int internal_fail(int code, const char *msg) { return fail(code, msg); }
 hipStream_t internal_stream(swx_ctx *ctx) { return ctx->stream; }
 int internal_device(const swx_ctx *ctx) { return ctx->device; }
@@ -1187,6 +1550,176 @@ int swx_align(const swx_profile *p, const int8_t *ref, int64_t rlen, uint32_t fl
     memcpy(out->cigar, cig.data() + rec.cigar_off, sizeof(uint32_t) * rec.cigar_len);
   }
   out->rec.cigar_off = 0;
+  return SWX_OK;
+}
+
+}  // extern "C"
+
+// ---- graph mode ---------------------------------------------------------------
+struct swx_graph {
+  swx_ctx *ctx = nullptr;
+  swx::GraphState g;
+};
+
+extern "C" {
+
+int swx_graph_create(swx_ctx *ctx, const swx_graph_cfg *cfg, swx_graph **out, swx_graph_io *io) {
+  if (!ctx || !cfg || !out || !io) return fail(SWX_EINVAL, "null argument");
+  *out = nullptr;
+  if (cfg->max_pairs < 1 || cfg->max_qlen < 1 || cfg->max_rlen < 0 || cfg->qcat_cap < 0 ||
+      cfg->rcat_cap < 0 || cfg->nq_cap < 1 || cfg->nr_cap < 1 || (cfg->flags & ~SWX_ALL))
+    return fail(SWX_EINVAL, "bad graph capacities or flags");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(SWX_EDEVICE, "hipSetDevice failed");
+  swx_graph *gr = new (std::nothrow) swx_graph();
+  if (!gr) return fail(SWX_ENOMEM, "host allocation failed");
+  gr->ctx = ctx;
+  GraphState &g = gr->g;
+  g.cfg = *cfg;
+  g.matrix.assign(cfg->matrix, cfg->matrix + (size_t)cfg->n * cfg->n);
+  g.cfg.matrix = g.matrix.data();
+  int rc = make_scoring(g.matrix.data(), cfg->n, cfg->gap_open, cfg->gap_extend, &g.sc);
+  if (rc) { delete gr; return rc; }
+  g.B = cfg->max_pairs;
+  g.QM = cfg->max_qlen;
+  g.RM = cfg->max_rlen;
+  const int64_t bound = (int64_t)std::max(g.sc.smax, 0) * std::min<int64_t>(g.QM, g.RM);
+  if (bound >= (1 << 26) - 1) { delete gr; return fail(SWX_EOVERFLOW, "scores could exceed the lane range"); }
+  g.clamp = bound > kInter16Limit - 1;
+  g.need32 = bound >= kInter16Limit;
+  int8_t *dmat = g.A.get<int8_t>((int64_t)g.sc.n * g.sc.n);
+  if (!dmat) { delete gr; return fail(SWX_ENOMEM, "device pool exhausted"); }
+  if (hipMemcpy(dmat, g.matrix.data(), (size_t)g.sc.n * g.sc.n, hipMemcpyHostToDevice) != hipSuccess) {
+    delete gr;
+    return fail(SWX_EDEVICE, "could not upload the matrix");
+  }
+  g.sc.dmat = dmat;
+  if ((rc = graph_alloc(g))) { delete gr; return rc; }
+  // valid empty contents: every code 0, every offset 0, every pair (0, 0)
+  hipStream_t st = ctx->stream;
+  bool ok = fill_u8(g.cfg.qcat_cap, (uint8_t *)g.qcat, 0, st) == hipSuccess &&
+            fill_u8(g.cfg.rcat_cap, (uint8_t *)g.rcat, 0, st) == hipSuccess &&
+            fill_i64(g.cfg.nq_cap + 1, g.qoff, 0, st) == hipSuccess &&
+            fill_i64(g.cfg.nr_cap + 1, g.roff, 0, st) == hipSuccess &&
+            fill_i64(g.B, g.pair_q, 0, st) == hipSuccess && fill_i64(g.B, g.pair_r, 0, st) == hipSuccess &&
+            hipStreamSynchronize(st) == hipSuccess;
+  if (!ok) { delete gr; return fail(SWX_EDEVICE, "could not clear the graph buffers"); }
+  // capture the whole chain once
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    delete gr;
+    return fail(SWX_EDEVICE, "could not begin stream capture");
+  }
+  rc = fixed_issue(g, st);
+  hipGraph_t graph = nullptr;
+  const hipError_t ce = hipStreamEndCapture(st, &graph);
+  if (rc != SWX_OK || ce != hipSuccess || !graph) {
+    if (graph) hipGraphDestroy(graph);
+    delete gr;
+    return rc != SWX_OK ? rc : fail(SWX_EDEVICE, "stream capture failed");
+  }
+  g.graph = graph;
+  if (hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(graph);
+    delete gr;
+    return fail(SWX_EDEVICE, "could not instantiate the graph");
+  }
+  io->qcat = g.qcat; io->qoff = g.qoff; io->rcat = g.rcat; io->roff = g.roff;
+  io->pair_q = g.pair_q; io->pair_r = g.pair_r;
+  io->recs = (swx_rec *)g.recs;
+  io->cigar = g.cigar;
+  io->cigar_cap = g.cigar_cap;
+  *out = gr;
+  return SWX_OK;
+}
+
+static int graph_check(swx_graph *gr) {
+  GraphState &g = gr->g;
+  uint32_t bad = 0;
+  int64_t nerr = 0;
+  if (hipMemcpy(&bad, g.bad, 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&nerr, g.status, 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(SWX_EDEVICE, "could not read the graph status");
+  if (bad & 1u) return fail(SWX_EINVAL, "offsets must be non-decreasing and within the code arrays");
+  if (bad & 2u) return fail(SWX_EINVAL, "pair index out of range");
+  if (bad & 12u) return fail(SWX_EINVAL, "symbol code outside [0, n)");
+  if (nerr) return fail(SWX_EINTERNAL, "internal consistency check failed");
+  return SWX_OK;
+}
+
+int swx_graph_run(swx_graph *gr) {
+  if (!gr) return fail(SWX_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(gr->ctx->mu);
+  if (hipSetDevice(gr->ctx->device) != hipSuccess) return fail(SWX_EDEVICE, "hipSetDevice failed");
+  HIP_TRY(hipGraphLaunch(gr->g.exec, gr->ctx->stream));
+  HIP_TRY(hipStreamSynchronize(gr->ctx->stream));
+  return graph_check(gr);
+}
+
+int swx_graph_run_eager(swx_graph *gr) {
+  if (!gr) return fail(SWX_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(gr->ctx->mu);
+  if (hipSetDevice(gr->ctx->device) != hipSuccess) return fail(SWX_EDEVICE, "hipSetDevice failed");
+  int rc = fixed_issue(gr->g, gr->ctx->stream);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(gr->ctx->stream));
+  return graph_check(gr);
+}
+
+int swx_graph_load(swx_graph *gr, const swx_batch *b) {
+  if (!gr || !b) return fail(SWX_EINVAL, "null argument");
+  GraphState &g = gr->g;
+  if (b->in_mem != SWX_MEM_HOST) return fail(SWX_EINVAL, "swx_graph_load takes host memory");
+  if (b->npairs < 0 || b->npairs > g.B || b->nq < 1 || b->nq > g.cfg.nq_cap ||
+      b->nr < 0 || b->nr + 1 > g.cfg.nr_cap || b->qcat_len > g.cfg.qcat_cap ||
+      b->rcat_len > g.cfg.rcat_cap || !b->qoff || !b->roff ||
+      (b->npairs && (!b->pair_q || !b->pair_r)) || (b->qcat_len && !b->qcat) ||
+      (b->rcat_len && !b->rcat))
+    return fail(SWX_EINVAL, "batch does not fit the graph's capacities");
+  // offsets padded with their last value; pair slots past npairs take the
+  // empty reference nr (roff[nr] == roff[nr + 1])
+  std::vector<int64_t> qo(g.cfg.nq_cap + 1), ro(g.cfg.nr_cap + 1), pq(g.B, 0), pr(g.B, b->nr);
+  for (int64_t k = 0; k <= g.cfg.nq_cap; ++k) qo[k] = b->qoff[std::min(k, b->nq)];
+  for (int64_t k = 0; k <= g.cfg.nr_cap; ++k) ro[k] = b->roff[std::min(k, b->nr)];
+  for (int64_t k = 0; k < b->npairs; ++k) { pq[k] = b->pair_q[k]; pr[k] = b->pair_r[k]; }
+  std::lock_guard<std::mutex> lk(gr->ctx->mu);
+  hipStream_t st = gr->ctx->stream;
+  if (b->qcat_len) HIP_TRY(hipMemcpyAsync(g.qcat, b->qcat, b->qcat_len, hipMemcpyHostToDevice, st));
+  if (b->rcat_len) HIP_TRY(hipMemcpyAsync(g.rcat, b->rcat, b->rcat_len, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(g.qoff, qo.data(), 8 * qo.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(g.roff, ro.data(), 8 * ro.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(g.pair_q, pq.data(), 8 * pq.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(g.pair_r, pr.data(), 8 * pr.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return SWX_OK;
+}
+
+int swx_graph_read(swx_graph *gr, int64_t npairs, swx_batch_out *out) {
+  if (!gr || !out || npairs < 0 || npairs > gr->g.B || (npairs && !out->recs))
+    return fail(SWX_EINVAL, "bad arguments");
+  GraphState &g = gr->g;
+  std::lock_guard<std::mutex> lk(gr->ctx->mu);
+  if (npairs == 0) { out->cigar_used = 0; return SWX_OK; }
+  HIP_TRY(hipMemcpy(out->recs, g.recs, sizeof(swx_rec) * npairs, hipMemcpyDeviceToHost));
+  int64_t used = 0;
+  for (int64_t k = 0; k < npairs; ++k)
+    used = std::max<int64_t>(used, out->recs[k].cigar_off + out->recs[k].cigar_len);
+  out->cigar_used = used;
+  if (used > out->cigar_cap || (used && !out->cigar)) return fail(SWX_ERANGE, "CIGAR arena too small");
+  if (used) HIP_TRY(hipMemcpy(out->cigar, g.cigar, sizeof(uint32_t) * used, hipMemcpyDeviceToHost));
+  return SWX_OK;
+}
+
+int swx_graph_destroy(swx_graph *gr) {
+  if (!gr) return fail(SWX_EINVAL, "null argument");
+  {
+    std::lock_guard<std::mutex> lk(gr->ctx->mu);
+    (void)hipSetDevice(gr->ctx->device);
+    (void)hipStreamSynchronize(gr->ctx->stream);
+    if (gr->g.exec) (void)hipGraphExecDestroy(gr->g.exec);
+    if (gr->g.graph) (void)hipGraphDestroy(gr->g.graph);
+    gr->g.A.release();
+  }
+  delete gr;
   return SWX_OK;
 }
 

@@ -153,6 +153,7 @@ struct TbArgs {
   const int64_t *cig_off;
   int32_t *cig_len;
   uint8_t *err;
+  int64_t wave_cells;    // wide bands with more cells go to the wave-parallel kernel
 };
 
 hipError_t tb_classify(const TbArgs &a, int64_t npairs, uint8_t *cls, uint64_t *key, int64_t *vals,
@@ -160,6 +161,12 @@ hipError_t tb_classify(const TbArgs &a, int64_t npairs, uint8_t *cls, uint64_t *
 hipError_t tb_tasks(int64_t n0, int64_t n1, const int64_t *sorted, const TbArgs &a, int32_t bw,
                     TbTask *tasks, int64_t *dir_words, hipStream_t st);
 hipError_t tb_offsets(int64_t ntasks, TbTask *tasks, const int64_t *off, hipStream_t st);
+hipError_t tb_tasks_range(const int64_t *range, int64_t ntasks_cap, const int64_t *sorted,
+                          const TbArgs &a, int32_t bw, TbTask *tasks, int64_t *dir_words,
+                          hipStream_t st);
+hipError_t tbw_tasks_range(const int64_t *range, int64_t ntasks_cap, const int64_t *sorted,
+                           const TbArgs &a, TbwTask *tasks, int64_t *dir_words, int64_t *bnd_words,
+                           hipStream_t st);
 hipError_t tb_band(const TbArgs &a, const TbTask *tasks, int64_t ntasks, const int64_t *sorted,
                    int32_t bw, hipStream_t st);
 hipError_t tbw_tasks(int64_t n0, int64_t n1, const int64_t *sorted, const TbArgs &a,
@@ -172,6 +179,9 @@ hipError_t tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, int wa
                    int32_t *bnd, hipStream_t st);
 int tb_wave_waves(int64_t m, int n);   // waves per workgroup for a pair of m rows
 int tb_wave_max_strips();
+hipError_t fill_u8(int64_t n, uint8_t *p, uint8_t v, hipStream_t st);
+hipError_t fill_i64(int64_t n, int64_t *p, int64_t v, hipStream_t st);
+hipError_t class_ranges(const int64_t *counts, int64_t *ranges, hipStream_t st);
 hipError_t count_classes(int64_t n, const uint8_t *cls, int64_t *counts, hipStream_t st);
 hipError_t sort_keys(int64_t n, uint64_t *keys, uint64_t *keys_alt, int64_t *vals,
                      int64_t *vals_alt, void *tmp, size_t *tmp_bytes, int64_t **sorted_out,
@@ -227,6 +237,8 @@ hipError_t launch_pair_stats(int64_t n, const int32_t *qlen, const int64_t *rlen
                              hipStream_t st);
 hipError_t lens_to_i64(int64_t n, const int32_t *len, int64_t *out, hipStream_t st);
 hipError_t mark_lanes(int64_t n, const int64_t *ids, uint8_t *lanebits, int v, hipStream_t st);
+hipError_t mark_lanes_dev(int64_t cap, const int64_t *n_dev, const int64_t *ids, uint8_t *lanebits,
+                          int v, hipStream_t st);
 hipError_t launch_any_flag(int64_t n, const uint8_t *flag, int64_t *count, hipStream_t st);
 hipError_t launch_views(int64_t npairs, const int64_t *qoff, const int64_t *roff,
                         const int64_t *pair_q, const int64_t *pair_r, int64_t *qstart,
@@ -259,11 +271,11 @@ hipError_t launch_begins(int64_t npairs, const int32_t *score1, const int32_t *q
                          const int64_t *rend, const int32_t *rscore, const int32_t *rqend,
                          const int64_t *rrend, int32_t *qbeg, int64_t *rbeg, uint8_t *err,
                          hipStream_t st);
-hipError_t plan_sort(int64_t n, const int64_t *ids, const int32_t *qlen, const int64_t *rlen,
+hipError_t plan_sort(int64_t n, const int64_t *n_dev, const int64_t *ids, const int32_t *qlen, const int64_t *rlen,
                      const int32_t *band, int32_t R, uint64_t *keys, uint64_t *keys_alt,
                      int64_t *vals, int64_t *vals_alt, void *tmp, size_t *tmp_bytes,
                      int64_t **sorted_out, hipStream_t st);
-hipError_t plan_tasks_dev(int64_t n, int64_t ntasks, int32_t slots, int32_t R,
+hipError_t plan_tasks_dev(int64_t n, const int64_t *n_dev, int64_t ntasks, int32_t slots, int32_t R,
                           int64_t qdata_per_row, const int64_t *sorted, const int32_t *qlen,
                           const int64_t *rlen, const int32_t *band, InterTask *tasks,
                           int64_t *bnd_size, int64_t *qdata_size, hipStream_t st);

@@ -46,7 +46,7 @@ __global__ void k_tb_classify(TbArgs a, int64_t npairs, uint8_t *cls, uint64_t *
       safe_band(m, w, a.score[p], a.smax, a.o, a.e, &dlo, &bw);
       // bands wider than 32 go to the strip kernel (a 64-wide band in one
       // lane's registers spills and leaves too few waves)
-      c = bw <= 8 ? 1 : bw <= 16 ? 2 : bw <= 32 ? 3 : (m * bw > kWaveTbCells ? 6 : 5);
+      c = bw <= 8 ? 1 : bw <= 16 ? 2 : bw <= 32 ? 3 : (m * bw > a.wave_cells ? 6 : 5);
     } else {
       a.err[p] = 1;
     }
@@ -57,12 +57,20 @@ __global__ void k_tb_classify(TbArgs a, int64_t npairs, uint8_t *cls, uint64_t *
   ccap[p] = (c != 0) ? (m + w + 2) : 0;
 }
 
-__global__ void k_tb_tasks(int64_t n0, int64_t n1, const int64_t *sorted, const TbArgs a,
-                           int32_t bw, TbTask *tasks, int64_t *dir_words) {
-  // tasks over sorted[n0 .. n1)
+// tasks over sorted[n0 .. n1); with range (device) the bounds are read there
+// and every task slot up to ntasks_cap is written (empty past the range)
+__global__ void k_tb_tasks(int64_t n0, int64_t n1, const int64_t *range, int64_t ntasks_cap,
+                           const int64_t *sorted, const TbArgs a, int32_t bw, TbTask *tasks,
+                           int64_t *dir_words) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (range) { n0 = range[0]; n1 = range[1]; }
   const int64_t ntasks = (n1 - n0 + 63) / 64;
-  if (t >= ntasks) return;
+  if (t >= (range ? ntasks_cap : ntasks)) return;
+  if (t >= ntasks) {
+    tasks[t] = TbTask{};
+    dir_words[t] = 0;
+    return;
+  }
   const int64_t s0 = n0 + t * 64;
   const int64_t s1 = (s0 + 64 < n1) ? s0 + 64 : n1;
   int64_t rows = 1;
@@ -103,6 +111,7 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
   const int64_t tid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (tid >= ntasks) return;
   const TbTask tk = tasks[tid];
+  if (tk.nslots == 0) return;
   const bool live = lane < tk.nslots;
   const int64_t p = live ? sorted[tk.slot_base + lane] : -1;
   int64_t m = 1, w = 1, dlo = 0, bwl = 1;
@@ -125,7 +134,8 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
   // base + k (1-based columns j use symbol r[j-1]); row i covers j = i+dlo+k
   auto ref_byte = [&](int64_t j) -> uint32_t {   // symbol code of column j (1-based)
     if (!live || j < 1 || j > w) return 0u;
-    const uint32_t v = (uint32_t)(uint8_t)r[j - 1];
+    const int32_t c = r[j - 1];
+    const uint32_t v = (c >= 0 && c < a.n) ? (uint32_t)c : 0u;   // a bad code never indexes a table
     return LUT4 ? v * 8u : v;
   };
   uint32_t win[NW];
@@ -171,7 +181,8 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
       const int64_t i = i0 + u;
-      qo[u] = (live && i <= m) ? (uint32_t)(uint8_t)q[i - 1] : 0xFFu;
+      const int32_t c = (live && i <= m) ? (int32_t)q[i - 1] : -1;
+      qo[u] = (c >= 0 && c < a.n) ? (uint32_t)c : 0xFFu;
       no[u] = ref_byte(i + 1 + dlo + 4 * NW - 1);
     }
   };
@@ -309,8 +320,17 @@ hipError_t tb_tasks(int64_t n0, int64_t n1, const int64_t *sorted, const TbArgs 
                     TbTask *tasks, int64_t *dir_words, hipStream_t st) {
   const int64_t nt = (n1 - n0 + 63) / 64;
   if (nt <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tb_tasks, dim3(nblk(nt, 128)), dim3(128), 0, st, n0, n1, sorted, a, bw,
-                     tasks, dir_words);
+  hipLaunchKernelGGL(k_tb_tasks, dim3(nblk(nt, 128)), dim3(128), 0, st, n0, n1,
+                     (const int64_t *)nullptr, (int64_t)0, sorted, a, bw, tasks, dir_words);
+  return hipGetLastError();
+}
+
+hipError_t tb_tasks_range(const int64_t *range, int64_t ntasks_cap, const int64_t *sorted,
+                          const TbArgs &a, int32_t bw, TbTask *tasks, int64_t *dir_words,
+                          hipStream_t st) {
+  if (ntasks_cap <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tb_tasks, dim3(nblk(ntasks_cap, 128)), dim3(128), 0, st, (int64_t)0,
+                     (int64_t)0, range, ntasks_cap, sorted, a, bw, tasks, dir_words);
   return hipGetLastError();
 }
 
@@ -356,11 +376,19 @@ namespace {
 constexpr int kStripR = 16;
 }
 
-__global__ void k_tbw_tasks(int64_t n0, int64_t n1, const int64_t *sorted, const TbArgs a,
-                            TbwTask *tasks, int64_t *dir_words, int64_t *bnd_words) {
+__global__ void k_tbw_tasks(int64_t n0, int64_t n1, const int64_t *range, int64_t ntasks_cap,
+                            const int64_t *sorted, const TbArgs a, TbwTask *tasks,
+                            int64_t *dir_words, int64_t *bnd_words) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (range) { n0 = range[0]; n1 = range[1]; }
   const int64_t ntasks = (n1 - n0 + 63) / 64;
-  if (t >= ntasks) return;
+  if (t >= (range ? ntasks_cap : ntasks)) return;
+  if (t >= ntasks) {
+    tasks[t] = TbwTask{};
+    dir_words[t] = 0;
+    bnd_words[t] = 0;
+    return;
+  }
   const int64_t s0 = n0 + t * 64;
   const int64_t s1 = (s0 + 64 < n1) ? s0 + 64 : n1;
   int64_t rows = 1, wmax = 1, dlo_min = 0, dhi_max = 0;
@@ -406,6 +434,7 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
   const int64_t tid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (tid >= ntasks) return;
   const TbwTask tk = tasks[tid];
+  if (tk.nslots == 0) return;
   const bool live = lane < tk.nslots;
   const int64_t p = live ? sorted[tk.slot_base + lane] : -1;
   int64_t m = 1, w = 1, dlo = 0, bwl = 1;
@@ -452,8 +481,8 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
       const int64_t i = sR + 1 + k;
       lut[k] = 0;
       qn[k] = 0;
-      if (live && i <= m) {
-        const int32_t qs = q[i - 1];
+      const int32_t qs = (live && i <= m) ? (int32_t)q[i - 1] : -1;
+      if (qs >= 0 && qs < a.n) {   // a bad code never indexes a table
         if (LUT4) {
           uint32_t l = 0;
           for (int b = 0; b < a.n; ++b) l |= (uint32_t)(uint8_t)s_mat[qs * a.n + b] << (8 * b);
@@ -472,7 +501,8 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
       const bool inprev = j >= plo && j < phi;
       h = inprev ? bH[j * 64 + lane] : kNeg;
       f = inprev ? bF[j * 64 + lane] : kNeg;
-      sy = (live && j >= 1 && j <= w) ? (uint32_t)(uint8_t)r[j - 1] : 0u;
+      const int32_t c = (live && j >= 1 && j <= w) ? (int32_t)r[j - 1] : -1;
+      sy = (c >= 0 && c < a.n) ? (uint32_t)c : 0u;
     };
     int32_t n_h = kNeg, n_f = kNeg;
     uint32_t n_sy = 0;
@@ -895,8 +925,17 @@ hipError_t tbw_tasks(int64_t n0, int64_t n1, const int64_t *sorted, const TbArgs
                      TbwTask *tasks, int64_t *dir_words, int64_t *bnd_words, hipStream_t st) {
   const int64_t nt = (n1 - n0 + 63) / 64;
   if (nt <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tbw_tasks, dim3(nblk(nt, 128)), dim3(128), 0, st, n0, n1, sorted, a, tasks,
-                     dir_words, bnd_words);
+  hipLaunchKernelGGL(k_tbw_tasks, dim3(nblk(nt, 128)), dim3(128), 0, st, n0, n1,
+                     (const int64_t *)nullptr, (int64_t)0, sorted, a, tasks, dir_words, bnd_words);
+  return hipGetLastError();
+}
+
+hipError_t tbw_tasks_range(const int64_t *range, int64_t ntasks_cap, const int64_t *sorted,
+                           const TbArgs &a, TbwTask *tasks, int64_t *dir_words, int64_t *bnd_words,
+                           hipStream_t st) {
+  if (ntasks_cap <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tbw_tasks, dim3(nblk(ntasks_cap, 128)), dim3(128), 0, st, (int64_t)0,
+                     (int64_t)0, range, ntasks_cap, sorted, a, tasks, dir_words, bnd_words);
   return hipGetLastError();
 }
 

@@ -1,0 +1,131 @@
+"""GPU tests of graph mode: the batched path captured once as a hipGraph and
+replayed.  Every replay (with other eager work of the program and
+synchronisations between replays) must equal the same chain issued eagerly
+and the oracle, bit for bit, and new batch contents loaded into the graph's
+buffers must give new, correct results."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1208_6350_amd as swx
+import workloads as W
+from tests.test_gpu_parity import FIELDS
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _graph_for(ctx, b, max_pairs, max_qlen, max_rlen, extra=1.2):
+    return swx.Graph(ctx, b.matrix, b.gap_open, b.gap_extend, max_pairs=max_pairs,
+                     max_qlen=max_qlen, max_rlen=max_rlen, qcat_cap=int(len(b.qcat) * extra) + 64,
+                     rcat_cap=int(len(b.rcat) * extra) + 64, nq_cap=max_pairs + 1,
+                     nr_cap=max_pairs + 2)
+
+
+def _check_oracle(b, recs, cig):
+    ref, rcig, rcoff = oracle.align_many(b.qcat, b.qoff, b.rcat, b.roff, b.pair_q, b.pair_r,
+                                         b.matrix, b.gap_open, b.gap_extend)
+    for k, f in enumerate(FIELDS):
+        bad = np.nonzero(recs[f].astype(np.int64) != ref[:, k])[0]
+        assert len(bad) == 0, f"{f}: pair {bad[0]} gpu {recs[f][bad[0]]} oracle {ref[bad[0], k]}"
+    for p in range(b.npairs):
+        g = cig[recs["cigar_off"][p]:recs["cigar_off"][p] + recs["cigar_len"][p]]
+        assert np.array_equal(g, rcig[rcoff[p]:rcoff[p] + ref[p, 7]]), p
+
+
+@pytest.fixture()
+def ctx():
+    c = swx.Context(0)
+    yield c
+    c.close()
+
+
+def test_graph_replays_equal_eager_and_oracle(ctx):
+    a = W.random_pairs(901, 300, (1, 150), (0, 500))
+    other = W.random_pairs(902, 80, (1, 60), (0, 200))
+    g = _graph_for(ctx, a, max_pairs=384, max_qlen=160, max_rlen=520)
+    try:
+        g.load(a.qcat, a.qoff, a.rcat, a.roff, a.pair_q, a.pair_r)
+        g.run(eager=True)
+        recs_e, cig_e = g.read()
+        _check_oracle(a, recs_e, cig_e)
+        for k in range(3):
+            # the program's own eager work between replays
+            ctx.align_batch(other.matrix, other.gap_open, other.gap_extend, other.qcat, other.qoff,
+                            other.rcat, other.roff, other.pair_q, other.pair_r)
+            g.run()
+            recs_g, cig_g = g.read()
+            _say(f"[graph] replay {k}: {len(recs_g)} records")
+            assert recs_g.tobytes() == recs_e.tobytes(), f"replay {k} differs from eager"
+            assert np.array_equal(cig_g, cig_e), f"replay {k} CIGARs differ"
+        # new contents in the same buffers
+        b = W.random_pairs(903, 250, (1, 160), (0, 520))
+        g.load(b.qcat, b.qoff, b.rcat, b.roff, b.pair_q, b.pair_r)
+        g.run()
+        recs_b, cig_b = g.read()
+        _check_oracle(b, recs_b, cig_b)
+        # the same pairs through the ordinary batch call
+        recs_c, cig_c = ctx.align_batch(b.matrix, b.gap_open, b.gap_extend, b.qcat, b.qoff, b.rcat,
+                                        b.roff, b.pair_q, b.pair_r)
+        for f in FIELDS:
+            assert np.array_equal(recs_b[f], recs_c[f]), f
+    finally:
+        g.close()
+
+
+def test_graph_wide_lanes_and_protein(ctx):
+    """Scores past the 16-bit field (re-run on 32-bit lanes inside the graph)
+    and the general-alphabet profile."""
+    gen = np.random.Generator(np.random.PCG64(13))
+    mat = W.dna_matrix(8, -8)
+    qs, rs = [], []
+    for L in (250, 256, 258, 300, 40, 120):
+        ref = gen.integers(0, 4, size=L + 100).astype(np.int8)
+        qs.append(ref[50:50 + L].copy())
+        rs.append(ref)
+    b = W.from_lists("graph-threshold", mat, 10, 2, qs, rs)
+    g = _graph_for(ctx, b, max_pairs=8, max_qlen=300, max_rlen=400)
+    try:
+        g.load(b.qcat, b.qoff, b.rcat, b.roff, b.pair_q, b.pair_r)
+        for k in range(2):
+            g.run()
+            recs, cig = g.read()
+            _check_oracle(b, recs, cig)
+        assert set(recs["lane_bits"]) == {16, 32}
+    finally:
+        g.close()
+    p = W.random_pairs(904, 120, (1, 120), (1, 300), alphabet=24, o=11, e=1)
+    g = _graph_for(ctx, p, max_pairs=128, max_qlen=120, max_rlen=300)
+    try:
+        g.load(p.qcat, p.qoff, p.rcat, p.roff, p.pair_q, p.pair_r)
+        g.run()
+        recs, cig = g.read()
+        _check_oracle(p, recs, cig)
+    finally:
+        g.close()
+
+
+def test_graph_rejects_bad_contents(ctx):
+    a = W.random_pairs(905, 20, (3, 30), (3, 60))
+    g = _graph_for(ctx, a, max_pairs=32, max_qlen=40, max_rlen=80)
+    try:
+        bad = a.rcat.copy()
+        bad[3] = 9
+        g.load(a.qcat, a.qoff, bad, a.roff, a.pair_q, a.pair_r)
+        with pytest.raises(swx.SwxError) as ei:
+            g.run()
+        assert ei.value.status == -1
+        g.load(a.qcat, a.qoff, a.rcat, a.roff, a.pair_q, a.pair_r)
+        g.run()
+        recs, cig = g.read()
+        _check_oracle(a, recs, cig)
+    finally:
+        g.close()
