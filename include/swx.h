@@ -206,8 +206,8 @@ int swx_autotune(swx_ctx *ctx, const swx_batch *b, int64_t max_pairs, const char
  * max_rlen, offsets non-decreasing within the code arrays, codes in [0, n)
  * over the whole code arrays (create fills them with 0).  Violations of the
  * validated ones are reported by swx_graph_run as SWX_EINVAL; lengths above
- * the capacities are the caller's error.  All pairs take the batched path
- * (no intra-sequence routing).  Results equal swx_align_batch's.
+ * the capacities are the caller's error.  Every pair takes the route the
+ * configuration names.  Results equal swx_align_batch's.
  * Errors: SWX_EINVAL (capacities < 1, flags), SWX_EOVERFLOW (scores could
  * exceed the lanes), SWX_ENOMEM, SWX_EDEVICE. */
 typedef struct swx_graph swx_graph;
@@ -221,7 +221,13 @@ typedef struct {
   int64_t nq_cap, nr_cap;       /* numbers of queries / references (offsets hold cap + 1) */
   uint32_t flags;               /* SWX_BEGIN | SWX_CIGAR | SWX_SCORE2 */
   int32_t mask_len;
+  int32_t route;                /* SWX_ROUTE_BATCHED: one pair per 16-bit lane half (best for
+                                   many pairs); SWX_ROUTE_INTRA: every pair spread over a wave
+                                   (lowest latency for few pairs) */
+  int32_t pad2_;
 } swx_graph_cfg;
+#define SWX_ROUTE_BATCHED 0
+#define SWX_ROUTE_INTRA 1
 
 typedef struct {   /* device buffers owned by the graph (valid until swx_graph_destroy) */
   int8_t *qcat; int64_t *qoff; int8_t *rcat; int64_t *roff;   /* inputs, [cap], [cap + 1] */

@@ -96,7 +96,7 @@ class SwxGraphCfg(ctypes.Structure):
                 ("max_rlen", ctypes.c_int64), ("qcat_cap", ctypes.c_int64),
                 ("rcat_cap", ctypes.c_int64), ("nq_cap", ctypes.c_int64),
                 ("nr_cap", ctypes.c_int64), ("flags", ctypes.c_uint32),
-                ("mask_len", ctypes.c_int32)]
+                ("mask_len", ctypes.c_int32), ("route", ctypes.c_int32), ("pad2_", ctypes.c_int32)]
 
 
 class SwxGraphIo(ctypes.Structure):
@@ -408,12 +408,12 @@ class Graph:
     capacity (swx_graph_*): load a host batch, run (replay), read results."""
 
     def __init__(self, ctx: "Context", matrix, o, e, max_pairs, max_qlen, max_rlen, qcat_cap,
-                 rcat_cap, nq_cap, nr_cap, flags=SWX_ALL, mask_len=-1):
+                 rcat_cap, nq_cap, nr_cap, flags=SWX_ALL, mask_len=-1, route=0):
         self._m = np.ascontiguousarray(matrix, dtype=np.int8)
         cfg = SwxGraphCfg(matrix=self._m.ctypes.data, n=self._m.shape[0], gap_open=o,
                           gap_extend=e, max_pairs=max_pairs, max_qlen=max_qlen, pad_=0,
                           max_rlen=max_rlen, qcat_cap=qcat_cap, rcat_cap=rcat_cap, nq_cap=nq_cap,
-                          nr_cap=nr_cap, flags=flags, mask_len=mask_len)
+                          nr_cap=nr_cap, flags=flags, mask_len=mask_len, route=route, pad2_=0)
         h = ctypes.c_void_p()
         self.io = SwxGraphIo()
         _check(lib().swx_graph_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h),

@@ -425,6 +425,60 @@ __global__ __launch_bounds__(64) void k_intra_finish(IntraPairArgs a, int mode) 
   }
 }
 
+// ---- fixed-capacity (graph) jobs: one per pair, fixed strides -------------
+__global__ void k_intra_jobs_fixed(int64_t B, const int64_t *rlen, int32_t kbits, int32_t sh,
+                                   int64_t mc_stride, int64_t bnd_stride, IntraJob *jobs,
+                                   IntraPair *pairs) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= B) return;
+  IntraJob jb{};
+  jb.pair = k;
+  jb.cw = 0;
+  jb.c0 = 0;
+  jb.c1 = rlen[k];
+  jb.mc_off = k * mc_stride;
+  jb.bnd_off = k * bnd_stride;
+  jb.kbits = kbits;
+  jb.band = -1;
+  jobs[k] = jb;
+  pairs[k] = IntraPair{k, k * mc_stride, kbits, sh};
+}
+
+__global__ void k_intra_rev_jobs_fixed(int64_t B, const int32_t *score, const int64_t *rend,
+                                       const int32_t *band, int32_t kbits, int64_t bnd_stride,
+                                       IntraJob *jobs) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= B) return;
+  IntraJob jb{};
+  jb.pair = k;
+  jb.cw = 0;
+  jb.c0 = 0;
+  jb.c1 = score[k] > 0 ? rend[k] + 1 : 0;
+  jb.mc_off = 0;
+  jb.bnd_off = k * bnd_stride;
+  jb.kbits = kbits;
+  jb.band = band[k];
+  jobs[k] = jb;
+}
+
+hipError_t intra_jobs_fixed(int64_t B, const int64_t *rlen, int32_t kbits, int32_t sh,
+                            int64_t mc_stride, int64_t bnd_stride, IntraJob *jobs, IntraPair *pairs,
+                            hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_intra_jobs_fixed, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, B, rlen,
+                     kbits, sh, mc_stride, bnd_stride, jobs, pairs);
+  return hipGetLastError();
+}
+
+hipError_t intra_rev_jobs_fixed(int64_t B, const int32_t *score, const int64_t *rend,
+                                const int32_t *band, int32_t kbits, int64_t bnd_stride,
+                                IntraJob *jobs, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_intra_rev_jobs_fixed, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, B,
+                     score, rend, band, kbits, bnd_stride, jobs);
+  return hipGetLastError();
+}
+
 // ---- launchers ----------------------------------------------------------------
 size_t intra_lds_bytes(int n, int RL) { return (size_t)(n + 1) * 64 * RL; }
 

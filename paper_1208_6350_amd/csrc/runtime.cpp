@@ -1000,6 +1000,16 @@ struct GraphState {
   size_t tb_sort_bytes = 0;
   FixedTb tb[6];
   uint32_t *cscr = nullptr;
+  // intra route: every pair spread over a wave (one job per pair)
+  bool intra = false;
+  int RL = 16, waves = 1;
+  int32_t kbits = 1, sh = 1024;
+  int64_t bnd_stride = 0;
+  IntraJob *jobs = nullptr, *rjobs = nullptr;
+  IntraPair *ipairs = nullptr;
+  uint32_t *maxcol = nullptr, *ibnd = nullptr;
+  int32_t *part_v = nullptr;
+  int64_t *part_j = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -1108,10 +1118,25 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
   HIP_TRY(launch_views(B, g.qoff, g.roff, g.pair_q, g.pair_r, g.qstart, g.qlen, g.rstart, g.rlen, st));
   PairView fview{g.qstart, g.rstart, g.qlen, g.rlen, g.qcat, g.rcat, 0};
   FillOut fout{g.score, g.qend, g.rend, g.ovf};
-  if ((rc = fixed_fill(g, g.p16, nullptr, nullptr, g.qlen, g.rlen, nullptr, fview, false, nullptr,
-                       fout, st)))
+  IntraArgs ia{};
+  if (g.intra) {
+    HIP_TRY(fill_u8(4 * B * g.RM, (uint8_t *)g.maxcol, 0, st));
+    HIP_TRY(intra_jobs_fixed(B, g.rlen, g.kbits, g.sh, g.RM, g.bnd_stride, g.jobs, g.ipairs, st));
+    ia.jobs = g.jobs; ia.njobs = B; ia.view = fview; ia.matrix = g.sc.dmat;
+    ia.n = g.sc.n; ia.o = g.sc.o; ia.e = g.sc.e; ia.bias = g.sc.bias;
+    ia.maxcol = g.maxcol; ia.bnd = g.ibnd; ia.err = g.err;
+    HIP_TRY(intra_fill(ia, g.RL, g.waves, false, st));
+    IntraPairArgs e{};
+    e.pairs = g.ipairs; e.maxcol = g.maxcol; e.qlen = g.qlen; e.rlen = g.rlen;
+    e.score = g.score; e.qend = g.qend; e.rend = g.rend; e.overflow = g.ovf;
+    e.part_v = g.part_v; e.part_j = g.part_j;
+    HIP_TRY(intra_end(e, B, st));
+    HIP_TRY(fill_u8(B, g.lanebits, 32, st));
+  } else if ((rc = fixed_fill(g, g.p16, nullptr, nullptr, g.qlen, g.rlen, nullptr, fview, false,
+                              nullptr, fout, st))) {
     return rc;
-  if (g.need32) {
+  }
+  if (g.need32 && !g.intra) {
     const int64_t *nw = nullptr;
     if ((rc = fixed_select(g, g.ovf, &nw, st))) return rc;
     if ((rc = fixed_fill(g, g.p32, g.ids, nw, g.qlen, g.rlen, nullptr, fview, false, nullptr, fout,
@@ -1127,11 +1152,22 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
     HIP_TRY(fill_u8(4 * B, (uint8_t *)g.rsc, 0, st));
     PairView rview{g.rqs, g.rrs, g.rql, g.rrl, g.qcat, g.rcat, 1};
     FillOut rout{g.rsc, g.rqe, g.rre, g.rov};
+    if (g.intra) {
+      HIP_TRY(intra_rev_jobs_fixed(B, g.score, g.rend, g.band, g.kbits, g.bnd_stride, g.rjobs, st));
+      IntraArgs ra = ia;
+      ra.jobs = g.rjobs;
+      ra.view = rview;
+      ra.maxcol = nullptr;
+      ra.target = g.tgt;
+      ra.out = rout;
+      HIP_TRY(intra_fill(ra, g.RL, g.waves, true, st));
+    }
     const int64_t *n16 = nullptr;
-    if ((rc = fixed_select(g, g.f16, &n16, st))) return rc;
-    if ((rc = fixed_fill(g, g.r16, g.ids, n16, g.rql, g.rrl, g.band, rview, true, g.tgt, rout, st)))
+    if (!g.intra && (rc = fixed_select(g, g.f16, &n16, st))) return rc;
+    if (!g.intra && (rc = fixed_fill(g, g.r16, g.ids, n16, g.rql, g.rrl, g.band, rview, true,
+                                     g.tgt, rout, st)))
       return rc;
-    if (g.need32) {
+    if (g.need32 && !g.intra) {
       const int64_t *n32 = nullptr;
       if ((rc = fixed_select(g, g.f32, &n32, st))) return rc;
       if ((rc = fixed_fill(g, g.r32, g.ids, n32, g.rql, g.rrl, g.band, rview, true, g.tgt, rout,
@@ -1190,7 +1226,14 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
     if ((rc = fixed_scan(g, g.len64, g.cig_off_final, B + 1, st))) return rc;
     HIP_TRY(launch_cigar_compact(B, g.cscr, g.coff, g.cig_len, g.cig_off_final, g.cigar, st));
   }
-  if (flags & SWX_SCORE2) {
+  if ((flags & SWX_SCORE2) && g.intra) {
+    IntraPairArgs e{};
+    e.pairs = g.ipairs; e.maxcol = g.maxcol; e.qlen = g.qlen; e.rlen = g.rlen;
+    e.score = g.score; e.qend = g.qend; e.rend = g.rend; e.rbeg = g.rbeg;
+    e.mask_len = g.cfg.mask_len; e.score2 = g.score2; e.rend2 = g.rend2;
+    e.part_v = g.part_v; e.part_j = g.part_j;
+    HIP_TRY(intra_score2(e, B, st));
+  } else if (flags & SWX_SCORE2) {
     Score2InterArgs s2{};
     s2.rlen = g.rlen; s2.qlen = g.qlen; s2.score1 = g.score; s2.rbeg = g.rbeg; s2.rend = g.rend;
     s2.mask_len = g.cfg.mask_len; s2.score2 = g.score2; s2.rend2 = g.rend2;
@@ -1244,10 +1287,33 @@ static int graph_alloc(GraphState &g) {
   g.len64 = A.get<int64_t>(B + 1);
   g.cig_off_final = A.get<int64_t>(B + 1);
   int rc;
-  const int R = (g.sc.qsel ? 32 : 32);
-  if ((rc = fixed_plan_alloc(g, g.p16, 16, R))) return rc;
-  if ((rc = fixed_plan_alloc(g, g.r16, 16, R))) return rc;
-  if (g.need32) {
+  const int R = 32;
+  if (g.intra) {
+    g.RL = pick_rl(g.QM, g.sc.n);
+    g.sh = 64 * g.RL;
+    const int64_t qp = (g.QM + g.sh - 1) / g.sh * g.sh;
+    const int64_t nstrips = qp / g.sh;
+    if (nstrips > intra_max_strips()) return fail(SWX_EINVAL, "max_qlen too long for the intra route");
+    g.kbits = code_bits(qp);
+    const int64_t bound = (int64_t)std::max(g.sc.smax, 0) * std::min<int64_t>(g.QM, g.RM);
+    if (g.kbits > 30 || bound >= (int64_t(1) << (32 - g.kbits)))
+      return fail(SWX_EOVERFLOW, "score range and query length exceed the max-array word");
+    g.waves = intra_waves(nstrips, g.sc.n, g.RL);
+    g.bnd_stride = 2 * (nstrips - 1) * g.RM;
+    g.jobs = A.get<IntraJob>(B);
+    g.rjobs = A.get<IntraJob>(B);
+    g.ipairs = A.get<IntraPair>(B);
+    g.maxcol = A.get<uint32_t>(B * std::max<int64_t>(g.RM, 1));
+    g.ibnd = A.get<uint32_t>(std::max<int64_t>(B * g.bnd_stride, 1));
+    g.part_v = A.get<int32_t>(B * intra_slices());
+    g.part_j = A.get<int64_t>(B * intra_slices());
+    if (!g.jobs || !g.rjobs || !g.ipairs || !g.maxcol || !g.ibnd || !g.part_v || !g.part_j)
+      return fail(SWX_ENOMEM, "device pool exhausted (graph intra route)");
+  } else {
+    if ((rc = fixed_plan_alloc(g, g.p16, 16, R))) return rc;
+    if ((rc = fixed_plan_alloc(g, g.r16, 16, R))) return rc;
+  }
+  if (g.need32 && !g.intra) {
     if ((rc = fixed_plan_alloc(g, g.p32, 32, R))) return rc;
     if ((rc = fixed_plan_alloc(g, g.r32, 32, R))) return rc;
   }
@@ -1587,6 +1653,7 @@ int swx_graph_create(swx_ctx *ctx, const swx_graph_cfg *cfg, swx_graph **out, sw
   if (bound >= (1 << 26) - 1) { delete gr; return fail(SWX_EOVERFLOW, "scores could exceed the lane range"); }
   g.clamp = bound > kInter16Limit - 1;
   g.need32 = bound >= kInter16Limit;
+  g.intra = cfg->route == SWX_ROUTE_INTRA;
   int8_t *dmat = g.A.get<int8_t>((int64_t)g.sc.n * g.sc.n);
   if (!dmat) { delete gr; return fail(SWX_ENOMEM, "device pool exhausted"); }
   if (hipMemcpy(dmat, g.matrix.data(), (size_t)g.sc.n * g.sc.n, hipMemcpyHostToDevice) != hipSuccess) {

@@ -220,6 +220,12 @@ int intra_slices();
 hipError_t intra_fill(const IntraArgs &a, int RL, int waves, bool rev, hipStream_t st);
 int intra_max_strips();
 int intra_max_waves();
+hipError_t intra_jobs_fixed(int64_t B, const int64_t *rlen, int32_t kbits, int32_t sh,
+                            int64_t mc_stride, int64_t bnd_stride, IntraJob *jobs, IntraPair *pairs,
+                            hipStream_t st);
+hipError_t intra_rev_jobs_fixed(int64_t B, const int32_t *score, const int64_t *rend,
+                                const int32_t *band, int32_t kbits, int64_t bnd_stride,
+                                IntraJob *jobs, hipStream_t st);
 size_t intra_static_lds();
 hipError_t intra_end(const IntraPairArgs &a, int64_t npairs, hipStream_t st);
 hipError_t intra_score2(const IntraPairArgs &a, int64_t npairs, hipStream_t st);

@@ -23,11 +23,14 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _graph_for(ctx, b, max_pairs, max_qlen, max_rlen, extra=1.2):
+def _graph_for(ctx, b, max_pairs, max_qlen, max_rlen, extra=1.2, route=0):
     return swx.Graph(ctx, b.matrix, b.gap_open, b.gap_extend, max_pairs=max_pairs,
                      max_qlen=max_qlen, max_rlen=max_rlen, qcat_cap=int(len(b.qcat) * extra) + 64,
                      rcat_cap=int(len(b.rcat) * extra) + 64, nq_cap=max_pairs + 1,
-                     nr_cap=max_pairs + 2)
+                     nr_cap=max_pairs + 2, route=route)
+
+
+ROUTES = [0, 1]   # batched (one pair per lane half), intra (one pair per wave)
 
 
 def _check_oracle(b, recs, cig):
@@ -48,10 +51,11 @@ def ctx():
     c.close()
 
 
-def test_graph_replays_equal_eager_and_oracle(ctx):
+@pytest.mark.parametrize("route", ROUTES)
+def test_graph_replays_equal_eager_and_oracle(ctx, route):
     a = W.random_pairs(901, 300, (1, 150), (0, 500))
     other = W.random_pairs(902, 80, (1, 60), (0, 200))
-    g = _graph_for(ctx, a, max_pairs=384, max_qlen=160, max_rlen=520)
+    g = _graph_for(ctx, a, max_pairs=384, max_qlen=160, max_rlen=520, route=route)
     try:
         g.load(a.qcat, a.qoff, a.rcat, a.roff, a.pair_q, a.pair_r)
         g.run(eager=True)
@@ -81,7 +85,8 @@ def test_graph_replays_equal_eager_and_oracle(ctx):
         g.close()
 
 
-def test_graph_wide_lanes_and_protein(ctx):
+@pytest.mark.parametrize("route", ROUTES)
+def test_graph_wide_lanes_and_protein(ctx, route):
     """Scores past the 16-bit field (re-run on 32-bit lanes inside the graph)
     and the general-alphabet profile."""
     gen = np.random.Generator(np.random.PCG64(13))
@@ -92,23 +97,37 @@ def test_graph_wide_lanes_and_protein(ctx):
         qs.append(ref[50:50 + L].copy())
         rs.append(ref)
     b = W.from_lists("graph-threshold", mat, 10, 2, qs, rs)
-    g = _graph_for(ctx, b, max_pairs=8, max_qlen=300, max_rlen=400)
+    g = _graph_for(ctx, b, max_pairs=8, max_qlen=300, max_rlen=400, route=route)
     try:
         g.load(b.qcat, b.qoff, b.rcat, b.roff, b.pair_q, b.pair_r)
         for k in range(2):
             g.run()
             recs, cig = g.read()
             _check_oracle(b, recs, cig)
-        assert set(recs["lane_bits"]) == {16, 32}
+        assert set(recs["lane_bits"]) == ({16, 32} if route == 0 else {32})
     finally:
         g.close()
     p = W.random_pairs(904, 120, (1, 120), (1, 300), alphabet=24, o=11, e=1)
-    g = _graph_for(ctx, p, max_pairs=128, max_qlen=120, max_rlen=300)
+    g = _graph_for(ctx, p, max_pairs=128, max_qlen=120, max_rlen=300, route=route)
     try:
         g.load(p.qcat, p.qoff, p.rcat, p.roff, p.pair_q, p.pair_r)
         g.run()
         recs, cig = g.read()
         _check_oracle(p, recs, cig)
+    finally:
+        g.close()
+
+
+def test_graph_long_queries_intra_route(ctx):
+    """The intra route with queries taller than one strip (hand-over rows)."""
+    b = W.random_pairs(906, 12, (600, 2500), (800, 3000), planted=0.7)
+    g = _graph_for(ctx, b, max_pairs=16, max_qlen=2600, max_rlen=3100, route=1)
+    try:
+        g.load(b.qcat, b.qoff, b.rcat, b.roff, b.pair_q, b.pair_r)
+        for k in range(2):
+            g.run()
+            recs, cig = g.read()
+            _check_oracle(b, recs, cig)
     finally:
         g.close()
 
