@@ -112,7 +112,7 @@ def cpu_baseline(b, seconds):
 
 
 def serving_phase(rate, seconds, warmup=0.25, pool_short=20_000, pool_long=200, workers=8,
-                  mem_budget=32 << 30):
+                  mem_budget=32 << 30, graph_batch=0):
     """Open-loop Poisson replay of the serving workload through swx_server_*:
     90% 150-nt reads vs 1-kb windows, 10% 10-kb reads vs 20-kb windows.
     Latency = completion time - scheduled arrival (so queueing behind an
@@ -132,7 +132,8 @@ def serving_phase(rate, seconds, warmup=0.25, pool_short=20_000, pool_long=200, 
     cells = (pool.qlen()[which].astype(np.int64) * pool.rlen()[which])
     lng = is_long[which]
     srv = swx.Server(pool.matrix, pool.gap_open, pool.gap_extend, workers=workers,
-                     mem_budget=mem_budget)
+                     mem_budget=mem_budget, graph_batch=graph_batch, graph_max_qlen=200,
+                     graph_max_rlen=1100)
     done_ns = np.zeros(n, dtype=np.int64)
     bsize = np.zeros(n, dtype=np.int64)
     t0 = time.monotonic_ns() + 20_000_000
@@ -176,6 +177,7 @@ def serving_phase(rate, seconds, warmup=0.25, pool_short=20_000, pool_long=200, 
             "batches": stats["batches"], "max_batch": stats["max_batch_seen"],
             "mean_batch": round(float(bsize[meas].mean()), 1), "deferred_busy": busy,
             "workers": workers, "mem_budget_gib": mem_budget / 2**30,
+            "graph_batch": graph_batch, "graph_batches": stats["graph_batches"],
             "pool": f"{pool_short} short + {pool_long} long requests"}
 
 
@@ -189,27 +191,32 @@ def graph_phase(ctx, batch=512, reps=20):
     import workloads as W
     pool = W.config5_pool(n_short=batch, n_long=1)
     b = pool.subset(np.arange(batch))
-    g = swx.Graph(ctx, b.matrix, b.gap_open, b.gap_extend, max_pairs=batch, max_qlen=200,
-                  max_rlen=1100, qcat_cap=batch * 200, rcat_cap=batch * 1100 + 8,
-                  nq_cap=batch + 1, nr_cap=batch + 2)
-    t_call, t_graph = [], []
+    graphs = {name: swx.Graph(ctx, b.matrix, b.gap_open, b.gap_extend, max_pairs=batch,
+                              max_qlen=200, max_rlen=1100, qcat_cap=batch * 200,
+                              rcat_cap=batch * 1100 + 8, nq_cap=batch + 1, nr_cap=batch + 2,
+                              route=route)
+              for name, route in (("graph_batched", 0), ("graph_intra", 1))}
+    times = {"call": [], "graph_batched": [], "graph_intra": []}
     try:
         for k in range(reps):
             t = time.perf_counter()
             ctx.align_batch(b.matrix, b.gap_open, b.gap_extend, b.qcat, b.qoff, b.rcat, b.roff,
                             b.pair_q, b.pair_r)
-            t_call.append(time.perf_counter() - t)
-            t = time.perf_counter()
-            g.load(b.qcat, b.qoff, b.rcat, b.roff, b.pair_q, b.pair_r)
-            g.run()
-            g.read()
-            t_graph.append(time.perf_counter() - t)
+            times["call"].append(time.perf_counter() - t)
+            for name, g in graphs.items():
+                t = time.perf_counter()
+                g.load(b.qcat, b.qoff, b.rcat, b.roff, b.pair_q, b.pair_r)
+                g.run()
+                g.read()
+                times[name].append(time.perf_counter() - t)
     finally:
-        g.close()
-    mc, mg = float(np.median(t_call)) * 1e3, float(np.median(t_graph)) * 1e3
-    return {"pairs": batch, "call_ms": round(mc, 3), "graph_ms": round(mg, 3),
-            "call_gcups": round(b.cells() / mc / 1e6, 2), "graph_gcups": round(b.cells() / mg / 1e6, 2),
-            "note": "host inputs and outputs, copies included, median of %d" % reps}
+        for g in graphs.values():
+            g.close()
+    out = {"pairs": batch, "note": "host inputs and outputs, copies included, median of %d" % reps}
+    for name, ts in times.items():
+        m = float(np.median(ts)) * 1e3
+        out[name] = {"ms": round(m, 3), "gcups": round(b.cells() / m / 1e6, 2)}
+    return out
 
 
 def main():

@@ -284,6 +284,10 @@ typedef struct {
   uint32_t flags;       /* SWX_BEGIN | SWX_CIGAR | SWX_SCORE2 for every request */
   int32_t mask_len;     /* as for swx_align_batch */
   int64_t long_cells;   /* qlen * rlen above this: long class; <= 0: 2^22 */
+  int32_t graph_batch;  /* > 0: worker 0 runs short batches through a captured graph (intra
+                           route) of this many requests per replay; 0: eager batches */
+  int32_t graph_max_qlen;   /* graph capacities (<= 0: 256 and 1536); requests beyond */
+  int64_t graph_max_rlen;   /* them take the eager path */
 } swx_server_cfg;
 
 typedef struct {
@@ -306,6 +310,7 @@ typedef struct {
   int64_t submitted, deferred;     /* requests accepted / refused with SWX_EBUSY */
   int64_t admitted, completed;     /* taken into a batch / finished */
   int64_t batches, max_batch_seen;
+  int64_t graph_batches;           /* batches replayed through the captured graph */
   int64_t pending;                 /* waiting now */
   int64_t inflight_bytes, peak_inflight_bytes;
 } swx_server_stats;

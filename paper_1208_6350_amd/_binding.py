@@ -72,13 +72,14 @@ class SwxServerCfg(ctypes.Structure):
                 ("mem_budget", ctypes.c_int64), ("max_pending", ctypes.c_int32),
                 ("workers", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("mask_len", ctypes.c_int32),
-                ("long_cells", ctypes.c_int64)]
+                ("long_cells", ctypes.c_int64), ("graph_batch", ctypes.c_int32),
+                ("graph_max_qlen", ctypes.c_int32), ("graph_max_rlen", ctypes.c_int64)]
 
 
 class SwxServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
                 ("submitted", "deferred", "admitted", "completed", "batches", "max_batch_seen",
-                 "pending", "inflight_bytes", "peak_inflight_bytes")]
+                 "graph_batches", "pending", "inflight_bytes", "peak_inflight_bytes")]
 
 
 REQ_DTYPE = np.dtype([("query_id", "<i8"), ("query", "<u8"), ("qlen", "<i4"), ("_pad", "<i4"),
@@ -471,12 +472,15 @@ class Server:
     returns (the library copies them)."""
 
     def __init__(self, matrix, o, e, device=0, mem_budget=0, max_pending=0, workers=0,
-                 max_batch=0, flags=SWX_ALL, mask_len=-1, long_cells=0):
+                 max_batch=0, flags=SWX_ALL, mask_len=-1, long_cells=0, graph_batch=0,
+                 graph_max_qlen=0, graph_max_rlen=0):
         self._m = np.ascontiguousarray(matrix, dtype=np.int8)
         cfg = SwxServerCfg(device=device, matrix=self._m.ctypes.data, n=self._m.shape[0],
                            gap_open=o, gap_extend=e, mem_budget=mem_budget,
                            max_pending=max_pending, workers=workers, max_batch=max_batch,
-                           flags=flags, mask_len=mask_len, long_cells=long_cells)
+                           flags=flags, mask_len=mask_len, long_cells=long_cells,
+                           graph_batch=graph_batch, graph_max_qlen=graph_max_qlen,
+                           graph_max_rlen=graph_max_rlen)
         h = ctypes.c_void_p()
         _check(lib().swx_server_create(ctypes.byref(cfg), ctypes.byref(h)), "swx_server_create")
         self.handle = h.value

@@ -45,10 +45,12 @@ struct Req {
   int64_t t_submit = 0;
 };
 
-// device-resident registered query
+// registered query: resident on the device, with a host copy for batches
+// that go through a captured graph
 struct RegQuery {
   int8_t *dev = nullptr;
   int32_t qlen = 0;
+  std::vector<int8_t> host;
 };
 
 // growable device / pinned host buffers of one worker
@@ -124,9 +126,115 @@ bool admissible(const swx_server *s, const Req &r, int64_t extra) {
   return r.cls == 0 || s->inflight_long + extra + r.footprint <= s->cfg.mem_budget / 4 * 3;
 }
 
-void run_batch(swx_server *s, swx_ctx *ctx, std::vector<Req> &batch, Staging &stg) {
+int64_t req_qlen(const swx_server *s, const Req &r) {
+  return r.query_id >= 0 ? s->queries[r.query_id].qlen : (int64_t)r.qdata.size();
+}
+
+// A batch of short requests through the worker's captured graph (intra
+// route: every request spread over a wave), in chunks of the graph's
+// capacity.  Returns false when the requests do not fit the graph (or hold an
+// empty query, which the eager path takes).
+bool run_graph_batch(swx_server *s, swx_graph *g, std::vector<Req> &batch,
+                     std::vector<swx_completion> &out, int64_t t_start) {
+  const int64_t cap = s->cfg.graph_batch;
+  for (const Req &r : batch) {
+    const int64_t ql = req_qlen(s, r);
+    if (ql < 1 || ql > s->cfg.graph_max_qlen || (int64_t)r.rdata.size() > s->cfg.graph_max_rlen)
+      return false;
+  }
+  const int64_t nb = (int64_t)batch.size();
+  out.resize(nb);
+  for (int64_t c0 = 0; c0 < nb; c0 += cap) {
+    const int64_t n = std::min(cap, nb - c0);
+    std::vector<int8_t> qcat, rcat;
+    std::vector<int64_t> qoff(n + 1), roff(n + 2), pq(n), pr(n);
+    for (int64_t k = 0; k < n; ++k) {
+      const Req &r = batch[c0 + k];
+      qoff[k] = (int64_t)qcat.size();
+      if (r.query_id >= 0) {
+        const auto &h = s->queries[r.query_id].host;
+        qcat.insert(qcat.end(), h.begin(), h.end());
+      } else {
+        qcat.insert(qcat.end(), r.qdata.begin(), r.qdata.end());
+      }
+      roff[k] = (int64_t)rcat.size();
+      rcat.insert(rcat.end(), r.rdata.begin(), r.rdata.end());
+      pq[k] = k;
+      pr[k] = k;
+    }
+    qoff[n] = (int64_t)qcat.size();
+    roff[n] = roff[n + 1] = (int64_t)rcat.size();   // reference n: empty, for padding
+    swx_batch b{};
+    b.matrix = s->matrix.data(); b.n = s->cfg.n;
+    b.gap_open = s->cfg.gap_open; b.gap_extend = s->cfg.gap_extend;
+    b.qcat = qcat.data(); b.qcat_len = (int64_t)qcat.size(); b.qoff = qoff.data(); b.nq = n;
+    b.rcat = rcat.data(); b.rcat_len = (int64_t)rcat.size(); b.roff = roff.data(); b.nr = n;
+    b.pair_q = pq.data(); b.pair_r = pr.data(); b.npairs = n;
+    b.in_mem = SWX_MEM_HOST;
+    std::vector<swx_rec> recs(n);
+    std::vector<uint32_t> cig((size_t)std::max<int64_t>(qoff[n] + roff[n] + n, 1));
+    swx_batch_out bo{};
+    bo.recs = recs.data(); bo.cigar = cig.data(); bo.cigar_cap = (int64_t)cig.size();
+    bo.out_mem = SWX_MEM_HOST;
+    int status = swx_graph_load(g, &b);
+    if (status == SWX_OK) status = swx_graph_run(g);
+    if (status == SWX_OK) status = swx_graph_read(g, n, &bo);
+    const int64_t t_done = now_ns();
+    for (int64_t k = 0; k < n; ++k) {
+      swx_completion &c = out[c0 + k];
+      memset(&c, 0, sizeof(c));
+      c.ticket = batch[c0 + k].ticket;
+      c.tag = batch[c0 + k].tag;
+      c.status = status;
+      c.t_submit_ns = batch[c0 + k].t_submit;
+      c.t_start_ns = t_start;
+      c.t_done_ns = t_done;
+      c.batch_size = (int32_t)n;
+      if (status == SWX_OK) {
+        c.rec = recs[k];
+        const int32_t cl = recs[k].cigar_len;
+        if (cl > 0) {
+          c.cigar = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)cl);
+          if (c.cigar) memcpy(c.cigar, cig.data() + recs[k].cigar_off, sizeof(uint32_t) * cl);
+          else c.status = SWX_ENOMEM;
+        }
+        c.rec.cigar_off = 0;
+      }
+    }
+  }
+  return true;
+}
+
+void finish_batch(swx_server *s, std::vector<Req> &batch, std::vector<swx_completion> &out) {
+  int64_t fp = 0;
+  for (const Req &r : batch) fp += r.footprint;
+  const int64_t nb = (int64_t)batch.size();
+  std::lock_guard<std::mutex> g(s->mu);
+  s->inflight_bytes -= fp;
+  if (nb > 0 && batch[0].cls == 1) s->inflight_long -= fp;
+  s->stats.batches += 1;
+  s->stats.completed += nb;
+  if (nb > s->stats.max_batch_seen) s->stats.max_batch_seen = nb;
+  for (auto &c : out) s->done.push_back(c);
+  s->cv_done.notify_all();
+  s->cv_work.notify_all();
+}
+
+void run_batch(swx_server *s, swx_ctx *ctx, swx_graph *graph, std::vector<Req> &batch,
+               Staging &stg) {
   const int64_t nb = (int64_t)batch.size();
   const int64_t t_start = now_ns();
+  if (graph && nb > 0 && batch[0].cls == 0) {
+    std::vector<swx_completion> gout;
+    if (run_graph_batch(s, graph, batch, gout, t_start)) {
+      std::lock_guard<std::mutex> g(s->mu);
+      s->stats.graph_batches += 1;
+    }
+    if (!gout.empty()) {
+      finish_batch(s, batch, gout);
+      return;
+    }
+  }
   // layout: queries (registered ones gathered on the device, inline ones
   // copied from the host), references, offsets, pair lists
   std::vector<int64_t> qoff(nb + 1), roff(nb + 1), pq(nb), pr(nb);
@@ -229,17 +337,7 @@ void run_batch(swx_server *s, swx_ctx *ctx, std::vector<Req> &batch, Staging &st
       c.rec.cigar_off = 0;
     }
   }
-  int64_t fp = 0;
-  for (const Req &r : batch) fp += r.footprint;
-  std::lock_guard<std::mutex> g(s->mu);
-  s->inflight_bytes -= fp;
-  if (nb > 0 && batch[0].cls == 1) s->inflight_long -= fp;
-  s->stats.batches += 1;
-  s->stats.completed += nb;
-  if (nb > s->stats.max_batch_seen) s->stats.max_batch_seen = nb;
-  for (auto &c : out) s->done.push_back(c);
-  s->cv_done.notify_all();
-  s->cv_work.notify_all();
+  finish_batch(s, batch, out);
 }
 
 // Worker 0 serves only short requests, so a short request never waits behind
@@ -257,6 +355,25 @@ void worker_main(swx_server *s, int w) {
   swx_ctx *ctx = s->ctxs[w];
   Staging stg;
   std::vector<Req> batch;
+  // the short-request worker replays a captured graph
+  swx_graph *graph = nullptr;
+  if (w == 0 && s->cfg.graph_batch > 0) {
+    swx_graph_cfg gc{};
+    gc.matrix = s->matrix.data(); gc.n = s->cfg.n;
+    gc.gap_open = s->cfg.gap_open; gc.gap_extend = s->cfg.gap_extend;
+    gc.max_pairs = s->cfg.graph_batch;
+    gc.max_qlen = s->cfg.graph_max_qlen;
+    gc.max_rlen = s->cfg.graph_max_rlen;
+    gc.qcat_cap = (int64_t)s->cfg.graph_batch * s->cfg.graph_max_qlen;
+    gc.rcat_cap = (int64_t)s->cfg.graph_batch * s->cfg.graph_max_rlen + 8;
+    gc.nq_cap = s->cfg.graph_batch + 1;
+    gc.nr_cap = s->cfg.graph_batch + 2;
+    gc.flags = s->cfg.flags;
+    gc.mask_len = s->cfg.mask_len;
+    gc.route = SWX_ROUTE_INTRA;
+    swx_graph_io io{};
+    if (swx_graph_create(ctx, &gc, &graph, &io) != SWX_OK) graph = nullptr;   // eager batches then
+  }
   for (;;) {
     batch.clear();
     {
@@ -281,8 +398,9 @@ void worker_main(swx_server *s, int w) {
       if (s->inflight_bytes > s->stats.peak_inflight_bytes)
         s->stats.peak_inflight_bytes = s->inflight_bytes;
     }
-    run_batch(s, ctx, batch, stg);
+    run_batch(s, ctx, graph, batch, stg);
   }
+  if (graph) swx_graph_destroy(graph);
   stg.release();
 }
 
@@ -305,6 +423,11 @@ int swx_server_create(const swx_server_cfg *cfg, swx_server **out) {
   if (s->cfg.workers > 16) s->cfg.workers = 16;
   if (s->cfg.max_batch <= 0) s->cfg.max_batch = 1 << 16;
   if (s->cfg.long_cells <= 0) s->cfg.long_cells = int64_t(1) << 22;
+  if (s->cfg.graph_batch < 0) s->cfg.graph_batch = 0;
+  if (s->cfg.graph_batch > 0) {
+    if (s->cfg.graph_max_qlen <= 0) s->cfg.graph_max_qlen = 256;
+    if (s->cfg.graph_max_rlen <= 0) s->cfg.graph_max_rlen = 1536;
+  }
   s->matrix.assign(cfg->matrix, cfg->matrix + (size_t)cfg->n * cfg->n);
   s->cfg.matrix = s->matrix.data();
   for (int w = 0; w < s->cfg.workers; ++w) {
@@ -330,6 +453,7 @@ int swx_server_register_query(swx_server *s, const int8_t *query, int32_t qlen, 
       return swx::internal_fail(SWX_EINVAL, "symbol code outside [0, n)");
   RegQuery rq;
   rq.qlen = qlen;
+  rq.host.assign(query, query + qlen);
   if (hipSetDevice(s->cfg.device) != hipSuccess || hipMalloc((void **)&rq.dev, (size_t)qlen) != hipSuccess)
     return swx::internal_fail(SWX_ENOMEM, "device allocation failed");
   if (hipMemcpy(rq.dev, query, (size_t)qlen, hipMemcpyHostToDevice) != hipSuccess) {

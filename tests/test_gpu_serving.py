@@ -153,3 +153,39 @@ def test_invalid_request_accepts_nothing():
         assert srv.stats()["submitted"] == 0
     finally:
         srv.close()
+
+
+def test_serving_graph_worker_equals_oracle():
+    """The short-request worker replays a captured graph (intra route) in
+    chunks of its capacity; requests beyond its capacities, or with an empty
+    query, take the eager path.  Every result equals the oracle."""
+    a = W.random_pairs(813, 150, (0, 150), (0, 900))
+    big = W.random_pairs(814, 6, (200, 400), (1000, 2000), planted=0.7)
+    reqs = np.concatenate([
+        swx.make_requests(a.qcat, a.qoff, a.rcat, a.roff, a.pair_q, a.pair_r),
+        swx.make_requests(big.qcat, big.qoff, big.rcat, big.roff, big.pair_q, big.pair_r)])
+    reqs["tag"] = np.arange(len(reqs))
+    srv = swx.Server(a.matrix, a.gap_open, a.gap_extend, workers=2, max_batch=48,
+                     graph_batch=32, graph_max_qlen=160, graph_max_rlen=1000)
+    try:
+        _say(f"[serve-graph] submitting {len(reqs)} requests")
+        for chunk in np.array_split(np.arange(len(reqs)), 6):
+            assert srv.submit(reqs[chunk])[0] == 0
+            time.sleep(0.002)
+        out, cigs = _collect(srv, len(reqs))
+        stats = srv.stats()
+    finally:
+        srv.close()
+    _say(f"[serve-graph] {stats['batches']} batches, {stats['graph_batches']} through the graph")
+    assert (out["status"] == 0).all()
+    assert stats["graph_batches"] >= 1, stats
+    by_tag = {int(t): k for k, t in enumerate(out["tag"])}
+    for part, off in ((a, 0), (big, a.npairs)):
+        ref, rcig, rcoff = oracle.align_many(part.qcat, part.qoff, part.rcat, part.roff,
+                                             part.pair_q, part.pair_r, part.matrix,
+                                             part.gap_open, part.gap_extend)
+        for p in range(part.npairs):
+            k = by_tag[off + p]
+            for f_i, f in enumerate(FIELDS):
+                assert int(out["rec"][k][f]) == int(ref[p][f_i]), (off + p, f)
+            assert np.array_equal(cigs[k], rcig[rcoff[p]:rcoff[p] + ref[p, 7]]), off + p
