@@ -40,8 +40,8 @@ def parse():
     ap.add_argument("--per-pair-sample", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serve-rate", type=float, default=1e5,
-                    help="offered load of the serving phase, requests per second")
+    ap.add_argument("--serve-rate", default="2e4,5e4",
+                    help="offered loads of the serving phase, requests per second (comma list)")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -111,8 +111,8 @@ def cpu_baseline(b, seconds):
                       f"{dt:.1f} s, whole path incl. begin/CIGAR/score2)"}
 
 
-def serving_phase(rate, seconds, warmup=0.25, pool_short=20_000, pool_long=200, workers=8,
-                  mem_budget=32 << 30, graph_batch=0):
+def serving_phase(rate, seconds, warmup=0.25, pool_short=20_000, pool_long=200, workers=3,
+                  mem_budget=32 << 30, graph_batch=0, side_streams=-1):
     """Open-loop Poisson replay of the serving workload through swx_server_*:
     90% 150-nt reads vs 1-kb windows, 10% 10-kb reads vs 20-kb windows.
     Latency = completion time - scheduled arrival (so queueing behind an
@@ -133,7 +133,7 @@ def serving_phase(rate, seconds, warmup=0.25, pool_short=20_000, pool_long=200, 
     lng = is_long[which]
     srv = swx.Server(pool.matrix, pool.gap_open, pool.gap_extend, workers=workers,
                      mem_budget=mem_budget, graph_batch=graph_batch, graph_max_qlen=200,
-                     graph_max_rlen=1100)
+                     graph_max_rlen=1100, side_streams=side_streams)
     done_ns = np.zeros(n, dtype=np.int64)
     bsize = np.zeros(n, dtype=np.int64)
     t0 = time.monotonic_ns() + 20_000_000
@@ -359,7 +359,8 @@ def main():
     }
     if not args.no_serve:
         print("[bench] serving phase", flush=True, file=sys.stderr)
-        line["serving"] = serving_phase(args.serve_rate, args.serve_seconds)
+        line["serving"] = [serving_phase(float(r), args.serve_seconds)
+                           for r in str(args.serve_rate).split(",")]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds)
     print(json.dumps(line), flush=True)

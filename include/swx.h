@@ -178,13 +178,15 @@ typedef struct {
   int64_t long_rlen;
   int64_t intra_jobs;
   int32_t fill_rows;
-  int32_t reserved;    /* must be 0 */
+  int32_t side_streams;  /* 1: independent traceback launches run side by side on two
+                            side streams of the context (made on first use); 0: all
+                            on the context's stream (one hardware queue per context) */
 } swx_tuning;
 int swx_get_tuning(const swx_ctx *ctx, swx_tuning *out);
 int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t);
 
 /* Autotuner: runs the first min(npairs, max_pairs) pairs of b under candidate
- * settings of each knob in turn (fill_rows, then long_cells, then intra_jobs;
+ * settings of each knob in turn (fill_rows, long_cells, intra_jobs, side_streams;
  * each timed as the best of two runs after a warm-up, a change kept only if
  * at least 3% faster), installs the fastest in ctx and returns it in *out.
  * cache_path (may be NULL) names a text file of one JSON object per line,
@@ -269,7 +271,15 @@ int swx_graph_destroy(swx_graph *g);
  *     requests arriving while batches run join the next batch and batches
  *     overlap on the GPU.  With two or more workers, worker 0 serves only
  *     short requests and the others prefer long ones (qlen * rlen >
- *     long_cells), so short requests do not wait behind long batches.
+ *     long_cells), so short requests do not wait behind long batches.  The
+ *     device gives a process few hardware queues (four by default), and
+ *     streams beyond that share them, so that a short batch queued behind a
+ *     long kernel on a shared queue waits for it: keep workers at four or
+ *     fewer, each on a single stream (side_streams off), for short-request
+ *     latency.
+ *   - Short batches may replay a captured graph on worker 0 (graph_batch);
+ *     under a mix with long requests this is slower than the eager batch
+ *     path, which is the default.
  *   - A request's result never depends on the batch it ran in.
  * Timestamps are CLOCK_MONOTONIC nanoseconds. */
 typedef struct swx_server swx_server;
@@ -279,7 +289,7 @@ typedef struct {
   const int8_t *matrix; int32_t n; int32_t gap_open; int32_t gap_extend;   /* copied */
   int64_t mem_budget;   /* bytes; <= 0: 4 GiB */
   int32_t max_pending;  /* submit accepts no more while this many wait; <= 0: 2^20 */
-  int32_t workers;      /* concurrent batches (1..16); <= 0: 2 */
+  int32_t workers;      /* concurrent batches (1..16); <= 0: 3 */
   int32_t max_batch;    /* requests per batch; <= 0: 65536 */
   uint32_t flags;       /* SWX_BEGIN | SWX_CIGAR | SWX_SCORE2 for every request */
   int32_t mask_len;     /* as for swx_align_batch */
@@ -288,6 +298,9 @@ typedef struct {
                            route) of this many requests per replay; 0: eager batches */
   int32_t graph_max_qlen;   /* graph capacities (<= 0: 256 and 1536); requests beyond */
   int64_t graph_max_rlen;   /* them take the eager path */
+  int32_t side_streams;     /* workers' side streams (swx_tuning.side_streams); < 0: off when
+                               workers > 1, so that every worker holds one stream */
+  int32_t pad_;
 } swx_server_cfg;
 
 typedef struct {

@@ -63,7 +63,7 @@ class SwxBatchOut(ctypes.Structure):
 class SwxTuning(ctypes.Structure):
     _fields_ = [("long_cells", ctypes.c_int64), ("long_rlen", ctypes.c_int64),
                 ("intra_jobs", ctypes.c_int64), ("fill_rows", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("side_streams", ctypes.c_int32)]
 
 
 class SwxServerCfg(ctypes.Structure):
@@ -73,7 +73,8 @@ class SwxServerCfg(ctypes.Structure):
                 ("workers", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("mask_len", ctypes.c_int32),
                 ("long_cells", ctypes.c_int64), ("graph_batch", ctypes.c_int32),
-                ("graph_max_qlen", ctypes.c_int32), ("graph_max_rlen", ctypes.c_int64)]
+                ("graph_max_qlen", ctypes.c_int32), ("graph_max_rlen", ctypes.c_int64),
+                ("side_streams", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class SwxServerStats(ctypes.Structure):
@@ -259,7 +260,7 @@ def swx_last_stage_ms(ctx: int, cap: int = 8) -> list:
 def swx_get_tuning(ctx: int) -> dict:
     t = SwxTuning()
     _check(lib().swx_get_tuning(ctx, ctypes.byref(t)), "swx_get_tuning")
-    return {k: getattr(t, k) for k, _ in SwxTuning._fields_ if k != "reserved"}
+    return {k: getattr(t, k) for k, _ in SwxTuning._fields_}
 
 
 def swx_set_tuning(ctx: int, **changes) -> None:
@@ -269,7 +270,7 @@ def swx_set_tuning(ctx: int, **changes) -> None:
     if unknown:
         raise KeyError(f"unknown tuning keys {sorted(unknown)}")
     cur.update(changes)
-    t = SwxTuning(**cur, reserved=0)
+    t = SwxTuning(**cur)
     _check(lib().swx_set_tuning(ctx, ctypes.byref(t)), "swx_set_tuning")
 
 
@@ -371,7 +372,7 @@ class Context:
         path = cache_path.encode() if cache_path else None
         _check(lib().swx_autotune(self.handle, ctypes.byref(b), int(max_pairs), path,
                                   ctypes.byref(t), ctypes.byref(fc)), "swx_autotune")
-        return {k: getattr(t, k) for k, _ in SwxTuning._fields_ if k != "reserved"}, bool(fc.value)
+        return {k: getattr(t, k) for k, _ in SwxTuning._fields_}, bool(fc.value)
 
     def tuning(self) -> dict:
         return swx_get_tuning(self.handle)
@@ -473,14 +474,14 @@ class Server:
 
     def __init__(self, matrix, o, e, device=0, mem_budget=0, max_pending=0, workers=0,
                  max_batch=0, flags=SWX_ALL, mask_len=-1, long_cells=0, graph_batch=0,
-                 graph_max_qlen=0, graph_max_rlen=0):
+                 graph_max_qlen=0, graph_max_rlen=0, side_streams=-1):
         self._m = np.ascontiguousarray(matrix, dtype=np.int8)
         cfg = SwxServerCfg(device=device, matrix=self._m.ctypes.data, n=self._m.shape[0],
                            gap_open=o, gap_extend=e, mem_budget=mem_budget,
                            max_pending=max_pending, workers=workers, max_batch=max_batch,
                            flags=flags, mask_len=mask_len, long_cells=long_cells,
                            graph_batch=graph_batch, graph_max_qlen=graph_max_qlen,
-                           graph_max_rlen=graph_max_rlen)
+                           graph_max_rlen=graph_max_rlen, side_streams=side_streams)
         h = ctypes.c_void_p()
         _check(lib().swx_server_create(ctypes.byref(cfg), ctypes.byref(h)), "swx_server_create")
         self.handle = h.value

@@ -105,7 +105,8 @@ struct swx_ctx {
   int64_t intra_jobs = 2048;               // target column chunks over all long pairs
   int32_t fill_rows = 32;                  // strip height of the batched fill
   // side streams (default priority) for independent kernels of one stage
-  static constexpr int kAux = 4;
+  static constexpr int kAux = 2;   // side streams, created on first use
+  bool side_streams = true;
   hipStream_t aux[kAux] = {};
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kAux] = {};
@@ -334,12 +335,24 @@ struct SideLaunch {
 
 static int run_side_by_side(swx_ctx *ctx, std::vector<SideLaunch> &ls) {
   if (ls.empty()) return SWX_OK;
-  if (ls.size() == 1) {
-    HIP_TRY(ls[0].fn(ctx->stream));
+  if (ls.size() == 1 || !ctx->side_streams) {
+    for (auto &l : ls) HIP_TRY(l.fn(ctx->stream));
+    return SWX_OK;
+  }
+  constexpr int na = swx_ctx::kAux;
+  // side streams are made on first use, so a context that never needs them
+  // (short pairs only) holds a single stream and a single hardware queue
+  bool have = true;
+  for (int k = 0; k < na; ++k)
+    if (!ctx->aux[k] && hipStreamCreate(&ctx->aux[k]) != hipSuccess) {
+      ctx->aux[k] = nullptr;
+      have = false;
+    }
+  if (!have) {   // no side streams: one after the other on the main stream
+    for (auto &l : ls) HIP_TRY(l.fn(ctx->stream));
     return SWX_OK;
   }
   std::stable_sort(ls.begin(), ls.end(), [](const SideLaunch &x, const SideLaunch &y) { return x.cost > y.cost; });
-  constexpr int na = 2;
   HIP_TRY(hipEventRecord(ctx->fork_ev, ctx->stream));
   for (int k = 0; k < na; ++k) HIP_TRY(hipStreamWaitEvent(ctx->aux[k], ctx->fork_ev, 0));
   double load[na] = {0, 0};
@@ -1396,13 +1409,15 @@ int swx_get_tuning(const swx_ctx *ctx, swx_tuning *out) {
   t.long_rlen = ctx->long_rlen;
   t.intra_jobs = ctx->intra_jobs;
   t.fill_rows = ctx->fill_rows;
+  t.side_streams = ctx->side_streams ? 1 : 0;
   *out = t;
   return SWX_OK;
 }
 
 int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t) {
   if (!ctx || !t) return fail(SWX_EINVAL, "null argument");
-  if (t->long_cells < -1 || t->long_rlen < 0 || t->intra_jobs < 1 || t->reserved != 0 ||
+  if (t->long_cells < -1 || t->long_rlen < 0 || t->intra_jobs < 1 ||
+      (t->side_streams != 0 && t->side_streams != 1) ||
       (t->fill_rows != 16 && t->fill_rows != 24 && t->fill_rows != 32))
     return fail(SWX_EINVAL, "tuning value out of range");
   std::lock_guard<std::mutex> g(ctx->mu);
@@ -1410,6 +1425,7 @@ int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t) {
   ctx->long_rlen = t->long_rlen;
   ctx->intra_jobs = t->intra_jobs;
   ctx->fill_rows = t->fill_rows;
+  ctx->side_streams = t->side_streams != 0;
   return SWX_OK;
 }
 
@@ -1435,8 +1451,7 @@ int swx_ctx_create(int device, swx_ctx **out) {
   }
   bool ok = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess;
   for (int k = 0; k < swx_ctx::kAux && ok; ++k)
-    ok = hipStreamCreate(&c->aux[k]) == hipSuccess &&
-         hipEventCreateWithFlags(&c->join_ev[k], hipEventDisableTiming) == hipSuccess;
+    ok = hipEventCreateWithFlags(&c->join_ev[k], hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     delete c;
     return fail(SWX_EDEVICE, "could not create side streams");

@@ -419,7 +419,7 @@ int swx_server_create(const swx_server_cfg *cfg, swx_server **out) {
   s->cfg = *cfg;
   if (s->cfg.mem_budget <= 0) s->cfg.mem_budget = int64_t(4) << 30;
   if (s->cfg.max_pending <= 0) s->cfg.max_pending = 1 << 20;
-  if (s->cfg.workers <= 0) s->cfg.workers = 2;
+  if (s->cfg.workers <= 0) s->cfg.workers = 3;
   if (s->cfg.workers > 16) s->cfg.workers = 16;
   if (s->cfg.max_batch <= 0) s->cfg.max_batch = 1 << 16;
   if (s->cfg.long_cells <= 0) s->cfg.long_cells = int64_t(1) << 22;
@@ -432,7 +432,15 @@ int swx_server_create(const swx_server_cfg *cfg, swx_server **out) {
   s->cfg.matrix = s->matrix.data();
   for (int w = 0; w < s->cfg.workers; ++w) {
     swx_ctx *c = nullptr;
-    const int rc = swx_ctx_create(cfg->device, &c);
+    int rc = swx_ctx_create(cfg->device, &c);
+    if (rc == SWX_OK) {
+      swx_tuning t{};
+      rc = swx_get_tuning(c, &t);
+      t.side_streams = s->cfg.side_streams < 0 ? (s->cfg.workers > 1 ? 0 : 1)
+                                               : (s->cfg.side_streams ? 1 : 0);
+      if (rc == SWX_OK) rc = swx_set_tuning(c, &t);
+      if (rc != SWX_OK) swx_ctx_destroy(c);
+    }
     if (rc != SWX_OK) {
       for (swx_ctx *x : s->ctxs) swx_ctx_destroy(x);
       delete s;
