@@ -349,6 +349,43 @@ int swx_server_stats_get(swx_server *s, swx_server_stats *out);
  * polled are dropped). */
 int swx_server_destroy(swx_server *s);
 
+/* Discrete-event simulation of the serving policy on a virtual clock, with
+ * no device: the arrival schedule is replayed against a modelled GPU on which
+ * a batch of k requests holding C query x reference cells takes
+ * batch_us + k * request_us + C / cells_per_us microseconds (batches do not
+ * slow each other down: the model checks the policy, not performance).
+ * Footprints, size classes, admission, the pending-queue limit (an arrival
+ * that finds max_pending requests waiting is refused: status SWX_EBUSY) and
+ * batch formation are the serving loop's own code.  Events are taken one at
+ * a time, a completion before an arrival at the same time, and each is
+ * followed by dispatch to the free workers in worker order.  Arrivals must
+ * be in non-decreasing time order.  Fills out[k]
+ * for every request and *stats (may be NULL).  Errors: SWX_EINVAL for null
+ * pointers, n < 0, unsorted arrivals, negative lengths or a non-positive
+ * cells_per_us. */
+typedef struct {
+  double arrival_us;
+  int64_t qlen, rlen;
+} swx_sim_request;
+
+typedef struct {
+  double cells_per_us;  /* modelled cell rate */
+  double batch_us;      /* fixed cost of a batch */
+  double request_us;    /* cost per request of a batch */
+} swx_sim_model;
+
+typedef struct {
+  double start_us, done_us;   /* batch start and end (-1 if refused) */
+  int64_t batch_id;           /* dispatch order, -1 if refused */
+  int64_t footprint;          /* admission estimate, bytes */
+  int32_t worker, batch_size; /* -1 / 0 if refused */
+  int32_t cls, status;        /* size class (0 short, 1 long); SWX_OK or SWX_EBUSY */
+} swx_sim_result;
+
+int swx_server_simulate(const swx_server_cfg *cfg, const swx_sim_model *model,
+                        const swx_sim_request *rq, int64_t n, swx_sim_result *out,
+                        swx_server_stats *stats);
+
 /* ---- diagnostics ------------------------------------------------------------ */
 const char *swx_strerror(int status);
 const char *swx_last_error(void);

@@ -11,4 +11,5 @@ from ._binding import (  # noqa: F401
     swx_ctx_create, swx_ctx_destroy, swx_last_error, swx_last_stage_ms, swx_profile_create,
     swx_profile_destroy, swx_result_free, swx_strerror, swx_get_tuning, swx_set_tuning, REC_DTYPE,
     Server, make_requests, REQ_DTYPE, COMPLETION_DTYPE, SWX_EBUSY, Graph,
+    simulate_serving, SIM_REQ_DTYPE, SIM_RESULT_DTYPE,
 )

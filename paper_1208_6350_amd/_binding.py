@@ -108,6 +108,11 @@ class SwxGraphIo(ctypes.Structure):
                 ("cigar", ctypes.c_void_p), ("cigar_cap", ctypes.c_int64)]
 
 
+class SwxSimModel(ctypes.Structure):
+    _fields_ = [("cells_per_us", ctypes.c_double), ("batch_us", ctypes.c_double),
+                ("request_us", ctypes.c_double)]
+
+
 # name -> (restype, argtypes)
 _SIGS = {
     "swx_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
@@ -149,6 +154,9 @@ _SIGS = {
     "swx_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxServerStats)]),
     "swx_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "swx_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxTuning)]),
+    "swx_server_simulate": (ctypes.c_int, [ctypes.POINTER(SwxServerCfg), ctypes.POINTER(SwxSimModel),
+                                           ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                           ctypes.POINTER(SwxServerStats)]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -540,6 +548,32 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+SIM_REQ_DTYPE = np.dtype([("arrival_us", "<f8"), ("qlen", "<i8"), ("rlen", "<i8")])
+SIM_RESULT_DTYPE = np.dtype([("start_us", "<f8"), ("done_us", "<f8"), ("batch_id", "<i8"),
+                             ("footprint", "<i8"), ("worker", "<i4"), ("batch_size", "<i4"),
+                             ("cls", "<i4"), ("status", "<i4")])
+
+
+def simulate_serving(arrival_us, qlen, rlen, cells_per_us, batch_us=0.0, request_us=0.0, n=4,
+                     mem_budget=0, max_pending=0, workers=0, max_batch=0, long_cells=0):
+    """swx_server_simulate: the serving policy on a virtual clock against a
+    modelled GPU (no device needed).  Returns (SIM_RESULT_DTYPE array, stats)."""
+    rq = np.zeros(len(arrival_us), dtype=SIM_REQ_DTYPE)
+    rq["arrival_us"] = arrival_us
+    rq["qlen"] = qlen
+    rq["rlen"] = rlen
+    out = np.zeros(len(rq), dtype=SIM_RESULT_DTYPE)
+    cfg = SwxServerCfg(device=0, matrix=None, n=n, gap_open=1, gap_extend=1,
+                       mem_budget=mem_budget, max_pending=max_pending, workers=workers,
+                       max_batch=max_batch, flags=0, mask_len=-1, long_cells=long_cells)
+    model = SwxSimModel(cells_per_us=cells_per_us, batch_us=batch_us, request_us=request_us)
+    st = SwxServerStats()
+    _check(lib().swx_server_simulate(ctypes.byref(cfg), ctypes.byref(model), rq.ctypes.data,
+                                     len(rq), out.ctypes.data, ctypes.byref(st)),
+           "swx_server_simulate")
+    return out, {k: getattr(st, k) for k, _ in SwxServerStats._fields_}
 
 
 def make_requests(qcat, qoff, rcat, roff, pair_q, pair_r, tags=None, query_ids=None):

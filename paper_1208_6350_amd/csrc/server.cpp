@@ -26,6 +26,7 @@
 
 #include "../../include/swx.h"
 #include "runtime_internal.h"
+#include "serve_policy.h"
 
 namespace {
 
@@ -98,8 +99,7 @@ struct swx_server {
   std::deque<Req> pending[2];        // [0] short, [1] long requests, FIFO each
   std::deque<swx_completion> done;
   std::vector<RegQuery> queries;
-  int64_t inflight_bytes = 0;
-  int64_t inflight_long = 0;         // part of inflight_bytes held by long requests
+  swx_sched::Budget budget;          // footprint of the work in flight
   uint64_t next_ticket = 1;
   bool stop = false;
   swx_server_stats stats{};
@@ -108,23 +108,6 @@ struct swx_server {
 };
 
 namespace {
-
-// Device bytes a request's work takes while it runs: sequences, boundary
-// rows and max array (about 64 bytes per query or reference symbol), the
-// query profile, and the traceback band (one nibble per cell of a band at
-// most as wide as the query, plus slack).
-int64_t footprint(int64_t qlen, int64_t rlen, int32_t n) {
-  const int64_t band = std::min<int64_t>(rlen, qlen + 64);
-  return 64 * (qlen + rlen) + (int64_t)(n + 1) * qlen + qlen * band / 2 + 4096;
-}
-
-// Long requests may hold at most 3/4 of the budget, so short ones always find
-// room; a request larger than its share still runs once nothing else does.
-bool admissible(const swx_server *s, const Req &r, int64_t extra) {
-  if (s->inflight_bytes == 0 && extra == 0) return true;
-  if (s->inflight_bytes + extra + r.footprint > s->cfg.mem_budget) return false;
-  return r.cls == 0 || s->inflight_long + extra + r.footprint <= s->cfg.mem_budget / 4 * 3;
-}
 
 int64_t req_qlen(const swx_server *s, const Req &r) {
   return r.query_id >= 0 ? s->queries[r.query_id].qlen : (int64_t)r.qdata.size();
@@ -210,8 +193,7 @@ void finish_batch(swx_server *s, std::vector<Req> &batch, std::vector<swx_comple
   for (const Req &r : batch) fp += r.footprint;
   const int64_t nb = (int64_t)batch.size();
   std::lock_guard<std::mutex> g(s->mu);
-  s->inflight_bytes -= fp;
-  if (nb > 0 && batch[0].cls == 1) s->inflight_long -= fp;
+  swx_sched::release(s->budget, nb > 0 ? batch[0].cls : 0, fp);
   s->stats.batches += 1;
   s->stats.completed += nb;
   if (nb > s->stats.max_batch_seen) s->stats.max_batch_seen = nb;
@@ -340,17 +322,6 @@ void run_batch(swx_server *s, swx_ctx *ctx, swx_graph *graph, std::vector<Req> &
   finish_batch(s, batch, out);
 }
 
-// Worker 0 serves only short requests, so a short request never waits behind
-// a batch of long ones; the other workers prefer long requests and take short
-// ones when no long request is admissible.
-int pick_class(const swx_server *s, int w) {
-  if (w == 0 && s->cfg.workers > 1)
-    return (!s->pending[0].empty() && admissible(s, s->pending[0].front(), 0)) ? 0 : -1;
-  for (int c : {1, 0})
-    if (!s->pending[c].empty() && admissible(s, s->pending[c].front(), 0)) return c;
-  return -1;
-}
-
 void worker_main(swx_server *s, int w) {
   swx_ctx *ctx = s->ctxs[w];
   Staging stg;
@@ -378,25 +349,16 @@ void worker_main(swx_server *s, int w) {
     batch.clear();
     {
       std::unique_lock<std::mutex> lk(s->mu);
+      auto next = [&] { return swx_sched::pick_class(s->cfg, s->budget, s->pending, w); };
       s->cv_work.wait(lk, [&] {
-        return (s->stop && s->pending[0].empty() && s->pending[1].empty()) ||
-               pick_class(s, w) >= 0;
+        return (s->stop && s->pending[0].empty() && s->pending[1].empty()) || next() >= 0;
       });
-      const int c = pick_class(s, w);
+      const int c = next();
       if (c < 0) break;   // stopping, and nothing left for this worker
-      std::deque<Req> &q = s->pending[c];
-      int64_t fp = 0;
-      while (!q.empty() && (int64_t)batch.size() < s->cfg.max_batch &&
-             admissible(s, q.front(), fp)) {
-        fp += q.front().footprint;
-        batch.push_back(std::move(q.front()));
-        q.pop_front();
-      }
-      s->inflight_bytes += fp;
-      if (c == 1) s->inflight_long += fp;
+      swx_sched::take_batch(s->cfg, s->budget, s->pending[c], c, batch);
       s->stats.admitted += (int64_t)batch.size();
-      if (s->inflight_bytes > s->stats.peak_inflight_bytes)
-        s->stats.peak_inflight_bytes = s->inflight_bytes;
+      if (s->budget.inflight > s->stats.peak_inflight_bytes)
+        s->stats.peak_inflight_bytes = s->budget.inflight;
     }
     run_batch(s, ctx, graph, batch, stg);
   }
@@ -417,17 +379,7 @@ int swx_server_create(const swx_server_cfg *cfg, swx_server **out) {
   swx_server *s = new (std::nothrow) swx_server();
   if (!s) return swx::internal_fail(SWX_ENOMEM, "host allocation failed");
   s->cfg = *cfg;
-  if (s->cfg.mem_budget <= 0) s->cfg.mem_budget = int64_t(4) << 30;
-  if (s->cfg.max_pending <= 0) s->cfg.max_pending = 1 << 20;
-  if (s->cfg.workers <= 0) s->cfg.workers = 3;
-  if (s->cfg.workers > 16) s->cfg.workers = 16;
-  if (s->cfg.max_batch <= 0) s->cfg.max_batch = 1 << 16;
-  if (s->cfg.long_cells <= 0) s->cfg.long_cells = int64_t(1) << 22;
-  if (s->cfg.graph_batch < 0) s->cfg.graph_batch = 0;
-  if (s->cfg.graph_batch > 0) {
-    if (s->cfg.graph_max_qlen <= 0) s->cfg.graph_max_qlen = 256;
-    if (s->cfg.graph_max_rlen <= 0) s->cfg.graph_max_rlen = 1536;
-  }
+  swx_sched::apply_defaults(s->cfg);
   s->matrix.assign(cfg->matrix, cfg->matrix + (size_t)cfg->n * cfg->n);
   s->cfg.matrix = s->matrix.data();
   for (int w = 0; w < s->cfg.workers; ++w) {
@@ -515,8 +467,8 @@ int swx_server_submit(swx_server *s, const swx_request *rq, int32_t nreq, uint64
       ql = s->queries[r.query_id].qlen;
     }
     if (r.rlen > 0) q.rdata.assign(r.ref, r.ref + r.rlen);
-    q.footprint = footprint(ql, r.rlen, s->cfg.n);
-    q.cls = ql * r.rlen > s->cfg.long_cells ? 1 : 0;
+    q.footprint = swx_sched::footprint(ql, r.rlen, s->cfg.n);
+    q.cls = swx_sched::size_class(ql, r.rlen, s->cfg.long_cells);
     q.t_submit = t;
     reqs.push_back(std::move(q));
   }
@@ -565,7 +517,7 @@ int swx_server_stats_get(swx_server *s, swx_server_stats *out) {
   std::lock_guard<std::mutex> g(s->mu);
   *out = s->stats;
   out->pending = (int64_t)(s->pending[0].size() + s->pending[1].size());
-  out->inflight_bytes = s->inflight_bytes;
+  out->inflight_bytes = s->budget.inflight;
   return SWX_OK;
 }
 
