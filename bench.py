@@ -44,6 +44,9 @@ def parse():
                     help="offered loads of the serving phase, requests per second (comma list)")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed steps (no autotuner, output modes, graph, per-pair, "
+                         "serving or CPU phases): the form the kernel profiles are taken of")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (default: tune on a 100k-pair sample first)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -255,7 +258,7 @@ def main():
         del src, dst
     ctx = swx.Context(0)
     tuning = None
-    if not args.no_autotune:
+    if not args.no_autotune and not args.headline_only:
         t = time.perf_counter()
         tuning, _ = ctx.autotune(b.matrix, b.gap_open, b.gap_extend, dq, dqo, dr, dro, dpq, dpr,
                                  max_pairs=100_000, in_mem=swx.SWX_MEM_DEVICE)
@@ -295,7 +298,8 @@ def main():
     # the paper's output modes side by side (its own comparison: score only,
     # score with begin/end, full alignment with CIGAR and score2)
     modes = {}
-    for name, fl in (("score_end", 0), ("begin_end", swx.SWX_BEGIN), ("full", swx.SWX_ALL)):
+    for name, fl in () if args.headline_only else (
+            ("score_end", 0), ("begin_end", swx.SWX_BEGIN), ("full", swx.SWX_ALL)):
         ts = []
         for k in range(3):
             torch.cuda.synchronize()
@@ -312,11 +316,11 @@ def main():
 
     # graph mode against the ordinary call on small batches of short pairs
     # (serving-sized: where per-call planning and launches dominate)
-    graph_cmp = graph_phase(ctx)
+    graph_cmp = None if args.headline_only else graph_phase(ctx)
 
     # per-pair form: the same library, one pair per call
     per_pair = None
-    if args.per_pair_sample > 0:
+    if args.per_pair_sample > 0 and not args.headline_only:
         pp = b.subset(np.arange(min(args.per_pair_sample, b.npairs)))
         t = time.perf_counter()
         for p in range(pp.npairs):
@@ -357,11 +361,11 @@ def main():
         "graph": graph_cmp,
         "per_pair": per_pair,
     }
-    if not args.no_serve:
+    if not args.no_serve and not args.headline_only:
         print("[bench] serving phase", flush=True, file=sys.stderr)
         line["serving"] = [serving_phase(float(r), args.serve_seconds)
                            for r in str(args.serve_rate).split(",")]
-    if not args.no_cpu:
+    if not args.no_cpu and not args.headline_only:
         line["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
