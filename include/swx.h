@@ -181,12 +181,17 @@ typedef struct {
   int32_t side_streams;  /* 1: independent traceback launches run side by side on two
                             side streams of the context (made on first use); 0: all
                             on the context's stream (one hardware queue per context) */
+  int32_t fill_sched;    /* order of the batched fill's tasks (tasks are sorted by size,
+                            ascending): 0 in that order, one wave per task; 1 largest
+                            first (default); 2 a grid of resident waves taking tasks
+                            largest first from a device work queue */
+  int32_t pad_;          /* must be 0 */
 } swx_tuning;
 int swx_get_tuning(const swx_ctx *ctx, swx_tuning *out);
 int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t);
 
 /* Autotuner: runs the first min(npairs, max_pairs) pairs of b under candidate
- * settings of each knob in turn (fill_rows, long_cells, intra_jobs, side_streams;
+ * settings of each knob in turn (fill_rows, long_cells, intra_jobs, side_streams, fill_sched;
  * each timed as the best of two runs after a warm-up, a change kept only if
  * at least 3% faster), installs the fastest in ctx and returns it in *out.
  * cache_path (may be NULL) names a text file of one JSON object per line,

@@ -63,7 +63,8 @@ class SwxBatchOut(ctypes.Structure):
 class SwxTuning(ctypes.Structure):
     _fields_ = [("long_cells", ctypes.c_int64), ("long_rlen", ctypes.c_int64),
                 ("intra_jobs", ctypes.c_int64), ("fill_rows", ctypes.c_int32),
-                ("side_streams", ctypes.c_int32)]
+                ("side_streams", ctypes.c_int32), ("fill_sched", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 class SwxServerCfg(ctypes.Structure):
@@ -268,7 +269,7 @@ def swx_last_stage_ms(ctx: int, cap: int = 8) -> list:
 def swx_get_tuning(ctx: int) -> dict:
     t = SwxTuning()
     _check(lib().swx_get_tuning(ctx, ctypes.byref(t)), "swx_get_tuning")
-    return {k: getattr(t, k) for k, _ in SwxTuning._fields_}
+    return {k: getattr(t, k) for k, _ in SwxTuning._fields_ if k != "pad_"}
 
 
 def swx_set_tuning(ctx: int, **changes) -> None:
@@ -380,7 +381,7 @@ class Context:
         path = cache_path.encode() if cache_path else None
         _check(lib().swx_autotune(self.handle, ctypes.byref(b), int(max_pairs), path,
                                   ctypes.byref(t), ctypes.byref(fc)), "swx_autotune")
-        return {k: getattr(t, k) for k, _ in SwxTuning._fields_}, bool(fc.value)
+        return {k: getattr(t, k) for k, _ in SwxTuning._fields_ if k != "pad_"}, bool(fc.value)
 
     def tuning(self) -> dict:
         return swx_get_tuning(self.handle)

@@ -77,21 +77,15 @@ __device__ __forceinline__ uint32_t word_of(const uint4 &v, int k) {
 // 168 (three waves) for shorter strips.
 template <int R> constexpr int fill_waves() { return R >= 32 ? 2 : 3; }
 
+// One task (up to 64 or 128 pairs) on one wave: every strip, column group by
+// column group.  tid is uniform across the wave, so the task and everything
+// derived from it (bounds, plane addresses) live in SGPRs.
 template <class V, int R, uint32_t MODE, bool CLAMP, bool REV>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fill_waves<R>()))) void k_inter_fill(
-    InterArgs a) {
+__device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid,
+                                           const uint32_t *s_lut) {
   using T = VT<V>;
   constexpr int NH = T::kHalves;
-  __shared__ uint32_t s_lut[8];
-  if (threadIdx.x < 8) s_lut[threadIdx.x] = a.lut[threadIdx.x];
-  __syncthreads();
-
   const int lane = threadIdx.x & 63;
-  // the wave index is uniform across the wave: say so, so that the task and
-  // everything derived from it (bounds, plane addresses) live in SGPRs
-  const int64_t tid = (int64_t)blockIdx.x * (blockDim.x >> 6) +
-                      __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  if (tid >= a.ntasks) return;
   const InterTask tk = a.tasks[tid];
   if (tk.nslots == 0) return;   // an empty task of a fixed-capacity plan
   constexpr bool rev = REV;
@@ -368,6 +362,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fill_waves<
   }
 }
 
+// Task order: tasks are sorted by (band, strips, columns) ascending, so the
+// largest come last.  sched 0 runs task blockIdx-order ascending, 1 runs
+// them largest first, 2 keeps a grid of resident waves that take tasks
+// largest first from a device counter (a work queue: one 64-bit atomic per
+// task) until it runs past the last task.
+template <class V, int R, uint32_t MODE, bool CLAMP, bool REV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fill_waves<R>()))) void k_inter_fill(
+    InterArgs a) {
+  __shared__ uint32_t s_lut[8];
+  if (threadIdx.x < 8) s_lut[threadIdx.x] = a.lut[threadIdx.x];
+  __syncthreads();
+  const bool queued = a.sched == 2;
+  int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+              __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  for (;;) {   // one pass unless queued (a single call site keeps one copy of the body)
+    if (queued) {
+      unsigned long long t = 0;
+      if ((threadIdx.x & 63) == 0) t = atomicAdd(a.queue, 1ull);
+      const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)t);
+      const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(t >> 32));
+      k = (int64_t)(((uint64_t)hi << 32) | lo);
+    }
+    if (k >= a.ntasks) return;
+    inter_task<V, R, MODE, CLAMP, REV>(a, a.sched == 0 ? k : a.ntasks - 1 - k, s_lut);
+    if (!queued) return;
+  }
+}
+
+__global__ void k_zero_queue(unsigned long long *q) {
+  if (threadIdx.x == 0) *q = 0ull;
+}
+
 // ---- packed reference symbols: per task, column group, lane -------------
 // One block per task.  The reference bytes of a chunk of 256 columns are read
 // pair by pair (consecutive threads read consecutive bytes of one sequence,
@@ -467,8 +493,15 @@ __global__ __launch_bounds__(256) void k_inter_prof(PackArgs a) {
 template <class V, int R, uint32_t MODE>
 static hipError_t launch_fill(const InterArgs &a, hipStream_t st) {
   const int waves_per_block = 4;
-  const int64_t blocks = (a.ntasks + waves_per_block - 1) / waves_per_block;
+  int64_t blocks = (a.ntasks + waves_per_block - 1) / waves_per_block;
   if (blocks == 0) return hipSuccess;
+  if (a.sched == 2) {
+    if (!a.queue || a.cus < 1) return hipErrorInvalidValue;
+    // resident blocks: waves per SIMD x 4 SIMDs per CU / 4 waves per block
+    const int64_t resident = (int64_t)a.cus * fill_waves<R>();
+    if (blocks > resident) blocks = resident;
+    hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, st, a.queue);
+  }
   const dim3 g((unsigned)blocks), b(64 * waves_per_block);
   if (a.rev) {
     if (a.clamp) hipLaunchKernelGGL((k_inter_fill<V, R, MODE, true, true>), g, b, 0, st, a);

@@ -104,6 +104,9 @@ struct swx_ctx {
   int64_t long_rlen = int64_t(1) << 16;    // ... or a reference longer than this
   int64_t intra_jobs = 2048;               // target column chunks over all long pairs
   int32_t fill_rows = 32;                  // strip height of the batched fill
+  int32_t fill_sched = 1;                  // task order of the batched fill (InterArgs::sched)
+  int32_t cus = 0;                         // compute units of the device
+  unsigned long long *queue = nullptr;     // work-queue counter of the batched fill
   // side streams (default priority) for independent kernels of one stage
   static constexpr int kAux = 2;   // side streams, created on first use
   bool side_streams = true;
@@ -278,6 +281,9 @@ static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &v
   a.dummy = sc.dmat;   // any readable device bytes
   a.target = d_target;
   a.out = out;
+  a.sched = ctx->fill_sched;
+  a.cus = ctx->cus;
+  a.queue = ctx->queue;
   if (mark_fill >= 0) HIP_TRY(hipEventRecord(ctx->ev[mark_fill], st));
   HIP_TRY(inter_fill(a, pl.lane_bits, pl.R, st));
   if (mark_fill >= 0) HIP_TRY(hipEventRecord(ctx->ev[mark_fill + 1], st));
@@ -983,6 +989,8 @@ struct FixedTb {   // one traceback class
 
 struct GraphState {
   swx_graph_cfg cfg{};
+  int32_t fill_sched = 1, cus = 0;    // the creating context's fill schedule
+  unsigned long long *queue = nullptr;
   std::vector<int8_t> matrix;
   Scoring sc{};
   DevArena A;
@@ -1102,6 +1110,9 @@ static int fixed_fill(GraphState &g, FixedPlan &pl, const int64_t *ids, const in
   a.dummy = g.sc.dmat;
   a.target = target;
   a.out = out;
+  a.sched = g.fill_sched;
+  a.cus = g.cus;
+  a.queue = g.queue;
   HIP_TRY(inter_fill(a, pl.lane_bits, pl.R, st));
   return SWX_OK;
 }
@@ -1268,6 +1279,7 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
 static int graph_alloc(GraphState &g) {
   DevArena &A = g.A;
   const int64_t B = g.B;
+  g.queue = A.get<unsigned long long>(1);
   g.qcat = A.get<int8_t>(g.cfg.qcat_cap);
   g.rcat = A.get<int8_t>(g.cfg.rcat_cap);
   g.qoff = A.get<int64_t>(g.cfg.nq_cap + 1);
@@ -1410,6 +1422,7 @@ int swx_get_tuning(const swx_ctx *ctx, swx_tuning *out) {
   t.intra_jobs = ctx->intra_jobs;
   t.fill_rows = ctx->fill_rows;
   t.side_streams = ctx->side_streams ? 1 : 0;
+  t.fill_sched = ctx->fill_sched;
   *out = t;
   return SWX_OK;
 }
@@ -1417,7 +1430,8 @@ int swx_get_tuning(const swx_ctx *ctx, swx_tuning *out) {
 int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t) {
   if (!ctx || !t) return fail(SWX_EINVAL, "null argument");
   if (t->long_cells < -1 || t->long_rlen < 0 || t->intra_jobs < 1 ||
-      (t->side_streams != 0 && t->side_streams != 1) ||
+      (t->side_streams != 0 && t->side_streams != 1) || t->fill_sched < 0 || t->fill_sched > 2 ||
+      t->pad_ != 0 ||
       (t->fill_rows != 16 && t->fill_rows != 24 && t->fill_rows != 32))
     return fail(SWX_EINVAL, "tuning value out of range");
   std::lock_guard<std::mutex> g(ctx->mu);
@@ -1426,6 +1440,7 @@ int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t) {
   ctx->intra_jobs = t->intra_jobs;
   ctx->fill_rows = t->fill_rows;
   ctx->side_streams = t->side_streams != 0;
+  ctx->fill_sched = t->fill_sched;
   return SWX_OK;
 }
 
@@ -1456,6 +1471,11 @@ int swx_ctx_create(int device, swx_ctx **out) {
     delete c;
     return fail(SWX_EDEVICE, "could not create side streams");
   }
+  if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      c->cus < 1 || hipMalloc(&c->queue, 256) != hipSuccess) {
+    delete c;
+    return fail(SWX_EDEVICE, "could not query the device or allocate the work queue");
+  }
   *out = c;
   return SWX_OK;
 }
@@ -1467,6 +1487,7 @@ int swx_ctx_destroy(swx_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     ctx->arena.release();
+    if (ctx->queue) (void)hipFree(ctx->queue);
     for (auto &e : ctx->ev)
       if (e) (void)hipEventDestroy(e);
     for (int k = 0; k < swx_ctx::kAux; ++k) {
@@ -1669,6 +1690,8 @@ int swx_graph_create(swx_ctx *ctx, const swx_graph_cfg *cfg, swx_graph **out, sw
   g.clamp = bound > kInter16Limit - 1;
   g.need32 = bound >= kInter16Limit;
   g.intra = cfg->route == SWX_ROUTE_INTRA;
+  g.fill_sched = ctx->fill_sched;
+  g.cus = ctx->cus;
   int8_t *dmat = g.A.get<int8_t>((int64_t)g.sc.n * g.sc.n);
   if (!dmat) { delete gr; return fail(SWX_ENOMEM, "device pool exhausted"); }
   if (hipMemcpy(dmat, g.matrix.data(), (size_t)g.sc.n * g.sc.n, hipMemcpyHostToDevice) != hipSuccess) {

@@ -85,6 +85,10 @@ struct InterArgs {
   const int8_t *dummy;        // readable bytes for empty slots
   const int32_t *target;      // reversed pass: per pair score to reach
   FillOut out;
+  int32_t sched;              // task order: 0 grid ascending, 1 grid largest first,
+                              // 2 resident waves on a device queue, largest first
+  int32_t cus;                // compute units (sched 2 sizes its grid to them)
+  unsigned long long *queue;  // sched 2: the queue's counter (zeroed by the launch)
 };
 
 // Largest score the 16-bit inter path represents exactly together with its
