@@ -232,10 +232,26 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
     fetch_group(g0);
     if constexpr (MODE == kQGen) fetch_prof(nsy.x & 0xFFu, nsy.y & 0xFFu);
 
+    // Forward pass: a group's boundary words are stored one group late,
+    // right after the wait for the next group's operands, so that the memory
+    // counter never waits for a store issued moments earlier (loads and
+    // stores in flight together make every wait a wait for all).  Before the
+    // first group the pending words are the first group's own (a write of
+    // what was read).  The reversed pass, short of registers, stores at once.
+    constexpr bool kDelay = !REV;
+    uint4 ph = nh, pf = nf, pc = nc;
+    int64_t pgi = g0 * 64 + lane, pghf = pgi;
+    auto flush = [&]() {
+      bH[pghf] = ph;
+      bF[pghf] = pf;
+      if (!rev) bC[pgi] = pc;
+    };
+
 #pragma unroll 1
     for (int64_t g = g0; g < g1; ++g) {
       const uint4 ch = nh, cf = nf, cc = nc;
       const uint2 sy = nsy;
+      if constexpr (kDelay) flush();
       if (g + 1 < g1) fetch_group(g + 1);
       uint32_t lx[4][2];   // QSEL: LUT words of the group's 4 columns
       if constexpr (MODE == kQSel) {
@@ -316,9 +332,12 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
       // first group's words instead (they stay in L2).  A store that is
       // skipped instead costs registers: the compiler splits the loop.
       const int64_t ghf = (last && !rev) ? (int64_t)lane : gi;
-      bH[ghf] = make_uint4(oh[0], oh[1], oh[2], oh[3]);
-      bF[ghf] = make_uint4(of[0], of[1], of[2], of[3]);
-      if (!rev) bC[gi] = make_uint4(oc[0], oc[1], oc[2], oc[3]);
+      ph = make_uint4(oh[0], oh[1], oh[2], oh[3]);
+      pf = make_uint4(of[0], of[1], of[2], of[3]);
+      pc = make_uint4(oc[0], oc[1], oc[2], oc[3]);
+      pgi = gi;
+      pghf = ghf;
+      if constexpr (!kDelay) flush();
       if (rev && (g & 1)) {
         // leave the strip once every pair has reached its target at or before
         // the group's last column: later columns can neither give an earlier
@@ -333,6 +352,7 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
         if (wave_max64(need) <= 4 * g + 4) { cdone = 4 * g + 4; break; }
       }
     }
+    if constexpr (kDelay) flush();   // the strip's last group, before the next strip reads it
     // merge the strip best into the pair best (earlier strips win ties)
 #pragma unroll
     for (int h = 0; h < NH; ++h) {

@@ -98,8 +98,8 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
                                                  const int64_t *sorted) {
   __shared__ int8_t s_mat[32 * 32];
   __shared__ uint32_t s_lut4[32];   // LUT4: scores of query symbol x against reference 0..3
-  constexpr int kRB = BW <= 16 ? 16 : (BW <= 32 ? 8 : 4);
-  __shared__ uint32_t s_walk[4 * kRB * (BW / 8) * 64];   // walk cache: per wave, row, dword, lane
+  constexpr int kRunSlots = 16;     // CIGAR runs per thread kept in LDS during the walk
+  __shared__ uint32_t s_runs[kRunSlots * 256];
   for (int k = threadIdx.x; k < a.n * a.n; k += blockDim.x) s_mat[k] = a.matrix[k];
   if (LUT4 && (int)threadIdx.x < a.n) {
     uint32_t l = 0;
@@ -245,39 +245,37 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
   if (!live) return;
   if (s1 <= 0) { a.cig_len[p] = 0; return; }
   if (hend != s1 || kend < 0 || kend >= BW) a.err[p] = 1;
-  // traceback from (m, w) in state H; runs are written end -> begin, then reversed
+  // Walk from (m, w) in state H.  D moves stay in their row and every other
+  // move goes up exactly one row, so a lane handles row m - t at its t-th row
+  // step: the lanes step through rows together, and each lane's row codes
+  // stream in kWP rows ahead, loaded at the same point of every step.  The
+  // walk itself issues no global store (a store between a load and its use
+  // would make the wait for that load a wait for everything): runs go to
+  // this thread's LDS slots, and are written out, in CIGAR order, after the
+  // walk.  A lane whose runs outgrow its slots finishes on a plain walk.
   uint32_t *out = a.cig + a.cig_off[p];
   int32_t nruns = 0;
   int64_t i = m, j = w;
   int state = 0;
   uint32_t cur_op = 0xFF, cur_len = 0;
-  int64_t guard = 2 * (m + w) + 4;
-  // the walk only moves up (and left): RB rows of choice codes at a time are
-  // pulled into this lane's LDS slots with independent loads, instead of one
-  // dependent global load per step
-  constexpr int RB = BW <= 16 ? 16 : (BW <= 32 ? 8 : 4);
-  const int wv = (int)(threadIdx.x >> 6);
-  int64_t blk_hi = -1;   // rows (blk_hi - RB, blk_hi] are cached
-  while ((i > 0 || j > 0) && guard-- > 0) {
-    const int64_t k = j - i - dlo;
-    if (k < 0 || k >= BW) { a.err[p] = 1; break; }
-    if (i > blk_hi || i <= blk_hi - RB) {
-      blk_hi = i;
+  bool walking = true, bad = false, full = false;
+  uint32_t pend = 0;
+  // (a masked OR rather than a select chain, which the compiler would turn
+  // into an indexed load from a private copy of the ring)
+  auto code_at = [&](const uint32_t (&rc)[ND], int64_t k) -> uint32_t {
+    const uint32_t idx = (uint32_t)(k >> 3);
+    uint32_t word = 0;
 #pragma unroll
-      for (int rr = 0; rr < RB; ++rr) {
-        const int64_t row = i - rr;
-#pragma unroll
-        for (int d = 0; d < ND; ++d)
-          s_walk[((wv * RB + rr) * ND + d) * 64 + lane] =
-              row >= 0 ? dir[((int64_t)row * ND + d) * 64 + lane] : 0u;
-      }
-    }
-    const uint32_t c =
-        (s_walk[((wv * RB + (int)(blk_hi - i)) * ND + (int)(k >> 3)) * 64 + lane] >> (4 * (k & 7))) & 0xFu;
+    for (int d = 0; d < ND; ++d) word |= rc[d] & (0u - (uint32_t)(idx == (uint32_t)d));
+    return (word >> (4 * (k & 7))) & 0xFu;
+  };
+  // one move of the state machine from code c; returns the op (0xFF: none)
+  auto move = [&](uint32_t c, bool &up) -> uint32_t {
     uint32_t op = 0xFF;
+    up = false;
     if (state == 0) {
       const uint32_t src = c & 3u;
-      if (src == 0 && i > 0 && j > 0) { op = 0; --i; --j; }
+      if (src == 0 && i > 0 && j > 0) { op = 0; --i; --j; up = true; }
       else if (src == 1) state = 1;
       else state = 2;
     } else if (state == 1) {
@@ -288,20 +286,88 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
       op = 1;
       state = (c & 8u) ? 0 : 2;
       --i;
+      up = true;
     }
-    if (op != 0xFF) {
-      if (op == cur_op) ++cur_len;
-      else {
-        if (cur_len) out[nruns++] = (cur_len << 4) | cur_op;
-        cur_op = op;
-        cur_len = 1;
+    return op;
+  };
+  constexpr int kWP = 8;
+  uint32_t ring[kWP][ND];
+  // rows above row 0 are never walked: their slots load row 0, so that every
+  // load lands straight in its ring registers
+  auto load_row = [&](int64_t row, uint32_t (&dst)[ND]) {
+    const int64_t rr = row >= 0 ? row : 0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) dst[d] = dir[(rr * ND + d) * 64 + lane];
+  };
+#pragma unroll
+  for (int u = 0; u < kWP; ++u) load_row(m - u, ring[u]);
+  for (int64_t t0 = 0; t0 <= m && walking; t0 += kWP) {
+#pragma unroll
+    for (int u = 0; u < kWP; ++u) {   // no early exit: every step issues the same loads
+      const int64_t row = m - (t0 + u);
+      // the moves inside this row: D moves, then one M or I out of it
+      for (int g = 0; g < 2 * BW + 4 && row >= 0 && walking; ++g) {
+        const int64_t k = j - i - dlo;
+        if (k < 0 || k >= BW || i != row) { bad = true; walking = false; break; }
+        bool up;
+        const uint32_t op = move(code_at(ring[u], k), up);
+        if (op != 0xFF) {
+          if (op == cur_op) ++cur_len;
+          else {
+            if (cur_len) {
+              const uint32_t run = (cur_len << 4) | cur_op;
+              if (nruns == kRunSlots) {   // no slot left: finish on the plain walk
+                pend = run;
+                full = true;
+                walking = false;
+              } else {
+                s_runs[nruns * 256 + threadIdx.x] = run;
+                ++nruns;
+              }
+            }
+            cur_op = op;
+            cur_len = 1;
+          }
+        }
+        if ((i == 0 && j == 0) || full) { walking = false; break; }
+        if (up) break;
+      }
+      load_row(row - kWP, ring[u]);   // the slot is free again: kWP rows up
+    }
+  }
+  if (full) {
+    // the runs so far, the one that found no slot, then the rest of the walk
+    for (int32_t x = 0; x < nruns; ++x) out[x] = s_runs[x * 256 + threadIdx.x];
+    out[nruns++] = pend;
+    int64_t guard = 2 * (m + w) + 4;
+    while ((i > 0 || j > 0) && guard-- > 0) {
+      const int64_t k = j - i - dlo;
+      if (k < 0 || k >= BW) { bad = true; break; }
+      const uint32_t word = dir[((int64_t)i * ND + (k >> 3)) * 64 + lane];
+      bool up;
+      const uint32_t op = move((word >> (4 * (k & 7))) & 0xFu, up);
+      if (op != 0xFF) {
+        if (op == cur_op) ++cur_len;
+        else {
+          if (cur_len) out[nruns++] = (cur_len << 4) | cur_op;
+          cur_op = op;
+          cur_len = 1;
+        }
       }
     }
   }
-  if (i != 0 || j != 0) a.err[p] = 1;
-  if (cur_len) out[nruns++] = (cur_len << 4) | cur_op;
-  for (int32_t x = 0, y = nruns - 1; x < y; ++x, --y) {
-    const uint32_t t = out[x]; out[x] = out[y]; out[y] = t;
+  if (bad || i != 0 || j != 0) a.err[p] = 1;
+  if (full) {
+    if (cur_len) out[nruns++] = (cur_len << 4) | cur_op;
+    for (int32_t x = 0, y = nruns - 1; x < y; ++x, --y) {
+      const uint32_t t = out[x]; out[x] = out[y]; out[y] = t;
+    }
+  } else {
+    // runs were found end -> begin: write them reversed
+    const int32_t total = nruns + (cur_len ? 1 : 0);
+    if (cur_len) out[0] = (cur_len << 4) | cur_op;
+    for (int32_t x = 0; x < nruns; ++x) out[total - 1 - x] = s_runs[x * 256 + threadIdx.x];
+    nruns = total;
   }
   a.cig_len[p] = nruns;
 }
@@ -496,53 +562,102 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
 #pragma unroll
     for (int k = 0; k < R; ++k) { H[k] = kNeg; E[k] = kNeg; }
     int32_t hdtop = (clo >= 1 && clo - 1 >= plo && clo - 1 < phi) ? bH[(clo - 1) * 64 + lane] : kNeg;
-    // the row above, the reference symbol: requested one column ahead
-    auto fetch = [&](int64_t j, int32_t &h, int32_t &f, uint32_t &sy) {
-      const bool inprev = j >= plo && j < phi;
-      h = inprev ? bH[j * 64 + lane] : kNeg;
-      f = inprev ? bF[j * 64 + lane] : kNeg;
-      const int32_t c = (live && j >= 1 && j <= w) ? (int32_t)r[j - 1] : -1;
-      sy = (c >= 0 && c < a.n) ? (uint32_t)c : 0u;
-    };
-    int32_t n_h = kNeg, n_f = kNeg;
-    uint32_t n_sy = 0;
-    if (clo < chi) fetch(clo, n_h, n_f, n_sy);
-    for (int64_t j = clo; j < chi; ++j) {
-      const int32_t hup0 = n_h, fup0 = n_f;
-      const uint32_t sym = n_sy;
-      if (j + 1 < chi) fetch(j + 1, n_h, n_f, n_sy);
-      const uint32_t sym8 = LUT4 ? sym * 8u : sym;
-      int32_t hdiag = hdtop;
-      hdtop = hup0;
-      int32_t hup = hup0, fup = fup0;
-      uint32_t dw0 = 0, dw1 = 0;
+    // Columns go in blocks of kPB.  At the top of a block the wave waits for
+    // the block's operands (loaded at the top of the previous block), then
+    // stores the previous block's codes and boundary values and requests the
+    // next block's operands, and only then computes: every memory operation
+    // has a whole block of arithmetic to complete before the next wait
+    // (loads and stores in flight together make every wait a wait for all).
+    // Loads are unconditional (indices clamped into the buffers) and land
+    // straight in their registers; the row above outside the previous
+    // strip's window reads as -inf.
+    constexpr int kPB = 8;
+    const int8_t *rr = live ? r : (const int8_t *)a.matrix;   // readable bytes for empty lanes
+    int32_t n_h[kPB], n_f[kPB], n_c[kPB];
+    auto fetch_block = [&](int64_t j0) {
 #pragma unroll
-      for (int k = 0; k < R; ++k) {
-        const int32_t sc = LUT4 ? __builtin_amdgcn_sbfe(lut[k], sym8, 8) : (int32_t)s_mat[qn[k] + sym];
-        const int32_t diag = hdiag + sc;
-        const int32_t fo = hup - o, fx = fup - e;
-        const int32_t fij = fo > fx ? fo : fx;
-        const int32_t eo = H[k] - o, ex = E[k] - e;      // H[k], E[k] = row k at column j-1
-        const int32_t eij = eo > ex ? eo : ex;
-        int32_t h = diag > eij ? diag : eij;
-        h = h > fij ? h : fij;
-        uint32_t c = (h == diag) ? 0u : (h == eij ? 1u : 2u);
-        c |= (eo >= ex) ? 4u : 0u;
-        c |= (fo >= fx) ? 8u : 0u;
-        if (k < 8) dw0 |= c << (4 * k);
-        else dw1 |= c << (4 * (k - 8));
-        hdiag = H[k];
-        H[k] = h;
-        E[k] = eij;
-        hup = h;
-        fup = fij;
+      for (int u = 0; u < kPB; ++u) {
+        int64_t j = j0 + u;
+        j = j < 0 ? 0 : (j > tk.wmax ? tk.wmax : j);
+        n_h[u] = bH[j * 64 + lane];
+        n_f[u] = bF[j * 64 + lane];
+        int64_t x = j0 + u - 1;
+        x = x < 0 ? 0 : (x > w - 1 ? w - 1 : x);
+        n_c[u] = (int32_t)rr[live ? x : 0];
       }
-      const int64_t jc = j - cstart;
-      sdir[(jc * 2) * 64 + lane] = dw0;
-      sdir[(jc * 2 + 1) * 64 + lane] = dw1;
-      bH[j * 64 + lane] = H[R - 1];
-      bF[j * 64 + lane] = fup;
+    };
+    uint32_t p_d0[kPB], p_d1[kPB];
+    int32_t p_h[kPB], p_f[kPB];
+    int64_t p_j0 = -1;   // first column of the pending block (-1: none)
+    int64_t p_jc0 = 0;
+    auto flush = [&]() {
+      if (p_j0 < 0) return;
+#pragma unroll
+      for (int u = 0; u < kPB; ++u) {
+        if (p_j0 + u < chi) {
+          const int64_t jc = p_jc0 + u;
+          sdir[(jc * 2) * 64 + lane] = p_d0[u];
+          sdir[(jc * 2 + 1) * 64 + lane] = p_d1[u];
+          bH[(p_j0 + u) * 64 + lane] = p_h[u];
+          bF[(p_j0 + u) * 64 + lane] = p_f[u];
+        }
+      }
+    };
+    fetch_block(clo);
+    for (int64_t j0 = clo; j0 < chi; j0 += kPB) {
+      int32_t c_h[kPB], c_f[kPB];
+      uint32_t c_sy[kPB];
+#pragma unroll
+      for (int u = 0; u < kPB; ++u) {
+        const int64_t j = j0 + u;
+        const bool inprev = j >= plo && j < phi;
+        c_h[u] = inprev ? n_h[u] : kNeg;
+        c_f[u] = inprev ? n_f[u] : kNeg;
+        const int32_t c = (live && j >= 1 && j <= w) ? n_c[u] : -1;
+        c_sy[u] = (c >= 0 && c < a.n) ? (uint32_t)c : 0u;
+      }
+      // the operands are consumed (waited for) before any store is issued
+      __builtin_amdgcn_sched_barrier(0);
+      flush();
+      fetch_block(j0 + kPB);   // past the window too: clamped, and never used
+#pragma unroll
+      for (int u = 0; u < kPB; ++u) {
+        const int32_t hup0 = c_h[u], fup0 = c_f[u];
+        const uint32_t sym8 = LUT4 ? c_sy[u] * 8u : c_sy[u];
+        int32_t hdiag = hdtop;
+        hdtop = hup0;
+        int32_t hup = hup0, fup = fup0;
+        uint32_t dw0 = 0, dw1 = 0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          const int32_t sc = LUT4 ? __builtin_amdgcn_sbfe(lut[k], sym8, 8) : (int32_t)s_mat[qn[k] + c_sy[u]];
+          const int32_t diag = hdiag + sc;
+          const int32_t fo = hup - o, fx = fup - e;
+          const int32_t fij = fo > fx ? fo : fx;
+          const int32_t eo = H[k] - o, ex = E[k] - e;      // H[k], E[k] = row k at column j-1
+          const int32_t eij = eo > ex ? eo : ex;
+          int32_t h = diag > eij ? diag : eij;
+          h = h > fij ? h : fij;
+          uint32_t c = (h == diag) ? 0u : (h == eij ? 1u : 2u);
+          c |= (eo >= ex) ? 4u : 0u;
+          c |= (fo >= fx) ? 8u : 0u;
+          if (k < 8) dw0 |= c << (4 * k);
+          else dw1 |= c << (4 * (k - 8));
+          hdiag = H[k];
+          H[k] = h;
+          E[k] = eij;
+          hup = h;
+          fup = fij;
+        }
+        p_d0[u] = dw0;
+        p_d1[u] = dw1;
+        p_h[u] = H[R - 1];
+        p_f[u] = fup;
+      }
+      p_j0 = j0;
+      p_jc0 = j0 - cstart;
     }
+    flush();   // the strip's last block, before the next strip reads it
     plo = clo;
     phi = chi;
   }
