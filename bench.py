@@ -314,6 +314,20 @@ def main():
         best = min(ts[1:])
         modes[name] = {"ms": round(best * 1e3, 3), "gcups": round(cells / best / 1e9, 1)}
 
+    # the recurrence's cell rate at 8-bit (SWAR) and packed 16-bit lane widths
+    lanes = None
+    if not args.headline_only:
+        lanes = {}
+        res = {}
+        for bits in (16, 8):
+            ctx.lane_probe(bits, columns=256, blocks=256)   # warm-up
+            best, ms, gcups = ctx.lane_probe(bits, columns=4096, blocks=2048)
+            res[bits] = best
+            lanes[f"w{bits}"] = {"ms": round(ms, 3), "gcups": round(gcups, 1)}
+        lanes["same_scores"] = bool(np.array_equal(res[8][:len(res[16])], res[16]))
+        lanes["note"] = ("synthetic 16-row DNA pairs x 4096 columns, recurrence + column max; "
+                         "8-bit = four SWAR byte lanes per register")
+
     # graph mode against the ordinary call on small batches of short pairs
     # (serving-sized: where per-call planning and launches dominate)
     graph_cmp = None if args.headline_only else graph_phase(ctx)
@@ -359,6 +373,7 @@ def main():
         "tuning": tuning,
         "modes": modes,
         "graph": graph_cmp,
+        "lane_widths": lanes,
         "per_pair": per_pair,
     }
     if not args.no_serve and not args.headline_only:

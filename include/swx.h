@@ -398,6 +398,18 @@ const char *swx_last_error(void);
  * order: prepare, fill, rerun32, reverse, traceback, score2, records.
  * Returns the number of stages written (at most cap). */
 int swx_last_stage_ms(const swx_ctx *ctx, double *ms, int cap);
+/* Lane-width probe (method section: narrow saturating lanes).  Runs the fill
+ * recurrence -- biased H, E, F with the zero floor and the column max -- over
+ * blocks x 256 threads of synthetic pairs (16 query rows x `columns`
+ * reference columns each, DNA +2/-2, gap_open/gap_extend <= 60) at `bits`
+ * = 8 (four SWAR byte lanes per register: gfx950 has no packed 8-bit add or
+ * max) or 16 (two packed 16-bit lanes).  Pair p's query symbol of row r is a
+ * hash of p*16 + r, so both widths align the same pairs: best[p] (host
+ * array of blocks * 256 * 32/bits words) receives pair p's best score and
+ * *ms the kernel time.  Errors: SWX_EINVAL for other widths, sizes < 1,
+ * blocks > 2^20 or bad gaps. */
+int swx_lane_probe(swx_ctx *ctx, int32_t bits, int64_t columns, int64_t blocks, int32_t gap_open,
+                   int32_t gap_extend, uint32_t *best, double *ms);
 
 #ifdef __cplusplus
 }

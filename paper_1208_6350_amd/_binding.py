@@ -155,6 +155,9 @@ _SIGS = {
     "swx_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxServerStats)]),
     "swx_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "swx_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxTuning)]),
+    "swx_lane_probe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_double)]),
     "swx_server_simulate": (ctypes.c_int, [ctypes.POINTER(SwxServerCfg), ctypes.POINTER(SwxSimModel),
                                            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                            ctypes.POINTER(SwxServerStats)]),
@@ -360,6 +363,16 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def lane_probe(self, bits, columns=4096, blocks=2048, o=3, e=1):
+        """swx_lane_probe: (best scores per synthetic pair, kernel ms, GCUPS)."""
+        n = blocks * 256 * (32 // bits)
+        best = np.zeros(n, dtype=np.uint32)
+        ms = ctypes.c_double()
+        _check(lib().swx_lane_probe(self.handle, bits, columns, blocks, o, e, best.ctypes.data,
+                                    ctypes.byref(ms)), "swx_lane_probe")
+        cells = n * 16 * columns
+        return best, ms.value, cells / (ms.value * 1e-3) / 1e9
 
     def stage_ms(self):
         return swx_last_stage_ms(self.handle)

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libswx.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["fill_inter.hip", "fill_intra.hip", "aux_kernels.hip", "plan.hip", "traceback.hip", "runtime.cpp", "server.cpp", "autotune.cpp",
-           "simulate.cpp"]
+           "simulate.cpp", "lane_probe.hip"]
 ARCH = os.environ.get("SWX_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -1511,6 +1511,30 @@ int swx_last_stage_ms(const swx_ctx *ctx, double *ms, int cap) {
   return n;
 }
 
+int swx_lane_probe(swx_ctx *ctx, int32_t bits, int64_t columns, int64_t blocks, int32_t gap_open,
+                   int32_t gap_extend, uint32_t *best, double *ms) {
+  if (!ctx || !best || !ms) return fail(SWX_EINVAL, "null argument");
+  if ((bits != 8 && bits != 16) || columns < 1 || blocks < 1 || blocks > (int64_t(1) << 20) ||
+      gap_open < gap_extend || gap_extend < 0 || gap_open > 60)
+    return fail(SWX_EINVAL, "bad probe arguments");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(SWX_EDEVICE, "hipSetDevice failed");
+  ctx->arena.reset();
+  const int64_t npairs = blocks * 256 * (32 / bits);
+  uint32_t *d = ctx->arena.get<uint32_t>(npairs);
+  if (!d) return fail(SWX_ENOMEM, "device pool exhausted (probe)");
+  hipStream_t st = ctx->stream;
+  HIP_TRY(hipEventRecord(ctx->ev[0], st));
+  HIP_TRY(lane_probe(bits, columns, blocks, gap_open, gap_extend, d, st));
+  HIP_TRY(hipEventRecord(ctx->ev[1], st));
+  HIP_TRY(hipMemcpyAsync(best, d, sizeof(uint32_t) * (size_t)npairs, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  float t = 0;
+  HIP_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]));
+  *ms = t;
+  return SWX_OK;
+}
+
 int swx_profile_create(swx_ctx *ctx, const int8_t *query, int32_t qlen, const int8_t *matrix,
                        int32_t n, int32_t gap_open, int32_t gap_extend, swx_profile **out) {
   if (!out) return fail(SWX_EINVAL, "out is null");

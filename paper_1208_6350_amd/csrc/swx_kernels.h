@@ -181,6 +181,10 @@ int tb_wave_waves(int64_t m, int n);   // waves per workgroup for a pair of m ro
 int tb_wave_max_strips();
 hipError_t fill_u8(int64_t n, uint8_t *p, uint8_t v, hipStream_t st);
 hipError_t fill_i64(int64_t n, int64_t *p, int64_t v, hipStream_t st);
+// lane-width probe: blocks x 256 threads, each 32/bits synthetic pairs of 16
+// rows x cols columns; best[pair] = the pair's best score
+hipError_t lane_probe(int bits, int64_t cols, int64_t blocks, int32_t o, int32_t e, uint32_t *best,
+                      hipStream_t st);
 hipError_t class_ranges(const int64_t *counts, int64_t *ranges, hipStream_t st);
 hipError_t count_classes(int64_t n, const uint8_t *cls, int64_t *counts, hipStream_t st);
 hipError_t sort_keys(int64_t n, uint64_t *keys, uint64_t *keys_alt, int64_t *vals,
