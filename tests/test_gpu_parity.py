@@ -167,6 +167,13 @@ def test_config4_sample(ctx):
     assert_parity(ctx, b)
 
 
+def test_all_vs_all_short_reads(ctx):
+    """Every pair of 90 overlapping 70-nt reads (4,005 pairs, one shared
+    code array for queries and references)."""
+    b = W.all_vs_all(n_reads=90)
+    assert_parity(ctx, b)
+
+
 def test_config3_sample(ctx):
     full = W.config3(ntargets=600)
     assert_parity(ctx, full)

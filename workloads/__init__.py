@@ -317,6 +317,26 @@ def config5_pool(seed_k: int = 5, n_short: int = 50_000, n_long: int = 1_000) ->
     return b
 
 
+def all_vs_all(n_reads: int = 4000, read_len: int = 70, region_len: int = 1500,
+               sub_rate: float = 0.01, seed_k: int = 6) -> Batch:
+    """All-vs-all overlap of short reads from one region: n_reads reads of
+    read_len nt drawn at uniform offsets of an i.i.d. region_len-nt ACGT
+    region, each with sub_rate substitutions per base; every pair i < j is
+    aligned (+2/-2, gap open 3, extend 1).  Stands in for a read-overlap graph
+    over reads of one genomic locus: no real read set is available.  The
+    reads are stored once and serve as queries and references."""
+    g = rng_for(seed_k)
+    region = random_dna(g, region_len)
+    starts = g.integers(0, region_len - read_len + 1, size=n_reads)
+    src = np.concatenate([region[s:s + read_len] for s in starts])
+    off = np.arange(n_reads + 1, dtype=np.int64) * read_len
+    reads, roff = mutate_many(g, src, off, sub_rate, 0.0, 0.0, 1)
+    iu, ju = np.triu_indices(n_reads, k=1)
+    return Batch(f"all-vs-all-{n_reads}x{read_len}", dna_matrix(), 3, 1, reads, roff,
+                 reads, roff, iu.astype(np.int64), ju.astype(np.int64),
+                 {"starts": starts})
+
+
 def poisson_schedule(g: np.random.Generator, rate: float, duration: float, pool_size: int,
                      is_long: np.ndarray | None = None, long_frac: float = 0.10):
     """Open-loop Poisson arrivals over `duration` seconds; each arrival draws a
