@@ -71,6 +71,15 @@ def _load():
             lib.orc_align_many.argtypes = [p8, p64, p8, p64, p64, p64, i64, p8, i32, i32, i32,
                                            u32, i64, ctypes.POINTER(_Res), pu32, p64, i32]
             lib.orc_align_many.restype = ctypes.c_int64
+            lib.orc_column_row.argtypes = [p8, i64, p8, i64, p8, i32, i32, i32, i64, i64]
+            lib.orc_column_row.restype = ctypes.c_int64
+            lib.orc_suboptimal.argtypes = [p8, i64, p8, i64, p8, i32, i32, i32, i64, i64,
+                                           ctypes.POINTER(_Sub), pu32, i64]
+            lib.orc_suboptimal.restype = ctypes.c_int
+            lib.orc_suboptimal_many.argtypes = [p8, p64, p8, p64, p64, p64, i64, p8, i32, i32,
+                                                i32, p64, p64, ctypes.POINTER(_Sub), pu32, p64,
+                                                i32]
+            lib.orc_suboptimal_many.restype = ctypes.c_int64
             _lib = lib
     return _lib
 
@@ -235,4 +244,75 @@ def align_many(qcat, qoff, rcat, roff, pair_q, pair_r, matrix, o, e,
     if fails:
         raise RuntimeError(f"oracle failed on {fails} pairs")
     rec = np.frombuffer(res, dtype=np.int64).reshape(-1, 8)[:npairs].copy()
+    return rec, cig, coff
+
+
+class _Sub(ctypes.Structure):
+    _fields_ = [("read_begin2", ctypes.c_int64), ("read_end2", ctypes.c_int64),
+                ("ref_begin2", ctypes.c_int64), ("cigar_len", ctypes.c_int64)]
+
+
+def column_row(q, r, matrix, o, e, col, target):
+    """Smallest row i with H(i, col) == target, or -1."""
+    lib = _load()
+    q, qp = _i8(q)
+    r, rp = _i8(r)
+    m, n = _mat(matrix)
+    return int(lib.orc_column_row(qp, len(q), rp, len(r),
+                                  m.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), n, int(o),
+                                  int(e), int(col), int(target)))
+
+
+def suboptimal(q, r, matrix, o, e, score2, ref_end2):
+    """The alignment behind score2: (read_begin2, read_end2, ref_begin2,
+    [(len, op)]); all -1 and [] when score2 <= 0."""
+    lib = _load()
+    q, qp = _i8(q)
+    r, rp = _i8(r)
+    m, n = _mat(matrix)
+    cap = len(q) + len(r) + 1
+    buf = np.zeros(cap, dtype=np.uint32)
+    res = _Sub()
+    rc = lib.orc_suboptimal(qp, len(q), rp, len(r),
+                            m.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), n, int(o), int(e),
+                            int(score2), int(ref_end2), ctypes.byref(res),
+                            buf.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), cap)
+    if rc != 0:
+        raise RuntimeError("oracle internal inconsistency (suboptimal)")
+    return res.read_begin2, res.read_end2, res.ref_begin2, decode_cigar(buf[:res.cigar_len])
+
+
+def suboptimal_many(qcat, qoff, rcat, roff, pair_q, pair_r, matrix, o, e, score2, ref_end2,
+                    nthreads=None):
+    """The suboptimal alignment of many pairs (score2, ref_end2 per pair from
+    align_many).  Returns (records[npairs, 4] int64: read_begin2, read_end2,
+    ref_begin2, cigar_len; cigar words; cigar offsets)."""
+    lib = _load()
+    qcat, qcp = _i8(qcat)
+    rcat, rcp = _i8(rcat)
+    qoff, qop = _i64(qoff)
+    roff, rop = _i64(roff)
+    pq, pqp = _i64(pair_q)
+    pr, prp = _i64(pair_r)
+    s2, s2p = _i64(score2)
+    e2, e2p = _i64(ref_end2)
+    m, n = _mat(matrix)
+    npairs = len(pq)
+    lens = (qoff[pq + 1] - qoff[pq]) + (roff[pr + 1] - roff[pr]) + 1
+    coff = np.zeros(npairs + 1, dtype=np.int64)
+    if npairs:
+        coff[1:] = np.cumsum(lens)
+    cig = np.zeros(max(int(coff[-1]), 1), dtype=np.uint32)
+    res = (_Sub * max(npairs, 1))()
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    fails = lib.orc_suboptimal_many(qcp, qop, rcp, rop, pqp, prp, npairs,
+                                    m.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), n, int(o),
+                                    int(e), s2p, e2p, res,
+                                    cig.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                    coff.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    int(nthreads))
+    if fails:
+        raise RuntimeError(f"oracle failed on {fails} pairs (suboptimal)")
+    rec = np.frombuffer(res, dtype=np.int64).reshape(-1, 4)[:npairs].copy()
     return rec, cig, coff

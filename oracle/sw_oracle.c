@@ -295,6 +295,120 @@ int orc_align(const int8_t *q, int64_t lq, const int8_t *r, int64_t lr,
   return rc;
 }
 
+/* ---- the suboptimal alignment (method section, Fig. 1 caption) ---------- */
+/* The alignment behind score2: it ends in column ref_end2 at the smallest row
+ * whose H equals score2; its begin is T2 relative to that end (largest jb,
+ * then largest ib, among begins of alignments reaching the end with score
+ * exactly score2 -- the start-propagation DP, which carries that begin for
+ * every cell); its CIGAR is T3 on the begin..end rectangle. */
+int64_t orc_column_row(const int8_t *q, int64_t lq, const int8_t *r, int64_t lr,
+                       const int8_t *mat, int32_t n, int32_t o, int32_t e,
+                       int64_t col, int64_t target) {
+  if (lq <= 0 || col < 0 || col >= lr) return -1;
+  /* the forward recurrence of orc_fill, columns 0..col, keeping column col */
+  int64_t *hprev = (int64_t *)malloc(sizeof(int64_t) * lq);
+  int64_t *hcur = (int64_t *)malloc(sizeof(int64_t) * lq);
+  int64_t *erow = (int64_t *)malloc(sizeof(int64_t) * lq);
+  for (int64_t i = 0; i < lq; ++i) { hprev[i] = 0; erow[i] = NEG_INF; }
+  int64_t row = -1;
+  for (int64_t j = 0; j <= col; ++j) {
+    int64_t f = NEG_INF;
+    for (int64_t i = 0; i < lq; ++i) {
+      int64_t hdiag = (i > 0) ? hprev[i - 1] : 0;
+      int64_t hup = (i > 0) ? hcur[i - 1] : 0;
+      int64_t eij = max2(erow[i] - e, hprev[i] - o);
+      int64_t fij = max2(f - e, hup - o);
+      int64_t h = max2(max2(hdiag + score_of(mat, n, q[i], r[j]), eij), max2(fij, 0));
+      hcur[i] = h;
+      erow[i] = eij;
+      f = fij;
+      if (j == col && row < 0 && h == target) row = i;
+    }
+    int64_t *t = hprev; hprev = hcur; hcur = t;
+  }
+  free(hprev); free(hcur); free(erow);
+  return row;
+}
+
+int orc_suboptimal(const int8_t *q, int64_t lq, const int8_t *r, int64_t lr,
+                   const int8_t *mat, int32_t n, int32_t o, int32_t e,
+                   int64_t score2, int64_t ref_end2,
+                   orc_sub *res, uint32_t *cigar, int64_t cap) {
+  res->read_begin2 = res->read_end2 = res->ref_begin2 = -1;
+  res->cigar_len = 0;
+  if (score2 <= 0) return 0;
+  int64_t ie = orc_column_row(q, lq, r, lr, mat, n, o, e, ref_end2, score2);
+  if (ie < 0) return -1;
+  int64_t ib, jb;
+  if (orc_begin_startprop(q, lq, r, lr, mat, n, o, e, ie, ref_end2, score2, &ib, &jb) != 0)
+    return -1;
+  int64_t gs;
+  int64_t runs = orc_traceback(q, r, mat, n, o, e, ib, ie, jb, ref_end2, cigar, cap, &gs);
+  if (runs < 0 || gs != score2) return -1;
+  res->read_begin2 = ib;
+  res->read_end2 = ie;
+  res->ref_begin2 = jb;
+  res->cigar_len = runs;
+  return 0;
+}
+
+typedef struct {
+  const int8_t *qcat; const int64_t *qoff;
+  const int8_t *rcat; const int64_t *roff;
+  const int64_t *pq, *pr; int64_t npairs;
+  const int8_t *mat; int32_t n, o, e;
+  const int64_t *score2, *ref_end2;
+  orc_sub *res; uint32_t *cigar; const int64_t *coff;
+  int64_t next, failures;
+  pthread_mutex_t mu;
+} sub_ctx;
+
+static void *sub_worker(void *arg) {
+  sub_ctx *c = (sub_ctx *)arg;
+  for (;;) {
+    pthread_mutex_lock(&c->mu);
+    int64_t p = c->next++;
+    pthread_mutex_unlock(&c->mu);
+    if (p >= c->npairs) break;
+    int64_t qi = c->pq[p], ri = c->pr[p];
+    uint32_t *cg = NULL; int64_t cap = 0;
+    if (c->cigar && c->coff) { cg = c->cigar + c->coff[p]; cap = c->coff[p + 1] - c->coff[p]; }
+    if (orc_suboptimal(c->qcat + c->qoff[qi], c->qoff[qi + 1] - c->qoff[qi],
+                       c->rcat + c->roff[ri], c->roff[ri + 1] - c->roff[ri],
+                       c->mat, c->n, c->o, c->e, c->score2[p], c->ref_end2[p],
+                       &c->res[p], cg, cap) != 0) {
+      pthread_mutex_lock(&c->mu);
+      c->failures++;
+      pthread_mutex_unlock(&c->mu);
+    }
+  }
+  return NULL;
+}
+
+int64_t orc_suboptimal_many(const int8_t *qcat, const int64_t *qoff,
+                            const int8_t *rcat, const int64_t *roff,
+                            const int64_t *pair_q, const int64_t *pair_r, int64_t npairs,
+                            const int8_t *mat, int32_t n, int32_t o, int32_t e,
+                            const int64_t *score2, const int64_t *ref_end2,
+                            orc_sub *res, uint32_t *cigar, const int64_t *cigar_off,
+                            int32_t nthreads) {
+  sub_ctx c;
+  c.qcat = qcat; c.qoff = qoff; c.rcat = rcat; c.roff = roff;
+  c.pq = pair_q; c.pr = pair_r; c.npairs = npairs;
+  c.mat = mat; c.n = n; c.o = o; c.e = e;
+  c.score2 = score2; c.ref_end2 = ref_end2;
+  c.res = res; c.cigar = cigar; c.coff = cigar_off;
+  c.next = 0; c.failures = 0;
+  pthread_mutex_init(&c.mu, NULL);
+  if (nthreads < 1) nthreads = 1;
+  pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+  for (int32_t t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, sub_worker, &c);
+  for (int32_t t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+  free(th);
+  pthread_mutex_destroy(&c.mu);
+  return c.failures;
+}
+
 /* ---- many pairs over threads ------------------------------------------- */
 typedef struct {
   const int8_t *qcat; const int64_t *qoff;

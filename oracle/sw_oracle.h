@@ -121,6 +121,39 @@ int64_t orc_align_many(const int8_t *qcat, const int64_t *qoff,
                        orc_result *res, uint32_t *cigar, const int64_t *cigar_off,
                        int32_t nthreads);
 
+/* The suboptimal alignment behind score2 (method section; Fig. 1 caption,
+ * whose dashed arrows trace it).  Reading: it ends in column ref_end2 at the
+ * smallest row i with H(i, ref_end2) = score2; its begin is T2 relative to
+ * that end (the start-propagation DP); its CIGAR is T3 on the rectangle.
+ * score2 <= 0: every coordinate -1, no CIGAR. */
+typedef struct {
+  int64_t read_begin2, read_end2, ref_begin2;
+  int64_t cigar_len;
+} orc_sub;
+
+/* Smallest row i with H(i, col) == target (the forward recurrence up to
+ * column col), or -1. */
+int64_t orc_column_row(const int8_t *q, int64_t lq, const int8_t *r, int64_t lr,
+                       const int8_t *mat, int32_t n, int32_t o, int32_t e,
+                       int64_t col, int64_t target);
+
+/* Returns 0, or -1 on an internal inconsistency or allocation failure. */
+int orc_suboptimal(const int8_t *q, int64_t lq, const int8_t *r, int64_t lr,
+                   const int8_t *mat, int32_t n, int32_t o, int32_t e,
+                   int64_t score2, int64_t ref_end2,
+                   orc_sub *res, uint32_t *cigar, int64_t cap);
+
+/* Many pairs (score2 and ref_end2 per pair, from the primary results) over
+ * nthreads threads; CIGARs as in orc_align_many.  Returns 0 or the number of
+ * failed pairs. */
+int64_t orc_suboptimal_many(const int8_t *qcat, const int64_t *qoff,
+                            const int8_t *rcat, const int64_t *roff,
+                            const int64_t *pair_q, const int64_t *pair_r, int64_t npairs,
+                            const int8_t *mat, int32_t n, int32_t o, int32_t e,
+                            const int64_t *score2, const int64_t *ref_end2,
+                            orc_sub *res, uint32_t *cigar, const int64_t *cigar_off,
+                            int32_t nthreads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -73,6 +73,10 @@ static int dig_less(const uint8_t *a, int na, const uint8_t *b, int nb) {
 }
 
 static void visit(bctx *c, int i, int j, int64_t s, int i0, int j0) {
+  if (c->pass == 4) {   /* smallest row of a cell in column je with score best */
+    if (j == c->je && s == c->best && (c->ie < 0 || i < c->ie)) c->ie = i;
+    return;
+  }
   if (c->pass == 1) {
     if (s > c->maxcol[j]) c->maxcol[j] = s;
     if (s > c->best) {
@@ -143,6 +147,38 @@ int brute_align(const int8_t *q, int lq, const int8_t *r, int lr,
   *nops_out = 0;
   if (c.best <= 0) return 0;
   ends[0] = c.ie; ends[1] = c.je;
+  c.pass = 2;
+  for (int i0 = 0; i0 < lq; ++i0)
+    for (int j0 = 0; j0 < lr; ++j0) run_from(&c, i0, j0);
+  begins[0] = c.ib; begins[1] = c.jb;
+  c.pass = 3;
+  run_from(&c, c.ib, c.jb);
+  memcpy(ops_out, c.best_ops, (size_t)c.best_nops);
+  *nops_out = c.best_nops;
+  return 0;
+}
+
+/* The alignment behind a given (score s, column je), found the same way:
+ * the smallest row ie of a cell in column je reached by an alignment of
+ * score s; then, among alignments of score s whose cell is (ie, je), the
+ * begin with the largest jb, then the largest ib; then the op string with the
+ * smallest backward choice digits.  Returns 0 (ends/begins -1 when no
+ * alignment of score s ends in column je), or -1 when inputs exceed MAXL. */
+int brute_sub(const int8_t *q, int lq, const int8_t *r, int lr,
+              const int8_t *mat, int n, int o, int e, int je, int64_t s,
+              int *ends, int *begins, uint8_t *ops_out, int *nops_out) {
+  if (lq > MAXL || lr > MAXL || lq < 0 || lr < 0) return -1;
+  bctx c;
+  memset(&c, 0, sizeof c);
+  c.q = q; c.r = r; c.mat = mat; c.lq = lq; c.lr = lr; c.n = n; c.o = o; c.e = e;
+  c.best = s; c.ie = -1; c.je = je;
+  ends[0] = ends[1] = begins[0] = begins[1] = -1;
+  *nops_out = 0;
+  c.pass = 4;
+  for (int i0 = 0; i0 < lq; ++i0)
+    for (int j0 = 0; j0 < lr; ++j0) run_from(&c, i0, j0);
+  if (c.ie < 0) return 0;
+  ends[0] = c.ie; ends[1] = je;
   c.pass = 2;
   for (int i0 = 0; i0 < lq; ++i0)
     for (int j0 = 0; j0 < lr; ++j0) run_from(&c, i0, j0);

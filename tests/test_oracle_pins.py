@@ -326,3 +326,76 @@ def test_brute_close_gap_costs(o, e):
         if len(q) == 0:
             continue
         _check_against_brute(q, r, dna_matrix(3, -int(g.integers(1, 4))), o, e)
+
+
+# ---------------------------------------------------------------------------
+# the suboptimal alignment behind score2
+# ---------------------------------------------------------------------------
+def _score2_from_brute(b, mask_len):
+    """T4 on the brute-force max array (independent of the oracle)."""
+    if b["score1"] <= 0:
+        return 0, -1
+    lo, hi = b["begin"][1] - mask_len, b["end"][1] + mask_len
+    best, at = 0, -1
+    for j, v in enumerate(b["maxcol"]):
+        if lo <= j <= hi:
+            continue
+        if v > best:
+            best, at = int(v), j
+    return best, at
+
+
+@pytest.mark.parametrize("o,e", [(3, 1), (2, 1), (5, 2), (4, 1)])
+def test_suboptimal_matches_brute_force(o, e):
+    """End row (smallest row of column ref_end2 at score2), T2 begin relative to
+    that end, and the T3 CIGAR (o > e) of the alignment behind score2, against
+    exhaustive enumeration, with narrow masks so that score2 is often set."""
+    g = np.random.Generator(np.random.PCG64(41 + o * 10 + e))
+    mat = dna_matrix()
+    checked = 0
+    for _ in range(400):
+        lq = int(g.integers(2, 8))
+        lr = int(g.integers(3, 11))
+        q = g.integers(0, 4, size=lq).astype(np.int8)
+        r = g.integers(0, 4, size=lr).astype(np.int8)
+        if g.random() < 0.5:   # plant a second copy of part of the query
+            k = int(g.integers(1, min(lq, lr) + 1))
+            p0 = int(g.integers(0, lr - k + 1))
+            r[p0:p0 + k] = q[:k]
+        mask = int(g.integers(0, 3))
+        b = brute.enumerate_align(q, r, mat, o, e)
+        s2, e2 = _score2_from_brute(b, mask)
+        a = oracle.align(q, r, mat, o, e, mask_len=mask)
+        assert (a.score2, a.ref_end2) == (s2, e2)
+        rb2, re2, jb2, cig2 = oracle.suboptimal(q, r, mat, o, e, s2, e2)
+        if s2 <= 0:
+            assert (rb2, re2, jb2, cig2) == (-1, -1, -1, [])
+            continue
+        bs = brute.enumerate_sub(q, r, mat, o, e, e2, s2)
+        assert bs["end"] == (re2, e2), (q, r, o, e, mask)
+        assert bs["begin"] == (rb2, jb2), (q, r, o, e, mask)
+        assert bs["cigar"] == cig2, (q, r, o, e, mask)
+        assert rescore(q, r, mat, o, e, rb2, jb2, cig2)[0] == s2
+        checked += 1
+    assert checked > 100
+
+
+def test_suboptimal_column_row_and_crossing_primary():
+    """A second copy right of a long primary with a narrow mask: the
+    suboptimal alignment may reach back into the masked columns; its score is
+    score2 and it ends in column ref_end2 at the first row of that score."""
+    g = np.random.Generator(np.random.PCG64(77))
+    mat = dna_matrix()
+    for _ in range(50):
+        q = g.integers(0, 4, size=40).astype(np.int8)
+        r = np.concatenate([g.integers(0, 4, size=20), q, g.integers(0, 4, size=5), q[:25],
+                            g.integers(0, 4, size=20)]).astype(np.int8)
+        a = oracle.align(q, r, mat, 3, 1, mask_len=2)
+        rb2, re2, jb2, cig2 = oracle.suboptimal(q, r, mat, 3, 1, a.score2, a.ref_end2)
+        assert a.score2 > 0
+        assert rescore(q, r, mat, 3, 1, rb2, jb2, cig2)[0] == a.score2
+        span_r = sum(n for n, op in cig2 if op in "MD")
+        assert jb2 + span_r - 1 == a.ref_end2
+        assert oracle.column_row(q, r, mat, 3, 1, a.ref_end2, a.score2) == re2
+        for i in range(re2):   # no smaller row of that column reaches score2
+            assert oracle.column_row(q[:i + 1], r, mat, 3, 1, a.ref_end2, a.score2) in (-1, re2)
