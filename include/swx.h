@@ -72,6 +72,14 @@ extern "C" {
 #define SWX_CIGAR   2u     /* compute the CIGAR (banded pass); implies SWX_BEGIN */
 #define SWX_SCORE2  4u     /* compute score2 / ref_end2; implies SWX_BEGIN */
 #define SWX_ALL     7u
+#define SWX_SUBOPT  8u     /* also the alignment behind score2 (method section; the dashed
+                              path of Fig. 1): batch calls only, into swx_batch_out.sub_recs;
+                              implies SWX_ALL.  Reading: it ends in column ref_end2 at the
+                              smallest row whose H equals score2; its begin is T2 relative to
+                              that end (among begins of alignments reaching the end with
+                              score exactly score2: largest ref begin, then largest query
+                              begin); its CIGAR is T3 on that rectangle.  Pairs with score2 ==
+                              0 get -1 coordinates and no CIGAR. */
 
 #define SWX_MEM_HOST   0u  /* buffers are host memory */
 #define SWX_MEM_DEVICE 1u  /* buffers are device memory of the context's GPU */
@@ -140,20 +148,26 @@ typedef struct {
 
 /* Output of a batch.  recs [npairs] and cigar [cigar_cap] are caller-owned and
  * live in out_mem.  On SWX_ERANGE the records are complete but the CIGARs did
- * not fit: cigar_used holds the number of words needed. */
+ * not fit: cigar_used holds the number of words needed.  With SWX_SUBOPT,
+ * sub_recs [npairs] (also in out_mem) receives each pair's suboptimal
+ * alignment as a record -- score1 = score2, read/ref begin and end of that
+ * alignment, score2 = 0, ref_end2 = -1 -- with its CIGAR in the same arena
+ * after every primary CIGAR (cigar_off counts from the arena's start). */
 typedef struct {
   swx_rec *recs;
   uint32_t *cigar;
   int64_t cigar_cap;
   int64_t cigar_used;  /* out */
   uint32_t out_mem;
+  uint32_t pad_;
+  swx_rec *sub_recs;   /* SWX_SUBOPT only; otherwise ignored (may be NULL) */
 } swx_batch_out;
 
 /* Aligns every pair.  Synchronous with respect to the host. */
 int swx_align_batch(swx_ctx *ctx, const swx_batch *b, swx_batch_out *out);
 
-/* Upper bound on CIGAR words for a batch: sum over pairs of qlen + rlen + 1
- * (host-memory batches only; returns -1 otherwise). */
+/* Upper bound on CIGAR words for a batch: sum over pairs of qlen + rlen + 1,
+ * twice that with SWX_SUBOPT (host-memory batches only; returns -1 otherwise). */
 int64_t swx_cigar_bound(const swx_batch *b);
 
 /* ---- launch configuration ---------------------------------------------------

@@ -18,6 +18,7 @@ SWX_BEGIN = 1
 SWX_CIGAR = 2
 SWX_SCORE2 = 4
 SWX_ALL = 7
+SWX_SUBOPT = 8
 SWX_MEM_HOST = 0
 SWX_MEM_DEVICE = 1
 SWX_REF_DEVICE = 1 << 8
@@ -57,7 +58,8 @@ class SwxBatch(ctypes.Structure):
 class SwxBatchOut(ctypes.Structure):
     _fields_ = [("recs", ctypes.c_void_p), ("cigar", ctypes.c_void_p),
                 ("cigar_cap", ctypes.c_int64), ("cigar_used", ctypes.c_int64),
-                ("out_mem", ctypes.c_uint32)]
+                ("out_mem", ctypes.c_uint32), ("pad_", ctypes.c_uint32),
+                ("sub_recs", ctypes.c_void_p)]
 
 
 class SwxTuning(ctypes.Structure):
@@ -319,18 +321,18 @@ def _make_batch(matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r, flags, mas
     return b, m
 
 
-def swx_cigar_bound(matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r) -> int:
+def swx_cigar_bound(matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r, flags=0) -> int:
     arrs = [np.ascontiguousarray(x, dtype=np.int64) for x in (qoff, roff, pair_q, pair_r)]
     qc = np.ascontiguousarray(qcat, dtype=np.int8)
     rc = np.ascontiguousarray(rcat, dtype=np.int8)
-    b, _m = _make_batch(matrix, o, e, qc, arrs[0], rc, arrs[1], arrs[2], arrs[3], 0, -1,
+    b, _m = _make_batch(matrix, o, e, qc, arrs[0], rc, arrs[1], arrs[2], arrs[3], flags, -1,
                         SWX_MEM_HOST)
     return int(lib().swx_cigar_bound(ctypes.byref(b)))
 
 
 def swx_align_batch(ctx: int, matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r,
                     flags=SWX_ALL, mask_len=-1, in_mem=SWX_MEM_HOST, recs=None, cigar=None,
-                    out_mem=SWX_MEM_HOST):
+                    out_mem=SWX_MEM_HOST, sub_recs=None):
     """Raw batch call.  Host-memory inputs are numpy arrays; device-memory
     inputs are torch tensors.  recs/cigar are caller-owned outputs (numpy
     structured array of REC_DTYPE and uint32 array on the host, or torch
@@ -343,6 +345,7 @@ def swx_align_batch(ctx: int, matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair
     out.cigar_cap = int(cigar.numel() if hasattr(cigar, "numel") else
                         (len(cigar) if cigar is not None else 0))
     out.out_mem = int(out_mem)
+    out.sub_recs = _ptr(sub_recs)
     st = lib().swx_align_batch(ctx, ctypes.byref(b), ctypes.byref(out))
     return st, int(out.cigar_used)
 
@@ -411,19 +414,22 @@ class Context:
 
     def align_batch(self, matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r,
                     flags=SWX_ALL, mask_len=-1):
-        """Host-memory batch: returns (records [REC_DTYPE], cigar words)."""
+        """Host-memory batch: returns (records [REC_DTYPE], cigar words), and
+        with SWX_SUBOPT (records, cigar words, suboptimal records)."""
         qcat = np.ascontiguousarray(qcat, dtype=np.int8)
         rcat = np.ascontiguousarray(rcat, dtype=np.int8)
         qoff, roff, pair_q, pair_r = (np.ascontiguousarray(x, dtype=np.int64)
                                       for x in (qoff, roff, pair_q, pair_r))
         npairs = len(pair_q)
         recs = np.zeros(npairs, dtype=REC_DTYPE)
-        cap = swx_cigar_bound(matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r)
+        sub = np.zeros(npairs, dtype=REC_DTYPE) if flags & SWX_SUBOPT else None
+        cap = swx_cigar_bound(matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r, flags)
         cig = np.zeros(max(cap, 1), dtype=np.uint32)
         st, used = swx_align_batch(self.handle, matrix, o, e, qcat, qoff, rcat, roff, pair_q,
-                                   pair_r, flags, mask_len, SWX_MEM_HOST, recs, cig, SWX_MEM_HOST)
+                                   pair_r, flags, mask_len, SWX_MEM_HOST, recs, cig, SWX_MEM_HOST,
+                                   sub)
         _check(st, "swx_align_batch")
-        return recs, cig[:used]
+        return (recs, cig[:used]) if sub is None else (recs, cig[:used], sub)
 
 
 # ---- graph mode ---------------------------------------------------------------

@@ -541,6 +541,117 @@ hipError_t launch_records(int64_t npairs, const int32_t *score1, const int32_t *
   return hipGetLastError();
 }
 
+// ---- the suboptimal alignment (the one behind score2) -------------------------
+// Step 1: a window of the reference ending at ref_end2 that holds every
+// positive-scoring path into that column (no such path spans more than
+// W = Lq + (smax*Lq - o)/e + 1 columns; with e = 0 the whole prefix), so the
+// forward recurrence started there is exact at the window's last column.
+__global__ void k_sub_window(int64_t npairs, const int64_t *rstart, const int32_t *qlen,
+                             const int32_t *score2, const int64_t *rend2, int32_t smax, int32_t o,
+                             int32_t e, int64_t *wrstart, int64_t *wrlen, uint8_t *flag) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const bool ok = score2[p] > 0 && rend2[p] >= 0;
+  int64_t lo = 0;
+  if (ok && e > 0) {
+    const int64_t lq = qlen[p];
+    const int64_t span = lq + ((int64_t)smax * lq - o) / e + 1;
+    lo = rend2[p] - span + 1;
+    if (lo < 0) lo = 0;
+  }
+  wrstart[p] = rstart[p] + (ok ? lo : 0);
+  wrlen[p] = ok ? rend2[p] - lo + 1 : 0;
+  flag[p] = ok ? 1 : 0;
+}
+
+// Step 2: the anchored reversed pass from (end row, ref_end2): reversed
+// prefixes, target anchor + score2; pairs whose window pass did not reproduce
+// score2 at its last column are flagged as inconsistent.
+__global__ void k_sub_rev_views(int64_t npairs, const int64_t *qstart, const int64_t *rstart,
+                                const int32_t *qlen, const int32_t *score2, const int64_t *rend2,
+                                const int32_t *wscore, const int32_t *wqend, uint32_t anchor,
+                                int64_t *rqstart, int32_t *rqlen, int64_t *rrstart, int64_t *rrlen,
+                                int32_t *target, uint8_t *flag, uint8_t *err) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  bool ok = score2[p] > 0 && rend2[p] >= 0;
+  if (ok && (wscore[p] != score2[p] || wqend[p] < 0 || wqend[p] >= qlen[p])) {
+    err[p] = 1;
+    ok = false;
+  }
+  rqstart[p] = qstart[p];
+  rrstart[p] = rstart[p];
+  rqlen[p] = ok ? wqend[p] + 1 : 0;
+  rrlen[p] = ok ? rend2[p] + 1 : 0;
+  target[p] = ok ? (int32_t)(anchor + (uint32_t)score2[p]) : 0;
+  flag[p] = ok ? 1 : 0;
+}
+
+// Step 3: begin = end - reversed end; the suboptimal record's arrays.
+__global__ void k_sub_begins(int64_t npairs, const int32_t *score2, const int64_t *rend2,
+                             const int32_t *wqend, const uint8_t *flag, const int32_t *target,
+                             const int32_t *rscore, const int32_t *rqend, const int64_t *rrend,
+                             int32_t *sscore, int32_t *sqbeg, int32_t *sqend, int64_t *srbeg,
+                             int64_t *srend, uint8_t *err) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const bool ok = flag[p] != 0;
+  if (ok && rscore[p] != target[p]) err[p] = 1;
+  sscore[p] = ok ? score2[p] : 0;
+  sqend[p] = ok ? wqend[p] : -1;
+  srend[p] = ok ? rend2[p] : -1;
+  sqbeg[p] = ok ? wqend[p] - rqend[p] : -1;
+  srbeg[p] = ok ? rend2[p] - rrend[p] : -1;
+}
+
+// records' CIGAR offsets counted from the arena's start
+__global__ void k_shift_cigar_offsets(int64_t npairs, int64_t base, swx_rec_dev *recs) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  if (recs[p].cigar_len > 0) recs[p].cigar_off += base;
+}
+
+hipError_t launch_sub_window(int64_t npairs, const int64_t *rstart, const int32_t *qlen,
+                             const int32_t *score2, const int64_t *rend2, int32_t smax, int32_t o,
+                             int32_t e, int64_t *wrstart, int64_t *wrlen, uint8_t *flag,
+                             hipStream_t st) {
+  if (!npairs) return hipSuccess;
+  hipLaunchKernelGGL(k_sub_window, dim3(blocks_for(npairs, 256)), dim3(256), 0, st, npairs, rstart,
+                     qlen, score2, rend2, smax, o, e, wrstart, wrlen, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_rev_views(int64_t npairs, const int64_t *qstart, const int64_t *rstart,
+                                const int32_t *qlen, const int32_t *score2, const int64_t *rend2,
+                                const int32_t *wscore, const int32_t *wqend, uint32_t anchor,
+                                int64_t *rqstart, int32_t *rqlen, int64_t *rrstart, int64_t *rrlen,
+                                int32_t *target, uint8_t *flag, uint8_t *err, hipStream_t st) {
+  if (!npairs) return hipSuccess;
+  hipLaunchKernelGGL(k_sub_rev_views, dim3(blocks_for(npairs, 256)), dim3(256), 0, st, npairs,
+                     qstart, rstart, qlen, score2, rend2, wscore, wqend, anchor, rqstart, rqlen,
+                     rrstart, rrlen, target, flag, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_begins(int64_t npairs, const int32_t *score2, const int64_t *rend2,
+                             const int32_t *wqend, const uint8_t *flag, const int32_t *target,
+                             const int32_t *rscore, const int32_t *rqend, const int64_t *rrend,
+                             int32_t *sscore, int32_t *sqbeg, int32_t *sqend, int64_t *srbeg,
+                             int64_t *srend, uint8_t *err, hipStream_t st) {
+  if (!npairs) return hipSuccess;
+  hipLaunchKernelGGL(k_sub_begins, dim3(blocks_for(npairs, 256)), dim3(256), 0, st, npairs, score2,
+                     rend2, wqend, flag, target, rscore, rqend, rrend, sscore, sqbeg, sqend, srbeg,
+                     srend, err);
+  return hipGetLastError();
+}
+
+hipError_t shift_cigar_offsets(int64_t npairs, int64_t base, swx_rec_dev *recs, hipStream_t st) {
+  if (!npairs || !base) return hipSuccess;
+  hipLaunchKernelGGL(k_shift_cigar_offsets, dim3(blocks_for(npairs, 256)), dim3(256), 0, st, npairs,
+                     base, recs);
+  return hipGetLastError();
+}
+
 hipError_t launch_begins(int64_t npairs, const int32_t *score1, const int32_t *qend,
                          const int64_t *rend, const int32_t *rscore, const int32_t *rqend,
                          const int64_t *rrend, int32_t *qbeg, int64_t *rbeg, uint8_t *err,

@@ -182,6 +182,12 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
     V hdtop = T::zero();
     if (s > 0 && clo >= 1 && clo - 1 >= plo && clo - 1 < phi)
       hdtop = T::from(reinterpret_cast<const uint32_t *>(bH)[bnd_index(clo - 1, lane)]);
+    // anchored reversed pass: the corner before the first cell holds
+    // `anchor` and the row above the first row the gap run that leaves it;
+    // every other border starts from zero, far below, so only alignments that
+    // leave the corner (forward: end in the anchor cell, possibly with a
+    // deletion run) reach anchor + target
+    if (REV && NH == 1 && s == 0 && a.anchor) hdtop = T::splat(a.anchor);
     uint32_t sb[NH];      // encoded strip best (value * 32 + row code)
     uint32_t sbk[NH];     // sb | 31: its value part, for the strict comparison
     int32_t sbcol[NH];
@@ -283,7 +289,17 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
           X[0][0] = lx[k][0];
           X[0][1] = lx[k][1];
         }
-        const V hup = T::from(word_of(ch, k));
+        V hup = T::from(word_of(ch, k));
+        // anchored reversed pass: the row above the first row is the run of
+        // gap symbols that may follow the anchor cell's alignment (a forward
+        // alignment may end in a deletion run: its end cell is then in the
+        // gap state), H = anchor - o - c*e at column c
+        if constexpr (REV && NH == 1) {   // anchored passes run on 32-bit lanes only
+          if (s == 0 && a.anchor) {
+            const uint32_t gap = (uint32_t)a.o + (uint32_t)c * (uint32_t)a.e;
+            hup = T::splat(a.anchor > gap ? a.anchor - gap : 0u);
+          }
+        }
         const V hdiag_in = hdtop;
         V F = T::from(word_of(cf, k));
         const V cmin = T::from(word_of(cc, k));
@@ -321,7 +337,9 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
         for (int h = 0; h < NH; ++h) {
           const uint32_t v = T::half(cm, h);
           const uint32_t vk = v | 31u;
-          const bool imp = vk > sbk[h];
+          // lastcol (32-bit lanes): only the pair's last column (padded
+          // column rp - 1) counts
+          const bool imp = vk > sbk[h] && (REV || NH == 2 || !a.lastcol || c == rp - 1);
           sb[h] = imp ? v : sb[h];
           sbk[h] = imp ? vk : sbk[h];
           sbcol[h] = imp ? (int32_t)c : sbcol[h];

@@ -236,7 +236,7 @@ static int plan_pass(swx_ctx *ctx, const Scoring &sc, const int64_t *ids, int64_
 // events mark_fill and mark_fill + 1 bracket the fill kernel alone
 static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &view, bool rev,
                     const int32_t *d_target, FillOut out, int64_t score_bound,
-                    int mark_fill = -1) {
+                    int mark_fill = -1, uint32_t anchor = 0, int lastcol = 0) {
   hipStream_t st = ctx->stream;
   if (pl.ntasks == 0) {
     if (mark_fill >= 0) {
@@ -284,6 +284,8 @@ static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &v
   a.sched = ctx->fill_sched;
   a.cus = ctx->cus;
   a.queue = ctx->queue;
+  a.anchor = anchor;
+  a.lastcol = lastcol;
   if (mark_fill >= 0) HIP_TRY(hipEventRecord(ctx->ev[mark_fill], st));
   HIP_TRY(inter_fill(a, pl.lane_bits, pl.R, st));
   if (mark_fill >= 0) HIP_TRY(hipEventRecord(ctx->ev[mark_fill + 1], st));
@@ -785,6 +787,7 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
   DevArena &A = ctx->arena;
   hipStream_t st = ctx->stream;
   const int64_t np = b.npairs;
+  if (flags & SWX_SUBOPT) flags |= SWX_ALL;
   if (flags & (SWX_CIGAR | SWX_SCORE2)) flags |= SWX_BEGIN;
   int rc;
   HIP_TRY(hipEventRecord(ctx->ev[0], st));
@@ -925,6 +928,87 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
     }
   }
   HIP_TRY(hipEventRecord(ctx->ev[6], st));
+
+  // The suboptimal alignment behind score2: its end row (a forward pass over
+  // a window of the reference ending at ref_end2, best taken in the last
+  // column only), its begin (the reversed pass anchored at that end, on
+  // 32-bit lanes offset by kAnchor so that only alignments starting at the
+  // anchor cell can reach the target), its CIGAR (the banded traceback),
+  // placed in the arena after every primary CIGAR.
+  if (flags & SWX_SUBOPT) {
+    constexpr uint32_t kAnchor = 1u << 25;
+    if (score_bound >= (int64_t(1) << 24))
+      return fail(SWX_EOVERFLOW, "scores too large for the suboptimal alignment's anchored pass");
+    int64_t *wrs = A.get<int64_t>(np), *wrl = A.get<int64_t>(np), *wre = A.get<int64_t>(np);
+    int32_t *wsc = A.get<int32_t>(np), *wqe = A.get<int32_t>(np);
+    uint8_t *wov = A.get<uint8_t>(np), *sfl = A.get<uint8_t>(np), *slb = A.get<uint8_t>(np);
+    int64_t *rqs = A.get<int64_t>(np), *rrs = A.get<int64_t>(np), *rrl = A.get<int64_t>(np);
+    int32_t *rql = A.get<int32_t>(np), *tgt = A.get<int32_t>(np), *rsc = A.get<int32_t>(np);
+    int32_t *rqe = A.get<int32_t>(np);
+    int64_t *rre = A.get<int64_t>(np);
+    uint8_t *rov = A.get<uint8_t>(np);
+    int32_t *s_score = A.get<int32_t>(np), *s_qbeg = A.get<int32_t>(np), *s_qend = A.get<int32_t>(np);
+    int64_t *s_rbeg = A.get<int64_t>(np), *s_rend = A.get<int64_t>(np);
+    int32_t *s_cig_len = A.get<int32_t>(np);
+    int64_t *s_cig_off = A.get<int64_t>(np + 1);
+    if (!wrs || !wrl || !wre || !wsc || !wqe || !wov || !sfl || !slb || !rqs || !rrs || !rrl ||
+        !rql || !tgt || !rsc || !rqe || !rre || !rov || !s_score || !s_qbeg || !s_qend ||
+        !s_rbeg || !s_rend || !s_cig_len || !s_cig_off)
+      return fail(SWX_ENOMEM, "device pool exhausted (suboptimal)");
+    HIP_TRY(launch_sub_window(np, rstart, qlen, score2, rend2, sc.smax, sc.o, sc.e, wrs, wrl, sfl,
+                              st));
+    HIP_TRY(hipMemsetAsync(wsc, 0, sizeof(int32_t) * np, st));
+    HIP_TRY(hipMemsetAsync(wqe, 0xFF, sizeof(int32_t) * np, st));
+    int64_t *ids = nullptr, cnt = 0;
+    if ((rc = select_flagged(ctx, sfl, np, &ids, &cnt))) return rc;
+    if (cnt > 0) {
+      Plan pw;
+      if ((rc = plan_pass(ctx, sc, ids, cnt, qlen, wrl, nullptr, 32, R, pw))) return rc;
+      PairView wview{qstart, wrs, qlen, wrl, b.qcat, b.rcat, 0};
+      FillOut wout{wsc, wqe, wre, wov};
+      if ((rc = run_fill(ctx, pw, sc, wview, false, nullptr, wout, score_bound, -1, 0, 1)))
+        return rc;
+    }
+    HIP_TRY(launch_sub_rev_views(np, qstart, rstart, qlen, score2, rend2, wsc, wqe, kAnchor, rqs,
+                                 rql, rrs, rrl, tgt, sfl, err, st));
+    HIP_TRY(hipMemsetAsync(rsc, 0, sizeof(int32_t) * np, st));
+    if ((rc = select_flagged(ctx, sfl, np, &ids, &cnt))) return rc;
+    if (cnt > 0) {
+      Plan pr;
+      if ((rc = plan_pass(ctx, sc, ids, cnt, rql, rrl, nullptr, 32, R, pr))) return rc;
+      PairView rview{rqs, rrs, rql, rrl, b.qcat, b.rcat, 1};
+      FillOut rout{rsc, rqe, rre, rov};
+      if ((rc = run_fill(ctx, pr, sc, rview, true, tgt, rout, score_bound + kAnchor, -1, kAnchor,
+                         0)))
+        return rc;
+    }
+    HIP_TRY(launch_sub_begins(np, score2, rend2, wqe, sfl, tgt, rsc, rqe, rre, s_score, s_qbeg,
+                              s_qend, s_rbeg, s_rend, err, st));
+    // CIGARs after the primaries (cigar_used holds their total even when they did not fit)
+    HIP_TRY(hipMemsetAsync(s_cig_len, 0, sizeof(int32_t) * np, st));
+    HIP_TRY(hipMemsetAsync(s_cig_off, 0, sizeof(int64_t) * (np + 1), st));
+    const int64_t base = out->cigar_used;
+    swx_batch_out so = *out;
+    so.cigar = (out->cigar && base <= out->cigar_cap) ? out->cigar + base : nullptr;
+    so.cigar_cap = out->cigar_cap > base ? out->cigar_cap - base : 0;
+    uint32_t sflags = SWX_BEGIN | SWX_CIGAR;
+    int rc_sub = SWX_OK;
+    if ((rc = run_traceback(ctx, sc, b, np, s_score, s_qbeg, s_qend, s_rbeg, s_rend, qstart,
+                            rstart, qlen, rlen, s_cig_len, s_cig_off, err, &so, &sflags, &rc_sub)))
+      return rc;
+    out->cigar_used = base + so.cigar_used;
+    if (rc_sub != SWX_OK) rc_range = rc_sub;
+    if (!(flags & SWX_CIGAR)) sflags &= ~SWX_CIGAR;   // the primaries did not fit either
+    HIP_TRY(hipMemsetAsync(slb, 32, np, st));
+    swx_rec_dev *srec = (out->out_mem == SWX_MEM_DEVICE) ? (swx_rec_dev *)out->sub_recs
+                                                         : A.get<swx_rec_dev>(np);
+    if (!srec) return fail(SWX_ENOMEM, "device pool exhausted");
+    HIP_TRY(launch_records(np, s_score, s_score, s_qbeg, s_qend, s_rbeg, s_rend, s_rend, s_cig_off,
+                           s_cig_len, slb, sflags, srec, st));
+    if (sflags & SWX_CIGAR) HIP_TRY(shift_cigar_offsets(np, base, srec, st));
+    if (out->out_mem != SWX_MEM_DEVICE)
+      HIP_TRY(hipMemcpyAsync(out->sub_recs, srec, sizeof(swx_rec) * np, hipMemcpyDeviceToHost, st));
+  }
 
   // records
   swx_rec_dev *drec = (out->out_mem == SWX_MEM_DEVICE) ? (swx_rec_dev *)out->recs
@@ -1580,7 +1664,7 @@ int64_t swx_cigar_bound(const swx_batch *b) {
     if (qi < 0 || qi >= b->nq || ri < 0 || ri >= b->nr) return -1;
     s += (b->qoff[qi + 1] - b->qoff[qi]) + (b->roff[ri + 1] - b->roff[ri]) + 1;
   }
-  return s;
+  return (b->flags & SWX_SUBOPT) ? 2 * s : s;
 }
 
 static int align_batch_locked(swx_ctx *ctx, const swx_batch *b, swx_batch_out *out) {
@@ -1595,7 +1679,9 @@ static int align_batch_locked(swx_ctx *ctx, const swx_batch *b, swx_batch_out *o
     return fail(SWX_EINVAL, "null code arrays");
   if (!out || (b->npairs && !out->recs)) return fail(SWX_EINVAL, "null output");
   if (b->in_mem > 1 || out->out_mem > 1) return fail(SWX_EINVAL, "bad memory-space flag");
-  if (b->flags & ~SWX_ALL) return fail(SWX_EINVAL, "unknown flag bits");
+  if (b->flags & ~(SWX_ALL | SWX_SUBOPT)) return fail(SWX_EINVAL, "unknown flag bits");
+  if ((b->flags & SWX_SUBOPT) && b->npairs && !out->sub_recs)
+    return fail(SWX_EINVAL, "SWX_SUBOPT needs sub_recs");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(SWX_EDEVICE, "hipSetDevice failed");
   ctx->arena.reset();
   DevArena &A = ctx->arena;

@@ -89,6 +89,10 @@ struct InterArgs {
                               // 2 resident waves on a device queue, largest first
   int32_t cus;                // compute units (sched 2 sizes its grid to them)
   unsigned long long *queue;  // sched 2: the queue's counter (zeroed by the launch)
+  uint32_t anchor;            // reversed pass on 32-bit lanes: start value of the first cell
+                              // (0: a local pass, every border starts from zero)
+  int32_t lastcol;            // forward pass on 32-bit lanes: the best counts only the
+                              // last column
 };
 
 // Largest score the 16-bit inter path represents exactly together with its

@@ -277,6 +277,23 @@ hipError_t launch_records(int64_t npairs, const int32_t *score1, const int32_t *
                           const int64_t *rend, const int64_t *rend2, const int64_t *cig_off,
                           const int32_t *cig_len, const uint8_t *lane_bits, uint32_t flags,
                           swx_rec_dev *recs, hipStream_t st);
+// the suboptimal alignment: window views, anchored reversed views, begins,
+// and CIGAR offsets of records counted from the arena's start
+hipError_t launch_sub_window(int64_t npairs, const int64_t *rstart, const int32_t *qlen,
+                             const int32_t *score2, const int64_t *rend2, int32_t smax, int32_t o,
+                             int32_t e, int64_t *wrstart, int64_t *wrlen, uint8_t *flag,
+                             hipStream_t st);
+hipError_t launch_sub_rev_views(int64_t npairs, const int64_t *qstart, const int64_t *rstart,
+                                const int32_t *qlen, const int32_t *score2, const int64_t *rend2,
+                                const int32_t *wscore, const int32_t *wqend, uint32_t anchor,
+                                int64_t *rqstart, int32_t *rqlen, int64_t *rrstart, int64_t *rrlen,
+                                int32_t *target, uint8_t *flag, uint8_t *err, hipStream_t st);
+hipError_t launch_sub_begins(int64_t npairs, const int32_t *score2, const int64_t *rend2,
+                             const int32_t *wqend, const uint8_t *flag, const int32_t *target,
+                             const int32_t *rscore, const int32_t *rqend, const int64_t *rrend,
+                             int32_t *sscore, int32_t *sqbeg, int32_t *sqend, int64_t *srbeg,
+                             int64_t *srend, uint8_t *err, hipStream_t st);
+hipError_t shift_cigar_offsets(int64_t npairs, int64_t base, swx_rec_dev *recs, hipStream_t st);
 hipError_t launch_begins(int64_t npairs, const int32_t *score1, const int32_t *qend,
                          const int64_t *rend, const int32_t *rscore, const int32_t *rqend,
                          const int64_t *rrend, int32_t *qbeg, int64_t *rbeg, uint8_t *err,

@@ -199,3 +199,61 @@ def test_invalid_symbols_rejected(ctx):
         ctx.align_batch(b.matrix, b.gap_open, b.gap_extend, b.qcat, b.qoff, b.rcat, b.roff,
                         b.pair_q, b.pair_r)
     assert ei.value.status == -1
+
+
+def _two_copy_pairs(seed, npairs, alphabet=4, o=3, e=1):
+    """References holding two mutated copies of the query (the second often
+    partial), so that score2 comes from a real second hit."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    qs, rs = [], []
+    for _ in range(npairs):
+        lq = int(g.integers(8, 120))
+        q = g.integers(0, alphabet, size=lq).astype(np.int8)
+        parts = [g.integers(0, alphabet, size=int(g.integers(0, 60)))]
+        for k in range(2):
+            c = q[:int(g.integers(max(4, lq // 3), lq + 1))] if k else q
+            c = c.copy()
+            sub = g.random(len(c)) < 0.05
+            c[sub] = (c[sub] + g.integers(1, alphabet, size=int(sub.sum()))) % alphabet
+            parts += [c, g.integers(0, alphabet, size=int(g.integers(0, 40)))]
+        if g.random() < 0.5:
+            parts = parts[::-1]
+        qs.append(q)
+        rs.append(np.concatenate(parts).astype(np.int8))
+    mat = W.dna_matrix(n=alphabet) if alphabet <= 8 else W.protein_matrix_standin()
+    return W.from_lists(f"two-copies-{seed}", mat, o, e, qs, rs)
+
+
+@pytest.mark.parametrize("mask_len", [2, -1])
+def test_suboptimal_alignment(ctx, mask_len):
+    """SWX_SUBOPT: the alignment behind score2 (end row, begin, CIGAR) equals
+    the oracle's, and the primary records are unchanged."""
+    for b in (_two_copy_pairs(71, 120), W.random_pairs(72, 150, (1, 90), (0, 300), planted=0.8),
+              _two_copy_pairs(73, 60, alphabet=24, o=11, e=1)):
+        _say(f"[parity] {b.name}: suboptimal, mask_len={mask_len}")
+        recs, cig, sub = ctx.align_batch(b.matrix, b.gap_open, b.gap_extend, b.qcat, b.qoff,
+                                         b.rcat, b.roff, b.pair_q, b.pair_r,
+                                         swx.SWX_ALL | swx.SWX_SUBOPT, mask_len)
+        ref, rcig, rcoff = oracle.align_many(b.qcat, b.qoff, b.rcat, b.roff, b.pair_q, b.pair_r,
+                                             b.matrix, b.gap_open, b.gap_extend, swx.SWX_ALL,
+                                             mask_len)
+        for k, f in enumerate(FIELDS):
+            assert np.array_equal(recs[f].astype(np.int64), ref[:, k]), f
+        sref, scig, scoff = oracle.suboptimal_many(b.qcat, b.qoff, b.rcat, b.roff, b.pair_q,
+                                                   b.pair_r, b.matrix, b.gap_open, b.gap_extend,
+                                                   ref[:, 1], ref[:, 6])
+        s2 = ref[:, 1]
+        assert np.array_equal(sub["score1"].astype(np.int64), s2)
+        for f, col in (("read_begin1", 0), ("read_end1", 1), ("ref_begin1", 2)):
+            got = sub[f].astype(np.int64)
+            bad = np.nonzero(got != sref[:, col])[0]
+            assert len(bad) == 0, f"{f}: pair {bad[0]} gpu {got[bad[0]]} oracle {sref[bad[0], col]}"
+        assert np.array_equal(sub["ref_end1"].astype(np.int64), ref[:, 6])
+        assert (sub["score2"] == 0).all() and (sub["ref_end2"] == -1).all()
+        for p in range(b.npairs):
+            g = cig[sub["cigar_off"][p]:sub["cigar_off"][p] + sub["cigar_len"][p]]
+            e = scig[scoff[p]:scoff[p] + sref[p, 3]]
+            assert np.array_equal(g, e), (p, swx.decode_cigar(g), swx.decode_cigar(e))
+            pg = cig[recs["cigar_off"][p]:recs["cigar_off"][p] + recs["cigar_len"][p]]
+            assert np.array_equal(pg, rcig[rcoff[p]:rcoff[p] + ref[p, 7]]), p
+        assert (s2 > 0).sum() > b.npairs // 3
