@@ -176,21 +176,39 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
   const int64_t kend = w - m - dlo;
   // Rows go in blocks of UB: the query symbols and the window's next
   // reference bytes of block b+1 are requested while block b is computed.
+  // The loads are unconditional (indices clamped into the sequences), so
+  // they land straight in their registers; values outside the pair are
+  // masked when decoded.
   constexpr int UB = BW <= 16 ? 8 : (BW <= 32 ? 4 : 2);
-  auto load_block = [&](int64_t i0, uint32_t (&qo)[UB], uint32_t (&no)[UB]) {
+  const int8_t *qq = live ? q : (const int8_t *)a.matrix;   // readable bytes for empty lanes
+  const int8_t *rr = live ? r : (const int8_t *)a.matrix;
+  const int64_t mq = live ? m : 1, wr = live ? w : 1;
+  auto load_block = [&](int64_t i0, int32_t (&qo)[UB], int32_t (&no)[UB]) {
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      int64_t x = i0 + u - 1;                       // query index of row i0 + u
+      x = x < 0 ? 0 : (x > mq - 1 ? mq - 1 : x);
+      qo[u] = qq[x];
+      int64_t y = i0 + u + dlo + 4 * NW - 1;   // reference index of the window's new column
+      y = y < 0 ? 0 : (y > wr - 1 ? wr - 1 : y);
+      no[u] = rr[y];
+    }
+  };
+  int32_t qraw[UB], nraw[UB];
+  load_block(1, qraw, nraw);
+  for (int64_t i0 = 1; i0 <= tk.rows; i0 += UB) {
+    uint32_t qb[UB], nbb[UB];
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
       const int64_t i = i0 + u;
-      const int32_t c = (live && i <= m) ? (int32_t)q[i - 1] : -1;
-      qo[u] = (c >= 0 && c < a.n) ? (uint32_t)c : 0xFFu;
-      no[u] = ref_byte(i + 1 + dlo + 4 * NW - 1);
+      const int32_t c = (live && i <= m) ? qraw[u] : -1;
+      qb[u] = (c >= 0 && c < a.n) ? (uint32_t)c : 0xFFu;
+      const int64_t j = i + 1 + dlo + 4 * NW - 1;   // 1-based column entering the window
+      const int32_t cr = (live && j >= 1 && j <= w) ? nraw[u] : 0;
+      const uint32_t v = (cr >= 0 && cr < a.n) ? (uint32_t)cr : 0u;   // a bad code never indexes a table
+      nbb[u] = LUT4 ? v * 8u : v;
     }
-  };
-  uint32_t qb[UB], nbb[UB];
-  load_block(1, qb, nbb);
-  for (int64_t i0 = 1; i0 <= tk.rows; i0 += UB) {
-    uint32_t qn[UB], nn[UB];
-    load_block(i0 + UB, qn, nn);
+    load_block(i0 + UB, qraw, nraw);
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
       const int64_t i = i0 + u;
@@ -226,9 +244,8 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
         ev = eij;
         hleft = h;
       }
-      uint32_t *drow = dir + (int64_t)i * ND * 64;
 #pragma unroll
-      for (int d = 0; d < ND; ++d) drow[(int64_t)d * 64 + lane] = dw[d];
+      for (int d = 0; d < ND; ++d) dir[(i * ND + d) * 64 + lane] = dw[d];
       if (live && i == m) {
 #pragma unroll
         for (int k = 0; k < BW; ++k)
@@ -239,8 +256,6 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
       for (int d = 0; d < NW - 1; ++d) win[d] = __builtin_amdgcn_alignbyte(win[d + 1], win[d], 1);
       win[NW - 1] = (win[NW - 1] >> 8) | (nbb[u] << 24);
     }
-#pragma unroll
-    for (int u = 0; u < UB; ++u) { qb[u] = qn[u]; nbb[u] = nn[u]; }
   }
   if (!live) return;
   if (s1 <= 0) { a.cig_len[p] = 0; return; }
