@@ -468,15 +468,24 @@ __global__ __launch_bounds__(256) void k_inter_rsym(PackArgs a) {
   uint2 *dst = a.rsym + rsym_offset(tk.bnd_off);
   for (int64_t c0 = 0; c0 < tk.rp; c0 += kRsymChunk) {
     const int64_t c = c0 + threadIdx.x;
-    for (int s = 0; s < nslots; ++s) {
-      const int64_t j = c - s_pad[s];
-      const int64_t len = s_len[s];
-      uint8_t v = pad_sym;
-      if (j >= 0 && j < len) {
-        const int8_t c = s_base[s][reversed ? len - 1 - j : j];
-        v = (c >= 0 && c < a.n) ? (uint8_t)c : pad_sym;   // a bad code never indexes a table
+    // slots in groups of 16: the group's loads are all in flight before the
+    // first byte is written to the tile
+    for (int s0 = 0; s0 < nslots; s0 += 16) {
+      int8_t raw[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int s = s0 + u;
+        const int64_t j = c - s_pad[s];
+        const int64_t len = s_len[s];
+        const bool in = j >= 0 && j < len;
+        raw[u] = in ? s_base[s][reversed ? len - 1 - j : j] : (int8_t)-1;
       }
-      tile[s * kRsymStride + threadIdx.x] = v;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int8_t x = raw[u];
+        tile[(s0 + u) * kRsymStride + threadIdx.x] =
+            (x >= 0 && x < a.n) ? (uint8_t)x : pad_sym;   // a bad code never indexes a table
+      }
     }
     __syncthreads();
     int64_t ng = (tk.rp - c0) / 4;
