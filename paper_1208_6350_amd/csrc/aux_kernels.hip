@@ -245,28 +245,59 @@ __global__ __launch_bounds__(256) void k_score2_inter(Score2InterArgs a) {
   if (tid >= a.ntasks) return;
   const InterTask tk = a.tasks[tid];
   const uint32_t *bC = a.bnd + tk.bnd_off + 2 * (int64_t)tk.rp * 64;
-  for (int h = 0; h < a.halves; ++h) {
+  // a lane owns slots lane and lane + 64 (16-bit halves of one word): both
+  // scans share one pass over the plane
+  int64_t pr[2], lr[2], padr[2], lo[2], hi[2], at[2];
+  int32_t best[2];
+  int64_t gfirst = tk.rp / 4;
+  for (int h = 0; h < 2; ++h) {
     const int s = lane + 64 * h;
-    if (s >= tk.nslots) continue;
-    const int64_t p = a.slot_pair[tk.slot_base + s];
-    if (p < 0) continue;
-    int32_t best = 0;
-    int64_t at = -1;
-    if (a.score1[p] > 0) {
-      const int64_t lr = a.rlen[p];
-      const int64_t padr = tk.rp - lr;
+    pr[h] = (h < a.halves && s < tk.nslots) ? a.slot_pair[tk.slot_base + s] : -1;
+    best[h] = 0;
+    at[h] = -1;
+    lr[h] = 0;
+    padr[h] = tk.rp;
+    lo[h] = hi[h] = 0;
+    if (pr[h] >= 0 && a.score1[pr[h]] > 0) {
+      const int64_t p = pr[h];
+      lr[h] = a.rlen[p];
+      padr[h] = tk.rp - lr[h];
       int64_t m = a.mask_len;
       if (m < 0) { m = a.qlen[p] / 2; if (m < 15) m = 15; }
-      const int64_t lo = a.rbeg[p] - m, hi = a.rend[p] + m;
-      for (int64_t j = 0; j < lr; ++j) {
-        if (j >= lo && j <= hi) continue;
-        const uint32_t wv = bC[bnd_index(j + padr, lane)];
-        const int32_t v = (a.halves == 2) ? (int32_t)(h ? (wv >> 16) : (wv & 0xFFFFu)) : (int32_t)wv;
-        if (v > best) { best = v; at = j; }
+      lo[h] = a.rbeg[p] - m;
+      hi[h] = a.rend[p] + m;
+      gfirst = min(gfirst, padr[h] / 4);
+    }
+  }
+  // the plane holds 4 columns per 16-byte word: 4 words (16 columns) are
+  // read at a time, all in flight together, and scanned in column order
+  const uint4 *w4 = reinterpret_cast<const uint4 *>(bC);
+  const int64_t gend = tk.rp / 4;
+  for (int64_t g0 = gfirst; g0 < gend; g0 += 4) {
+    uint4 wd[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) wd[u] = w4[min(g0 + u, gend - 1) * 64 + lane];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t ws[4] = {wd[u].x, wd[u].y, wd[u].z, wd[u].w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int64_t c = 4 * (g0 + u) + k;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int64_t j = c - padr[h];
+          const bool in = g0 + u < gend && j >= 0 && j < lr[h] && (j < lo[h] || j > hi[h]);
+          const int32_t v = (a.halves == 2) ? (int32_t)(h ? (ws[k] >> 16) : (ws[k] & 0xFFFFu))
+                                            : (int32_t)ws[k];
+          if (in && v > best[h]) { best[h] = v; at[h] = j; }
+        }
       }
     }
-    a.score2[p] = best;
-    a.rend2[p] = best > 0 ? at : -1;
+  }
+  for (int h = 0; h < 2; ++h) {
+    if (pr[h] < 0) continue;
+    a.score2[pr[h]] = best[h];
+    a.rend2[pr[h]] = best[h] > 0 ? at[h] : -1;
   }
 }
 
