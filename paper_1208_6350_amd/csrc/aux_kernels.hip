@@ -375,6 +375,29 @@ __global__ void k_begins(int64_t npairs, const int32_t *score1, const int32_t *q
 }
 
 // ---- input validation -------------------------------------------------------
+// Any byte of p[0, len) outside [0, n), 1 <= n <= 32.  The 16-byte-aligned
+// body is read in 16-byte words and tested four bytes at a time: a byte b is
+// bad when its top bit is set (negative) or when (b & 0x7F) + 128 - n reaches
+// 128 (no carry leaves the byte, since 127 + 127 < 256).
+__device__ __forceinline__ bool symbols_bad(const int8_t *p, int64_t len, int32_t n, int64_t tid,
+                                            int64_t stride) {
+  const uint32_t add = (uint32_t)(128 - n) * 0x01010101u;
+  const int64_t head = (int64_t)((16 - ((uintptr_t)p & 15)) & 15);
+  const int64_t h = head < len ? head : len;
+  const int64_t nw = (len - h) / 16;
+  bool bad = false;
+  for (int64_t k = tid; k < h; k += stride) bad |= p[k] < 0 || p[k] >= n;
+  const uint4 *w = reinterpret_cast<const uint4 *>(p + h);
+  for (int64_t k = tid; k < nw; k += stride) {
+    const uint4 v = w[k];
+    const uint32_t x[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bad |= ((x[i] | ((x[i] & 0x7F7F7F7Fu) + add)) & 0x80808080u) != 0;
+  }
+  for (int64_t k = h + 16 * nw + tid; k < len; k += stride) bad |= p[k] < 0 || p[k] >= n;
+  return bad;
+}
+
 __global__ void k_validate(ValidateArgs a) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -390,14 +413,8 @@ __global__ void k_validate(ValidateArgs a) {
   for (int64_t k = tid; k < a.npairs; k += stride) {
     if (a.pair_q[k] < 0 || a.pair_q[k] >= a.nq || a.pair_r[k] < 0 || a.pair_r[k] >= a.nr) bad |= 2u;
   }
-  for (int64_t k = tid; k < a.qcat_len; k += stride) {
-    const int8_t c = a.qcat[k];
-    if (c < 0 || c >= a.n) bad |= 4u;
-  }
-  for (int64_t k = tid; k < a.rcat_len; k += stride) {
-    const int8_t c = a.rcat[k];
-    if (c < 0 || c >= a.n) bad |= 8u;
-  }
+  if (symbols_bad(a.qcat, a.qcat_len, a.n, tid, stride)) bad |= 4u;
+  if (symbols_bad(a.rcat, a.rcat_len, a.n, tid, stride)) bad |= 8u;
   if (bad) atomicOr(a.bad, bad);
 }
 

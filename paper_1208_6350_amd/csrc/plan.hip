@@ -31,8 +31,16 @@ __global__ void k_plan_keys(int64_t n, const int64_t *n_dev, const int64_t *ids,
   const uint64_t qc = (uint64_t)((q + R - 1) / R);
   uint64_t r = (uint64_t)rlen[p];
   if (r > 0xFFFFFFFull) r = 0xFFFFFFFull;
+  // band class: the band half-width, except that pairs whose band spans
+  // nearly the whole reference (2 * band + R >= rlen: a strip's window then
+  // leaves out few columns) are grouped by size alone, after the banded ones,
+  // and unbanded pairs come last
   uint64_t b = 0;
-  if (band) b = band[p] < 0 ? 0xFFFFFull : (uint64_t)(band[p] > 0xFFFFE ? 0xFFFFE : band[p]);
+  if (band) {
+    if (band[p] < 0) b = 0xFFFFFull;
+    else if (2 * (int64_t)band[p] + R >= (int64_t)rlen[p]) b = 0xFFFFEull;
+    else b = (uint64_t)(band[p] > 0xFFFFD ? 0xFFFFD : band[p]);
+  }
   keys[k] = (b << 44) | ((qc > 0xFFFF ? 0xFFFF : qc) << 28) | r;
   vals[k] = p;
 }

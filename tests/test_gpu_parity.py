@@ -201,6 +201,64 @@ def test_invalid_symbols_rejected(ctx):
     assert ei.value.status == -1
 
 
+@pytest.mark.parametrize("which", ["q", "r"])
+def test_invalid_symbol_anywhere_is_found(ctx, which):
+    # symbols are checked 16 bytes at a time after an unaligned head: a bad
+    # byte at every position of the first words, of the last words and in
+    # the middle, with each kind of bad value (n, the top of the range, and
+    # negative ones), is found; the untouched batch passes
+    b = W.random_pairs(607, 40, (30, 90), (30, 90))
+    ctx.align_batch(b.matrix, b.gap_open, b.gap_extend, b.qcat, b.qoff, b.rcat, b.roff,
+                    b.pair_q, b.pair_r)
+    cat = b.qcat if which == "q" else b.rcat
+    n = b.matrix.shape[0]
+    L = len(cat)
+    spots = list(range(0, 40)) + list(range(L // 2 - 20, L // 2 + 20)) + list(range(L - 40, L))
+    for k, pos in enumerate(spots):
+        bad = [n, 31, 32, 127, -1, -128][k % 6]
+        keep = int(cat[pos])
+        cat[pos] = bad
+        with pytest.raises(swx.SwxError) as ei:
+            ctx.align_batch(b.matrix, b.gap_open, b.gap_extend, b.qcat, b.qoff, b.rcat, b.roff,
+                            b.pair_q, b.pair_r)
+        assert ei.value.status == -1, (which, pos, bad)
+        cat[pos] = keep
+
+
+@pytest.mark.parametrize("shift", [0, 1, 7, 15])
+def test_invalid_symbol_in_unaligned_device_input(ctx, shift):
+    # device-resident codes starting at every alignment class: the unaligned
+    # head, the 16-byte body and the tail are each checked
+    import torch
+    b = W.random_pairs(608, 30, (20, 60), (20, 60))
+    dev = torch.device("cuda:0")
+    to = lambda x: torch.as_tensor(np.ascontiguousarray(x)).to(dev)
+    L = len(b.rcat)
+    buf = torch.zeros(L + 32, dtype=torch.int8, device=dev)
+    rc = buf[shift:shift + L]
+    dq, dqo, dro, dpq, dpr = to(b.qcat), to(b.qoff), to(b.roff), to(b.pair_q), to(b.pair_r)
+    recs = torch.empty(b.npairs * swx.REC_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    cig = torch.empty(int(b.qlen().sum() + b.rlen().sum() + b.npairs), dtype=torch.int32,
+                      device=dev)
+
+    def run(cat):
+        rc.copy_(torch.as_tensor(cat).to(dev))
+        torch.cuda.synchronize()
+        st, _ = swx.swx_align_batch(ctx.handle, b.matrix, b.gap_open, b.gap_extend, dq, dqo, rc,
+                                    dro, dpq, dpr, swx.SWX_ALL, -1, swx.SWX_MEM_DEVICE, recs, cig,
+                                    swx.SWX_MEM_DEVICE)
+        torch.cuda.synchronize()
+        return st
+
+    assert run(b.rcat) == 0
+    n = b.matrix.shape[0]
+    for pos in (0, 1, 14, 15, 16, 17, L // 2, L - 17, L - 16, L - 2, L - 1):
+        for bad in (n, -1):
+            cat = b.rcat.copy()
+            cat[pos] = bad
+            assert run(cat) == -1, (shift, pos, bad)
+
+
 def _two_copy_pairs(seed, npairs, alphabet=4, o=3, e=1):
     """References holding two mutated copies of the query (the second often
     partial), so that score2 comes from a real second hit."""
