@@ -447,7 +447,7 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
   }
   if (hc[5] > 0) {   // bands wider than 64 diagonals: row strips, columns swept
     const int64_t nc = hc[5];
-    const int64_t nt = (nc + 63) / 64;
+    const int64_t nt = (nc + kTbwSlots - 1) / kTbwSlots;
     TbwTask *tasks = A.get<TbwTask>(nt);
     int64_t *dsz = A.get<int64_t>(nt + 1), *doff = A.get<int64_t>(nt + 1);
     int64_t *bsz = A.get<int64_t>(nt + 1), *boff = A.get<int64_t>(nt + 1);
@@ -1439,16 +1439,18 @@ static int graph_alloc(GraphState &g) {
   }
   {
     FixedTb &t = g.tb[5];
-    t.cap_tasks = capT;
-    t.tasks = A.get<TbwTask>(capT);
-    t.dsz = A.get<int64_t>(capT + 1); t.doff = A.get<int64_t>(capT + 1);
-    t.bsz = A.get<int64_t>(capT + 1); t.boff = A.get<int64_t>(capT + 1);
+    const int64_t capW = (B + kTbwSlots - 1) / kTbwSlots;
+    t.cap_tasks = capW;
+    t.tasks = A.get<TbwTask>(capW);
+    t.dsz = A.get<int64_t>(capW + 1); t.doff = A.get<int64_t>(capW + 1);
+    t.bsz = A.get<int64_t>(capW + 1); t.boff = A.get<int64_t>(capW + 1);
     // a safe band is at most m + w + 1 diagonals wide; the union over a task's
-    // pairs at most 2 (m + w) + 1
+    // pairs at most 2 (m + w) + 1; a strip of width W holds (W + 4) / 2 code
+    // dwords per lane
     const int64_t W = 16 + 2 * (g.QM + g.RM) + 2;
     const int64_t nstrips = (g.QM + 15) / 16;
-    t.dir = A.get<uint32_t>(capT * (nstrips + 1) * W * 2 * 64);
-    t.bnd = A.get<int32_t>(capT * 2 * (g.RM + 1) * 64);
+    t.dir = A.get<uint32_t>(capW * nstrips * ((W + 4) / 2) * 64);
+    t.bnd = A.get<int32_t>(capW * 2 * (g.RM + 1) * kTbwSlots);
     if (!t.tasks || !t.dsz || !t.doff || !t.bsz || !t.boff || !t.dir || !t.bnd)
       return fail(SWX_ENOMEM, "device pool exhausted (graph traceback)");
   }

@@ -76,7 +76,9 @@ struct TbTask {
   int64_t dir_off;     // dwords
 };
 
-struct TbwTask {        // wide-band traceback task (64 pairs)
+constexpr int kTbwSlots = 16;   // pairs per wide-band traceback task (four lanes each)
+
+struct TbwTask {        // wide-band traceback task (kTbwSlots pairs)
   int32_t nslots, pad_;
   int64_t rows, wmax, dlo, width;
   int64_t slot_base;

@@ -445,24 +445,55 @@ hipError_t tb_band(const TbArgs &a, const TbTask *tasks, int64_t ntasks, const i
 }
 
 
-// ---- wide bands: row strips in registers, columns swept left to right ------
-// One lane per pair; the task's strip s covers rows sR+1 .. sR+R (1-based,
-// row 0 is the virtual row before the begin) and columns
-// [c0(s), c0(s) + W) with c0(s) = sR + 1 + dlo_min, clipped to [0, wmax]; W =
-// R + width of the union of the lanes' bands, so every lane computes a
-// superset of its own safe band.  H and F of a strip's last row are handed to
-// the next strip through global memory; choice codes are stored per
-// (strip, column) as R nibbles (two dwords for R = 16), lane-interleaved.
+// ---- wide bands: row strips over four lanes, columns swept left to right ---
+// A task holds kTbwSlots pairs; four consecutive lanes share one pair.  The
+// task's strip s covers rows sR+1 .. sR+R (R = 16, 1-based, row 0 is the
+// virtual row before the begin) and columns [clo(s), chi(s)): the unclipped
+// window starts at c0(s) = sR + 1 + dlo_min and is W = R + (width of the union
+// of the task's bands) columns wide, clipped to [0, wmax], so every pair
+// computes a superset of its own safe band.  Lane g of a pair holds rows
+// sR+4g+1 .. sR+4g+4 and at step t computes column clo + t - g: the H and F of
+// its last row reach lane g+1 through a one-lane DPP shift, one step later,
+// as the row above.  H and F of a strip's last row are handed to the next
+// strip through global memory.  Lane g's four choice codes of step t (16 bits)
+// are stored as half t & 1 of dword [s][t >> 1][g][slot], so that each store
+// covers the whole wave with one 256-byte write.
 namespace {
-constexpr int kStripR = 16;
+constexpr int kStripR = 16;                     // rows per strip
+constexpr int kStripLP = 4;                     // lanes per pair
+constexpr int kStripRL = kStripR / kStripLP;    // rows per lane
+static_assert(kTbwSlots * kStripLP == 64, "one task per wave");
+
+// columns of strip s and the code dwords a strip holds per (lane, slot)
+__device__ __forceinline__ void strip_window(int64_t s, const TbwTask &tk, int64_t *clo,
+                                             int64_t *chi) {
+  const int64_t cstart = s * kStripR + 1 + tk.dlo;
+  int64_t lo = cstart > 0 ? cstart : 0;
+  int64_t hi = cstart + tk.width;
+  if (hi > tk.wmax + 1) hi = tk.wmax + 1;
+  *clo = lo;
+  *chi = hi > lo ? hi : lo;
 }
+// lane k of each quad of lanes, to the whole quad (k a constant after unrolling)
+__device__ __forceinline__ int32_t quad_bcast(int32_t x, int k) {
+  switch (k) {
+    case 0: return __builtin_amdgcn_update_dpp(0, x, 0x00, 0xF, 0xF, false);
+    case 1: return __builtin_amdgcn_update_dpp(0, x, 0x55, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_update_dpp(0, x, 0xAA, 0xF, 0xF, false);
+    default: return __builtin_amdgcn_update_dpp(0, x, 0xFF, 0xF, 0xF, false);
+  }
+}
+__host__ __device__ __forceinline__ int64_t strip_dwords(int64_t width) {
+  return (width + kStripLP) / 2;   // steps: at most width + kStripLP - 1
+}
+}  // namespace
 
 __global__ void k_tbw_tasks(int64_t n0, int64_t n1, const int64_t *range, int64_t ntasks_cap,
                             const int64_t *sorted, const TbArgs a, TbwTask *tasks,
                             int64_t *dir_words, int64_t *bnd_words) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (range) { n0 = range[0]; n1 = range[1]; }
-  const int64_t ntasks = (n1 - n0 + 63) / 64;
+  const int64_t ntasks = (n1 - n0 + kTbwSlots - 1) / kTbwSlots;
   if (t >= (range ? ntasks_cap : ntasks)) return;
   if (t >= ntasks) {
     tasks[t] = TbwTask{};
@@ -470,8 +501,8 @@ __global__ void k_tbw_tasks(int64_t n0, int64_t n1, const int64_t *range, int64_
     bnd_words[t] = 0;
     return;
   }
-  const int64_t s0 = n0 + t * 64;
-  const int64_t s1 = (s0 + 64 < n1) ? s0 + 64 : n1;
+  const int64_t s0 = n0 + t * kTbwSlots;
+  const int64_t s1 = (s0 + kTbwSlots < n1) ? s0 + kTbwSlots : n1;
   int64_t rows = 1, wmax = 1, dlo_min = 0, dhi_max = 0;
   for (int64_t k = s0; k < s1; ++k) {
     const int64_t p = sorted[k];
@@ -492,8 +523,8 @@ __global__ void k_tbw_tasks(int64_t n0, int64_t n1, const int64_t *range, int64_
   tk.slot_base = s0;
   tasks[t] = tk;
   const int64_t nstrips = (rows + kStripR - 1) / kStripR;
-  dir_words[t] = (nstrips * tk.width + tk.width) * 2 * 64;   // + row 0
-  bnd_words[t] = 2 * (wmax + 1) * 64;
+  dir_words[t] = nstrips * strip_dwords(tk.width) * 64;
+  bnd_words[t] = 2 * (wmax + 1) * kTbwSlots;
 }
 
 __global__ void k_tbw_offsets(int64_t ntasks, TbwTask *tasks, const int64_t *doff,
@@ -505,19 +536,21 @@ __global__ void k_tbw_offsets(int64_t ntasks, TbwTask *tasks, const int64_t *dof
 template <bool LUT4>
 __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks, int64_t ntasks,
                                                   const int64_t *sorted, int32_t *bndbuf) {
-  constexpr int R = kStripR;
-  constexpr int kCB = 16;   // walk cache: columns per lane
+  constexpr int LP = kStripLP, RL = kStripRL, NS = kTbwSlots;
+  constexpr int kCU = 8;    // walk cache: code dwords (16 steps) per lane
   __shared__ int8_t s_mat[32 * 32];
-  __shared__ uint32_t s_walk[4 * kCB * 2 * 64];
+  __shared__ uint32_t s_walk[4 * 64 * kCU];
   for (int k = threadIdx.x; k < a.n * a.n; k += blockDim.x) s_mat[k] = a.matrix[k];
   __syncthreads();
   const int lane = threadIdx.x & 63;
+  const int g = lane & (LP - 1);        // row group of this lane
+  const int slot = lane / LP;           // pair slot of the task
   const int64_t tid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (tid >= ntasks) return;
   const TbwTask tk = tasks[tid];
   if (tk.nslots == 0) return;
-  const bool live = lane < tk.nslots;
-  const int64_t p = live ? sorted[tk.slot_base + lane] : -1;
+  const bool live = slot < tk.nslots;
+  const int64_t p = live ? sorted[tk.slot_base + slot] : -1;
   int64_t m = 1, w = 1, dlo = 0, bwl = 1;
   int32_t s1 = 0;
   const int8_t *q = a.qcat, *r = a.rcat;
@@ -532,34 +565,33 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
   const int32_t o = a.o, e = a.e;
   uint32_t *dir = a.dir + tk.dir_off;
   int32_t *bH = bndbuf + tk.bnd_off;
-  int32_t *bF = bH + (tk.wmax + 1) * 64;
-  const int64_t W = tk.width;
-  // row 0 (virtual): H(0,0) = 0, H(0,j) = E(0,j) = -(o + (j-1)e), F = -inf.
-  // Its choice codes sit before strip 0 (W columns starting at column 0).
-  for (int64_t j = 0; j <= tk.wmax; ++j) {
-    bH[j * 64 + lane] = (j == 0) ? 0 : -(o + (int32_t)(j - 1) * e);
-    bF[j * 64 + lane] = kNeg;
+  int32_t *bF = bH + (tk.wmax + 1) * NS;
+  const int64_t SW = strip_dwords(tk.width);
+  // row 0 (virtual): H(0,0) = 0, H(0,j) = -(o + (j-1)e), F = -inf; the walk
+  // decodes row 0 itself, so it has no stored codes
+  for (int64_t j = g; j <= tk.wmax; j += LP) {
+    bH[j * NS + slot] = (j == 0) ? 0 : -(o + (int32_t)(j - 1) * e);
+    bF[j * NS + slot] = kNeg;
   }
-  for (int64_t j = 0; j < W; ++j) {
-    const uint32_t c = (j == 0) ? 0u : (1u | ((j == 1 || o <= e) ? 4u : 0u));
-    dir[(j * 2) * 64 + lane] = c;
-    dir[(j * 2 + 1) * 64 + lane] = 0;
-  }
-  const int64_t nstrips = (tk.rows + R - 1) / R;
-  int64_t plo = 0, phi = tk.wmax + 1;   // columns of row sR that hold valid values
+  const int64_t nstrips = (tk.rows + kStripR - 1) / kStripR;
+  int32_t plo = 0, phi = (int32_t)tk.wmax + 1;   // columns of row sR that hold valid values
+  const int8_t *rr = live ? r : (const int8_t *)a.matrix;   // readable bytes for empty slots
   for (int64_t s = 0; s < nstrips; ++s) {
-    const int64_t sR = s * R;
-    const int64_t cstart = sR + 1 + tk.dlo;             // unclipped window start
-    const int64_t clo = cstart > 0 ? cstart : 0;
-    int64_t chi = cstart + W;
-    if (chi > tk.wmax + 1) chi = tk.wmax + 1;
-    uint32_t *sdir = dir + (W + s * W) * 2 * 64;
-    // row symbols and per-row score tables
-    int32_t lut[R];
-    int32_t qn[R];
+    const int64_t sR = s * kStripR;
+    int64_t clo64, chi64;
+    strip_window(s, tk, &clo64, &chi64);
+    // 32-bit column and step arithmetic (a strip task spans well under 2^31
+    // code dwords), so that the block's addresses stay in few registers
+    const int32_t clo = (int32_t)clo64, chi = (int32_t)chi64;
+    const int32_t ncol = chi - clo;
+    const int32_t nsteps = ncol + LP - 1;
+    const int32_t wmax = (int32_t)tk.wmax, wl = (int32_t)w;
+    uint32_t *sdir = dir + s * SW * 64;
+    // this lane's rows: score tables
+    int32_t lut[RL], qn[RL];
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const int64_t i = sR + 1 + k;
+    for (int k = 0; k < RL; ++k) {
+      const int64_t i = sR + g * RL + 1 + k;
       lut[k] = 0;
       qn[k] = 0;
       const int32_t qs = (live && i <= m) ? (int32_t)q[i - 1] : -1;
@@ -573,144 +605,181 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
         }
       }
     }
-    int32_t H[R], E[R];
+    int32_t H[RL], E[RL];
 #pragma unroll
-    for (int k = 0; k < R; ++k) { H[k] = kNeg; E[k] = kNeg; }
-    int32_t hdtop = (clo >= 1 && clo - 1 >= plo && clo - 1 < phi) ? bH[(clo - 1) * 64 + lane] : kNeg;
-    // Columns go in blocks of kPB.  At the top of a block the wave waits for
-    // the block's operands (loaded at the top of the previous block), then
+    for (int k = 0; k < RL; ++k) { H[k] = kNeg; E[k] = kNeg; }
+    // H of the row above at the previous column (lane 0: row sR at clo - 1)
+    int32_t hdiag0 = kNeg;
+    if (g == 0 && clo >= 1 && clo - 1 >= plo && clo - 1 < phi) hdiag0 = bH[(clo - 1) * NS + slot];
+    int32_t xh = kNeg, xf = kNeg;   // last row's H, F of the previous step
+    uint32_t xs = 0;                // reference symbol of the previous step
+    // Steps go in blocks of kPB.  Lane 0 of a pair consumes the row above and
+    // the reference symbol of its column; the pair's four lanes load them, a
+    // quarter each, and hand them over by a DPP broadcast inside the lane
+    // quad (the other lanes take theirs from the lane before).  The strip's
+    // last row goes the other way: lane 3 broadcasts it and the lanes keep
+    // a quarter each for the boundary stores.  At the top of a block the wave
+    // waits for the block's operands (requested one block earlier), then
     // stores the previous block's codes and boundary values and requests the
-    // next block's operands, and only then computes: every memory operation
-    // has a whole block of arithmetic to complete before the next wait
-    // (loads and stores in flight together make every wait a wait for all).
-    // Loads are unconditional (indices clamped into the buffers) and land
-    // straight in their registers; the row above outside the previous
-    // strip's window reads as -inf.
-    constexpr int kPB = 8;
-    const int8_t *rr = live ? r : (const int8_t *)a.matrix;   // readable bytes for empty lanes
-    int32_t n_h[kPB], n_f[kPB], n_c[kPB];
-    auto fetch_block = [&](int64_t j0) {
+    // next block's operands, and only then computes.
+    constexpr int kPB = 4;   // (8 leaves three waves per SIMD, 4 leaves four)
+    constexpr int kPV = kPB / LP;   // columns per lane and block
+    int32_t n_h[kPV], n_f[kPV], n_c[kPV];
+    // lane g loads columns clo + t0 + g + LP * v of the block
+    auto fetch_block = [&](int32_t t0) {
 #pragma unroll
-      for (int u = 0; u < kPB; ++u) {
-        int64_t j = j0 + u;
-        j = j < 0 ? 0 : (j > tk.wmax ? tk.wmax : j);
-        n_h[u] = bH[j * 64 + lane];
-        n_f[u] = bF[j * 64 + lane];
-        int64_t x = j0 + u - 1;
-        x = x < 0 ? 0 : (x > w - 1 ? w - 1 : x);
-        n_c[u] = (int32_t)rr[live ? x : 0];
+      for (int v = 0; v < kPV; ++v) {
+        int32_t j = clo + t0 + g + LP * v;
+        j = j < 0 ? 0 : (j > wmax ? wmax : j);
+        n_h[v] = bH[j * NS + slot];
+        n_f[v] = bF[j * NS + slot];
+        int32_t x = clo + t0 + g + LP * v - 1;
+        x = x < 0 ? 0 : (x > wl - 1 ? wl - 1 : x);
+        n_c[v] = (int32_t)rr[x];
       }
     };
-    uint32_t p_d0[kPB], p_d1[kPB];
-    int32_t p_h[kPB], p_f[kPB];
-    int64_t p_j0 = -1;   // first column of the pending block (-1: none)
-    int64_t p_jc0 = 0;
+    uint32_t p_code[kPB / 2];
+    int32_t p_h[kPV], p_f[kPV];   // last row of step g + LP * v of the pending block
+    int32_t p_t0 = -1;   // first step of the pending block (-1: none)
     auto flush = [&]() {
-      if (p_j0 < 0) return;
+      if (p_t0 < 0) return;
 #pragma unroll
-      for (int u = 0; u < kPB; ++u) {
-        if (p_j0 + u < chi) {
-          const int64_t jc = p_jc0 + u;
-          sdir[(jc * 2) * 64 + lane] = p_d0[u];
-          sdir[(jc * 2 + 1) * 64 + lane] = p_d1[u];
-          bH[(p_j0 + u) * 64 + lane] = p_h[u];
-          bF[(p_j0 + u) * 64 + lane] = p_f[u];
+      for (int u = 0; u < kPB / 2; ++u)
+        if (p_t0 + 2 * u < nsteps) sdir[((p_t0 >> 1) + u) * 64 + lane] = p_code[u];
+#pragma unroll
+      for (int v = 0; v < kPV; ++v) {
+        const int32_t t = p_t0 + g + LP * v, j = clo + t - (LP - 1);
+        if (t >= LP - 1 && t < nsteps) {
+          bH[j * NS + slot] = p_h[v];
+          bF[j * NS + slot] = p_f[v];
         }
       }
     };
-    fetch_block(clo);
-    for (int64_t j0 = clo; j0 < chi; j0 += kPB) {
-      int32_t c_h[kPB], c_f[kPB];
-      uint32_t c_sy[kPB];
+    fetch_block(0);
+    for (int32_t t0 = 0; t0 < nsteps; t0 += kPB) {
+      int32_t c_h[kPV], c_f[kPV];
+      int32_t c_sy[kPV];
 #pragma unroll
-      for (int u = 0; u < kPB; ++u) {
-        const int64_t j = j0 + u;
+      for (int v = 0; v < kPV; ++v) {
+        const int32_t j = clo + t0 + g + LP * v;
         const bool inprev = j >= plo && j < phi;
-        c_h[u] = inprev ? n_h[u] : kNeg;
-        c_f[u] = inprev ? n_f[u] : kNeg;
-        const int32_t c = (live && j >= 1 && j <= w) ? n_c[u] : -1;
-        c_sy[u] = (c >= 0 && c < a.n) ? (uint32_t)c : 0u;
+        c_h[v] = inprev ? n_h[v] : kNeg;
+        c_f[v] = inprev ? n_f[v] : kNeg;
+        const int32_t c = (live && j >= 1 && j <= wl) ? n_c[v] : -1;
+        c_sy[v] = (c >= 0 && c < a.n) ? c : 0;
       }
       // the operands are consumed (waited for) before any store is issued
       __builtin_amdgcn_sched_barrier(0);
       flush();
-      fetch_block(j0 + kPB);   // past the window too: clamped, and never used
+      fetch_block(t0 + kPB);   // past the window too: clamped, and never used
+      uint32_t acc = 0;
 #pragma unroll
       for (int u = 0; u < kPB; ++u) {
-        const int32_t hup0 = c_h[u], fup0 = c_f[u];
-        const uint32_t sym8 = LUT4 ? c_sy[u] * 8u : c_sy[u];
-        int32_t hdiag = hdtop;
-        hdtop = hup0;
-        int32_t hup = hup0, fup = fup0;
-        uint32_t dw0 = 0, dw1 = 0;
+        const int32_t t = t0 + u;
+        constexpr int kNone = 0;
+        // lane 0's operands: from lane u % 4 of the quad
+        const int32_t bh = quad_bcast(c_h[u / LP], u & (LP - 1));
+        const int32_t bf = quad_bcast(c_f[u / LP], u & (LP - 1));
+        const int32_t bs = quad_bcast(c_sy[u / LP], u & (LP - 1));
+        // the other lanes': from the lane before (its last row, one step earlier)
+        const int32_t dh = __builtin_amdgcn_update_dpp(kNone, xh, 0x111, 0xF, 0xF, false);
+        const int32_t df = __builtin_amdgcn_update_dpp(kNone, xf, 0x111, 0xF, 0xF, false);
+        const int32_t ds = __builtin_amdgcn_update_dpp(kNone, (int32_t)xs, 0x111, 0xF, 0xF, false);
+        const int32_t hup0 = g == 0 ? bh : dh;
+        const int32_t fup0 = g == 0 ? bf : df;
+        const uint32_t sym = (uint32_t)(g == 0 ? bs : ds);
+        uint32_t code = 0;
+        if (t >= g && t < g + ncol) {
+          const uint32_t sym8 = LUT4 ? sym * 8u : sym;
+          int32_t hdiag = hdiag0;
+          hdiag0 = hup0;
+          int32_t hup = hup0, fup = fup0;
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-          const int32_t sc = LUT4 ? __builtin_amdgcn_sbfe(lut[k], sym8, 8) : (int32_t)s_mat[qn[k] + c_sy[u]];
-          const int32_t diag = hdiag + sc;
-          const int32_t fo = hup - o, fx = fup - e;
-          const int32_t fij = fo > fx ? fo : fx;
-          const int32_t eo = H[k] - o, ex = E[k] - e;      // H[k], E[k] = row k at column j-1
-          const int32_t eij = eo > ex ? eo : ex;
-          int32_t h = diag > eij ? diag : eij;
-          h = h > fij ? h : fij;
-          uint32_t c = (h == diag) ? 0u : (h == eij ? 1u : 2u);
-          c |= (eo >= ex) ? 4u : 0u;
-          c |= (fo >= fx) ? 8u : 0u;
-          if (k < 8) dw0 |= c << (4 * k);
-          else dw1 |= c << (4 * (k - 8));
-          hdiag = H[k];
-          H[k] = h;
-          E[k] = eij;
-          hup = h;
-          fup = fij;
+          for (int k = 0; k < RL; ++k) {
+            const int32_t sc = LUT4 ? __builtin_amdgcn_sbfe(lut[k], sym8, 8) : (int32_t)s_mat[qn[k] + sym];
+            const int32_t diag = hdiag + sc;
+            const int32_t fo = hup - o, fx = fup - e;
+            const int32_t fij = fo > fx ? fo : fx;
+            const int32_t eo = H[k] - o, ex = E[k] - e;      // H[k], E[k] = row k at column j-1
+            const int32_t eij = eo > ex ? eo : ex;
+            int32_t h = diag > eij ? diag : eij;
+            h = h > fij ? h : fij;
+            uint32_t c = (h == diag) ? 0u : (h == eij ? 1u : 2u);
+            c |= (eo >= ex) ? 4u : 0u;
+            c |= (fo >= fx) ? 8u : 0u;
+            code |= c << (4 * k);
+            hdiag = H[k];
+            H[k] = h;
+            E[k] = eij;
+            hup = h;
+            fup = fij;
+          }
+          xh = hup;
+          xf = fup;
         }
-        p_d0[u] = dw0;
-        p_d1[u] = dw1;
-        p_h[u] = H[R - 1];
-        p_f[u] = fup;
+        xs = sym;
+        // lane 3's last row, kept by lane u % 4
+        const int32_t lh = quad_bcast(xh, LP - 1);
+        const int32_t lf = quad_bcast(xf, LP - 1);
+        if (g == (u & (LP - 1))) {
+          p_h[u / LP] = lh;
+          p_f[u / LP] = lf;
+        }
+        acc |= code << (16 * (u & 1));
+        if (u & 1) {
+          p_code[u >> 1] = acc;
+          acc = 0;
+        }
       }
-      p_j0 = j0;
-      p_jc0 = j0 - cstart;
+      p_t0 = t0;
     }
     flush();   // the strip's last block, before the next strip reads it
     plo = clo;
     phi = chi;
   }
   if (!live) return;
-  if (s1 <= 0) { a.cig_len[p] = 0; return; }
-  // traceback from (m, w) in state H
+  if (s1 <= 0) {
+    if (g == 0) a.cig_len[p] = 0;
+    return;
+  }
+  // Traceback from (m, w) in state H.  The four lanes of a pair walk it
+  // together; when the walk leaves the cached columns, each lane pulls kCU
+  // dwords of its own row group into the pair's LDS slots.
   uint32_t *out = a.cig + a.cig_off[p];
   int32_t nruns = 0;
   int64_t i = m, j = w;
   int state = 0;
   uint32_t cur_op = 0xFF, cur_len = 0;
   int64_t guard = 2 * (m + w) + 4;
-  const int wv = (int)(threadIdx.x >> 6);
-  int64_t cache_s = -1, cache_hi = -1;
+  uint32_t *cache = s_walk + ((threadIdx.x >> 6) * 64 + slot * LP) * kCU;   // [g][kCU]
+  int64_t cache_s = -1, cache_j = -1;
+  bool bad = false;
   while ((i > 0 || j > 0) && guard-- > 0) {
     uint32_t c;
     if (i == 0) {
       c = (j == 0) ? 0u : (1u | ((j == 1 || o <= e) ? 4u : 0u));
     } else {
-      const int64_t s = (i - 1) / R, k = (i - 1) % R;
-      const int64_t jc = j - (s * R + 1 + tk.dlo);
-      if (jc < 0 || jc >= W || j > tk.wmax) { a.err[p] = 1; break; }
-      // the walk only moves up and left: CB columns of this strip's codes at a
-      // time are pulled into the lane's LDS slots with independent loads
-      if (s != cache_s || jc > cache_hi || jc <= cache_hi - kCB) {
+      const int64_t s = (i - 1) / kStripR, k = (i - 1) % kStripR;
+      const int64_t gk = k / RL;
+      int64_t clo, chi;
+      strip_window(s, tk, &clo, &chi);
+      if (j < clo || j >= chi) { bad = true; break; }
+      const int64_t t = j - clo + gk;
+      // cached: dwords (cache_j - clo + g) / 2 - kCU + 1 .. (cache_j - clo + g) / 2 of row group g
+      const int64_t top = (cache_j - clo + gk) >> 1;
+      if (s != cache_s || (t >> 1) > top || (t >> 1) <= top - kCU) {
         cache_s = s;
-        cache_hi = jc;
+        cache_j = j;
+        const int64_t mytop = (j - clo + g) >> 1;
 #pragma unroll
-        for (int cc = 0; cc < kCB; ++cc) {
-          const int64_t jj = jc - cc;
-#pragma unroll
-          for (int d = 0; d < 2; ++d)
-            s_walk[((wv * kCB + cc) * 2 + d) * 64 + lane] =
-                jj >= 0 ? dir[(W + s * W + jj) * 2 * 64 + d * 64 + lane] : 0u;
+        for (int x = 0; x < kCU; ++x) {
+          const int64_t uu = mytop - x;
+          cache[g * kCU + x] = uu >= 0 ? dir[(s * SW + uu) * 64 + slot * LP + g] : 0u;
         }
       }
-      const uint32_t dwv = s_walk[((wv * kCB + (int)(cache_hi - jc)) * 2 + (int)(k >> 3)) * 64 + lane];
-      c = (dwv >> (4 * (k & 7))) & 0xFu;
+      const int64_t top2 = (cache_j - clo + gk) >> 1;
+      const uint32_t dwv = cache[gk * kCU + (top2 - (t >> 1))];
+      c = (dwv >> (16 * (t & 1) + 4 * (k % RL))) & 0xFu;
     }
     uint32_t op = 0xFF;
     if (state == 0) {
@@ -730,13 +799,15 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
     if (op != 0xFF) {
       if (op == cur_op) ++cur_len;
       else {
-        if (cur_len) out[nruns++] = (cur_len << 4) | cur_op;
+        if (cur_len && g == 0) out[nruns] = (cur_len << 4) | cur_op;
+        if (cur_len) ++nruns;
         cur_op = op;
         cur_len = 1;
       }
     }
   }
-  if (i != 0 || j != 0) a.err[p] = 1;
+  if (g != 0) return;
+  if (bad || i != 0 || j != 0) a.err[p] = 1;
   if (cur_len) out[nruns++] = (cur_len << 4) | cur_op;
   for (int32_t x = 0, y = nruns - 1; x < y; ++x, --y) {
     const uint32_t t = out[x]; out[x] = out[y]; out[y] = t;
@@ -1053,7 +1124,7 @@ hipError_t tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, int wa
 
 hipError_t tbw_tasks(int64_t n0, int64_t n1, const int64_t *sorted, const TbArgs &a,
                      TbwTask *tasks, int64_t *dir_words, int64_t *bnd_words, hipStream_t st) {
-  const int64_t nt = (n1 - n0 + 63) / 64;
+  const int64_t nt = (n1 - n0 + kTbwSlots - 1) / kTbwSlots;
   if (nt <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_tbw_tasks, dim3(nblk(nt, 128)), dim3(128), 0, st, n0, n1,
                      (const int64_t *)nullptr, (int64_t)0, sorted, a, tasks, dir_words, bnd_words);
