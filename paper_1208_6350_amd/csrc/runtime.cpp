@@ -333,13 +333,19 @@ struct DeviceBatch {
 
 // Runs independent launches side by side: each goes to a side stream that
 // first waits for everything queued on the main stream, and the main stream
-// then waits for all of them.  Launches come with a cost estimate and are
-// placed longest first on the least loaded of two side streams (the device
-// gives a process few hardware queues; more streams would share them).
+// then waits for all of them.  Launches come with a cost estimate (an
+// estimated run time alone on the device) and are placed longest first on the
+// least loaded of two side streams (the device gives a process few hardware
+// queues; more streams would share them).  A `lead` launch (one whose few,
+// long waves leave most of the device to others) goes first, alone, and its
+// stream is charged only kLeadShare of its cost: the launches beside it run
+// mostly in its shadow.
 struct SideLaunch {
   double cost;
   std::function<hipError_t(hipStream_t)> fn;
+  bool lead = false;
 };
+constexpr double kLeadShare = 0.3;
 
 static int run_side_by_side(swx_ctx *ctx, std::vector<SideLaunch> &ls) {
   if (ls.empty()) return SWX_OK;
@@ -360,13 +366,15 @@ static int run_side_by_side(swx_ctx *ctx, std::vector<SideLaunch> &ls) {
     for (auto &l : ls) HIP_TRY(l.fn(ctx->stream));
     return SWX_OK;
   }
-  std::stable_sort(ls.begin(), ls.end(), [](const SideLaunch &x, const SideLaunch &y) { return x.cost > y.cost; });
+  std::stable_sort(ls.begin(), ls.end(), [](const SideLaunch &x, const SideLaunch &y) {
+    return x.lead != y.lead ? x.lead : x.cost > y.cost;
+  });
   HIP_TRY(hipEventRecord(ctx->fork_ev, ctx->stream));
   for (int k = 0; k < na; ++k) HIP_TRY(hipStreamWaitEvent(ctx->aux[k], ctx->fork_ev, 0));
   double load[na] = {0, 0};
   for (auto &l : ls) {
     const int k = load[0] <= load[1] ? 0 : 1;
-    load[k] += l.cost;
+    load[k] += l.lead ? kLeadShare * l.cost : l.cost;
     HIP_TRY(l.fn(ctx->aux[k]));
   }
   for (int k = 0; k < na; ++k) {
@@ -442,7 +450,11 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
     TbArgs tc = ta;
     tc.dir = A.get<uint32_t>(words);
     if (!tc.dir) return fail(SWX_ENOMEM, "device pool exhausted (choice codes)");
-    launches.push_back({(double)words * 8, [=](hipStream_t s_) { return tb_band(tc, tasks, nt, sorted, bw, s_); }});
+    // measured time per cell alone on the device, relative: 8-wide bands
+    // pay the most per-row overhead per cell, 16-wide the least
+    const double per_cell = bw == 8 ? 2.0 : (bw == 16 ? 1.2 : 1.5);
+    launches.push_back({(double)words * 8 * per_cell,
+                        [=](hipStream_t s_) { return tb_band(tc, tasks, nt, sorted, bw, s_); }});
     pos += nc;
   }
   if (hc[5] > 0) {   // bands wider than 64 diagonals: row strips, columns swept
@@ -466,7 +478,9 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
     tc.dir = A.get<uint32_t>(tot[0]);
     int32_t *bnd = A.get<int32_t>(tot[1]);
     if (!tc.dir || !bnd) return fail(SWX_ENOMEM, "device pool exhausted (wide band)");
-    launches.push_back({(double)tot[0] * 8, [=](hipStream_t s_) { return tb_strip(tc, tasks, nt, sorted, bnd, s_); }});
+    launches.push_back({(double)tot[0] * 8 * 1.7,
+                        [=](hipStream_t s_) { return tb_strip(tc, tasks, nt, sorted, bnd, s_); },
+                        true});
     pos += nc;
   }
   if (hc[6] > 0) {   // long pairs with wide bands: one pair per wave
