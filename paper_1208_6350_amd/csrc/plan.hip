@@ -144,10 +144,10 @@ hipError_t count_classes(int64_t n, const uint8_t *cls, int64_t *counts, hipStre
 
 hipError_t sort_keys(int64_t n, uint64_t *keys, uint64_t *keys_alt, int64_t *vals,
                      int64_t *vals_alt, void *tmp, size_t *tmp_bytes, int64_t **sorted_out,
-                     hipStream_t st) {
+                     hipStream_t st, int end_bit) {
   hipcub::DoubleBuffer<uint64_t> kb(keys, keys_alt);
   hipcub::DoubleBuffer<int64_t> vb(vals, vals_alt);
-  hipError_t e = hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, kb, vb, (int)n, 0, 64, st);
+  hipError_t e = hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, kb, vb, (int)n, 0, end_bit, st);
   if (tmp) *sorted_out = vb.Current();
   return e;
 }
@@ -165,10 +165,17 @@ hipError_t plan_sort(int64_t n, const int64_t *n_dev, const int64_t *ids, const 
                      const int64_t *rlen, const int32_t *band, int32_t R, uint64_t *keys,
                      uint64_t *keys_alt, int64_t *vals, int64_t *vals_alt, void *tmp,
                      size_t *tmp_bytes, int64_t **sorted_out, hipStream_t st) {
+  // without a band the top field is zero: sort the low 44 bits only.  The
+  // size query covers both bit ranges, so one buffer serves either pass.
+  const int end_bit = band ? 64 : 44;
   if (tmp == nullptr) {
     hipcub::DoubleBuffer<uint64_t> kb(keys, keys_alt);
     hipcub::DoubleBuffer<int64_t> vb(vals, vals_alt);
-    return hipcub::DeviceRadixSort::SortPairs(nullptr, *tmp_bytes, kb, vb, (int)n, 0, 64, st);
+    size_t b44 = 0, b64 = 0;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, b44, kb, vb, (int)n, 0, 44, st);
+    if (e == hipSuccess) e = hipcub::DeviceRadixSort::SortPairs(nullptr, b64, kb, vb, (int)n, 0, 64, st);
+    *tmp_bytes = b44 > b64 ? b44 : b64;
+    return e;
   }
   if (n == 0) { *sorted_out = vals; return hipSuccess; }
   hipLaunchKernelGGL(k_plan_keys, dim3(nb(n, 256)), dim3(256), 0, st, n, n_dev, ids, qlen, rlen,
@@ -177,7 +184,7 @@ hipError_t plan_sort(int64_t n, const int64_t *n_dev, const int64_t *ids, const 
   if (e != hipSuccess) return e;
   hipcub::DoubleBuffer<uint64_t> kb(keys, keys_alt);
   hipcub::DoubleBuffer<int64_t> vb(vals, vals_alt);
-  e = hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, kb, vb, (int)n, 0, 64, st);
+  e = hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, kb, vb, (int)n, 0, end_bit, st);
   *sorted_out = vb.Current();
   return e;
 }

@@ -308,9 +308,9 @@ static int read_i64(swx_ctx *ctx, const int64_t *d, int64_t *h, int64_t n = 1) {
   return SWX_OK;
 }
 
-// ids of the pairs whose flag is set (device list) and their count (host)
-static int select_flagged(swx_ctx *ctx, const uint8_t *flag, int64_t np, int64_t **ids,
-                          int64_t *count) {
+// ids of the pairs whose flag is set (device list) and their count (device)
+static int select_flagged_dev(swx_ctx *ctx, const uint8_t *flag, int64_t np, int64_t **ids,
+                              const int64_t **count_dev) {
   DevArena &A = ctx->arena;
   int64_t *f64 = A.get<int64_t>(np + 1), *pos = A.get<int64_t>(np + 1);
   *ids = A.get<int64_t>(np);
@@ -320,7 +320,17 @@ static int select_flagged(swx_ctx *ctx, const uint8_t *flag, int64_t np, int64_t
   int rc = scan(ctx, f64, pos, np + 1);
   if (rc) return rc;
   HIP_TRY(compact_flags(np, flag, pos, *ids, ctx->stream));
-  return read_i64(ctx, pos + np, count);
+  *count_dev = pos + np;
+  return SWX_OK;
+}
+
+// the same with the count read back to the host
+static int select_flagged(swx_ctx *ctx, const uint8_t *flag, int64_t np, int64_t **ids,
+                          int64_t *count) {
+  const int64_t *cd = nullptr;
+  int rc = select_flagged_dev(ctx, flag, np, ids, &cd);
+  if (rc) return rc;
+  return read_i64(ctx, cd, count);
 }
 
 // ---- banded traceback: classify by band width, one register kernel per
@@ -418,20 +428,31 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
   HIP_TRY(count_classes(np, cls, counts, st));
   size_t tmp_bytes = 0;
   int64_t *sorted = nullptr;
-  HIP_TRY(sort_keys(np, k0, k1, v0, v1, nullptr, &tmp_bytes, &sorted, st));
+  HIP_TRY(sort_keys(np, k0, k1, v0, v1, nullptr, &tmp_bytes, &sorted, st, kTbKeyBits));
   void *tmp = A.alloc(tmp_bytes);
   if (!tmp) return fail(SWX_ENOMEM, "device pool exhausted (sort)");
-  HIP_TRY(sort_keys(np, k0, k1, v0, v1, tmp, &tmp_bytes, &sorted, st));
-  int64_t hc[8], capw = 0;
+  HIP_TRY(sort_keys(np, k0, k1, v0, v1, tmp, &tmp_bytes, &sorted, st, kTbKeyBits));
+  // the class counts and the CIGAR scratch size in one read (class 7 is
+  // never used)
+  HIP_TRY(hipMemcpyAsync(counts + 7, coff + np, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+  int64_t hc[8];
   if ((rc = read_i64(ctx, counts, hc, 8))) return rc;
-  if ((rc = read_i64(ctx, coff + np, &capw))) return rc;
+  const int64_t capw = hc[7];
   uint32_t *cscr = A.get<uint32_t>(capw);
   if (!cscr) return fail(SWX_ENOMEM, "device pool exhausted (CIGAR scratch)");
   ta.cig = cscr;
   ta.cig_off = coff;
-  // plan every class first (host reads of sizes), then launch the classes'
-  // kernels side by side: the small classes would not fill the GPU alone
-  std::vector<SideLaunch> launches;
+  // plan every class first, read all their buffer sizes back in one go, then
+  // launch the classes' kernels side by side: the small classes would not
+  // fill the GPU alone.  totals: [c - 1] code words of band class c, [3] and
+  // [4] code and boundary words of the strip class.
+  int64_t *totals = A.get<int64_t>(8);
+  if (!totals) return fail(SWX_ENOMEM, "device pool exhausted (traceback sizes)");
+  struct BandPlan { TbTask *tasks; int64_t nt; int32_t bw; };
+  BandPlan bands[3];
+  int nbands = 0;
+  TbwTask *wtasks = nullptr;
+  int64_t wnt = 0;
   int64_t pos = hc[0];
   for (int c = 1; c <= 3; ++c) {
     const int64_t nc = hc[c];
@@ -445,16 +466,8 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
     HIP_TRY(tb_tasks(pos, pos + nc, sorted, ta, bw, tasks, dsz, st));
     if ((rc = scan(ctx, dsz, doff, nt + 1))) return rc;
     HIP_TRY(tb_offsets(nt, tasks, doff, st));
-    int64_t words = 0;
-    if ((rc = read_i64(ctx, doff + nt, &words))) return rc;
-    TbArgs tc = ta;
-    tc.dir = A.get<uint32_t>(words);
-    if (!tc.dir) return fail(SWX_ENOMEM, "device pool exhausted (choice codes)");
-    // measured time per cell alone on the device, relative: 8-wide bands
-    // pay the most per-row overhead per cell, 16-wide the least
-    const double per_cell = bw == 8 ? 2.0 : (bw == 16 ? 1.2 : 1.5);
-    launches.push_back({(double)words * 8 * per_cell,
-                        [=](hipStream_t s_) { return tb_band(tc, tasks, nt, sorted, bw, s_); }});
+    HIP_TRY(hipMemcpyAsync(totals + (c - 1), doff + nt, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    bands[nbands++] = BandPlan{tasks, nt, bw};
     pos += nc;
   }
   if (hc[5] > 0) {   // bands wider than 64 diagonals: row strips, columns swept
@@ -471,17 +484,38 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
     if ((rc = scan(ctx, dsz, doff, nt + 1))) return rc;
     if ((rc = scan(ctx, bsz, boff, nt + 1))) return rc;
     HIP_TRY(tbw_offsets(nt, tasks, doff, boff, st));
-    int64_t tot[2];
-    if ((rc = read_i64(ctx, doff + nt, &tot[0]))) return rc;
-    if ((rc = read_i64(ctx, boff + nt, &tot[1]))) return rc;
-    TbArgs tc = ta;
-    tc.dir = A.get<uint32_t>(tot[0]);
-    int32_t *bnd = A.get<int32_t>(tot[1]);
-    if (!tc.dir || !bnd) return fail(SWX_ENOMEM, "device pool exhausted (wide band)");
-    launches.push_back({(double)tot[0] * 8 * 1.7,
-                        [=](hipStream_t s_) { return tb_strip(tc, tasks, nt, sorted, bnd, s_); },
-                        true});
+    HIP_TRY(hipMemcpyAsync(totals + 3, doff + nt, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(totals + 4, boff + nt, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    wtasks = tasks;
+    wnt = nt;
     pos += nc;
+  }
+  std::vector<SideLaunch> launches;
+  if (nbands > 0 || wnt > 0) {
+    int64_t ht[5];
+    if ((rc = read_i64(ctx, totals, ht, 5))) return rc;
+    for (int k = 0; k < nbands; ++k) {
+      const BandPlan bp = bands[k];
+      const int64_t words = ht[(bp.bw == 8 ? 1 : bp.bw == 16 ? 2 : 3) - 1];
+      TbArgs tc = ta;
+      tc.dir = A.get<uint32_t>(words);
+      if (!tc.dir) return fail(SWX_ENOMEM, "device pool exhausted (choice codes)");
+      // measured time per cell alone on the device, relative: 8-wide bands
+      // pay the most per-row overhead per cell, 16-wide the least
+      const double per_cell = bp.bw == 8 ? 2.0 : (bp.bw == 16 ? 1.2 : 1.5);
+      launches.push_back({(double)words * 8 * per_cell, [=](hipStream_t s_) {
+                            return tb_band(tc, bp.tasks, bp.nt, sorted, bp.bw, s_);
+                          }});
+    }
+    if (wnt > 0) {
+      TbArgs tc = ta;
+      tc.dir = A.get<uint32_t>(ht[3]);
+      int32_t *bnd = A.get<int32_t>(ht[4]);
+      if (!tc.dir || !bnd) return fail(SWX_ENOMEM, "device pool exhausted (wide band)");
+      launches.push_back({(double)ht[3] * 8 * 1.7,
+                          [=](hipStream_t s_) { return tb_strip(tc, wtasks, wnt, sorted, bnd, s_); },
+                          true});
+    }
   }
   if (hc[6] > 0) {   // long pairs with wide bands: one pair per wave
     const int64_t nc = hc[6];
@@ -888,12 +922,22 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
     HIP_TRY(hipMemsetAsync(rsc, 0, sizeof(int32_t) * np, st));
     PairView rview{rqs, rrs, rql, rrl, b.qcat, b.rcat, 1};
     FillOut rout{rsc, rqe, rre, rov};
-    for (int lb : {16, 32}) {
-      int64_t *ids = nullptr, cnt = 0;
-      if ((rc = select_flagged(ctx, lb == 16 ? f16 : f32, np, &ids, &cnt))) return rc;
-      if (cnt == 0) continue;
+    // both lane widths' pair lists first, their counts in one read, so that
+    // no read waits for a queued fill
+    int64_t *rids[2] = {nullptr, nullptr}, rcnt[2] = {0, 0};
+    const int64_t *rcd[2] = {nullptr, nullptr};
+    int64_t *rc2 = A.get<int64_t>(2);
+    if (!rc2) return fail(SWX_ENOMEM, "device pool exhausted (reverse counts)");
+    for (int k = 0; k < 2; ++k) {
+      if ((rc = select_flagged_dev(ctx, k == 0 ? f16 : f32, np, &rids[k], &rcd[k]))) return rc;
+      HIP_TRY(hipMemcpyAsync(rc2 + k, rcd[k], sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    }
+    if ((rc = read_i64(ctx, rc2, rcnt, 2))) return rc;
+    for (int k = 0; k < 2; ++k) {
+      if (rcnt[k] == 0) continue;
       Plan pr;
-      if ((rc = plan_pass(ctx, sc, ids, cnt, rql, rrl, band, lb, R, pr))) return rc;
+      if ((rc = plan_pass(ctx, sc, rids[k], rcnt[k], rql, rrl, band, k == 0 ? 16 : 32, R, pr)))
+        return rc;
       if ((rc = run_fill(ctx, pr, sc, rview, true, tgt, rout, score_bound))) return rc;
     }
     if (lp.nlong > 0 &&
@@ -1316,7 +1360,7 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
     if ((rc = fixed_scan(g, g.ccap, g.coff, B + 1, st))) return rc;
     HIP_TRY(count_classes(B, g.cls, g.counts, st));
     size_t sb = g.tb_sort_bytes;
-    HIP_TRY(sort_keys(B, g.tk0, g.tk1, g.tv0, g.tv1, g.tb_sort_tmp, &sb, &g.tb_sorted, st));
+    HIP_TRY(sort_keys(B, g.tk0, g.tk1, g.tv0, g.tv1, g.tb_sort_tmp, &sb, &g.tb_sorted, st, kTbKeyBits));
     HIP_TRY(class_ranges(g.counts, g.ranges, st));
     for (int c = 1; c <= 3; ++c) {
       FixedTb &t = g.tb[c];
@@ -1469,7 +1513,7 @@ static int graph_alloc(GraphState &g) {
       return fail(SWX_ENOMEM, "device pool exhausted (graph traceback)");
   }
   size_t sb = 0;
-  HIP_TRY(sort_keys(B, g.tk0, g.tk1, g.tv0, g.tv1, nullptr, &sb, &g.tb_sorted, nullptr));
+  HIP_TRY(sort_keys(B, g.tk0, g.tk1, g.tv0, g.tv1, nullptr, &sb, &g.tb_sorted, nullptr, kTbKeyBits));
   g.tb_sort_bytes = sb;
   g.tb_sort_tmp = A.alloc(sb);
   // scan scratch: the largest scan is over B + 1 elements

@@ -76,7 +76,8 @@ struct TbTask {
   int64_t dir_off;     // dwords
 };
 
-constexpr int kTbwSlots = 16;   // pairs per wide-band traceback task (four lanes each)
+constexpr int kTbwSlots = 16;
+constexpr int kTbKeyBits = 23;  // traceback sort key: class (3 bits) above 20 bits of rows   // pairs per wide-band traceback task (four lanes each)
 
 struct TbwTask {        // wide-band traceback task (kTbwSlots pairs)
   int32_t nslots, pad_;
@@ -191,7 +192,7 @@ hipError_t class_ranges(const int64_t *counts, int64_t *ranges, hipStream_t st);
 hipError_t count_classes(int64_t n, const uint8_t *cls, int64_t *counts, hipStream_t st);
 hipError_t sort_keys(int64_t n, uint64_t *keys, uint64_t *keys_alt, int64_t *vals,
                      int64_t *vals_alt, void *tmp, size_t *tmp_bytes, int64_t **sorted_out,
-                     hipStream_t st);
+                     hipStream_t st, int end_bit = 64);
 hipError_t rev_prepare(int64_t npairs, const int32_t *score, const int32_t *qend,
                        const int64_t *rend, const uint8_t *lanebits, int32_t smax, int32_t o,
                        int32_t e, int32_t *band, uint8_t *f16, uint8_t *f32, hipStream_t st);

@@ -52,7 +52,8 @@ __global__ void k_tb_classify(TbArgs a, int64_t npairs, uint8_t *cls, uint64_t *
     }
   }
   cls[p] = c;
-  key[p] = ((uint64_t)c << 40) | (uint64_t)(m > 0xFFFFFFFFFll ? 0xFFFFFFFFFll : m);
+  // class, then rows (clamped: only the grouping of similar heights matters)
+  key[p] = ((uint64_t)c << (kTbKeyBits - 3)) | (uint64_t)(m > 0xFFFFF ? 0xFFFFF : m);
   vals[p] = p;
   ccap[p] = (c != 0) ? (m + w + 2) : 0;
 }
