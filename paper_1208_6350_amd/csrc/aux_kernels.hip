@@ -433,7 +433,16 @@ __global__ void k_pair_stats(int64_t n, const int32_t *qlen, const int64_t *rlen
     best = o > best ? o : best;
     cells += __shfl_xor(cells, off, 64);
   }
-  if ((threadIdx.x & 63) == 0) {
+  // one pair of atomics per block, not per wave: they all meet at two words
+  __shared__ int64_t s_best[4], s_cells[4];
+  const int wv = (int)(threadIdx.x >> 6);
+  if ((threadIdx.x & 63) == 0) { s_best[wv] = best; s_cells[wv] = cells; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+      best = s_best[k] > best ? s_best[k] : best;
+      cells += s_cells[k];
+    }
     if (best > 0) atomicMax((unsigned long long *)&stats[0], (unsigned long long)best);
     if (cells > 0) atomicAdd((unsigned long long *)&stats[1], (unsigned long long)cells);
   }
@@ -467,7 +476,7 @@ hipError_t launch_pair_stats(int64_t n, const int32_t *qlen, const int64_t *rlen
                              hipStream_t st) {
   if (!n) return hipSuccess;
   unsigned b = blocks_for(n, 256);
-  if (b > 1024) b = 1024;
+  if (b > 256) b = 256;
   hipLaunchKernelGGL(k_pair_stats, dim3(b), dim3(256), 0, st, n, qlen, rlen, stats);
   return hipGetLastError();
 }

@@ -45,29 +45,46 @@ __global__ void k_plan_keys(int64_t n, const int64_t *n_dev, const int64_t *ids,
   vals[k] = p;
 }
 
+__device__ __forceinline__ int64_t wave_max_i64(int64_t v) {
+  for (int off = 32; off >= 1; off >>= 1) {
+    const int64_t o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// one wave per task: the lanes take the task's slots in turn, and the
+// maxima are reduced across the wave
 __global__ void k_plan_tasks(int64_t n, const int64_t *n_dev, int64_t ntasks, int32_t slots,
                              int32_t R, int64_t qdata_per_row, const int64_t *sorted,
                              const int32_t *qlen, const int64_t *rlen, const int32_t *band,
                              InterTask *tasks, int64_t *bnd_size, int64_t *qdata_size) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (t >= ntasks) return;
   if (n_dev) n = *n_dev;
   const int64_t s0 = t * slots;
   int64_t s1 = (s0 + slots < n) ? s0 + slots : n;
   if (s1 < s0) s1 = s0;   // a task past the valid ids is empty
-  int64_t mq = 1, mr = 1;
-  int32_t mb = band ? 0 : -1;
-  for (int64_t k = s0; k < s1; ++k) {
+  int64_t mq = 1, mr = 1, mb = 0;   // mb: a negative band (none) counts as the largest
+  for (int64_t k = s0 + lane; k < s1; k += 64) {
     const int64_t p = sorted[k];
     if (qlen[p] > mq) mq = qlen[p];
     if (rlen[p] > mr) mr = rlen[p];
-    if (band) mb = (band[p] < 0 || mb < 0) ? -1 : (band[p] > mb ? band[p] : mb);
+    if (band) {
+      const int64_t b = band[p] < 0 ? INT64_MAX : band[p];
+      mb = b > mb ? b : mb;
+    }
   }
+  mq = wave_max_i64(mq);
+  mr = wave_max_i64(mr);
+  mb = wave_max_i64(mb);
+  if (lane != 0) return;
   InterTask tk{};
   tk.nslots = (int32_t)(s1 - s0);
   tk.qp = (int32_t)((mq + R - 1) / R * R);
   tk.rp = (int32_t)((mr + 7) / 8 * 8);
-  tk.band = mb;
+  tk.band = band ? (mb == INT64_MAX ? -1 : (int32_t)mb) : -1;
   tk.slot_base = s0;
   tasks[t] = tk;
   bnd_size[t] = 3 * (int64_t)tk.rp * 64;
@@ -194,7 +211,7 @@ hipError_t plan_tasks_dev(int64_t n, const int64_t *n_dev, int64_t ntasks, int32
                           const int64_t *rlen, const int32_t *band, InterTask *tasks,
                           int64_t *bnd_size, int64_t *qdata_size, hipStream_t st) {
   if (ntasks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_plan_tasks, dim3(nb(ntasks, 128)), dim3(128), 0, st, n, n_dev, ntasks,
+  hipLaunchKernelGGL(k_plan_tasks, dim3(nb(ntasks, 4)), dim3(256), 0, st, n, n_dev, ntasks,
                      slots, R, qdata_per_row, sorted, qlen, rlen, band, tasks, bnd_size,
                      qdata_size);
   return hipGetLastError();

@@ -58,28 +58,41 @@ __global__ void k_tb_classify(TbArgs a, int64_t npairs, uint8_t *cls, uint64_t *
   ccap[p] = (c != 0) ? (m + w + 2) : 0;
 }
 
+__device__ __forceinline__ int64_t wave_max_i64(int64_t v) {
+  for (int off = 32; off >= 1; off >>= 1) {
+    const int64_t o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
 // tasks over sorted[n0 .. n1); with range (device) the bounds are read there
-// and every task slot up to ntasks_cap is written (empty past the range)
+// and every task slot up to ntasks_cap is written (empty past the range).
+// One wave per task, one lane per slot.
 __global__ void k_tb_tasks(int64_t n0, int64_t n1, const int64_t *range, int64_t ntasks_cap,
                            const int64_t *sorted, const TbArgs a, int32_t bw, TbTask *tasks,
                            int64_t *dir_words) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (range) { n0 = range[0]; n1 = range[1]; }
   const int64_t ntasks = (n1 - n0 + 63) / 64;
   if (t >= (range ? ntasks_cap : ntasks)) return;
   if (t >= ntasks) {
-    tasks[t] = TbTask{};
-    dir_words[t] = 0;
+    if (lane == 0) {
+      tasks[t] = TbTask{};
+      dir_words[t] = 0;
+    }
     return;
   }
   const int64_t s0 = n0 + t * 64;
   const int64_t s1 = (s0 + 64 < n1) ? s0 + 64 : n1;
   int64_t rows = 1;
-  for (int64_t k = s0; k < s1; ++k) {
-    const int64_t p = sorted[k];
-    const int64_t m = a.qend[p] - a.qbeg[p] + 1;
-    rows = m > rows ? m : rows;
+  if (s0 + lane < s1) {
+    const int64_t p = sorted[s0 + lane];
+    rows = a.qend[p] - a.qbeg[p] + 1;
   }
+  rows = wave_max_i64(rows);
+  if (lane != 0) return;
   TbTask tk{};
   tk.nslots = (int32_t)(s1 - s0);
   tk.rows = (int32_t)rows;
@@ -402,7 +415,7 @@ hipError_t tb_tasks(int64_t n0, int64_t n1, const int64_t *sorted, const TbArgs 
                     TbTask *tasks, int64_t *dir_words, hipStream_t st) {
   const int64_t nt = (n1 - n0 + 63) / 64;
   if (nt <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tb_tasks, dim3(nblk(nt, 128)), dim3(128), 0, st, n0, n1,
+  hipLaunchKernelGGL(k_tb_tasks, dim3(nblk(nt, 4)), dim3(256), 0, st, n0, n1,
                      (const int64_t *)nullptr, (int64_t)0, sorted, a, bw, tasks, dir_words);
   return hipGetLastError();
 }
@@ -411,7 +424,7 @@ hipError_t tb_tasks_range(const int64_t *range, int64_t ntasks_cap, const int64_
                           const TbArgs &a, int32_t bw, TbTask *tasks, int64_t *dir_words,
                           hipStream_t st) {
   if (ntasks_cap <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tb_tasks, dim3(nblk(ntasks_cap, 128)), dim3(128), 0, st, (int64_t)0,
+  hipLaunchKernelGGL(k_tb_tasks, dim3(nblk(ntasks_cap, 4)), dim3(256), 0, st, (int64_t)0,
                      (int64_t)0, range, ntasks_cap, sorted, a, bw, tasks, dir_words);
   return hipGetLastError();
 }
@@ -492,29 +505,38 @@ __host__ __device__ __forceinline__ int64_t strip_dwords(int64_t width) {
 __global__ void k_tbw_tasks(int64_t n0, int64_t n1, const int64_t *range, int64_t ntasks_cap,
                             const int64_t *sorted, const TbArgs a, TbwTask *tasks,
                             int64_t *dir_words, int64_t *bnd_words) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // one wave per task, one lane per slot
+  const int lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (range) { n0 = range[0]; n1 = range[1]; }
   const int64_t ntasks = (n1 - n0 + kTbwSlots - 1) / kTbwSlots;
   if (t >= (range ? ntasks_cap : ntasks)) return;
   if (t >= ntasks) {
-    tasks[t] = TbwTask{};
-    dir_words[t] = 0;
-    bnd_words[t] = 0;
+    if (lane == 0) {
+      tasks[t] = TbwTask{};
+      dir_words[t] = 0;
+      bnd_words[t] = 0;
+    }
     return;
   }
   const int64_t s0 = n0 + t * kTbwSlots;
   const int64_t s1 = (s0 + kTbwSlots < n1) ? s0 + kTbwSlots : n1;
-  int64_t rows = 1, wmax = 1, dlo_min = 0, dhi_max = 0;
-  for (int64_t k = s0; k < s1; ++k) {
-    const int64_t p = sorted[k];
+  int64_t rows = 1, wmax = 1, ndlo_max = 0, dhi_max = 0;   // ndlo: -dlo, so all four are maxima
+  if (lane < kTbwSlots && s0 + lane < s1) {
+    const int64_t p = sorted[s0 + lane];
     const int64_t m = a.qend[p] - a.qbeg[p] + 1, w = a.rend[p] - a.rbeg[p] + 1;
     int64_t dlo, bw;
     safe_band(m, w, a.score[p], a.smax, a.o, a.e, &dlo, &bw);
     rows = m > rows ? m : rows;
     wmax = w > wmax ? w : wmax;
-    dlo_min = dlo < dlo_min ? dlo : dlo_min;
+    ndlo_max = -dlo > ndlo_max ? -dlo : ndlo_max;
     dhi_max = (dlo + bw - 1) > dhi_max ? (dlo + bw - 1) : dhi_max;
   }
+  rows = wave_max_i64(rows);
+  wmax = wave_max_i64(wmax);
+  const int64_t dlo_min = -wave_max_i64(ndlo_max);
+  dhi_max = wave_max_i64(dhi_max);
+  if (lane != 0) return;
   TbwTask tk{};
   tk.nslots = (int32_t)(s1 - s0);
   tk.rows = rows;
@@ -1127,7 +1149,7 @@ hipError_t tbw_tasks(int64_t n0, int64_t n1, const int64_t *sorted, const TbArgs
                      TbwTask *tasks, int64_t *dir_words, int64_t *bnd_words, hipStream_t st) {
   const int64_t nt = (n1 - n0 + kTbwSlots - 1) / kTbwSlots;
   if (nt <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tbw_tasks, dim3(nblk(nt, 128)), dim3(128), 0, st, n0, n1,
+  hipLaunchKernelGGL(k_tbw_tasks, dim3(nblk(nt, 4)), dim3(256), 0, st, n0, n1,
                      (const int64_t *)nullptr, (int64_t)0, sorted, a, tasks, dir_words, bnd_words);
   return hipGetLastError();
 }
@@ -1136,7 +1158,7 @@ hipError_t tbw_tasks_range(const int64_t *range, int64_t ntasks_cap, const int64
                            const TbArgs &a, TbwTask *tasks, int64_t *dir_words, int64_t *bnd_words,
                            hipStream_t st) {
   if (ntasks_cap <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tbw_tasks, dim3(nblk(ntasks_cap, 128)), dim3(128), 0, st, (int64_t)0,
+  hipLaunchKernelGGL(k_tbw_tasks, dim3(nblk(ntasks_cap, 4)), dim3(256), 0, st, (int64_t)0,
                      (int64_t)0, range, ntasks_cap, sorted, a, tasks, dir_words, bnd_words);
   return hipGetLastError();
 }
