@@ -228,12 +228,14 @@ __global__ void k_band_tb(BandArgs a) {
 }
 
 // ---- CIGAR compaction -----------------------------------------------------
+// 16 lanes per pair (most CIGARs have few runs), 16 pairs per block
 __global__ void k_cigar_compact(int64_t npairs, const uint32_t *src, const int64_t *src_off,
                                 const int32_t *len, const int64_t *dst_off, uint32_t *dst) {
-  const int64_t p = blockIdx.x;
+  const int64_t p = (int64_t)blockIdx.x * (blockDim.x / 16) + threadIdx.x / 16;
   if (p >= npairs) return;
   const int32_t n = len[p];
-  for (int32_t k = threadIdx.x; k < n; k += blockDim.x) dst[dst_off[p] + k] = src[src_off[p] + k];
+  const int64_t so = src_off[p], d = dst_off[p];
+  for (int32_t k = threadIdx.x & 15; k < n; k += 16) dst[d + k] = src[so + k];
 }
 
 // ---- score2 on inter tasks (max array = final CM plane) -------------------
@@ -566,7 +568,7 @@ hipError_t launch_cigar_compact(int64_t npairs, const uint32_t *src, const int64
                                 const int32_t *len, const int64_t *dst_off, uint32_t *dst,
                                 hipStream_t st) {
   if (!npairs) return hipSuccess;
-  hipLaunchKernelGGL(k_cigar_compact, dim3((unsigned)npairs), dim3(64), 0, st, npairs, src,
+  hipLaunchKernelGGL(k_cigar_compact, dim3(blocks_for(npairs, 16)), dim3(256), 0, st, npairs, src,
                      src_off, len, dst_off, dst);
   return hipGetLastError();
 }

@@ -144,22 +144,33 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
   constexpr int ND = BW / 8;        // direction dwords per row
   constexpr int NW = BW / 4 + 2;    // reference window dwords
 
+  const int8_t *qq = live ? q : (const int8_t *)a.matrix;   // readable bytes for empty lanes
+  const int8_t *rr = live ? r : (const int8_t *)a.matrix;
+  const int64_t mq = live ? m : 1, wr = live ? w : 1;
   // reference window: byte k of the window = symbol at local column
-  // base + k (1-based columns j use symbol r[j-1]); row i covers j = i+dlo+k
-  auto ref_byte = [&](int64_t j) -> uint32_t {   // symbol code of column j (1-based)
-    if (!live || j < 1 || j > w) return 0u;
-    const int32_t c = r[j - 1];
-    const uint32_t v = (c >= 0 && c < a.n) ? (uint32_t)c : 0u;   // a bad code never indexes a table
-    return LUT4 ? v * 8u : v;
-  };
+  // base + k (1-based columns j use symbol r[j-1]); row i covers j = i+dlo+k.
+  // Its bytes are loaded all at once (indices clamped into the sequence) and
+  // masked afterwards.
   uint32_t win[NW];
   {
     const int64_t j0 = 1 + dlo;   // row 1, k = 0
+    int32_t raw[4 * NW];
+#pragma unroll
+    for (int x = 0; x < 4 * NW; ++x) {
+      int64_t y = j0 + x - 1;
+      y = y < 0 ? 0 : (y > wr - 1 ? wr - 1 : y);
+      raw[x] = rr[y];
+    }
 #pragma unroll
     for (int d = 0; d < NW; ++d) {
       uint32_t v = 0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) v |= ref_byte(j0 + 4 * d + b) << (8 * b);
+      for (int b = 0; b < 4; ++b) {
+        const int64_t j = j0 + 4 * d + b;
+        const int32_t c = (live && j >= 1 && j <= w) ? raw[4 * d + b] : 0;
+        const uint32_t sy = (c >= 0 && c < a.n) ? (uint32_t)c : 0u;   // a bad code never indexes a table
+        v |= (LUT4 ? sy * 8u : sy) << (8 * b);
+      }
       win[d] = v;
     }
   }
@@ -194,9 +205,6 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
   // they land straight in their registers; values outside the pair are
   // masked when decoded.
   constexpr int UB = BW <= 16 ? 8 : (BW <= 32 ? 4 : 2);
-  const int8_t *qq = live ? q : (const int8_t *)a.matrix;   // readable bytes for empty lanes
-  const int8_t *rr = live ? r : (const int8_t *)a.matrix;
-  const int64_t mq = live ? m : 1, wr = live ? w : 1;
   auto load_block = [&](int64_t i0, int32_t (&qo)[UB], int32_t (&no)[UB]) {
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
@@ -599,6 +607,8 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
   const int64_t nstrips = (tk.rows + kStripR - 1) / kStripR;
   int32_t plo = 0, phi = (int32_t)tk.wmax + 1;   // columns of row sR that hold valid values
   const int8_t *rr = live ? r : (const int8_t *)a.matrix;   // readable bytes for empty slots
+  const int8_t *qq = live ? q : (const int8_t *)a.matrix;
+  const int64_t mq = live ? m : 1;
   for (int64_t s = 0; s < nstrips; ++s) {
     const int64_t sR = s * kStripR;
     int64_t clo64, chi64;
@@ -611,13 +621,19 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
     const int32_t wmax = (int32_t)tk.wmax, wl = (int32_t)w;
     uint32_t *sdir = dir + s * SW * 64;
     // this lane's rows: score tables
-    int32_t lut[RL], qn[RL];
+    int32_t lut[RL], qn[RL], qraw[RL];
+#pragma unroll
+    for (int k = 0; k < RL; ++k) {   // all loads first (clamped), then decode
+      int64_t x = sR + g * RL + k;
+      x = x > mq - 1 ? mq - 1 : x;
+      qraw[k] = qq[x];
+    }
 #pragma unroll
     for (int k = 0; k < RL; ++k) {
       const int64_t i = sR + g * RL + 1 + k;
       lut[k] = 0;
       qn[k] = 0;
-      const int32_t qs = (live && i <= m) ? (int32_t)q[i - 1] : -1;
+      const int32_t qs = (live && i <= m) ? qraw[k] : -1;
       if (qs >= 0 && qs < a.n) {   // a bad code never indexes a table
         if (LUT4) {
           uint32_t l = 0;
