@@ -499,10 +499,11 @@ __device__ __forceinline__ void strip_window(int64_t s, const TbwTask &tk, int64
 // lane k of each quad of lanes, to the whole quad (k a constant after unrolling)
 __device__ __forceinline__ int32_t quad_bcast(int32_t x, int k) {
   switch (k) {
-    case 0: return __builtin_amdgcn_update_dpp(0, x, 0x00, 0xF, 0xF, false);
-    case 1: return __builtin_amdgcn_update_dpp(0, x, 0x55, 0xF, 0xF, false);
-    case 2: return __builtin_amdgcn_update_dpp(0, x, 0xAA, 0xF, 0xF, false);
-    default: return __builtin_amdgcn_update_dpp(0, x, 0xFF, 0xF, 0xF, false);
+    // every source lane exists: no old value to keep
+    case 0: return __builtin_amdgcn_mov_dpp(x, 0x00, 0xF, 0xF, true);
+    case 1: return __builtin_amdgcn_mov_dpp(x, 0x55, 0xF, 0xF, true);
+    case 2: return __builtin_amdgcn_mov_dpp(x, 0xAA, 0xF, 0xF, true);
+    default: return __builtin_amdgcn_mov_dpp(x, 0xFF, 0xF, 0xF, true);
   }
 }
 __host__ __device__ __forceinline__ int64_t strip_dwords(int64_t width) {
@@ -644,9 +645,9 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
         }
       }
     }
-    int32_t H[RL], E[RL];
+    int32_t H[RL], E[RL], HO[RL];   // HO = H - o: the E opening of the next column
 #pragma unroll
-    for (int k = 0; k < RL; ++k) { H[k] = kNeg; E[k] = kNeg; }
+    for (int k = 0; k < RL; ++k) { H[k] = kNeg; E[k] = kNeg; HO[k] = kNeg - o; }
     // H of the row above at the previous column (lane 0: row sR at clo - 1)
     int32_t hdiag0 = kNeg;
     if (g == 0 && clo >= 1 && clo - 1 >= plo && clo - 1 < phi) hdiag0 = bH[(clo - 1) * NS + slot];
@@ -715,15 +716,16 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
 #pragma unroll
       for (int u = 0; u < kPB; ++u) {
         const int32_t t = t0 + u;
-        constexpr int kNone = 0;
         // lane 0's operands: from lane u % 4 of the quad
         const int32_t bh = quad_bcast(c_h[u / LP], u & (LP - 1));
         const int32_t bf = quad_bcast(c_f[u / LP], u & (LP - 1));
         const int32_t bs = quad_bcast(c_sy[u / LP], u & (LP - 1));
         // the other lanes': from the lane before (its last row, one step earlier)
-        const int32_t dh = __builtin_amdgcn_update_dpp(kNone, xh, 0x111, 0xF, 0xF, false);
-        const int32_t df = __builtin_amdgcn_update_dpp(kNone, xf, 0x111, 0xF, 0xF, false);
-        const int32_t ds = __builtin_amdgcn_update_dpp(kNone, (int32_t)xs, 0x111, 0xF, 0xF, false);
+        // (lane 0 of each row of 16 has no source and reads 0; it is a
+        // pair's lane 0, which takes the loaded operands instead)
+        const int32_t dh = __builtin_amdgcn_mov_dpp(xh, 0x111, 0xF, 0xF, true);
+        const int32_t df = __builtin_amdgcn_mov_dpp(xf, 0x111, 0xF, 0xF, true);
+        const int32_t ds = __builtin_amdgcn_mov_dpp((int32_t)xs, 0x111, 0xF, 0xF, true);
         const int32_t hup0 = g == 0 ? bh : dh;
         const int32_t fup0 = g == 0 ? bf : df;
         const uint32_t sym = (uint32_t)(g == 0 ? bs : ds);
@@ -732,14 +734,14 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
           const uint32_t sym8 = LUT4 ? sym * 8u : sym;
           int32_t hdiag = hdiag0;
           hdiag0 = hup0;
-          int32_t hup = hup0, fup = fup0;
+          int32_t hupo = hup0 - o, fup = fup0;   // hupo: H of the row above, minus o
 #pragma unroll
           for (int k = 0; k < RL; ++k) {
             const int32_t sc = LUT4 ? __builtin_amdgcn_sbfe(lut[k], sym8, 8) : (int32_t)s_mat[qn[k] + sym];
             const int32_t diag = hdiag + sc;
-            const int32_t fo = hup - o, fx = fup - e;
+            const int32_t fo = hupo, fx = fup - e;
             const int32_t fij = fo > fx ? fo : fx;
-            const int32_t eo = H[k] - o, ex = E[k] - e;      // H[k], E[k] = row k at column j-1
+            const int32_t eo = HO[k], ex = E[k] - e;      // row k at column j-1
             const int32_t eij = eo > ex ? eo : ex;
             int32_t h = diag > eij ? diag : eij;
             h = h > fij ? h : fij;
@@ -750,9 +752,11 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
             hdiag = H[k];
             H[k] = h;
             E[k] = eij;
-            hup = h;
+            hupo = h - o;
+            HO[k] = hupo;
             fup = fij;
           }
+          const int32_t hup = H[RL - 1];
           xh = hup;
           xf = fup;
         }
