@@ -29,6 +29,8 @@
 // saturating subtraction of the bias, which also applies the zero floor.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lanes.h"
 #include "swx_internal.h"
 #include "swx_kernels.h"
@@ -89,7 +91,10 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
   const InterTask tk = a.tasks[tid];
   if (tk.nslots == 0) return;   // an empty task of a fixed-capacity plan
   constexpr bool rev = REV;
-  const int nstrips = tk.qp / R;
+  const int nstrips = (tk.qp + R - 1) / R;
+  // forward passes only: the last strip has R / 2 rows (a reversed pass,
+  // padded at the bottom, runs its last strip full: the extra rows are padding)
+  const bool half_tail = !REV && (tk.qp % R) != 0;
   const int64_t rp = tk.rp;
 
   // slots of this lane
@@ -194,6 +199,7 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
 #pragma unroll
     for (int h = 0; h < NH; ++h) { sb[h] = 0u; sbk[h] = 31u; sbcol[h] = -1; }
     const bool last = (s == nstrips - 1);
+    const bool half = last && half_tail;
 
     // Column groups of 4.  The boundary words and reference symbols of group
     // g+1 are requested before group g is computed, so the loads overlap four
@@ -253,122 +259,133 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
       if (!rev) bC[pgi] = pc;
     };
 
-#pragma unroll 1
-    for (int64_t g = g0; g < g1; ++g) {
-      const uint4 ch = nh, cf = nf, cc = nc;
-      const uint2 sy = nsy;
-      if constexpr (kDelay) flush();
-      if (g + 1 < g1) fetch_group(g + 1);
-      uint32_t lx[4][2];   // QSEL: LUT words of the group's 4 columns
-      if constexpr (MODE == kQSel) {
-#pragma unroll
+    // the column groups, computing NR rows per column: R, or R / 2 in a
+    // half strip (a second copy of the loop, chosen once per strip)
+    auto run_groups = [&](auto nr) {
+      constexpr int NR = decltype(nr)::value;
+  #pragma unroll 1
+      for (int64_t g = g0; g < g1; ++g) {
+        const uint4 ch = nh, cf = nf, cc = nc;
+        const uint2 sy = nsy;
+        if constexpr (kDelay) flush();
+        if (g + 1 < g1) fetch_group(g + 1);
+        uint32_t lx[4][2];   // QSEL: LUT words of the group's 4 columns
+        if constexpr (MODE == kQSel) {
+  #pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            lx[k][0] = s_lut[__builtin_amdgcn_ubfe(sy.x, 8 * k, 8)];
+            lx[k][1] = (NH == 2) ? s_lut[__builtin_amdgcn_ubfe(sy.y, 8 * k, 8)] : 0u;
+          }
+        }
+        uint32_t oh[4], of[4], oc[4];
+  #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          lx[k][0] = s_lut[__builtin_amdgcn_ubfe(sy.x, 8 * k, 8)];
-          lx[k][1] = (NH == 2) ? s_lut[__builtin_amdgcn_ubfe(sy.y, 8 * k, 8)] : 0u;
-        }
-      }
-      uint32_t oh[4], of[4], oc[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        // keep the scheduler from hoisting later columns' score operands
-        // (independent of the recurrence) into this one: they would take
-        // R registers per column
-        __builtin_amdgcn_sched_barrier(0);
-        const int64_t c = 4 * g + k;
-        uint32_t X[R / 4][2];
-        if constexpr (MODE == kQGen) {
-#pragma unroll
-          for (int i = 0; i < R / 4; ++i) { X[i][0] = nX[i][0]; X[i][1] = nX[i][1]; }
-          if (k < 3) {
-            fetch_prof(__builtin_amdgcn_ubfe(sy.x, 8 * (k + 1), 8),
-                       __builtin_amdgcn_ubfe(sy.y, 8 * (k + 1), 8));
-          } else if (g + 1 < g1) {
-            fetch_prof(nsy.x & 0xFFu, nsy.y & 0xFFu);
+          // keep the scheduler from hoisting later columns' score operands
+          // (independent of the recurrence) into this one: they would take
+          // R registers per column
+          __builtin_amdgcn_sched_barrier(0);
+          const int64_t c = 4 * g + k;
+          uint32_t X[R / 4][2];
+          if constexpr (MODE == kQGen) {
+  #pragma unroll
+            for (int i = 0; i < R / 4; ++i) { X[i][0] = nX[i][0]; X[i][1] = nX[i][1]; }
+            if (k < 3) {
+              fetch_prof(__builtin_amdgcn_ubfe(sy.x, 8 * (k + 1), 8),
+                         __builtin_amdgcn_ubfe(sy.y, 8 * (k + 1), 8));
+            } else if (g + 1 < g1) {
+              fetch_prof(nsy.x & 0xFFu, nsy.y & 0xFFu);
+            }
+          } else {
+            X[0][0] = lx[k][0];
+            X[0][1] = lx[k][1];
           }
-        } else {
-          X[0][0] = lx[k][0];
-          X[0][1] = lx[k][1];
-        }
-        V hup = T::from(word_of(ch, k));
-        // anchored reversed pass: the row above the first row is the run of
-        // gap symbols that may follow the anchor cell's alignment (a forward
-        // alignment may end in a deletion run: its end cell is then in the
-        // gap state), H = anchor - o - c*e at column c
-        if constexpr (REV && NH == 1) {   // anchored passes run on 32-bit lanes only
-          if (s == 0 && a.anchor) {
-            const uint32_t gap = (uint32_t)a.o + (uint32_t)c * (uint32_t)a.e;
-            hup = T::splat(a.anchor > gap ? a.anchor - gap : 0u);
+          V hup = T::from(word_of(ch, k));
+          // anchored reversed pass: the row above the first row is the run of
+          // gap symbols that may follow the anchor cell's alignment (a forward
+          // alignment may end in a deletion run: its end cell is then in the
+          // gap state), H = anchor - o - c*e at column c
+          if constexpr (REV && NH == 1) {   // anchored passes run on 32-bit lanes only
+            if (s == 0 && a.anchor) {
+              const uint32_t gap = (uint32_t)a.o + (uint32_t)c * (uint32_t)a.e;
+              hup = T::splat(a.anchor > gap ? a.anchor - gap : 0u);
+            }
           }
-        }
-        const V hdiag_in = hdtop;
-        V F = T::from(word_of(cf, k));
-        const V cmin = T::from(word_of(cc, k));
+          const V hdiag_in = hdtop;
+          V F = T::from(word_of(cf, k));
+          const V cmin = T::from(word_of(cc, k));
 
-        // rows: the part of each cell that does not depend on the F chain
-        // (diagonal + substitution, max with E) is computed one row ahead
-        hdtop = hup;
-        V cm = T::zero();
-        V ho = T::zero();
-        auto score_of = [&](int r) -> V {
-          uint32_t sraw;
-          if constexpr (MODE == kQSel) sraw = perm(X[0][1], X[0][0], sel[r]);
-          else sraw = perm(X[r >> 2][1], X[r >> 2][0], T::sel_const(r & 3));
-          return T::from(sraw);
-        };
-        V u_next = T::max(T::add(hdiag_in, score_of(0)), E[0]);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const V u = u_next;
-          if (r + 1 < R) u_next = T::max(T::add(H[r], score_of(r + 1)), E[r + 1]);
-          const V hb = T::max(u, F);
-          const V hn = T::subs(hb, vbias);
-          H[r] = hn;
-          const uint32_t code = code_top - (uint32_t)r;
-          cm = T::max(cm, CLAMP ? T::enc(hn, T::code_splat(code)) : T::enc_nosat(hn, code, mul32));
-          ho = T::subs(hb, vo);
-          E[r] = T::max(T::subs(E[r], ve), ho);
-          F = T::max(T::subs(F, ve), ho);   // F of the next row
+          // rows: the part of each cell that does not depend on the F chain
+          // (diagonal + substitution, max with E) is computed one row ahead
+          hdtop = hup;
+          V cm = T::zero();
+          V ho = T::zero();
+          auto score_of = [&](int r) -> V {
+            uint32_t sraw;
+            if constexpr (MODE == kQSel) sraw = perm(X[0][1], X[0][0], sel[r]);
+            else sraw = perm(X[r >> 2][1], X[r >> 2][0], T::sel_const(r & 3));
+            return T::from(sraw);
+          };
+          V u_next = T::max(T::add(hdiag_in, score_of(0)), E[0]);
+  #pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const V u = u_next;
+            if (r + 1 < NR) u_next = T::max(T::add(H[r], score_of(r + 1)), E[r + 1]);
+            const V hb = T::max(u, F);
+            const V hn = T::subs(hb, vbias);
+            H[r] = hn;
+            const uint32_t code = code_top - (uint32_t)r;
+            cm = T::max(cm, CLAMP ? T::enc(hn, T::code_splat(code)) : T::enc_nosat(hn, code, mul32));
+            ho = T::subs(hb, vo);
+            E[r] = T::max(T::subs(E[r], ve), ho);
+            F = T::max(T::subs(F, ve), ho);   // F of the next row
+          }
+          oh[k] = T::bits(H[NR - 1]);
+          of[k] = T::bits(F);
+          oc[k] = T::bits(T::max(cmin, T::shr5(cm)));
+          // strip best: first column reaching the strip's largest value
+  #pragma unroll
+          for (int h = 0; h < NH; ++h) {
+            const uint32_t v = T::half(cm, h);
+            const uint32_t vk = v | 31u;
+            // lastcol (32-bit lanes): only the pair's last column (padded
+            // column rp - 1) counts
+            const bool imp = vk > sbk[h] && (REV || NH == 2 || !a.lastcol || c == rp - 1);
+            sb[h] = imp ? v : sb[h];
+            sbk[h] = imp ? vk : sbk[h];
+            sbcol[h] = imp ? (int32_t)c : sbcol[h];
+          }
         }
-        oh[k] = T::bits(H[R - 1]);
-        of[k] = T::bits(F);
-        oc[k] = T::bits(T::max(cmin, T::shr5(cm)));
-        // strip best: first column reaching the strip's largest value
-#pragma unroll
-        for (int h = 0; h < NH; ++h) {
-          const uint32_t v = T::half(cm, h);
-          const uint32_t vk = v | 31u;
-          // lastcol (32-bit lanes): only the pair's last column (padded
-          // column rp - 1) counts
-          const bool imp = vk > sbk[h] && (REV || NH == 2 || !a.lastcol || c == rp - 1);
-          sb[h] = imp ? v : sb[h];
-          sbk[h] = imp ? vk : sbk[h];
-          sbcol[h] = imp ? (int32_t)c : sbcol[h];
+        const int64_t gi = g * 64 + lane;
+        // the last forward strip has no reader for H and F: it overwrites the
+        // first group's words instead (they stay in L2).  A store that is
+        // skipped instead costs registers: the compiler splits the loop.
+        const int64_t ghf = (last && !rev) ? (int64_t)lane : gi;
+        ph = make_uint4(oh[0], oh[1], oh[2], oh[3]);
+        pf = make_uint4(of[0], of[1], of[2], of[3]);
+        pc = make_uint4(oc[0], oc[1], oc[2], oc[3]);
+        pgi = gi;
+        pghf = ghf;
+        if constexpr (!kDelay) flush();
+        if (rev && (g & 1)) {
+          // leave the strip once every pair has reached its target at or before
+          // the group's last column: later columns can neither give an earlier
+          // column nor a smaller row
+          int64_t need = -1;
+  #pragma unroll
+          for (int h = 0; h < NH; ++h) {
+            int64_t rr = reach[h];
+            if (rr >= 0 && (int32_t)(sb[h] >> 5) >= tgt[h] && sbcol[h] < rr) rr = sbcol[h];
+            need = rr > need ? rr : need;
+          }
+          if (wave_max64(need) <= 4 * g + 4) { cdone = 4 * g + 4; break; }
         }
       }
-      const int64_t gi = g * 64 + lane;
-      // the last forward strip has no reader for H and F: it overwrites the
-      // first group's words instead (they stay in L2).  A store that is
-      // skipped instead costs registers: the compiler splits the loop.
-      const int64_t ghf = (last && !rev) ? (int64_t)lane : gi;
-      ph = make_uint4(oh[0], oh[1], oh[2], oh[3]);
-      pf = make_uint4(of[0], of[1], of[2], of[3]);
-      pc = make_uint4(oc[0], oc[1], oc[2], oc[3]);
-      pgi = gi;
-      pghf = ghf;
-      if constexpr (!kDelay) flush();
-      if (rev && (g & 1)) {
-        // leave the strip once every pair has reached its target at or before
-        // the group's last column: later columns can neither give an earlier
-        // column nor a smaller row
-        int64_t need = -1;
-#pragma unroll
-        for (int h = 0; h < NH; ++h) {
-          int64_t rr = reach[h];
-          if (rr >= 0 && (int32_t)(sb[h] >> 5) >= tgt[h] && sbcol[h] < rr) rr = sbcol[h];
-          need = rr > need ? rr : need;
-        }
-        if (wave_max64(need) <= 4 * g + 4) { cdone = 4 * g + 4; break; }
-      }
+    };
+    if constexpr (MODE == kQSel && !REV) {
+      if (half) run_groups(std::integral_constant<int, R / 2>{});
+      else run_groups(std::integral_constant<int, R>{});
+    } else {
+      run_groups(std::integral_constant<int, R>{});
     }
     if constexpr (kDelay) flush();   // the strip's last group, before the next strip reads it
     // merge the strip best into the pair best (earlier strips win ties)

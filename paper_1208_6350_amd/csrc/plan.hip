@@ -28,7 +28,7 @@ __global__ void k_plan_keys(int64_t n, const int64_t *n_dev, const int64_t *ids,
   const int64_t p = ids ? ids[k] : k;
   int64_t q = qlen[p];
   if (q < 1) q = 1;
-  const uint64_t qc = (uint64_t)((q + R - 1) / R);
+  const uint64_t qc = (uint64_t)((q + R / 2 - 1) / (R / 2));   // half-strip buckets
   uint64_t r = (uint64_t)rlen[p];
   if (r > 0xFFFFFFFull) r = 0xFFFFFFFull;
   // band class: the band half-width, except that pairs whose band spans
@@ -82,7 +82,10 @@ __global__ void k_plan_tasks(int64_t n, const int64_t *n_dev, int64_t ntasks, in
   if (lane != 0) return;
   InterTask tk{};
   tk.nslots = (int32_t)(s1 - s0);
-  tk.qp = (int32_t)((mq + R - 1) / R * R);
+  // without a query profile the last strip may be half high: rows are
+  // padded to a multiple of R / 2 (an odd multiple leaves a half strip last)
+  const int64_t unit = qdata_per_row == 0 ? R / 2 : R;
+  tk.qp = (int32_t)((mq + unit - 1) / unit * unit);
   tk.rp = (int32_t)((mr + 7) / 8 * 8);
   tk.band = band ? (mb == INT64_MAX ? -1 : (int32_t)mb) : -1;
   tk.slot_base = s0;

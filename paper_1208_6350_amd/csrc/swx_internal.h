@@ -21,7 +21,8 @@ constexpr int kSlots32 = 64;
 
 struct InterTask {
   int32_t nslots;     // occupied slots
-  int32_t qp;         // padded rows (multiple of the strip height)
+  int32_t qp;         // padded rows: a multiple of the strip height R, or (no
+                      // query profile) of R / 2, the last strip then half high
   int32_t rp;         // padded columns (multiple of 8)
   int32_t band;       // reversed pass: band half-width around the main diagonal (-1: none)
   int64_t slot_base;  // slots are slot_pair[slot_base + s]
