@@ -569,7 +569,7 @@ template <bool LUT4>
 __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks, int64_t ntasks,
                                                   const int64_t *sorted, int32_t *bndbuf) {
   constexpr int LP = kStripLP, RL = kStripRL, NS = kTbwSlots;
-  constexpr int kCU = 8;    // walk cache: code dwords (16 steps) per lane
+  constexpr int kCU = 16;   // walk cache: code dwords (32 steps) per lane
   __shared__ int8_t s_mat[32 * 32];
   __shared__ uint32_t s_walk[4 * 64 * kCU];
   for (int k = threadIdx.x; k < a.n * a.n; k += blockDim.x) s_mat[k] = a.matrix[k];
@@ -786,8 +786,13 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
     return;
   }
   // Traceback from (m, w) in state H.  The four lanes of a pair walk it
-  // together; when the walk leaves the cached columns, each lane pulls kCU
-  // dwords of its own row group into the pair's LDS slots.
+  // together.  Each lane keeps kCU code dwords of its own row group of the
+  // current strip in the pair's LDS slots (a window of columns ending at the
+  // column where it was filled; the walk only moves up and left).  On entering
+  // a strip the lanes also request the strip above, ending at the current
+  // column, into registers: when the walk gets there, the window is written
+  // to LDS from those registers without waiting for memory.  Only a walk
+  // that leaves a window sideways waits for a load.
   uint32_t *out = a.cig + a.cig_off[p];
   int32_t nruns = 0;
   int64_t i = m, j = w;
@@ -796,6 +801,19 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
   int64_t guard = 2 * (m + w) + 4;
   uint32_t *cache = s_walk + ((threadIdx.x >> 6) * 64 + slot * LP) * kCU;   // [g][kCU]
   int64_t cache_s = -1, cache_j = -1;
+  uint32_t pfx[kCU];              // the strip above, in flight
+  int64_t pf_s = -1, pf_j = -1;
+  auto fetch_window = [&](int64_t s, int64_t jj, uint32_t (&dst)[kCU]) {
+    int64_t clo, chi;
+    strip_window(s, tk, &clo, &chi);
+    const int64_t mytop = (jj - clo + g) >> 1;
+#pragma unroll
+    for (int x = 0; x < kCU; ++x) {
+      int64_t uu = mytop - x;
+      uu = uu < 0 ? 0 : (uu > SW - 1 ? SW - 1 : uu);   // clamped: never read outside the strip
+      dst[x] = dir[(s * SW + uu) * 64 + slot * LP + g];
+    }
+  };
   bool bad = false;
   while ((i > 0 || j > 0) && guard-- > 0) {
     uint32_t c;
@@ -811,14 +829,25 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
       // cached: dwords (cache_j - clo + g) / 2 - kCU + 1 .. (cache_j - clo + g) / 2 of row group g
       const int64_t top = (cache_j - clo + gk) >> 1;
       if (s != cache_s || (t >> 1) > top || (t >> 1) <= top - kCU) {
-        cache_s = s;
-        cache_j = j;
-        const int64_t mytop = (j - clo + g) >> 1;
+        const int64_t ptop = (pf_j - clo + gk) >> 1;
+        const bool use_pf = s == pf_s && (t >> 1) <= ptop && (t >> 1) > ptop - kCU;
+        if (use_pf) {
 #pragma unroll
-        for (int x = 0; x < kCU; ++x) {
-          const int64_t uu = mytop - x;
-          cache[g * kCU + x] = uu >= 0 ? dir[(s * SW + uu) * 64 + slot * LP + g] : 0u;
+          for (int x = 0; x < kCU; ++x) cache[g * kCU + x] = pfx[x];
+          cache_j = pf_j;
+        } else {
+          uint32_t now[kCU];
+          fetch_window(s, j, now);
+#pragma unroll
+          for (int x = 0; x < kCU; ++x) cache[g * kCU + x] = now[x];
+          cache_j = j;
         }
+        if (s != cache_s && s > 0) {   // a new strip: request the one above
+          fetch_window(s - 1, j, pfx);
+          pf_s = s - 1;
+          pf_j = j;
+        }
+        cache_s = s;
       }
       const int64_t top2 = (cache_j - clo + gk) >> 1;
       const uint32_t dwv = cache[gk * kCU + (top2 - (t >> 1))];
