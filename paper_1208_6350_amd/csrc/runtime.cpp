@@ -355,7 +355,7 @@ struct SideLaunch {
   std::function<hipError_t(hipStream_t)> fn;
   bool lead = false;
 };
-constexpr double kLeadShare = 0.3;
+constexpr double kLeadShare = 0.2;
 
 static int run_side_by_side(swx_ctx *ctx, std::vector<SideLaunch> &ls) {
   if (ls.empty()) return SWX_OK;
@@ -381,12 +381,19 @@ static int run_side_by_side(swx_ctx *ctx, std::vector<SideLaunch> &ls) {
   });
   HIP_TRY(hipEventRecord(ctx->fork_ev, ctx->stream));
   for (int k = 0; k < na; ++k) HIP_TRY(hipStreamWaitEvent(ctx->aux[k], ctx->fork_ev, 0));
+  // place every launch first, then submit stream by stream: the lead's
+  // stream is filled before the other one starts (measured: interleaved
+  // submission lets the other stream's first kernel take the device first)
   double load[na] = {0, 0};
-  for (auto &l : ls) {
+  std::vector<int> where(ls.size());
+  for (size_t x = 0; x < ls.size(); ++x) {
     const int k = load[0] <= load[1] ? 0 : 1;
-    load[k] += l.lead ? kLeadShare * l.cost : l.cost;
-    HIP_TRY(l.fn(ctx->aux[k]));
+    load[k] += ls[x].lead ? kLeadShare * ls[x].cost : ls[x].cost;
+    where[x] = k;
   }
+  for (int k = 0; k < na; ++k)
+    for (size_t x = 0; x < ls.size(); ++x)
+      if (where[x] == k) HIP_TRY(ls[x].fn(ctx->aux[k]));
   for (int k = 0; k < na; ++k) {
     HIP_TRY(hipEventRecord(ctx->join_ev[k], ctx->aux[k]));
     HIP_TRY(hipStreamWaitEvent(ctx->stream, ctx->join_ev[k], 0));
