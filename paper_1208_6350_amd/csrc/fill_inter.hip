@@ -485,12 +485,12 @@ __global__ __launch_bounds__(256) void k_inter_rsym(PackArgs a) {
   uint2 *dst = a.rsym + rsym_offset(tk.bnd_off);
   for (int64_t c0 = 0; c0 < tk.rp; c0 += kRsymChunk) {
     const int64_t c = c0 + threadIdx.x;
-    // slots in groups of 16: the group's loads are all in flight before the
-    // first byte is written to the tile
-    for (int s0 = 0; s0 < nslots; s0 += 16) {
-      int8_t raw[16];
+    // slots in groups of 64: the group's loads are all in flight before the
+    // first byte is written to the tile (one memory wait per 64 slots)
+    for (int s0 = 0; s0 < nslots; s0 += 64) {
+      int8_t raw[64];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < 64; ++u) {
         const int s = s0 + u;
         const int64_t j = c - s_pad[s];
         const int64_t len = s_len[s];
@@ -498,7 +498,7 @@ __global__ __launch_bounds__(256) void k_inter_rsym(PackArgs a) {
         raw[u] = in ? s_base[s][reversed ? len - 1 - j : j] : (int8_t)-1;
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < 64; ++u) {
         const int8_t x = raw[u];
         tile[(s0 + u) * kRsymStride + threadIdx.x] =
             (x >= 0 && x < a.n) ? (uint8_t)x : pad_sym;   // a bad code never indexes a table
