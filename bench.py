@@ -40,9 +40,10 @@ def parse():
     ap.add_argument("--per-pair-sample", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serve-rate", default="2e4,5e4",
-                    help="offered loads of the serving phase, requests per second (comma list)")
-    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--serve-rate", default="2e4,1e5,5e5,2e6",
+                    help="offered loads of the serving phase, requests per second (comma list): "
+                         "the workload's three loads, and one below capacity")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed steps (no autotuner, output modes, graph, per-pair, "
@@ -114,18 +115,27 @@ def cpu_baseline(b, seconds):
                       f"{dt:.1f} s, whole path incl. begin/CIGAR/score2)"}
 
 
-def serving_phase(rate, seconds, warmup=0.25, pool_short=20_000, pool_long=200, workers=3,
-                  mem_budget=32 << 30, graph_batch=0, side_streams=-1):
+_SERVE_POOL = {}
+
+
+def serving_phase(rate, seconds, warmup=0.5, pool_short=50_000, pool_long=1_000, workers=3,
+                  mem_budget=32 << 30, max_pending=8192, graph_batch=0, side_streams=-1):
     """Open-loop Poisson replay of the serving workload through swx_server_*:
-    90% 150-nt reads vs 1-kb windows, 10% 10-kb reads vs 20-kb windows.
-    Latency = completion time - scheduled arrival (so queueing behind an
-    overloaded server counts).  Requests arriving in the first `warmup`
-    seconds are served but not measured."""
+    90% 150-nt reads vs 1-kb windows, 10% 10-kb reads vs 20-kb windows, drawn
+    from a seeded pool.  Latency = completion time - scheduled arrival (so
+    queueing behind an overloaded server counts).  A request that finds the
+    queue full (max_pending waiting) is refused and counted, not retried, so
+    an offered load above capacity measures saturated throughput and the
+    queueing delay of the admitted requests.  Requests arriving in the first
+    `warmup` seconds are served but not measured."""
     import numpy as np
 
     import paper_1208_6350_amd as swx
     import workloads as W
-    pool = W.config5_pool(n_short=pool_short, n_long=pool_long)
+    key = (pool_short, pool_long)
+    if key not in _SERVE_POOL:
+        _SERVE_POOL[key] = W.config5_pool(n_short=pool_short, n_long=pool_long)
+    pool = _SERVE_POOL[key]
     is_long = pool.meta["is_long"]
     g = W.rng_for(105)
     t_arr, which = W.poisson_schedule(g, rate, warmup + seconds, pool.npairs, is_long, 0.10)
@@ -135,21 +145,28 @@ def serving_phase(rate, seconds, warmup=0.25, pool_short=20_000, pool_long=200, 
     cells = (pool.qlen()[which].astype(np.int64) * pool.rlen()[which])
     lng = is_long[which]
     srv = swx.Server(pool.matrix, pool.gap_open, pool.gap_extend, workers=workers,
-                     mem_budget=mem_budget, graph_batch=graph_batch, graph_max_qlen=200,
-                     graph_max_rlen=1100, side_streams=side_streams)
+                     mem_budget=mem_budget, max_pending=max_pending, graph_batch=graph_batch,
+                     graph_max_qlen=200, graph_max_rlen=1100, side_streams=side_streams)
     done_ns = np.zeros(n, dtype=np.int64)
     bsize = np.zeros(n, dtype=np.int64)
+    accepted = np.zeros(n, dtype=bool)
     t0 = time.monotonic_ns() + 20_000_000
     arr_ns = t0 + (t_arr * 1e9).astype(np.int64)
-    sub, got, busy = 0, 0, 0
+    sub, got, nacc = 0, 0, 0
     limit = t0 + int((warmup + seconds + 120) * 1e9)
-    while got < n and time.monotonic_ns() < limit:
+    while (sub < n or got < nacc) and time.monotonic_ns() < limit:
         now = time.monotonic_ns()
         k = int(np.searchsorted(arr_ns, now, side="right"))
         if k > sub:
-            st, tk = srv.submit(reqs[sub:k])
-            busy += (k - sub) - len(tk)
-            sub += len(tk)
+            # each size class has its own queue limit: submit the arrivals
+            # class by class, so that a full long queue refuses only long ones
+            for c in (False, True):
+                idx = sub + np.nonzero(lng[sub:k] == c)[0]
+                if len(idx):
+                    st, tk = srv.submit(reqs[idx])
+                    accepted[idx[:len(tk)]] = True
+                    nacc += len(tk)
+            sub = k   # the refused rest of this arrival group is dropped
         out = srv.poll(65536, timeout_us=200)
         if len(out):
             tags = out["tag"].astype(np.int64)
@@ -160,9 +177,10 @@ def serving_phase(rate, seconds, warmup=0.25, pool_short=20_000, pool_long=200, 
                 raise RuntimeError("serving request failed")
     stats = srv.stats()
     srv.close()
-    if got < n:
-        raise RuntimeError(f"serving phase did not finish: {got}/{n}")
-    meas = t_arr >= warmup
+    if got < nacc or sub < n:
+        raise RuntimeError(f"serving phase did not finish: {got}/{nacc}")
+    meas = (t_arr >= warmup) & accepted
+    offered = t_arr >= warmup
     lat_ms = (done_ns - arr_ns) / 1e6
 
     def pct(mask):
@@ -171,15 +189,18 @@ def serving_phase(rate, seconds, warmup=0.25, pool_short=20_000, pool_long=200, 
         return {"p50_ms": round(float(np.percentile(lat_ms[mask], 50)), 3),
                 "p99_ms": round(float(np.percentile(lat_ms[mask], 99)), 3),
                 "n": int(mask.sum())}
-    wall = (done_ns[meas].max() - arr_ns[meas].min()) / 1e9
-    return {"offered_per_s": rate, "seconds": seconds, "requests": int(meas.sum()),
+    wall = (done_ns[meas].max() - arr_ns[offered].min()) / 1e9 if meas.any() else float("nan")
+    return {"offered_per_s": rate, "seconds": seconds, "warmup_s": warmup,
+            "requests_offered": int(offered.sum()), "requests_admitted": int(meas.sum()),
+            "refused_queue_full": int((offered & ~accepted).sum()),
             "offered_gcups": round(float(cells.mean()) * rate / 1e9, 1),
             "sustained_gcups": round(float(cells[meas].sum()) / wall / 1e9, 1),
             "latency_all": pct(meas), "latency_short": pct(meas & ~lng),
             "latency_long": pct(meas & lng),
             "batches": stats["batches"], "max_batch": stats["max_batch_seen"],
-            "mean_batch": round(float(bsize[meas].mean()), 1), "deferred_busy": busy,
+            "mean_batch": round(float(bsize[meas].mean()), 1) if meas.any() else None,
             "workers": workers, "mem_budget_gib": mem_budget / 2**30,
+            "max_pending": max_pending,
             "graph_batch": graph_batch, "graph_batches": stats["graph_batches"],
             "pool": f"{pool_short} short + {pool_long} long requests"}
 

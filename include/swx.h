@@ -307,7 +307,8 @@ typedef struct {
   int device;
   const int8_t *matrix; int32_t n; int32_t gap_open; int32_t gap_extend;   /* copied */
   int64_t mem_budget;   /* bytes; <= 0: 4 GiB */
-  int32_t max_pending;  /* submit accepts no more while this many wait; <= 0: 2^20 */
+  int32_t max_pending;  /* submit accepts no more requests of a size class while this
+                           many of that class wait; <= 0: 2^20 */
   int32_t workers;      /* concurrent batches (1..16); <= 0: 3 */
   int32_t max_batch;    /* requests per batch; <= 0: 65536 */
   uint32_t flags;       /* SWX_BEGIN | SWX_CIGAR | SWX_SCORE2 for every request */
@@ -352,9 +353,13 @@ int swx_server_create(const swx_server_cfg *cfg, swx_server **out);
 /* Uploads a query once; *query_id names it in later requests.  SWX_EINVAL for
  * qlen < 1 or a symbol >= n. */
 int swx_server_register_query(swx_server *s, const int8_t *query, int32_t qlen, int64_t *query_id);
-/* Queues nreq requests in order; tickets[k] names request k.  All requests
- * are validated first (SWX_EINVAL: none queued).  When the queue is full the
- * first *naccepted are queued and SWX_EBUSY is returned. */
+/* Queues nreq requests in order; tickets[k] names request k.  The fields of
+ * every request, and the symbols of those that fit the queues, are checked
+ * first (SWX_EINVAL: none queued; requests past the fitting prefix are
+ * neither checked nor copied).  When a request finds its
+ * size class's queue full (max_pending waiting), it and the requests after it
+ * are not queued: the first *naccepted are, and SWX_EBUSY is returned (a
+ * caller that keeps short requests flowing submits the classes separately). */
 int swx_server_submit(swx_server *s, const swx_request *rq, int32_t nreq, uint64_t *tickets,
                       int32_t *naccepted);
 /* Moves up to max finished completions into done (waiting up to timeout_us

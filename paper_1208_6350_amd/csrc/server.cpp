@@ -431,17 +431,34 @@ int swx_server_submit(swx_server *s, const swx_request *rq, int32_t nreq, uint64
   if (!s || (nreq > 0 && (!rq || !tickets)) || !naccepted || nreq < 0)
     return swx::internal_fail(SWX_EINVAL, "null argument");
   *naccepted = 0;
-  // validate everything first: a rejected call accepts nothing
+  // the fields of every request first; then, under the lock, the prefix that
+  // fits its classes' queues.  Only that prefix is checked symbol by symbol
+  // and copied (an overloaded server refuses most of a large call, and must
+  // not spend its time copying what it refuses); a rejected call accepts
+  // nothing.
   int64_t nq;
+  int32_t nfit = 0;
   {
     std::lock_guard<std::mutex> g(s->mu);
     nq = (int64_t)s->queries.size();
+    for (int32_t k = 0; k < nreq; ++k) {
+      const swx_request &r = rq[k];
+      if (r.rlen < 0 || (r.rlen > 0 && !r.ref)) return swx::internal_fail(SWX_EINVAL, "bad reference");
+      if (r.query_id >= nq) return swx::internal_fail(SWX_EINVAL, "unknown query id");
+      if (r.query_id < 0 && (r.qlen < 1 || !r.query)) return swx::internal_fail(SWX_EINVAL, "bad query");
+    }
+    int64_t room[2] = {s->cfg.max_pending - (int64_t)s->pending[0].size(),
+                       s->cfg.max_pending - (int64_t)s->pending[1].size()};
+    for (; nfit < nreq; ++nfit) {
+      const swx_request &r = rq[nfit];
+      const int64_t ql = r.query_id < 0 ? r.qlen : s->queries[r.query_id].qlen;
+      const int c = swx_sched::size_class(ql, r.rlen, s->cfg.long_cells);
+      if (room[c] <= 0) break;
+      --room[c];
+    }
   }
-  for (int32_t k = 0; k < nreq; ++k) {
+  for (int32_t k = 0; k < nfit; ++k) {
     const swx_request &r = rq[k];
-    if (r.rlen < 0 || (r.rlen > 0 && !r.ref)) return swx::internal_fail(SWX_EINVAL, "bad reference");
-    if (r.query_id >= nq) return swx::internal_fail(SWX_EINVAL, "unknown query id");
-    if (r.query_id < 0 && (r.qlen < 1 || !r.query)) return swx::internal_fail(SWX_EINVAL, "bad query");
     if (r.query_id < 0)
       for (int32_t i = 0; i < r.qlen; ++i)
         if (r.query[i] < 0 || r.query[i] >= s->cfg.n)
@@ -452,8 +469,8 @@ int swx_server_submit(swx_server *s, const swx_request *rq, int32_t nreq, uint64
   }
   const int64_t t = now_ns();
   std::vector<Req> reqs;
-  reqs.reserve((size_t)nreq);
-  for (int32_t k = 0; k < nreq; ++k) {
+  reqs.reserve((size_t)nfit);
+  for (int32_t k = 0; k < nfit; ++k) {
     const swx_request &r = rq[k];
     Req q;
     q.tag = r.tag;
@@ -475,7 +492,9 @@ int swx_server_submit(swx_server *s, const swx_request *rq, int32_t nreq, uint64
   std::lock_guard<std::mutex> g(s->mu);
   int32_t acc = 0;
   for (Req &q : reqs) {
-    if ((int64_t)(s->pending[0].size() + s->pending[1].size()) >= s->cfg.max_pending) break;
+    // each size class has its own queue limit: a backlog of long requests
+    // never refuses short ones
+    if ((int64_t)s->pending[q.cls].size() >= s->cfg.max_pending) break;
     q.ticket = s->next_ticket++;
     tickets[acc++] = q.ticket;
     s->pending[q.cls].push_back(std::move(q));

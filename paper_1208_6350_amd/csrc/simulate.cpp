@@ -113,7 +113,7 @@ extern "C" int swx_server_simulate(const swx_server_cfg *cfg_in, const swx_sim_m
       t = t_done;
     } else {                                // a request arrives
       t = t_arr;
-      if ((int64_t)(pending[0].size() + pending[1].size()) >= cfg.max_pending) {
+      if ((int64_t)pending[out[a].cls].size() >= cfg.max_pending) {
         out[a].status = SWX_EBUSY;
         st.deferred += 1;
       } else {

@@ -141,6 +141,35 @@ def test_admission_budget_and_queue_limit():
         srv.close()
 
 
+def test_size_classes_have_their_own_queue_limit():
+    # long requests fill their queue and are refused; short ones submitted
+    # next are still queued, and every accepted request equals the oracle
+    lb = W.random_pairs(815, 8, (30, 40), (30, 40))   # at least 900 cells: long below
+    sb = W.random_pairs(816, 4, (5, 10), (5, 10))     # at most 100 cells: short
+    srv = swx.Server(lb.matrix, lb.gap_open, lb.gap_extend, workers=1, max_pending=2,
+                     mem_budget=1, long_cells=500)
+    try:
+        lr = swx.make_requests(lb.qcat, lb.qoff, lb.rcat, lb.roff, lb.pair_q, lb.pair_r,
+                               tags=np.arange(lb.npairs))
+        st, tk = srv.submit(lr)
+        assert st == swx.SWX_EBUSY and 2 <= len(tk) < lb.npairs
+        sr = swx.make_requests(sb.qcat, sb.qoff, sb.rcat, sb.roff, sb.pair_q[:2], sb.pair_r[:2],
+                               tags=100 + np.arange(2))
+        st2, tk2 = srv.submit(sr)
+        assert st2 == 0 and len(tk2) == 2
+        out, _ = _collect(srv, len(tk) + 2)
+    finally:
+        srv.close()
+    assert (out["status"] == 0).all()
+    for bt, base in ((lb, 0), (sb, 100)):
+        ref, _, _ = oracle.align_many(bt.qcat, bt.qoff, bt.rcat, bt.roff, bt.pair_q, bt.pair_r,
+                                      bt.matrix, bt.gap_open, bt.gap_extend)
+        for c in out[(out["tag"] >= base) & (out["tag"] < base + 100)]:
+            p = int(c["tag"]) - base
+            for f_i, f in enumerate(FIELDS):
+                assert int(c["rec"][f]) == int(ref[p][f_i]), (base, p, f)
+
+
 def test_invalid_request_accepts_nothing():
     b = W.random_pairs(812, 4, (3, 10), (3, 10))
     b.rcat[1] = 7

@@ -83,7 +83,7 @@ def _policy_schedule(arr, ql, rl, *, cells_per_us, batch_us, request_us, n, mem_
             t = t_done
         else:
             t = t_arr
-            if len(pending[0]) + len(pending[1]) >= max_pending:
+            if len(pending[cls[a]]) >= max_pending:
                 res[a]["status"] = swx.SWX_EBUSY
             else:
                 pending[cls[a]].append(a)
