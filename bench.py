@@ -423,7 +423,10 @@ def main():
                      "frac": round(achieved / PEAK_PK16_TOPS, 4),
                      "traffic": recorded_traffic(b.npairs),
                      "kernel": "k_inter_fill (forward fill, packed 16-bit lanes)",
-                     "fill_ms": round(fill_avg, 3), "ops_per_cell": OPS_PER_CELL},
+                     "fill_ms": round(fill_avg, 3), "ops_per_cell": OPS_PER_CELL,
+                     # the whole path (fill, saturation re-run, reverse, traceback,
+                     # score2) against the same roofline: GCUPS x 10 ops / peak
+                     "path_frac": round(value * OPS_PER_CELL / 1e3 / PEAK_PK16_TOPS, 4)},
         "stages_ms": stage_avg,
         "tuning": tuning,
         "modes": modes,
