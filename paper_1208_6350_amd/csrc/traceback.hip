@@ -205,36 +205,40 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
   // they land straight in their registers; values outside the pair are
   // masked when decoded.
   constexpr int UB = BW <= 16 ? 8 : (BW <= 32 ? 4 : 2);
-  auto load_block = [&](int64_t i0, int32_t (&qo)[UB], int32_t (&no)[UB]) {
+  // row and column arithmetic in 32 bits (pairs of this path are far
+  // shorter than 2^31), so that clamps are single instructions
+  const int32_t mq32 = (int32_t)mq, wr32 = (int32_t)wr, dlo32 = (int32_t)dlo;
+  const int32_t m32 = (int32_t)m, w32 = (int32_t)w, rows32 = (int32_t)tk.rows;
+  auto load_block = [&](int32_t i0, int32_t (&qo)[UB], int32_t (&no)[UB]) {
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
-      int64_t x = i0 + u - 1;                       // query index of row i0 + u
-      x = x < 0 ? 0 : (x > mq - 1 ? mq - 1 : x);
+      int32_t x = i0 + u - 1;                       // query index of row i0 + u
+      x = x < 0 ? 0 : (x > mq32 - 1 ? mq32 - 1 : x);
       qo[u] = qq[x];
-      int64_t y = i0 + u + dlo + 4 * NW - 1;   // reference index of the window's new column
-      y = y < 0 ? 0 : (y > wr - 1 ? wr - 1 : y);
+      int32_t y = i0 + u + dlo32 + 4 * NW - 1;   // reference index of the window's new column
+      y = y < 0 ? 0 : (y > wr32 - 1 ? wr32 - 1 : y);
       no[u] = rr[y];
     }
   };
   int32_t qraw[UB], nraw[UB];
   load_block(1, qraw, nraw);
-  for (int64_t i0 = 1; i0 <= tk.rows; i0 += UB) {
+  for (int32_t i0 = 1; i0 <= rows32; i0 += UB) {
     uint32_t qb[UB], nbb[UB];
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
-      const int64_t i = i0 + u;
-      const int32_t c = (live && i <= m) ? qraw[u] : -1;
+      const int32_t i = i0 + u;
+      const int32_t c = (live && i <= m32) ? qraw[u] : -1;
       qb[u] = (c >= 0 && c < a.n) ? (uint32_t)c : 0xFFu;
-      const int64_t j = i + 1 + dlo + 4 * NW - 1;   // 1-based column entering the window
-      const int32_t cr = (live && j >= 1 && j <= w) ? nraw[u] : 0;
+      const int32_t j = i + 1 + dlo32 + 4 * NW - 1;   // 1-based column entering the window
+      const int32_t cr = (live && j >= 1 && j <= w32) ? nraw[u] : 0;
       const uint32_t v = (cr >= 0 && cr < a.n) ? (uint32_t)cr : 0u;   // a bad code never indexes a table
       nbb[u] = LUT4 ? v * 8u : v;
     }
     load_block(i0 + UB, qraw, nraw);
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
-      const int64_t i = i0 + u;
-      if (i > tk.rows) break;
+      const int32_t i = i0 + u;
+      if (i > rows32) break;
       int32_t lut = 0, qrow = 0;
       if (qb[u] != 0xFFu) {
         if (LUT4) lut = (int32_t)s_lut4[qb[u]];
@@ -268,7 +272,7 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
       }
 #pragma unroll
       for (int d = 0; d < ND; ++d) dir[(i * ND + d) * 64 + lane] = dw[d];
-      if (live && i == m) {
+      if (live && i == m32) {
 #pragma unroll
         for (int k = 0; k < BW; ++k)
           if (k == kend) hend = H[k];
