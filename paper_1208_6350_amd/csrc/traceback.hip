@@ -296,14 +296,14 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
   // walk.  A lane whose runs outgrow its slots finishes on a plain walk.
   uint32_t *out = a.cig + a.cig_off[p];
   int32_t nruns = 0;
-  int64_t i = m, j = w;
+  int32_t i = m32, j = w32;   // 32-bit walk state
   int state = 0;
   uint32_t cur_op = 0xFF, cur_len = 0;
   bool walking = true, bad = false, full = false;
   uint32_t pend = 0;
   // (a masked OR rather than a select chain, which the compiler would turn
   // into an indexed load from a private copy of the ring)
-  auto code_at = [&](const uint32_t (&rc)[ND], int64_t k) -> uint32_t {
+  auto code_at = [&](const uint32_t (&rc)[ND], int32_t k) -> uint32_t {
     const uint32_t idx = (uint32_t)(k >> 3);
     uint32_t word = 0;
 #pragma unroll
@@ -335,20 +335,20 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
   uint32_t ring[kWP][ND];
   // rows above row 0 are never walked: their slots load row 0, so that every
   // load lands straight in its ring registers
-  auto load_row = [&](int64_t row, uint32_t (&dst)[ND]) {
-    const int64_t rr = row >= 0 ? row : 0;
+  auto load_row = [&](int32_t row, uint32_t (&dst)[ND]) {
+    const int32_t rr = row >= 0 ? row : 0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) dst[d] = dir[(rr * ND + d) * 64 + lane];
   };
 #pragma unroll
   for (int u = 0; u < kWP; ++u) load_row(m - u, ring[u]);
-  for (int64_t t0 = 0; t0 <= m && walking; t0 += kWP) {
+  for (int32_t t0 = 0; t0 <= m32 && walking; t0 += kWP) {
 #pragma unroll
     for (int u = 0; u < kWP; ++u) {   // no early exit: every step issues the same loads
-      const int64_t row = m - (t0 + u);
+      const int32_t row = m32 - (t0 + u);
       // the moves inside this row: D moves, then one M or I out of it
       for (int g = 0; g < 2 * BW + 4 && row >= 0 && walking; ++g) {
-        const int64_t k = j - i - dlo;
+        const int32_t k = j - i - dlo32;
         if (k < 0 || k >= BW || i != row) { bad = true; walking = false; break; }
         bool up;
         const uint32_t op = move(code_at(ring[u], k), up);
@@ -382,9 +382,9 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
     out[nruns++] = pend;
     int64_t guard = 2 * (m + w) + 4;
     while ((i > 0 || j > 0) && guard-- > 0) {
-      const int64_t k = j - i - dlo;
+      const int32_t k = j - i - dlo32;
       if (k < 0 || k >= BW) { bad = true; break; }
-      const uint32_t word = dir[((int64_t)i * ND + (k >> 3)) * 64 + lane];
+      const uint32_t word = dir[(i * ND + (k >> 3)) * 64 + lane];
       bool up;
       const uint32_t op = move((word >> (4 * (k & 7))) & 0xFu, up);
       if (op != 0xFF) {
@@ -799,23 +799,33 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
   // that leaves a window sideways waits for a load.
   uint32_t *out = a.cig + a.cig_off[p];
   int32_t nruns = 0;
-  int64_t i = m, j = w;
+  // (32-bit walk state: a strip task spans well under 2^31 code dwords)
+  int32_t i = (int32_t)m, j = (int32_t)w;
   int state = 0;
   uint32_t cur_op = 0xFF, cur_len = 0;
   int64_t guard = 2 * (m + w) + 4;
   uint32_t *cache = s_walk + ((threadIdx.x >> 6) * 64 + slot * LP) * kCU;   // [g][kCU]
-  int64_t cache_s = -1, cache_j = -1;
+  int32_t cache_s = -1, cache_j = -1;
   uint32_t pfx[kCU];              // the strip above, in flight
-  int64_t pf_s = -1, pf_j = -1;
-  auto fetch_window = [&](int64_t s, int64_t jj, uint32_t (&dst)[kCU]) {
-    int64_t clo, chi;
-    strip_window(s, tk, &clo, &chi);
-    const int64_t mytop = (jj - clo + g) >> 1;
+  int32_t pf_s = -1, pf_j = -1;
+  const int32_t SW32 = (int32_t)SW, dlo32 = (int32_t)tk.dlo, width32 = (int32_t)tk.width;
+  const int32_t wmax32 = (int32_t)tk.wmax;
+  auto window32 = [&](int32_t s, int32_t &clo, int32_t &chi) {   // strip_window in 32 bits
+    const int32_t cstart = s * kStripR + 1 + dlo32;
+    clo = cstart > 0 ? cstart : 0;
+    int32_t hi = cstart + width32;
+    hi = hi > wmax32 + 1 ? wmax32 + 1 : hi;
+    chi = hi > clo ? hi : clo;
+  };
+  auto fetch_window = [&](int32_t s, int32_t jj, uint32_t (&dst)[kCU]) {
+    int32_t clo, chi;
+    window32(s, clo, chi);
+    const int32_t mytop = (jj - clo + g) >> 1;
 #pragma unroll
     for (int x = 0; x < kCU; ++x) {
-      int64_t uu = mytop - x;
-      uu = uu < 0 ? 0 : (uu > SW - 1 ? SW - 1 : uu);   // clamped: never read outside the strip
-      dst[x] = dir[(s * SW + uu) * 64 + slot * LP + g];
+      int32_t uu = mytop - x;
+      uu = uu < 0 ? 0 : (uu > SW32 - 1 ? SW32 - 1 : uu);   // clamped: never read outside the strip
+      dst[x] = dir[(s * SW32 + uu) * 64 + slot * LP + g];
     }
   };
   bool bad = false;
@@ -824,16 +834,16 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
     if (i == 0) {
       c = (j == 0) ? 0u : (1u | ((j == 1 || o <= e) ? 4u : 0u));
     } else {
-      const int64_t s = (i - 1) / kStripR, k = (i - 1) % kStripR;
-      const int64_t gk = k / RL;
-      int64_t clo, chi;
-      strip_window(s, tk, &clo, &chi);
+      const int32_t s = (i - 1) / kStripR, k = (i - 1) % kStripR;
+      const int32_t gk = k / RL;
+      int32_t clo, chi;
+      window32(s, clo, chi);
       if (j < clo || j >= chi) { bad = true; break; }
-      const int64_t t = j - clo + gk;
+      const int32_t t = j - clo + gk;
       // cached: dwords (cache_j - clo + g) / 2 - kCU + 1 .. (cache_j - clo + g) / 2 of row group g
-      const int64_t top = (cache_j - clo + gk) >> 1;
+      const int32_t top = (cache_j - clo + gk) >> 1;
       if (s != cache_s || (t >> 1) > top || (t >> 1) <= top - kCU) {
-        const int64_t ptop = (pf_j - clo + gk) >> 1;
+        const int32_t ptop = (pf_j - clo + gk) >> 1;
         const bool use_pf = s == pf_s && (t >> 1) <= ptop && (t >> 1) > ptop - kCU;
         if (use_pf) {
 #pragma unroll
@@ -853,7 +863,7 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
         }
         cache_s = s;
       }
-      const int64_t top2 = (cache_j - clo + gk) >> 1;
+      const int32_t top2 = (cache_j - clo + gk) >> 1;
       const uint32_t dwv = cache[gk * kCU + (top2 - (t >> 1))];
       c = (dwv >> (16 * (t & 1) + 4 * (k % RL))) & 0xFu;
     }
