@@ -264,8 +264,13 @@ int swx_graph_run(swx_graph *g);
 int swx_graph_run_eager(swx_graph *g);
 /* Copies a host-memory batch into the graph's input buffers, padding pair
  * slots past npairs with (query 0, reference nr), an empty reference: needs
- * npairs <= max_pairs, nq <= nq_cap, nr + 1 <= nr_cap and the code arrays
- * within their capacities (SWX_EINVAL otherwise). */
+ * npairs <= max_pairs, nq <= nq_cap, nr + 1 <= nr_cap, the code arrays
+ * within their capacities, offsets non-decreasing within the code arrays,
+ * pair indices in range and every pair within max_qlen and max_rlen
+ * (SWX_EINVAL otherwise, checked on the host before any copy).  Symbol codes
+ * are checked by swx_graph_run.  Contents written straight into the device
+ * buffers (swx_graph_io) are not checked beforehand: the run clamps every
+ * index and length into the buffers and reports the violation afterwards. */
 int swx_graph_load(swx_graph *g, const swx_batch *b);
 /* Copies the records of the first npairs pairs, and the CIGAR words they
  * refer to, from the graph's output buffers to host memory (SWX_ERANGE when

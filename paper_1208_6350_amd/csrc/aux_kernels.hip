@@ -15,16 +15,26 @@
 namespace swx {
 
 // ---- pair views -----------------------------------------------------------
+// Views of the pairs.  Every index and range is clamped into the arrays
+// (pair indices into [0, nq) and [0, nr), a sequence into its code array, its
+// length to the caps): input that the validation kernel flags still drives
+// every later kernel inside its buffers, where a caller's device buffers
+// (the graph's) are checked only by that kernel, in the same launch order.
 __global__ void k_views(int64_t npairs, const int64_t *qoff, const int64_t *roff,
-                        const int64_t *pair_q, const int64_t *pair_r,
+                        const int64_t *pair_q, const int64_t *pair_r, ViewCaps caps,
                         int64_t *qstart, int32_t *qlen, int64_t *rstart, int64_t *rlen) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npairs) return;
-  const int64_t qi = pair_q[p], ri = pair_r[p];
-  qstart[p] = qoff[qi];
-  qlen[p] = (int32_t)(qoff[qi + 1] - qoff[qi]);
-  rstart[p] = roff[ri];
-  rlen[p] = roff[ri + 1] - roff[ri];
+  auto clamp = [](int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); };
+  const int64_t qi = clamp(pair_q[p], 0, caps.nq - 1), ri = clamp(pair_r[p], 0, caps.nr - 1);
+  const int64_t q0 = clamp(qoff[qi], 0, caps.qcat_len);
+  const int64_t q1 = clamp(qoff[qi + 1], q0, caps.qcat_len);
+  const int64_t r0 = clamp(roff[ri], 0, caps.rcat_len);
+  const int64_t r1 = clamp(roff[ri + 1], r0, caps.rcat_len);
+  qstart[p] = q0;
+  qlen[p] = (int32_t)(q1 - q0 < caps.max_qlen ? q1 - q0 : caps.max_qlen);
+  rstart[p] = r0;
+  rlen[p] = r1 - r0 < caps.max_rlen ? r1 - r0 : caps.max_rlen;
 }
 
 // Reversed prefixes q[0..qend] and r[0..rend] (read backwards by the fill).
@@ -526,11 +536,13 @@ hipError_t launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, voi
 }
 
 hipError_t launch_views(int64_t npairs, const int64_t *qoff, const int64_t *roff,
-                        const int64_t *pair_q, const int64_t *pair_r, int64_t *qstart,
-                        int32_t *qlen, int64_t *rstart, int64_t *rlen, hipStream_t st) {
+                        const int64_t *pair_q, const int64_t *pair_r, const ViewCaps &caps,
+                        int64_t *qstart, int32_t *qlen, int64_t *rstart, int64_t *rlen,
+                        hipStream_t st) {
   if (!npairs) return hipSuccess;
+  if (caps.nq < 1 || caps.nr < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_views, dim3(blocks_for(npairs, 256)), dim3(256), 0, st, npairs, qoff, roff,
-                     pair_q, pair_r, qstart, qlen, rstart, rlen);
+                     pair_q, pair_r, caps, qstart, qlen, rstart, rlen);
   return hipGetLastError();
 }
 

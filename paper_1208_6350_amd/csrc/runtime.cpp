@@ -875,7 +875,11 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
     return fail(SWX_ENOMEM, "device pool exhausted (pair arrays)");
   HIP_TRY(hipMemsetAsync(err, 0, np, st));
   HIP_TRY(hipMemsetAsync(lanebits, 16, np, st));
-  HIP_TRY(launch_views(np, b.qoff, b.roff, b.pair_q, b.pair_r, qstart, qlen, rstart, rlen, st));
+  {
+    const ViewCaps vc{b.nq, b.nr, b.qcat_len, b.rcat_len, INT32_MAX, 0, INT64_MAX};
+    HIP_TRY(launch_views(np, b.qoff, b.roff, b.pair_q, b.pair_r, vc, qstart, qlen, rstart, rlen,
+                         st));
+  }
   // a score can reach smax * min(qlen, rlen); the 32-bit lanes hold < 2^26
   HIP_TRY(hipMemsetAsync(stats, 0, 8 * 4, st));
   HIP_TRY(launch_pair_stats(np, qlen, rlen, stats, st));
@@ -1288,7 +1292,12 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
   ValidateArgs va{g.qcat, g.cfg.qcat_cap, g.qoff, g.cfg.nq_cap, g.rcat, g.cfg.rcat_cap, g.roff,
                   g.cfg.nr_cap, g.pair_q, g.pair_r, B, g.sc.n, g.bad};
   HIP_TRY(launch_validate(va, st));
-  HIP_TRY(launch_views(B, g.qoff, g.roff, g.pair_q, g.pair_r, g.qstart, g.qlen, g.rstart, g.rlen, st));
+  {
+    const ViewCaps vc{g.cfg.nq_cap, g.cfg.nr_cap, g.cfg.qcat_cap, g.cfg.rcat_cap,
+                      (int32_t)g.QM, 0, g.RM};
+    HIP_TRY(launch_views(B, g.qoff, g.roff, g.pair_q, g.pair_r, vc, g.qstart, g.qlen, g.rstart,
+                         g.rlen, st));
+  }
   PairView fview{g.qstart, g.rstart, g.qlen, g.rlen, g.qcat, g.rcat, 0};
   FillOut fout{g.score, g.qend, g.rend, g.ovf};
   IntraArgs ia{};
@@ -1957,6 +1966,21 @@ int swx_graph_load(swx_graph *gr, const swx_batch *b) {
       (b->npairs && (!b->pair_q || !b->pair_r)) || (b->qcat_len && !b->qcat) ||
       (b->rcat_len && !b->rcat))
     return fail(SWX_EINVAL, "batch does not fit the graph's capacities");
+  // the host holds the whole batch here: offsets, pair indices and lengths
+  // are checked before anything reaches the device
+  for (int64_t k = 0; k < b->nq; ++k)
+    if (b->qoff[k] < 0 || b->qoff[k] > b->qoff[k + 1] || b->qoff[k + 1] > b->qcat_len)
+      return fail(SWX_EINVAL, "offsets must be non-decreasing and within the code arrays");
+  for (int64_t k = 0; k < b->nr; ++k)
+    if (b->roff[k] < 0 || b->roff[k] > b->roff[k + 1] || b->roff[k + 1] > b->rcat_len)
+      return fail(SWX_EINVAL, "offsets must be non-decreasing and within the code arrays");
+  for (int64_t k = 0; k < b->npairs; ++k) {
+    const int64_t qi = b->pair_q[k], ri = b->pair_r[k];
+    if (qi < 0 || qi >= b->nq || ri < 0 || ri >= b->nr)
+      return fail(SWX_EINVAL, "pair index out of range");
+    if (b->qoff[qi + 1] - b->qoff[qi] > g.QM || b->roff[ri + 1] - b->roff[ri] > g.RM)
+      return fail(SWX_EINVAL, "a pair exceeds the graph's length capacities");
+  }
   // offsets padded with their last value; pair slots past npairs take the
   // empty reference nr (roff[nr] == roff[nr + 1])
   std::vector<int64_t> qo(g.cfg.nq_cap + 1), ro(g.cfg.nr_cap + 1), pq(g.B, 0), pr(g.B, b->nr);

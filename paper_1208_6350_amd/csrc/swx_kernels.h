@@ -253,9 +253,16 @@ hipError_t mark_lanes(int64_t n, const int64_t *ids, uint8_t *lanebits, int v, h
 hipError_t mark_lanes_dev(int64_t cap, const int64_t *n_dev, const int64_t *ids, uint8_t *lanebits,
                           int v, hipStream_t st);
 hipError_t launch_any_flag(int64_t n, const uint8_t *flag, int64_t *count, hipStream_t st);
+// bounds the views are clamped into (see k_views)
+struct ViewCaps {
+  int64_t nq, nr, qcat_len, rcat_len;
+  int32_t max_qlen, pad_;
+  int64_t max_rlen;
+};
 hipError_t launch_views(int64_t npairs, const int64_t *qoff, const int64_t *roff,
-                        const int64_t *pair_q, const int64_t *pair_r, int64_t *qstart,
-                        int32_t *qlen, int64_t *rstart, int64_t *rlen, hipStream_t st);
+                        const int64_t *pair_q, const int64_t *pair_r, const ViewCaps &caps,
+                        int64_t *qstart, int32_t *qlen, int64_t *rstart, int64_t *rlen,
+                        hipStream_t st);
 hipError_t launch_rev_views(int64_t npairs, const int64_t *qstart, const int64_t *rstart,
                             const int32_t *qlen, const int64_t *rlen,
                             const int32_t *score, const int32_t *qend, const int64_t *rend,

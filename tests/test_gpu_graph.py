@@ -132,6 +132,40 @@ def test_graph_long_queries_intra_route(ctx):
         g.close()
 
 
+def test_graph_load_checks_indices_offsets_and_lengths(ctx):
+    # the host rejects a batch whose indices, offsets or lengths would take a
+    # kernel outside the graph's buffers; a valid batch then runs as usual
+    a = W.random_pairs(906, 20, (3, 30), (3, 60))
+    g = _graph_for(ctx, a, max_pairs=32, max_qlen=40, max_rlen=80)
+    try:
+        cases = []
+        pq = a.pair_q.copy(); pq[5] = a.pair_q.max() + 100
+        cases.append((a.qoff, a.roff, pq, a.pair_r))
+        pr = a.pair_r.copy(); pr[7] = -1
+        cases.append((a.qoff, a.roff, a.pair_q, pr))
+        qo = a.qoff.copy(); qo[3], qo[4] = qo[4], qo[3]
+        if qo[3] != qo[4]:
+            cases.append((qo, a.roff, a.pair_q, a.pair_r))
+        ro = a.roff.copy(); ro[-1] = len(a.rcat) + 5
+        cases.append((a.qoff, ro, a.pair_q, a.pair_r))
+        for qoff, roff, pair_q, pair_r in cases:
+            with pytest.raises(swx.SwxError) as ei:
+                g.load(a.qcat, qoff, a.rcat, roff, pair_q, pair_r)
+            assert ei.value.status == -1
+        long_q = np.concatenate([a.qcat, np.zeros(50, dtype=np.int8)])
+        long_off = np.concatenate([a.qoff, [a.qoff[-1] + 50]]).astype(np.int64)
+        pq = a.pair_q.copy(); pq[0] = len(a.qoff) - 1   # a 50-symbol query: above max_qlen
+        with pytest.raises(swx.SwxError) as ei:
+            g.load(long_q, long_off, a.rcat, a.roff, pq, a.pair_r)
+        assert ei.value.status == -1
+        g.load(a.qcat, a.qoff, a.rcat, a.roff, a.pair_q, a.pair_r)
+        g.run()
+        recs, cig = g.read()
+        _check_oracle(a, recs, cig)
+    finally:
+        g.close()
+
+
 def test_graph_rejects_bad_contents(ctx):
     a = W.random_pairs(905, 20, (3, 30), (3, 60))
     g = _graph_for(ctx, a, max_pairs=32, max_qlen=40, max_rlen=80)
