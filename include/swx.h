@@ -270,7 +270,10 @@ int swx_graph_run_eager(swx_graph *g);
  * (SWX_EINVAL otherwise, checked on the host before any copy).  Symbol codes
  * are checked by swx_graph_run.  Contents written straight into the device
  * buffers (swx_graph_io) are not checked beforehand: the run clamps every
- * index and length into the buffers and reports the violation afterwards. */
+ * index, offset and length into the buffers and capacities (so no kernel
+ * leaves them), reports bad offsets, indices and codes afterwards as
+ * SWX_EINVAL, and aligns a pair longer than the capacities truncated to
+ * them (the caller's error, not reported). */
 int swx_graph_load(swx_graph *g, const swx_batch *b);
 /* Copies the records of the first npairs pairs, and the CIGAR words they
  * refer to, from the graph's output buffers to host memory (SWX_ERANGE when
