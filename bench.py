@@ -391,6 +391,9 @@ def main():
     per_pair = None
     if args.per_pair_sample > 0 and not args.headline_only:
         pp = b.subset(np.arange(min(args.per_pair_sample, b.npairs)))
+        # one untimed pass: the first call of each size class captures its graph
+        for p in range(pp.npairs):
+            ctx.align_pair(pp.query(p), pp.ref(p), pp.matrix, pp.gap_open, pp.gap_extend)
         t = time.perf_counter()
         for p in range(pp.npairs):
             ctx.align_pair(pp.query(p), pp.ref(p), pp.matrix, pp.gap_open, pp.gap_extend)

@@ -124,7 +124,12 @@ int swx_profile_destroy(swx_profile *p);
  * ref: [rlen] codes in host memory, or device memory when flags has
  * SWX_REF_DEVICE.  rlen == 0 is valid and yields "no alignment".  Synchronous:
  * returns when out is filled.  out->cigar is malloc'd by the library (NULL when
- * the CIGAR was not requested or is empty). */
+ * the CIGAR was not requested or is empty).  A pair of qlen <= 4096 and
+ * rlen <= 65536 replays a graph of capacity one pair (the chain of
+ * swx_graph_*, one pair spread over a wave) captured on first use for its
+ * scoring scheme, flags, mask width and power-of-two size class and kept on
+ * the context (at most 8, least recently used replaced); larger pairs take the
+ * batch path.  Either way the result equals swx_align_batch's. */
 #define SWX_REF_DEVICE (1u << 8)
 int swx_align(const swx_profile *p, const int8_t *ref, int64_t rlen, uint32_t flags,
               int32_t mask_len, swx_result *out);

@@ -113,6 +113,21 @@ struct swx_ctx {
   hipStream_t aux[kAux] = {};
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kAux] = {};
+  // one-pair calls (swx_align): captured graphs of capacity one pair, one per
+  // scoring scheme, flags and power-of-two size class, least recently used
+  // evicted; pair_mu serialises their use (taken before mu, never inside it)
+  struct PairGraph {
+    std::vector<int8_t> matrix;
+    int32_t n = 0, o = 0, e = 0, mask_len = 0;
+    uint32_t flags = 0;
+    int32_t qcap = 0;
+    int64_t rcap = 0;
+    swx_graph *g = nullptr;
+    uint64_t last_use = 0;
+  };
+  std::mutex pair_mu;
+  std::vector<PairGraph> pair_graphs;
+  uint64_t pair_clock = 0;
 };
 
 struct swx_profile {
@@ -1643,6 +1658,11 @@ int swx_ctx_create(int device, swx_ctx **out) {
 int swx_ctx_destroy(swx_ctx *ctx) {
   if (!ctx) return fail(SWX_EINVAL, "ctx is null");
   {
+    std::lock_guard<std::mutex> lk(ctx->pair_mu);
+    for (auto &pg : ctx->pair_graphs) swx_graph_destroy(pg.g);
+    ctx->pair_graphs.clear();
+  }
+  {
     std::lock_guard<std::mutex> g(ctx->mu);
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
@@ -1800,13 +1820,67 @@ int swx_align_batch(swx_ctx *ctx, const swx_batch *b, swx_batch_out *out) {
   return align_batch_locked(ctx, b, out);
 }
 
+// The one-pair call through a cached graph (intra route: the pair spread over
+// a wave).  Returns 1 when no graph serves the pair (too large, or one could
+// not be made): the caller then takes the batch path.
+static constexpr int32_t kPairGraphMaxQ = 4096;
+static constexpr int64_t kPairGraphMaxR = int64_t(1) << 16;
+static constexpr size_t kPairGraphs = 8;
+
+static int align_pair_graph(const swx_profile *p, int64_t rlen, uint32_t flags,
+                            int32_t mask_len, const swx_batch &b, swx_rec &rec,
+                            std::vector<uint32_t> &cig) {
+  swx_ctx *ctx = p->ctx;
+  const int64_t ql = (int64_t)p->query.size();
+  if (ql > kPairGraphMaxQ || rlen > kPairGraphMaxR) return 1;
+  int32_t qcap = 64;
+  while (qcap < ql) qcap *= 2;
+  int64_t rcap = 256;
+  while (rcap < rlen) rcap *= 2;
+  std::lock_guard<std::mutex> lk(ctx->pair_mu);
+  swx_ctx::PairGraph *hit = nullptr;
+  for (auto &pg : ctx->pair_graphs)
+    if (pg.n == p->n && pg.o == p->o && pg.e == p->e && pg.flags == flags &&
+        pg.mask_len == mask_len && pg.qcap == qcap && pg.rcap == rcap && pg.matrix == p->matrix) {
+      hit = &pg;
+      break;
+    }
+  if (!hit) {
+    if (ctx->pair_graphs.size() >= kPairGraphs) {   // evict the least recently used
+      size_t old = 0;
+      for (size_t k = 1; k < ctx->pair_graphs.size(); ++k)
+        if (ctx->pair_graphs[k].last_use < ctx->pair_graphs[old].last_use) old = k;
+      swx_graph_destroy(ctx->pair_graphs[old].g);
+      ctx->pair_graphs.erase(ctx->pair_graphs.begin() + (std::ptrdiff_t)old);
+    }
+    swx_graph_cfg cfg{};
+    cfg.matrix = p->matrix.data(); cfg.n = p->n; cfg.gap_open = p->o; cfg.gap_extend = p->e;
+    cfg.max_pairs = 1; cfg.max_qlen = qcap; cfg.max_rlen = rcap;
+    cfg.qcat_cap = qcap; cfg.rcat_cap = rcap; cfg.nq_cap = 1; cfg.nr_cap = 2;
+    cfg.flags = flags; cfg.mask_len = mask_len; cfg.route = SWX_ROUTE_INTRA;
+    swx_graph *gr = nullptr;
+    swx_graph_io io{};
+    if (swx_graph_create(ctx, &cfg, &gr, &io) != SWX_OK) return 1;
+    swx_ctx::PairGraph pg;
+    pg.matrix = p->matrix; pg.n = p->n; pg.o = p->o; pg.e = p->e;
+    pg.flags = flags; pg.mask_len = mask_len; pg.qcap = qcap; pg.rcap = rcap; pg.g = gr;
+    ctx->pair_graphs.push_back(std::move(pg));
+    hit = &ctx->pair_graphs.back();
+  }
+  hit->last_use = ++ctx->pair_clock;
+  int rc = swx_graph_load(hit->g, &b);
+  if (rc == SWX_OK) rc = swx_graph_run(hit->g);
+  if (rc != SWX_OK) return rc;
+  swx_batch_out bo{&rec, cig.data(), (int64_t)cig.size(), 0, SWX_MEM_HOST};
+  return swx_graph_read(hit->g, 1, &bo);
+}
+
 int swx_align(const swx_profile *p, const int8_t *ref, int64_t rlen, uint32_t flags,
               int32_t mask_len, swx_result *out) {
   if (!p || !out || (rlen > 0 && !ref)) return fail(SWX_EINVAL, "null argument");
   if (rlen < 0) return fail(SWX_EINVAL, "rlen must be >= 0");
   if (flags & ~(SWX_ALL | SWX_REF_DEVICE)) return fail(SWX_EINVAL, "unknown flag bits");
   swx_ctx *ctx = p->ctx;
-  std::lock_guard<std::mutex> g(ctx->mu);
   memset(out, 0, sizeof(*out));
   std::vector<int8_t> href;
   const int8_t *rptr = ref;
@@ -1816,6 +1890,33 @@ int swx_align(const swx_profile *p, const int8_t *ref, int64_t rlen, uint32_t fl
       return fail(SWX_EDEVICE, "could not read the device reference");
     rptr = href.data();
   }
+  {
+    const int64_t qoff[2] = {0, (int64_t)p->query.size()};
+    const int64_t roff[2] = {0, rlen};
+    const int64_t pq = 0, pr = 0;
+    swx_batch b{};
+    b.matrix = p->matrix.data(); b.n = p->n; b.gap_open = p->o; b.gap_extend = p->e;
+    b.qcat = p->query.data(); b.qcat_len = (int64_t)p->query.size(); b.qoff = qoff; b.nq = 1;
+    b.rcat = rptr; b.rcat_len = rlen; b.roff = roff; b.nr = 1;
+    b.pair_q = &pq; b.pair_r = &pr; b.npairs = 1;
+    b.flags = flags & SWX_ALL; b.mask_len = mask_len; b.in_mem = SWX_MEM_HOST;
+    swx_rec rec{};
+    std::vector<uint32_t> cig((size_t)(p->query.size() + rlen + 2));
+    const int rc = align_pair_graph(p, rlen, flags & SWX_ALL, mask_len, b, rec, cig);
+    if (rc < 0) return rc;
+    if (rc == SWX_OK) {
+      out->rec = rec;
+      out->cigar = nullptr;
+      if (rec.cigar_len > 0) {
+        out->cigar = (uint32_t *)malloc(sizeof(uint32_t) * rec.cigar_len);
+        if (!out->cigar) return fail(SWX_ENOMEM, "host allocation failed");
+        memcpy(out->cigar, cig.data() + rec.cigar_off, sizeof(uint32_t) * rec.cigar_len);
+      }
+      out->rec.cigar_off = 0;
+      return SWX_OK;
+    }
+  }
+  std::lock_guard<std::mutex> g(ctx->mu);
   const int64_t qoff[2] = {0, (int64_t)p->query.size()};
   const int64_t roff[2] = {0, rlen};
   const int64_t pq = 0, pr = 0;

@@ -192,6 +192,38 @@ def test_batch_equals_single(ctx):
                                           recs["cigar_len"][p]])
 
 
+def test_single_pair_calls_equal_batch(ctx):
+    """The one-pair entry point (captured graphs per size class, reused across
+    calls; the batch path beyond them): edge shapes, protein, every flag set
+    and mask width, and a bad symbol, each equal to the batch result."""
+    g = np.random.Generator(np.random.PCG64(44))
+    qs = [np.array([1], np.int8), np.array([0, 1, 2, 3] * 20, np.int8),
+          g.integers(0, 4, 300).astype(np.int8), g.integers(0, 4, 70).astype(np.int8)]
+    rs = [np.array([1, 2, 1], np.int8), np.zeros(0, np.int8),
+          g.integers(0, 4, 1500).astype(np.int8), g.integers(0, 4, 5000).astype(np.int8)]
+    dna = W.from_lists("single-dna", W.dna_matrix(), 3, 1, qs, rs)
+    prot = W.random_pairs(515, 6, (20, 200), (50, 700), alphabet=24,
+                          matrix=W.protein_matrix_standin(), o=11, e=1)
+    for b in (dna, prot):
+        for flags, mask in ((swx.SWX_ALL, -1), (0, -1), (swx.SWX_BEGIN, -1),
+                            (swx.SWX_SCORE2 | swx.SWX_BEGIN, 7)):
+            recs, cig = ctx.align_batch(b.matrix, b.gap_open, b.gap_extend, b.qcat, b.qoff,
+                                        b.rcat, b.roff, b.pair_q, b.pair_r, flags, mask)
+            for p in range(b.npairs):
+                for rep in range(2):   # the second call replays the cached graph
+                    rec, c1 = ctx.align_pair(b.query(p), b.ref(p), b.matrix, b.gap_open,
+                                             b.gap_extend, flags, mask)
+                    for f in FIELDS:
+                        assert rec[f] == recs[f][p], (b.name, flags, p, f)
+                    assert c1 == swx.decode_cigar(cig[recs["cigar_off"][p]:recs["cigar_off"][p] +
+                                                      recs["cigar_len"][p]])
+    bad = dna.ref(2).copy()
+    bad[10] = 7
+    with pytest.raises(swx.SwxError) as ei:
+        ctx.align_pair(dna.query(2), bad, dna.matrix, dna.gap_open, dna.gap_extend)
+    assert ei.value.status == -1
+
+
 def test_invalid_symbols_rejected(ctx):
     b = W.random_pairs(606, 5, (3, 10), (3, 10))
     b.rcat[2] = 9
