@@ -148,7 +148,7 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
     int64_t clo = 0, chi = rp;
     if (rev) {
       if (tk.band >= 0) {
-        clo = sR - tk.band; if (clo < 0) clo = 0;
+        clo = sR - tk.band_q; if (clo < 0) clo = 0;
         const int64_t c2 = (int64_t)sR + R + tk.band;
         if (c2 < chi) chi = c2;
       }

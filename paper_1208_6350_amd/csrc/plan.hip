@@ -58,7 +58,8 @@ __device__ __forceinline__ int64_t wave_max_i64(int64_t v) {
 __global__ void k_plan_tasks(int64_t n, const int64_t *n_dev, int64_t ntasks, int32_t slots,
                              int32_t R, int64_t qdata_per_row, const int64_t *sorted,
                              const int32_t *qlen, const int64_t *rlen, const int32_t *band,
-                             InterTask *tasks, int64_t *bnd_size, int64_t *qdata_size) {
+                             const int32_t *band_q, InterTask *tasks, int64_t *bnd_size,
+                             int64_t *qdata_size) {
   const int lane = threadIdx.x & 63;
   const int64_t t = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (t >= ntasks) return;
@@ -66,7 +67,8 @@ __global__ void k_plan_tasks(int64_t n, const int64_t *n_dev, int64_t ntasks, in
   const int64_t s0 = t * slots;
   int64_t s1 = (s0 + slots < n) ? s0 + slots : n;
   if (s1 < s0) s1 = s0;   // a task past the valid ids is empty
-  int64_t mq = 1, mr = 1, mb = 0;   // mb: a negative band (none) counts as the largest
+  // mb, mbq: a negative band (none) counts as the largest
+  int64_t mq = 1, mr = 1, mb = 0, mbq = 0;
   for (int64_t k = s0 + lane; k < s1; k += 64) {
     const int64_t p = sorted[k];
     if (qlen[p] > mq) mq = qlen[p];
@@ -74,11 +76,14 @@ __global__ void k_plan_tasks(int64_t n, const int64_t *n_dev, int64_t ntasks, in
     if (band) {
       const int64_t b = band[p] < 0 ? INT64_MAX : band[p];
       mb = b > mb ? b : mb;
+      const int64_t bq = band_q ? (band_q[p] < 0 ? INT64_MAX : band_q[p]) : b;
+      mbq = bq > mbq ? bq : mbq;
     }
   }
   mq = wave_max_i64(mq);
   mr = wave_max_i64(mr);
   mb = wave_max_i64(mb);
+  mbq = wave_max_i64(mbq);
   if (lane != 0) return;
   InterTask tk{};
   tk.nslots = (int32_t)(s1 - s0);
@@ -88,6 +93,7 @@ __global__ void k_plan_tasks(int64_t n, const int64_t *n_dev, int64_t ntasks, in
   tk.qp = (int32_t)((mq + unit - 1) / unit * unit);
   tk.rp = (int32_t)((mr + 7) / 8 * 8);
   tk.band = band ? (mb == INT64_MAX ? -1 : (int32_t)mb) : -1;
+  tk.band_q = (band && mbq != INT64_MAX && tk.band >= 0) ? (int32_t)mbq : tk.band;
   tk.slot_base = s0;
   tasks[t] = tk;
   bnd_size[t] = 3 * (int64_t)tk.rp * 64;
@@ -125,29 +131,48 @@ __global__ void k_count_classes(int64_t n, const uint8_t *cls, int64_t *counts) 
                                                    (unsigned long long)c[threadIdx.x]);
 }
 
-// reversed pass setup: band G' per pair and the lane width it runs at.
-// Every alignment of score score1 that ends at the end cell stays within
-// G' = (smax*min(qend+1, rend+1) - o + e - score1) / e diagonals of the
-// reversed start (e > 0); with e == 0 no band is used.
+// reversed pass setup: drift band per pair and the lane width it runs at.
+// Every alignment of score score1 in the reversed region starts at the
+// reversed corner (T1 leaves no other cell of that value there).  A path
+// that drifts d diagonals off the corner's diagonal holds at least d gap
+// symbols, so score1 <= smax*min(qend+1, rend+1) - o - (d-1)e: d <= G'.
+// When the drift is towards the query (i - j = d) those d symbols are
+// insertions, which also leave at most qend+1-d rows for matches:
+// score1 <= smax*(qend+1-d) - o - (d-1)e, so d <= Gq =
+// (smax*(qend+1) - o + e - score1) / (smax + e); towards the reference
+// likewise with rend+1 (Gr).  band = max(min(G', Gq), min(G', Gr)) bounds
+// both sides, band_q = min(G', Gq) the query side (e > 0; with e == 0 no band
+// is used).
+__device__ __forceinline__ int64_t rev_drift(int64_t num, int64_t den) {
+  const int64_t g = num / den;
+  return g < 0 ? 0 : (g > (1 << 30) ? (1 << 30) : g);
+}
+
 __global__ void k_rev_prepare(int64_t n, const int32_t *score, const int32_t *qend,
                               const int64_t *rend, const uint8_t *lanebits, int32_t smax,
-                              int32_t o, int32_t e, int32_t *band, uint8_t *f16, uint8_t *f32) {
+                              int32_t o, int32_t e, int32_t *band, int32_t *band_q, uint8_t *f16,
+                              uint8_t *f32) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const bool ok = score[p] > 0;
-  int32_t b = 0;
+  int32_t b = 0, bq = 0;
   if (ok) {
     if (e > 0) {
-      int64_t ml = (int64_t)qend[p] + 1;
-      if (rend[p] + 1 < ml) ml = rend[p] + 1;
-      int64_t g = ((int64_t)smax * ml - o + e - score[p]) / e;
-      if (g < 0) g = 0;
-      b = (int32_t)(g > (1 << 30) ? (1 << 30) : g);
+      const int64_t rows = (int64_t)qend[p] + 1, cols = rend[p] + 1;
+      const int64_t base = -(int64_t)o + e - score[p];
+      const int64_t g = rev_drift((int64_t)smax * (rows < cols ? rows : cols) + base, e);
+      int64_t gq = rev_drift((int64_t)smax * rows + base, (int64_t)smax + e);
+      int64_t gr = rev_drift((int64_t)smax * cols + base, (int64_t)smax + e);
+      gq = gq < g ? gq : g;
+      gr = gr < g ? gr : g;
+      b = (int32_t)(gq > gr ? gq : gr);
+      bq = (int32_t)gq;
     } else {
-      b = -1;
+      b = bq = -1;
     }
   }
   band[p] = b;
+  band_q[p] = bq;
   f16[p] = (ok && lanebits[p] == 16) ? 1 : 0;
   f32[p] = (ok && lanebits[p] == 32) ? 1 : 0;
 }
@@ -174,10 +199,11 @@ hipError_t sort_keys(int64_t n, uint64_t *keys, uint64_t *keys_alt, int64_t *val
 
 hipError_t rev_prepare(int64_t npairs, const int32_t *score, const int32_t *qend,
                        const int64_t *rend, const uint8_t *lanebits, int32_t smax, int32_t o,
-                       int32_t e, int32_t *band, uint8_t *f16, uint8_t *f32, hipStream_t st) {
+                       int32_t e, int32_t *band, int32_t *band_q, uint8_t *f16, uint8_t *f32,
+                       hipStream_t st) {
   if (!npairs) return hipSuccess;
   hipLaunchKernelGGL(k_rev_prepare, dim3(nb(npairs, 256)), dim3(256), 0, st, npairs, score, qend,
-                     rend, lanebits, smax, o, e, band, f16, f32);
+                     rend, lanebits, smax, o, e, band, band_q, f16, f32);
   return hipGetLastError();
 }
 
@@ -211,11 +237,12 @@ hipError_t plan_sort(int64_t n, const int64_t *n_dev, const int64_t *ids, const 
 
 hipError_t plan_tasks_dev(int64_t n, const int64_t *n_dev, int64_t ntasks, int32_t slots, int32_t R,
                           int64_t qdata_per_row, const int64_t *sorted, const int32_t *qlen,
-                          const int64_t *rlen, const int32_t *band, InterTask *tasks,
-                          int64_t *bnd_size, int64_t *qdata_size, hipStream_t st) {
+                          const int64_t *rlen, const int32_t *band, const int32_t *band_q,
+                          InterTask *tasks, int64_t *bnd_size, int64_t *qdata_size,
+                          hipStream_t st) {
   if (ntasks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_plan_tasks, dim3(nb(ntasks, 4)), dim3(256), 0, st, n, n_dev, ntasks,
-                     slots, R, qdata_per_row, sorted, qlen, rlen, band, tasks, bnd_size,
+                     slots, R, qdata_per_row, sorted, qlen, rlen, band, band_q, tasks, bnd_size,
                      qdata_size);
   return hipGetLastError();
 }

@@ -194,8 +194,8 @@ static T *alloc_or_null(DevArena &A, int64_t n) { return A.get<T>(n); }
 // Sort the pass's pairs by (band, padded query height, reference length) on
 // the device, cut them into tasks, derive buffer offsets and allocate.
 static int plan_pass(swx_ctx *ctx, const Scoring &sc, const int64_t *ids, int64_t n,
-                     const int32_t *qlen, const int64_t *rlen, const int32_t *band, int lane_bits,
-                     int R, Plan &pl) {
+                     const int32_t *qlen, const int64_t *rlen, const int32_t *band,
+                     const int32_t *band_q, int lane_bits, int R, Plan &pl) {
   DevArena &A = ctx->arena;
   hipStream_t st = ctx->stream;
   pl = Plan{};
@@ -222,7 +222,7 @@ static int plan_pass(swx_ctx *ctx, const Scoring &sc, const int64_t *ids, int64_
   HIP_TRY(hipMemsetAsync(bsz + pl.ntasks, 0, 8, st));
   HIP_TRY(hipMemsetAsync(qsz + pl.ntasks, 0, 8, st));
   HIP_TRY(plan_tasks_dev(n, nullptr, pl.ntasks, slots, R, per_row, pl.d_sorted, qlen, rlen, band,
-                         pl.d_tasks, bsz, qsz, st));
+                         band_q, pl.d_tasks, bsz, qsz, st));
   size_t t1 = 0, t2 = 0;
   HIP_TRY(launch_exclusive_scan(bsz, boff, pl.ntasks + 1, nullptr, &t1, st));
   void *s1 = A.alloc(t1);
@@ -914,7 +914,7 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
   // 24-row strips exist for the 4-symbol selector profile only
   const int R = (ctx->fill_rows == 24 && !sc.qsel) ? 32 : ctx->fill_rows;
   Plan p16, p32;
-  if ((rc = plan_pass(ctx, sc, lp.d_short, lp.nshort, qlen, rlen, nullptr, 16, R, p16))) return rc;
+  if ((rc = plan_pass(ctx, sc, lp.d_short, lp.nshort, qlen, rlen, nullptr, nullptr, 16, R, p16))) return rc;
   if ((rc = run_fill(ctx, p16, sc, fview, false, nullptr, fout, score_bound, 1))) return rc;
   if (lp.nlong > 0) {
     if ((rc = run_intra_forward(ctx, sc, lp, fview, fout, err))) return rc;
@@ -926,7 +926,7 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
   int64_t *wide = nullptr, nwide = 0;
   if ((rc = select_flagged(ctx, ovf, np, &wide, &nwide))) return rc;
   if (nwide > 0) {
-    if ((rc = plan_pass(ctx, sc, wide, nwide, qlen, rlen, nullptr, 32, R, p32))) return rc;
+    if ((rc = plan_pass(ctx, sc, wide, nwide, qlen, rlen, nullptr, nullptr, 32, R, p32))) return rc;
     if ((rc = run_fill(ctx, p32, sc, fview, false, nullptr, fout, score_bound))) return rc;
     HIP_TRY(mark_lanes(nwide, wide, lanebits, 32, st));
   }
@@ -936,14 +936,16 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
   if (flags & SWX_BEGIN) {
     int64_t *rqs = A.get<int64_t>(np), *rrs = A.get<int64_t>(np), *rrl = A.get<int64_t>(np);
     int32_t *rql = A.get<int32_t>(np), *tgt = A.get<int32_t>(np), *band = A.get<int32_t>(np);
-    int32_t *rsc = A.get<int32_t>(np), *rqe = A.get<int32_t>(np);
+    int32_t *band_q = A.get<int32_t>(np), *rsc = A.get<int32_t>(np), *rqe = A.get<int32_t>(np);
     int64_t *rre = A.get<int64_t>(np);
     uint8_t *rov = A.get<uint8_t>(np), *f16 = A.get<uint8_t>(np), *f32 = A.get<uint8_t>(np);
-    if (!rqs || !rrs || !rrl || !rql || !tgt || !band || !rsc || !rqe || !rre || !rov || !f16 || !f32)
+    if (!rqs || !rrs || !rrl || !rql || !tgt || !band || !band_q || !rsc || !rqe || !rre || !rov ||
+        !f16 || !f32)
       return fail(SWX_ENOMEM, "device pool exhausted (reverse)");
     HIP_TRY(launch_rev_views(np, qstart, rstart, qlen, rlen, score, qend, rend, rqs, rql, rrs,
                              rrl, tgt, err, st));
-    HIP_TRY(rev_prepare(np, score, qend, rend, lanebits, sc.smax, sc.o, sc.e, band, f16, f32, st));
+    HIP_TRY(rev_prepare(np, score, qend, rend, lanebits, sc.smax, sc.o, sc.e, band, band_q, f16,
+                        f32, st));
     if (lp.nlong > 0) HIP_TRY(clear_flags(lp.nlong, lp.d_long, f16, f32, st));
     HIP_TRY(hipMemsetAsync(rsc, 0, sizeof(int32_t) * np, st));
     PairView rview{rqs, rrs, rql, rrl, b.qcat, b.rcat, 1};
@@ -962,7 +964,7 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
     for (int k = 0; k < 2; ++k) {
       if (rcnt[k] == 0) continue;
       Plan pr;
-      if ((rc = plan_pass(ctx, sc, rids[k], rcnt[k], rql, rrl, band, k == 0 ? 16 : 32, R, pr)))
+      if ((rc = plan_pass(ctx, sc, rids[k], rcnt[k], rql, rrl, band, band_q, k == 0 ? 16 : 32, R, pr)))
         return rc;
       if ((rc = run_fill(ctx, pr, sc, rview, true, tgt, rout, score_bound))) return rc;
     }
@@ -1047,7 +1049,7 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
     if ((rc = select_flagged(ctx, sfl, np, &ids, &cnt))) return rc;
     if (cnt > 0) {
       Plan pw;
-      if ((rc = plan_pass(ctx, sc, ids, cnt, qlen, wrl, nullptr, 32, R, pw))) return rc;
+      if ((rc = plan_pass(ctx, sc, ids, cnt, qlen, wrl, nullptr, nullptr, 32, R, pw))) return rc;
       PairView wview{qstart, wrs, qlen, wrl, b.qcat, b.rcat, 0};
       FillOut wout{wsc, wqe, wre, wov};
       if ((rc = run_fill(ctx, pw, sc, wview, false, nullptr, wout, score_bound, -1, 0, 1)))
@@ -1059,7 +1061,7 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
     if ((rc = select_flagged(ctx, sfl, np, &ids, &cnt))) return rc;
     if (cnt > 0) {
       Plan pr;
-      if ((rc = plan_pass(ctx, sc, ids, cnt, rql, rrl, nullptr, 32, R, pr))) return rc;
+      if ((rc = plan_pass(ctx, sc, ids, cnt, rql, rrl, nullptr, nullptr, 32, R, pr))) return rc;
       PairView rview{rqs, rrs, rql, rrl, b.qcat, b.rcat, 1};
       FillOut rout{rsc, rqe, rre, rov};
       if ((rc = run_fill(ctx, pr, sc, rview, true, tgt, rout, score_bound + kAnchor, -1, kAnchor,
@@ -1172,7 +1174,7 @@ struct GraphState {
   int64_t cigar_cap = 0;
   // per pair
   int64_t *qstart, *rstart, *rlen, *rend, *rbeg, *rend2, *rqs, *rrs, *rrl, *rre;
-  int32_t *qlen, *score, *qend, *qbeg, *score2, *rql, *tgt, *band, *rsc, *rqe, *cig_len;
+  int32_t *qlen, *score, *qend, *qbeg, *score2, *rql, *tgt, *band, *band_q, *rsc, *rqe, *cig_len;
   uint8_t *ovf, *lanebits, *err, *rov, *f16, *f32, *cls;
   uint32_t *bad;
   int64_t *status;            // [0] pairs with an error flag
@@ -1246,8 +1248,8 @@ static int fixed_plan_alloc(GraphState &g, FixedPlan &pl, int lane_bits, int R) 
 // plan + fill of one pass over ids[0 .. *n_dev) (ids null: all B pairs)
 static int fixed_fill(GraphState &g, FixedPlan &pl, const int64_t *ids, const int64_t *n_dev,
                       const int32_t *qlen, const int64_t *rlen, const int32_t *band,
-                      const PairView &view, bool rev, const int32_t *target, FillOut out,
-                      hipStream_t st) {
+                      const int32_t *band_q, const PairView &view, bool rev,
+                      const int32_t *target, FillOut out, hipStream_t st) {
   size_t sb = pl.sort_bytes;
   HIP_TRY(plan_sort(pl.cap_n, n_dev, ids, qlen, rlen, band, pl.R, pl.k0, pl.k1, pl.v0, pl.v1,
                     pl.sort_tmp, &sb, &pl.sorted, st));
@@ -1256,7 +1258,7 @@ static int fixed_fill(GraphState &g, FixedPlan &pl, const int64_t *ids, const in
   HIP_TRY(fill_i64(1, pl.bsz + pl.ntasks, 0, st));
   HIP_TRY(fill_i64(1, pl.qsz + pl.ntasks, 0, st));
   HIP_TRY(plan_tasks_dev(pl.cap_n, n_dev, pl.ntasks, pl.slots, pl.R, per_row, pl.sorted, qlen, rlen,
-                         band, pl.tasks, pl.bsz, pl.qsz, st));
+                         band, band_q, pl.tasks, pl.bsz, pl.qsz, st));
   int rc;
   if ((rc = fixed_scan(g, pl.bsz, pl.boff, pl.ntasks + 1, st))) return rc;
   if ((rc = fixed_scan(g, pl.qsz, pl.qoff, pl.ntasks + 1, st))) return rc;
@@ -1329,15 +1331,15 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
     e.part_v = g.part_v; e.part_j = g.part_j;
     HIP_TRY(intra_end(e, B, st));
     HIP_TRY(fill_u8(B, g.lanebits, 32, st));
-  } else if ((rc = fixed_fill(g, g.p16, nullptr, nullptr, g.qlen, g.rlen, nullptr, fview, false,
+  } else if ((rc = fixed_fill(g, g.p16, nullptr, nullptr, g.qlen, g.rlen, nullptr, nullptr, fview, false,
                               nullptr, fout, st))) {
     return rc;
   }
   if (g.need32 && !g.intra) {
     const int64_t *nw = nullptr;
     if ((rc = fixed_select(g, g.ovf, &nw, st))) return rc;
-    if ((rc = fixed_fill(g, g.p32, g.ids, nw, g.qlen, g.rlen, nullptr, fview, false, nullptr, fout,
-                         st)))
+    if ((rc = fixed_fill(g, g.p32, g.ids, nw, g.qlen, g.rlen, nullptr, nullptr, fview, false, nullptr,
+                         fout, st)))
       return rc;
     HIP_TRY(mark_lanes_dev(B, nw, g.ids, g.lanebits, 32, st));
   }
@@ -1345,7 +1347,7 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
     HIP_TRY(launch_rev_views(B, g.qstart, g.rstart, g.qlen, g.rlen, g.score, g.qend, g.rend, g.rqs,
                              g.rql, g.rrs, g.rrl, g.tgt, g.err, st));
     HIP_TRY(rev_prepare(B, g.score, g.qend, g.rend, g.lanebits, g.sc.smax, g.sc.o, g.sc.e, g.band,
-                        g.f16, g.f32, st));
+                        g.band_q, g.f16, g.f32, st));
     HIP_TRY(fill_u8(4 * B, (uint8_t *)g.rsc, 0, st));
     PairView rview{g.rqs, g.rrs, g.rql, g.rrl, g.qcat, g.rcat, 1};
     FillOut rout{g.rsc, g.rqe, g.rre, g.rov};
@@ -1361,14 +1363,14 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
     }
     const int64_t *n16 = nullptr;
     if (!g.intra && (rc = fixed_select(g, g.f16, &n16, st))) return rc;
-    if (!g.intra && (rc = fixed_fill(g, g.r16, g.ids, n16, g.rql, g.rrl, g.band, rview, true,
-                                     g.tgt, rout, st)))
+    if (!g.intra && (rc = fixed_fill(g, g.r16, g.ids, n16, g.rql, g.rrl, g.band, g.band_q, rview,
+                                     true, g.tgt, rout, st)))
       return rc;
     if (g.need32 && !g.intra) {
       const int64_t *n32 = nullptr;
       if ((rc = fixed_select(g, g.f32, &n32, st))) return rc;
-      if ((rc = fixed_fill(g, g.r32, g.ids, n32, g.rql, g.rrl, g.band, rview, true, g.tgt, rout,
-                           st)))
+      if ((rc = fixed_fill(g, g.r32, g.ids, n32, g.rql, g.rrl, g.band, g.band_q, rview, true,
+                           g.tgt, rout, st)))
         return rc;
     }
     HIP_TRY(launch_begins(B, g.score, g.qend, g.rend, g.rsc, g.rqe, g.rre, g.qbeg, g.rbeg, g.err, st));
@@ -1463,14 +1465,16 @@ static int graph_alloc(GraphState &g) {
   g.cigar_cap = B * (g.QM + g.RM + 2);
   g.cigar = A.get<uint32_t>(g.cigar_cap);
   g.cscr = A.get<uint32_t>(g.cigar_cap);
+  bool per_pair = true;
   for (int64_t **p : {&g.qstart, &g.rstart, &g.rlen, &g.rend, &g.rbeg, &g.rend2, &g.rqs, &g.rrs,
                       &g.rrl, &g.rre, &g.tv0, &g.tv1})
-    *p = A.get<int64_t>(B);
+    per_pair = (*p = A.get<int64_t>(B)) != nullptr && per_pair;
   for (int32_t **p : {&g.qlen, &g.score, &g.qend, &g.qbeg, &g.score2, &g.rql, &g.tgt, &g.band,
-                      &g.rsc, &g.rqe, &g.cig_len})
-    *p = A.get<int32_t>(B);
+                      &g.band_q, &g.rsc, &g.rqe, &g.cig_len})
+    per_pair = (*p = A.get<int32_t>(B)) != nullptr && per_pair;
   for (uint8_t **p : {&g.ovf, &g.lanebits, &g.err, &g.rov, &g.f16, &g.f32, &g.cls})
-    *p = A.get<uint8_t>(B);
+    per_pair = (*p = A.get<uint8_t>(B)) != nullptr && per_pair;
+  if (!per_pair) return fail(SWX_ENOMEM, "device pool exhausted (graph)");
   g.bad = A.get<uint32_t>(1);
   g.status = A.get<int64_t>(1);
   g.f64 = A.get<int64_t>(B + 1);

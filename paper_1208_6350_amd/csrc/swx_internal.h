@@ -24,7 +24,10 @@ struct InterTask {
   int32_t qp;         // padded rows: a multiple of the strip height R, or (no
                       // query profile) of R / 2, the last strip then half high
   int32_t rp;         // padded columns (multiple of 8)
-  int32_t band;       // reversed pass: band half-width around the main diagonal (-1: none)
+  int32_t band;       // reversed pass: band half-width around the main diagonal (-1: none);
+                      // columns j <= i + band of row i
+  int32_t band_q;     // reversed pass: columns j >= i - band_q (-1: none; band_q <= band)
+  int32_t pad_;
   int64_t slot_base;  // slots are slot_pair[slot_base + s]
   int64_t bnd_off;    // boundary planes at bnd + bnd_off: 3 planes of rp*64 dwords;
                       // packed reference symbols at rsym + rsym_offset(bnd_off)

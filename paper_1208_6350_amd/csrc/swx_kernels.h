@@ -195,7 +195,8 @@ hipError_t sort_keys(int64_t n, uint64_t *keys, uint64_t *keys_alt, int64_t *val
                      hipStream_t st, int end_bit = 64);
 hipError_t rev_prepare(int64_t npairs, const int32_t *score, const int32_t *qend,
                        const int64_t *rend, const uint8_t *lanebits, int32_t smax, int32_t o,
-                       int32_t e, int32_t *band, uint8_t *f16, uint8_t *f32, hipStream_t st);
+                       int32_t e, int32_t *band, int32_t *band_q, uint8_t *f16, uint8_t *f32,
+                       hipStream_t st);
 
 hipError_t inter_fill(const InterArgs &a, int lane_bits, int R, hipStream_t st);
 
@@ -314,8 +315,9 @@ hipError_t plan_sort(int64_t n, const int64_t *n_dev, const int64_t *ids, const 
                      int64_t **sorted_out, hipStream_t st);
 hipError_t plan_tasks_dev(int64_t n, const int64_t *n_dev, int64_t ntasks, int32_t slots, int32_t R,
                           int64_t qdata_per_row, const int64_t *sorted, const int32_t *qlen,
-                          const int64_t *rlen, const int32_t *band, InterTask *tasks,
-                          int64_t *bnd_size, int64_t *qdata_size, hipStream_t st);
+                          const int64_t *rlen, const int32_t *band, const int32_t *band_q,
+                          InterTask *tasks, int64_t *bnd_size, int64_t *qdata_size,
+                          hipStream_t st);
 hipError_t plan_offsets_dev(int64_t ntasks, InterTask *tasks, const int64_t *bnd_off,
                             const int64_t *qdata_off, hipStream_t st);
 hipError_t flags_to_i64(int64_t n, const uint8_t *flag, int64_t *f64, hipStream_t st);
