@@ -15,7 +15,7 @@
 // The previous row of H and F lives in registers; cells left of column 0 hold
 // -inf and cells right of the last column only feed cells right of it, so no
 // per-cell masking is needed.  Choice codes of one row are packed 8 per dword
-// and stored lane-interleaved (coalesced).
+// (the first cell in the top nibble) and stored lane-interleaved (coalesced).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,6 +26,30 @@
 namespace swx {
 
 constexpr int32_t kNeg = -(1 << 29);
+
+// Choice code of a cell: bit 3 "H does not come from the diagonal"
+// (diag < H), bit 2 "F rather than E" (E < F), bit 1 "E extends" (the
+// opening H - o < the extension E - e), bit 0 "F extends".  Each bit is the
+// sign of a difference (every value here lies in [-2^30, 2^26]), shifted into
+// the accumulator from the right, so a word fills from its top nibble down.
+// Ties give M before E before F and "open" before "extend" (rule T3).
+constexpr uint32_t kCodeNotM = 8u, kCodeF = 4u, kCodeEExt = 2u, kCodeFExt = 1u;
+__device__ __forceinline__ uint32_t push_code(uint32_t acc, int32_t diag, int32_t h, int32_t eij,
+                                              int32_t fij, int32_t eo, int32_t ex, int32_t fo,
+                                              int32_t fx) {
+  acc = __builtin_amdgcn_alignbit(acc, (uint32_t)(diag - h), 31);
+  acc = __builtin_amdgcn_alignbit(acc, (uint32_t)(eij - fij), 31);
+  acc = __builtin_amdgcn_alignbit(acc, (uint32_t)(eo - ex), 31);
+  return __builtin_amdgcn_alignbit(acc, (uint32_t)(fo - fx), 31);
+}
+// the source of H named by a code: 0 diagonal, 1 E, 2 F
+__device__ __forceinline__ uint32_t code_src(uint32_t c) {
+  return (c & kCodeNotM) ? ((c & kCodeF) ? 2u : 1u) : 0u;
+}
+// row 0 of the global DP: reached from the left by one deletion run
+__device__ __forceinline__ uint32_t row0_code(int64_t j, int32_t o, int32_t e) {
+  return (j == 0) ? 0u : (kCodeNotM | ((j == 1 || o <= e) ? 0u : kCodeEExt));
+}
 
 __device__ __forceinline__ bool tb_coords_ok(const TbArgs &a, int64_t p) {
   return a.qbeg[p] >= 0 && a.qbeg[p] <= a.qend[p] && a.qend[p] < a.qlen[p] && a.rbeg[p] >= 0 &&
@@ -188,11 +212,11 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
       if (j == 0) h = 0;
       else if (j > 0) {
         h = -(o + (int32_t)(j - 1) * e);
-        c = 1u | ((j == 1 || o <= e) ? 4u : 0u);
+        c = row0_code(j, o, e);
       }
       H[k] = h;
       F[k] = kNeg;
-      dw[k >> 3] |= c << (4 * (k & 7));
+      dw[k >> 3] |= c << (4 * (7 - (k & 7)));
     }
 #pragma unroll
     for (int d = 0; d < ND; ++d) dir[(int64_t)d * 64 + lane] = dw[d];
@@ -261,10 +285,7 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
         const int32_t eij = eo > ex ? eo : ex;
         int32_t h = diag > eij ? diag : eij;
         h = h > fij ? h : fij;
-        uint32_t c = (h == diag) ? 0u : (h == eij ? 1u : 2u);
-        c |= (eo >= ex) ? 4u : 0u;
-        c |= (fo >= fx) ? 8u : 0u;
-        dw[k >> 3] |= c << (4 * (k & 7));
+        dw[k >> 3] = push_code(dw[k >> 3], diag, h, eij, fij, eo, ex, fo, fx);
         H[k] = h;
         F[k] = fij;
         ev = eij;
@@ -308,24 +329,24 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
     uint32_t word = 0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) word |= rc[d] & (0u - (uint32_t)(idx == (uint32_t)d));
-    return (word >> (4 * (k & 7))) & 0xFu;
+    return (word >> (4 * (7 - (k & 7)))) & 0xFu;
   };
   // one move of the state machine from code c; returns the op (0xFF: none)
   auto move = [&](uint32_t c, bool &up) -> uint32_t {
     uint32_t op = 0xFF;
     up = false;
     if (state == 0) {
-      const uint32_t src = c & 3u;
+      const uint32_t src = code_src(c);
       if (src == 0 && i > 0 && j > 0) { op = 0; --i; --j; up = true; }
       else if (src == 1) state = 1;
       else state = 2;
     } else if (state == 1) {
       op = 2;
-      state = (c & 4u) ? 0 : 1;
+      state = (c & kCodeEExt) ? 1 : 0;
       --j;
     } else {
       op = 1;
-      state = (c & 8u) ? 0 : 2;
+      state = (c & kCodeFExt) ? 2 : 0;
       --i;
       up = true;
     }
@@ -386,7 +407,7 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
       if (k < 0 || k >= BW) { bad = true; break; }
       const uint32_t word = dir[(i * ND + (k >> 3)) * 64 + lane];
       bool up;
-      const uint32_t op = move((word >> (4 * (k & 7))) & 0xFu, up);
+      const uint32_t op = move((word >> (4 * (7 - (k & 7)))) & 0xFu, up);
       if (op != 0xFF) {
         if (op == cur_op) ++cur_len;
         else {
@@ -749,10 +770,7 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
             const int32_t eij = eo > ex ? eo : ex;
             int32_t h = diag > eij ? diag : eij;
             h = h > fij ? h : fij;
-            uint32_t c = (h == diag) ? 0u : (h == eij ? 1u : 2u);
-            c |= (eo >= ex) ? 4u : 0u;
-            c |= (fo >= fx) ? 8u : 0u;
-            code |= c << (4 * k);
+            code = push_code(code, diag, h, eij, fij, eo, ex, fo, fx);   // row k: bits 4(RL-1-k)
             hdiag = H[k];
             H[k] = h;
             E[k] = eij;
@@ -832,7 +850,7 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
   while ((i > 0 || j > 0) && guard-- > 0) {
     uint32_t c;
     if (i == 0) {
-      c = (j == 0) ? 0u : (1u | ((j == 1 || o <= e) ? 4u : 0u));
+      c = row0_code(j, o, e);
     } else {
       const int32_t s = (i - 1) / kStripR, k = (i - 1) % kStripR;
       const int32_t gk = k / RL;
@@ -865,21 +883,21 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
       }
       const int32_t top2 = (cache_j - clo + gk) >> 1;
       const uint32_t dwv = cache[gk * kCU + (top2 - (t >> 1))];
-      c = (dwv >> (16 * (t & 1) + 4 * (k % RL))) & 0xFu;
+      c = (dwv >> (16 * (t & 1) + 4 * (RL - 1 - k % RL))) & 0xFu;
     }
     uint32_t op = 0xFF;
     if (state == 0) {
-      const uint32_t src = c & 3u;
+      const uint32_t src = code_src(c);
       if (src == 0 && i > 0 && j > 0) { op = 0; --i; --j; }
       else if (src == 1) state = 1;
       else state = 2;
     } else if (state == 1) {
       op = 2;
-      state = (c & 4u) ? 0 : 1;
+      state = (c & kCodeEExt) ? 1 : 0;
       --j;
     } else {
       op = 1;
-      state = (c & 8u) ? 0 : 2;
+      state = (c & kCodeFExt) ? 2 : 0;
       --i;
     }
     if (op != 0xFF) {
@@ -915,9 +933,6 @@ __device__ __forceinline__ int32_t tb_from_above(int32_t src, int32_t top) {
   return __builtin_amdgcn_update_dpp(top, src, 0x138, 0xF, 0xF, false);   // wave_shr:1
 }
 
-__device__ __forceinline__ uint32_t row0_code(int64_t j, int32_t o, int32_t e) {
-  return (j == 0) ? 0u : (1u | ((j == 1 || o <= e) ? 4u : 0u));
-}
 
 constexpr int kTbMaxStrips = 256;
 constexpr int kTbMaxWaves = 8;
@@ -1070,11 +1085,9 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
         const int32_t eij = eo > ex ? eo : ex;
         int32_t h = diag > eij ? diag : eij;
         h = h > fij ? h : fij;
-        uint32_t c = (h == diag) ? 0u : (h == eij ? 1u : 2u);
-        c |= (eo >= ex) ? 4u : 0u;
-        c |= (fo >= fx) ? 8u : 0u;
-        if (k < 8) dw0 |= c << (4 * k);
-        else dw1 |= c << (4 * (k - 8));
+        // row k: bits 4(7 - k%8) of dw0 (k < 8) or dw1
+        if (k < 8) dw0 = push_code(dw0, diag, h, eij, fij, eo, ex, fo, fx);
+        else dw1 = push_code(dw1, diag, h, eij, fij, eo, ex, fo, fx);
         hdiag = H[k];
         H[k] = h;
         E[k] = eij;
@@ -1151,21 +1164,21 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
         __builtin_amdgcn_wave_barrier();
       }
       const uint2 dv = s_tile[(t - tile_lo) * 64 + L];
-      c = ((rr < 8 ? dv.x : dv.y) >> (4 * (rr & 7))) & 0xFu;
+      c = ((rr < 8 ? dv.x : dv.y) >> (4 * (7 - (rr & 7)))) & 0xFu;
     }
     uint32_t op = 0xFF;
     if (state == 0) {
-      const uint32_t src = c & 3u;
+      const uint32_t src = code_src(c);
       if (src == 0 && i > 0 && j > 0) { op = 0; --i; --j; }
       else if (src == 1) state = 1;
       else state = 2;
     } else if (state == 1) {
       op = 2;
-      state = (c & 4u) ? 0 : 1;
+      state = (c & kCodeEExt) ? 1 : 0;
       --j;
     } else {
       op = 1;
-      state = (c & 8u) ? 0 : 2;
+      state = (c & kCodeFExt) ? 2 : 0;
       --i;
     }
     if (op != 0xFF) {
