@@ -12,6 +12,7 @@
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/swx.h"
@@ -128,6 +129,9 @@ struct swx_ctx {
   std::mutex pair_mu;
   std::vector<PairGraph> pair_graphs;
   uint64_t pair_clock = 0;
+  // pinned landing area of the small device-to-host reads between stages
+  static constexpr int64_t kPinned = 512;   // int64 values
+  int64_t *pinned = nullptr;
 };
 
 struct swx_profile {
@@ -188,6 +192,17 @@ struct Plan {
 
 static inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// Wait for a stream by polling it.  A blocking wait sleeps until an interrupt
+// wakes the thread, tens of microseconds after the stream has drained, and
+// every host read between the stages of a call paid that with an idle device.
+static hipError_t wait_stream(hipStream_t st) {
+  for (;;) {
+    const hipError_t e = hipStreamQuery(st);
+    if (e != hipErrorNotReady) return e;
+    std::this_thread::yield();
+  }
+}
+
 template <class T>
 static T *alloc_or_null(DevArena &A, int64_t n) { return A.get<T>(n); }
 
@@ -233,10 +248,10 @@ static int plan_pass(swx_ctx *ctx, const Scoring &sc, const int64_t *ids, int64_
   if (!s2) return fail(SWX_ENOMEM, "device pool exhausted (scan)");
   HIP_TRY(launch_exclusive_scan(qsz, qoff, pl.ntasks + 1, s2, &t2, st));
   HIP_TRY(plan_offsets_dev(pl.ntasks, pl.d_tasks, boff, qoff, st));
-  int64_t tot[2] = {0, 0};
-  HIP_TRY(hipMemcpyAsync(&tot[0], boff + pl.ntasks, 8, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(&tot[1], qoff + pl.ntasks, 8, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipMemcpyAsync(ctx->pinned, boff + pl.ntasks, 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(ctx->pinned + 1, qoff + pl.ntasks, 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(wait_stream(st));
+  const int64_t tot[2] = {ctx->pinned[0], ctx->pinned[1]};
   pl.d_bnd = A.get<uint32_t>(tot[0]);
   pl.d_rsym = A.get<uint2>(rsym_offset(tot[0]));
   if (!pl.d_bnd || !pl.d_rsym) return fail(SWX_ENOMEM, "device pool exhausted (boundary planes)");
@@ -317,9 +332,13 @@ static int scan(swx_ctx *ctx, const int64_t *in, int64_t *out, int64_t n) {
   return SWX_OK;
 }
 
+// n values from the device; small reads land in pinned memory (a direct copy,
+// no staging through the runtime's own buffers).  Callers hold ctx->mu.
 static int read_i64(swx_ctx *ctx, const int64_t *d, int64_t *h, int64_t n = 1) {
-  HIP_TRY(hipMemcpyAsync(h, d, 8 * n, hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  const bool pin = n <= swx_ctx::kPinned;
+  HIP_TRY(hipMemcpyAsync(pin ? ctx->pinned : h, d, 8 * n, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(wait_stream(ctx->stream));
+  if (pin) memcpy(h, ctx->pinned, 8 * (size_t)n);
   return SWX_OK;
 }
 
@@ -870,8 +889,9 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
                   b.pair_q, b.pair_r, np, sc.n, d_bad};
   HIP_TRY(launch_validate(va, st));
   uint32_t bad = 0;
-  HIP_TRY(hipMemcpyAsync(&bad, d_bad, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipMemcpyAsync(ctx->pinned, d_bad, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(wait_stream(st));
+  memcpy(&bad, ctx->pinned, sizeof(uint32_t));
   if (bad & 1u) return fail(SWX_EINVAL, "offsets must be non-decreasing and within the code arrays");
   if (bad & 2u) return fail(SWX_EINVAL, "pair index out of range");
   if (bad & 12u) return fail(SWX_EINVAL, "symbol code outside [0, n)");
@@ -1651,7 +1671,8 @@ int swx_ctx_create(int device, swx_ctx **out) {
     return fail(SWX_EDEVICE, "could not create side streams");
   }
   if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
-      c->cus < 1 || hipMalloc(&c->queue, 256) != hipSuccess) {
+      c->cus < 1 || hipMalloc(&c->queue, 256) != hipSuccess ||
+      hipHostMalloc(&c->pinned, 8 * swx_ctx::kPinned, hipHostMallocDefault) != hipSuccess) {
     delete c;
     return fail(SWX_EDEVICE, "could not query the device or allocate the work queue");
   }
@@ -1672,6 +1693,7 @@ int swx_ctx_destroy(swx_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     ctx->arena.release();
     if (ctx->queue) (void)hipFree(ctx->queue);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     for (auto &e : ctx->ev)
       if (e) (void)hipEventDestroy(e);
     for (int k = 0; k < swx_ctx::kAux; ++k) {
@@ -2028,13 +2050,17 @@ int swx_graph_create(swx_ctx *ctx, const swx_graph_cfg *cfg, swx_graph **out, sw
   return SWX_OK;
 }
 
+// waits for the stream and reads the run's flags; the caller holds ctx->mu
 static int graph_check(swx_graph *gr) {
   GraphState &g = gr->g;
-  uint32_t bad = 0;
-  int64_t nerr = 0;
-  if (hipMemcpy(&bad, g.bad, 4, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(&nerr, g.status, 8, hipMemcpyDeviceToHost) != hipSuccess)
+  swx_ctx *ctx = gr->ctx;
+  if (hipMemcpyAsync(ctx->pinned, g.bad, 4, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+      hipMemcpyAsync(ctx->pinned + 1, g.status, 8, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+      wait_stream(ctx->stream) != hipSuccess)
     return fail(SWX_EDEVICE, "could not read the graph status");
+  uint32_t bad = 0;
+  memcpy(&bad, ctx->pinned, 4);
+  const int64_t nerr = ctx->pinned[1];
   if (bad & 1u) return fail(SWX_EINVAL, "offsets must be non-decreasing and within the code arrays");
   if (bad & 2u) return fail(SWX_EINVAL, "pair index out of range");
   if (bad & 12u) return fail(SWX_EINVAL, "symbol code outside [0, n)");
@@ -2047,7 +2073,6 @@ int swx_graph_run(swx_graph *gr) {
   std::lock_guard<std::mutex> lk(gr->ctx->mu);
   if (hipSetDevice(gr->ctx->device) != hipSuccess) return fail(SWX_EDEVICE, "hipSetDevice failed");
   HIP_TRY(hipGraphLaunch(gr->g.exec, gr->ctx->stream));
-  HIP_TRY(hipStreamSynchronize(gr->ctx->stream));
   return graph_check(gr);
 }
 
@@ -2057,7 +2082,6 @@ int swx_graph_run_eager(swx_graph *gr) {
   if (hipSetDevice(gr->ctx->device) != hipSuccess) return fail(SWX_EDEVICE, "hipSetDevice failed");
   int rc = fixed_issue(gr->g, gr->ctx->stream);
   if (rc) return rc;
-  HIP_TRY(hipStreamSynchronize(gr->ctx->stream));
   return graph_check(gr);
 }
 
@@ -2100,7 +2124,7 @@ int swx_graph_load(swx_graph *gr, const swx_batch *b) {
   HIP_TRY(hipMemcpyAsync(g.roff, ro.data(), 8 * ro.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(g.pair_q, pq.data(), 8 * pq.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(g.pair_r, pr.data(), 8 * pr.size(), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(wait_stream(st));   // the host vectors must outlive the copies
   return SWX_OK;
 }
 
