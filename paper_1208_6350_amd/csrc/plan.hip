@@ -85,6 +85,10 @@ __global__ void k_plan_tasks(int64_t n, const int64_t *n_dev, int64_t ntasks, in
   mb = wave_max_i64(mb);
   mbq = wave_max_i64(mbq);
   if (lane != 0) return;
+  if (t == 0) {   // the totals' slots of the two scans
+    bnd_size[ntasks] = 0;
+    qdata_size[ntasks] = 0;
+  }
   InterTask tk{};
   tk.nslots = (int32_t)(s1 - s0);
   // without a query profile the last strip may be half high: rows are
@@ -109,9 +113,11 @@ __global__ void k_plan_offsets(int64_t ntasks, InterTask *tasks, const int64_t *
 }
 
 // flagged compaction: out[k] = the k-th pair with flag != 0 (in pair order)
+// f64[0 .. n) = flags as 0/1 and f64[n] = 0 (the total's slot of the scan)
 __global__ void k_flag_to_i64(int64_t n, const uint8_t *flag, int64_t *f64) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p < n) f64[p] = flag[p] ? 1 : 0;
+  else if (p == n) f64[n] = 0;
 }
 
 __global__ void k_compact(int64_t n, const uint8_t *flag, const int64_t *pos, int64_t *out) {
@@ -256,8 +262,7 @@ hipError_t plan_offsets_dev(int64_t ntasks, InterTask *tasks, const int64_t *bnd
 }
 
 hipError_t flags_to_i64(int64_t n, const uint8_t *flag, int64_t *f64, hipStream_t st) {
-  if (!n) return hipSuccess;
-  hipLaunchKernelGGL(k_flag_to_i64, dim3(nb(n, 256)), dim3(256), 0, st, n, flag, f64);
+  hipLaunchKernelGGL(k_flag_to_i64, dim3(nb(n + 1, 256)), dim3(256), 0, st, n, flag, f64);
   return hipGetLastError();
 }
 

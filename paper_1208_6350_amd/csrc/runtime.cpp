@@ -234,9 +234,8 @@ static int plan_pass(swx_ctx *ctx, const Scoring &sc, const int64_t *ids, int64_
   if (!tmp) return fail(SWX_ENOMEM, "device pool exhausted (sort)");
   HIP_TRY(plan_sort(n, nullptr, ids, qlen, rlen, band, R, k0, k1, v0, v1, tmp, &tmp_bytes, &pl.d_sorted, st));
   const int64_t per_row = sc.qsel ? 0 : (int64_t)(sc.n + 1) * halves * 64;
-  HIP_TRY(hipMemsetAsync(bsz + pl.ntasks, 0, 8, st));
-  HIP_TRY(hipMemsetAsync(qsz + pl.ntasks, 0, 8, st));
-  HIP_TRY(plan_tasks_dev(n, nullptr, pl.ntasks, slots, R, per_row, pl.d_sorted, qlen, rlen, band,
+  HIP_TRY(plan_tasks_dev(   // also clears bsz[ntasks], qsz[ntasks]
+                         n, nullptr, pl.ntasks, slots, R, per_row, pl.d_sorted, qlen, rlen, band,
                          band_q, pl.d_tasks, bsz, qsz, st));
   size_t t1 = 0, t2 = 0;
   HIP_TRY(launch_exclusive_scan(bsz, boff, pl.ntasks + 1, nullptr, &t1, st));
@@ -349,8 +348,7 @@ static int select_flagged_dev(swx_ctx *ctx, const uint8_t *flag, int64_t np, int
   int64_t *f64 = A.get<int64_t>(np + 1), *pos = A.get<int64_t>(np + 1);
   *ids = A.get<int64_t>(np);
   if (!f64 || !pos || !*ids) return fail(SWX_ENOMEM, "device pool exhausted (select)");
-  HIP_TRY(hipMemsetAsync(f64 + np, 0, 8, ctx->stream));
-  HIP_TRY(flags_to_i64(np, flag, f64, ctx->stream));
+  HIP_TRY(flags_to_i64(np, flag, f64, ctx->stream));   // also clears f64[np]
   int rc = scan(ctx, f64, pos, np + 1);
   if (rc) return rc;
   HIP_TRY(compact_flags(np, flag, pos, *ids, ctx->stream));
@@ -1275,9 +1273,8 @@ static int fixed_fill(GraphState &g, FixedPlan &pl, const int64_t *ids, const in
                     pl.sort_tmp, &sb, &pl.sorted, st));
   const int halves = pl.lane_bits == 16 ? 2 : 1;
   const int64_t per_row = g.sc.qsel ? 0 : (int64_t)(g.sc.n + 1) * halves * 64;
-  HIP_TRY(fill_i64(1, pl.bsz + pl.ntasks, 0, st));
-  HIP_TRY(fill_i64(1, pl.qsz + pl.ntasks, 0, st));
-  HIP_TRY(plan_tasks_dev(pl.cap_n, n_dev, pl.ntasks, pl.slots, pl.R, per_row, pl.sorted, qlen, rlen,
+  HIP_TRY(plan_tasks_dev(   // also clears bsz[ntasks], qsz[ntasks]
+                         pl.cap_n, n_dev, pl.ntasks, pl.slots, pl.R, per_row, pl.sorted, qlen, rlen,
                          band, band_q, pl.tasks, pl.bsz, pl.qsz, st));
   int rc;
   if ((rc = fixed_scan(g, pl.bsz, pl.boff, pl.ntasks + 1, st))) return rc;
@@ -1309,8 +1306,7 @@ static int fixed_fill(GraphState &g, FixedPlan &pl, const int64_t *ids, const in
 
 // flagged pairs -> ids[0 .. *count) with the count on the device (pos[B])
 static int fixed_select(GraphState &g, const uint8_t *flag, const int64_t **count, hipStream_t st) {
-  HIP_TRY(fill_i64(1, g.f64 + g.B, 0, st));
-  HIP_TRY(flags_to_i64(g.B, flag, g.f64, st));
+  HIP_TRY(flags_to_i64(g.B, flag, g.f64, st));   // also clears g.f64[B]
   int rc;
   if ((rc = fixed_scan(g, g.f64, g.pos, g.B + 1, st))) return rc;
   HIP_TRY(compact_flags(g.B, flag, g.pos, g.ids, st));
@@ -1643,6 +1639,23 @@ int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t) {
   return SWX_OK;
 }
 
+// frees whatever a context holds (also one that was only partly created)
+static void release_ctx(swx_ctx *ctx) {
+  (void)hipSetDevice(ctx->device);
+  ctx->arena.release();
+  if (ctx->queue) (void)hipFree(ctx->queue);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  for (auto &e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (int k = 0; k < swx_ctx::kAux; ++k) {
+    if (ctx->aux[k]) (void)hipStreamDestroy(ctx->aux[k]);
+    if (ctx->join_ev[k]) (void)hipEventDestroy(ctx->join_ev[k]);
+  }
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
 int swx_ctx_create(int device, swx_ctx **out) {
   if (!out) return fail(SWX_EINVAL, "out is null");
   *out = nullptr;
@@ -1654,12 +1667,12 @@ int swx_ctx_create(int device, swx_ctx **out) {
   if (!c) return fail(SWX_ENOMEM, "host allocation failed");
   c->device = device;
   if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&c->stream) != hipSuccess) {
-    delete c;
+    release_ctx(c);
     return fail(SWX_EDEVICE, "could not create a stream");
   }
   for (auto &e : c->ev) {
     if (hipEventCreate(&e) != hipSuccess) {
-      delete c;
+      release_ctx(c);
       return fail(SWX_EDEVICE, "could not create events");
     }
   }
@@ -1667,13 +1680,13 @@ int swx_ctx_create(int device, swx_ctx **out) {
   for (int k = 0; k < swx_ctx::kAux && ok; ++k)
     ok = hipEventCreateWithFlags(&c->join_ev[k], hipEventDisableTiming) == hipSuccess;
   if (!ok) {
-    delete c;
+    release_ctx(c);
     return fail(SWX_EDEVICE, "could not create side streams");
   }
   if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
       c->cus < 1 || hipMalloc(&c->queue, 256) != hipSuccess ||
       hipHostMalloc(&c->pinned, 8 * swx_ctx::kPinned, hipHostMallocDefault) != hipSuccess) {
-    delete c;
+    release_ctx(c);
     return fail(SWX_EDEVICE, "could not query the device or allocate the work queue");
   }
   *out = c;
@@ -1690,23 +1703,11 @@ int swx_ctx_destroy(swx_ctx *ctx) {
   {
     std::lock_guard<std::mutex> g(ctx->mu);
     (void)hipSetDevice(ctx->device);
-    (void)hipStreamSynchronize(ctx->stream);
-    ctx->arena.release();
-    if (ctx->queue) (void)hipFree(ctx->queue);
-    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-    for (auto &e : ctx->ev)
-      if (e) (void)hipEventDestroy(e);
-    for (int k = 0; k < swx_ctx::kAux; ++k) {
-      if (ctx->aux[k]) {
-        (void)hipStreamSynchronize(ctx->aux[k]);
-        (void)hipStreamDestroy(ctx->aux[k]);
-      }
-      if (ctx->join_ev[k]) (void)hipEventDestroy(ctx->join_ev[k]);
-    }
-    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
-    (void)hipStreamDestroy(ctx->stream);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (int k = 0; k < swx_ctx::kAux; ++k)
+      if (ctx->aux[k]) (void)hipStreamSynchronize(ctx->aux[k]);
   }
-  delete ctx;
+  release_ctx(ctx);
   return SWX_OK;
 }
 

@@ -320,6 +320,7 @@ hipError_t plan_tasks_dev(int64_t n, const int64_t *n_dev, int64_t ntasks, int32
                           hipStream_t st);
 hipError_t plan_offsets_dev(int64_t ntasks, InterTask *tasks, const int64_t *bnd_off,
                             const int64_t *qdata_off, hipStream_t st);
+// f64[0 .. n) = flag != 0, f64[n] = 0 (n + 1 values, ready for an exclusive scan)
 hipError_t flags_to_i64(int64_t n, const uint8_t *flag, int64_t *f64, hipStream_t st);
 hipError_t compact_flags(int64_t n, const uint8_t *flag, const int64_t *pos, int64_t *out,
                          hipStream_t st);
