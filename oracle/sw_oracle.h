@@ -32,12 +32,11 @@
  *   T5        : score1 == 0 -> no alignment, every coordinate -1.
  *
  * Pins (tests/test_oracle_pins.py): exhaustive enumeration of all local
- * alignments on short sequences fixes score1, the max array, T1, T2, T4 and,
- * for o > e, T3; Kadane's maximum subarray (no gap can pay) and a one-matrix
+ * alignments on short sequences fixes score1, the max array, T1, T2, T4 and
+ * T3 at every gap setting o >= e >= 0 (the enumeration walks gap state paths,
+ * re-opened runs included, so the T3 choice digits are defined at o == e and
+ * o == 0 as well); Kadane's maximum subarray (no gap can pay) and a one-matrix
  * linear-gap SW (o == e) fix score1 and the max array at larger sizes.
- * Parity unpinned: the T3 CIGAR when o == e, where several state paths give
- * different op strings of equal score; there only re-scoring and span checks
- * apply, and GPU agreement rests on following the same procedure.
  *
  * All coordinates are 0-based and inclusive.  CIGAR entries are
  * (length << 4) | op with op M=0, I=1 (consumes query), D=2 (consumes

@@ -15,11 +15,19 @@
  *   (ie, je)         among cells of score1 alignments: smallest j, then i
  *   (ib, jb)         among begins of score1 alignments whose cell is (ie, je):
  *                    largest jb, then largest ib
- *   ops              among score1 alignments from (ib, jb) to (ie, je): the op
- *                    string whose backward choice digits are smallest
- *                    (state H: M=0 < D=1 < I=2; inside a gap run: the step
- *                    that opens the run = 0, an extending step = 1).  Meant
- *                    for o > e, where an op string fixes its state path.
+ *   ops              among score1 state paths from (ib, jb) to (ie, je): the
+ *                    op string of the path whose backward choice digits are
+ *                    smallest (state H: M=0 < D=1 < I=2; each gap symbol:
+ *                    opening = 0, extending the gap state = 1).
+ *
+ * A state path is an op string plus, for every gap symbol that follows a gap
+ * symbol of the same kind, whether it extends the gap (cost e) or opens a new
+ * one straight after it (cost o: the gap state is left for H and entered
+ * again, which the three-state recurrence allows).  For o > e a re-opened
+ * run scores less than the extended one, so the op string alone fixes the
+ * best path; for o == e both score the same and the digits decide between
+ * them.  Pass 3 enumerates both choices; passes 1 and 2 need only the
+ * extending one, since re-opening never raises a score (o >= e).
  */
 #include <stdint.h>
 #include <string.h>
@@ -39,6 +47,7 @@ typedef struct {
   int ib, jb, have_begin;
   /* pass 3 */
   uint8_t ops[MAXOPS];
+  uint8_t opn[MAXOPS];   /* per op: 1 when a gap symbol opens its gap (or op is M) */
   int nops;
   uint8_t best_dig[4 * MAXOPS];
   int best_ndig, have_path;
@@ -48,18 +57,22 @@ typedef struct {
 
 static int sc(const bctx *c, int i, int j) { return c->mat[c->q[i] * c->n + c->r[j]]; }
 
-/* backward choice digits of an op string (forward order ops[0..nops)) */
-static int digits(const uint8_t *ops, int nops, uint8_t *dig) {
+/* backward choice digits of a state path (forward order ops[0..nops), with
+ * opn[k] = 1 when gap symbol k opens its gap) */
+static int digits(const uint8_t *ops, const uint8_t *opn, int nops, uint8_t *dig) {
   int nd = 0;
   int k = nops - 1;
   while (k >= 0) {
     uint8_t op = ops[k];
     if (op == 0) { dig[nd++] = 0; --k; continue; }
     dig[nd++] = (op == 2) ? 1 : 2;   /* H picks D (state E) or I (state F) */
-    while (k >= 0 && ops[k] == op) {
-      int extend = (k - 1 >= 0 && ops[k - 1] == op);
-      dig[nd++] = extend ? 1 : 0;
+    /* inside the gap state: emit the symbol, then leave it (open) or stay
+     * (extend: the previous symbol is the same gap kind) */
+    for (;;) {
+      const int open = opn[k];
+      dig[nd++] = open ? 0 : 1;
       --k;
+      if (open) break;
     }
   }
   return nd;
@@ -93,7 +106,7 @@ static void visit(bctx *c, int i, int j, int64_t s, int i0, int j0) {
   } else {
     if (s == c->best && i == c->ie && j == c->je) {
       uint8_t dig[4 * MAXOPS];
-      int nd = digits(c->ops, c->nops, dig);
+      int nd = digits(c->ops, c->opn, c->nops, dig);
       if (!c->have_path || dig_less(dig, nd, c->best_dig, c->best_ndig)) {
         c->have_path = 1;
         memcpy(c->best_dig, dig, (size_t)nd); c->best_ndig = nd;
@@ -106,24 +119,29 @@ static void visit(bctx *c, int i, int j, int64_t s, int i0, int j0) {
 static void walk(bctx *c, int i, int j, int64_t s, uint8_t last, int i0, int j0) {
   visit(c, i, j, s, i0, j0);
   if (i + 1 < c->lq && j + 1 < c->lr) {
+    c->opn[c->nops] = 1;
     c->ops[c->nops++] = 0;
     walk(c, i + 1, j + 1, s + sc(c, i + 1, j + 1), 0, i0, j0);
     c->nops--;
   }
-  if (j + 1 < c->lr) {          /* D consumes the reference */
-    c->ops[c->nops++] = 2;
-    walk(c, i, j + 1, s - (last == 2 ? c->e : c->o), 2, i0, j0);
-    c->nops--;
-  }
-  if (i + 1 < c->lq) {          /* I consumes the query */
-    c->ops[c->nops++] = 1;
-    walk(c, i + 1, j, s - (last == 1 ? c->e : c->o), 1, i0, j0);
-    c->nops--;
+  for (int g = 0; g < 2; ++g) {   /* g = 0: D consumes the reference; g = 1: I the query */
+    const uint8_t op = g == 0 ? 2 : 1;
+    const int ni = g == 0 ? i : i + 1, nj = g == 0 ? j + 1 : j;
+    if (ni >= c->lq || nj >= c->lr) continue;
+    /* after a symbol of the same gap: extend; in pass 3 also re-open */
+    for (int open = (last == op) ? 0 : 1; open <= 1; ++open) {
+      if (open && last == op && c->pass != 3) break;
+      c->opn[c->nops] = (uint8_t)open;
+      c->ops[c->nops++] = op;
+      walk(c, ni, nj, s - (open ? c->o : c->e), op, i0, j0);
+      c->nops--;
+    }
   }
 }
 
 static void run_from(bctx *c, int i0, int j0) {
   c->nops = 0;
+  c->opn[c->nops] = 1;
   c->ops[c->nops++] = 0;
   walk(c, i0, j0, sc(c, i0, j0), 0, i0, j0);
 }

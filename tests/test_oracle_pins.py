@@ -1,8 +1,10 @@
 """Pins of the CPU oracle against facts fixed outside the oracle itself.
 
 * P1: exhaustive enumeration of all local alignments (tests/brute) on short
-  sequences fixes score1, the max array, the T1 end, the T2 begin and, for
-  o > e, the T3 CIGAR (smallest backward choice-digit string).
+  sequences fixes score1, the max array, the T1 end, the T2 begin and the T3
+  CIGAR (the state path with the smallest backward choice-digit string; the
+  enumeration covers re-opened gap runs, so o == e is pinned too), at every
+  gap setting o >= e >= 0 including o == e and o == 0.
 * P2: closed forms (self-alignment, exact substring, one substitution, one
   deletion, one-symbol query).
 * P3: special cases that reduce to textbook routines (Kadane's maximum
@@ -27,7 +29,7 @@ from tests import brute
 from tests.helpers import kadane_local, rescore, score2_from_maxcol, textbook_linear_sw
 from workloads import dna_matrix, mutate_many, protein_matrix_standin
 
-GAPS = [(3, 1), (2, 1), (5, 2), (11, 1), (1, 1), (4, 4), (3, 0)]
+GAPS = [(3, 1), (2, 1), (5, 2), (11, 1), (1, 1), (4, 4), (3, 0), (0, 0), (2, 2), (3, 3)]
 
 
 def _check_against_brute(q, r, mat, o, e):
@@ -42,20 +44,18 @@ def _check_against_brute(q, r, mat, o, e):
         assert a.cigar == [] and a.score2 == 0 and a.ref_end2 == -1
         return
     assert (ie, je) == b["end"] == (a.read_end1, a.ref_end1)
-    if o > 0:
-        assert (a.read_begin1, a.ref_begin1) == b["begin"]
-        sp = oracle.begin_startprop(q, r, mat, o, e, ie, je, s1)
-        assert sp == b["begin"]
+    assert (a.read_begin1, a.ref_begin1) == b["begin"]
+    sp = oracle.begin_startprop(q, r, mat, o, e, ie, je, s1)
+    assert sp == b["begin"]
     sc, cq, cr = rescore(q, r, mat, o, e, a.read_begin1, a.ref_begin1, a.cigar)
     assert sc == a.score1
     assert cq == a.read_end1 - a.read_begin1 + 1 and cr == a.ref_end1 - a.ref_begin1 + 1
-    if o > e:
-        assert a.cigar == b["cigar"]
+    assert a.cigar == b["cigar"]
     m = max(len(q) // 2, 15)
     assert (a.score2, a.ref_end2) == score2_from_maxcol(b["maxcol"], a.ref_begin1, a.ref_end1, m)
 
 
-@pytest.mark.parametrize("o,e", [(3, 1), (2, 1), (1, 1), (5, 2)])
+@pytest.mark.parametrize("o,e", [(3, 1), (2, 1), (1, 1), (5, 2), (2, 2), (0, 0), (3, 0)])
 def test_brute_all_ternary_pairs_len3(o, e):
     """Every pair of length-3 sequences over 3 symbols (729 pairs)."""
     mat = np.array([[2, -1, -2], [-1, 2, -1], [-2, -1, 3]], dtype=np.int8)
@@ -104,7 +104,7 @@ def test_brute_planted_len8():
         q = q[:8]
         if len(q) == 0:
             continue
-        o, e = [(3, 1), (2, 1), (1, 1), (4, 1)][k % 4]
+        o, e = [(3, 1), (2, 1), (1, 1), (4, 1), (2, 2), (3, 3), (0, 0)][k % 7]
         _check_against_brute(q, r, mat, o, e)
 
 
@@ -345,10 +345,10 @@ def _score2_from_brute(b, mask_len):
     return best, at
 
 
-@pytest.mark.parametrize("o,e", [(3, 1), (2, 1), (5, 2), (4, 1)])
+@pytest.mark.parametrize("o,e", [(3, 1), (2, 1), (5, 2), (4, 1), (2, 2), (0, 0)])
 def test_suboptimal_matches_brute_force(o, e):
     """End row (smallest row of column ref_end2 at score2), T2 begin relative to
-    that end, and the T3 CIGAR (o > e) of the alignment behind score2, against
+    that end, and the T3 CIGAR of the alignment behind score2, against
     exhaustive enumeration, with narrow masks so that score2 is often set."""
     g = np.random.Generator(np.random.PCG64(41 + o * 10 + e))
     mat = dna_matrix()
