@@ -271,9 +271,10 @@ int swx_graph_run_eager(swx_graph *g);
  * slots past npairs with (query 0, reference nr), an empty reference: needs
  * npairs <= max_pairs, nq <= nq_cap, nr + 1 <= nr_cap, the code arrays
  * within their capacities, offsets non-decreasing within the code arrays,
- * pair indices in range and every pair within max_qlen and max_rlen
- * (SWX_EINVAL otherwise, checked on the host before any copy).  Symbol codes
- * are checked by swx_graph_run.  Contents written straight into the device
+ * pair indices in range, every pair within max_qlen and max_rlen and every
+ * symbol code in [0, n) (SWX_EINVAL otherwise, checked on the host before any
+ * copy, so a rejected load leaves the buffers as they were).  Contents written
+ * straight into the device
  * buffers (swx_graph_io) are not checked beforehand: the run clamps every
  * index, offset and length into the buffers and capacities (so no kernel
  * leaves them), reports bad offsets, indices and codes afterwards as
@@ -296,7 +297,10 @@ int swx_graph_destroy(swx_graph *g);
  *     work takes (sequences, boundary rows, max array, profile and traceback
  *     band); requests leave the queue only while the estimates of the work in
  *     flight stay within mem_budget, long requests within 3/4 of it so that
- *     short ones always find room (a request above its share runs alone).
+ *     short ones always find room.  A long request above that share starts
+ *     only on an idle device: while one heads the long queue, no new short
+ *     batch starts until the work in flight has drained, so it cannot be held
+ *     back for good by steady short traffic.
  *   - Continuous batching: each of `workers` worker threads owns a context
  *     (own HIP stream and device pool); a free worker takes every queued
  *     request of one size class that fits (up to max_batch) as one batch, so

@@ -2111,6 +2111,13 @@ int swx_graph_load(swx_graph *gr, const swx_batch *b) {
     if (b->qoff[qi + 1] - b->qoff[qi] > g.QM || b->roff[ri + 1] - b->roff[ri] > g.RM)
       return fail(SWX_EINVAL, "a pair exceeds the graph's length capacities");
   }
+  // symbols too: a rejected code must never reach the device buffers, where
+  // it would outlive this load past the next, shorter one (every run checks
+  // the whole code arrays)
+  for (int64_t k = 0; k < b->qcat_len; ++k)
+    if (b->qcat[k] < 0 || b->qcat[k] >= g.sc.n) return fail(SWX_EINVAL, "symbol code outside [0, n)");
+  for (int64_t k = 0; k < b->rcat_len; ++k)
+    if (b->rcat[k] < 0 || b->rcat[k] >= g.sc.n) return fail(SWX_EINVAL, "symbol code outside [0, n)");
   // offsets padded with their last value; pair slots past npairs take the
   // empty reference nr (roff[nr] == roff[nr + 1])
   std::vector<int64_t> qo(g.cfg.nq_cap + 1), ro(g.cfg.nr_cap + 1), pq(g.B, 0), pr(g.B, b->nr);

@@ -59,14 +59,26 @@ inline bool admissible(const swx_server_cfg &c, const Budget &b, int64_t fp, int
   return cls == 0 || b.inflight_long + extra + fp <= c.mem_budget / 4 * 3;
 }
 
+// A long request above the long requests' share can only start on an idle
+// device: it needs the device alone.
+inline bool needs_device_alone(const swx_server_cfg &c, int64_t fp) {
+  return fp > c.mem_budget / 4 * 3;
+}
+
 // The class worker w serves next, or -1.  Worker 0 serves only short
 // requests (when there are other workers), so a short request never waits
 // behind a batch of long ones; the others prefer long requests and take
-// short ones when no long request is admissible.  Q is a queue of items with
-// a `footprint` member.
+// short ones when no long request is admissible.  Drain: while the head of
+// the long queue needs the device alone, no new batch of short requests
+// starts, so that the work in flight drains and the long request runs on the
+// idle device (otherwise steady short traffic would keep the device from
+// ever being idle and hold it, and every long request behind it, back for
+// good).  Q is a queue of items with a `footprint` member.
 template <class Q>
 int pick_class(const swx_server_cfg &c, const Budget &b, const Q pending[2], int w) {
+  const bool drain = !pending[1].empty() && needs_device_alone(c, pending[1].front().footprint);
   auto ok = [&](int k) {
+    if (k == 0 && drain) return false;
     return !pending[k].empty() && admissible(c, b, pending[k].front().footprint, k, 0);
   };
   if (w == 0 && c.workers > 1) return ok(0) ? 0 : -1;

@@ -224,6 +224,33 @@ def test_single_pair_calls_equal_batch(ctx):
     assert ei.value.status == -1
 
 
+def test_rejected_single_pair_leaves_no_trace(ctx):
+    """A one-pair call rejected for a bad reference symbol leaves nothing
+    behind in the cached one-pair graph: a later, shorter reference of the
+    same size class (the bad byte's position lies past its end) aligns and
+    equals the batch result."""
+    g = np.random.Generator(np.random.PCG64(4400))
+    q = g.integers(0, 4, 120).astype(np.int8)
+    bad = g.integers(0, 4, 1500).astype(np.int8)
+    bad[1400] = 7
+    good = g.integers(0, 4, 1100).astype(np.int8)
+    good[300:420] = q
+    m = W.dna_matrix()
+    rec, c1 = ctx.align_pair(q, good, m, 3, 1)          # caches the size class's graph
+    with pytest.raises(swx.SwxError) as ei:
+        ctx.align_pair(q, bad, m, 3, 1)
+    assert ei.value.status == -1
+    b = W.from_lists("after-reject", m, 3, 1, [q], [good])
+    recs, cig = ctx.align_batch(b.matrix, 3, 1, b.qcat, b.qoff, b.rcat, b.roff, b.pair_q,
+                                b.pair_r)
+    for rep in range(2):
+        rec, c1 = ctx.align_pair(q, good, m, 3, 1)
+        for f in FIELDS:
+            assert rec[f] == recs[f][0], f
+        assert c1 == swx.decode_cigar(cig[:recs["cigar_len"][0]])
+    assert rec["score1"] >= 200
+
+
 def test_invalid_symbols_rejected(ctx):
     b = W.random_pairs(606, 5, (3, 10), (3, 10))
     b.rcat[2] = 9

@@ -48,7 +48,11 @@ def _policy_schedule(arr, ql, rl, *, cells_per_us, batch_us, request_us, n, mem_
             if busy[w] is not None:
                 continue
             order = [0] if (w == 0 and workers > 1) else [1, 0]
-            c = next((k for k in order if pending[k] and admissible(fp[pending[k][0]], k, 0)), -1)
+            # a long head above the long share waits for an idle device, and
+            # no short batch starts meanwhile
+            drain = bool(pending[1]) and fp[pending[1][0]] > mem_budget // 4 * 3
+            c = next((k for k in order if pending[k] and not (k == 0 and drain)
+                      and admissible(fp[pending[k][0]], k, 0)), -1)
             if c < 0:
                 continue
             members, extra = [], 0
@@ -204,3 +208,32 @@ def test_simulator_rejects_bad_input():
     with pytest.raises(swx.SwxError) as ei:
         swx.simulate_serving([0.0], [-1], [10], cells_per_us=1.0)
     assert ei.value.status == SWX_EINVAL
+
+
+def test_long_request_above_its_share_runs_under_steady_short_traffic():
+    # a long request whose footprint exceeds the long share (3/4 of the budget)
+    # can only start on an idle device; short requests arrive faster than one
+    # batch lasts, so without the drain rule the device would never be idle
+    # before the arrivals stop
+    budget = 64 << 20
+    assert _footprint(10000, 20000, 4) > budget // 4 * 3
+    n_short = 4000
+    arr = list(np.arange(n_short) * 25.0)          # 0 .. 100 ms, one every 25 us
+    ql, rl = [150] * n_short, [1000] * n_short
+    arr.append(1000.0)
+    ql.append(10000)
+    rl.append(20000)
+    order = np.argsort(arr, kind="stable")
+    arr, ql, rl = np.asarray(arr)[order], np.asarray(ql)[order], np.asarray(rl)[order]
+    out, _ = swx.simulate_serving(arr, ql, rl, cells_per_us=5e5, batch_us=100.0,
+                                  mem_budget=budget, workers=3)
+    assert (out["status"] == 0).all()
+    k = int(np.nonzero(ql == 10000)[0][0])
+    assert out["batch_size"][k] == 1
+    # it starts within a few short batches of its arrival, long before the
+    # short arrivals end
+    assert out["start_us"][k] - arr[k] < 1000.0
+    assert out["start_us"][k] < arr[-1] / 10
+    # short requests keep being served after it starts
+    later = (arr > out["start_us"][k]) & (ql == 150)
+    assert (out["start_us"][later] < out["done_us"][k]).any()
