@@ -92,8 +92,11 @@ def recorded_traffic(pairs):
         return None
 
 
-def cpu_baseline(b, seconds):
-    """The oracle, unmodified, over a bounded sample of the workload."""
+def cpu_baseline(b, seconds, gpu_out=None):
+    """The oracle, unmodified, over a bounded sample of the workload.  With
+    gpu_out = (records, CIGAR arena) of the timed GPU run, the oracle's results
+    for the sample (the first pairs of the batch) are compared with them field
+    by field and CIGAR word by word, outside the timed region."""
     import numpy as np
 
     import oracle
@@ -106,13 +109,22 @@ def cpu_baseline(b, seconds):
     n = int(min(b.npairs, max(2000, seconds * rate / (b.cells() / b.npairs))))
     s = b.subset(np.arange(n))
     t = time.perf_counter()
-    oracle.align_many(s.qcat, s.qoff, s.rcat, s.roff, s.pair_q, s.pair_r, s.matrix,
-                      s.gap_open, s.gap_extend, nthreads=threads)
+    ref, rcig, rcoff = oracle.align_many(s.qcat, s.qoff, s.rcat, s.roff, s.pair_q, s.pair_r,
+                                         s.matrix, s.gap_open, s.gap_extend, nthreads=threads)
     dt = time.perf_counter() - t
-    return {"value": round(s.cells() / dt / 1e9, 4), "unit": "GCUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": f"first {n} pairs of the same workload ({s.cells()/1e9:.2f} G cells, "
-                      f"{dt:.1f} s, whole path incl. begin/CIGAR/score2)"}
+    out = {"value": round(s.cells() / dt / 1e9, 4), "unit": "GCUPS", "cores": threads,
+           "kind": "oracle",
+           "sample": f"first {n} pairs of the same workload ({s.cells()/1e9:.2f} G cells, "
+                     f"{dt:.1f} s, whole path incl. begin/CIGAR/score2)"}
+    parity = None
+    if gpu_out is not None:
+        from tests.fullsize import mismatches
+        recs, cig = gpu_out
+        bad = mismatches(recs[:n], cig, ref, rcig, rcoff)
+        parity = {"pairs": n, "mismatches": bad["pairs_bad"], "by_field": bad,
+                  "checked": "records and CIGARs of the last timed step (device-resident "
+                             "outputs) against the oracle on the same pairs"}
+    return out, parity
 
 
 _SERVE_POOL = {}
@@ -334,14 +346,20 @@ def main():
     fill_ms = []
     stages = None
     t0 = time.perf_counter()
+    step_used = []
     for k in range(args.steps):
-        step()
+        step_used.append(step())
         st_ms = ctx.stage_ms()
         fill_ms.append(st_ms[1])
         stages = st_ms if stages is None else [a + c for a, c in zip(stages, st_ms)]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     print(f"[bench] {args.steps} timed steps in {dt:.3f}s", flush=True, file=sys.stderr)
+    # the last timed step's outputs, kept for the parity check (later phases
+    # reuse the buffers)
+    last_used = step_used[-1]
+    gpu_out = (recs.cpu().numpy().view(swx.REC_DTYPE).copy(),
+               cig[:last_used].cpu().numpy().view(np.uint32).copy())
     ms_per_step = dt * 1e3 / args.steps
     value = cells * args.steps / dt / 1e9
     fill_avg = sum(fill_ms) / len(fill_ms)
@@ -443,7 +461,7 @@ def main():
         line["serving"] = [serving_phase(float(r), args.serve_seconds)
                            for r in str(args.serve_rate).split(",")]
     if not args.no_cpu and not args.headline_only:
-        line["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds)
+        line["cpu_baseline"], line["parity"] = cpu_baseline(b, args.cpu_seconds, gpu_out)
     print(json.dumps(line), flush=True)
 
 

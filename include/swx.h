@@ -121,21 +121,40 @@ int swx_profile_create(swx_ctx *ctx, const int8_t *query, int32_t qlen, const in
 int swx_profile_destroy(swx_profile *p);
 
 /* ---- one pair --------------------------------------------------------------
- * ref: [rlen] codes in host memory, or device memory when flags has
- * SWX_REF_DEVICE.  rlen == 0 is valid and yields "no alignment".  Synchronous:
- * returns when out is filled.  out->cigar is malloc'd by the library (NULL when
- * the CIGAR was not requested or is empty).  A pair of qlen <= 4096 and
- * rlen <= 65536 replays a graph of capacity one pair (the chain of
- * swx_graph_*, one pair spread over a wave) captured on first use for its
- * scoring scheme, flags, mask width and power-of-two size class and kept on
- * the context (at most 8, least recently used replaced); larger pairs take the
- * batch path.  Either way the result equals swx_align_batch's. */
+ * The paper's per-pair call (Results section, the library's API: a profile
+ * aligned against one reference returns the optimal score, the suboptimal
+ * score, both ends, both begins and the CIGAR; method section "Algorithm and
+ * implementation" for how each is found).
+ * p: a profile of this library (its context runs the call).  ref: [rlen]
+ * codes in host memory, or device memory of the context's GPU when flags has
+ * SWX_REF_DEVICE; the caller keeps ownership.  rlen == 0 is valid and yields
+ * "no alignment".  flags: SWX_BEGIN | SWX_CIGAR | SWX_SCORE2 (+ SWX_REF_DEVICE);
+ * mask_len as for swx_align_batch.  hip_stream: a hipStream_t of the
+ * context's device, or NULL for the context's own stream; the call's device
+ * work is queued on it, after whatever the caller queued there before (a
+ * device-resident ref may be written by that earlier work).  Synchronous:
+ * returns when out is filled (it waits for that stream, never for the whole
+ * device).  out->cigar is malloc'd by the library (NULL when the CIGAR was
+ * not requested or is empty; release with swx_result_free).  A pair of
+ * qlen <= 4096 and rlen <= 65536 replays a graph of capacity one pair (the
+ * chain of swx_graph_*, one pair spread over a wave) captured on first use
+ * for its scoring scheme, flags, mask width and power-of-two size class and
+ * kept on the context (at most 8, least recently used replaced); larger pairs
+ * take the batch path.  Either way the result equals swx_align_batch's.
+ * Errors: SWX_EINVAL (null p or out, rlen < 0, unknown flag bits, a symbol
+ * >= n: out untouched beyond being zeroed), SWX_EDEVICE, SWX_ENOMEM. */
 #define SWX_REF_DEVICE (1u << 8)
 int swx_align(const swx_profile *p, const int8_t *ref, int64_t rlen, uint32_t flags,
-              int32_t mask_len, swx_result *out);
+              int32_t mask_len, void *hip_stream, swx_result *out);
 void swx_result_free(swx_result *r);
 
 /* ---- many pairs ------------------------------------------------------------
+ * The per-pair computation of swx_align (method section "Algorithm and
+ * implementation": max array and end, reversed pass for the begin, banded
+ * pass for the CIGAR, masked max array for score2; Results section for the
+ * outputs), for many pairs in one call: the paper's callers align one query
+ * against many references (database search) or many reads against their
+ * windows (read mapping), which here share launches.
  * Queries and references are concatenated code arrays with offsets
  * (qoff[nq+1], roff[nr+1], non-decreasing, within [0, qcat_len] and
  * [0, rcat_len]); pair k aligns query pair_q[k] against reference pair_r[k].
@@ -168,8 +187,17 @@ typedef struct {
   swx_rec *sub_recs;   /* SWX_SUBOPT only; otherwise ignored (may be NULL) */
 } swx_batch_out;
 
-/* Aligns every pair.  Synchronous with respect to the host. */
-int swx_align_batch(swx_ctx *ctx, const swx_batch *b, swx_batch_out *out);
+/* Aligns every pair.  hip_stream: a hipStream_t of the context's device, or
+ * NULL for the context's own stream; every kernel and copy of the call is
+ * queued on it (side streams of the context fork from it and join back into
+ * it), after whatever the caller queued there before, so device-resident
+ * inputs may be written by that earlier work.  Synchronous with respect to
+ * the host: returns when the outputs are written (waiting for that stream,
+ * never for the whole device).  Errors: SWX_EINVAL (null pointers, negative
+ * counts, bad memory-space flag or flag bits, offsets, pair indices or
+ * symbols out of range), SWX_EOVERFLOW, SWX_ERANGE (records complete, CIGARs
+ * not copied), SWX_ENOMEM, SWX_EDEVICE, SWX_EINTERNAL. */
+int swx_align_batch(swx_ctx *ctx, const swx_batch *b, swx_batch_out *out, void *hip_stream);
 
 /* Upper bound on CIGAR words for a batch: sum over pairs of qlen + rlen + 1,
  * twice that with SWX_SUBOPT (host-memory batches only; returns -1 otherwise). */
@@ -263,10 +291,12 @@ typedef struct {   /* device buffers owned by the graph (valid until swx_graph_d
 } swx_graph_io;
 
 int swx_graph_create(swx_ctx *ctx, const swx_graph_cfg *cfg, swx_graph **out, swx_graph_io *io);
-/* One replay on the context's stream; returns when the outputs are ready. */
-int swx_graph_run(swx_graph *g);
+/* One replay on hip_stream (a hipStream_t of the context's device, or NULL for
+ * the context's own stream), after the work queued there before; returns when
+ * the outputs are ready (waiting for that stream only). */
+int swx_graph_run(swx_graph *g, void *hip_stream);
 /* The same chain issued kernel by kernel without the graph (for checking). */
-int swx_graph_run_eager(swx_graph *g);
+int swx_graph_run_eager(swx_graph *g, void *hip_stream);
 /* Copies a host-memory batch into the graph's input buffers, padding pair
  * slots past npairs with (query 0, reference nr), an empty reference: needs
  * npairs <= max_pairs, nq <= nq_cap, nr + 1 <= nr_cap, the code arrays

@@ -125,10 +125,11 @@ _SIGS = {
                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "swx_profile_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "swx_align": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
-                                 ctypes.c_uint32, ctypes.c_int32, ctypes.POINTER(SwxResult)]),
+                                 ctypes.c_uint32, ctypes.c_int32, ctypes.c_void_p,
+                                 ctypes.POINTER(SwxResult)]),
     "swx_result_free": (None, [ctypes.POINTER(SwxResult)]),
     "swx_align_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxBatch),
-                                       ctypes.POINTER(SwxBatchOut)]),
+                                       ctypes.POINTER(SwxBatchOut), ctypes.c_void_p]),
     "swx_cigar_bound": (ctypes.c_int64, [ctypes.POINTER(SwxBatch)]),
     "swx_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "swx_last_error": (ctypes.c_char_p, []),
@@ -137,8 +138,8 @@ _SIGS = {
     "swx_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxTuning)]),
     "swx_graph_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxGraphCfg),
                                         ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(SwxGraphIo)]),
-    "swx_graph_run": (ctypes.c_int, [ctypes.c_void_p]),
-    "swx_graph_run_eager": (ctypes.c_int, [ctypes.c_void_p]),
+    "swx_graph_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "swx_graph_run_eager": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "swx_graph_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxBatch)]),
     "swx_graph_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(SwxBatchOut)]),
     "swx_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
@@ -232,18 +233,27 @@ def decode_cigar(words) -> list:
     return [(int(w) >> 4, ops[int(w) & 0xF]) for w in words]
 
 
-def swx_align(profile: int, ref, flags: int = SWX_ALL, mask_len: int = -1):
+def _stream(stream):
+    """hipStream_t handle of a torch stream (or a raw handle); None: NULL."""
+    if stream is None:
+        return None
+    return int(getattr(stream, "cuda_stream", stream)) or None
+
+
+def swx_align(profile: int, ref, flags: int = SWX_ALL, mask_len: int = -1, stream=None):
     """Align one reference (numpy int8, or a device pointer with its length as a
-    tuple (ptr, rlen) and flags | SWX_REF_DEVICE).  Returns (record dict, cigar list)."""
+    tuple (ptr, rlen) and flags | SWX_REF_DEVICE) on `stream` (a torch stream,
+    a raw hipStream_t, or None for the context's own).  Returns (record dict,
+    cigar list)."""
     res = SwxResult()
     if isinstance(ref, tuple):
         ptr, rlen = ref
         st = lib().swx_align(profile, ctypes.c_void_p(ptr), int(rlen), int(flags),
-                             int(mask_len), ctypes.byref(res))
+                             int(mask_len), _stream(stream), ctypes.byref(res))
     else:
         r = np.ascontiguousarray(ref, dtype=np.int8)
         st = lib().swx_align(profile, r.ctypes.data if len(r) else None, len(r), int(flags),
-                             int(mask_len), ctypes.byref(res))
+                             int(mask_len), _stream(stream), ctypes.byref(res))
     _check(st, "swx_align")
     rec = {k: getattr(res.rec, k) for k, _ in SwxRec._fields_}
     cig = [res.cigar[k] for k in range(res.rec.cigar_len)] if res.rec.cigar_len else []
@@ -332,11 +342,13 @@ def swx_cigar_bound(matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r, flags=
 
 def swx_align_batch(ctx: int, matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r,
                     flags=SWX_ALL, mask_len=-1, in_mem=SWX_MEM_HOST, recs=None, cigar=None,
-                    out_mem=SWX_MEM_HOST, sub_recs=None):
+                    out_mem=SWX_MEM_HOST, sub_recs=None, stream=None):
     """Raw batch call.  Host-memory inputs are numpy arrays; device-memory
     inputs are torch tensors.  recs/cigar are caller-owned outputs (numpy
     structured array of REC_DTYPE and uint32 array on the host, or torch
-    tensors on the device).  Returns (status, cigar_used)."""
+    tensors on the device).  stream: a torch stream or raw hipStream_t the
+    call's work is queued on (None: the context's own).  Returns (status,
+    cigar_used)."""
     b, _m = _make_batch(matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r, flags, mask_len,
                         in_mem)
     out = SwxBatchOut()
@@ -346,7 +358,7 @@ def swx_align_batch(ctx: int, matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair
                         (len(cigar) if cigar is not None else 0))
     out.out_mem = int(out_mem)
     out.sub_recs = _ptr(sub_recs)
-    st = lib().swx_align_batch(ctx, ctypes.byref(b), ctypes.byref(out))
+    st = lib().swx_align_batch(ctx, ctypes.byref(b), ctypes.byref(out), _stream(stream))
     return st, int(out.cigar_used)
 
 
@@ -405,10 +417,10 @@ class Context:
     def set_tuning(self, **changes) -> None:
         swx_set_tuning(self.handle, **changes)
 
-    def align_pair(self, query, ref, matrix, o, e, flags=SWX_ALL, mask_len=-1):
+    def align_pair(self, query, ref, matrix, o, e, flags=SWX_ALL, mask_len=-1, stream=None):
         p = swx_profile_create(self.handle, query, matrix, o, e)
         try:
-            return swx_align(p, ref, flags, mask_len)
+            return swx_align(p, ref, flags, mask_len, stream)
         finally:
             swx_profile_destroy(p)
 
@@ -463,9 +475,9 @@ class Graph:
         _check(lib().swx_graph_load(self.handle, ctypes.byref(b)), "swx_graph_load")
         self.npairs = len(pair_q)
 
-    def run(self, eager=False):
+    def run(self, eager=False, stream=None):
         f = lib().swx_graph_run_eager if eager else lib().swx_graph_run
-        _check(f(self.handle), "swx_graph_run")
+        _check(f(self.handle, _stream(stream)), "swx_graph_run")
 
     def read(self):
         recs = np.zeros(self.npairs, dtype=REC_DTYPE)

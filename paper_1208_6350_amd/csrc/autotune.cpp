@@ -142,7 +142,7 @@ extern "C" int swx_autotune(swx_ctx *ctx, const swx_batch *b, int64_t max_pairs,
   if (cap < 0) {   // device inputs: size the CIGAR arena from a first run
     bo.cigar = nullptr;
     bo.cigar_cap = 0;
-    rc = swx_align_batch(ctx, &s, &bo);
+    rc = swx_align_batch(ctx, &s, &bo, nullptr);
     if (rc != SWX_OK && rc != SWX_ERANGE) return rc;
     cap = bo.cigar_used;
   }
@@ -155,7 +155,7 @@ extern "C" int swx_autotune(swx_ctx *ctx, const swx_batch *b, int64_t max_pairs,
     double best = 1e30;
     for (int k = 0; k < 3; ++k) {   // a warm-up, then the best of two
       const double t0 = now_s();
-      r = swx_align_batch(ctx, &s, &bo);
+      r = swx_align_batch(ctx, &s, &bo, nullptr);
       if (r) return r;
       const double dt = (now_s() - t0) * 1e3;
       if (k > 0 && dt < best) best = dt;

@@ -93,7 +93,8 @@ class DevArena {
 
 struct swx_ctx {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // the stream of the running call (own, or the caller's)
+  hipStream_t own = nullptr;      // the context's own stream
   swx::DevArena arena;
   std::mutex mu;
   hipEvent_t ev[8] = {};
@@ -142,6 +143,22 @@ struct swx_profile {
 };
 
 namespace swx {
+
+// Runs a call on the caller's stream: while it lives, ctx->stream names
+// `user` (when not null) instead of the context's own stream.  Every stage of
+// a call issues its work on ctx->stream, so the call is ordered after the
+// work the caller queued on that stream before it; side streams fork from it
+// and join back into it.  Callers hold ctx->mu.
+struct StreamScope {
+  swx_ctx *c;
+  hipStream_t saved;
+  StreamScope(swx_ctx *c_, void *user) : c(c_), saved(c_->stream) {
+    if (user) c->stream = (hipStream_t)user;
+  }
+  ~StreamScope() { c->stream = saved; }
+  StreamScope(const StreamScope &) = delete;
+  StreamScope &operator=(const StreamScope &) = delete;
+};
 
 struct Scoring {
   int32_t n, o, e, bias, smax;
@@ -1652,7 +1669,7 @@ static void release_ctx(swx_ctx *ctx) {
     if (ctx->join_ev[k]) (void)hipEventDestroy(ctx->join_ev[k]);
   }
   if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
-  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  if (ctx->own) (void)hipStreamDestroy(ctx->own);
   delete ctx;
 }
 
@@ -1666,10 +1683,11 @@ int swx_ctx_create(int device, swx_ctx **out) {
   swx_ctx *c = new (std::nothrow) swx_ctx();
   if (!c) return fail(SWX_ENOMEM, "host allocation failed");
   c->device = device;
-  if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&c->stream) != hipSuccess) {
+  if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&c->own) != hipSuccess) {
     release_ctx(c);
     return fail(SWX_EDEVICE, "could not create a stream");
   }
+  c->stream = c->own;
   for (auto &e : c->ev) {
     if (hipEventCreate(&e) != hipSuccess) {
       release_ctx(c);
@@ -1841,9 +1859,10 @@ static int align_batch_locked(swx_ctx *ctx, const swx_batch *b, swx_batch_out *o
   return run_pipeline(ctx, sc, db, b->flags, b->mask_len, out);
 }
 
-int swx_align_batch(swx_ctx *ctx, const swx_batch *b, swx_batch_out *out) {
+int swx_align_batch(swx_ctx *ctx, const swx_batch *b, swx_batch_out *out, void *hip_stream) {
   if (!ctx || !b || !out) return fail(SWX_EINVAL, "null argument");
   std::lock_guard<std::mutex> g(ctx->mu);
+  StreamScope ss(ctx, hip_stream);
   return align_batch_locked(ctx, b, out);
 }
 
@@ -1854,8 +1873,10 @@ static constexpr int32_t kPairGraphMaxQ = 4096;
 static constexpr int64_t kPairGraphMaxR = int64_t(1) << 16;
 static constexpr size_t kPairGraphs = 8;
 
+static int graph_run_on(swx_graph *gr, void *hip_stream);
+
 static int align_pair_graph(const swx_profile *p, int64_t rlen, uint32_t flags,
-                            int32_t mask_len, const swx_batch &b, swx_rec &rec,
+                            int32_t mask_len, const swx_batch &b, void *hip_stream, swx_rec &rec,
                             std::vector<uint32_t> &cig) {
   swx_ctx *ctx = p->ctx;
   const int64_t ql = (int64_t)p->query.size();
@@ -1896,14 +1917,14 @@ static int align_pair_graph(const swx_profile *p, int64_t rlen, uint32_t flags,
   }
   hit->last_use = ++ctx->pair_clock;
   int rc = swx_graph_load(hit->g, &b);
-  if (rc == SWX_OK) rc = swx_graph_run(hit->g);
+  if (rc == SWX_OK) rc = graph_run_on(hit->g, hip_stream);
   if (rc != SWX_OK) return rc;
   swx_batch_out bo{&rec, cig.data(), (int64_t)cig.size(), 0, SWX_MEM_HOST};
   return swx_graph_read(hit->g, 1, &bo);
 }
 
 int swx_align(const swx_profile *p, const int8_t *ref, int64_t rlen, uint32_t flags,
-              int32_t mask_len, swx_result *out) {
+              int32_t mask_len, void *hip_stream, swx_result *out) {
   if (!p || !out || (rlen > 0 && !ref)) return fail(SWX_EINVAL, "null argument");
   if (rlen < 0) return fail(SWX_EINVAL, "rlen must be >= 0");
   if (flags & ~(SWX_ALL | SWX_REF_DEVICE)) return fail(SWX_EINVAL, "unknown flag bits");
@@ -1913,8 +1934,17 @@ int swx_align(const swx_profile *p, const int8_t *ref, int64_t rlen, uint32_t fl
   const int8_t *rptr = ref;
   if (flags & SWX_REF_DEVICE) {
     href.resize((size_t)rlen);
-    if (rlen && hipMemcpy(href.data(), ref, (size_t)rlen, hipMemcpyDeviceToHost) != hipSuccess)
-      return fail(SWX_EDEVICE, "could not read the device reference");
+    // ordered after the caller's work on its stream (which may write ref)
+    if (rlen) {
+      if (hip_stream) {
+        if (hipMemcpyAsync(href.data(), ref, (size_t)rlen, hipMemcpyDeviceToHost,
+                           (hipStream_t)hip_stream) != hipSuccess ||
+            wait_stream((hipStream_t)hip_stream) != hipSuccess)
+          return fail(SWX_EDEVICE, "could not read the device reference");
+      } else if (hipMemcpy(href.data(), ref, (size_t)rlen, hipMemcpyDeviceToHost) != hipSuccess) {
+        return fail(SWX_EDEVICE, "could not read the device reference");
+      }
+    }
     rptr = href.data();
   }
   {
@@ -1929,7 +1959,7 @@ int swx_align(const swx_profile *p, const int8_t *ref, int64_t rlen, uint32_t fl
     b.flags = flags & SWX_ALL; b.mask_len = mask_len; b.in_mem = SWX_MEM_HOST;
     swx_rec rec{};
     std::vector<uint32_t> cig((size_t)(p->query.size() + rlen + 2));
-    const int rc = align_pair_graph(p, rlen, flags & SWX_ALL, mask_len, b, rec, cig);
+    const int rc = align_pair_graph(p, rlen, flags & SWX_ALL, mask_len, b, hip_stream, rec, cig);
     if (rc < 0) return rc;
     if (rc == SWX_OK) {
       out->rec = rec;
@@ -1944,6 +1974,7 @@ int swx_align(const swx_profile *p, const int8_t *ref, int64_t rlen, uint32_t fl
     }
   }
   std::lock_guard<std::mutex> g(ctx->mu);
+  StreamScope ss(ctx, hip_stream);
   const int64_t qoff[2] = {0, (int64_t)p->query.size()};
   const int64_t roff[2] = {0, rlen};
   const int64_t pq = 0, pr = 0;
@@ -2069,17 +2100,23 @@ static int graph_check(swx_graph *gr) {
   return SWX_OK;
 }
 
-int swx_graph_run(swx_graph *gr) {
-  if (!gr) return fail(SWX_EINVAL, "null argument");
+static int graph_run_on(swx_graph *gr, void *hip_stream) {
   std::lock_guard<std::mutex> lk(gr->ctx->mu);
+  StreamScope ss(gr->ctx, hip_stream);
   if (hipSetDevice(gr->ctx->device) != hipSuccess) return fail(SWX_EDEVICE, "hipSetDevice failed");
   HIP_TRY(hipGraphLaunch(gr->g.exec, gr->ctx->stream));
   return graph_check(gr);
 }
 
-int swx_graph_run_eager(swx_graph *gr) {
+int swx_graph_run(swx_graph *gr, void *hip_stream) {
+  if (!gr) return fail(SWX_EINVAL, "null argument");
+  return graph_run_on(gr, hip_stream);
+}
+
+int swx_graph_run_eager(swx_graph *gr, void *hip_stream) {
   if (!gr) return fail(SWX_EINVAL, "null argument");
   std::lock_guard<std::mutex> lk(gr->ctx->mu);
+  StreamScope ss(gr->ctx, hip_stream);
   if (hipSetDevice(gr->ctx->device) != hipSuccess) return fail(SWX_EDEVICE, "hipSetDevice failed");
   int rc = fixed_issue(gr->g, gr->ctx->stream);
   if (rc) return rc;

@@ -160,7 +160,7 @@ bool run_graph_batch(swx_server *s, swx_graph *g, std::vector<Req> &batch,
     bo.recs = recs.data(); bo.cigar = cig.data(); bo.cigar_cap = (int64_t)cig.size();
     bo.out_mem = SWX_MEM_HOST;
     int status = swx_graph_load(g, &b);
-    if (status == SWX_OK) status = swx_graph_run(g);
+    if (status == SWX_OK) status = swx_graph_run(g, nullptr);
     if (status == SWX_OK) status = swx_graph_read(g, n, &bo);
     const int64_t t_done = now_ns();
     for (int64_t k = 0; k < n; ++k) {
@@ -293,7 +293,7 @@ void run_batch(swx_server *s, swx_ctx *ctx, swx_graph *graph, std::vector<Req> &
       bo.cigar = cig.data();
       bo.cigar_cap = cig_cap;
       bo.out_mem = SWX_MEM_HOST;
-      status = swx_align_batch(ctx, &b, &bo);
+      status = swx_align_batch(ctx, &b, &bo, nullptr);
     }
   }
   const int64_t t_done = now_ns();

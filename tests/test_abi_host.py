@@ -62,7 +62,9 @@ def test_profile_argument_validation():
 def test_null_pointers_rejected():
     lib = swx.lib()
     assert lib.swx_ctx_create(0, None) == -1
-    assert lib.swx_align_batch(None, None, None) == -1
+    assert lib.swx_align_batch(None, None, None, None) == -1
+    assert lib.swx_align(None, None, 0, 0, -1, None, None) == -1
+    assert lib.swx_graph_run(None, None) == -1
     assert lib.swx_profile_destroy(None) == -1
     lib.swx_result_free(None)   # no-op
 

@@ -172,7 +172,18 @@ def test_graph_rejects_bad_contents(ctx):
     try:
         bad = a.rcat.copy()
         bad[3] = 9
-        g.load(a.qcat, a.qoff, bad, a.roff, a.pair_q, a.pair_r)
+        # a load checks the symbols on the host and leaves the buffers alone
+        with pytest.raises(swx.SwxError) as ei:
+            g.load(a.qcat, a.qoff, bad, a.roff, a.pair_q, a.pair_r)
+        assert ei.value.status == -1
+        g.load(a.qcat, a.qoff, a.rcat, a.roff, a.pair_q, a.pair_r)
+        g.run()
+        # a bad code written straight into the device buffer is found by the run
+        import ctypes
+        hip = ctypes.CDLL("libamdhip64.so")
+        hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        nine = (ctypes.c_int8 * 1)(9)
+        assert hip.hipMemcpy(ctypes.c_void_p(g.io.rcat + 3), ctypes.addressof(nine), 1, 1) == 0
         with pytest.raises(swx.SwxError) as ei:
             g.run()
         assert ei.value.status == -1
