@@ -199,6 +199,27 @@ typedef struct {
  * not copied), SWX_ENOMEM, SWX_EDEVICE, SWX_EINTERNAL. */
 int swx_align_batch(swx_ctx *ctx, const swx_batch *b, swx_batch_out *out, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * alignments as swx_align_batch (same arguments, same results), with every
+ * scratch buffer of the call taken from one static device array of
+ * SWX_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends.  The call makes no hipMalloc, hipFree, stream or
+ * other allocating library call; the caller still provides the inputs and
+ * outputs.  Side streams are not used.  All calls on one GPU share that
+ * GPU's array and run one at a time (a call returns only after its device
+ * work is done; overlapping calls from other threads wait); the array keeps
+ * the last call's contents, and every call clears what it needs.  Limits:
+ * npairs <= SWX_NOALLOC_MAX_PAIRS and, for host-memory inputs, the staged
+ * inputs within half of the array (SWX_EINVAL otherwise, before any device
+ * work); a batch whose work needs more scratch than the array fails with
+ * SWX_ENOMEM (outputs then undefined).  About 4,000 pairs of 250 x 650 fit.
+ * hip_stream: as for swx_align_batch. */
+#define SWX_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define SWX_NOALLOC_MAX_PAIRS 65536
+int swx_align_batch_noalloc(swx_ctx *ctx, const swx_batch *b, swx_batch_out *out,
+                            void *hip_stream);
+
 /* Upper bound on CIGAR words for a batch: sum over pairs of qlen + rlen + 1,
  * twice that with SWX_SUBOPT (host-memory batches only; returns -1 otherwise). */
 int64_t swx_cigar_bound(const swx_batch *b);

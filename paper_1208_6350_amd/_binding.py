@@ -130,6 +130,8 @@ _SIGS = {
     "swx_result_free": (None, [ctypes.POINTER(SwxResult)]),
     "swx_align_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxBatch),
                                        ctypes.POINTER(SwxBatchOut), ctypes.c_void_p]),
+    "swx_align_batch_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxBatch),
+                                               ctypes.POINTER(SwxBatchOut), ctypes.c_void_p]),
     "swx_cigar_bound": (ctypes.c_int64, [ctypes.POINTER(SwxBatch)]),
     "swx_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "swx_last_error": (ctypes.c_char_p, []),
@@ -349,6 +351,22 @@ def swx_align_batch(ctx: int, matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair
     tensors on the device).  stream: a torch stream or raw hipStream_t the
     call's work is queued on (None: the context's own).  Returns (status,
     cigar_used)."""
+    return _batch_call(lib().swx_align_batch, ctx, matrix, o, e, qcat, qoff, rcat, roff, pair_q,
+                       pair_r, flags, mask_len, in_mem, recs, cigar, out_mem, sub_recs, stream)
+
+
+def swx_align_batch_noalloc(ctx: int, matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r,
+                            flags=SWX_ALL, mask_len=-1, in_mem=SWX_MEM_HOST, recs=None,
+                            cigar=None, out_mem=SWX_MEM_HOST, stream=None):
+    """The batch call that allocates no device memory (its scratch is the
+    library's static per-GPU array).  Arguments as swx_align_batch."""
+    return _batch_call(lib().swx_align_batch_noalloc, ctx, matrix, o, e, qcat, qoff, rcat, roff,
+                       pair_q, pair_r, flags, mask_len, in_mem, recs, cigar, out_mem, None,
+                       stream)
+
+
+def _batch_call(fn, ctx, matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r, flags, mask_len,
+                in_mem, recs, cigar, out_mem, sub_recs, stream):
     b, _m = _make_batch(matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r, flags, mask_len,
                         in_mem)
     out = SwxBatchOut()
@@ -358,7 +376,7 @@ def swx_align_batch(ctx: int, matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair
                         (len(cigar) if cigar is not None else 0))
     out.out_mem = int(out_mem)
     out.sub_recs = _ptr(sub_recs)
-    st = lib().swx_align_batch(ctx, ctypes.byref(b), ctypes.byref(out), _stream(stream))
+    st = fn(ctx, ctypes.byref(b), ctypes.byref(out), _stream(stream))
     return st, int(out.cigar_used)
 
 

@@ -40,13 +40,24 @@ static int fail(int code, const std::string &msg) {
 // Bump allocation from large blocks that are kept across calls; reset() makes
 // the whole pool reusable.  Calls on one context are serialised, so a reset at
 // the start of a call cannot free memory that a running call still uses.
+// In fixed mode (use_fixed) every allocation comes from one given block and
+// nothing is ever allocated from the device: a request past its end fails.
 class DevArena {
  public:
   ~DevArena() { release(); }
   void reset() {
     cur_ = 0;
     off_ = 0;
+    fixed_off_ = 0;
   }
+  void use_fixed(void *p, size_t bytes) {
+    fixed_ = p;
+    fixed_size_ = bytes;
+    fixed_off_ = 0;
+    fixed_short_ = false;
+  }
+  void use_pool() { fixed_ = nullptr; }
+  bool fixed_exhausted() const { return fixed_short_; }
   void release() {
     for (auto &b : blocks_) (void)hipFree(b.ptr);
     blocks_.clear();
@@ -57,6 +68,15 @@ class DevArena {
   void *alloc(size_t bytes) {
     bytes = (bytes + 255) & ~size_t(255);
     if (bytes == 0) bytes = 256;
+    if (fixed_) {
+      if (bytes > fixed_size_ - fixed_off_) {
+        fixed_short_ = true;
+        return nullptr;
+      }
+      void *p = (char *)fixed_ + fixed_off_;
+      fixed_off_ += bytes;
+      return p;
+    }
     while (cur_ < blocks_.size()) {
       Block &b = blocks_[cur_];
       if (off_ + bytes <= b.size) {
@@ -87,7 +107,34 @@ class DevArena {
   };
   std::vector<Block> blocks_;
   size_t cur_ = 0, off_ = 0;
+  void *fixed_ = nullptr;
+  size_t fixed_size_ = 0, fixed_off_ = 0;
+  bool fixed_short_ = false;
 };
+
+// ---- static scratch of the entry point that allocates nothing ---------------
+// One array per GPU (each device holds its own copy of a __device__ variable),
+// kept until the process ends.  Host code never uses its name as an address:
+// the device address comes from hipGetSymbolAddress, taken once per device
+// with that device current (at the first context made on it).
+static __device__ __align__(256) uint8_t scratch[SWX_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_use[kMaxDevices];   // one call at a time per device
+
+// the device address of `scratch` on `device` (current), or nullptr
+static void *scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
 
 }  // namespace swx
 
@@ -133,6 +180,7 @@ struct swx_ctx {
   // pinned landing area of the small device-to-host reads between stages
   static constexpr int64_t kPinned = 512;   // int64 values
   int64_t *pinned = nullptr;
+  void *scratch = nullptr;   // this device's static scratch (swx_align_batch_noalloc)
 };
 
 struct swx_profile {
@@ -1707,6 +1755,11 @@ int swx_ctx_create(int device, swx_ctx **out) {
     release_ctx(c);
     return fail(SWX_EDEVICE, "could not query the device or allocate the work queue");
   }
+  c->scratch = scratch_address(device);
+  if (!c->scratch) {
+    release_ctx(c);
+    return fail(SWX_EDEVICE, "could not find the device address of the static scratch");
+  }
   *out = c;
   return SWX_OK;
 }
@@ -1864,6 +1917,43 @@ int swx_align_batch(swx_ctx *ctx, const swx_batch *b, swx_batch_out *out, void *
   std::lock_guard<std::mutex> g(ctx->mu);
   StreamScope ss(ctx, hip_stream);
   return align_batch_locked(ctx, b, out);
+}
+
+int swx_align_batch_noalloc(swx_ctx *ctx, const swx_batch *b, swx_batch_out *out,
+                            void *hip_stream) {
+  if (!ctx || !b || !out) return fail(SWX_EINVAL, "null argument");
+  if (b->npairs > SWX_NOALLOC_MAX_PAIRS)
+    return fail(SWX_EINVAL, "batch above SWX_NOALLOC_MAX_PAIRS pairs");
+  // host-memory inputs are staged in the scratch too
+  if (b->in_mem == SWX_MEM_HOST) {
+    const int64_t staged = b->qcat_len + b->rcat_len + 8 * (b->nq + b->nr + 2 + 2 * b->npairs);
+    if (staged < 0 || staged > (int64_t)SWX_NOALLOC_SCRATCH_BYTES / 2)
+      return fail(SWX_EINVAL, "inputs above half of the static scratch (SWX_NOALLOC_SCRATCH_BYTES)");
+  }
+  if (!ctx->scratch || ctx->device < 0 || ctx->device >= kMaxDevices)
+    return fail(SWX_EDEVICE, "no static scratch on this device");
+  std::lock_guard<std::mutex> dev(g_scratch_use[ctx->device]);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  StreamScope ss(ctx, hip_stream);
+  struct Restore {   // pool mode and side streams as they were, whatever happens
+    swx_ctx *c;
+    bool side;
+    ~Restore() {
+      c->arena.use_pool();
+      c->side_streams = side;
+    }
+  } restore{ctx, ctx->side_streams};
+  ctx->arena.use_fixed(ctx->scratch, SWX_NOALLOC_SCRATCH_BYTES);
+  ctx->side_streams = false;   // making side streams would allocate
+  int rc = align_batch_locked(ctx, b, out);
+  const bool short_of_scratch = ctx->arena.fixed_exhausted();
+  // the scratch is free for the next call only once this call's work is done
+  if (wait_stream(ctx->stream) != hipSuccess && rc == SWX_OK)
+    rc = fail(SWX_EDEVICE, "stream wait failed");
+  if (rc == SWX_ENOMEM && short_of_scratch)
+    rc = fail(SWX_ENOMEM, "the batch needs more device scratch than the static "
+                          "SWX_NOALLOC_SCRATCH_BYTES; split it or use swx_align_batch");
+  return rc;
 }
 
 // The one-pair call through a cached graph (intra route: the pair spread over
