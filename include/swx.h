@@ -253,13 +253,17 @@ typedef struct {
                             ascending): 0 in that order, one wave per task; 1 largest
                             first (default); 2 a grid of resident waves taking tasks
                             largest first from a device work queue */
-  int32_t pad_;          /* must be 0 */
+  int32_t fill_coop;     /* 0 (default): a pass with fewer tasks than the device holds
+                            waves runs each task on the four waves of a workgroup, which
+                            take its strips round robin (a strip follows the one above
+                            column group by column group); 1: never; 2: always */
 } swx_tuning;
 int swx_get_tuning(const swx_ctx *ctx, swx_tuning *out);
 int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t);
 
 /* Autotuner: runs the first min(npairs, max_pairs) pairs of b under candidate
- * settings of each knob in turn (fill_rows, long_cells, intra_jobs, side_streams, fill_sched;
+ * settings of each knob in turn (fill_rows, long_cells, intra_jobs, side_streams, fill_sched,
+ * fill_coop;
  * each timed as the best of two runs after a warm-up, a change kept only if
  * at least 3% faster), installs the fastest in ctx and returns it in *out.
  * cache_path (may be NULL) names a text file of one JSON object per line,

@@ -79,19 +79,45 @@ __device__ __forceinline__ uint32_t word_of(const uint4 &v, int k) {
 // 168 (three waves) for shorter strips.
 template <int R> constexpr int fill_waves() { return R >= 32 ? 2 : 3; }
 
+// Shared state of a cooperative task: the four waves of a workgroup take the
+// strips of one task round robin, strip s starting on a column group once
+// strip s - 1 has stored that group of the boundary planes (in place: every
+// strip reads a group before it writes it, in strip order).
+struct CoopShared {
+  int32_t prog[kCoopMaxStrips];            // strip s stored groups [0, prog & ~bit31); bit 31: done
+  int64_t reach[kSlots16];                 // reversed pass: earliest column reaching the target
+  int32_t mval[kCoopWaves][kSlots16];      // per-wave partial results, merged at the end
+  int32_t mrow[kCoopWaves][kSlots16];
+  int64_t mcol[kCoopWaves][kSlots16];
+  int64_t task;                            // queued scheduling: the workgroup's task
+};
+constexpr int32_t kStripDone = (int32_t)0x80000000u;
+constexpr int64_t kCoopSpinLimit = int64_t(1) << 26;
+
 // One task (up to 64 or 128 pairs) on one wave: every strip, column group by
 // column group.  tid is uniform across the wave, so the task and everything
 // derived from it (bounds, plane addresses) live in SGPRs.
-template <class V, int R, uint32_t MODE, bool CLAMP, bool REV>
+template <class V, int R, uint32_t MODE, bool CLAMP, bool REV, bool COOP>
 __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid,
-                                           const uint32_t *s_lut) {
+                                           const uint32_t *s_lut, CoopShared *cs, int wave) {
   using T = VT<V>;
   constexpr int NH = T::kHalves;
   const int lane = threadIdx.x & 63;
   const InterTask tk = a.tasks[tid];
-  if (tk.nslots == 0) return;   // an empty task of a fixed-capacity plan
+  if (tk.nslots == 0) return;   // an empty task of a fixed-capacity plan (uniform per workgroup)
   constexpr bool rev = REV;
   const int nstrips = (tk.qp + R - 1) / R;
+  // cooperative task: this wave's strips are s_first, s_first + s_step, ...
+  constexpr bool coop = COOP;
+  const bool sync = coop && nstrips <= kCoopMaxStrips;
+  int s_first = 0, s_step = 1, s_end = nstrips;
+  if (sync) {
+    s_first = wave;
+    s_step = kCoopWaves;
+  } else if (coop && wave != 0) {
+    s_end = 0;   // too many strips to pipeline: wave 0 takes the whole task
+  }
+  bool spin_fail = false;
   // forward passes only: the last strip has R / 2 rows (a reversed pass,
   // padded at the bottom, runs its last strip full: the extra rows are padding)
   const bool half_tail = !REV && (tk.qp % R) != 0;
@@ -143,10 +169,54 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
   const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
 
   int64_t plo = 0, phi = 0;  // column window of the previous strip (multiples of 4)
-  for (int s = 0; s < nstrips; ++s) {
+  for (int s = s_first; s < s_end; s += s_step) {
     const int sR = s * R;
+    // cooperative: progress of strip s - 1 (groups known stored; done)
+    int32_t avail = 0;
+    bool pdone = (s == 0);
+    auto wait_prev = [&](int64_t g) {
+      if (!sync || pdone || g < avail) return;
+      int64_t spins = 0;
+      for (;;) {
+        const int32_t v = __hip_atomic_load(&cs->prog[s - 1], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+        avail = v & ~kStripDone;
+        pdone = (v & kStripDone) != 0;
+        if (pdone || g < avail) break;
+        if (++spins > kCoopSpinLimit) {   // never expected: fail the task's pairs, go on
+          spin_fail = true;
+          pdone = true;
+          avail = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    };
+    auto publish = [&](int64_t groups, bool fin) {
+      if (!sync) return;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if (lane == 0)
+        __hip_atomic_store(&cs->prog[s], (int32_t)groups | (fin ? kStripDone : 0),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
     int64_t clo = 0, chi = rp;
     if (rev) {
+      if (sync) {   // earliest columns reached by strips above, as far as known now
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          const int64_t r = __hip_atomic_load(&cs->reach[lane + 64 * h], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (r < reach[h]) reach[h] = r;
+        }
+        // the previous strip's window start (its end comes with its progress)
+        plo = 0;
+        if (s > 0 && tk.band >= 0) {
+          plo = (int64_t)(s - 1) * R - tk.band_q;
+          if (plo < 0) plo = 0;
+          plo &= ~(int64_t)3;
+        }
+      }
       if (tk.band >= 0) {
         clo = sR - tk.band_q; if (clo < 0) clo = 0;
         const int64_t c2 = (int64_t)sR + R + tk.band;
@@ -162,7 +232,11 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
       clo &= ~(int64_t)3;
       chi = (chi + 3) & ~(int64_t)3;
       if (chi > rp) chi = rp;
-      if (clo >= chi) break;   // later strips have even later windows
+      if (clo >= chi) {   // later strips have even later windows
+        if (!sync) break;
+        publish(0, true);   // nothing stored: the strip below reads zeros
+        continue;
+      }
     }
 
     // per-row byte selectors (QSEL): query symbol of each half, 0x0C = pad
@@ -185,8 +259,13 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
 #pragma unroll
     for (int r = 0; r < R; ++r) { H[r] = T::zero(); E[r] = T::zero(); }
     V hdtop = T::zero();
-    if (s > 0 && clo >= 1 && clo - 1 >= plo && clo - 1 < phi)
+    if (sync && s > 0 && clo >= 1) {
+      wait_prev((clo - 1) >> 2);
+      if (clo - 1 >= plo && ((clo - 1) >> 2) < avail)
+        hdtop = T::from(reinterpret_cast<const uint32_t *>(bH)[bnd_index(clo - 1, lane)]);
+    } else if (s > 0 && clo >= 1 && clo - 1 >= plo && clo - 1 < phi) {
       hdtop = T::from(reinterpret_cast<const uint32_t *>(bH)[bnd_index(clo - 1, lane)]);
+    }
     // anchored reversed pass: the corner before the first cell holds
     // `anchor` and the row above the first row the gap run that leaves it;
     // every other border starts from zero, far below, so only alignments that
@@ -210,8 +289,15 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
     uint2 nsy;
     auto fetch_group = [&](int64_t g) {
       // forward strips all span every column, so only the first strip lacks a
-      // row above; reversed strips use column windows
-      const bool inprev = rev ? ((s > 0) && (4 * g >= plo) && (4 * g < phi)) : (s > 0);
+      // row above; reversed strips use column windows.  Cooperative: wait
+      // until the strip above has stored the group (or finished short of it).
+      bool inprev;
+      if (sync) {
+        wait_prev(g);
+        inprev = (s > 0) && (!rev || 4 * g >= plo) && (g < avail);
+      } else {
+        inprev = rev ? ((s > 0) && (4 * g >= plo) && (4 * g < phi)) : (s > 0);
+      }
       const int64_t gi = g * 64 + lane;
       nsy = rsym[gi];
       nh = inprev ? bH[gi] : zero4;
@@ -265,6 +351,9 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
       constexpr int NR = decltype(nr)::value;
   #pragma unroll 1
       for (int64_t g = g0; g < g1; ++g) {
+        // groups before g - 1 are stored (their stores precede the loads of
+        // group g, which the release below waits for)
+        if (sync && g > g0) publish(g - 1, false);
         const uint4 ch = nh, cf = nf, cc = nc;
         const uint2 sy = nsy;
         if constexpr (kDelay) flush();
@@ -388,6 +477,7 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
       run_groups(std::integral_constant<int, R>{});
     }
     if constexpr (kDelay) flush();   // the strip's last group, before the next strip reads it
+    publish(cdone >> 2, true);
     // merge the strip best into the pair best (earlier strips win ties)
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
@@ -398,11 +488,52 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
         if (v > bval[h] || (v == bval[h] && col < bcol[h])) {
           bval[h] = v; brow[h] = row; bcol[h] = col;
         }
-        if (rev && v >= tgt[h] && sbcol[h] < reach[h]) reach[h] = sbcol[h];
+        if (rev && v >= tgt[h] && sbcol[h] < reach[h]) {
+          reach[h] = sbcol[h];
+          if (sync)
+            __hip_atomic_fetch_min(&cs->reach[lane + 64 * h], (int64_t)sbcol[h], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
       }
     }
     plo = clo;
     phi = cdone;
+  }
+
+  if constexpr (coop) {
+    // merge the waves' partial results: largest value, then smallest column,
+    // then smallest row (the order a single wave's strip-by-strip merge gives)
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      cs->mval[wave][lane + 64 * h] = bval[h];
+      cs->mrow[wave][lane + 64 * h] = brow[h];
+      cs->mcol[wave][lane + 64 * h] = bcol[h];
+    }
+    if (spin_fail) {
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+        if (pid[h] >= 0 && a.out.err) a.out.err[pid[h]] = 1;
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        for (int w = 1; w < kCoopWaves; ++w) {
+          const int32_t v = cs->mval[w][lane + 64 * h];
+          const int32_t r = cs->mrow[w][lane + 64 * h];
+          const int64_t c = cs->mcol[w][lane + 64 * h];
+          if (v > bval[h] || (v == bval[h] && v > 0 && (c < bcol[h] || (c == bcol[h] && r < brow[h])))) {
+            bval[h] = v; brow[h] = r; bcol[h] = c;
+          }
+        }
+      }
+    }
+    __syncthreads();   // the shared state is reused by the workgroup's next task
+    if (wave != 0) return;
+  } else if (spin_fail) {
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+      if (pid[h] >= 0 && a.out.err) a.out.err[pid[h]] = 1;
   }
 
   constexpr int32_t limit = (NH == 2) ? kInter16Limit : (1 << 26) - 1;
@@ -422,25 +553,38 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
 // them largest first, 2 keeps a grid of resident waves that take tasks
 // largest first from a device counter (a work queue: one 64-bit atomic per
 // task) until it runs past the last task.
-template <class V, int R, uint32_t MODE, bool CLAMP, bool REV>
+template <class V, int R, uint32_t MODE, bool CLAMP, bool REV, bool COOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fill_waves<R>()))) void k_inter_fill(
     InterArgs a) {
+  struct NoShared {};
   __shared__ uint32_t s_lut[8];
+  __shared__ std::conditional_t<COOP, CoopShared, NoShared> s_coop;
+  CoopShared *csp = nullptr;
+  if constexpr (COOP) csp = &s_coop;
   if (threadIdx.x < 8) s_lut[threadIdx.x] = a.lut[threadIdx.x];
   __syncthreads();
   const bool queued = a.sched == 2;
-  int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) +
-              __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  constexpr bool coop = COOP;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  // one task per wave, or (cooperative) one task per workgroup
+  int64_t k = coop ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
   for (;;) {   // one pass unless queued (a single call site keeps one copy of the body)
-    if (queued) {
+    if constexpr (coop) {
+      if (queued && threadIdx.x == 0) s_coop.task = (int64_t)atomicAdd(a.queue, 1ull);
+      for (int i = threadIdx.x; i < kCoopMaxStrips; i += blockDim.x) s_coop.prog[i] = 0;
+      for (int i = threadIdx.x; i < kSlots16; i += blockDim.x) s_coop.reach[i] = kNoReach;
+      __syncthreads();
+      if (queued) k = s_coop.task;
+    } else if (queued) {
       unsigned long long t = 0;
       if ((threadIdx.x & 63) == 0) t = atomicAdd(a.queue, 1ull);
       const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)t);
       const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(t >> 32));
       k = (int64_t)(((uint64_t)hi << 32) | lo);
     }
-    if (k >= a.ntasks) return;
-    inter_task<V, R, MODE, CLAMP, REV>(a, a.sched == 0 ? k : a.ntasks - 1 - k, s_lut);
+    if (k >= a.ntasks) return;   // uniform per workgroup in the cooperative mode
+    inter_task<V, R, MODE, CLAMP, REV, COOP>(a, a.sched == 0 ? k : a.ntasks - 1 - k, s_lut, csp,
+                                             wave);
     if (!queued) return;
   }
 }
@@ -557,7 +701,8 @@ __global__ __launch_bounds__(256) void k_inter_prof(PackArgs a) {
 template <class V, int R, uint32_t MODE>
 static hipError_t launch_fill(const InterArgs &a, hipStream_t st) {
   const int waves_per_block = 4;
-  int64_t blocks = (a.ntasks + waves_per_block - 1) / waves_per_block;
+  if (a.coop != 1 && a.coop != kCoopWaves) return hipErrorInvalidValue;
+  int64_t blocks = a.coop > 1 ? a.ntasks : (a.ntasks + waves_per_block - 1) / waves_per_block;
   if (blocks == 0) return hipSuccess;
   if (a.sched == 2) {
     if (!a.queue || a.cus < 1) return hipErrorInvalidValue;
@@ -567,12 +712,23 @@ static hipError_t launch_fill(const InterArgs &a, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, st, a.queue);
   }
   const dim3 g((unsigned)blocks), b(64 * waves_per_block);
+  const bool coop = a.coop > 1;
   if (a.rev) {
-    if (a.clamp) hipLaunchKernelGGL((k_inter_fill<V, R, MODE, true, true>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((k_inter_fill<V, R, MODE, false, true>), g, b, 0, st, a);
+    if (a.clamp) {
+      if (coop) hipLaunchKernelGGL((k_inter_fill<V, R, MODE, true, true, true>), g, b, 0, st, a);
+      else hipLaunchKernelGGL((k_inter_fill<V, R, MODE, true, true, false>), g, b, 0, st, a);
+    } else {
+      if (coop) hipLaunchKernelGGL((k_inter_fill<V, R, MODE, false, true, true>), g, b, 0, st, a);
+      else hipLaunchKernelGGL((k_inter_fill<V, R, MODE, false, true, false>), g, b, 0, st, a);
+    }
   } else {
-    if (a.clamp) hipLaunchKernelGGL((k_inter_fill<V, R, MODE, true, false>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((k_inter_fill<V, R, MODE, false, false>), g, b, 0, st, a);
+    if (a.clamp) {
+      if (coop) hipLaunchKernelGGL((k_inter_fill<V, R, MODE, true, false, true>), g, b, 0, st, a);
+      else hipLaunchKernelGGL((k_inter_fill<V, R, MODE, true, false, false>), g, b, 0, st, a);
+    } else {
+      if (coop) hipLaunchKernelGGL((k_inter_fill<V, R, MODE, false, false, true>), g, b, 0, st, a);
+      else hipLaunchKernelGGL((k_inter_fill<V, R, MODE, false, false, false>), g, b, 0, st, a);
+    }
   }
   return hipGetLastError();
 }

@@ -154,6 +154,7 @@ struct swx_ctx {
   int64_t intra_jobs = 2048;               // target column chunks over all long pairs
   int32_t fill_rows = 32;                  // strip height of the batched fill
   int32_t fill_sched = 1;                  // task order of the batched fill (InterArgs::sched)
+  int32_t fill_coop = 0;                   // cooperative tasks: 0 automatic, 1 never, 2 always
   int32_t cus = 0;                         // compute units of the device
   unsigned long long *queue = nullptr;     // work-queue counter of the batched fill
   // side streams (default priority) for independent kernels of one stage
@@ -256,6 +257,16 @@ struct Plan {
 };
 
 static inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Waves per task of a batched fill pass: a pass with fewer tasks than the
+// device holds waves (two per SIMD) leaves SIMDs idle and makes its largest
+// task the critical path, so its tasks run on a workgroup's four waves each.
+static int coop_waves(int32_t policy, int64_t ntasks, int32_t cus) {
+  if (policy == 1) return 1;
+  if (policy == 2) return kCoopWaves;
+  return ntasks < (int64_t)cus * 4 * 2 ? kCoopWaves : 1;
+}
+
 
 // Wait for a stream by polling it.  A blocking wait sleeps until an interrupt
 // wakes the thread, tens of microseconds after the stream has drained, and
@@ -380,6 +391,7 @@ static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &v
   a.queue = ctx->queue;
   a.anchor = anchor;
   a.lastcol = lastcol;
+  a.coop = coop_waves(ctx->fill_coop, pl.ntasks, ctx->cus);
   if (mark_fill >= 0) HIP_TRY(hipEventRecord(ctx->ev[mark_fill], st));
   HIP_TRY(inter_fill(a, pl.lane_bits, pl.R, st));
   if (mark_fill >= 0) HIP_TRY(hipEventRecord(ctx->ev[mark_fill + 1], st));
@@ -987,7 +999,7 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
   if (score_bound >= (1 << 26) - 1)
     return fail(SWX_EOVERFLOW, "a score could exceed the 32-bit lane range");
   PairView fview{qstart, rstart, qlen, rlen, b.qcat, b.rcat, 0};
-  FillOut fout{score, qend, rend, ovf};
+  FillOut fout{score, qend, rend, ovf, err};
 
   // long pairs take the intra-sequence path, the rest the batched one
   LongPath lp;
@@ -1032,7 +1044,7 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
     if (lp.nlong > 0) HIP_TRY(clear_flags(lp.nlong, lp.d_long, f16, f32, st));
     HIP_TRY(hipMemsetAsync(rsc, 0, sizeof(int32_t) * np, st));
     PairView rview{rqs, rrs, rql, rrl, b.qcat, b.rcat, 1};
-    FillOut rout{rsc, rqe, rre, rov};
+    FillOut rout{rsc, rqe, rre, rov, err};
     // both lane widths' pair lists first, their counts in one read, so that
     // no read waits for a queued fill
     int64_t *rids[2] = {nullptr, nullptr}, rcnt[2] = {0, 0};
@@ -1134,7 +1146,7 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
       Plan pw;
       if ((rc = plan_pass(ctx, sc, ids, cnt, qlen, wrl, nullptr, nullptr, 32, R, pw))) return rc;
       PairView wview{qstart, wrs, qlen, wrl, b.qcat, b.rcat, 0};
-      FillOut wout{wsc, wqe, wre, wov};
+      FillOut wout{wsc, wqe, wre, wov, err};
       if ((rc = run_fill(ctx, pw, sc, wview, false, nullptr, wout, score_bound, -1, 0, 1)))
         return rc;
     }
@@ -1146,7 +1158,7 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
       Plan pr;
       if ((rc = plan_pass(ctx, sc, ids, cnt, rql, rrl, nullptr, nullptr, 32, R, pr))) return rc;
       PairView rview{rqs, rrs, rql, rrl, b.qcat, b.rcat, 1};
-      FillOut rout{rsc, rqe, rre, rov};
+      FillOut rout{rsc, rqe, rre, rov, err};
       if ((rc = run_fill(ctx, pr, sc, rview, true, tgt, rout, score_bound + kAnchor, -1, kAnchor,
                          0)))
         return rc;
@@ -1243,6 +1255,7 @@ struct FixedTb {   // one traceback class
 struct GraphState {
   swx_graph_cfg cfg{};
   int32_t fill_sched = 1, cus = 0;    // the creating context's fill schedule
+  int32_t fill_coop = 0;
   unsigned long long *queue = nullptr;
   std::vector<int8_t> matrix;
   Scoring sc{};
@@ -1365,6 +1378,7 @@ static int fixed_fill(GraphState &g, FixedPlan &pl, const int64_t *ids, const in
   a.sched = g.fill_sched;
   a.cus = g.cus;
   a.queue = g.queue;
+  a.coop = coop_waves(g.fill_coop, pl.ntasks, g.cus);
   HIP_TRY(inter_fill(a, pl.lane_bits, pl.R, st));
   return SWX_OK;
 }
@@ -1397,7 +1411,7 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
                          g.rlen, st));
   }
   PairView fview{g.qstart, g.rstart, g.qlen, g.rlen, g.qcat, g.rcat, 0};
-  FillOut fout{g.score, g.qend, g.rend, g.ovf};
+  FillOut fout{g.score, g.qend, g.rend, g.ovf, g.err};
   IntraArgs ia{};
   if (g.intra) {
     HIP_TRY(fill_u8(4 * B * g.RM, (uint8_t *)g.maxcol, 0, st));
@@ -1431,7 +1445,7 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
                         g.band_q, g.f16, g.f32, st));
     HIP_TRY(fill_u8(4 * B, (uint8_t *)g.rsc, 0, st));
     PairView rview{g.rqs, g.rrs, g.rql, g.rrl, g.qcat, g.rcat, 1};
-    FillOut rout{g.rsc, g.rqe, g.rre, g.rov};
+    FillOut rout{g.rsc, g.rqe, g.rre, g.rov, g.err};
     if (g.intra) {
       HIP_TRY(intra_rev_jobs_fixed(B, g.score, g.rend, g.band, g.kbits, g.bnd_stride, g.rjobs, st));
       IntraArgs ra = ia;
@@ -1683,6 +1697,7 @@ int swx_get_tuning(const swx_ctx *ctx, swx_tuning *out) {
   t.fill_rows = ctx->fill_rows;
   t.side_streams = ctx->side_streams ? 1 : 0;
   t.fill_sched = ctx->fill_sched;
+  t.fill_coop = ctx->fill_coop;
   *out = t;
   return SWX_OK;
 }
@@ -1691,7 +1706,7 @@ int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t) {
   if (!ctx || !t) return fail(SWX_EINVAL, "null argument");
   if (t->long_cells < -1 || t->long_rlen < 0 || t->intra_jobs < 1 ||
       (t->side_streams != 0 && t->side_streams != 1) || t->fill_sched < 0 || t->fill_sched > 2 ||
-      t->pad_ != 0 ||
+      t->fill_coop < 0 || t->fill_coop > 2 ||
       (t->fill_rows != 16 && t->fill_rows != 24 && t->fill_rows != 32))
     return fail(SWX_EINVAL, "tuning value out of range");
   std::lock_guard<std::mutex> g(ctx->mu);
@@ -1701,6 +1716,7 @@ int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t) {
   ctx->fill_rows = t->fill_rows;
   ctx->side_streams = t->side_streams != 0;
   ctx->fill_sched = t->fill_sched;
+  ctx->fill_coop = t->fill_coop;
   return SWX_OK;
 }
 
@@ -2126,6 +2142,7 @@ int swx_graph_create(swx_ctx *ctx, const swx_graph_cfg *cfg, swx_graph **out, sw
   g.need32 = bound >= kInter16Limit;
   g.intra = cfg->route == SWX_ROUTE_INTRA;
   g.fill_sched = ctx->fill_sched;
+  g.fill_coop = ctx->fill_coop;
   g.cus = ctx->cus;
   int8_t *dmat = g.A.get<int8_t>((int64_t)g.sc.n * g.sc.n);
   if (!dmat) { delete gr; return fail(SWX_ENOMEM, "device pool exhausted"); }

@@ -52,6 +52,7 @@ struct FillOut {
   int32_t *qend;       // T1 row (in the view's coordinates)
   int64_t *rend;       // T1 column
   uint8_t *overflow;   // 1 when the lane width saturated: re-run wider
+  uint8_t *err;        // set when an internal check fails (may be null)
 };
 
 // Boundary plane layout.  Each plane (H of the strip's last row, F below it,
@@ -97,7 +98,16 @@ struct InterArgs {
                               // (0: a local pass, every border starts from zero)
   int32_t lastcol;            // forward pass on 32-bit lanes: the best counts only the
                               // last column
+  int32_t coop;               // 1: one wave per task; 4: the four waves of a workgroup share
+                              // a task, wave w taking strips w, w + 4, ... (a strip starts on
+                              // a column group once the strip above has stored it)
+  int32_t pad_;
 };
+
+// Strips per task that the cooperative mode pipelines (a task with more runs
+// on one wave of its workgroup).
+constexpr int kCoopMaxStrips = 512;
+constexpr int kCoopWaves = 4;
 
 // Largest score the 16-bit inter path represents exactly together with its
 // 5-bit row code (value * 32 + code <= 65535).

@@ -84,9 +84,13 @@ def test_tuning_invariance(ctx):
                  {"long_cells": 0, "long_rlen": 0, "intra_jobs": 5000},
                  {"long_cells": 100_000, "long_rlen": 1000, "fill_rows": 16},
                  {"long_cells": 100_000, "side_streams": 0},
-                 {"fill_sched": 0}, {"fill_sched": 2}, {"fill_sched": 2, "fill_rows": 16}):
+                 {"fill_sched": 0}, {"fill_sched": 2}, {"fill_sched": 2, "fill_rows": 16},
+                 {"fill_coop": 1}, {"fill_coop": 2}, {"fill_coop": 2, "fill_sched": 2},
+                 {"fill_coop": 2, "fill_sched": 0, "fill_rows": 24},
+                 {"fill_coop": 2, "long_cells": 1 << 62, "long_rlen": 1 << 62}):
         ctx.set_tuning(**{"long_cells": 1 << 22, "long_rlen": 1 << 16, "intra_jobs": 2048,
-                          "fill_rows": 32, "side_streams": 1, "fill_sched": 1, **tune})
+                          "fill_rows": 32, "side_streams": 1, "fill_sched": 1, "fill_coop": 0,
+                          **tune})
         _say(f"[tuning] {tune}")
         recs, cig = ctx.align_batch(b.matrix, b.gap_open, b.gap_extend, b.qcat, b.qoff, b.rcat,
                                     b.roff, b.pair_q, b.pair_r)
@@ -101,7 +105,8 @@ def test_tuning_invariance(ctx):
 
 def test_tuning_rejects_bad_values(ctx):
     for bad in ({"fill_rows": 20}, {"intra_jobs": 0}, {"long_cells": -2}, {"long_rlen": -1},
-                {"side_streams": 2}, {"fill_sched": 3}, {"fill_sched": -1}):
+                {"side_streams": 2}, {"fill_sched": 3}, {"fill_sched": -1}, {"fill_coop": 3},
+                {"fill_coop": -1}):
         with pytest.raises(swx.SwxError) as ei:
             ctx.set_tuning(**bad)
         assert ei.value.status == -1

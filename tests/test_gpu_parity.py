@@ -23,11 +23,15 @@ def _say(msg):
 
 # Every parity test runs with the default routing, with every pair forced
 # onto the batched (one pair per lane half) path with 32- and with 24-row
-# strips, and with every pair forced onto the intra-sequence (one pair per
-# wave) path.
+# strips, one wave per task and (cooperative) a workgroup's four waves per
+# task, in grid order and from the device queue, and with every pair forced
+# onto the intra-sequence (one pair per wave) path.
 PATHS = {"auto": {"long_cells": -1},
          "rows24": {"long_cells": 1 << 62, "long_rlen": 1 << 62, "fill_rows": 24},
-         "batched": {"long_cells": 1 << 62, "long_rlen": 1 << 62},
+         "batched": {"long_cells": 1 << 62, "long_rlen": 1 << 62, "fill_coop": 1},
+         "coop": {"long_cells": 1 << 62, "long_rlen": 1 << 62, "fill_coop": 2},
+         "coop_queue": {"long_cells": 1 << 62, "long_rlen": 1 << 62, "fill_coop": 2,
+                        "fill_sched": 2, "fill_rows": 16},
          "intra": {"long_cells": 0, "long_rlen": 0, "intra_jobs": 256}}
 
 
