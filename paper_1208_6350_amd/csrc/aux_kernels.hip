@@ -522,6 +522,54 @@ hipError_t launch_any_flag(int64_t n, const uint8_t *flag, int64_t *count, hipSt
   return hipGetLastError();
 }
 
+// ---- the query profile of one query (method section: built once per query) --
+// fwd[sym][x], x in [0, qp): the biased score S(q[x - pad], sym) + bias, with
+// pad = qp - qlen rows on top scoring 0 (and every byte of sym == n, the
+// padding symbol, 0), laid out as the batched fill's forward strips read it.
+// rev[c][sym][k], c in [0, 16), k in [0, rev_row): the biased score of query
+// position qlen - 1 - (k + c), 0 for k + c >= qlen (the reversed pass's
+// padding rows at the bottom): copy c serves rows that start c bytes past a
+// 16-byte boundary.
+__global__ void k_build_qprof(const int8_t *q, int32_t qlen, const int8_t *matrix, int32_t n,
+                              int32_t bias, int32_t qp, uint8_t *fwd, int64_t rev_row,
+                              uint8_t *rev) {
+  const int64_t nf = (int64_t)(n + 1) * qp;
+  const int64_t nr = 16 * (int64_t)(n + 1) * rev_row;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nf + nr; k += stride) {
+    int64_t i;
+    int32_t sym;
+    if (k < nf) {
+      sym = (int32_t)(k / qp);
+      i = k % qp - (qp - qlen);
+    } else {
+      const int64_t u = k - nf;
+      const int64_t c = u / ((int64_t)(n + 1) * rev_row);
+      const int64_t rest = u % ((int64_t)(n + 1) * rev_row);
+      sym = (int32_t)(rest / rev_row);
+      const int64_t pos = rest % rev_row + c;
+      i = pos < qlen ? qlen - 1 - pos : -1;
+    }
+    uint8_t b = 0;
+    if (sym < n && i >= 0 && i < qlen) {
+      const int32_t qc = q[i];
+      if (qc >= 0 && qc < n) b = (uint8_t)(matrix[qc * n + sym] + bias);   // codes checked before
+    }
+    if (k < nf) fwd[k] = b;
+    else rev[k - nf] = b;
+  }
+}
+
+hipError_t build_qprof(const int8_t *q, int32_t qlen, const int8_t *matrix, int32_t n, int32_t bias,
+                       int32_t qp, uint8_t *fwd, int64_t rev_row, uint8_t *rev, hipStream_t st) {
+  const int64_t total = (int64_t)(n + 1) * qp + 16 * (int64_t)(n + 1) * rev_row;
+  unsigned b = blocks_for(total, 256);
+  if (b > 2048) b = 2048;
+  hipLaunchKernelGGL(k_build_qprof, dim3(b), dim3(256), 0, st, q, qlen, matrix, n, bias, qp, fwd,
+                     rev_row, rev);
+  return hipGetLastError();
+}
+
 hipError_t launch_validate(const ValidateArgs &a, hipStream_t st) {
   const int64_t work = a.qcat_len + a.rcat_len + a.npairs + a.nq + a.nr + 2;
   int64_t blocks = (work + 255) / 256;

@@ -164,6 +164,7 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
   // see through, so value * 32 + code stays one v_pk_mad_u16
   uint32_t mul32;
   asm volatile("v_mov_b32 %0, %1" : "=v"(mul32) : "s"(0x00200020u));
+  const V vtop = T::splat((uint32_t)kInter16Limit);   // the value field's top (16-bit lanes)
   const V vo = T::splat((uint32_t)a.o);
   const V ve = T::splat((uint32_t)a.e);
   const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
@@ -306,17 +307,37 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
     };
     // QGEN: profile words of the next column, one column ahead
     uint32_t nX[R / 4][2];
+    // a batch whose pairs share one query reads the query's profile, built
+    // once: forward rows sR .. sR + R - 1 of a symbol are contiguous; a
+    // reversed pass needs rows from qlen - lq + sR on (lq: the reversed
+    // view's height), taken from the copy of the table shifted so that they
+    // start on a 16-byte boundary
+    int64_t qoffA = 0, qoffB = 0;
+    if (a.qprof) {
+      if constexpr (REV) {
+        const int64_t kA = (int64_t)a.qprof_qlen - qs[0].len + sR;
+        qoffA = (kA & 15) * a.qprof_copy + (kA & ~(int64_t)15);
+        if constexpr (NH == 2) {
+          const int64_t kB = (int64_t)a.qprof_qlen - qs[1].len + sR;
+          qoffB = (kB & 15) * a.qprof_copy + (kB & ~(int64_t)15);
+        }
+      } else {
+        qoffA = qoffB = sR;
+      }
+    }
     auto fetch_prof = [&](uint32_t symA, uint32_t symB) {
       const int np1 = a.n + 1;
       const uint8_t *base = a.prof + tk.qdata_off + (int64_t)s * np1 * NH * 64 * R;
-      const uint4 *pA = (const uint4 *)(base + (((int64_t)symA * NH + 0) * 64 + lane) * R);
+      const uint4 *pA = a.qprof ? (const uint4 *)(a.qprof + symA * a.qprof_row + qoffA)
+                                : (const uint4 *)(base + (((int64_t)symA * NH + 0) * 64 + lane) * R);
 #pragma unroll
       for (int k = 0; k < R / 16; ++k) {
         const uint4 v = pA[k];
         nX[4 * k + 0][0] = v.x; nX[4 * k + 1][0] = v.y; nX[4 * k + 2][0] = v.z; nX[4 * k + 3][0] = v.w;
       }
       if constexpr (NH == 2) {
-        const uint4 *pB = (const uint4 *)(base + (((int64_t)symB * 2 + 1) * 64 + lane) * R);
+        const uint4 *pB = a.qprof ? (const uint4 *)(a.qprof + symB * a.qprof_row + qoffB)
+                                  : (const uint4 *)(base + (((int64_t)symB * 2 + 1) * 64 + lane) * R);
 #pragma unroll
         for (int k = 0; k < R / 16; ++k) {
           const uint4 v = pB[k];
@@ -423,7 +444,10 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
             const V hn = T::subs(hb, vbias);
             H[r] = hn;
             const uint32_t code = code_top - (uint32_t)r;
-            cm = T::max(cm, CLAMP ? T::enc(hn, T::code_splat(code)) : T::enc_nosat(hn, code, mul32));
+            // scores past the 11-bit value field enter the code as the field's
+            // top (the pass is then flagged and re-run wider)
+            // (32-bit lanes hold any score beside the code)
+            cm = T::max(cm, T::enc_nosat((CLAMP && NH == 2) ? T::min(hn, vtop) : hn, code, mul32));
             ho = T::subs(hb, vo);
             E[r] = T::max(T::subs(E[r], ve), ho);
             F = T::max(T::subs(F, ve), ho);   // F of the next row
@@ -734,7 +758,7 @@ static hipError_t launch_fill(const InterArgs &a, hipStream_t st) {
 }
 
 hipError_t inter_fill(const InterArgs &a, int lane_bits, int R, hipStream_t st) {
-  const bool qsel = (a.prof == nullptr);
+  const bool qsel = (a.prof == nullptr && a.qprof == nullptr);
   if (lane_bits == 16) {
     if (R == 32) return qsel ? launch_fill<u16x2, 32, kQSel>(a, st) : launch_fill<u16x2, 32, kQGen>(a, st);
     if (R == 24 && qsel) return launch_fill<u16x2, 24, kQSel>(a, st);

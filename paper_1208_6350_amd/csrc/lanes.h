@@ -29,16 +29,13 @@ template <> struct VT<u16x2> {
   static __device__ __forceinline__ u16x2 max(u16x2 a, u16x2 b) {
     return __builtin_elementwise_max(a, b);
   }
-  // value * 32 + code, saturating at 0xFFFF (v_pk_mad_u16 with clamp).  The
-  // row code sits in the low 5 bits so that a max over rows also yields, among
-  // rows of equal value, the one with the largest code.
-  static __device__ __forceinline__ u16x2 enc(u16x2 h, uint32_t code2) {
-    uint32_t r;
-    asm("v_pk_mad_u16 %0, %1, 32, %2 op_sel_hi:[1,0,1] clamp" : "=v"(r) : "v"(bits(h)), "s"(code2));
-    return from(r);
+  static __device__ __forceinline__ u16x2 min(u16x2 a, u16x2 b) {
+    return __builtin_elementwise_min(a, b);
   }
-  // value * 32 + code without saturation: only for pairs whose scores
-  // cannot exceed the 11-bit value field (checked before launch)
+  // value * 32 + code: the row code sits in the low 5 bits so that a max over
+  // rows also yields, among rows of equal value, the one with the largest
+  // code.  The value must fit the 11-bit field (the fill clamps it first when
+  // a score could exceed it)
   static __device__ __forceinline__ u16x2 enc_nosat(u16x2 h, uint32_t code, uint32_t mul32) {
     return h * from(mul32) + (u16x2){(unsigned short)code, (unsigned short)code};
   }
@@ -52,7 +49,6 @@ template <> struct VT<u16x2> {
     return (uint32_t)k | 0x0C00u | ((uint32_t)(k + 4) << 16) | 0x0C000000u;
   }
   static constexpr uint32_t kPadSel = 0x0C0C0C0Cu;
-  static constexpr uint32_t code_splat(uint32_t c) { return c * 0x10001u; }
 };
 
 // one 32-bit lane per register
@@ -67,7 +63,7 @@ template <> struct VT<uint32_t> {
     return __builtin_elementwise_sub_sat(a, b);
   }
   static __device__ __forceinline__ uint32_t max(uint32_t a, uint32_t b) { return a > b ? a : b; }
-  static __device__ __forceinline__ uint32_t enc(uint32_t h, uint32_t code) { return h * 32u + code; }
+  static __device__ __forceinline__ uint32_t min(uint32_t a, uint32_t b) { return a < b ? a : b; }
   static __device__ __forceinline__ uint32_t enc_nosat(uint32_t h, uint32_t code, uint32_t) {
     return h * 32u + code;
   }
@@ -75,7 +71,6 @@ template <> struct VT<uint32_t> {
   static __device__ __forceinline__ uint32_t half(uint32_t v, int) { return v; }
   static constexpr uint32_t sel_const(int k) { return (uint32_t)k | 0x0C0C0C00u; }
   static constexpr uint32_t kPadSel = 0x0C0C0C0Cu;
-  static constexpr uint32_t code_splat(uint32_t c) { return c; }
 };
 
 __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {

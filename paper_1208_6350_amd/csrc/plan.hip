@@ -101,7 +101,8 @@ __global__ void k_plan_tasks(int64_t n, const int64_t *n_dev, int64_t ntasks, in
   tk.slot_base = s0;
   tasks[t] = tk;
   bnd_size[t] = 3 * (int64_t)tk.rp * 64;
-  qdata_size[t] = ((int64_t)tk.qp * qdata_per_row + 15) / 16 * 16;
+  // qdata_per_row < 0: a profile shared by every task (whole strips, no bytes per task)
+  qdata_size[t] = qdata_per_row > 0 ? ((int64_t)tk.qp * qdata_per_row + 15) / 16 * 16 : 0;
 }
 
 __global__ void k_plan_offsets(int64_t ntasks, InterTask *tasks, const int64_t *bnd_off,

@@ -189,6 +189,12 @@ struct swx_profile {
   std::vector<int8_t> query;
   std::vector<int8_t> matrix;
   int32_t n = 0, o = 0, e = 0;
+  // alphabets above 4 symbols: the query profile on the device, built once
+  // (forward strips of 32 and of 16 rows, and the reversed table)
+  uint8_t *dev = nullptr;
+  uint8_t *fwd32 = nullptr, *fwd16 = nullptr, *rev = nullptr;
+  int32_t qp32 = 0, qp16 = 0;
+  int64_t rev_row = 0;
 };
 
 namespace swx {
@@ -245,6 +251,14 @@ static int make_scoring(const int8_t *mat, int32_t n, int32_t o, int32_t e, Scor
   return SWX_OK;
 }
 
+// The query profile of a batch whose pairs all use one query (k_build_qprof):
+// forward strips of R rows, and the reversed table of 16 shifted copies.
+struct SharedProf {
+  const uint8_t *fwd = nullptr, *rev = nullptr;
+  int64_t fwd_row = 0, rev_row = 0;
+  int32_t qlen = 0, R = 0;
+};
+
 // ---- device-side planning of one fill pass ---------------------------------
 struct Plan {
   int64_t n = 0, ntasks = 0;
@@ -286,7 +300,8 @@ static T *alloc_or_null(DevArena &A, int64_t n) { return A.get<T>(n); }
 // the device, cut them into tasks, derive buffer offsets and allocate.
 static int plan_pass(swx_ctx *ctx, const Scoring &sc, const int64_t *ids, int64_t n,
                      const int32_t *qlen, const int64_t *rlen, const int32_t *band,
-                     const int32_t *band_q, int lane_bits, int R, Plan &pl) {
+                     const int32_t *band_q, int lane_bits, int R, Plan &pl,
+                     const SharedProf *sp = nullptr) {
   DevArena &A = ctx->arena;
   hipStream_t st = ctx->stream;
   pl = Plan{};
@@ -309,7 +324,8 @@ static int plan_pass(swx_ctx *ctx, const Scoring &sc, const int64_t *ids, int64_
   void *tmp = A.alloc(tmp_bytes);
   if (!tmp) return fail(SWX_ENOMEM, "device pool exhausted (sort)");
   HIP_TRY(plan_sort(n, nullptr, ids, qlen, rlen, band, R, k0, k1, v0, v1, tmp, &tmp_bytes, &pl.d_sorted, st));
-  const int64_t per_row = sc.qsel ? 0 : (int64_t)(sc.n + 1) * halves * 64;
+  // profile bytes per padded row and task; -1: a profile shared by every task
+  const int64_t per_row = sc.qsel ? 0 : (sp ? -1 : (int64_t)(sc.n + 1) * halves * 64);
   HIP_TRY(plan_tasks_dev(   // also clears bsz[ntasks], qsz[ntasks]
                          n, nullptr, pl.ntasks, slots, R, per_row, pl.d_sorted, qlen, rlen, band,
                          band_q, pl.d_tasks, bsz, qsz, st));
@@ -330,7 +346,7 @@ static int plan_pass(swx_ctx *ctx, const Scoring &sc, const int64_t *ids, int64_
   pl.d_bnd = A.get<uint32_t>(tot[0]);
   pl.d_rsym = A.get<uint2>(rsym_offset(tot[0]));
   if (!pl.d_bnd || !pl.d_rsym) return fail(SWX_ENOMEM, "device pool exhausted (boundary planes)");
-  if (!sc.qsel) {
+  if (per_row > 0) {
     pl.d_prof = A.get<uint8_t>(tot[1]);
     if (!pl.d_prof) return fail(SWX_ENOMEM, "device pool exhausted (profiles)");
   }
@@ -341,7 +357,8 @@ static int plan_pass(swx_ctx *ctx, const Scoring &sc, const int64_t *ids, int64_
 // events mark_fill and mark_fill + 1 bracket the fill kernel alone
 static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &view, bool rev,
                     const int32_t *d_target, FillOut out, int64_t score_bound,
-                    int mark_fill = -1, uint32_t anchor = 0, int lastcol = 0) {
+                    int mark_fill = -1, uint32_t anchor = 0, int lastcol = 0,
+                    const SharedProf *sp = nullptr) {
   hipStream_t st = ctx->stream;
   if (pl.ntasks == 0) {
     if (mark_fill >= 0) {
@@ -364,13 +381,19 @@ static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &v
   pk.strip_rows = pl.R;
   pk.rev = rev ? 1 : 0;
   HIP_TRY(inter_pack_ref(pk, st));
-  if (!sc.qsel) HIP_TRY(inter_pack(pk, st));
+  if (!sc.qsel && !sp) HIP_TRY(inter_pack(pk, st));
   InterArgs a{};
   a.tasks = pl.d_tasks;
   a.ntasks = pl.ntasks;
   a.slot_pair = pl.d_sorted;
   a.view = view;
-  a.prof = sc.qsel ? nullptr : pl.d_prof;
+  a.prof = (sc.qsel || sp) ? nullptr : pl.d_prof;
+  if (sp && !sc.qsel) {
+    a.qprof = rev ? sp->rev : sp->fwd;
+    a.qprof_row = rev ? sp->rev_row : sp->fwd_row;
+    a.qprof_copy = (int64_t)(sc.n + 1) * sp->rev_row;
+    a.qprof_qlen = sp->qlen;
+  }
   a.bnd = pl.d_bnd;
   a.rsym = pl.d_rsym;
   for (int k = 0; k < 8; ++k) a.lut[k] = sc.lut[k];
@@ -750,9 +773,13 @@ static int rl_slot(int RL) { return RL == 4 ? 0 : RL == 8 ? 1 : RL == 16 ? 2 : 3
 // path a pair occupies one 16-bit lane half for cells * t; a full GPU holds
 // about 2048 waves * 128 halves, so a pair larger than twice the batch's
 // average work per half would finish last -- it is faster spread over a wave.
-static int64_t long_threshold(const swx_ctx *ctx, int64_t total_cells) {
+// A batch of few tasks runs each on four waves (cooperative strips), which
+// shortens a task's time about four times.
+static int64_t long_threshold(const swx_ctx *ctx, int64_t total_cells, int64_t npairs) {
   if (ctx->long_cells >= 0) return ctx->long_cells;
-  return std::max<int64_t>(2048, 2 * total_cells / (2048 * 128));
+  const int64_t base = std::max<int64_t>(2048, 2 * total_cells / (2048 * 128));
+  const int64_t tasks = (npairs + kSlots16 - 1) / kSlots16;
+  return coop_waves(ctx->fill_coop, tasks, ctx->cus) > 1 ? base * kCoopWaves : base;
 }
 
 static int code_bits(int64_t rows_padded) {
@@ -776,7 +803,7 @@ static int split_pairs(swx_ctx *ctx, int64_t np, const int32_t *qlen, const int6
   DevArena &A = ctx->arena;
   uint8_t *fl = A.get<uint8_t>(np), *fs = A.get<uint8_t>(np);
   if (!fl || !fs) return fail(SWX_ENOMEM, "device pool exhausted (split)");
-  HIP_TRY(split_long(np, qlen, rlen, long_threshold(ctx, total_cells), ctx->long_rlen, fl, fs,
+  HIP_TRY(split_long(np, qlen, rlen, long_threshold(ctx, total_cells, np), ctx->long_rlen, fl, fs,
                      ctx->stream));
   int rc;
   if ((rc = select_flagged(ctx, fl, np, &lp.d_long, &lp.nlong))) return rc;
@@ -947,7 +974,7 @@ static int run_intra_reverse(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
 }
 
 static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, uint32_t flags,
-                        int32_t mask_len, swx_batch_out *out) {
+                        int32_t mask_len, swx_batch_out *out, const swx_profile *prof) {
   DevArena &A = ctx->arena;
   hipStream_t st = ctx->stream;
   const int64_t np = b.npairs;
@@ -1001,16 +1028,51 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
   PairView fview{qstart, rstart, qlen, rlen, b.qcat, b.rcat, 0};
   FillOut fout{score, qend, rend, ovf, err};
 
+  // 24-row strips exist for the 4-symbol selector profile only
+  const int R = (ctx->fill_rows == 24 && !sc.qsel) ? 32 : ctx->fill_rows;
+  // every pair on one query (general alphabets): the query profile is built
+  // once (or comes resident with the caller's profile) and every batched
+  // pass reads it, instead of profile bytes per task
+  SharedProf shp;
+  const SharedProf *sp = nullptr;
+  if (!sc.qsel && b.nq == 1) {
+    if (prof && prof->dev) {
+      shp.fwd = R == 32 ? prof->fwd32 : prof->fwd16;
+      shp.fwd_row = R == 32 ? prof->qp32 : prof->qp16;
+      shp.rev = prof->rev;
+      shp.rev_row = prof->rev_row;
+      shp.qlen = (int32_t)prof->query.size();
+    } else {
+      int64_t qo[2];
+      HIP_TRY(hipMemcpyAsync(ctx->pinned, b.qoff, 16, hipMemcpyDeviceToHost, st));
+      HIP_TRY(wait_stream(st));
+      memcpy(qo, ctx->pinned, 16);
+      const int64_t ql = qo[1] - qo[0];
+      if (ql < 1 || ql > INT32_MAX / 4) return fail(SWX_EINVAL, "bad query length");
+      shp.qlen = (int32_t)ql;
+      shp.fwd_row = round_up(ql, R);
+      shp.rev_row = qprof_rev_row(ql, 32);
+      uint8_t *fw = A.get<uint8_t>((sc.n + 1) * shp.fwd_row);
+      uint8_t *rv = A.get<uint8_t>(16 * (sc.n + 1) * shp.rev_row);
+      if (!fw || !rv) return fail(SWX_ENOMEM, "device pool exhausted (query profile)");
+      HIP_TRY(build_qprof(b.qcat + qo[0], shp.qlen, sc.dmat, sc.n, sc.bias, (int32_t)shp.fwd_row, fw,
+                          shp.rev_row, rv, st));
+      shp.fwd = fw;
+      shp.rev = rv;
+    }
+    shp.R = R;
+    sp = &shp;
+  }
+
   // long pairs take the intra-sequence path, the rest the batched one
   LongPath lp;
   if ((rc = split_pairs(ctx, np, qlen, rlen, hstats[1], lp))) return rc;
 
   // forward fill, 16-bit lanes (events 1 and 2 bracket the fill kernels)
-  // 24-row strips exist for the 4-symbol selector profile only
-  const int R = (ctx->fill_rows == 24 && !sc.qsel) ? 32 : ctx->fill_rows;
   Plan p16, p32;
-  if ((rc = plan_pass(ctx, sc, lp.d_short, lp.nshort, qlen, rlen, nullptr, nullptr, 16, R, p16))) return rc;
-  if ((rc = run_fill(ctx, p16, sc, fview, false, nullptr, fout, score_bound, 1))) return rc;
+  if ((rc = plan_pass(ctx, sc, lp.d_short, lp.nshort, qlen, rlen, nullptr, nullptr, 16, R, p16, sp)))
+    return rc;
+  if ((rc = run_fill(ctx, p16, sc, fview, false, nullptr, fout, score_bound, 1, 0, 0, sp))) return rc;
   if (lp.nlong > 0) {
     if ((rc = run_intra_forward(ctx, sc, lp, fview, fout, err))) return rc;
     HIP_TRY(hipEventRecord(ctx->ev[2], st));
@@ -1021,8 +1083,8 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
   int64_t *wide = nullptr, nwide = 0;
   if ((rc = select_flagged(ctx, ovf, np, &wide, &nwide))) return rc;
   if (nwide > 0) {
-    if ((rc = plan_pass(ctx, sc, wide, nwide, qlen, rlen, nullptr, nullptr, 32, R, p32))) return rc;
-    if ((rc = run_fill(ctx, p32, sc, fview, false, nullptr, fout, score_bound))) return rc;
+    if ((rc = plan_pass(ctx, sc, wide, nwide, qlen, rlen, nullptr, nullptr, 32, R, p32, sp))) return rc;
+    if ((rc = run_fill(ctx, p32, sc, fview, false, nullptr, fout, score_bound, -1, 0, 0, sp))) return rc;
     HIP_TRY(mark_lanes(nwide, wide, lanebits, 32, st));
   }
   HIP_TRY(hipEventRecord(ctx->ev[3], st));
@@ -1059,9 +1121,10 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
     for (int k = 0; k < 2; ++k) {
       if (rcnt[k] == 0) continue;
       Plan pr;
-      if ((rc = plan_pass(ctx, sc, rids[k], rcnt[k], rql, rrl, band, band_q, k == 0 ? 16 : 32, R, pr)))
+      if ((rc = plan_pass(ctx, sc, rids[k], rcnt[k], rql, rrl, band, band_q, k == 0 ? 16 : 32, R, pr,
+                          sp)))
         return rc;
-      if ((rc = run_fill(ctx, pr, sc, rview, true, tgt, rout, score_bound))) return rc;
+      if ((rc = run_fill(ctx, pr, sc, rview, true, tgt, rout, score_bound, -1, 0, 0, sp))) return rc;
     }
     if (lp.nlong > 0 &&
         (rc = run_intra_reverse(ctx, sc, lp, rview, score, qend, rend, band, tgt, rout, err)))
@@ -1144,10 +1207,10 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
     if ((rc = select_flagged(ctx, sfl, np, &ids, &cnt))) return rc;
     if (cnt > 0) {
       Plan pw;
-      if ((rc = plan_pass(ctx, sc, ids, cnt, qlen, wrl, nullptr, nullptr, 32, R, pw))) return rc;
+      if ((rc = plan_pass(ctx, sc, ids, cnt, qlen, wrl, nullptr, nullptr, 32, R, pw, sp))) return rc;
       PairView wview{qstart, wrs, qlen, wrl, b.qcat, b.rcat, 0};
       FillOut wout{wsc, wqe, wre, wov, err};
-      if ((rc = run_fill(ctx, pw, sc, wview, false, nullptr, wout, score_bound, -1, 0, 1)))
+      if ((rc = run_fill(ctx, pw, sc, wview, false, nullptr, wout, score_bound, -1, 0, 1, sp)))
         return rc;
     }
     HIP_TRY(launch_sub_rev_views(np, qstart, rstart, qlen, score2, rend2, wsc, wqe, kAnchor, rqs,
@@ -1156,11 +1219,11 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
     if ((rc = select_flagged(ctx, sfl, np, &ids, &cnt))) return rc;
     if (cnt > 0) {
       Plan pr;
-      if ((rc = plan_pass(ctx, sc, ids, cnt, rql, rrl, nullptr, nullptr, 32, R, pr))) return rc;
+      if ((rc = plan_pass(ctx, sc, ids, cnt, rql, rrl, nullptr, nullptr, 32, R, pr, sp))) return rc;
       PairView rview{rqs, rrs, rql, rrl, b.qcat, b.rcat, 1};
       FillOut rout{rsc, rqe, rre, rov, err};
       if ((rc = run_fill(ctx, pr, sc, rview, true, tgt, rout, score_bound + kAnchor, -1, kAnchor,
-                         0)))
+                         0, sp)))
         return rc;
     }
     HIP_TRY(launch_sub_begins(np, score2, rend2, wqe, sfl, tgt, rsc, rqe, rre, s_score, s_qbeg,
@@ -1849,12 +1912,50 @@ int swx_profile_create(swx_ctx *ctx, const int8_t *query, int32_t qlen, const in
   p->n = n;
   p->o = gap_open;
   p->e = gap_extend;
+  if (!sc.qsel) {
+    // the query profile on the device, once: forward strips of 32 and of 16
+    // rows and the reversed table (alphabets of at most 4 symbols need none:
+    // their fill builds two scores per instruction from a 4-byte table)
+    p->qp32 = (int32_t)round_up(qlen, 32);
+    p->qp16 = (int32_t)round_up(qlen, 16);
+    p->rev_row = qprof_rev_row(qlen, 32);
+    const int64_t n1 = n + 1;
+    const int64_t f32b = n1 * p->qp32, f16b = n1 * p->qp16, rb = 16 * n1 * p->rev_row;
+    const int64_t scratch = qlen + (int64_t)n * n;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    hipStream_t st = ctx->stream;
+    bool ok = hipSetDevice(ctx->device) == hipSuccess &&
+              hipMalloc(&p->dev, (size_t)(f32b + f16b + rb + scratch + 64)) == hipSuccess;
+    if (ok) {
+      p->fwd32 = p->dev;
+      p->fwd16 = p->fwd32 + f32b;
+      p->rev = p->fwd16 + f16b;
+      int8_t *dq = (int8_t *)(p->rev + rb), *dm = dq + qlen;
+      ok = hipMemcpyAsync(dq, query, qlen, hipMemcpyHostToDevice, st) == hipSuccess &&
+           hipMemcpyAsync(dm, matrix, (size_t)n * n, hipMemcpyHostToDevice, st) == hipSuccess &&
+           build_qprof(dq, qlen, dm, n, sc.bias, p->qp32, p->fwd32, p->rev_row, p->rev, st) ==
+               hipSuccess &&
+           build_qprof(dq, qlen, dm, n, sc.bias, p->qp16, p->fwd16, 0, p->rev, st) == hipSuccess &&
+           hipStreamSynchronize(st) == hipSuccess;
+    }
+    if (!ok) {
+      if (p->dev) (void)hipFree(p->dev);
+      delete p;
+      return fail(SWX_EDEVICE, "could not build the device query profile");
+    }
+  }
   *out = p;
   return SWX_OK;
 }
 
 int swx_profile_destroy(swx_profile *p) {
   if (!p) return fail(SWX_EINVAL, "profile is null");
+  if (p->dev) {
+    std::lock_guard<std::mutex> g(p->ctx->mu);
+    (void)hipSetDevice(p->ctx->device);
+    (void)hipStreamSynchronize(p->ctx->stream);
+    (void)hipFree(p->dev);
+  }
   delete p;
   return SWX_OK;
 }
@@ -1877,7 +1978,8 @@ int64_t swx_cigar_bound(const swx_batch *b) {
   return (b->flags & SWX_SUBOPT) ? 2 * s : s;
 }
 
-static int align_batch_locked(swx_ctx *ctx, const swx_batch *b, swx_batch_out *out) {
+static int align_batch_locked(swx_ctx *ctx, const swx_batch *b, swx_batch_out *out,
+                              const swx_profile *prof = nullptr) {
   Scoring sc;
   int rc = make_scoring(b->matrix, b->n, b->gap_open, b->gap_extend, &sc);
   if (rc) return rc;
@@ -1925,7 +2027,7 @@ static int align_batch_locked(swx_ctx *ctx, const swx_batch *b, swx_batch_out *o
     out->cigar_used = 0;
     return SWX_OK;
   }
-  return run_pipeline(ctx, sc, db, b->flags, b->mask_len, out);
+  return run_pipeline(ctx, sc, db, b->flags, b->mask_len, out, prof);
 }
 
 int swx_align_batch(swx_ctx *ctx, const swx_batch *b, swx_batch_out *out, void *hip_stream) {
@@ -2093,7 +2195,7 @@ int swx_align(const swx_profile *p, const int8_t *ref, int64_t rlen, uint32_t fl
   swx_rec rec{};
   std::vector<uint32_t> cig((size_t)(p->query.size() + rlen + 2));
   swx_batch_out bo{&rec, cig.data(), (int64_t)cig.size(), 0, SWX_MEM_HOST};
-  int rc = align_batch_locked(ctx, &b, &bo);
+  int rc = align_batch_locked(ctx, &b, &bo, p);
   if (rc) return rc;
   out->rec = rec;
   out->cigar = nullptr;

@@ -98,10 +98,17 @@ struct InterArgs {
                               // (0: a local pass, every border starts from zero)
   int32_t lastcol;            // forward pass on 32-bit lanes: the best counts only the
                               // last column
+  const uint8_t *qprof;       // QGEN, every pair of the pass on one query: that query's profile
+                              // (null: per-task profile bytes at prof).  Forward: [sym][qp]
+                              // biased scores, rows padded at the top as the tasks pad them.
+                              // Reversed: 16 copies [c][sym][row], copy c shifted by c bytes,
+                              // byte k of a row the biased score of query position qlen-1-k
+  int64_t qprof_row;          // bytes per symbol row
+  int64_t qprof_copy;         // reversed: bytes per shifted copy
+  int32_t qprof_qlen;         // the query's length
   int32_t coop;               // 1: one wave per task; 4: the four waves of a workgroup share
                               // a task, wave w taking strips w, w + 4, ... (a strip starts on
                               // a column group once the strip above has stored it)
-  int32_t pad_;
 };
 
 // Strips per task that the cooperative mode pipelines (a task with more runs

@@ -247,6 +247,11 @@ hipError_t inter_pack(const PackArgs &a, hipStream_t st);
 hipError_t inter_pack_ref(const PackArgs &a, hipStream_t st);
 
 hipError_t launch_validate(const ValidateArgs &a, hipStream_t st);
+// the shared query profile of a pass whose pairs all use one query (k_build_qprof)
+hipError_t build_qprof(const int8_t *q, int32_t qlen, const int8_t *matrix, int32_t n, int32_t bias,
+                       int32_t qp, uint8_t *fwd, int64_t rev_row, uint8_t *rev, hipStream_t st);
+// bytes of a reversed row of the shared profile for strips of R rows
+inline int64_t qprof_rev_row(int64_t qlen, int R) { return (2 * qlen + 2 * R + 16 + 15) / 16 * 16; }
 hipError_t launch_pair_stats(int64_t n, const int32_t *qlen, const int64_t *rlen, int64_t *stats,
                              hipStream_t st);
 hipError_t lens_to_i64(int64_t n, const int32_t *len, int64_t *out, hipStream_t st);

@@ -157,3 +157,21 @@ def test_autotune_keeps_results_and_caches(ctx, tmp_path):
     t2, fc2 = ctx.autotune(b.matrix, b.gap_open, b.gap_extend, b.qcat, b.qoff, b.rcat, b.roff,
                            b.pair_q, b.pair_r, max_pairs=200, cache_path=cache)
     assert fc2 and t2 == t1 and ctx.tuning() == t1
+
+
+def test_single_pair_protein_beyond_graph_capacity(ctx):
+    """One protein pair above the one-pair graph's capacity (reference over
+    65,536 residues): swx_align takes the batch path and reads the profile's
+    resident device tables; equal to the oracle."""
+    g = np.random.Generator(np.random.PCG64(8123))
+    mat = W.protein_matrix_standin()
+    q = g.integers(0, 24, 150).astype(np.int8)
+    r = g.integers(0, 24, 70_000).astype(np.int8)
+    r[31_000:31_150] = q
+    r[50_000:50_120] = q[10:130]
+    for o, e in ((11, 1), (5, 5)):
+        rec, cig = ctx.align_pair(q, r, mat, o, e)
+        a = oracle.align(q, r, mat, o, e)
+        for f in FIELDS:
+            assert rec[f] == getattr(a, f), (o, e, f)
+        assert cig == a.cigar
