@@ -257,13 +257,20 @@ typedef struct {
                             waves runs each task on the four waves of a workgroup, which
                             take its strips round robin (a strip follows the one above
                             column group by column group); 1: never; 2: always */
+  int32_t intra_bits;    /* lanes of the intra-sequence forward pass. 16: packed 16-bit
+                            lanes, two column chunks per wave (on twice intra_jobs chunks),
+                            for every long pair whose scores fit (smax * min(qlen, rlen)
+                            + bias <= 32766), 32-bit for the others; 32: always 32-bit;
+                            0 (default): as 16 when those 16-bit waves number at least
+                            four per compute unit, else as 32 */
+  int32_t pad_;          /* must be 0 */
 } swx_tuning;
 int swx_get_tuning(const swx_ctx *ctx, swx_tuning *out);
 int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t);
 
 /* Autotuner: runs the first min(npairs, max_pairs) pairs of b under candidate
  * settings of each knob in turn (fill_rows, long_cells, intra_jobs, side_streams, fill_sched,
- * fill_coop;
+ * fill_coop, intra_bits;
  * each timed as the best of two runs after a warm-up, a change kept only if
  * at least 3% faster), installs the fastest in ctx and returns it in *out.
  * cache_path (may be NULL) names a text file of one JSON object per line,

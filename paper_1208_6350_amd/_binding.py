@@ -66,7 +66,8 @@ class SwxTuning(ctypes.Structure):
     _fields_ = [("long_cells", ctypes.c_int64), ("long_rlen", ctypes.c_int64),
                 ("intra_jobs", ctypes.c_int64), ("fill_rows", ctypes.c_int32),
                 ("side_streams", ctypes.c_int32), ("fill_sched", ctypes.c_int32),
-                ("fill_coop", ctypes.c_int32)]
+                ("fill_coop", ctypes.c_int32), ("intra_bits", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 class SwxServerCfg(ctypes.Structure):

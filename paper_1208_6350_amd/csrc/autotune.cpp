@@ -82,13 +82,15 @@ bool cache_lookup(const char *path, const std::string &key, swx_tuning *t) {
       t->long_cells = lc;
       t->long_rlen = lr;
       t->intra_jobs = ij;
-      int64_t ss = 1, fs = 1, fc = 0;
+      int64_t ss = 1, fs = 1, fc = 0, ib = 0;
       (void)parse_i64(s, "side_streams", &ss);
       (void)parse_i64(s, "fill_sched", &fs);
       (void)parse_i64(s, "fill_coop", &fc);
+      (void)parse_i64(s, "intra_bits", &ib);
       t->side_streams = ss ? 1 : 0;
       t->fill_sched = (fs >= 0 && fs <= 2) ? (int32_t)fs : 1;
       t->fill_coop = (fc >= 0 && fc <= 2) ? (int32_t)fc : 0;
+      t->intra_bits = (ib == 16 || ib == 32) ? (int32_t)ib : 0;
       found = true;
     }
   }
@@ -103,9 +105,10 @@ void cache_store(const char *path, const std::string &key, const swx_tuning &t, 
   fprintf(f,
           "{\"key\": \"%s\", \"fill_rows\": %d, \"long_cells\": %lld, \"long_rlen\": %lld, "
           "\"intra_jobs\": %lld, \"side_streams\": %d, \"fill_sched\": %d, "
-          "\"fill_coop\": %d, \"ms\": %.3f}\n",
+          "\"fill_coop\": %d, \"intra_bits\": %d, \"ms\": %.3f}\n",
           key.c_str(), t.fill_rows, (long long)t.long_cells, (long long)t.long_rlen,
-          (long long)t.intra_jobs, t.side_streams, t.fill_sched, t.fill_coop, ms);
+          (long long)t.intra_jobs, t.side_streams, t.fill_sched, t.fill_coop,
+          t.intra_bits, ms);
   fclose(f);
 }
 
@@ -192,6 +195,8 @@ extern "C" int swx_autotune(swx_ctx *ctx, const swx_batch *b, int64_t max_pairs,
   if ((rc = try_knob([](swx_tuning &t, int64_t v) { t.fill_sched = (int32_t)v; }, {1, 0, 2})))
     return rc;
   if ((rc = try_knob([](swx_tuning &t, int64_t v) { t.fill_coop = (int32_t)v; }, {0, 1, 2})))
+    return rc;
+  if ((rc = try_knob([](swx_tuning &t, int64_t v) { t.intra_bits = (int32_t)v; }, {0, 16, 32})))
     return rc;
   if ((rc = swx_set_tuning(ctx, &best))) return rc;
   cache_store(cache_path, key, best, best_ms);

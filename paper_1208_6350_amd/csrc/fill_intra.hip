@@ -29,6 +29,8 @@
 
 namespace swx {
 
+typedef u16x2 V16;
+
 constexpr int kDppWaveShr1 = 0x138;   // DPP control: lane k reads lane k - 1
 
 // value of src from the lane above; lane 0 takes `top`
@@ -330,6 +332,219 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
   }
 }
 
+// ---- packed 16-bit lanes: two column streams per wave ---------------------
+// The forward pass on 2 x 16-bit lanes.  Two jobs with the same strip layout
+// (jobs[2b] in the low halves, jobs[2b + 1] in the high halves) share a wave:
+// lane k holds rows [k*RL, (k+1)*RL) of both, so one packed instruction
+// updates a cell of each.  Both jobs' scores must stay below 2^15 (checked
+// before launch: a score can reach smax * min(qlen, rlen)).  The column max
+// leaves a lane per job as one 32-bit word value << 16 | (65535 - padded
+// row), built from the packed H with v_perm, so the max array has the same
+// layout as the 32-bit pass with kbits = 16.  Hand-over rows hold the 16-bit
+// values in 32-bit words, one row per job as in the 32-bit pass.
+template <int RL>
+__global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill16(IntraArgs a) {
+  extern __shared__ uint4 s_dyn[];            // per wave and job: [(n + 1) symbols][64 lanes][RL bytes]
+  __shared__ int8_t s_mat[32 * 32];
+  __shared__ int32_t s_prog[kMaxStrips];
+  __shared__ int32_t s_done[kMaxStrips];
+  constexpr int SH = 64 * RL;
+  using T = VT<u16x2>;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int NW = blockDim.x >> 6;
+  const int n = a.n;
+  const IntraJob jA = a.jobs[2 * (int64_t)blockIdx.x];
+  const IntraJob jB = a.jobs[2 * (int64_t)blockIdx.x + 1];
+  const bool hasB = jB.pair >= 0;
+  const int64_t pA = jA.pair, pB = hasB ? jB.pair : jA.pair;
+  const int32_t LqA = a.view.qlen[pA], LqB = a.view.qlen[pB];
+  const int64_t LrA = a.view.rlen[pA], LrB = a.view.rlen[pB];
+  const int8_t *qsA = a.view.qcat + a.view.qstart[pA], *qsB = a.view.qcat + a.view.qstart[pB];
+  const int8_t *rsA = a.view.rcat + a.view.rstart[pA], *rsB = a.view.rcat + a.view.rstart[pB];
+  // both jobs have the same padded height (the host pairs them so)
+  const int64_t qp = ((int64_t)LqA + SH - 1) / SH * SH;
+  const int nstrips = (int)(qp / SH);
+  for (int i = threadIdx.x; i < n * n; i += blockDim.x) s_mat[i] = a.matrix[i];
+  for (int i = threadIdx.x; i < nstrips && i < kMaxStrips; i += blockDim.x) {
+    s_prog[i] = 0;
+    s_done[i] = 0;
+  }
+  __syncthreads();
+  const int64_t qpadA = qp - LqA, qpadB = qp - LqB;
+  const int64_t widthA = jA.c1 - jA.cw, widthB = hasB ? jB.c1 - jB.cw : 0;
+  const int64_t width = widthA > widthB ? widthA : widthB;   // steps of the wave, both jobs
+  uint32_t *mcA = a.maxcol + jA.mc_off, *mcB = a.maxcol + (hasB ? jB.mc_off : jA.mc_off);
+  const V16 vbias = T::splat((uint32_t)a.bias), vo = T::splat((uint32_t)a.o), ve = T::splat((uint32_t)a.e);
+  const size_t tbl = (size_t)(n + 1) * 64 * RL;
+  uint8_t *s_profA = reinterpret_cast<uint8_t *>(s_dyn) + (size_t)wave * 2 * tbl;
+  uint8_t *s_profB = s_profA + tbl;
+  // v_perm selectors: the low (A) or high (B) 16-bit half of H above a 16-bit code
+  const uint32_t selA = 0x05040100u, selB = 0x07060100u;
+
+  for (int s = wave; s < nstrips; s += NW) {
+    uint32_t *bHA = a.bnd + jA.bnd_off + 2 * widthA * (int64_t)s;
+    uint32_t *bFA = bHA + widthA;
+    uint32_t *bHB = a.bnd + (hasB ? jB.bnd_off : jA.bnd_off) + 2 * widthB * (int64_t)s;
+    uint32_t *bFB = bHB + widthB;
+    uint32_t *iHA = bHA - 2 * widthA, *iFA = iHA + widthA;   // rows of strip s - 1
+    uint32_t *iHB = bHB - 2 * widthB, *iFB = iHB + widthB;
+    const bool hand_over = (s + 1 < nstrips);
+    auto publish = [&](int32_t ncols, bool fin) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if (lane == 0) {
+        __hip_atomic_store(&s_prog[s], ncols, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (fin) __hip_atomic_store(&s_done[s], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    };
+    // strip profiles of both jobs
+    {
+      int32_t qa[RL], qb[RL];
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int64_t row = (int64_t)s * SH + lane * RL + r;
+        const int64_t ia = row - qpadA, ib = row - qpadB;
+        qa[r] = (ia >= 0 && ia < LqA) ? (int32_t)qsA[ia] : -1;
+        qb[r] = (hasB && ib >= 0 && ib < LqB) ? (int32_t)qsB[ib] : -1;
+      }
+      for (int sy = 0; sy <= n; ++sy) {
+        uint32_t wa[RL / 4], wb[RL / 4];
+#pragma unroll
+        for (int k = 0; k < RL / 4; ++k) { wa[k] = 0u; wb[k] = 0u; }
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+          const uint32_t ba = (qa[r] >= 0 && sy < n) ? (uint32_t)(uint8_t)(s_mat[qa[r] * n + sy] + a.bias) : 0u;
+          const uint32_t bb = (qb[r] >= 0 && sy < n) ? (uint32_t)(uint8_t)(s_mat[qb[r] * n + sy] + a.bias) : 0u;
+          wa[r >> 2] |= ba << (8 * (r & 3));
+          wb[r >> 2] |= bb << (8 * (r & 3));
+        }
+        lds_store_words<RL>(s_profA + ((int64_t)sy * 64 + lane) * RL, wa);
+        lds_store_words<RL>(s_profB + ((int64_t)sy * 64 + lane) * RL, wb);
+      }
+    }
+    lds_wave_sync();
+
+    // code offset of this lane's rows: 65535 - padded row of row r is
+    // (RL - 1 - r) + DL
+    const uint32_t DL = 65535u - (uint32_t)((int64_t)s * SH + lane * RL + RL - 1);
+    int32_t avail = 0;
+    bool spin_fail = false;
+    auto wait_for = [&](int32_t need) {
+      if (s == 0) return;
+      int64_t spins = 0;
+      for (;;) {
+        const int32_t done = __hip_atomic_load(&s_done[s - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        avail = __hip_atomic_load(&s_prog[s - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (done || avail >= need) break;
+        if (++spins > kSpinLimit) { spin_fail = true; break; }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    };
+
+    V16 H[RL], E[RL];
+#pragma unroll
+    for (int r = 0; r < RL; ++r) { H[r] = T::zero(); E[r] = T::zero(); }
+    V16 hup_prev = T::zero();
+    V16 hout = T::zero(), fout = T::zero();
+    uint32_t cmoutA = 0u, cmoutB = 0u, sym = (uint32_t)n * 0x101u;
+    uint32_t symbuf = 0u, hbuf = 0u, fbuf = 0u;
+    uint32_t obHA = 0u, obFA = 0u, obCA = 0u, obHB = 0u, obFB = 0u, obCB = 0u;
+    const int64_t nsteps = width + 63;
+
+    // store the lane-63 outputs of steps' columns [cbase, cbase + cnt) (offsets
+    // from each job's first computed column)
+    auto flush = [&](int64_t cbase, int cnt) {
+      if (lane < cnt) {
+        const int64_t off = cbase + lane;
+        if (off < widthA) {
+          if (hand_over) { bHA[off] = obHA; bFA[off] = obFA; }
+          const int64_t col = jA.cw + off;
+          if (col >= jA.c0 && col < jA.c1) atomicMax(&mcA[col], obCA);
+        }
+        if (hasB && off < widthB) {
+          if (hand_over) { bHB[off] = obHB; bFB[off] = obFB; }
+          const int64_t col = jB.cw + off;
+          if (col >= jB.c0 && col < jB.c1) atomicMax(&mcB[col], obCB);
+        }
+      }
+      if (hand_over) publish((int32_t)(cbase + cnt), false);
+    };
+
+#pragma unroll 1
+    for (int64_t t = 0; t < nsteps; ++t) {
+      const int tm = (int)(t & 63);
+      if (tm == 0) {
+        // inputs of lane 0 for the next 64 steps, both jobs
+        const int64_t cend = (t + 64 < width) ? t + 64 : width;
+        if (s > 0 && cend > 0) wait_for((int32_t)cend);
+        const int64_t off = t + lane;
+        const int64_t cA = jA.cw + off, cB = (hasB ? jB.cw : 0) + off;
+        const bool inA = off < widthA, inB = hasB && off < widthB;
+        const uint32_t sa = inA ? (uint32_t)(uint8_t)rsA[cA] : (uint32_t)n;
+        const uint32_t sb = inB ? (uint32_t)(uint8_t)rsB[cB] : (uint32_t)n;
+        symbuf = sa | (sb << 8);
+        const bool prev = s > 0 && off < avail;
+        const uint32_t ha = (prev && inA) ? __hip_atomic_load(&iHA[off], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        const uint32_t fa = (prev && inA) ? __hip_atomic_load(&iFA[off], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        const uint32_t hb = (prev && inB) ? __hip_atomic_load(&iHB[off], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        const uint32_t fb = (prev && inB) ? __hip_atomic_load(&iFB[off], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        hbuf = perm(hb, ha, 0x05040100u);   // A in the low half, B in the high half
+        fbuf = perm(fb, fa, 0x05040100u);
+      }
+      const V16 hup = T::from(from_above(T::bits(hout), lane_value(hbuf, tm)));
+      V16 F = T::from(from_above(T::bits(fout), lane_value(fbuf, tm)));
+      const uint32_t cminA = from_above(cmoutA, 0u), cminB = from_above(cmoutB, 0u);
+      sym = from_above(sym, lane_value(symbuf, tm));
+
+      uint32_t XA[RL / 4], XB[RL / 4];
+      lds_load_words<RL>(s_profA + ((int64_t)(sym & 0xFFu) * 64 + lane) * RL, XA);
+      lds_load_words<RL>(s_profB + ((int64_t)((sym >> 8) & 0xFFu) * 64 + lane) * RL, XB);
+      uint32_t cmA = 0u, cmB = 0u;
+      auto score_of = [&](int r) -> V16 { return T::from(perm(XB[r >> 2], XA[r >> 2], T::sel_const(r & 3))); };
+      V16 u_next = T::max(T::add(hup_prev, score_of(0)), E[0]);
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const V16 u = u_next;
+        if (r + 1 < RL) u_next = T::max(T::add(H[r], score_of(r + 1)), E[r + 1]);
+        const V16 hb = T::max(u, F);
+        const V16 hn = T::subs(hb, vbias);
+        H[r] = hn;
+        const uint32_t kc = (uint32_t)(RL - 1 - r);
+        const uint32_t wa = perm(T::bits(hn), kc, selA), wb = perm(T::bits(hn), kc, selB);
+        cmA = cmA > wa ? cmA : wa;
+        cmB = cmB > wb ? cmB : wb;
+        const V16 ho = T::subs(hb, vo);
+        E[r] = T::max(T::subs(E[r], ve), ho);
+        F = T::max(T::subs(F, ve), ho);
+      }
+      hup_prev = hup;
+      hout = H[RL - 1];
+      fout = F;
+      const uint32_t cmlA = cmA + DL, cmlB = cmB + DL;
+      cmoutA = cminA > cmlA ? cminA : cmlA;
+      cmoutB = cminB > cmlB ? cminB : cmlB;
+
+      if (t >= 63) {
+        const int j = (int)((t - 63) & 63);
+        const uint32_t oh = lane_value(T::bits(hout), 63), of = lane_value(T::bits(fout), 63);
+        obHA = set_lane(obHA, j, oh & 0xFFFFu);
+        obFA = set_lane(obFA, j, of & 0xFFFFu);
+        obHB = set_lane(obHB, j, oh >> 16);
+        obFB = set_lane(obFB, j, of >> 16);
+        obCA = set_lane(obCA, j, lane_value(cmoutA, 63));
+        obCB = set_lane(obCB, j, lane_value(cmoutB, 63));
+        if (j == 63 || t == nsteps - 1) flush(t - 63 - j, j + 1);
+      }
+    }
+    publish((int32_t)width, true);
+    if (spin_fail && lane == 0) {
+      a.err[pA] = 1;
+      if (hasB) a.err[pB] = 1;
+    }
+  }
+}
+
 // ---- end of the best alignment and score2 from the max array --------------
 // Two phases: blocks (slice, pair) reduce a slice of one pair's max array to
 // its best (value, column) -- the largest value, then the smallest column --
@@ -489,6 +704,28 @@ static void launch_rl(const IntraArgs &a, int waves, bool rev, hipStream_t st) {
   if (rev) hipLaunchKernelGGL((k_intra_fill<RL, true>), g, b, lds, st, a);
   else hipLaunchKernelGGL((k_intra_fill<RL, false>), g, b, lds, st, a);
 }
+
+template <int RL>
+static void launch_rl16(const IntraArgs &a, int waves, hipStream_t st) {
+  const dim3 g((unsigned)(a.njobs / 2)), b(64 * waves);
+  const size_t lds = intra_lds_bytes16(a.n, RL) * waves;
+  hipLaunchKernelGGL((k_intra_fill16<RL>), g, b, lds, st, a);
+}
+
+hipError_t intra_fill16(const IntraArgs &a, int RL, int waves, hipStream_t st) {
+  if (a.njobs == 0) return hipSuccess;
+  if (waves < 1 || waves > kMaxWaves || (a.njobs & 1)) return hipErrorInvalidValue;
+  switch (RL) {
+    case 4: launch_rl16<4>(a, waves, st); break;
+    case 8: launch_rl16<8>(a, waves, st); break;
+    case 16: launch_rl16<16>(a, waves, st); break;
+    case 32: launch_rl16<32>(a, waves, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+size_t intra_lds_bytes16(int n, int RL) { return 2 * (size_t)(n + 1) * 64 * RL; }
 
 hipError_t intra_fill(const IntraArgs &a, int RL, int waves, bool rev, hipStream_t st) {
   if (a.njobs == 0) return hipSuccess;

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -155,6 +156,7 @@ struct swx_ctx {
   int32_t fill_rows = 32;                  // strip height of the batched fill
   int32_t fill_sched = 1;                  // task order of the batched fill (InterArgs::sched)
   int32_t fill_coop = 0;                   // cooperative tasks: 0 automatic, 1 never, 2 always
+  int32_t intra_bits = 0;                  // long pairs' lanes: 0 automatic, 16 where scores fit, 32
   int32_t cus = 0;                         // compute units of the device
   unsigned long long *queue = nullptr;     // work-queue counter of the batched fill
   // side streams (default priority) for independent kernels of one stage
@@ -825,7 +827,82 @@ static int intra_waves(int64_t nstrips, int n, int RL) {
   return (int)std::max<int64_t>(w, 1);
 }
 
-// Upload jobs (grouped by rows per lane and waves) and launch them.
+// Waves per workgroup of a 16-bit job pair (two profiles per wave in LDS).
+static int intra_waves16(int64_t nstrips, int n, int RL) {
+  const int64_t per = (int64_t)intra_lds_bytes16(n, RL);
+  const int64_t room = (65536 - 4096) / per;
+  int64_t w = std::min<int64_t>({nstrips, (int64_t)intra_max_waves(), room});
+  return (int)std::max<int64_t>(w, 1);
+}
+
+// Widest span of a positive-scoring path (the warm-up of every chunk of a
+// long pair): the reference length when gaps cost nothing to extend.
+static int64_t intra_warmup(const Scoring &sc, int64_t Lq, int64_t Lr) {
+  if (sc.e <= 0) return Lr;
+  return Lq + std::max<int64_t>((int64_t)sc.smax * Lq - sc.o, 0) / sc.e + 1;
+}
+
+// Column chunk width of a long pair: its share (by reference length) of
+// `target` chunks over all long pairs, at least 256 columns and half the
+// warm-up, and the whole reference when the warm-up spans it.
+static int64_t intra_chunk(const Scoring &sc, int64_t Lq, int64_t Lr, int64_t target,
+                           int64_t total_r) {
+  const int64_t W = intra_warmup(sc, Lq, Lr);
+  if (W >= Lr) return std::max<int64_t>(Lr, 1);
+  const int64_t want = std::max<int64_t>(1, target * Lr / std::max<int64_t>(total_r, 1));
+  const int64_t C = (Lr + want - 1) / want;
+  return std::max<int64_t>(C, std::max<int64_t>(256, W / 2));
+}
+
+// Packed 16-bit lanes hold a long pair when no score can pass 2^15 - 2 (the
+// a-priori bound smax * min(qlen, rlen) with the bias added on the way: T6)
+// and its padded height fits a 16-bit row code.
+static bool intra_fits16(const Scoring &sc, int64_t Lq, int64_t Lr, int RL) {
+  const int64_t bound = (int64_t)std::max(sc.smax, 0) * std::min(Lq, Lr);
+  return bound + sc.bias <= 32766 && round_up(Lq, 64 * RL) <= 65536;
+}
+
+// 16-bit waves per compute unit from which the automatic choice takes them.
+static constexpr int64_t kIntra16MinWavesPerCu = 4;
+
+// 16-bit forward jobs keyed by (rows per lane, strips): jobs of one key share
+// their padded height, so any two of them can share a wave.
+typedef std::map<std::pair<int, int64_t>, std::vector<IntraJob>> Jobs16;
+
+// Upload the 16-bit jobs (each key's list padded to an even count with an
+// empty job) and launch them, a pair of jobs per workgroup.
+static int launch_intra16_jobs(swx_ctx *ctx, const Jobs16 &jobs, IntraArgs a, const Scoring &sc) {
+  if (jobs.empty()) return SWX_OK;
+  std::vector<IntraJob> all;
+  std::vector<std::pair<int64_t, int64_t>> span;   // per key: first job, count
+  for (const auto &kv : jobs) {
+    const int64_t first = (int64_t)all.size();
+    all.insert(all.end(), kv.second.begin(), kv.second.end());
+    if (all.size() & 1) {
+      IntraJob none{};
+      none.pair = -1;
+      all.push_back(none);
+    }
+    span.push_back({first, (int64_t)all.size() - first});
+  }
+  IntraJob *dj = ctx->arena.get<IntraJob>((int64_t)all.size());
+  if (!dj) return fail(SWX_ENOMEM, "device pool exhausted (intra jobs)");
+  HIP_TRY(hipMemcpyAsync(dj, all.data(), sizeof(IntraJob) * all.size(), hipMemcpyHostToDevice,
+                         ctx->stream));
+  size_t k = 0;
+  for (const auto &kv : jobs) {
+    const int RL = kv.first.first;
+    a.jobs = dj + span[k].first;
+    a.njobs = span[k].second;
+    HIP_TRY(intra_fill16(a, RL, intra_waves16(kv.first.second, sc.n, RL), ctx->stream));
+    ++k;
+  }
+  HIP_TRY(hipStreamSynchronize(ctx->stream));   // the host job table must outlive the copy
+  return SWX_OK;
+}
+
+// Upload jobs (grouped by rows per lane and waves) and launch them; bnd: the
+// hand-over rows (null: allocated here, bnd_words of them).
 static int launch_intra_jobs(swx_ctx *ctx, std::vector<IntraJob> jobs[4][9], IntraArgs a,
                              int64_t bnd_words, bool rev) {
   DevArena &A = ctx->arena;
@@ -834,7 +911,7 @@ static int launch_intra_jobs(swx_ctx *ctx, std::vector<IntraJob> jobs[4][9], Int
     for (int w = 0; w <= 8; ++w) all.insert(all.end(), jobs[g][w].begin(), jobs[g][w].end());
   if (all.empty()) return SWX_OK;
   IntraJob *dj = A.get<IntraJob>((int64_t)all.size());
-  a.bnd = A.get<uint32_t>(bnd_words > 0 ? bnd_words : 1);
+  if (!a.bnd) a.bnd = A.get<uint32_t>(bnd_words > 0 ? bnd_words : 1);
   if (!dj || !a.bnd) return fail(SWX_ENOMEM, "device pool exhausted (intra jobs)");
   HIP_TRY(hipMemcpyAsync(dj, all.data(), sizeof(IntraJob) * all.size(), hipMemcpyHostToDevice,
                          ctx->stream));
@@ -857,32 +934,50 @@ static int launch_intra_jobs(swx_ctx *ctx, std::vector<IntraJob> jobs[4][9], Int
 // Forward pass of the long pairs: column chunks with a warm-up overlap, the
 // encoded max array per pair, then the end (T1) of each pair.
 static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, const PairView &view,
-                             const FillOut &out, uint8_t *err) {
+                             const FillOut &out, uint8_t *err, uint8_t *lanebits) {
   DevArena &A = ctx->arena;
   int64_t total_r = 0;
   for (int64_t k = 0; k < lp.nlong; ++k) total_r += std::max<int64_t>(lp.info[6 * k + 1], 1);
   std::vector<IntraJob> jobs[4][9];
+  Jobs16 jobs16;
+  std::vector<int64_t> ids16, ids32;
   lp.pairs.clear();
+  // Packed 16-bit lanes run two chunks per wave, with half the waves per
+  // workgroup (two profiles each in LDS), on twice the chunk target. Chosen
+  // automatically only when those waves still cover every SIMD of the device:
+  // a few long pairs in few chunks finish sooner on 32-bit lanes.
+  bool auto16 = false;
+  if (ctx->intra_bits == 0) {
+    std::map<std::pair<int, int64_t>, int64_t> count;
+    for (int64_t k = 0; k < lp.nlong; ++k) {
+      const int64_t Lq = lp.info[6 * k], Lr = lp.info[6 * k + 1];
+      const int RL = pick_rl(Lq, sc.n);
+      if (Lr == 0 || !intra_fits16(sc, Lq, Lr, RL)) continue;
+      const int64_t C = intra_chunk(sc, Lq, Lr, 2 * ctx->intra_jobs, total_r);
+      count[{RL, round_up(Lq, 64 * RL) / (64 * RL)}] += (Lr + C - 1) / C;
+    }
+    int64_t waves = 0;
+    for (const auto &kv : count)
+      waves += (kv.second + 1) / 2 * intra_waves16(kv.first.second, sc.n, kv.first.first);
+    auto16 = waves >= kIntra16MinWavesPerCu * (int64_t)ctx->cus;
+  }
   int64_t mc_words = 0, bnd_words = 0;
   for (int64_t k = 0; k < lp.nlong; ++k) {
     const int64_t p = lp.ids[k], Lq = lp.info[6 * k], Lr = lp.info[6 * k + 1];
     const int RL = pick_rl(Lq, sc.n);
     const int64_t SH = 64 * RL;
     const int64_t qp = (Lq + SH - 1) / SH * SH;
-    const int kb = code_bits(qp);
     const int64_t bound = (int64_t)std::max(sc.smax, 0) * std::min(Lq, Lr);
+    const bool w16 = (ctx->intra_bits == 16 || auto16) && intra_fits16(sc, Lq, Lr, RL);
+    const int kb = w16 ? 16 : code_bits(qp);
     if (kb > 30 || bound >= (int64_t(1) << (32 - kb)))
       return fail(SWX_EOVERFLOW, "long pair: score range and query length exceed the max-array word");
+    (w16 ? ids16 : ids32).push_back(p);
     IntraPair ip{p, mc_words, kb, (int32_t)SH};
     lp.pairs.push_back(ip);
     if (Lr > 0) {
-      // widest span of a positive-scoring path: the warm-up of every chunk
-      int64_t W = Lr;
-      if (sc.e > 0) W = Lq + std::max<int64_t>((int64_t)sc.smax * Lq - sc.o, 0) / sc.e + 1;
-      const int64_t want = std::max<int64_t>(1, ctx->intra_jobs * Lr / std::max<int64_t>(total_r, 1));
-      int64_t C = (Lr + want - 1) / want;
-      C = std::max<int64_t>(C, std::max<int64_t>(256, W / 2));
-      if (W >= Lr) C = Lr;
+      const int64_t W = intra_warmup(sc, Lq, Lr);
+      const int64_t C = intra_chunk(sc, Lq, Lr, (w16 ? 2 : 1) * ctx->intra_jobs, total_r);
       const int64_t nstrips = qp / SH;
       if (nstrips > intra_max_strips())
         return fail(SWX_EINVAL, "query too long for the intra-sequence path");
@@ -898,7 +993,8 @@ static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
         jb.kbits = kb;
         jb.band = -1;
         bnd_words += 2 * (jb.c1 - jb.cw) * (nstrips - 1);
-        jobs[rl_slot(RL)][waves].push_back(jb);
+        if (w16) jobs16[{RL, nstrips}].push_back(jb);
+        else jobs[rl_slot(RL)][waves].push_back(jb);
       }
     }
     mc_words += Lr;
@@ -919,8 +1015,21 @@ static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
   a.n = sc.n; a.o = sc.o; a.e = sc.e; a.bias = sc.bias;
   a.maxcol = lp.d_maxcol;
   a.err = err;
+  a.bnd = A.get<uint32_t>(bnd_words > 0 ? bnd_words : 1);
+  if (!a.bnd) return fail(SWX_ENOMEM, "device pool exhausted (hand-over rows)");
   int rc;
   if ((rc = launch_intra_jobs(ctx, jobs, a, bnd_words, false))) return rc;
+  if ((rc = launch_intra16_jobs(ctx, jobs16, a, sc))) return rc;
+  // lane widths of the long pairs (diagnostic)
+  for (int w = 0; w < 2; ++w) {
+    const std::vector<int64_t> &ids = w ? ids32 : ids16;
+    if (ids.empty()) continue;
+    int64_t *d = A.get<int64_t>((int64_t)ids.size());
+    if (!d) return fail(SWX_ENOMEM, "device pool exhausted (lane widths)");
+    HIP_TRY(hipMemcpyAsync(d, ids.data(), 8 * ids.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(mark_lanes((int64_t)ids.size(), d, lanebits, w ? 32 : 16, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));   // the host list must outlive the copy
+  }
   IntraPairArgs e{};
   e.pairs = lp.d_pairs; e.maxcol = lp.d_maxcol; e.qlen = view.qlen; e.rlen = view.rlen;
   e.score = out.score; e.qend = out.qend; e.rend = out.rend; e.overflow = out.overflow;
@@ -1074,9 +1183,8 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
     return rc;
   if ((rc = run_fill(ctx, p16, sc, fview, false, nullptr, fout, score_bound, 1, 0, 0, sp))) return rc;
   if (lp.nlong > 0) {
-    if ((rc = run_intra_forward(ctx, sc, lp, fview, fout, err))) return rc;
+    if ((rc = run_intra_forward(ctx, sc, lp, fview, fout, err, lanebits))) return rc;
     HIP_TRY(hipEventRecord(ctx->ev[2], st));
-    HIP_TRY(mark_lanes(lp.nlong, lp.d_long, lanebits, 32, st));
   }
 
   // saturated pairs: exact re-run on 32-bit lanes
@@ -1761,6 +1869,7 @@ int swx_get_tuning(const swx_ctx *ctx, swx_tuning *out) {
   t.side_streams = ctx->side_streams ? 1 : 0;
   t.fill_sched = ctx->fill_sched;
   t.fill_coop = ctx->fill_coop;
+  t.intra_bits = ctx->intra_bits;
   *out = t;
   return SWX_OK;
 }
@@ -1769,7 +1878,8 @@ int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t) {
   if (!ctx || !t) return fail(SWX_EINVAL, "null argument");
   if (t->long_cells < -1 || t->long_rlen < 0 || t->intra_jobs < 1 ||
       (t->side_streams != 0 && t->side_streams != 1) || t->fill_sched < 0 || t->fill_sched > 2 ||
-      t->fill_coop < 0 || t->fill_coop > 2 ||
+      t->fill_coop < 0 || t->fill_coop > 2 || (t->intra_bits != 0 && t->intra_bits != 16 && t->intra_bits != 32) ||
+      t->pad_ != 0 ||
       (t->fill_rows != 16 && t->fill_rows != 24 && t->fill_rows != 32))
     return fail(SWX_EINVAL, "tuning value out of range");
   std::lock_guard<std::mutex> g(ctx->mu);
@@ -1780,6 +1890,7 @@ int swx_set_tuning(swx_ctx *ctx, const swx_tuning *t) {
   ctx->side_streams = t->side_streams != 0;
   ctx->fill_sched = t->fill_sched;
   ctx->fill_coop = t->fill_coop;
+  ctx->intra_bits = t->intra_bits;
   return SWX_OK;
 }
 

@@ -226,6 +226,10 @@ struct IntraPairArgs {
 size_t intra_lds_bytes(int n, int RL);
 int intra_slices();
 hipError_t intra_fill(const IntraArgs &a, int RL, int waves, bool rev, hipStream_t st);
+// forward pass on packed 16-bit lanes: jobs[2b] and jobs[2b + 1] (same padded
+// height; pair -1: none) share workgroup b; a.njobs even
+hipError_t intra_fill16(const IntraArgs &a, int RL, int waves, hipStream_t st);
+size_t intra_lds_bytes16(int n, int RL);
 int intra_max_strips();
 int intra_max_waves();
 hipError_t intra_jobs_fixed(int64_t B, const int64_t *rlen, int32_t kbits, int32_t sh,

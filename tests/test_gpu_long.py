@@ -35,11 +35,33 @@ def ctx():
 
 
 def test_all_long_chunked(ctx):
-    """Every pair through the intra path, references cut into many chunks."""
-    ctx.set_tuning(long_cells=0, long_rlen=0, intra_jobs=400)
+    """Every pair through the intra path, references cut into many chunks, on
+    packed 16-bit lanes (two chunks per wave) and on 32-bit lanes."""
     b = W.random_pairs(701, 40, (1, 900), (0, 6000))
+    for bits in (16, 32, 0):
+        ctx.set_tuning(long_cells=0, long_rlen=0, intra_jobs=400, intra_bits=bits)
+        recs = assert_parity(ctx, b)
+        if bits:
+            assert (recs["lane_bits"][recs["score1"] > 0] == bits).all()
+
+
+def test_intra_lane_width_limit(ctx):
+    """Long pairs whose a-priori score bound lies just inside and just outside
+    the 16-bit lanes (smax * min(qlen, rlen) + bias <= 32766, rule T6): the
+    first take packed 16-bit lanes, the second 32-bit ones, and both reach
+    scores near the limit exactly."""
+    ctx.set_tuning(long_cells=0, long_rlen=0, intra_jobs=64, intra_bits=16)
+    g = np.random.Generator(np.random.PCG64(4094))
+    mat = W.dna_matrix(8, -8)   # smax 8, bias 8: the bound is 8 * L + 8
+    qs, rs = [], []
+    for L in (4094, 4095):
+        ref = g.integers(0, 4, size=L + 300).astype(np.int8)
+        qs.append(ref[100:100 + L].copy())
+        rs.append(ref)
+    b = W.from_lists("intra-16-limit", mat, 10, 2, qs, rs)
     recs = assert_parity(ctx, b)
-    assert (recs["lane_bits"][recs["score1"] > 0] == 32).all()
+    assert list(recs["score1"]) == [8 * 4094, 8 * 4095]
+    assert list(recs["lane_bits"]) == [16, 32]
 
 
 def test_long_gap_settings(ctx):
@@ -87,10 +109,13 @@ def test_tuning_invariance(ctx):
                  {"fill_sched": 0}, {"fill_sched": 2}, {"fill_sched": 2, "fill_rows": 16},
                  {"fill_coop": 1}, {"fill_coop": 2}, {"fill_coop": 2, "fill_sched": 2},
                  {"fill_coop": 2, "fill_sched": 0, "fill_rows": 24},
-                 {"fill_coop": 2, "long_cells": 1 << 62, "long_rlen": 1 << 62}):
+                 {"fill_coop": 2, "long_cells": 1 << 62, "long_rlen": 1 << 62},
+                 {"long_cells": 0, "long_rlen": 0, "intra_bits": 32},
+                 {"long_cells": 0, "long_rlen": 0, "intra_bits": 16},
+                 {"long_cells": 0, "long_rlen": 0, "intra_jobs": 4000}):
         ctx.set_tuning(**{"long_cells": 1 << 22, "long_rlen": 1 << 16, "intra_jobs": 2048,
                           "fill_rows": 32, "side_streams": 1, "fill_sched": 1, "fill_coop": 0,
-                          **tune})
+                          "intra_bits": 0, **tune})
         _say(f"[tuning] {tune}")
         recs, cig = ctx.align_batch(b.matrix, b.gap_open, b.gap_extend, b.qcat, b.qoff, b.rcat,
                                     b.roff, b.pair_q, b.pair_r)
@@ -106,7 +131,7 @@ def test_tuning_invariance(ctx):
 def test_tuning_rejects_bad_values(ctx):
     for bad in ({"fill_rows": 20}, {"intra_jobs": 0}, {"long_cells": -2}, {"long_rlen": -1},
                 {"side_streams": 2}, {"fill_sched": 3}, {"fill_sched": -1}, {"fill_coop": 3},
-                {"fill_coop": -1}):
+                {"fill_coop": -1}, {"intra_bits": 8}, {"intra_bits": -1}):
         with pytest.raises(swx.SwxError) as ei:
             ctx.set_tuning(**bad)
         assert ei.value.status == -1

@@ -25,14 +25,16 @@ def _say(msg):
 # onto the batched (one pair per lane half) path with 32- and with 24-row
 # strips, one wave per task and (cooperative) a workgroup's four waves per
 # task, in grid order and from the device queue, and with every pair forced
-# onto the intra-sequence (one pair per wave) path.
+# onto the intra-sequence (one pair per wave) path, on packed 16-bit lanes
+# where the scores fit and on 32-bit lanes throughout.
 PATHS = {"auto": {"long_cells": -1},
          "rows24": {"long_cells": 1 << 62, "long_rlen": 1 << 62, "fill_rows": 24},
          "batched": {"long_cells": 1 << 62, "long_rlen": 1 << 62, "fill_coop": 1},
          "coop": {"long_cells": 1 << 62, "long_rlen": 1 << 62, "fill_coop": 2},
          "coop_queue": {"long_cells": 1 << 62, "long_rlen": 1 << 62, "fill_coop": 2,
                         "fill_sched": 2, "fill_rows": 16},
-         "intra": {"long_cells": 0, "long_rlen": 0, "intra_jobs": 256}}
+         "intra": {"long_cells": 0, "long_rlen": 0, "intra_jobs": 256, "intra_bits": 16},
+         "intra32": {"long_cells": 0, "long_rlen": 0, "intra_jobs": 256, "intra_bits": 32}}
 
 
 @pytest.fixture(scope="module", params=list(PATHS))
@@ -144,7 +146,7 @@ def test_lane_width_threshold(ctx):
         rs.append(ref)
     b = W.from_lists("threshold", mat, 10, 2, qs, rs)
     recs = assert_parity(ctx, b)
-    if ctx.path in ("batched", "rows24"):
+    if ctx.path in ("batched", "rows24", "coop", "coop_queue"):
         assert set(recs["lane_bits"]) == {16, 32}
 
 
