@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed steps (no autotuner, output modes, graph, per-pair, "
                          "serving or CPU phases): the form the kernel profiles are taken of")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the per-configuration phase (the other four workloads)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (default: tune on a 100k-pair sample first)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -288,6 +290,180 @@ def graph_phase(ctx, batch=512, reps=20):
     return out
 
 
+PEAK_U32_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit lanes: one operation per lane-op
+
+
+def _dev_call(ctx, b, reps):
+    """Best and median of `reps` timed calls (after one untimed) of the whole
+    path on b with device-resident inputs and outputs; returns the times, the
+    library's per-stage times of the best call and the outputs of the last."""
+    import numpy as np
+    import torch
+
+    import paper_1208_6350_amd as swx
+    dev = torch.device("cuda:0")
+    to = lambda x: torch.as_tensor(np.ascontiguousarray(x)).to(dev)
+    dq, dqo, dr, dro, dpq, dpr = (to(b.qcat), to(b.qoff), to(b.rcat), to(b.roff), to(b.pair_q),
+                                  to(b.pair_r))
+    recs = torch.empty(b.npairs * swx.REC_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    cig = torch.empty(int(b.qlen().sum() + b.rlen().sum() + b.npairs), dtype=torch.int32,
+                      device=dev)
+    ts, stages, used = [], None, 0
+    for k in range(reps + 1):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, used = swx.swx_align_batch(ctx.handle, b.matrix, b.gap_open, b.gap_extend, dq, dqo,
+                                       dr, dro, dpq, dpr, swx.SWX_ALL, -1, swx.SWX_MEM_DEVICE,
+                                       recs, cig, swx.SWX_MEM_DEVICE)
+        torch.cuda.synchronize()
+        if st != 0:
+            raise swx.SwxError(st, "swx_align_batch")
+        if k:
+            ts.append(time.perf_counter() - t)
+            if ts[-1] == min(ts):
+                stages = ctx.stage_ms()
+    out = (recs.cpu().numpy().view(swx.REC_DTYPE).copy(),
+           cig[:used].cpu().numpy().view(np.uint32).copy())
+    return ts, stages, out
+
+
+def _entry(name, workload, b, ts, stages, recs, oracle_t, parity):
+    """One per-configuration record: whole-path time and rate, the forward
+    fill against the integer-VALU peak of the lanes it ran on, the oracle's
+    time beside it and the parity of the GPU outputs."""
+    import numpy as np
+    best = min(ts)
+    cells = b.cells()
+    bits = sorted(set(int(x) for x in recs["lane_bits"]))
+    # the roofline of the lanes each pair ran on: packed 16-bit lanes at the
+    # packed peak, 32-bit lanes (saturated re-runs, wide long pairs) at half
+    pc = (b.qlen()[b.pair_q].astype(np.float64) * b.rlen()[b.pair_r])
+    w16 = recs["lane_bits"] == 16
+    c16, c32 = float(pc[w16].sum()), float(pc[~w16].sum())
+    ideal_s = (c16 / PEAK_PK16_TOPS + c32 / PEAK_U32_TOPS) * OPS_PER_CELL / 1e12
+    fill = stages[1]
+    names = ["prepare", "fill", "rerun32", "reverse", "traceback", "score2", "records"]
+    return {"workload": workload, "pairs": b.npairs, "cells": cells,
+            "ms": round(best * 1e3, 3), "median_ms": round(float(np.median(ts)) * 1e3, 3),
+            "gcups": round(cells / best / 1e9, 2), "lane_bits": bits,
+            "stages_ms": {n: round(v, 3) for n, v in zip(names, stages)},
+            "roofline": {"bound": "alu", "unit": "Tops/s",
+                         "peak_16": round(PEAK_PK16_TOPS, 2), "peak_32": round(PEAK_U32_TOPS, 2),
+                         "cells_16": c16, "cells_32": c32,
+                         "ideal_fill_ms": round(ideal_s * 1e3, 4),
+                         "fill_frac": round(ideal_s / (fill * 1e-3), 4),
+                         "path_frac": round(ideal_s / best, 4)},
+            "oracle": oracle_t, "parity": parity}
+
+
+def config_phase(ctx, reps=3, with_oracle=True):
+    """The other workloads, each timed alone through the same entry point:
+    the single short pair (also one call per pair through swx_align), the
+    single long-reference pair, the protein one-against-many search at full
+    size and one long serving request.  Beside each, the oracle's time on a
+    bounded sample of it and the parity of the GPU result (against the
+    oracle's, or for the long-reference pair its stored result)."""
+    import numpy as np
+
+    import workloads as W
+    if with_oracle:
+        import oracle
+        from tests.fullsize import mismatches
+    threads = os.cpu_count() or 1
+    out = {}
+
+    def oracle_pairs(b, n):
+        s = b.subset(np.arange(n))
+        t = time.perf_counter()
+        ref, rcig, rcoff = oracle.align_many(s.qcat, s.qoff, s.rcat, s.roff, s.pair_q, s.pair_r,
+                                             s.matrix, s.gap_open, s.gap_extend,
+                                             nthreads=threads)
+        dt = time.perf_counter() - t
+        return s, dt, (ref, rcig, rcoff)
+
+    def check(recs, cig, n, res):
+        bad = mismatches(recs[:n], cig, *res)
+        return {"pairs": n, "mismatches": bad["pairs_bad"]}
+
+    # single short pair: batch entry point, and per call through swx_align
+    b = W.config1()
+    ts, st, (recs, cig) = _dev_call(ctx, b, reps * 10)
+    orc = par = None
+    if with_oracle:
+        s, dt, res = oracle_pairs(b, 1)
+        orc = {"seconds": round(dt, 4), "gcups": round(b.cells() / dt / 1e9, 4), "cores": 1,
+               "sample": "the whole pair"}
+        par = check(recs, cig, 1, res)
+    e = _entry("c1", "one DNA pair: 150-nt read vs 2,000-nt window", b, ts, st, recs, orc, par)
+    q, r = b.query(0), b.ref(0)
+    for k in range(3):
+        ctx.align_pair(q, r, b.matrix, b.gap_open, b.gap_extend)
+    pt = []
+    for k in range(50):
+        t = time.perf_counter()
+        ctx.align_pair(q, r, b.matrix, b.gap_open, b.gap_extend)
+        pt.append(time.perf_counter() - t)
+    e["per_call"] = {"entry": "swx_align (host buffers, copies included)",
+                     "median_ms": round(float(np.median(pt)) * 1e3, 3),
+                     "min_ms": round(min(pt) * 1e3, 3)}
+    out["c1"] = e
+
+    # single long-reference pair, checked against the oracle's stored result
+    b = W.config2()
+    ts, st, (recs, cig) = _dev_call(ctx, b, reps)
+    orc = par = None
+    if with_oracle:
+        cols = 200_000
+        s = b.subset(np.arange(1))
+        t = time.perf_counter()
+        oracle.align(s.query(0), s.ref(0)[:cols], s.matrix, s.gap_open, s.gap_extend)
+        dt = time.perf_counter() - t
+        orc = {"seconds": round(dt, 3), "gcups": round(1000 * cols / dt / 1e9, 4), "cores": 1,
+               "sample": f"the read against the first {cols} reference columns"}
+        with open(os.path.join(ROOT, "tests", "golden", "config2.json")) as f:
+            gold = json.load(f)
+        fields = ["score1", "score2", "read_begin1", "read_end1", "ref_begin1", "ref_end1",
+                  "ref_end2"]
+        got = {k: int(recs[k][0]) for k in fields}
+        ops = "MIDNSHP=X"
+        words = [(int(w) >> 4, ops[int(w) & 15]) for w in
+                 cig[int(recs["cigar_off"][0]):int(recs["cigar_off"][0]) +
+                     int(recs["cigar_len"][0])]]
+        same = all(got[k] == gold[k] for k in fields) and \
+            words == [(int(n), op) for n, op in gold["cigar"]]
+        par = {"pairs": 1, "mismatches": 0 if same else 1,
+               "checked": "every field and the CIGAR against the oracle's stored result"}
+    out["c2"] = _entry("c2", "one 1,000-nt read vs a 5,000,000-nt reference", b, ts, st, recs,
+                       orc, par)
+
+    # protein one-against-many search, full size
+    b = W.config3()
+    ts, st, (recs, cig) = _dev_call(ctx, b, reps)
+    orc = par = None
+    if with_oracle:
+        n = 20_000
+        s, dt, res = oracle_pairs(b, n)
+        orc = {"seconds": round(dt, 3), "gcups": round(s.cells() / dt / 1e9, 4),
+               "cores": threads, "sample": f"the first {n} targets"}
+        par = check(recs, cig, n, res)
+    out["c3"] = _entry("c3", "protein search: 300-aa query vs 100,000 targets (50-5,000 aa)",
+                       b, ts, st, recs, orc, par)
+
+    # one long serving request alone
+    pool = W.config5_pool(n_short=1, n_long=1)
+    b = pool.subset(np.arange(1, 2))
+    ts, st, (recs, cig) = _dev_call(ctx, b, reps)
+    orc = par = None
+    if with_oracle:
+        s, dt, res = oracle_pairs(b, 1)
+        orc = {"seconds": round(dt, 3), "gcups": round(b.cells() / dt / 1e9, 4), "cores": 1,
+               "sample": "the whole pair"}
+        par = check(recs, cig, 1, res)
+    out["c5_long"] = _entry("c5_long", "one long serving request: 10,000-nt read vs "
+                            "20,000-nt window, 10% error", b, ts, st, recs, orc, par)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -403,6 +579,14 @@ def main():
     # graph mode against the ordinary call on small batches of short pairs
     # (serving-sized: where per-call planning and launches dominate)
     graph_cmp = None if args.headline_only else graph_phase(ctx)
+    configs = None
+    if not args.headline_only and not args.no_configs:
+        print("[bench] per-configuration phase", flush=True, file=sys.stderr)
+        cctx = swx.Context(0)   # the library's default settings, not those tuned above
+        try:
+            configs = config_phase(cctx, with_oracle=not args.no_cpu)
+        finally:
+            cctx.close()
     avsa = None if args.headline_only else all_vs_all_phase(ctx)
 
     # per-pair form: the same library, one pair per call
@@ -454,6 +638,7 @@ def main():
         "graph": graph_cmp,
         "lane_widths": lanes,
         "all_vs_all": avsa,
+        "configs": configs,
         "per_pair": per_pair,
     }
     if not args.no_serve and not args.headline_only:

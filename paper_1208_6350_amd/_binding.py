@@ -185,6 +185,14 @@ def lib():
                 raise RuntimeError(
                     f"{path} is missing: build it with `python -m paper_1208_6350_amd.build` "
                     "(there is no CPU fallback)")
+            # One HIP runtime per process: torch carries its own libamdhip64
+            # under the same soname as the system's, so it is loaded first and
+            # the library binds to that copy (loaded the other way round,
+            # torch finds no device).
+            try:
+                import torch  # noqa: F401
+            except ImportError:
+                pass
             L = ctypes.CDLL(path)
             for name, (res, args) in _SIGS.items():
                 f = getattr(L, name)
