@@ -84,7 +84,15 @@ __device__ __forceinline__ void lds_store_words(uint8_t *dst, const uint32_t (&w
 // strip depends only on the one above, the waves of a workgroup are resident
 // together, and no strip ever waits on a later one, so the waits always end;
 // a spin limit still bounds them (exceeding it flags the pair as failed).
-constexpr int kMaxStrips = 256;
+//
+// Spread jobs (SPREAD): the strips of one job run on the waves of `segs`
+// workgroups (global wave g = segment * NW + wave takes strips g, g + segs*NW,
+// ...), with the progress counters, the reversed pass's hits and a completion
+// count in global memory (IntraSync, agent-scope release and acquire).  The
+// host launches a spread grid only when every workgroup of it fits on the
+// device at once (at most one per compute unit), so a strip's producer is
+// always running; the same spin limit bounds the waits.
+constexpr int kMaxStrips = kIntraMaxStrips;
 constexpr int kMaxWaves = 8;
 constexpr int64_t kSpinLimit = int64_t(1) << 26;
 
@@ -93,20 +101,39 @@ __device__ __forceinline__ void lds_wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <int RL, bool REV>
+template <int RL, bool REV, bool SPREAD>
 __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
   extern __shared__ uint4 s_dyn[];            // per wave: [(n + 1) symbols][64 lanes][RL bytes]
   __shared__ int8_t s_mat[32 * 32];
-  __shared__ int32_t s_prog[kMaxStrips];      // columns published by strip s (from its window start)
-  __shared__ int32_t s_done[kMaxStrips];      // strip s finished (s_prog is final)
-  __shared__ int64_t s_rcol[kMaxStrips];      // reversed pass: first column of strip s reaching the target
-  __shared__ int32_t s_rrow[kMaxStrips];
-  __shared__ unsigned long long s_best;       // reversed pass: smallest such column so far (~0: none)
+  __shared__ int32_t l_prog[SPREAD ? 1 : kMaxStrips];      // columns published by strip s (from its window start)
+  __shared__ int32_t l_done[SPREAD ? 1 : kMaxStrips];      // strip s finished (its progress is final)
+  __shared__ int64_t l_rcol[SPREAD ? 1 : kMaxStrips];      // reversed pass: first column of strip s reaching the target
+  __shared__ int32_t l_rrow[SPREAD ? 1 : kMaxStrips];
+  __shared__ unsigned long long l_best;       // reversed pass: smallest such column so far (~0: none)
   constexpr int SH = 64 * RL;
+  constexpr int SCOPE = SPREAD ? __HIP_MEMORY_SCOPE_AGENT : __HIP_MEMORY_SCOPE_WORKGROUP;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int NW = blockDim.x >> 6;
-  const IntraJob jb = a.jobs[blockIdx.x];
+  // spread grids: workgroups go to the 8 XCDs round robin by block id, so
+  // block 8 * slot + x (slot = (j / 8) * G + segment) puts every segment of
+  // job j on XCD j % 8, where the hand-over rows stay in one L2; the grid is
+  // 8 * G * ceil(njobs / 8) blocks and those past the last job leave at once
+  const int G = SPREAD ? a.segs : 1;
+  int64_t jix = blockIdx.x, seg = 0;
+  if constexpr (SPREAD) {
+    const int64_t slot = blockIdx.x / 8;
+    jix = (slot / G) * 8 + blockIdx.x % 8;
+    seg = slot % G;
+    if (jix >= a.njobs) return;
+  }
+  IntraSync *gs = SPREAD ? a.sync + jix : nullptr;
+  int32_t *s_prog = SPREAD ? gs->prog : l_prog;
+  int32_t *s_done = SPREAD ? gs->done : l_done;
+  int64_t *s_rcol = SPREAD ? gs->rcol : l_rcol;
+  int32_t *s_rrow = SPREAD ? gs->rrow : l_rrow;
+  unsigned long long *s_best = SPREAD ? &gs->best : &l_best;
+  const IntraJob jb = a.jobs[jix];
   const int64_t p = jb.pair;
   const int32_t Lq = a.view.qlen[p];
   const int64_t Lr = a.view.rlen[p];
@@ -117,13 +144,15 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
   const int64_t qp = ((int64_t)Lq + SH - 1) / SH * SH;
   const int nstrips = (int)(qp / SH);
   for (int i = threadIdx.x; i < n * n; i += blockDim.x) s_mat[i] = a.matrix[i];
-  for (int i = threadIdx.x; i < nstrips && i < kMaxStrips; i += blockDim.x) {
-    s_prog[i] = 0;
-    s_done[i] = 0;
-    s_rcol[i] = -1;
-    s_rrow[i] = -1;
+  if constexpr (!SPREAD) {   // spread jobs: set by intra_sync_init before the launch
+    for (int i = threadIdx.x; i < nstrips && i < kMaxStrips; i += blockDim.x) {
+      s_prog[i] = 0;
+      s_done[i] = 0;
+      s_rcol[i] = -1;
+      s_rrow[i] = -1;
+    }
+    if (threadIdx.x == 0) *s_best = ~0ull;
   }
-  if (threadIdx.x == 0) s_best = ~0ull;
   __syncthreads();
 
   const int64_t qpad = REV ? 0 : qp - Lq;   // forward: padding rows on top
@@ -149,7 +178,16 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
     if (chi < clo) chi = clo;
   };
 
-  for (int s = wave; s < nstrips; s += NW) {
+  auto fence_rel = [] {
+    if constexpr (SPREAD) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  };
+  auto fence_acq = [] {
+    if constexpr (SPREAD) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  };
+
+  for (int s = (int)seg * NW + wave; s < nstrips; s += G * NW) {
     int64_t clo, chi, plo = 0, phi = 0;
     window(s, clo, chi);
     if (s > 0) window(s - 1, plo, phi);
@@ -160,15 +198,14 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
     const bool hand_over = (s + 1 < nstrips);
     int32_t published = 0;
     auto publish = [&](int32_t ncols, bool fin) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      fence_rel();
       if (lane == 0) {
-        __hip_atomic_store(&s_prog[s], ncols, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (fin) __hip_atomic_store(&s_done[s], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_store(&s_prog[s], ncols, __ATOMIC_RELAXED, SCOPE);
+        if (fin) __hip_atomic_store(&s_done[s], 1, __ATOMIC_RELAXED, SCOPE);
       }
     };
     // the reversed pass skips a strip that cannot hold an earlier column
-    if (REV && __hip_atomic_load(&s_best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <=
-                   (unsigned long long)clo) {
+    if (REV && __hip_atomic_load(s_best, __ATOMIC_RELAXED, SCOPE) <= (unsigned long long)clo) {
       publish(0, true);
       continue;
     }
@@ -205,13 +242,13 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
       if (s == 0) return;
       int64_t spins = 0;
       for (;;) {
-        const int32_t done = __hip_atomic_load(&s_done[s - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        avail = __hip_atomic_load(&s_prog[s - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int32_t done = __hip_atomic_load(&s_done[s - 1], __ATOMIC_RELAXED, SCOPE);
+        avail = __hip_atomic_load(&s_prog[s - 1], __ATOMIC_RELAXED, SCOPE);
         if (done || avail >= need) break;
         if (++spins > kSpinLimit) { spin_fail = true; break; }
         __builtin_amdgcn_s_sleep(2);
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      fence_acq();
     };
 
     uint32_t H[RL], E[RL];
@@ -247,8 +284,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
       const int tm = (int)(t & 63);
       if (tm == 0) {
         if (REV && t >= 63 &&
-            (unsigned long long)(clo + t - 63) >=
-                __hip_atomic_load(&s_best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            (unsigned long long)(clo + t - 63) >= __hip_atomic_load(s_best, __ATOMIC_RELAXED, SCOPE)) {
           cdone = clo + t - 63;   // an earlier strip already reached the target at or before here
           break;
         }
@@ -305,7 +341,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
           if (lane == 0) {
             s_rcol[s] = col;
             s_rrow[s] = (int32_t)(M - (oc & M));
-            atomicMin(&s_best, (unsigned long long)col);
+            atomicMin(s_best, (unsigned long long)col);
           }
           break;
         }
@@ -315,7 +351,19 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
     publish((int32_t)(cdone - clo), true);
     if (spin_fail && lane == 0) a.err[p] = 1;   // reported as an internal failure
   }
-  __syncthreads();
+  if constexpr (SPREAD) {
+    if constexpr (!REV) return;
+    // the last segment of the job to finish reduces the strips' hits
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    __shared__ int32_t s_last;
+    if (threadIdx.x == 0) s_last = atomicAdd(&gs->fin, 1) == G - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  } else {
+    __syncthreads();
+  }
 
   if (REV && threadIdx.x == 0) {
     // first column reaching the target; on a tie the earlier strip (smaller row)
@@ -699,10 +747,40 @@ size_t intra_lds_bytes(int n, int RL) { return (size_t)(n + 1) * 64 * RL; }
 
 template <int RL>
 static void launch_rl(const IntraArgs &a, int waves, bool rev, hipStream_t st) {
-  const dim3 g((unsigned)a.njobs), b(64 * waves);
+  const dim3 b(64 * waves);
   const size_t lds = intra_lds_bytes(a.n, RL) * waves;
-  if (rev) hipLaunchKernelGGL((k_intra_fill<RL, true>), g, b, lds, st, a);
-  else hipLaunchKernelGGL((k_intra_fill<RL, false>), g, b, lds, st, a);
+  if (a.segs > 1) {
+    const dim3 g((unsigned)(8 * a.segs * ((a.njobs + 7) / 8)));
+    if (rev) hipLaunchKernelGGL((k_intra_fill<RL, true, true>), g, b, lds, st, a);
+    else hipLaunchKernelGGL((k_intra_fill<RL, false, true>), g, b, lds, st, a);
+    return;
+  }
+  const dim3 g((unsigned)a.njobs);
+  if (rev) hipLaunchKernelGGL((k_intra_fill<RL, true, false>), g, b, lds, st, a);
+  else hipLaunchKernelGGL((k_intra_fill<RL, false, false>), g, b, lds, st, a);
+}
+
+__global__ void k_intra_sync_init(IntraSync *sync, int64_t njobs) {
+  const int64_t j = blockIdx.x;
+  if (j >= njobs) return;
+  IntraSync &y = sync[j];
+  for (int i = threadIdx.x; i < kIntraMaxStrips; i += blockDim.x) {
+    y.prog[i] = 0;
+    y.done[i] = 0;
+    y.rcol[i] = -1;
+    y.rrow[i] = -1;
+  }
+  if (threadIdx.x == 0) {
+    y.best = ~0ull;
+    y.fin = 0;
+    y.pad_ = 0;
+  }
+}
+
+hipError_t intra_sync_init(IntraSync *sync, int64_t njobs, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_intra_sync_init, dim3((unsigned)njobs), dim3(256), 0, st, sync, njobs);
+  return hipGetLastError();
 }
 
 template <int RL>
@@ -729,7 +807,8 @@ size_t intra_lds_bytes16(int n, int RL) { return 2 * (size_t)(n + 1) * 64 * RL; 
 
 hipError_t intra_fill(const IntraArgs &a, int RL, int waves, bool rev, hipStream_t st) {
   if (a.njobs == 0) return hipSuccess;
-  if (waves < 1 || waves > kMaxWaves) return hipErrorInvalidValue;
+  if (waves < 1 || waves > kMaxWaves || (a.segs > 1 && !a.sync))
+    return hipErrorInvalidValue;
   switch (RL) {
     case 4: launch_rl<4>(a, waves, rev, st); break;
     case 8: launch_rl<8>(a, waves, rev, st); break;
@@ -742,7 +821,7 @@ hipError_t intra_fill(const IntraArgs &a, int RL, int waves, bool rev, hipStream
 
 int intra_max_strips() { return kMaxStrips; }
 int intra_max_waves() { return kMaxWaves; }
-size_t intra_static_lds() { return 32 * 32 + kMaxStrips * (4 + 4 + 8 + 4) + 8; }
+size_t intra_static_lds() { return 32 * 32 + kMaxStrips * (4 + 4 + 8 + 4) + 8 + 4; }
 
 int intra_slices() { return kSlices; }
 

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -769,8 +770,6 @@ static int pick_rl(int64_t rows, int n) {
   return best;
 }
 
-static int rl_slot(int RL) { return RL == 4 ? 0 : RL == 8 ? 1 : RL == 16 ? 2 : 3; }
-
 // Pairs above this many cells go to the intra-sequence path.  In the batched
 // path a pair occupies one 16-bit lane half for cells * t; a full GPU holds
 // about 2048 waves * 128 halves, so a pair larger than twice the batch's
@@ -865,6 +864,60 @@ static bool intra_fits16(const Scoring &sc, int64_t Lq, int64_t Lr, int RL) {
 // 16-bit waves per compute unit from which the automatic choice takes them.
 static constexpr int64_t kIntra16MinWavesPerCu = 4;
 
+// Launch shape of intra-sequence jobs: rows per lane, waves per workgroup and
+// workgroups per job (segs > 1: the job's strips spread over that many).
+struct IntraShape {
+  int rl, waves, segs;
+  bool operator<(const IntraShape &o) const {
+    return std::tie(rl, waves, segs) < std::tie(o.rl, o.waves, o.segs);
+  }
+};
+typedef std::map<IntraShape, std::vector<IntraJob>> IntraGroups;
+
+// Shape of a job of `rows` query rows over `width` columns (band >= 0: the
+// reversed pass's strip windows, SH + 2 * band wide and SH apart) when `jobs`
+// such jobs share the device.  With at least one job per compute unit the
+// device is full: the fewest instructions over all strips (pick_rl).  With
+// fewer, a job is as slow as its longer of two paths: the chain of strips,
+// each starting about 128 columns (banded: SH + 128) after the one above, and
+// the strips each wave runs in turn; a step costs about 12 instructions per
+// row of a lane plus 20.  Those jobs spread over up to four waves per
+// workgroup (one per SIMD) and as many workgroups as fit at once: at most one
+// per compute unit, and 32 (the compute units of one XCD) per XCD.
+static IntraShape intra_shape(int64_t rows, int64_t width, int32_t band, int n, int64_t jobs,
+                              int32_t cus) {
+  jobs = std::max<int64_t>(jobs, 1);
+  if (jobs >= cus || cus <= 0) {
+    const int RL = pick_rl(rows, n);
+    return {RL, intra_waves((rows + 64 * RL - 1) / (64 * RL), n, RL), 1};
+  }
+  const int64_t segs_max =
+      std::max<int64_t>(1, std::min<int64_t>(cus / jobs, 32 / ((jobs + 7) / 8)));
+  IntraShape best{pick_rl(rows, n), 1, 1};
+  double best_cost = -1;
+  for (int RL : {4, 8, 16, 32}) {
+    if (intra_lds_bytes(n, RL) + intra_static_lds() > 65536) continue;
+    const int64_t SH = 64 * RL;
+    const int64_t nstrips = std::max<int64_t>(1, (rows + SH - 1) / SH);
+    if (nstrips > intra_max_strips()) continue;
+    int64_t nw = std::min<int64_t>(4, intra_waves(nstrips, n, RL));
+    const int64_t g = std::min<int64_t>(segs_max, (nstrips + nw - 1) / nw);
+    if (g == 1) nw = intra_waves(nstrips, n, RL);
+    const int64_t win = band >= 0 ? std::min<int64_t>(width, SH + 2 * (int64_t)band) : width;
+    const int64_t lag = (band >= 0 ? SH : 0) + 128;
+    const int64_t tw = g * nw;
+    const int64_t chain = (nstrips - 1) * lag + win;
+    const int64_t turns = (nstrips + tw - 1) / tw * (win + 63);
+    // two waves share a SIMD beyond four per workgroup
+    const double cost = (double)std::max(chain, turns) * (12 * RL + 20) * (nw > 4 ? 1.5 : 1.0);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = {RL, (int)nw, (int)g};
+    }
+  }
+  return best;
+}
+
 // 16-bit forward jobs keyed by (rows per lane, strips): jobs of one key share
 // their padded height, so any two of them can share a wave.
 typedef std::map<std::pair<int, int64_t>, std::vector<IntraJob>> Jobs16;
@@ -901,30 +954,35 @@ static int launch_intra16_jobs(swx_ctx *ctx, const Jobs16 &jobs, IntraArgs a, co
   return SWX_OK;
 }
 
-// Upload jobs (grouped by rows per lane and waves) and launch them; bnd: the
-// hand-over rows (null: allocated here, bnd_words of them).
-static int launch_intra_jobs(swx_ctx *ctx, std::vector<IntraJob> jobs[4][9], IntraArgs a,
+// Upload jobs (grouped by launch shape) and launch them; bnd: the hand-over
+// rows (null: allocated here, bnd_words of them).
+static int launch_intra_jobs(swx_ctx *ctx, const IntraGroups &groups, IntraArgs a,
                              int64_t bnd_words, bool rev) {
   DevArena &A = ctx->arena;
   std::vector<IntraJob> all;
-  for (int g = 0; g < 4; ++g)
-    for (int w = 0; w <= 8; ++w) all.insert(all.end(), jobs[g][w].begin(), jobs[g][w].end());
+  int64_t nspread = 0;
+  for (const auto &kv : groups) {
+    all.insert(all.end(), kv.second.begin(), kv.second.end());
+    if (kv.first.segs > 1) nspread += (int64_t)kv.second.size();
+  }
   if (all.empty()) return SWX_OK;
   IntraJob *dj = A.get<IntraJob>((int64_t)all.size());
+  IntraSync *sync = nspread ? A.get<IntraSync>(nspread) : nullptr;
   if (!a.bnd) a.bnd = A.get<uint32_t>(bnd_words > 0 ? bnd_words : 1);
-  if (!dj || !a.bnd) return fail(SWX_ENOMEM, "device pool exhausted (intra jobs)");
+  if (!dj || !a.bnd || (nspread && !sync))
+    return fail(SWX_ENOMEM, "device pool exhausted (intra jobs)");
   HIP_TRY(hipMemcpyAsync(dj, all.data(), sizeof(IntraJob) * all.size(), hipMemcpyHostToDevice,
                          ctx->stream));
-  int64_t off = 0;
-  const int rls[4] = {4, 8, 16, 32};
-  for (int g = 0; g < 4; ++g) {
-    for (int w = 1; w <= 8; ++w) {
-      if (jobs[g][w].empty()) continue;
-      a.jobs = dj + off;
-      a.njobs = (int64_t)jobs[g][w].size();
-      HIP_TRY(intra_fill(a, rls[g], w, rev, ctx->stream));
-      off += a.njobs;
-    }
+  if (nspread) HIP_TRY(intra_sync_init(sync, nspread, ctx->stream));
+  int64_t off = 0, soff = 0;
+  for (const auto &kv : groups) {
+    a.jobs = dj + off;
+    a.njobs = (int64_t)kv.second.size();
+    a.segs = kv.first.segs;
+    a.sync = kv.first.segs > 1 ? sync + soff : nullptr;
+    HIP_TRY(intra_fill(a, kv.first.rl, kv.first.waves, rev, ctx->stream));
+    off += a.njobs;
+    if (kv.first.segs > 1) soff += a.njobs;
   }
   // the host job table must outlive the copy
   HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -938,7 +996,6 @@ static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
   DevArena &A = ctx->arena;
   int64_t total_r = 0;
   for (int64_t k = 0; k < lp.nlong; ++k) total_r += std::max<int64_t>(lp.info[6 * k + 1], 1);
-  std::vector<IntraJob> jobs[4][9];
   Jobs16 jobs16;
   std::vector<int64_t> ids16, ids32;
   lp.pairs.clear();
@@ -961,14 +1018,30 @@ static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
       waves += (kv.second + 1) / 2 * intra_waves16(kv.first.second, sc.n, kv.first.first);
     auto16 = waves >= kIntra16MinWavesPerCu * (int64_t)ctx->cus;
   }
+  // lanes of each pair, and the 32-bit jobs that will share the device
+  std::vector<uint8_t> is16(lp.nlong);
+  int64_t jobs32 = 0;
+  for (int64_t k = 0; k < lp.nlong; ++k) {
+    const int64_t Lq = lp.info[6 * k], Lr = lp.info[6 * k + 1];
+    is16[k] = (ctx->intra_bits == 16 || auto16) && intra_fits16(sc, Lq, Lr, pick_rl(Lq, sc.n));
+    if (!is16[k] && Lr > 0) {
+      const int64_t C = intra_chunk(sc, Lq, Lr, ctx->intra_jobs, total_r);
+      jobs32 += (Lr + C - 1) / C;
+    }
+  }
+  IntraGroups groups;
   int64_t mc_words = 0, bnd_words = 0;
   for (int64_t k = 0; k < lp.nlong; ++k) {
     const int64_t p = lp.ids[k], Lq = lp.info[6 * k], Lr = lp.info[6 * k + 1];
-    const int RL = pick_rl(Lq, sc.n);
+    const bool w16 = is16[k];
+    const int64_t W = intra_warmup(sc, Lq, Lr);
+    const int64_t C = intra_chunk(sc, Lq, Lr, (w16 ? 2 : 1) * ctx->intra_jobs, total_r);
+    const IntraShape shape = w16 ? IntraShape{pick_rl(Lq, sc.n), 0, 1}
+                                 : intra_shape(Lq, std::min(Lr, C + W), -1, sc.n, jobs32, ctx->cus);
+    const int RL = shape.rl;
     const int64_t SH = 64 * RL;
     const int64_t qp = (Lq + SH - 1) / SH * SH;
     const int64_t bound = (int64_t)std::max(sc.smax, 0) * std::min(Lq, Lr);
-    const bool w16 = (ctx->intra_bits == 16 || auto16) && intra_fits16(sc, Lq, Lr, RL);
     const int kb = w16 ? 16 : code_bits(qp);
     if (kb > 30 || bound >= (int64_t(1) << (32 - kb)))
       return fail(SWX_EOVERFLOW, "long pair: score range and query length exceed the max-array word");
@@ -976,12 +1049,9 @@ static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
     IntraPair ip{p, mc_words, kb, (int32_t)SH};
     lp.pairs.push_back(ip);
     if (Lr > 0) {
-      const int64_t W = intra_warmup(sc, Lq, Lr);
-      const int64_t C = intra_chunk(sc, Lq, Lr, (w16 ? 2 : 1) * ctx->intra_jobs, total_r);
       const int64_t nstrips = qp / SH;
       if (nstrips > intra_max_strips())
         return fail(SWX_EINVAL, "query too long for the intra-sequence path");
-      const int waves = intra_waves(nstrips, sc.n, RL);
       for (int64_t c0 = 0; c0 < Lr; c0 += C) {
         IntraJob jb{};
         jb.pair = p;
@@ -994,7 +1064,7 @@ static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
         jb.band = -1;
         bnd_words += 2 * (jb.c1 - jb.cw) * (nstrips - 1);
         if (w16) jobs16[{RL, nstrips}].push_back(jb);
-        else jobs[rl_slot(RL)][waves].push_back(jb);
+        else groups[shape].push_back(jb);
       }
     }
     mc_words += Lr;
@@ -1018,7 +1088,7 @@ static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
   a.bnd = A.get<uint32_t>(bnd_words > 0 ? bnd_words : 1);
   if (!a.bnd) return fail(SWX_ENOMEM, "device pool exhausted (hand-over rows)");
   int rc;
-  if ((rc = launch_intra_jobs(ctx, jobs, a, bnd_words, false))) return rc;
+  if ((rc = launch_intra_jobs(ctx, groups, a, bnd_words, false))) return rc;
   if ((rc = launch_intra16_jobs(ctx, jobs16, a, sc))) return rc;
   // lane widths of the long pairs (diagnostic)
   for (int w = 0; w < 2; ++w) {
@@ -1047,12 +1117,15 @@ static int run_intra_reverse(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
   int rc;
   if ((rc = gather_info(ctx, lp.nlong, lp.d_long, nullptr, nullptr, score, qend, rend, band, info)))
     return rc;
-  std::vector<IntraJob> jobs[4][9];
-  int64_t bnd_words = 0;
+  IntraGroups groups;
+  int64_t bnd_words = 0, njobs = 0;
+  for (int64_t k = 0; k < lp.nlong; ++k) njobs += info[6 * k + 2] > 0;
   for (int64_t k = 0; k < lp.nlong; ++k) {
     if (info[6 * k + 2] <= 0) continue;
     const int64_t rows = info[6 * k + 3] + 1, cols = info[6 * k + 4] + 1;
-    const int RL = pick_rl(rows, sc.n);
+    const IntraShape shape =
+        intra_shape(rows, cols, (int32_t)info[6 * k + 5], sc.n, njobs, ctx->cus);
+    const int RL = shape.rl;
     const int64_t SH = 64 * RL;
     const int64_t qp = (rows + SH - 1) / SH * SH;
     const int kb = code_bits(qp);
@@ -1069,7 +1142,7 @@ static int run_intra_reverse(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
     jb.kbits = kb;
     jb.band = (int32_t)info[6 * k + 5];
     bnd_words += 2 * cols * (nstrips - 1);
-    jobs[rl_slot(RL)][intra_waves(nstrips, sc.n, RL)].push_back(jb);
+    groups[shape].push_back(jb);
   }
   IntraArgs a{};
   a.view = rview;
@@ -1079,7 +1152,7 @@ static int run_intra_reverse(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
   a.target = tgt;
   a.out = rout;
   a.err = err;
-  return launch_intra_jobs(ctx, jobs, a, bnd_words, true);
+  return launch_intra_jobs(ctx, groups, a, bnd_words, true);
 }
 
 static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, uint32_t flags,

@@ -143,9 +143,26 @@ struct IntraJob {
 // w + NW, ...), strip s consuming strip s - 1's hand-over row as soon as the
 // columns it needs are published.
 
+// Most strips of one intra-sequence job.
+constexpr int kIntraMaxStrips = 256;
+
+// Progress of one spread job (its strips on several workgroups), in global
+// memory; intra_sync_init sets it before each launch.
+struct IntraSync {
+  int32_t prog[kIntraMaxStrips];     // columns published by strip s (from its window start)
+  int32_t done[kIntraMaxStrips];     // strip s finished (its progress is final)
+  int64_t rcol[kIntraMaxStrips];     // reversed pass: first column of strip s reaching the target (-1)
+  int32_t rrow[kIntraMaxStrips];     // ... and its row (-1)
+  unsigned long long best;           // reversed pass: smallest such column so far (~0: none)
+  int32_t fin;                       // segments of the job that have finished
+  int32_t pad_;
+};
+
 struct IntraArgs {
   const IntraJob *jobs;
   int64_t njobs;
+  int32_t segs;              // workgroups per job (0 or 1: one; > 1: a spread launch, sync below)
+  IntraSync *sync;           // spread launches: one per job
   PairView view;
   const int8_t *matrix;      // device n x n
   int32_t n, o, e, bias;

@@ -226,6 +226,8 @@ struct IntraPairArgs {
 size_t intra_lds_bytes(int n, int RL);
 int intra_slices();
 hipError_t intra_fill(const IntraArgs &a, int RL, int waves, bool rev, hipStream_t st);
+// sets the progress records of a spread launch's jobs (before each launch)
+hipError_t intra_sync_init(IntraSync *sync, int64_t njobs, hipStream_t st);
 // forward pass on packed 16-bit lanes: jobs[2b] and jobs[2b + 1] (same padded
 // height; pair -1: none) share workgroup b; a.njobs even
 hipError_t intra_fill16(const IntraArgs &a, int RL, int waves, hipStream_t st);
