@@ -47,6 +47,14 @@ __device__ __forceinline__ uint32_t set_lane(uint32_t vec, int at, uint32_t v) {
   return ((int)(threadIdx.x & 63) == at) ? v : vec;
 }
 
+constexpr int kDppWaveShl1 = 0x130;   // DPP control: lane k reads lane k + 1
+
+// vec moved one lane down (lane k takes lane k + 1) with lane 63 taking its
+// own v: a queue of lane 63's values, the newest at lane 63
+__device__ __forceinline__ uint32_t shift_in(uint32_t vec, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)vec, kDppWaveShl1, 0xF, 0xF, false);
+}
+
 // RL bytes (RL a multiple of 4) of the LDS profile as RL/4 words
 template <int RL>
 __device__ __forceinline__ void lds_load_words(const uint8_t *src, uint32_t (&w)[RL / 4]) {
@@ -260,23 +268,35 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
       if (lane == 0 && clo - 1 < plo + avail)
         hup_prev = __hip_atomic_load(&inH[clo - 1 - jb.cw], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    uint32_t hout = 0u, fout = 0u, cmout = 0u, sym = (uint32_t)n;
-    uint32_t symbuf = 0u, hbuf = 0u, fbuf = 0u;
+    uint32_t hout = 0u, fout = 0u, cmout = 0u;
+    uint32_t hbuf = 0u, fbuf = 0u;
     uint32_t obH = 0u, obF = 0u, obC = 0u;
     const int64_t nsteps = (chi - clo) + 63;
     int64_t cdone = chi;
+    // reference symbols of columns [c0, c0 + 64) at lane c - c0 (n past the window)
+    auto symbols = [&](int64_t c0) -> uint32_t {
+      const int64_t c = c0 + lane;
+      return c < chi ? (uint32_t)(uint8_t)rs[rv ? Lr - 1 - c : c] : (uint32_t)n;
+    };
+    // the symbols of this 64-step chunk and of the next one; the profile row
+    // of a step is read one step ahead (its symbol is the one the lane above
+    // holds now), so the LDS latency hides behind a step's arithmetic
+    uint32_t symbuf = symbols(clo), symnext = symbols(clo + 64);
+    uint32_t sym = from_above((uint32_t)n, lane_value(symbuf, 0));
+    uint32_t X[RL / 4];
+    lds_load_words<RL>(s_prof + ((int64_t)sym * 64 + lane) * RL, X);
 
-    // store the lane-63 outputs of columns [cbase, cbase + cnt)
-    auto flush = [&](int64_t cbase, int cnt) {
-      if (lane < cnt) {
-        const int64_t col = cbase + lane;
+    // store the outputs of columns [col - j, col], held by lanes 63 - j .. 63
+    auto flush = [&](int64_t col, int j) {
+      if (lane >= 63 - j) {
+        const int64_t c = col - 63 + lane;
         if (hand_over) {
-          bndH[col - jb.cw] = obH;
-          bndF[col - jb.cw] = obF;
+          bndH[c - jb.cw] = obH;
+          bndF[c - jb.cw] = obF;
         }
-        if (!REV && col >= jb.c0 && col < jb.c1) atomicMax(&mc[col], obC);
+        if (!REV && c >= jb.c0 && c < jb.c1) atomicMax(&mc[c], obC);
       }
-      if (hand_over) publish((int32_t)(cbase + cnt - clo), false);
+      if (hand_over) publish((int32_t)(col + 1 - clo), false);
     };
 
 #pragma unroll 1
@@ -288,24 +308,27 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
           cdone = clo + t - 63;   // an earlier strip already reached the target at or before here
           break;
         }
+        if (t > 0) {
+          symbuf = symnext;
+          symnext = symbols(clo + t + 64);
+        }
         // inputs of lane 0 for the next 64 steps
         const int64_t cend = (clo + t + 64 < phi) ? clo + t + 64 : phi;
         if (s > 0 && cend > plo) wait_for((int32_t)(cend - plo));
         const int64_t c = clo + t + lane;
-        const bool in = c < chi;
-        symbuf = in ? (uint32_t)(uint8_t)rs[rv ? Lr - 1 - c : c] : (uint32_t)n;
-        const bool prev = in && s > 0 && c >= plo && c < plo + avail && c < phi;
-        // read past the CU's L1 (another wave of this workgroup wrote them)
+        const bool prev = c < chi && s > 0 && c >= plo && c < plo + avail && c < phi;
+        // read past the CU's L1 (another wave wrote them)
         hbuf = prev ? __hip_atomic_load(&inH[c - jb.cw], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
         fbuf = prev ? __hip_atomic_load(&inF[c - jb.cw], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
       }
       const uint32_t hup = from_above(hout, lane_value(hbuf, tm));
       uint32_t F = from_above(fout, lane_value(fbuf, tm));
       const uint32_t cmin = from_above(cmout, 0u);
-      sym = from_above(sym, lane_value(symbuf, tm));
+      // next step's symbol and profile row
+      const uint32_t symn = from_above(sym, lane_value(tm == 63 ? symnext : symbuf, (tm + 1) & 63));
+      uint32_t Xn[RL / 4];
+      lds_load_words<RL>(s_prof + ((int64_t)symn * 64 + lane) * RL, Xn);
 
-      uint32_t X[RL / 4];
-      lds_load_words<RL>(s_prof + ((int64_t)sym * 64 + lane) * RL, X);
       uint32_t cm = 0u;
       uint32_t u_next = T::max(hup_prev + __builtin_amdgcn_ubfe(X[0], 0, 8), E[0]);
 #pragma unroll
@@ -327,25 +350,32 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
       fout = F;
       const uint32_t cml = cm + DL;
       cmout = cmin > cml ? cmin : cml;
+      sym = symn;
+#pragma unroll
+      for (int k = 0; k < RL / 4; ++k) X[k] = Xn[k];
 
+      // lane 63's outputs enter at lane 63 while the collected ones move one
+      // lane down: after 64 steps lane k holds the k-th column of the chunk
+      obH = shift_in(obH, hout);
+      obF = shift_in(obF, fout);
+      obC = shift_in(obC, cmout);
       if (t >= 63) {
         const int j = (int)((t - 63) & 63);
         const int64_t col = clo + t - 63;
-        const uint32_t oc = lane_value(cmout, 63);
-        obH = set_lane(obH, j, lane_value(hout, 63));
-        obF = set_lane(obF, j, lane_value(fout, 63));
-        obC = set_lane(obC, j, oc);
-        if (REV && tgt > 0 && (int32_t)(oc >> kb) >= tgt) {
-          flush(col - j, j + 1);
-          cdone = col + 1;
-          if (lane == 0) {
-            s_rcol[s] = col;
-            s_rrow[s] = (int32_t)(M - (oc & M));
-            atomicMin(s_best, (unsigned long long)col);
+        if (REV) {
+          const uint32_t oc = lane_value(cmout, 63);
+          if (tgt > 0 && (int32_t)(oc >> kb) >= tgt) {
+            flush(col, j);
+            cdone = col + 1;
+            if (lane == 0) {
+              s_rcol[s] = col;
+              s_rrow[s] = (int32_t)(M - (oc & M));
+              atomicMin(s_best, (unsigned long long)col);
+            }
+            break;
           }
-          break;
         }
-        if (j == 63 || t == nsteps - 1) flush(col - j, j + 1);
+        if (j == 63 || t == nsteps - 1) flush(col, j);
       }
     }
     publish((int32_t)(cdone - clo), true);
@@ -495,43 +525,57 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill16(IntraArgs a) {
     for (int r = 0; r < RL; ++r) { H[r] = T::zero(); E[r] = T::zero(); }
     V16 hup_prev = T::zero();
     V16 hout = T::zero(), fout = T::zero();
-    uint32_t cmoutA = 0u, cmoutB = 0u, sym = (uint32_t)n * 0x101u;
-    uint32_t symbuf = 0u, hbuf = 0u, fbuf = 0u;
-    uint32_t obHA = 0u, obFA = 0u, obCA = 0u, obHB = 0u, obFB = 0u, obCB = 0u;
+    uint32_t cmoutA = 0u, cmoutB = 0u;
+    uint32_t hbuf = 0u, fbuf = 0u;
+    uint32_t obH = 0u, obF = 0u, obCA = 0u, obCB = 0u;
     const int64_t nsteps = width + 63;
+    // both jobs' reference symbols of step offsets [o0, o0 + 64), A in the
+    // low byte, B in the next; the profile rows of a step are read one step
+    // ahead, as in the 32-bit pass
+    auto symbols = [&](int64_t o0) -> uint32_t {
+      const int64_t off = o0 + lane;
+      const uint32_t sa = off < widthA ? (uint32_t)(uint8_t)rsA[jA.cw + off] : (uint32_t)n;
+      const uint32_t sb = (hasB && off < widthB) ? (uint32_t)(uint8_t)rsB[jB.cw + off] : (uint32_t)n;
+      return sa | (sb << 8);
+    };
+    uint32_t symbuf = symbols(0), symnext = symbols(64);
+    uint32_t sym = from_above((uint32_t)n * 0x101u, lane_value(symbuf, 0));
+    uint32_t XA[RL / 4], XB[RL / 4];
+    lds_load_words<RL>(s_profA + ((int64_t)(sym & 0xFFu) * 64 + lane) * RL, XA);
+    lds_load_words<RL>(s_profB + ((int64_t)((sym >> 8) & 0xFFu) * 64 + lane) * RL, XB);
 
-    // store the lane-63 outputs of steps' columns [cbase, cbase + cnt) (offsets
-    // from each job's first computed column)
-    auto flush = [&](int64_t cbase, int cnt) {
-      if (lane < cnt) {
-        const int64_t off = cbase + lane;
+    // store the outputs of step offsets [o - j, o], held by lanes 63 - j .. 63
+    // (packed H and F: A in the low half, B in the high half)
+    auto flush = [&](int64_t o, int j) {
+      if (lane >= 63 - j) {
+        const int64_t off = o - 63 + lane;
         if (off < widthA) {
-          if (hand_over) { bHA[off] = obHA; bFA[off] = obFA; }
+          if (hand_over) { bHA[off] = obH & 0xFFFFu; bFA[off] = obF & 0xFFFFu; }
           const int64_t col = jA.cw + off;
           if (col >= jA.c0 && col < jA.c1) atomicMax(&mcA[col], obCA);
         }
         if (hasB && off < widthB) {
-          if (hand_over) { bHB[off] = obHB; bFB[off] = obFB; }
+          if (hand_over) { bHB[off] = obH >> 16; bFB[off] = obF >> 16; }
           const int64_t col = jB.cw + off;
           if (col >= jB.c0 && col < jB.c1) atomicMax(&mcB[col], obCB);
         }
       }
-      if (hand_over) publish((int32_t)(cbase + cnt), false);
+      if (hand_over) publish((int32_t)(o + 1), false);
     };
 
 #pragma unroll 1
     for (int64_t t = 0; t < nsteps; ++t) {
       const int tm = (int)(t & 63);
       if (tm == 0) {
+        if (t > 0) {
+          symbuf = symnext;
+          symnext = symbols(t + 64);
+        }
         // inputs of lane 0 for the next 64 steps, both jobs
         const int64_t cend = (t + 64 < width) ? t + 64 : width;
         if (s > 0 && cend > 0) wait_for((int32_t)cend);
         const int64_t off = t + lane;
-        const int64_t cA = jA.cw + off, cB = (hasB ? jB.cw : 0) + off;
         const bool inA = off < widthA, inB = hasB && off < widthB;
-        const uint32_t sa = inA ? (uint32_t)(uint8_t)rsA[cA] : (uint32_t)n;
-        const uint32_t sb = inB ? (uint32_t)(uint8_t)rsB[cB] : (uint32_t)n;
-        symbuf = sa | (sb << 8);
         const bool prev = s > 0 && off < avail;
         const uint32_t ha = (prev && inA) ? __hip_atomic_load(&iHA[off], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
         const uint32_t fa = (prev && inA) ? __hip_atomic_load(&iFA[off], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
@@ -543,11 +587,11 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill16(IntraArgs a) {
       const V16 hup = T::from(from_above(T::bits(hout), lane_value(hbuf, tm)));
       V16 F = T::from(from_above(T::bits(fout), lane_value(fbuf, tm)));
       const uint32_t cminA = from_above(cmoutA, 0u), cminB = from_above(cmoutB, 0u);
-      sym = from_above(sym, lane_value(symbuf, tm));
+      const uint32_t symn = from_above(sym, lane_value(tm == 63 ? symnext : symbuf, (tm + 1) & 63));
+      uint32_t XnA[RL / 4], XnB[RL / 4];
+      lds_load_words<RL>(s_profA + ((int64_t)(symn & 0xFFu) * 64 + lane) * RL, XnA);
+      lds_load_words<RL>(s_profB + ((int64_t)((symn >> 8) & 0xFFu) * 64 + lane) * RL, XnB);
 
-      uint32_t XA[RL / 4], XB[RL / 4];
-      lds_load_words<RL>(s_profA + ((int64_t)(sym & 0xFFu) * 64 + lane) * RL, XA);
-      lds_load_words<RL>(s_profB + ((int64_t)((sym >> 8) & 0xFFu) * 64 + lane) * RL, XB);
       uint32_t cmA = 0u, cmB = 0u;
       auto score_of = [&](int r) -> V16 { return T::from(perm(XB[r >> 2], XA[r >> 2], T::sel_const(r & 3))); };
       V16 u_next = T::max(T::add(hup_prev, score_of(0)), E[0]);
@@ -572,17 +616,17 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill16(IntraArgs a) {
       const uint32_t cmlA = cmA + DL, cmlB = cmB + DL;
       cmoutA = cminA > cmlA ? cminA : cmlA;
       cmoutB = cminB > cmlB ? cminB : cmlB;
+      sym = symn;
+#pragma unroll
+      for (int k = 0; k < RL / 4; ++k) { XA[k] = XnA[k]; XB[k] = XnB[k]; }
 
+      obH = shift_in(obH, T::bits(hout));
+      obF = shift_in(obF, T::bits(fout));
+      obCA = shift_in(obCA, cmoutA);
+      obCB = shift_in(obCB, cmoutB);
       if (t >= 63) {
         const int j = (int)((t - 63) & 63);
-        const uint32_t oh = lane_value(T::bits(hout), 63), of = lane_value(T::bits(fout), 63);
-        obHA = set_lane(obHA, j, oh & 0xFFFFu);
-        obFA = set_lane(obFA, j, of & 0xFFFFu);
-        obHB = set_lane(obHB, j, oh >> 16);
-        obFB = set_lane(obFB, j, of >> 16);
-        obCA = set_lane(obCA, j, lane_value(cmoutA, 63));
-        obCB = set_lane(obCB, j, lane_value(cmoutB, 63));
-        if (j == 63 || t == nsteps - 1) flush(t - 63 - j, j + 1);
+        if (j == 63 || t == nsteps - 1) flush(t - 63, j);
       }
     }
     publish((int32_t)width, true);

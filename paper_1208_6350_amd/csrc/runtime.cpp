@@ -540,6 +540,30 @@ static int gather_info(swx_ctx *ctx, int64_t n, const int64_t *d_ids, const int3
                        const int64_t *rlen, const int32_t *score, const int32_t *qend,
                        const int64_t *rend, const int32_t *band, std::vector<int64_t> &info);
 
+// Rows per lane of a wave traceback over m rows, w columns and a band of bw
+// diagonals (0: too tall for every choice).  Strip s starts SH + 128 steps
+// after strip s - 1 and sweeps a window of SH + bw columns; a wave runs its
+// workgroup's strips in turn, and a step costs about 16 instructions per row
+// of a lane plus 30: the cheapest of the longer of those two paths.
+static int tb_wave_rl(int64_t m, int64_t w, int64_t bw, int n) {
+  int best = 0;
+  double best_cost = 0;
+  for (int RL : {4, 8, 16}) {
+    const int64_t SH = 64 * RL, nstrips = (m + SH - 1) / SH;
+    if (nstrips > tb_wave_max_strips()) continue;
+    const int64_t waves = tb_wave_waves(m, n, RL);
+    const int64_t win = std::min<int64_t>(SH + bw, w + 1) + 63;
+    const int64_t chain = (nstrips - 1) * (SH + 128) + win;
+    const int64_t turns = (nstrips + waves - 1) / waves * win;
+    const double cost = (double)std::max(chain, turns) * (16 * RL + 30) * (waves > 4 ? 1.5 : 1.0);
+    if (best == 0 || cost < best_cost) {
+      best = RL;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
 static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, int64_t np,
                          const int32_t *score, const int32_t *qbeg, const int32_t *qend,
                          const int64_t *rbeg, const int64_t *rend, const int64_t *qstart,
@@ -555,7 +579,7 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
   ta.qcat = b.qcat; ta.rcat = b.rcat; ta.matrix = sc.dmat;
   ta.n = sc.n; ta.o = sc.o; ta.e = sc.e; ta.smax = sc.smax;
   ta.cig_len = cig_len; ta.err = err;
-  ta.wave_cells = kWaveTbCells;
+  ta.wave_cells = np <= kTbFewPairs ? kWaveTbCellsFew : kWaveTbCells;
   uint8_t *cls = A.get<uint8_t>(np);
   uint64_t *k0 = A.get<uint64_t>(np), *k1 = A.get<uint64_t>(np);
   int64_t *v0 = A.get<int64_t>(np), *v1 = A.get<int64_t>(np);
@@ -668,46 +692,47 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
     std::vector<int64_t> ids(nc);
     if ((rc = read_i64(ctx, sorted + pos, ids.data(), nc))) return rc;
     std::vector<TbWaveJob> jobs(nc);
-    std::vector<int> waves(nc);
-    int64_t dwords = 0, bwords = 0;
+    std::vector<std::pair<int, int>> shape(nc);   // rows per lane, waves
+    int64_t dbytes = 0, bwords = 0;
     for (int64_t k = 0; k < nc; ++k) {
       TbWaveJob &jb = jobs[k];
       jb.pair = ids[k];
       jb.m = info[6 * k + 3] - info[6 * k + 0] + 1;
       jb.w = info[6 * k + 4] - info[6 * k + 1] + 1;
       safe_band(jb.m, jb.w, info[6 * k + 2], sc.smax, sc.o, sc.e, &jb.dlo, &jb.bw);
-      jb.dir_off = dwords;
+      const int RL = tb_wave_rl(jb.m, jb.w, jb.bw, sc.n);
+      if (RL == 0) return fail(SWX_EINVAL, "alignment too long for the wave traceback");
+      const int64_t SH = 64 * RL, nstrips = (jb.m + SH - 1) / SH;
+      jb.dir_off = dbytes;
       jb.bnd_off = bwords;
-      const int64_t SH = 64 * kTbRL, nstrips = (jb.m + SH - 1) / SH;
-      if (nstrips > tb_wave_max_strips())
-        return fail(SWX_EINVAL, "alignment too long for the wave traceback");
       for (int64_t st_ = 0; st_ < nstrips; ++st_) {
         int64_t clo, chi;
-        tbw_window(st_, jb.dlo, jb.bw, jb.w, &clo, &chi);
-        dwords += ((chi - clo) + 63) * 64;
+        tbw_window(st_, SH, jb.dlo, jb.bw, jb.w, &clo, &chi);
+        dbytes += ((chi - clo) + 63) * 64 * tb_code_bytes(RL);
       }
+      dbytes = round_up(dbytes, 256);
       bwords += 2 * (jb.w + 1) * (nstrips + 1);
-      waves[k] = tb_wave_waves(jb.m, sc.n);
+      shape[k] = {RL, tb_wave_waves(jb.m, sc.n, RL)};
     }
-    // launch groups of equal workgroup size
+    // launch groups of equal shape
     std::vector<int64_t> order(nc);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return waves[x] < waves[y]; });
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return shape[x] < shape[y]; });
     std::vector<TbWaveJob> sorted_jobs(nc);
     for (int64_t k = 0; k < nc; ++k) sorted_jobs[k] = jobs[order[k]];
     TbWaveJob *dj = A.get<TbWaveJob>(nc);
-    uint2 *dirw = A.get<uint2>(std::max<int64_t>(dwords, 1));
+    uint8_t *dirw = A.get<uint8_t>(std::max<int64_t>(dbytes, 256));
     int32_t *bnd = A.get<int32_t>(std::max<int64_t>(bwords, 1));
     if (!dj || !dirw || !bnd) return fail(SWX_ENOMEM, "device pool exhausted (wave traceback)");
     HIP_TRY(hipMemcpyAsync(dj, sorted_jobs.data(), sizeof(TbWaveJob) * nc, hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));   // the host job table must outlive the copy
     for (int64_t k0 = 0; k0 < nc;) {
       int64_t k1 = k0;
-      while (k1 < nc && waves[order[k1]] == waves[order[k0]]) ++k1;
-      const int wv = waves[order[k0]];
+      while (k1 < nc && shape[order[k1]] == shape[order[k0]]) ++k1;
+      const int RL = shape[order[k0]].first, wv = shape[order[k0]].second;
       const TbWaveJob *jp = dj + k0;
       const int64_t cnt = k1 - k0;
-      launches.push_back({(double)dwords * 16, [=](hipStream_t s_) { return tb_wave(ta, jp, cnt, wv, dirw, bnd, s_); }});
+      launches.push_back({(double)dbytes * 32, [=](hipStream_t s_) { return tb_wave(ta, jp, cnt, RL, wv, dirw, bnd, s_); }});
       k0 = k1;
     }
     pos += nc;

@@ -111,28 +111,30 @@ __host__ __device__ inline void safe_band(int64_t m, int64_t w, int64_t s1, int3
   *bw = ((D > 0 ? D : 0) + hw) - *dlo + 1;
 }
 
-// Bands wider than 64 diagonals with more cells than this take the
-// wave-parallel traceback (one pair per wave) instead of one pair per lane.
+// Pairs with more band cells than this take the wave-parallel traceback (one
+// pair per workgroup) instead of one pair per lane; in a batch of at most
+// kTbFewPairs pairs (less than one wave of lanes) the lower kWaveTbCellsFew.
 constexpr int64_t kWaveTbCells = int64_t(1) << 18;
+constexpr int64_t kWaveTbCellsFew = int64_t(1) << 14;
+constexpr int64_t kTbFewPairs = 64;
 
-// Wave-parallel traceback of one pair: rows in strips of 64 * kTbRL, lane k
-// holding kTbRL rows, columns swept as a wavefront; choice codes stored per
-// (strip, step, lane) as kTbRL nibbles.
-constexpr int kTbRL = 16;
+// Wave-parallel traceback of one pair: rows in strips of 64 * RL (RL = 4, 8
+// or 16 rows per lane), columns swept as a wavefront; choice codes stored per
+// (strip, step, lane) as RL nibbles (2, 4 or 8 bytes).
 struct TbWaveJob {
   int64_t pair;
   int64_t m, w;          // rectangle: query rows qbeg..qend, reference columns rbeg..rend
   int64_t dlo, bw;       // safe band (diagonals j - i, 1-based coordinates)
-  int64_t dir_off;       // uint2 words of choice codes
+  int64_t dir_off;       // bytes: the pair's choice codes start there
   int64_t bnd_off;       // ints of the hand-over rows: per strip boundary (and the
                          // virtual top row) H then F, w + 1 each
 };
+__host__ __device__ inline int tb_code_bytes(int RL) { return RL / 2; }
 
 // column window [clo, chi) of strip s (rows s*SH+1 .. (s+1)*SH, 1-based;
 // column 0 is the virtual column left of the rectangle)
-__host__ __device__ inline void tbw_window(int64_t s, int64_t dlo, int64_t bw, int64_t w,
-                                           int64_t *clo, int64_t *chi) {
-  const int64_t SH = 64 * kTbRL;
+__host__ __device__ inline void tbw_window(int64_t s, int64_t SH, int64_t dlo, int64_t bw,
+                                           int64_t w, int64_t *clo, int64_t *chi) {
   int64_t lo = s * SH + 1 + dlo;
   if (lo < 0) lo = 0;
   int64_t hi = (s + 1) * SH + dlo + bw;
@@ -178,9 +180,9 @@ hipError_t tbw_offsets(int64_t ntasks, TbwTask *tasks, const int64_t *doff, cons
                        hipStream_t st);
 hipError_t tb_strip(const TbArgs &a, const TbwTask *tasks, int64_t ntasks, const int64_t *sorted,
                     int32_t *bndbuf, hipStream_t st);
-hipError_t tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, int waves, uint2 *dirw,
-                   int32_t *bnd, hipStream_t st);
-int tb_wave_waves(int64_t m, int n);   // waves per workgroup for a pair of m rows
+hipError_t tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, int RL, int waves,
+                   uint8_t *dirw, int32_t *bnd, hipStream_t st);
+int tb_wave_waves(int64_t m, int n, int RL);   // waves per workgroup for a pair of m rows
 int tb_wave_max_strips();
 hipError_t fill_u8(int64_t n, uint8_t *p, uint8_t v, hipStream_t st);
 hipError_t fill_i64(int64_t n, int64_t *p, int64_t v, hipStream_t st);

@@ -26,6 +26,7 @@
 namespace swx {
 
 constexpr int32_t kNeg = -(1 << 29);
+constexpr int64_t kTbMaxStripsDecl = 256;   // strips of one wave-traceback pair (kTbMaxStrips)
 
 // Choice code of a cell: bit 3 "H does not come from the diagonal"
 // (diag < H), bit 2 "F rather than E" (E < F), bit 1 "E extends" (the
@@ -69,8 +70,10 @@ __global__ void k_tb_classify(TbArgs a, int64_t npairs, uint8_t *cls, uint64_t *
       w = a.rend[p] - a.rbeg[p] + 1;
       safe_band(m, w, a.score[p], a.smax, a.o, a.e, &dlo, &bw);
       // bands wider than 32 go to the strip kernel (a 64-wide band in one
-      // lane's registers spills and leaves too few waves)
-      c = bw <= 8 ? 1 : bw <= 16 ? 2 : bw <= 32 ? 3 : (m * bw > a.wave_cells ? 6 : 5);
+      // lane's registers spills and leaves too few waves); pairs of more
+      // than wave_cells band cells to the wave-parallel kernel
+      const bool wave_fits = m <= int64_t(64) * 16 * kTbMaxStripsDecl;   // the wave kernel's strip limit
+      c = (m * bw > a.wave_cells && wave_fits) ? 6 : bw <= 8 ? 1 : bw <= 16 ? 2 : bw <= 32 ? 3 : 5;
     } else {
       a.err[p] = 1;
     }
@@ -920,32 +923,51 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
 }
 
 // ---- wave-parallel traceback (long pairs with wide bands) -------------------
-// One pair per wave.  Lane k holds rows [k*RL+1, (k+1)*RL] of a strip of
+// One pair per workgroup.  Lane k holds rows [k*RL+1, (k+1)*RL] of a strip of
 // 64*RL rows and computes column c - k at step c; the H and F leaving a lane's
 // last row move one lane down per step through a DPP shift, as in the
 // intra-sequence fill.  Each step stores the lane's RL choice codes (same
-// 4-bit code as the per-lane kernels) as one 8-byte word at [step][lane], so
-// a strip's codes are written with coalesced 512-byte stores.  The walk then
-// runs on the whole wave with uniform state, pulling 64 steps x 64 lanes of
-// codes (32 KiB) at a time into LDS: the walk only moves to smaller steps
-// and lanes inside a strip, so each tile serves at least 32 moves.
+// 4-bit code as the per-lane kernels, RL/2 bytes) at [step][lane], so a
+// strip's codes are written with coalesced stores.  The walk then runs on the
+// whole wave with uniform state, copying the codes of up to 32 KiB of steps
+// at a time (a contiguous range: steps [t - TS + 1, t] of the current strip)
+// into LDS with 16-byte loads: the walk only moves to smaller steps and lanes
+// inside a strip, so each copy serves many moves.  RL is chosen per pair on
+// the host: short lanes shorten the chain of strips and the work per step,
+// tall ones hold longer queries within the strip limit.
 __device__ __forceinline__ int32_t tb_from_above(int32_t src, int32_t top) {
   return __builtin_amdgcn_update_dpp(top, src, 0x138, 0xF, 0xF, false);   // wave_shr:1
 }
 
-
-constexpr int kTbMaxStrips = 256;
+constexpr int kTbMaxStrips = (int)kTbMaxStripsDecl;
 constexpr int kTbMaxWaves = 8;
 constexpr int64_t kTbSpinLimit = int64_t(1) << 26;
+constexpr int kTbTileBytes = 32768;
 
+// RL score bytes of the LDS profile as RL/4 words
+template <int RL>
+__device__ __forceinline__ void tb_prof_load(const int8_t *src, uint32_t (&w)[RL / 4]) {
+  if constexpr (RL == 16) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(src);
+    w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+  } else if constexpr (RL == 8) {
+    const uint2 v = *reinterpret_cast<const uint2 *>(src);
+    w[0] = v.x; w[1] = v.y;
+  } else {
+    w[0] = *reinterpret_cast<const uint32_t *>(src);
+  }
+}
+
+template <int RL>
 __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const TbWaveJob *jobs,
-                                                              uint2 *dirw, int32_t *bndbuf) {
-  constexpr int RL = kTbRL;
+                                                              uint8_t *dirw, int32_t *bndbuf) {
   constexpr int64_t SH = 64 * RL;
-  extern __shared__ uint4 s_dyn[];             // per wave: profile [(n+1)][64][RL] score bytes
-  __shared__ uint2 s_tile[64 * 64];
+  constexpr int WB = RL / 2;                      // code bytes per lane and step
+  constexpr int TS = kTbTileBytes / (64 * WB);    // steps per LDS tile
+  extern __shared__ uint4 s_dyn[];                // per wave: profile [(n+1)][64][RL] score bytes
+  __shared__ uint4 s_tile[kTbTileBytes / 16];
   __shared__ int8_t s_mat[32 * 32];
-  __shared__ int32_t s_prog[kTbMaxStrips];     // columns of strip s's last row published
+  __shared__ int32_t s_prog[kTbMaxStrips];        // columns of strip s's last row published
   __shared__ int32_t s_done[kTbMaxStrips];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -955,6 +977,7 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
   const int n = a.n;
   const int32_t o = a.o, e = a.e;
   const int64_t nstrips = (m + SH - 1) / SH;
+  uint8_t *dir = dirw + jb.dir_off;
   for (int k = threadIdx.x; k < n * n; k += blockDim.x) s_mat[k] = a.matrix[k];
   for (int k = threadIdx.x; k < nstrips && k < kTbMaxStrips; k += blockDim.x) {
     s_prog[k] = 0;
@@ -974,27 +997,27 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
   int8_t *s_prof = reinterpret_cast<int8_t *>(s_dyn) + (size_t)wave * (n + 1) * 64 * RL;
   bool spin_fail = false;
 
-  // choice codes of strip s start after those of strips 0..s-1
+  // choice codes of strip s start this many bytes after those of strip 0
   auto strip_base = [&](int64_t s) {
-    int64_t off = jb.dir_off;
+    int64_t off = 0;
     for (int64_t k = 0; k < s; ++k) {
       int64_t lo, hi;
-      tbw_window(k, jb.dlo, jb.bw, w, &lo, &hi);
-      off += ((hi - lo) + 63) * 64;
+      tbw_window(k, SH, jb.dlo, jb.bw, w, &lo, &hi);
+      off += ((hi - lo) + 63) * 64 * WB;
     }
     return off;
   };
 
   for (int64_t s = wave; s < nstrips; s += NW) {
     int64_t clo, chi, plo = 0, phi = w + 1;
-    tbw_window(s, jb.dlo, jb.bw, w, &clo, &chi);
-    if (s > 0) tbw_window(s - 1, jb.dlo, jb.bw, w, &plo, &phi);
+    tbw_window(s, SH, jb.dlo, jb.bw, w, &clo, &chi);
+    if (s > 0) tbw_window(s - 1, SH, jb.dlo, jb.bw, w, &plo, &phi);
     const int32_t *inH = bnd0 + 2 * (w + 1) * s;    // the row above this strip
     const int32_t *inF = inH + (w + 1);
     int32_t *outH = bnd0 + 2 * (w + 1) * (s + 1);   // this strip's last row
     int32_t *outF = outH + (w + 1);
     const bool hand_over = (s + 1 < nstrips);
-    const int64_t dbase = strip_base(s);
+    uint8_t *dstrip = dir + strip_base(s);
     auto publish = [&](int32_t ncols, bool fin) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       if (lane == 0) {
@@ -1035,8 +1058,9 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
           const uint32_t b = (qv[k] >= 0 && sy < n) ? (uint32_t)(uint8_t)s_mat[qv[k] * n + sy] : 0u;
           wv[k >> 2] |= b << (8 * (k & 3));
         }
-        uint4 *dst = reinterpret_cast<uint4 *>(s_prof + ((int64_t)sy * 64 + lane) * RL);
-        *dst = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(s_prof + ((int64_t)sy * 64 + lane) * RL);
+#pragma unroll
+        for (int k = 0; k < RL / 4; ++k) dst[k] = wv[k];
       }
     }
     __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -1050,34 +1074,49 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
       if (lane == 0 && clo - 1 < plo + avail) hup_prev = rd(&inH[clo - 1]);
     }
     int32_t hout = kNeg, fout = kNeg;
-    uint32_t sym = (uint32_t)n;
-    int32_t symbuf = 0, hbuf = kNeg, fbuf = kNeg;
+    int32_t hbuf = kNeg, fbuf = kNeg;
     int32_t obH = 0, obF = 0;
     const int64_t nsteps = (chi - clo) + 63;
+    // reference symbols of columns [c0, c0 + 64) at lane c - c0; the profile
+    // row of a step is read one step ahead (its symbol is the one the lane
+    // above holds now)
+    auto symbols = [&](int64_t c0) -> int32_t {
+      const int64_t c = c0 + lane;
+      return (c < chi && c >= 1) ? (int32_t)(uint8_t)r[c - 1] : n;
+    };
+    int32_t symbuf = symbols(clo), symnext = symbols(clo + 64);
+    uint32_t sym = (uint32_t)tb_from_above(n, __builtin_amdgcn_readlane(symbuf, 0));
+    uint32_t X[RL / 4];
+    tb_prof_load<RL>(s_prof + ((int64_t)sym * 64 + lane) * RL, X);
 #pragma unroll 1
     for (int64_t t = 0; t < nsteps; ++t) {
       const int tm = (int)(t & 63);
       if (tm == 0) {
+        if (t > 0) {
+          symbuf = symnext;
+          symnext = symbols(clo + t + 64);
+        }
         const int64_t cend = (clo + t + 64 < phi) ? clo + t + 64 : phi;
         if (cend > plo) wait_for((int32_t)(cend - plo));
         const int64_t c = clo + t + lane;
-        const bool in = c < chi;
-        symbuf = (in && c >= 1) ? (int32_t)(uint8_t)r[c - 1] : n;
-        const bool prev = in && c >= plo && c < phi && c < plo + avail;
+        const bool prev = c < chi && c >= plo && c < phi && c < plo + avail;
         hbuf = prev ? rd(&inH[c]) : kNeg;
         fbuf = prev ? rd(&inF[c]) : kNeg;
       }
       const int32_t hup = tb_from_above(hout, __builtin_amdgcn_readlane(hbuf, tm));
       int32_t fup = tb_from_above(fout, __builtin_amdgcn_readlane(fbuf, tm));
-      sym = (uint32_t)tb_from_above((int32_t)sym, __builtin_amdgcn_readlane(symbuf, tm));
-      const uint4 X = *reinterpret_cast<const uint4 *>(s_prof + ((int64_t)sym * 64 + lane) * RL);
-      const uint32_t Xw[4] = {X.x, X.y, X.z, X.w};
+      const uint32_t symn = (uint32_t)tb_from_above(
+          (int32_t)sym, __builtin_amdgcn_readlane(tm == 63 ? symnext : symbuf, (tm + 1) & 63));
+      uint32_t Xn[RL / 4];
+      tb_prof_load<RL>(s_prof + ((int64_t)symn * 64 + lane) * RL, Xn);
       int32_t hdiag = hup_prev;
       int32_t hcur = hup;
-      uint32_t dw0 = 0u, dw1 = 0u;
+      uint32_t dw[(RL + 7) / 8];
+#pragma unroll
+      for (int k = 0; k < (RL + 7) / 8; ++k) dw[k] = 0u;
 #pragma unroll
       for (int k = 0; k < RL; ++k) {
-        const int32_t sc = __builtin_amdgcn_sbfe((int32_t)Xw[k >> 2], 8 * (k & 3), 8);
+        const int32_t sc = __builtin_amdgcn_sbfe((int32_t)X[k >> 2], 8 * (k & 3), 8);
         const int32_t diag = hdiag + sc;
         const int32_t fo = hcur - o, fx = fup - e;
         const int32_t fij = fo > fx ? fo : fx;
@@ -1085,9 +1124,8 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
         const int32_t eij = eo > ex ? eo : ex;
         int32_t h = diag > eij ? diag : eij;
         h = h > fij ? h : fij;
-        // row k: bits 4(7 - k%8) of dw0 (k < 8) or dw1
-        if (k < 8) dw0 = push_code(dw0, diag, h, eij, fij, eo, ex, fo, fx);
-        else dw1 = push_code(dw1, diag, h, eij, fij, eo, ex, fo, fx);
+        // row k: nibble 7 - k % 8 of dword k / 8 (the first row on top)
+        dw[k >> 3] = push_code(dw[k >> 3], diag, h, eij, fij, eo, ex, fo, fx);
         hdiag = H[k];
         H[k] = h;
         E[k] = eij;
@@ -1097,7 +1135,12 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
       hup_prev = hup;
       hout = H[RL - 1];
       fout = fup;
-      dirw[dbase + t * 64 + lane] = make_uint2(dw0, dw1);
+      sym = symn;
+#pragma unroll
+      for (int k = 0; k < RL / 4; ++k) X[k] = Xn[k];
+      if constexpr (RL == 16) reinterpret_cast<uint2 *>(dstrip)[t * 64 + lane] = make_uint2(dw[0], dw[1]);
+      else if constexpr (RL == 8) reinterpret_cast<uint32_t *>(dstrip)[t * 64 + lane] = dw[0];
+      else reinterpret_cast<uint16_t *>(dstrip)[t * 64 + lane] = (uint16_t)dw[0];
       if (hand_over && t >= 63) {
         const int jj = (int)((t - 63) & 63);
         const int32_t vh = __builtin_amdgcn_readlane(hout, 63);
@@ -1113,14 +1156,17 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
     }
     publish((int32_t)(chi - clo), true);
   }
-  __threadfence_block();
+  // the walk reads every wave's codes: the barrier makes the workgroup's
+  // stores visible to it (they pass through this compute unit's caches)
   __syncthreads();
   if (wave != 0) return;
   if (spin_fail) a.err[p] = 1;
-  const int64_t dcur = strip_base(nstrips);
 
   // ---- walk back from (m, w) in state H (rule T3), uniform on the wave ------
-  const int64_t cap_end = dcur;
+  // The outer loop places the walk in a strip and a tile of its codes; the
+  // inner loop follows the path inside that tile on 32-bit local coordinates
+  // (tile step tl, lane L, row rr of the lane) until it leaves the tile, the
+  // strip or row 1.
   uint32_t *out = a.cig + a.cig_off[p];
   int32_t nruns = 0;
   int64_t i = m, j = w;
@@ -1128,69 +1174,123 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
   uint32_t cur_op = 0xFF, cur_len = 0;
   int64_t guard = 2 * (m + w) + 4;
   int64_t ws = nstrips;          // strip whose codes start at wbase
-  int64_t wbase = cap_end, wclo = 0, wchi = 0;
+  int64_t wbase = strip_base(nstrips), wclo = 0, wchi = 0;
   int64_t tile_s = -1, tile_lo = 0, tile_hi = -1;
+  const uint8_t *tile = reinterpret_cast<const uint8_t *>(s_tile);
   bool bad = false;
-  while ((i > 0 || j > 0) && guard-- > 0) {
-    uint32_t c;
-    if (i == 0) {
-      c = row0_code(j, o, e);
+  auto emit = [&](uint32_t op) {
+    if (op == cur_op) {
+      ++cur_len;
     } else {
-      const int64_t s = (i - 1) / SH;
-      while (ws > s) {   // step the strip cursor up (the walk only moves up)
-        --ws;
-        tbw_window(ws, jb.dlo, jb.bw, w, &wclo, &wchi);
-        wbase -= ((wchi - wclo) + 63) * 64;
-      }
-      if (j < wclo || j >= wchi) { bad = true; break; }
-      const int64_t x = (i - 1) - s * SH;
-      const int L = (int)(x / RL), rr = (int)(x % RL);
-      const int64_t t = (j - wclo) + L;
-      if (s != tile_s || t < tile_lo || t > tile_hi) {
-        tile_s = s;
-        tile_hi = t;
-        tile_lo = t >= 63 ? t - 63 : 0;
-        __builtin_amdgcn_wave_barrier();
-        for (int k = 0; k < 64; ++k) {
-          const int64_t tt = tile_lo + k;
-          if (tt <= tile_hi) {   // past the L1: other waves of the workgroup wrote these codes
-            const unsigned long long v = __hip_atomic_load(
-                reinterpret_cast<unsigned long long *>(&dirw[wbase + tt * 64 + lane]), __ATOMIC_RELAXED,
-                __HIP_MEMORY_SCOPE_AGENT);
-            s_tile[k * 64 + lane] = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
-          }
-        }
-        __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
-        __builtin_amdgcn_wave_barrier();
-      }
-      const uint2 dv = s_tile[(t - tile_lo) * 64 + L];
-      c = ((rr < 8 ? dv.x : dv.y) >> (4 * (7 - (rr & 7)))) & 0xFu;
+      if (cur_len && lane == 0) out[nruns] = (cur_len << 4) | cur_op;
+      if (cur_len) ++nruns;
+      cur_op = op;
+      cur_len = 1;
     }
-    uint32_t op = 0xFF;
-    if (state == 0) {
-      const uint32_t src = code_src(c);
-      if (src == 0 && i > 0 && j > 0) { op = 0; --i; --j; }
-      else if (src == 1) state = 1;
-      else state = 2;
-    } else if (state == 1) {
-      op = 2;
-      state = (c & kCodeEExt) ? 1 : 0;
-      --j;
-    } else {
-      op = 1;
-      state = (c & kCodeFExt) ? 2 : 0;
-      --i;
-    }
-    if (op != 0xFF) {
-      if (op == cur_op) {
-        ++cur_len;
+  };
+  while ((i > 0 || j > 0) && guard > 0) {
+    if (i == 0) {   // row 0: reached from the left by one deletion run
+      const uint32_t c = row0_code(j, o, e);
+      --guard;
+      if (state == 0) {
+        state = code_src(c) == 1 ? 1 : 2;
+      } else if (state == 1) {
+        emit(2);
+        state = (c & kCodeEExt) ? 1 : 0;
+        --j;
       } else {
-        if (cur_len && lane == 0) out[nruns] = (cur_len << 4) | cur_op;
-        if (cur_len) ++nruns;
-        cur_op = op;
-        cur_len = 1;
+        bad = true;   // no cell above row 0
+        break;
       }
+      continue;
     }
+    const int64_t s = (i - 1) / SH;
+    while (ws > s) {   // step the strip cursor up (the walk only moves up)
+      --ws;
+      tbw_window(ws, SH, jb.dlo, jb.bw, w, &wclo, &wchi);
+      wbase -= ((wchi - wclo) + 63) * 64 * WB;
+    }
+    if (j < wclo || j >= wchi) { bad = true; break; }
+    const int64_t x = (i - 1) - s * SH;
+    int L = (int)(x / RL), rr = (int)(x % RL);
+    const int64_t t = (j - wclo) + L;
+    if (s != tile_s || t < tile_lo || t > tile_hi) {
+      tile_s = s;
+      tile_hi = t;
+      tile_lo = t >= TS - 1 ? t - (TS - 1) : 0;
+      // steps [tile_lo, tile_hi] are contiguous: 16 bytes per lane and load
+      const uint4 *src = reinterpret_cast<const uint4 *>(dir + wbase + tile_lo * 64 * WB);
+      const int nv = (int)((tile_hi - tile_lo + 1) * 64 * WB / 16);
+      __builtin_amdgcn_wave_barrier();
+      for (int v = lane; v < nv; v += 64) s_tile[v] = src[v];
+      __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+      __builtin_amdgcn_wave_barrier();
+    }
+    // inside the tile: tl = t - tile_lo; j - wclo = t - L stays >= 0 on a
+    // valid path (the band keeps it in the window).  A state-0 step that
+    // names E or F takes that gap step on the same cell at once (the code is
+    // the same); the codes of the three cells the next step can reach (up,
+    // left, diagonal) are read from LDS before the step is decided, so their
+    // latency hides behind it.
+    int tl = (int)(t - tile_lo);
+    const int jl0 = (int)(t - L);      // j - wclo at entry
+    int di = 0, dj = 0;                // rows and columns moved in this tile
+    const int gmax = guard < (int64_t)0x7FFFFFFF ? (int)guard : 0x7FFFFFFF;
+    int g = 0;
+    auto code_at = [&](int tl_, int L_, int rr_) -> uint32_t {
+      tl_ = tl_ < 0 ? 0 : tl_;
+      L_ = L_ < 0 ? 0 : L_;
+      const uint8_t *wp = tile + ((tl_ * 64 + L_) * WB);
+      if constexpr (RL == 4) {
+        return ((uint32_t)*reinterpret_cast<const uint16_t *>(wp) >> (4 * (3 - rr_))) & 0xFu;
+      } else {
+        const uint32_t dv = reinterpret_cast<const uint32_t *>(wp)[rr_ >> 3];
+        return (dv >> (4 * (7 - (rr_ & 7)))) & 0xFu;
+      }
+    };
+    uint32_t c = code_at(tl, L, rr);
+    for (;;) {
+      // the cells one step up, left and diagonal
+      int rrU = rr - 1, LU = L, tlU = tl;
+      if (rrU < 0) { rrU = RL - 1; --LU; --tlU; }
+      const uint32_t cU = code_at(tlU, LU, rrU);
+      const uint32_t cL = code_at(tl - 1, L, rr);
+      const uint32_t cD = code_at(tlU - 1, LU, rrU);
+      // the step: 0 diagonal (M), 1 left (E: D), 2 up (F: I)
+      const uint32_t src = (c & kCodeNotM) ? ((c & kCodeF) ? 2u : 1u) : 0u;
+      uint32_t eff = state == 0 ? src : (uint32_t)state;
+      const int jcur = jl0 - dj + (int)wclo;
+      if (eff == 0 && jcur == 0) eff = 2;
+      state = eff == 0 ? 0 : eff == 1 ? ((c & kCodeEExt) ? 1 : 0) : ((c & kCodeFExt) ? 2 : 0);
+      emit(eff == 0 ? 0u : eff == 1 ? 2u : 1u);
+      ++g;
+      bool leave = g >= gmax;
+      if (eff == 1) {                  // left
+        ++dj;
+        --tl;
+        c = cL;
+      } else {                         // up, or diagonal (up and left)
+        ++di;
+        const bool lane_up = rr == 0;
+        rr = rrU;
+        L = LU;
+        tl = tlU;
+        if (eff == 0) {
+          ++dj;
+          --tl;
+          c = cD;
+        } else {
+          c = cU;
+        }
+        if (lane_up && L < 0) leave = true;   // into the strip above (or row 0)
+        if (i - di == 0) leave = true;
+      }
+      if (tl < 0 || jl0 - dj < 0) leave = true;   // past the tile, or left of the window
+      if (leave) break;
+    }
+    i -= di;
+    j -= dj;
+    guard -= g;
   }
   if (lane != 0) return;
   if (bad || i != 0 || j != 0) a.err[p] = 1;
@@ -1201,10 +1301,10 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
   a.cig_len[p] = nruns;
 }
 
-int tb_wave_waves(int64_t m, int n) {
-  const int64_t nstrips = (m + 64 * kTbRL - 1) / (64 * kTbRL);
-  const int64_t per = (int64_t)(n + 1) * 64 * kTbRL;
-  const int64_t stat = 64 * 64 * 8 + 32 * 32 + kTbMaxStrips * 8;
+int tb_wave_waves(int64_t m, int n, int RL) {
+  const int64_t nstrips = (m + 64 * RL - 1) / (64 * RL);
+  const int64_t per = (int64_t)(n + 1) * 64 * RL;
+  const int64_t stat = kTbTileBytes + 32 * 32 + kTbMaxStrips * 8;
   const int64_t room = (65536 - stat) / per;
   int64_t wv = std::min<int64_t>(std::min<int64_t>(nstrips, kTbMaxWaves), room);
   return (int)(wv < 1 ? 1 : wv);
@@ -1212,12 +1312,18 @@ int tb_wave_waves(int64_t m, int n) {
 
 int tb_wave_max_strips() { return kTbMaxStrips; }
 
-hipError_t tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, int waves, uint2 *dirw,
-                   int32_t *bnd, hipStream_t st) {
+hipError_t tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, int RL, int waves,
+                   uint8_t *dirw, int32_t *bnd, hipStream_t st) {
   if (njobs == 0) return hipSuccess;
   if (waves < 1 || waves > kTbMaxWaves) return hipErrorInvalidValue;
-  const size_t lds = (size_t)(a.n + 1) * 64 * kTbRL * waves;
-  hipLaunchKernelGGL(k_tb_wave, dim3((unsigned)njobs), dim3(64 * waves), lds, st, a, jobs, dirw, bnd);
+  const size_t lds = (size_t)(a.n + 1) * 64 * RL * waves;
+  const dim3 g((unsigned)njobs), b(64 * waves);
+  switch (RL) {
+    case 4: hipLaunchKernelGGL(k_tb_wave<4>, g, b, lds, st, a, jobs, dirw, bnd); break;
+    case 8: hipLaunchKernelGGL(k_tb_wave<8>, g, b, lds, st, a, jobs, dirw, bnd); break;
+    case 16: hipLaunchKernelGGL(k_tb_wave<16>, g, b, lds, st, a, jobs, dirw, bnd); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
