@@ -73,6 +73,29 @@ def fill_source_hash():
     return h.hexdigest()[:16]
 
 
+VALU_FILE = os.path.join(ROOT, "profiles", "k_inter_fill_valu_counters.md")
+
+
+def recorded_fields(path, pairs=None):
+    """The `- key: value` lines of a committed counter summary, or None when
+    the summary is missing, for another workload size or taken on a
+    different version of the fill kernel."""
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("fill_source_sha256") != fill_source_hash():
+        return None
+    if pairs is not None and vals.get("pairs") != str(pairs):
+        return None
+    return vals
+
+
 def recorded_traffic(pairs):
     """HBM bytes per forward-fill launch from the committed counter summary,
     or None when the summary is missing, for another workload size, or was
@@ -627,6 +650,8 @@ def main():
                      "peak": round(PEAK_PK16_TOPS, 2), "unit": "Tops/s",
                      "frac": round(achieved / PEAK_PK16_TOPS, 4),
                      "traffic": recorded_traffic(b.npairs),
+                     "valu_busy": (lambda v: float(v["valu_busy"]) if v else None)(
+                         recorded_fields(VALU_FILE)),
                      "kernel": "k_inter_fill (forward fill, packed 16-bit lanes)",
                      "fill_ms": round(fill_avg, 3), "ops_per_cell": OPS_PER_CELL,
                      # the whole path (fill, saturation re-run, reverse, traceback,
