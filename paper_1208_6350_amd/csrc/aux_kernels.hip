@@ -7,7 +7,7 @@
 //     Figure 1 caption),
 //   * CIGAR compaction and result records.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "swx_internal.h"
 #include "swx_kernels.h"
@@ -580,7 +580,8 @@ hipError_t launch_validate(const ValidateArgs &a, hipStream_t st) {
 
 hipError_t launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, void *tmp,
                                  size_t *tmp_bytes, hipStream_t st) {
-  return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, in, out, (int)n, st);
+  return rocprim::exclusive_scan(tmp, *tmp_bytes, in, out, (int64_t)0, (size_t)n,
+                                 rocprim::plus<int64_t>(), st);
 }
 
 hipError_t launch_views(int64_t npairs, const int64_t *qoff, const int64_t *roff,

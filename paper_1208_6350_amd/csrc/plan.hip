@@ -6,7 +6,7 @@
 // dimensions and little padding.  Task sizes and buffer offsets are derived on
 // the device; the host only reads back the totals it must allocate.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "swx_internal.h"
 #include "swx_kernels.h"
@@ -197,10 +197,10 @@ hipError_t count_classes(int64_t n, const uint8_t *cls, int64_t *counts, hipStre
 hipError_t sort_keys(int64_t n, uint64_t *keys, uint64_t *keys_alt, int64_t *vals,
                      int64_t *vals_alt, void *tmp, size_t *tmp_bytes, int64_t **sorted_out,
                      hipStream_t st, int end_bit) {
-  hipcub::DoubleBuffer<uint64_t> kb(keys, keys_alt);
-  hipcub::DoubleBuffer<int64_t> vb(vals, vals_alt);
-  hipError_t e = hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, kb, vb, (int)n, 0, end_bit, st);
-  if (tmp) *sorted_out = vb.Current();
+  rocprim::double_buffer<uint64_t> kb(keys, keys_alt);
+  rocprim::double_buffer<int64_t> vb(vals, vals_alt);
+  hipError_t e = rocprim::radix_sort_pairs(tmp, *tmp_bytes, kb, vb, (size_t)n, 0u, (unsigned)end_bit, st);
+  if (tmp) *sorted_out = vb.current();
   return e;
 }
 
@@ -222,11 +222,11 @@ hipError_t plan_sort(int64_t n, const int64_t *n_dev, const int64_t *ids, const 
   // size query covers both bit ranges, so one buffer serves either pass.
   const int end_bit = band ? 64 : 44;
   if (tmp == nullptr) {
-    hipcub::DoubleBuffer<uint64_t> kb(keys, keys_alt);
-    hipcub::DoubleBuffer<int64_t> vb(vals, vals_alt);
+    rocprim::double_buffer<uint64_t> kb(keys, keys_alt);
+    rocprim::double_buffer<int64_t> vb(vals, vals_alt);
     size_t b44 = 0, b64 = 0;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, b44, kb, vb, (int)n, 0, 44, st);
-    if (e == hipSuccess) e = hipcub::DeviceRadixSort::SortPairs(nullptr, b64, kb, vb, (int)n, 0, 64, st);
+    hipError_t e = rocprim::radix_sort_pairs(nullptr, b44, kb, vb, (size_t)n, 0u, 44u, st);
+    if (e == hipSuccess) e = rocprim::radix_sort_pairs(nullptr, b64, kb, vb, (size_t)n, 0u, 64u, st);
     *tmp_bytes = b44 > b64 ? b44 : b64;
     return e;
   }
@@ -235,10 +235,10 @@ hipError_t plan_sort(int64_t n, const int64_t *n_dev, const int64_t *ids, const 
                      band, R, keys, vals);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipcub::DoubleBuffer<uint64_t> kb(keys, keys_alt);
-  hipcub::DoubleBuffer<int64_t> vb(vals, vals_alt);
-  e = hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, kb, vb, (int)n, 0, end_bit, st);
-  *sorted_out = vb.Current();
+  rocprim::double_buffer<uint64_t> kb(keys, keys_alt);
+  rocprim::double_buffer<int64_t> vb(vals, vals_alt);
+  e = rocprim::radix_sort_pairs(tmp, *tmp_bytes, kb, vb, (size_t)n, 0u, (unsigned)end_bit, st);
+  *sorted_out = vb.current();
   return e;
 }
 
