@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed steps (no autotuner, output modes, graph, per-pair, "
                          "serving or CPU phases): the form the kernel profiles are taken of")
+    ap.add_argument("--no-large-avsa", action="store_true",
+                    help="skip the all-vs-all run at read-overlap-graph scale (2e8 pairs)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the per-configuration phase (the other four workloads)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -273,6 +275,58 @@ def all_vs_all_phase(ctx, n_reads=4000, reps=3):
     return {"reads": n_reads, "read_len": 70, "pairs": b.npairs, "cells": b.cells(),
             "ms": round(best * 1e3, 3), "gcups": round(b.cells() / best / 1e9, 1),
             "pairs_per_s": round(b.npairs / best, 0)}
+
+
+def all_vs_all_large_phase(ctx, n_reads=20000, chunk_pairs=20_000_000, check_pairs=20000,
+                           with_oracle=True):
+    """The all-vs-all overlap at read-overlap-graph scale (n_reads reads, every
+    pair i < j: about 2e8 pairs) through the sliced batch calls
+    (Context.align_batch_chunks), inputs device-resident, every output; each
+    slice's outputs are dropped once its call returns (the CIGAR arena of all
+    pairs at once would not fit).  The oracle checks the first check_pairs
+    pairs of the first slice."""
+    import numpy as np
+    import torch
+
+    import paper_1208_6350_amd as swx
+    import workloads as W
+    t = time.perf_counter()
+    b = W.all_vs_all(n_reads=n_reads)
+    gen_s = time.perf_counter() - t
+    dev = torch.device("cuda:0")
+    to = lambda x: torch.as_tensor(np.ascontiguousarray(x)).to(dev)
+    dq, dqo, dpq, dpr = to(b.qcat), to(b.qoff), to(b.pair_q), to(b.pair_r)
+    args = (b.matrix, b.gap_open, b.gap_extend, dq, dqo, dq, dqo)
+    # warm-up: one small slice
+    for _ in ctx.align_batch_chunks(*args, dpq[:100_000], dpr[:100_000], chunk_pairs=100_000):
+        pass
+    torch.cuda.synchronize()
+    first = None
+    t = time.perf_counter()
+    nslices = 0
+    for k0, k1, recs, cig in ctx.align_batch_chunks(*args, dpq, dpr, chunk_pairs=chunk_pairs):
+        nslices += 1
+        if first is None:
+            n = min(check_pairs, k1 - k0)
+            first = (recs[:n * swx.REC_DTYPE.itemsize].cpu().numpy().view(swx.REC_DTYPE).copy(),
+                     cig.cpu().numpy().view(np.uint32).copy(), n)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    out = {"reads": n_reads, "read_len": 70, "pairs": b.npairs, "cells": b.cells(),
+           "slices": nslices, "slice_pairs": chunk_pairs, "ms": round(dt * 1e3, 1),
+           "gcups": round(b.cells() / dt / 1e9, 1), "pairs_per_s": round(b.npairs / dt, 0),
+           "generate_s": round(gen_s, 1)}
+    if with_oracle:   # the oracle beside the timed run, as for cpu_baseline
+        import oracle
+        from tests.fullsize import mismatches
+        recs, cig, n = first
+        s = b.subset(np.arange(n))
+        ref, rcig, rcoff = oracle.align_many(s.qcat, s.qoff, s.rcat, s.roff, s.pair_q, s.pair_r,
+                                             s.matrix, s.gap_open, s.gap_extend,
+                                             nthreads=os.cpu_count() or 1)
+        out["parity"] = {"pairs": n, "mismatches": mismatches(recs, cig, ref, rcig,
+                                                              rcoff)["pairs_bad"]}
+    return out
 
 
 def graph_phase(ctx, batch=512, reps=20):
@@ -611,6 +665,10 @@ def main():
         finally:
             cctx.close()
     avsa = None if args.headline_only else all_vs_all_phase(ctx)
+    avsa_large = None
+    if not args.headline_only and not args.no_large_avsa:
+        print("[bench] all-vs-all at scale", flush=True, file=sys.stderr)
+        avsa_large = all_vs_all_large_phase(ctx, with_oracle=not args.no_cpu)
 
     # per-pair form: the same library, one pair per call
     per_pair = None
@@ -663,6 +721,7 @@ def main():
         "graph": graph_cmp,
         "lane_widths": lanes,
         "all_vs_all": avsa,
+        "all_vs_all_large": avsa_large,
         "configs": configs,
         "per_pair": per_pair,
     }

@@ -471,6 +471,58 @@ class Context:
         return (recs, cig[:used]) if sub is None else (recs, cig[:used], sub)
 
 
+    def align_batch_chunks(self, matrix, o, e, qcat, qoff, rcat, roff, pair_q, pair_r,
+                           chunk_pairs, cigar_words_per_pair=16, flags=SWX_ALL, mask_len=-1,
+                           stream=None):
+        """A pair list of any length in slices: yields (k0, k1, recs, cigar)
+        for each slice [k0, k1) of at most chunk_pairs pairs, computed by one
+        swx_align_batch call each.  Inputs are either all numpy arrays (host)
+        or all torch tensors on the context's device (device-resident; the
+        pair lists are sliced as views).  recs (chunk_pairs records) and the
+        CIGAR arena are reused from slice to slice -- consume or copy them
+        before the next one -- so the device memory held stays at one
+        slice's outputs however many pairs there are; a slice whose CIGARs
+        outgrow the arena (cigar_words_per_pair words per pair to start with)
+        is run again with one that fits.  recs[:k1 - k0] and cigar[:used] are
+        the slice's records (cigar_off relative to the slice's arena) and
+        CIGAR words."""
+        dev = hasattr(pair_q, "data_ptr")
+        npairs = int(pair_q.numel() if dev else len(pair_q))
+        chunk_pairs = max(1, int(chunk_pairs))
+        cap = max(1, min(chunk_pairs, npairs) * int(cigar_words_per_pair))
+        if dev:
+            import torch
+            recs = torch.empty(min(chunk_pairs, npairs) * REC_DTYPE.itemsize, dtype=torch.uint8,
+                               device=pair_q.device)
+            cig = torch.empty(cap, dtype=torch.int32, device=pair_q.device)
+            mem = SWX_MEM_DEVICE
+        else:
+            qcat = np.ascontiguousarray(qcat, dtype=np.int8)
+            rcat = np.ascontiguousarray(rcat, dtype=np.int8)
+            qoff, roff, pair_q, pair_r = (np.ascontiguousarray(x, dtype=np.int64)
+                                          for x in (qoff, roff, pair_q, pair_r))
+            recs = np.zeros(min(chunk_pairs, npairs), dtype=REC_DTYPE)
+            cig = np.zeros(cap, dtype=np.uint32)
+            mem = SWX_MEM_HOST
+        for k0 in range(0, npairs, chunk_pairs):
+            k1 = min(npairs, k0 + chunk_pairs)
+            pq, pr = pair_q[k0:k1], pair_r[k0:k1]
+            while True:
+                st, used = swx_align_batch(self.handle, matrix, o, e, qcat, qoff, rcat, roff, pq,
+                                           pr, flags, mask_len, mem, recs, cig, mem, None, stream)
+                if st == SWX_ERANGE and used > cap:
+                    cap = used
+                    if dev:
+                        import torch
+                        cig = torch.empty(cap, dtype=torch.int32, device=pair_q.device)
+                    else:
+                        cig = np.zeros(cap, dtype=np.uint32)
+                    continue
+                _check(st, "swx_align_batch")
+                break
+            yield k0, k1, recs, cig[:used]
+
+
 # ---- graph mode ---------------------------------------------------------------
 class Graph:
     """The batched path captured as one hipGraph for batches of a fixed
