@@ -142,6 +142,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
   int32_t *s_rrow = SPREAD ? gs->rrow : l_rrow;
   unsigned long long *s_best = SPREAD ? &gs->best : &l_best;
   const IntraJob jb = a.jobs[jix];
+  if (!REV && jb.c1 <= jb.cw) return;   // an empty column chunk
   const int64_t p = jb.pair;
   const int32_t Lq = a.view.qlen[p];
   const int64_t Lr = a.view.rlen[p];
@@ -732,23 +733,53 @@ __global__ __launch_bounds__(64) void k_intra_finish(IntraPairArgs a, int mode) 
   }
 }
 
-// ---- fixed-capacity (graph) jobs: one per pair, fixed strides -------------
-__global__ void k_intra_jobs_fixed(int64_t B, const int64_t *rlen, int32_t kbits, int32_t sh,
-                                   int64_t mc_stride, int64_t bnd_stride, IntraJob *jobs,
-                                   IntraPair *pairs) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= B) return;
+// ---- fixed-capacity (graph) jobs: fixed counts and strides -----------------
+// Fixed-capacity jobs cut into nc column chunks of cw_ columns per pair: job
+// k * nc + c owns columns [c * cw_, (c + 1) * cw_) of pair k and starts W =
+// Lq + floor(max(smax * Lq - o, 0) / e) + 1 columns early (no positive-scoring
+// path is wider, so its owned columns are exact); with e = 0 chunk 0 owns the
+// whole reference.  Chunks past the reference are empty.
+__global__ void k_intra_jobs_chunked(int64_t B, int32_t nc, int64_t cw_, const int32_t *qlen,
+                                     const int64_t *rlen, int32_t smax, int32_t o, int32_t e,
+                                     int32_t kbits, int32_t sh, int64_t mc_stride,
+                                     int64_t bnd_stride, IntraJob *jobs, IntraPair *pairs) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= B * nc) return;
+  const int64_t k = x / nc;
+  const int32_t c = (int32_t)(x % nc);
+  const int64_t Lr = rlen[k], Lq = qlen[k];
+  int64_t c0 = (int64_t)c * cw_, c1 = c0 + cw_, W = Lr;
+  if (e > 0) {
+    const int64_t gain = (int64_t)smax * Lq - o;
+    W = Lq + (gain > 0 ? gain : 0) / e + 1;
+  } else {
+    c0 = c == 0 ? 0 : Lr;
+    c1 = c == 0 ? Lr : Lr;
+  }
+  if (c1 > Lr) c1 = Lr;
+  if (c0 > Lr) c0 = Lr;
   IntraJob jb{};
   jb.pair = k;
-  jb.cw = 0;
-  jb.c0 = 0;
-  jb.c1 = rlen[k];
+  jb.c0 = c0;
+  jb.c1 = c1;
+  jb.cw = c0 >= c1 ? c1 : (c0 - W > 0 ? c0 - W : 0);
   jb.mc_off = k * mc_stride;
-  jb.bnd_off = k * bnd_stride;
+  jb.bnd_off = x * bnd_stride;
   jb.kbits = kbits;
   jb.band = -1;
-  jobs[k] = jb;
-  pairs[k] = IntraPair{k, k * mc_stride, kbits, sh};
+  jobs[x] = jb;
+  if (c == 0) pairs[k] = IntraPair{k, k * mc_stride, kbits, sh};
+}
+
+hipError_t intra_jobs_chunked(int64_t B, int32_t nc, int64_t cw, const int32_t *qlen,
+                              const int64_t *rlen, int32_t smax, int32_t o, int32_t e,
+                              int32_t kbits, int32_t sh, int64_t mc_stride, int64_t bnd_stride,
+                              IntraJob *jobs, IntraPair *pairs, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  const int64_t n = B * nc;
+  hipLaunchKernelGGL(k_intra_jobs_chunked, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, B,
+                     nc, cw, qlen, rlen, smax, o, e, kbits, sh, mc_stride, bnd_stride, jobs, pairs);
+  return hipGetLastError();
 }
 
 __global__ void k_intra_rev_jobs_fixed(int64_t B, const int32_t *score, const int64_t *rend,
@@ -766,15 +797,6 @@ __global__ void k_intra_rev_jobs_fixed(int64_t B, const int32_t *score, const in
   jb.kbits = kbits;
   jb.band = band[k];
   jobs[k] = jb;
-}
-
-hipError_t intra_jobs_fixed(int64_t B, const int64_t *rlen, int32_t kbits, int32_t sh,
-                            int64_t mc_stride, int64_t bnd_stride, IntraJob *jobs, IntraPair *pairs,
-                            hipStream_t st) {
-  if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_intra_jobs_fixed, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, B, rlen,
-                     kbits, sh, mc_stride, bnd_stride, jobs, pairs);
-  return hipGetLastError();
 }
 
 hipError_t intra_rev_jobs_fixed(int64_t B, const int32_t *score, const int64_t *rend,

@@ -842,6 +842,9 @@ static int split_pairs(swx_ctx *ctx, int64_t np, const int32_t *qlen, const int6
                      lp.info);
 }
 
+// Most column chunks per pair of a graph's intra-sequence forward pass.
+constexpr int64_t kGraphMaxChunks = 16;
+
 // Waves per workgroup of an intra job: one per strip, within the LDS budget
 // (a profile of (n + 1) * 64 * RL bytes per wave) and the kernel's maximum.
 static int intra_waves(int64_t nstrips, int n, int RL) {
@@ -1560,7 +1563,10 @@ struct GraphState {
   bool intra = false;
   int RL = 16, waves = 1;
   int32_t kbits = 1, sh = 1024;
-  int64_t bnd_stride = 0;
+  int64_t bnd_stride = 0;      // reversed pass: hand-over rows per pair
+  int32_t nc = 1;              // forward pass: column chunks per pair ...
+  int64_t chunk = 0;           // ... of this many columns ...
+  int64_t fbnd_stride = 0;     // ... and hand-over rows per chunk
   IntraJob *jobs = nullptr, *rjobs = nullptr;
   IntraPair *ipairs = nullptr;
   uint32_t *maxcol = nullptr, *ibnd = nullptr;
@@ -1684,8 +1690,9 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
   IntraArgs ia{};
   if (g.intra) {
     HIP_TRY(fill_u8(4 * B * g.RM, (uint8_t *)g.maxcol, 0, st));
-    HIP_TRY(intra_jobs_fixed(B, g.rlen, g.kbits, g.sh, g.RM, g.bnd_stride, g.jobs, g.ipairs, st));
-    ia.jobs = g.jobs; ia.njobs = B; ia.view = fview; ia.matrix = g.sc.dmat;
+    HIP_TRY(intra_jobs_chunked(B, g.nc, g.chunk, g.qlen, g.rlen, g.sc.smax, g.sc.o, g.sc.e,
+                               g.kbits, g.sh, g.RM, g.fbnd_stride, g.jobs, g.ipairs, st));
+    ia.jobs = g.jobs; ia.njobs = B * g.nc; ia.view = fview; ia.matrix = g.sc.dmat;
     ia.n = g.sc.n; ia.o = g.sc.o; ia.e = g.sc.e; ia.bias = g.sc.bias;
     ia.maxcol = g.maxcol; ia.bnd = g.ibnd; ia.err = g.err;
     HIP_TRY(intra_fill(ia, g.RL, g.waves, false, st));
@@ -1719,6 +1726,7 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
       HIP_TRY(intra_rev_jobs_fixed(B, g.score, g.rend, g.band, g.kbits, g.bnd_stride, g.rjobs, st));
       IntraArgs ra = ia;
       ra.jobs = g.rjobs;
+      ra.njobs = B;   // one reversed job per pair (the forward pass had g.nc per pair)
       ra.view = rview;
       ra.maxcol = nullptr;
       ra.target = g.tgt;
@@ -1866,11 +1874,29 @@ static int graph_alloc(GraphState &g) {
       return fail(SWX_EOVERFLOW, "score range and query length exceed the max-array word");
     g.waves = intra_waves(nstrips, g.sc.n, g.RL);
     g.bnd_stride = 2 * (nstrips - 1) * g.RM;
-    g.jobs = A.get<IntraJob>(B);
+    // the forward pass cuts each reference into column chunks that start the
+    // widest positive-scoring span early (for the capacity's query length;
+    // a shorter query starts later), so that a pair spreads over several
+    // workgroups instead of sweeping its reference on one
+    g.nc = 1;
+    g.chunk = std::max<int64_t>(g.RM, 1);
+    int64_t wcap = g.RM;
+    if (g.sc.e > 0) {
+      wcap = g.QM + std::max<int64_t>((int64_t)g.sc.smax * g.QM - g.sc.o, 0) / g.sc.e + 1;
+      const int64_t C = std::max<int64_t>(256, (wcap + 1) / 2);
+      const int64_t nc = std::min<int64_t>(kGraphMaxChunks, (g.RM + C - 1) / C);
+      if (nc > 1) {
+        g.nc = (int32_t)nc;
+        g.chunk = (g.RM + nc - 1) / nc;
+      }
+    }
+    g.fbnd_stride = 2 * (nstrips - 1) * std::min<int64_t>(g.RM, g.chunk + wcap);
+    g.jobs = A.get<IntraJob>(B * g.nc);
     g.rjobs = A.get<IntraJob>(B);
     g.ipairs = A.get<IntraPair>(B);
     g.maxcol = A.get<uint32_t>(B * std::max<int64_t>(g.RM, 1));
-    g.ibnd = A.get<uint32_t>(std::max<int64_t>(B * g.bnd_stride, 1));
+    g.ibnd = A.get<uint32_t>(std::max<int64_t>(
+        {B * g.bnd_stride, B * g.nc * g.fbnd_stride, int64_t(1)}));
     g.part_v = A.get<int32_t>(B * intra_slices());
     g.part_j = A.get<int64_t>(B * intra_slices());
     if (!g.jobs || !g.rjobs || !g.ipairs || !g.maxcol || !g.ibnd || !g.part_v || !g.part_j)

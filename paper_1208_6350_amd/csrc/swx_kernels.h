@@ -236,9 +236,10 @@ hipError_t intra_fill16(const IntraArgs &a, int RL, int waves, hipStream_t st);
 size_t intra_lds_bytes16(int n, int RL);
 int intra_max_strips();
 int intra_max_waves();
-hipError_t intra_jobs_fixed(int64_t B, const int64_t *rlen, int32_t kbits, int32_t sh,
-                            int64_t mc_stride, int64_t bnd_stride, IntraJob *jobs, IntraPair *pairs,
-                            hipStream_t st);
+hipError_t intra_jobs_chunked(int64_t B, int32_t nc, int64_t cw, const int32_t *qlen,
+                              const int64_t *rlen, int32_t smax, int32_t o, int32_t e,
+                              int32_t kbits, int32_t sh, int64_t mc_stride, int64_t bnd_stride,
+                              IntraJob *jobs, IntraPair *pairs, hipStream_t st);
 hipError_t intra_rev_jobs_fixed(int64_t B, const int32_t *score, const int64_t *rend,
                                 const int32_t *band, int32_t kbits, int64_t bnd_stride,
                                 IntraJob *jobs, hipStream_t st);
