@@ -39,14 +39,25 @@ def dna_matrix(match: int = 2, mismatch: int = -2, n: int = DNA) -> np.ndarray:
 def protein_matrix_standin(seed: int = SEED_BASE + 300) -> np.ndarray:
     """A labelled STAND-IN for BLOSUM62 (no such table is available here).
 
-    Symmetric 24 x 24 int8 with off-diagonal entries in [-4, 3] and a dominant
-    diagonal in [4, 11]; the last four codes (ambiguity/stop) score -1 against
-    residues and 1 against themselves.
+    Symmetric 24 x 24 int8 with a dominant diagonal in [4, 11] and
+    off-diagonal entries drawn from [-4, 3], then lowered by one at a time
+    (never below -4) until the expected score of two residues drawn from the
+    background frequencies (background_standin) is at most -1, as for
+    BLOSUM-type matrices (a local alignment of unrelated sequences then stays
+    short; with a positive expectation every target would align end to end).
+    The last four codes (ambiguity/stop) score -1 against residues and 1
+    against themselves.
     """
     g = np.random.Generator(np.random.PCG64(seed))
-    m = g.integers(-4, 4, size=(N_PROTEIN, N_PROTEIN)).astype(np.int8)
+    m = g.integers(-4, 4, size=(N_PROTEIN, N_PROTEIN)).astype(np.int64)
     m = np.triu(m) + np.triu(m, 1).T
-    np.fill_diagonal(m, g.integers(4, 12, size=N_PROTEIN).astype(np.int8))
+    np.fill_diagonal(m, g.integers(4, 12, size=N_PROTEIN))
+    f = background_standin()[:20]
+    off = ~np.eye(20, dtype=bool)
+    while float(f @ m[:20, :20] @ f) > -1.0:
+        sub = m[:20, :20]
+        sub[off] = np.maximum(sub[off] - 1, -4)
+        m[:20, :20] = sub
     m[20:, :] = -1
     m[:, 20:] = -1
     for k in range(20, N_PROTEIN):
