@@ -79,8 +79,18 @@ __global__ void k_tb_classify(TbArgs a, int64_t npairs, uint8_t *cls, uint64_t *
     }
   }
   cls[p] = c;
-  // class, then rows (clamped: only the grouping of similar heights matters)
-  key[p] = ((uint64_t)c << (kTbKeyBits - 3)) | (uint64_t)(m > 0xFFFFF ? 0xFFFFF : m);
+  // class, then rows (clamped: only the grouping of similar heights matters);
+  // wide bands (16 pairs share a task's column window, the union of their
+  // bands) by rows in steps of 16, then lowest and highest diagonal, so that
+  // a task's pairs have similar bands
+  uint64_t sub = (uint64_t)(m > 0xFFFFF ? 0xFFFFF : m);
+  if (c == 5) {
+    const int64_t mq = m / 16 > 63 ? 63 : m / 16;
+    const int64_t lo = -dlo < 0 ? 0 : (-dlo > 127 ? 127 : -dlo);
+    const int64_t hi = dlo + bw - 1 + 32;
+    sub = (uint64_t)(mq << 14) | (uint64_t)(lo << 7) | (uint64_t)(hi < 0 ? 0 : (hi > 127 ? 127 : hi));
+  }
+  key[p] = ((uint64_t)c << (kTbKeyBits - 3)) | sub;
   vals[p] = p;
   ccap[p] = (c != 0) ? (m + w + 2) : 0;
 }
