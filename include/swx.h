@@ -73,8 +73,8 @@ extern "C" {
 #define SWX_SCORE2  4u     /* compute score2 / ref_end2; implies SWX_BEGIN */
 #define SWX_ALL     7u
 #define SWX_SUBOPT  8u     /* also the alignment behind score2 (method section; the dashed
-                              path of Fig. 1): batch calls only, into swx_batch_out.sub_recs;
-                              implies SWX_ALL.  Reading: it ends in column ref_end2 at the
+                              path of Fig. 1): into swx_batch_out.sub_recs for batch calls,
+                              swx_result.sub for swx_align; implies SWX_ALL.  Reading: it ends in column ref_end2 at the
                               smallest row whose H equals score2; its begin is T2 relative to
                               that end (among begins of alignments reaching the end with
                               score exactly score2: largest ref begin, then largest query
@@ -98,11 +98,15 @@ typedef struct {
   int32_t lane_bits;   /* lane width that produced the result (16 or 32); diagnostic only */
 } swx_rec;
 
-/* Single-pair result: the record plus a CIGAR owned by the result
- * (release with swx_result_free). */
+/* Single-pair result: the record plus a CIGAR owned by the result, and with
+ * SWX_SUBOPT the suboptimal alignment's record (score1 = score2, begins and
+ * end of that alignment; score2 0, ref_end2 -1) and CIGAR (release both with
+ * swx_result_free; sub is zeroed and sub_cigar NULL without SWX_SUBOPT). */
 typedef struct {
   swx_rec rec;
   uint32_t *cigar;
+  swx_rec sub;
+  uint32_t *sub_cigar;
 } swx_result;
 
 /* ---- context --------------------------------------------------------------
@@ -128,7 +132,8 @@ int swx_profile_destroy(swx_profile *p);
  * p: a profile of this library (its context runs the call).  ref: [rlen]
  * codes in host memory, or device memory of the context's GPU when flags has
  * SWX_REF_DEVICE; the caller keeps ownership.  rlen == 0 is valid and yields
- * "no alignment".  flags: SWX_BEGIN | SWX_CIGAR | SWX_SCORE2 (+ SWX_REF_DEVICE);
+ * "no alignment".  flags: SWX_BEGIN | SWX_CIGAR | SWX_SCORE2 | SWX_SUBOPT
+ * (+ SWX_REF_DEVICE);
  * mask_len as for swx_align_batch.  hip_stream: a hipStream_t of the
  * context's device, or NULL for the context's own stream; the call's device
  * work is queued on it, after whatever the caller queued there before (a
@@ -139,8 +144,9 @@ int swx_profile_destroy(swx_profile *p);
  * qlen <= 4096 and rlen <= 65536 replays a graph of capacity one pair (the
  * chain of swx_graph_*, one pair spread over a wave) captured on first use
  * for its scoring scheme, flags, mask width and power-of-two size class and
- * kept on the context (at most 8, least recently used replaced); larger pairs
- * take the batch path.  Either way the result equals swx_align_batch's.
+ * kept on the context (at most 8, least recently used replaced); larger pairs,
+ * and calls with SWX_SUBOPT, take the batch path.  Either way the result
+ * equals swx_align_batch's.
  * Errors: SWX_EINVAL (null p or out, rlen < 0, unknown flag bits, a symbol
  * >= n: out untouched beyond being zeroed), SWX_EDEVICE, SWX_ENOMEM. */
 #define SWX_REF_DEVICE (1u << 8)

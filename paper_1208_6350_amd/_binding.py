@@ -40,7 +40,8 @@ class SwxRec(ctypes.Structure):
 
 
 class SwxResult(ctypes.Structure):
-    _fields_ = [("rec", SwxRec), ("cigar", ctypes.POINTER(ctypes.c_uint32))]
+    _fields_ = [("rec", SwxRec), ("cigar", ctypes.POINTER(ctypes.c_uint32)),
+                ("sub", SwxRec), ("sub_cigar", ctypes.POINTER(ctypes.c_uint32))]
 
 
 class SwxBatch(ctypes.Structure):
@@ -255,7 +256,8 @@ def swx_align(profile: int, ref, flags: int = SWX_ALL, mask_len: int = -1, strea
     """Align one reference (numpy int8, or a device pointer with its length as a
     tuple (ptr, rlen) and flags | SWX_REF_DEVICE) on `stream` (a torch stream,
     a raw hipStream_t, or None for the context's own).  Returns (record dict,
-    cigar list)."""
+    cigar list), and with SWX_SUBOPT also the suboptimal alignment's (record
+    dict, cigar list)."""
     res = SwxResult()
     if isinstance(ref, tuple):
         ptr, rlen = ref
@@ -268,7 +270,11 @@ def swx_align(profile: int, ref, flags: int = SWX_ALL, mask_len: int = -1, strea
     _check(st, "swx_align")
     rec = {k: getattr(res.rec, k) for k, _ in SwxRec._fields_}
     cig = [res.cigar[k] for k in range(res.rec.cigar_len)] if res.rec.cigar_len else []
+    sub = {k: getattr(res.sub, k) for k, _ in SwxRec._fields_}
+    scig = [res.sub_cigar[k] for k in range(res.sub.cigar_len)] if res.sub.cigar_len else []
     lib().swx_result_free(ctypes.byref(res))
+    if flags & SWX_SUBOPT:
+        return rec, decode_cigar(cig), sub, decode_cigar(scig)
     return rec, decode_cigar(cig)
 
 

@@ -2198,7 +2198,9 @@ int swx_profile_destroy(swx_profile *p) {
 void swx_result_free(swx_result *r) {
   if (!r) return;
   free(r->cigar);
+  free(r->sub_cigar);
   r->cigar = nullptr;
+  r->sub_cigar = nullptr;
 }
 
 int64_t swx_cigar_bound(const swx_batch *b) {
@@ -2370,9 +2372,11 @@ int swx_align(const swx_profile *p, const int8_t *ref, int64_t rlen, uint32_t fl
               int32_t mask_len, void *hip_stream, swx_result *out) {
   if (!p || !out || (rlen > 0 && !ref)) return fail(SWX_EINVAL, "null argument");
   if (rlen < 0) return fail(SWX_EINVAL, "rlen must be >= 0");
-  if (flags & ~(SWX_ALL | SWX_REF_DEVICE)) return fail(SWX_EINVAL, "unknown flag bits");
+  if (flags & ~(SWX_ALL | SWX_SUBOPT | SWX_REF_DEVICE)) return fail(SWX_EINVAL, "unknown flag bits");
   swx_ctx *ctx = p->ctx;
   memset(out, 0, sizeof(*out));
+  const bool subopt = (flags & SWX_SUBOPT) != 0;
+  if (subopt) flags |= SWX_ALL;
   std::vector<int8_t> href;
   const int8_t *rptr = ref;
   if (flags & SWX_REF_DEVICE) {
@@ -2390,7 +2394,7 @@ int swx_align(const swx_profile *p, const int8_t *ref, int64_t rlen, uint32_t fl
     }
     rptr = href.data();
   }
-  {
+  if (!subopt) {
     const int64_t qoff[2] = {0, (int64_t)p->query.size()};
     const int64_t roff[2] = {0, rlen};
     const int64_t pq = 0, pr = 0;
@@ -2426,20 +2430,28 @@ int swx_align(const swx_profile *p, const int8_t *ref, int64_t rlen, uint32_t fl
   b.qcat = p->query.data(); b.qcat_len = (int64_t)p->query.size(); b.qoff = qoff; b.nq = 1;
   b.rcat = rptr; b.rcat_len = rlen; b.roff = roff; b.nr = 1;
   b.pair_q = &pq; b.pair_r = &pr; b.npairs = 1;
-  b.flags = flags & SWX_ALL; b.mask_len = mask_len; b.in_mem = SWX_MEM_HOST;
-  swx_rec rec{};
-  std::vector<uint32_t> cig((size_t)(p->query.size() + rlen + 2));
-  swx_batch_out bo{&rec, cig.data(), (int64_t)cig.size(), 0, SWX_MEM_HOST};
+  b.flags = flags & (SWX_ALL | SWX_SUBOPT); b.mask_len = mask_len; b.in_mem = SWX_MEM_HOST;
+  swx_rec rec{}, sub{};
+  // the suboptimal alignment's CIGAR goes to the same arena
+  std::vector<uint32_t> cig((size_t)((subopt ? 2 : 1) * (p->query.size() + rlen + 2)));
+  swx_batch_out bo{&rec, cig.data(), (int64_t)cig.size(), 0, SWX_MEM_HOST, 0, subopt ? &sub : nullptr};
   int rc = align_batch_locked(ctx, &b, &bo, p);
   if (rc) return rc;
-  out->rec = rec;
-  out->cigar = nullptr;
-  if (rec.cigar_len > 0) {
-    out->cigar = (uint32_t *)malloc(sizeof(uint32_t) * rec.cigar_len);
-    if (!out->cigar) return fail(SWX_ENOMEM, "host allocation failed");
-    memcpy(out->cigar, cig.data() + rec.cigar_off, sizeof(uint32_t) * rec.cigar_len);
+  auto copy_out = [&](const swx_rec &r, swx_rec &dst, uint32_t *&dcig) {
+    dst = r;
+    dcig = nullptr;
+    if (r.cigar_len > 0) {
+      dcig = (uint32_t *)malloc(sizeof(uint32_t) * r.cigar_len);
+      if (!dcig) return false;
+      memcpy(dcig, cig.data() + r.cigar_off, sizeof(uint32_t) * r.cigar_len);
+    }
+    dst.cigar_off = 0;
+    return true;
+  };
+  if (!copy_out(rec, out->rec, out->cigar) || (subopt && !copy_out(sub, out->sub, out->sub_cigar))) {
+    swx_result_free(out);
+    return fail(SWX_ENOMEM, "host allocation failed");
   }
-  out->rec.cigar_off = 0;
   return SWX_OK;
 }
 

@@ -380,3 +380,29 @@ def test_suboptimal_alignment(ctx, mask_len):
             pg = cig[recs["cigar_off"][p]:recs["cigar_off"][p] + recs["cigar_len"][p]]
             assert np.array_equal(pg, rcig[rcoff[p]:rcoff[p] + ref[p, 7]]), p
         assert (s2 > 0).sum() > b.npairs // 3
+
+
+def test_single_pair_suboptimal(ctx):
+    """SWX_SUBOPT through the one-pair call (swx_align): the primary record and
+    CIGAR, and the suboptimal alignment's begins, end and CIGAR, equal the
+    oracle's, pair by pair."""
+    for b in (_two_copy_pairs(74, 24), _two_copy_pairs(75, 12, alphabet=24, o=11, e=1)):
+        _say(f"[parity] {b.name}: one-pair calls with the suboptimal alignment")
+        ref, rcig, rcoff = oracle.align_many(b.qcat, b.qoff, b.rcat, b.roff, b.pair_q, b.pair_r,
+                                             b.matrix, b.gap_open, b.gap_extend)
+        seen2 = 0
+        for p in range(b.npairs):
+            q, r = b.query(p), b.ref(p)
+            rec, cig, sub, scig = ctx.align_pair(q, r, b.matrix, b.gap_open, b.gap_extend,
+                                                 flags=swx.SWX_ALL | swx.SWX_SUBOPT)
+            for k, f in enumerate(FIELDS):
+                assert rec[f] == ref[p, k], (p, f)
+            assert cig == swx.decode_cigar(rcig[rcoff[p]:rcoff[p] + ref[p, 7]]), p
+            rb2, re2, fb2, ocig = oracle.suboptimal(q, r, b.matrix, b.gap_open, b.gap_extend,
+                                                    int(ref[p, 1]), int(ref[p, 6]))
+            assert sub["score1"] == ref[p, 1], p
+            assert (sub["read_begin1"], sub["read_end1"], sub["ref_begin1"]) == (rb2, re2, fb2), p
+            assert sub["ref_end1"] == ref[p, 6], p
+            assert scig == ocig, (p, scig, ocig)
+            seen2 += ref[p, 1] > 0
+        assert seen2 > b.npairs // 3
