@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed steps (no autotuner, output modes, graph, per-pair, "
                          "serving or CPU phases): the form the kernel profiles are taken of")
+    ap.add_argument("--only-config", choices=["c1", "c2", "c3", "c5_long"], default=None,
+                    help="run only this entry of the per-configuration phase (default "
+                         "settings, no oracle with --no-cpu) and print it: the form the "
+                         "per-configuration kernel profiles are taken of")
     ap.add_argument("--no-large-avsa", action="store_true",
                     help="skip the all-vs-all run at read-overlap-graph scale (2e8 pairs)")
     ap.add_argument("--no-configs", action="store_true",
@@ -433,7 +437,7 @@ def _entry(name, workload, b, ts, stages, recs, oracle_t, parity):
             "oracle": oracle_t, "parity": parity}
 
 
-def config_phase(ctx, reps=3, with_oracle=True):
+def config_phase(ctx, reps=3, with_oracle=True, only=None):
     """The other workloads, each timed alone through the same entry point:
     the single short pair (also one call per pair through swx_align), the
     single long-reference pair, the protein one-against-many search at full
@@ -463,6 +467,21 @@ def config_phase(ctx, reps=3, with_oracle=True):
         return {"pairs": n, "mismatches": bad["pairs_bad"]}
 
     # single short pair: batch entry point, and per call through swx_align
+    if only in (None, "c1"):
+        _config1(ctx, reps, with_oracle, out, oracle_pairs, check)
+    if only in (None, "c2"):
+        _config2(ctx, reps, with_oracle, out)
+    if only in (None, "c3"):
+        _config3(ctx, reps, with_oracle, out, oracle_pairs, check, threads)
+    if only in (None, "c5_long"):
+        _config5(ctx, reps, with_oracle, out, oracle_pairs, check)
+    return out
+
+
+def _config1(ctx, reps, with_oracle, out, oracle_pairs, check):
+    import numpy as np
+
+    import workloads as W
     b = W.config1()
     ts, st, (recs, cig) = _dev_call(ctx, b, reps * 10)
     orc = par = None
@@ -485,7 +504,15 @@ def config_phase(ctx, reps=3, with_oracle=True):
                      "min_ms": round(min(pt) * 1e3, 3)}
     out["c1"] = e
 
-    # single long-reference pair, checked against the oracle's stored result
+
+def _config2(ctx, reps, with_oracle, out):
+    """The single long-reference pair, checked against the oracle's stored
+    result."""
+    import numpy as np
+
+    import workloads as W
+    if with_oracle:
+        import oracle
     b = W.config2()
     ts, st, (recs, cig) = _dev_call(ctx, b, reps)
     orc = par = None
@@ -513,7 +540,10 @@ def config_phase(ctx, reps=3, with_oracle=True):
     out["c2"] = _entry("c2", "one 1,000-nt read vs a 5,000,000-nt reference", b, ts, st, recs,
                        orc, par)
 
-    # protein one-against-many search, full size
+
+def _config3(ctx, reps, with_oracle, out, oracle_pairs, check, threads):
+    """The protein one-against-many search at full size."""
+    import workloads as W
     b = W.config3()
     ts, st, (recs, cig) = _dev_call(ctx, b, reps)
     orc = par = None
@@ -526,7 +556,12 @@ def config_phase(ctx, reps=3, with_oracle=True):
     out["c3"] = _entry("c3", "protein search: 300-aa query vs 100,000 targets (50-5,000 aa)",
                        b, ts, st, recs, orc, par)
 
-    # one long serving request alone
+
+def _config5(ctx, reps, with_oracle, out, oracle_pairs, check):
+    """One long serving request alone."""
+    import numpy as np
+
+    import workloads as W
     pool = W.config5_pool(n_short=1, n_long=1)
     b = pool.subset(np.arange(1, 2))
     ts, st, (recs, cig) = _dev_call(ctx, b, reps)
@@ -538,7 +573,6 @@ def config_phase(ctx, reps=3, with_oracle=True):
         par = check(recs, cig, 1, res)
     out["c5_long"] = _entry("c5_long", "one long serving request: 10,000-nt read vs "
                             "20,000-nt window, 10% error", b, ts, st, recs, orc, par)
-    return out
 
 
 def main():
@@ -553,6 +587,14 @@ def main():
     import paper_1208_6350_amd as swx
     import workloads as W
 
+    if args.only_config:
+        cctx = swx.Context(0)
+        try:
+            out = config_phase(cctx, with_oracle=not args.no_cpu, only=args.only_config)
+        finally:
+            cctx.close()
+        print(json.dumps(out), flush=True)
+        return
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     b = W.config4(npairs=args.pairs)
