@@ -1173,10 +1173,8 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
   if (spin_fail) a.err[p] = 1;
 
   // ---- walk back from (m, w) in state H (rule T3), uniform on the wave ------
-  // The outer loop places the walk in a strip and a tile of its codes; the
-  // inner loop follows the path inside that tile on 32-bit local coordinates
-  // (tile step tl, lane L, row rr of the lane) until it leaves the tile, the
-  // strip or row 1.
+  // Each iteration places the walk in a strip and a tile of its codes and
+  // follows one run of the path (below).
   uint32_t *out = a.cig + a.cig_off[p];
   int32_t nruns = 0;
   int64_t i = m, j = w;
@@ -1188,14 +1186,14 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
   int64_t tile_s = -1, tile_lo = 0, tile_hi = -1;
   const uint8_t *tile = reinterpret_cast<const uint8_t *>(s_tile);
   bool bad = false;
-  auto emit = [&](uint32_t op) {
+  auto emit_run = [&](uint32_t op, uint32_t len) {
     if (op == cur_op) {
-      ++cur_len;
+      cur_len += len;
     } else {
       if (cur_len && lane == 0) out[nruns] = (cur_len << 4) | cur_op;
       if (cur_len) ++nruns;
       cur_op = op;
-      cur_len = 1;
+      cur_len = len;
     }
   };
   while ((i > 0 || j > 0) && guard > 0) {
@@ -1205,7 +1203,7 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
       if (state == 0) {
         state = code_src(c) == 1 ? 1 : 2;
       } else if (state == 1) {
-        emit(2);
+        emit_run(2u, 1u);
         state = (c & kCodeEExt) ? 1 : 0;
         --j;
       } else {
@@ -1236,71 +1234,67 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
       __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
       __builtin_amdgcn_wave_barrier();
     }
-    // inside the tile: tl = t - tile_lo; j - wclo = t - L stays >= 0 on a
-    // valid path (the band keeps it in the window).  A state-0 step that
-    // names E or F takes that gap step on the same cell at once (the code is
-    // the same); the codes of the three cells the next step can reach (up,
-    // left, diagonal) are read from LDS before the step is decided, so their
-    // latency hides behind it.
-    int tl = (int)(t - tile_lo);
-    const int jl0 = (int)(t - L);      // j - wclo at entry
-    int di = 0, dj = 0;                // rows and columns moved in this tile
-    const int gmax = guard < (int64_t)0x7FFFFFFF ? (int)guard : 0x7FFFFFFF;
-    int g = 0;
-    auto code_at = [&](int tl_, int L_, int rr_) -> uint32_t {
-      tl_ = tl_ < 0 ? 0 : tl_;
-      L_ = L_ < 0 ? 0 : L_;
-      const uint8_t *wp = tile + ((tl_ * 64 + L_) * WB);
+    // One run per iteration, on the whole wave: lane k reads the code of the
+    // k-th cell along the run's direction (diagonal for M, left for D, up for
+    // I; invalid past the strip's top, the window's left edge or the tile),
+    // and a ballot finds where the run ends.  In state H the diagonal run
+    // continues while a cell's code names the diagonal; a cell that names E
+    // or F takes that gap step at once (same code); a gap run continues while
+    // a cell's code extends the gap, the cell that does not still taking its
+    // step.  A run cut short by an unreadable cell resumes in the next
+    // iteration, after the strip cursor and the tile have moved.
+    const int jw = (int)(j - wclo);    // the current column in the window
+    const int xi = (int)x;             // the current row in the strip
+    const int tlo = (int)tile_lo;
+    auto lane_code = [&](int drow, int dcol, bool &valid) -> uint32_t {
+      const int xr = xi - lane * drow, jc = jw - lane * dcol;
+      const int xq = xr < 0 ? 0 : xr;
+      const int Lk = xq / RL, rk = xq % RL;
+      const int tk = jc + Lk - tlo;
+      valid = xr >= 0 && jc >= 0 && tk >= 0;
+      const uint8_t *wp = tile + (((valid ? tk : 0) * 64 + Lk) * WB);
       if constexpr (RL == 4) {
-        return ((uint32_t)*reinterpret_cast<const uint16_t *>(wp) >> (4 * (3 - rr_))) & 0xFu;
+        return ((uint32_t)*reinterpret_cast<const uint16_t *>(wp) >> (4 * (3 - rk))) & 0xFu;
       } else {
-        const uint32_t dv = reinterpret_cast<const uint32_t *>(wp)[rr_ >> 3];
-        return (dv >> (4 * (7 - (rr_ & 7)))) & 0xFu;
+        const uint32_t dv = reinterpret_cast<const uint32_t *>(wp)[rk >> 3];
+        return (dv >> (4 * (7 - (rk & 7)))) & 0xFu;
       }
     };
-    uint32_t c = code_at(tl, L, rr);
-    for (;;) {
-      // the cells one step up, left and diagonal
-      int rrU = rr - 1, LU = L, tlU = tl;
-      if (rrU < 0) { rrU = RL - 1; --LU; --tlU; }
-      const uint32_t cU = code_at(tlU, LU, rrU);
-      const uint32_t cL = code_at(tl - 1, L, rr);
-      const uint32_t cD = code_at(tlU - 1, LU, rrU);
-      // the step: 0 diagonal (M), 1 left (E: D), 2 up (F: I)
-      const uint32_t src = (c & kCodeNotM) ? ((c & kCodeF) ? 2u : 1u) : 0u;
-      uint32_t eff = state == 0 ? src : (uint32_t)state;
-      const int jcur = jl0 - dj + (int)wclo;
-      if (eff == 0 && jcur == 0) eff = 2;
-      state = eff == 0 ? 0 : eff == 1 ? ((c & kCodeEExt) ? 1 : 0) : ((c & kCodeFExt) ? 2 : 0);
-      emit(eff == 0 ? 0u : eff == 1 ? 2u : 1u);
-      ++g;
-      bool leave = g >= gmax;
-      if (eff == 1) {                  // left
-        ++dj;
-        --tl;
-        c = cL;
-      } else {                         // up, or diagonal (up and left)
-        ++di;
-        const bool lane_up = rr == 0;
-        rr = rrU;
-        L = LU;
-        tl = tlU;
-        if (eff == 0) {
-          ++dj;
-          --tl;
-          c = cD;
-        } else {
-          c = cU;
-        }
-        if (lane_up && L < 0) leave = true;   // into the strip above (or row 0)
-        if (i - di == 0) leave = true;
+    auto first_false = [](bool pred) -> int {
+      const unsigned long long bm = __ballot(pred);
+      return bm == ~0ull ? 64 : __builtin_ctzll(~bm);
+    };
+    if (state == 0) {
+      bool v;
+      const uint32_t ck = lane_code(1, 1, v);
+      const int K = first_false(v && (ck & kCodeNotM) == 0 && j - lane > 0);
+      if (K > 0) {
+        emit_run(0u, (uint32_t)K);
+        i -= K;
+        j -= K;
+        guard -= K;
+        continue;
       }
-      if (tl < 0 || jl0 - dj < 0) leave = true;   // past the tile, or left of the window
-      if (leave) break;
+      // the current cell (lane 0, always readable here) leaves the diagonal:
+      // its code names E or F (at column 0 the path can only go up)
+      const uint32_t c0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)ck);
+      const uint32_t src = code_src(c0);
+      state = src == 0 ? 2 : (int)src;
     }
-    i -= di;
-    j -= dj;
-    guard -= g;
+    const bool left = state == 1;
+    bool v;
+    const uint32_t ck = left ? lane_code(0, 1, v) : lane_code(1, 0, v);
+    const bool ext = v && (ck & (left ? kCodeEExt : kCodeFExt)) != 0 && (!left || j - lane > 0);
+    const int stop = first_false(ext);
+    // the cell that ends the run takes its step too, when it was readable
+    const bool ends = stop < 64 && ((__ballot(v) >> stop) & 1ull);
+    const int moves = ends ? stop + 1 : stop;
+    if (moves == 0) { bad = true; break; }
+    if (ends) state = 0;
+    emit_run(left ? 2u : 1u, (uint32_t)moves);
+    if (left) j -= moves;
+    else i -= moves;
+    guard -= moves;
   }
   if (lane != 0) return;
   if (bad || i != 0 || j != 0) a.err[p] = 1;
