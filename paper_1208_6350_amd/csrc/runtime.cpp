@@ -540,24 +540,46 @@ static int gather_info(swx_ctx *ctx, int64_t n, const int64_t *d_ids, const int3
                        const int64_t *rlen, const int32_t *score, const int32_t *qend,
                        const int64_t *rend, const int32_t *band, std::vector<int64_t> &info);
 
-// Rows per lane of a wave traceback over m rows, w columns and a band of bw
-// diagonals (0: too tall for every choice).  Strip s starts SH + 128 steps
-// after strip s - 1 and sweeps a window of SH + bw columns; a wave runs its
-// workgroup's strips in turn, and a step costs about 16 instructions per row
-// of a lane plus 30: the cheapest of the longer of those two paths.
-static int tb_wave_rl(int64_t m, int64_t w, int64_t bw, int n) {
-  int best = 0;
+// Shape of a wave traceback over m rows, w columns and a band of bw diagonals
+// when `jobs` such pairs share the device (rl 0: too tall for every choice).
+// Strip s starts SH + 128 steps after strip s - 1 and sweeps a window of
+// SH + bw columns; the waves of a pair's workgroups run its strips in turn,
+// and a step costs about 16 instructions per row of a lane plus 30: the
+// cheapest of the longer of those two paths.  With fewer pairs than compute
+// units a pair's strips spread over up to four waves in each of `segs`
+// workgroups (at most one per compute unit, 32 per XCD), as in the
+// intra-sequence fill.
+struct TbShape {
+  int rl, waves, segs;
+  bool operator<(const TbShape &x) const {
+    return rl != x.rl ? rl < x.rl : waves != x.waves ? waves < x.waves : segs < x.segs;
+  }
+  bool operator==(const TbShape &x) const { return rl == x.rl && waves == x.waves && segs == x.segs; }
+};
+
+static TbShape tb_wave_shape(int64_t m, int64_t w, int64_t bw, int n, int64_t jobs, int32_t cus) {
+  jobs = std::max<int64_t>(jobs, 1);
+  const int64_t segs_max =
+      (cus <= 0 || jobs >= cus)
+          ? 1
+          : std::max<int64_t>(1, std::min<int64_t>(cus / jobs, 32 / ((jobs + 7) / 8)));
+  TbShape best{0, 0, 0};
   double best_cost = 0;
   for (int RL : {4, 8, 16}) {
     const int64_t SH = 64 * RL, nstrips = (m + SH - 1) / SH;
     if (nstrips > tb_wave_max_strips()) continue;
-    const int64_t waves = tb_wave_waves(m, n, RL);
+    int64_t waves = tb_wave_waves(m, n, RL), g = 1;
+    if (segs_max > 1) {
+      const int64_t w4 = std::min<int64_t>(4, waves);
+      g = std::min<int64_t>(segs_max, (nstrips + w4 - 1) / w4);
+      if (g > 1) waves = w4;
+    }
     const int64_t win = std::min<int64_t>(SH + bw, w + 1) + 63;
     const int64_t chain = (nstrips - 1) * (SH + 128) + win;
-    const int64_t turns = (nstrips + waves - 1) / waves * win;
+    const int64_t turns = (nstrips + waves * g - 1) / (waves * g) * win;
     const double cost = (double)std::max(chain, turns) * (16 * RL + 30) * (waves > 4 ? 1.5 : 1.0);
-    if (best == 0 || cost < best_cost) {
-      best = RL;
+    if (best.rl == 0 || cost < best_cost) {
+      best = TbShape{RL, (int)waves, (int)g};
       best_cost = cost;
     }
   }
@@ -692,7 +714,7 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
     std::vector<int64_t> ids(nc);
     if ((rc = read_i64(ctx, sorted + pos, ids.data(), nc))) return rc;
     std::vector<TbWaveJob> jobs(nc);
-    std::vector<std::pair<int, int>> shape(nc);   // rows per lane, waves
+    std::vector<TbShape> shape(nc);
     int64_t dbytes = 0, bwords = 0;
     for (int64_t k = 0; k < nc; ++k) {
       TbWaveJob &jb = jobs[k];
@@ -700,7 +722,8 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
       jb.m = info[6 * k + 3] - info[6 * k + 0] + 1;
       jb.w = info[6 * k + 4] - info[6 * k + 1] + 1;
       safe_band(jb.m, jb.w, info[6 * k + 2], sc.smax, sc.o, sc.e, &jb.dlo, &jb.bw);
-      const int RL = tb_wave_rl(jb.m, jb.w, jb.bw, sc.n);
+      shape[k] = tb_wave_shape(jb.m, jb.w, jb.bw, sc.n, nc, ctx->cus);
+      const int RL = shape[k].rl;
       if (RL == 0) return fail(SWX_EINVAL, "alignment too long for the wave traceback");
       const int64_t SH = 64 * RL, nstrips = (jb.m + SH - 1) / SH;
       jb.dir_off = dbytes;
@@ -712,7 +735,6 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
       }
       dbytes = round_up(dbytes, 256);
       bwords += 2 * (jb.w + 1) * (nstrips + 1);
-      shape[k] = {RL, tb_wave_waves(jb.m, sc.n, RL)};
     }
     // launch groups of equal shape
     std::vector<int64_t> order(nc);
@@ -723,16 +745,27 @@ static int run_traceback(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, 
     TbWaveJob *dj = A.get<TbWaveJob>(nc);
     uint8_t *dirw = A.get<uint8_t>(std::max<int64_t>(dbytes, 256));
     int32_t *bnd = A.get<int32_t>(std::max<int64_t>(bwords, 1));
-    if (!dj || !dirw || !bnd) return fail(SWX_ENOMEM, "device pool exhausted (wave traceback)");
+    int64_t nspread = 0;
+    for (int64_t k = 0; k < nc; ++k) nspread += shape[k].segs > 1 ? 1 : 0;
+    IntraSync *sync = nspread ? A.get<IntraSync>(nspread) : nullptr;
+    if (!dj || !dirw || !bnd || (nspread && !sync))
+      return fail(SWX_ENOMEM, "device pool exhausted (wave traceback)");
     HIP_TRY(hipMemcpyAsync(dj, sorted_jobs.data(), sizeof(TbWaveJob) * nc, hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));   // the host job table must outlive the copy
     for (int64_t k0 = 0; k0 < nc;) {
       int64_t k1 = k0;
       while (k1 < nc && shape[order[k1]] == shape[order[k0]]) ++k1;
-      const int RL = shape[order[k0]].first, wv = shape[order[k0]].second;
+      const TbShape sh = shape[order[k0]];
       const TbWaveJob *jp = dj + k0;
       const int64_t cnt = k1 - k0;
-      launches.push_back({(double)dbytes * 32, [=](hipStream_t s_) { return tb_wave(ta, jp, cnt, RL, wv, dirw, bnd, s_); }});
+      IntraSync *gs = nullptr;
+      if (sh.segs > 1) {   // one progress record per spread pair
+        gs = sync;
+        sync += cnt;
+      }
+      launches.push_back({(double)dbytes * 32, [=](hipStream_t s_) {
+                            return tb_wave(ta, jp, cnt, sh.rl, sh.waves, sh.segs, gs, dirw, bnd, s_);
+                          }});
       k0 = k1;
     }
     pos += nc;

@@ -180,8 +180,10 @@ hipError_t tbw_offsets(int64_t ntasks, TbwTask *tasks, const int64_t *doff, cons
                        hipStream_t st);
 hipError_t tb_strip(const TbArgs &a, const TbwTask *tasks, int64_t ntasks, const int64_t *sorted,
                     int32_t *bndbuf, hipStream_t st);
+// segs > 1: each pair's strips spread over that many workgroups (sync: one
+// record per pair), then a walk kernel; else the fill and the walk in one
 hipError_t tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, int RL, int waves,
-                   uint8_t *dirw, int32_t *bnd, hipStream_t st);
+                   int segs, IntraSync *sync, uint8_t *dirw, int32_t *bnd, hipStream_t st);
 int tb_wave_waves(int64_t m, int n, int RL);   // waves per workgroup for a pair of m rows
 int tb_wave_max_strips();
 hipError_t fill_u8(int64_t n, uint8_t *p, uint8_t v, hipStream_t st);

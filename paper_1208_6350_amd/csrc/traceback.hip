@@ -968,39 +968,66 @@ __device__ __forceinline__ void tb_prof_load(const int8_t *src, uint32_t (&w)[RL
   }
 }
 
+// The walk back along the path (rule T3) over one pair's stored codes, by
+// one wave (uniform state); defined below.
 template <int RL>
+__device__ void tb_wave_walk(const TbArgs &a, const TbWaveJob &jb, const uint8_t *dir,
+                             uint4 *s_tile, int lane);
+
+// SPREAD: the pair's strips on the waves of `segs` workgroups (progress
+// records in global memory, agent scope, as in the intra-sequence fill; the
+// grid fits on the device at once), and the walk left to k_tb_walk.
+template <int RL, bool SPREAD>
 __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const TbWaveJob *jobs,
-                                                              uint8_t *dirw, int32_t *bndbuf) {
+                                                              int64_t njobs, int segs,
+                                                              IntraSync *sync, uint8_t *dirw,
+                                                              int32_t *bndbuf) {
   constexpr int64_t SH = 64 * RL;
   constexpr int WB = RL / 2;                      // code bytes per lane and step
-  constexpr int TS = kTbTileBytes / (64 * WB);    // steps per LDS tile
   extern __shared__ uint4 s_dyn[];                // per wave: profile [(n+1)][64][RL] score bytes
-  __shared__ uint4 s_tile[kTbTileBytes / 16];
+  __shared__ uint4 s_tile[SPREAD ? 1 : kTbTileBytes / 16];
   __shared__ int8_t s_mat[32 * 32];
-  __shared__ int32_t s_prog[kTbMaxStrips];        // columns of strip s's last row published
-  __shared__ int32_t s_done[kTbMaxStrips];
+  __shared__ int32_t l_prog[SPREAD ? 1 : kTbMaxStrips];   // columns of strip s's last row published
+  __shared__ int32_t l_done[SPREAD ? 1 : kTbMaxStrips];
+  constexpr int SCOPE = SPREAD ? __HIP_MEMORY_SCOPE_AGENT : __HIP_MEMORY_SCOPE_WORKGROUP;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int NW = blockDim.x >> 6;
-  const TbWaveJob jb = jobs[blockIdx.x];
+  // spread grids: block 8 * slot + x (slot = (j / 8) * G + segment) puts the
+  // segments of job j on XCD j % 8; blocks past the last job leave at once
+  const int G = SPREAD ? segs : 1;
+  int64_t jix = blockIdx.x, seg = 0;
+  if constexpr (SPREAD) {
+    const int64_t slot = blockIdx.x / 8;
+    jix = (slot / G) * 8 + blockIdx.x % 8;
+    seg = slot % G;
+    if (jix >= njobs) return;
+  }
+  int32_t *s_prog = SPREAD ? sync[jix].prog : l_prog;
+  int32_t *s_done = SPREAD ? sync[jix].done : l_done;
+  const TbWaveJob jb = jobs[jix];
   const int64_t p = jb.pair, m = jb.m, w = jb.w;
   const int n = a.n;
   const int32_t o = a.o, e = a.e;
   const int64_t nstrips = (m + SH - 1) / SH;
   uint8_t *dir = dirw + jb.dir_off;
   for (int k = threadIdx.x; k < n * n; k += blockDim.x) s_mat[k] = a.matrix[k];
-  for (int k = threadIdx.x; k < nstrips && k < kTbMaxStrips; k += blockDim.x) {
-    s_prog[k] = 0;
-    s_done[k] = 0;
+  if constexpr (!SPREAD) {   // spread jobs: set by intra_sync_init before the launch
+    for (int k = threadIdx.x; k < nstrips && k < kTbMaxStrips; k += blockDim.x) {
+      s_prog[k] = 0;
+      s_done[k] = 0;
+    }
   }
   const int8_t *q = a.qcat + a.qstart[p] + a.qbeg[p];
   const int8_t *r = a.rcat + a.rstart[p] + a.rbeg[p];
   // hand-over rows: row 0 is the virtual top row H(0,0) = 0,
   // H(0,j) = -(o + (j-1)e), F(0,j) = -inf; row s + 1 is strip s's last row
   int32_t *bnd0 = bndbuf + jb.bnd_off;
-  for (int64_t j = threadIdx.x; j <= w; j += blockDim.x) {
-    bnd0[j] = (j == 0) ? 0 : -(o + (int32_t)(j - 1) * e);
-    bnd0[(w + 1) + j] = kNeg;
+  if (seg == 0) {   // strip 0 (segment 0, wave 0) reads it after the barrier below
+    for (int64_t j = threadIdx.x; j <= w; j += blockDim.x) {
+      bnd0[j] = (j == 0) ? 0 : -(o + (int32_t)(j - 1) * e);
+      bnd0[(w + 1) + j] = kNeg;
+    }
   }
   __threadfence_block();
   __syncthreads();
@@ -1018,7 +1045,7 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
     return off;
   };
 
-  for (int64_t s = wave; s < nstrips; s += NW) {
+  for (int64_t s = seg * NW + wave; s < nstrips; s += (int64_t)G * NW) {
     int64_t clo, chi, plo = 0, phi = w + 1;
     tbw_window(s, SH, jb.dlo, jb.bw, w, &clo, &chi);
     if (s > 0) tbw_window(s - 1, SH, jb.dlo, jb.bw, w, &plo, &phi);
@@ -1029,10 +1056,11 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
     const bool hand_over = (s + 1 < nstrips);
     uint8_t *dstrip = dir + strip_base(s);
     auto publish = [&](int32_t ncols, bool fin) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if constexpr (SPREAD) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       if (lane == 0) {
-        __hip_atomic_store(&s_prog[s], ncols, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (fin) __hip_atomic_store(&s_done[s], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_store(&s_prog[s], ncols, __ATOMIC_RELAXED, SCOPE);
+        if (fin) __hip_atomic_store(&s_done[s], 1, __ATOMIC_RELAXED, SCOPE);
       }
     };
     int32_t avail = (s == 0) ? (int32_t)(w + 1) : 0;
@@ -1040,13 +1068,14 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
       if (s == 0) return;
       int64_t spins = 0;
       for (;;) {
-        const int32_t done = __hip_atomic_load(&s_done[s - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        avail = __hip_atomic_load(&s_prog[s - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int32_t done = __hip_atomic_load(&s_done[s - 1], __ATOMIC_RELAXED, SCOPE);
+        avail = __hip_atomic_load(&s_prog[s - 1], __ATOMIC_RELAXED, SCOPE);
         if (done || avail >= need) break;
         if (++spins > kTbSpinLimit) { spin_fail = true; break; }
         __builtin_amdgcn_s_sleep(2);
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      if constexpr (SPREAD) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     };
     auto rd = [](const int32_t *ptr) {   // past the L1: another wave wrote it
       return __hip_atomic_load(ptr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1166,11 +1195,41 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
     }
     publish((int32_t)(chi - clo), true);
   }
-  // the walk reads every wave's codes: the barrier makes the workgroup's
-  // stores visible to it (they pass through this compute unit's caches)
-  __syncthreads();
-  if (wave != 0) return;
-  if (spin_fail) a.err[p] = 1;
+  if (spin_fail && lane == 0) a.err[p] = 1;   // reported as an internal failure
+  if constexpr (!SPREAD) {
+    // the walk reads every wave's codes: the barrier makes the workgroup's
+    // stores visible to it (they pass through this compute unit's caches)
+    __syncthreads();
+    if (wave == 0) tb_wave_walk<RL>(a, jb, dir, s_tile, lane);
+  }
+}
+
+// The walk of spread pairs, one wave per pair, after their fill kernel.
+template <int RL>
+__global__ __launch_bounds__(64) void k_tb_walk(TbArgs a, const TbWaveJob *jobs, uint8_t *dirw) {
+  __shared__ uint4 s_tile[kTbTileBytes / 16];
+  const TbWaveJob jb = jobs[blockIdx.x];
+  tb_wave_walk<RL>(a, jb, dirw + jb.dir_off, s_tile, (int)(threadIdx.x & 63));
+}
+
+template <int RL>
+__device__ void tb_wave_walk(const TbArgs &a, const TbWaveJob &jb, const uint8_t *dir,
+                             uint4 *s_tile, int lane) {
+  constexpr int64_t SH = 64 * RL;
+  constexpr int WB = RL / 2;
+  constexpr int TS = kTbTileBytes / (64 * WB);
+  const int64_t p = jb.pair, m = jb.m, w = jb.w;
+  const int32_t o = a.o, e = a.e;
+  const int64_t nstrips = (m + SH - 1) / SH;
+  auto strip_base = [&](int64_t s) {
+    int64_t off = 0;
+    for (int64_t k = 0; k < s; ++k) {
+      int64_t lo, hi;
+      tbw_window(k, SH, jb.dlo, jb.bw, w, &lo, &hi);
+      off += ((hi - lo) + 63) * 64 * WB;
+    }
+    return off;
+  };
 
   // ---- walk back from (m, w) in state H (rule T3), uniform on the wave ------
   // Each iteration places the walk in a strip and a tile of its codes and
@@ -1316,16 +1375,34 @@ int tb_wave_waves(int64_t m, int n, int RL) {
 
 int tb_wave_max_strips() { return kTbMaxStrips; }
 
-hipError_t tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, int RL, int waves,
-                   uint8_t *dirw, int32_t *bnd, hipStream_t st) {
-  if (njobs == 0) return hipSuccess;
-  if (waves < 1 || waves > kTbMaxWaves) return hipErrorInvalidValue;
+template <int RL>
+static void launch_tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, int waves,
+                           int segs, IntraSync *sync, uint8_t *dirw, int32_t *bnd, hipStream_t st) {
   const size_t lds = (size_t)(a.n + 1) * 64 * RL * waves;
-  const dim3 g((unsigned)njobs), b(64 * waves);
+  if (segs > 1) {
+    const dim3 g((unsigned)(8 * segs * ((njobs + 7) / 8)));
+    hipLaunchKernelGGL((k_tb_wave<RL, true>), g, dim3(64 * waves), lds, st, a, jobs, njobs, segs,
+                       sync, dirw, bnd);
+    hipLaunchKernelGGL(k_tb_walk<RL>, dim3((unsigned)njobs), dim3(64), 0, st, a, jobs, dirw);
+  } else {
+    hipLaunchKernelGGL((k_tb_wave<RL, false>), dim3((unsigned)njobs), dim3(64 * waves), lds, st, a,
+                       jobs, njobs, 1, sync, dirw, bnd);
+  }
+}
+
+hipError_t tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, int RL, int waves,
+                   int segs, IntraSync *sync, uint8_t *dirw, int32_t *bnd, hipStream_t st) {
+  if (njobs == 0) return hipSuccess;
+  if (waves < 1 || waves > kTbMaxWaves || segs < 1 || (segs > 1 && !sync))
+    return hipErrorInvalidValue;
+  if (segs > 1) {
+    const hipError_t e = intra_sync_init(sync, njobs, st);
+    if (e != hipSuccess) return e;
+  }
   switch (RL) {
-    case 4: hipLaunchKernelGGL(k_tb_wave<4>, g, b, lds, st, a, jobs, dirw, bnd); break;
-    case 8: hipLaunchKernelGGL(k_tb_wave<8>, g, b, lds, st, a, jobs, dirw, bnd); break;
-    case 16: hipLaunchKernelGGL(k_tb_wave<16>, g, b, lds, st, a, jobs, dirw, bnd); break;
+    case 4: launch_tb_wave<4>(a, jobs, njobs, waves, segs, sync, dirw, bnd, st); break;
+    case 8: launch_tb_wave<8>(a, jobs, njobs, waves, segs, sync, dirw, bnd, st); break;
+    case 16: launch_tb_wave<16>(a, jobs, njobs, waves, segs, sync, dirw, bnd, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
