@@ -425,7 +425,7 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
           const V cmin = T::from(word_of(cc, k));
 
           // rows: the part of each cell that does not depend on the F chain
-          // (diagonal + substitution, max with E) is computed one row ahead
+          // (diagonal + substitution) is computed one row ahead
           hdtop = hup;
           V cm = T::zero();
           V ho = T::zero();
@@ -435,12 +435,14 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
             else sraw = perm(X[r >> 2][1], X[r >> 2][0], T::sel_const(r & 3));
             return T::from(sraw);
           };
-          V u_next = T::max(T::add(hdiag_in, score_of(0)), E[0]);
+          V u_next = T::add(hdiag_in, score_of(0));
   #pragma unroll
           for (int r = 0; r < NR; ++r) {
             const V u = u_next;
-            if (r + 1 < NR) u_next = T::max(T::add(H[r], score_of(r + 1)), E[r + 1]);
-            const V hb = T::max(u, F);
+            if (r + 1 < NR) u_next = T::add(H[r], score_of(r + 1));
+            // every lane value stays below 0x7C00 unless the pair has passed
+            // the 11-bit value field (then it is flagged and re-run wider)
+            const V hb = T::max3(u, E[r], F);
             const V hn = T::subs(hb, vbias);
             H[r] = hn;
             const uint32_t code = code_top - (uint32_t)r;

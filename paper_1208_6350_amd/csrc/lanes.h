@@ -32,6 +32,18 @@ template <> struct VT<u16x2> {
   static __device__ __forceinline__ u16x2 min(u16x2 a, u16x2 b) {
     return __builtin_elementwise_min(a, b);
   }
+  // Largest of three, in one instruction: the packed f16 three-way maximum.
+  // On 16-bit patterns below 0x7C00 (finite non-negative halves; denormals
+  // are kept by the kernels' float mode) the f16 order is the unsigned
+  // integer order, so this is the exact unsigned maximum there.  Larger
+  // patterns read as infinities, NaNs or negatives and give no such
+  // guarantee: callers keep every lane value below 0x7C00, or only reach
+  // such values in pairs that are already flagged for a 32-bit re-run.
+  static __device__ __forceinline__ u16x2 max3(u16x2 a, u16x2 b, u16x2 c) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const h2 x = __builtin_bit_cast(h2, a), y = __builtin_bit_cast(h2, b), z = __builtin_bit_cast(h2, c);
+    return __builtin_bit_cast(u16x2, __builtin_elementwise_maximum(__builtin_elementwise_maximum(x, y), z));
+  }
   // value * 32 + code: the row code sits in the low 5 bits so that a max over
   // rows also yields, among rows of equal value, the one with the largest
   // code.  The value must fit the 11-bit field (the fill clamps it first when
@@ -64,6 +76,9 @@ template <> struct VT<uint32_t> {
   }
   static __device__ __forceinline__ uint32_t max(uint32_t a, uint32_t b) { return a > b ? a : b; }
   static __device__ __forceinline__ uint32_t min(uint32_t a, uint32_t b) { return a < b ? a : b; }
+  static __device__ __forceinline__ uint32_t max3(uint32_t a, uint32_t b, uint32_t c) {
+    return max(max(a, b), c);
+  }
   static __device__ __forceinline__ uint32_t enc_nosat(uint32_t h, uint32_t code, uint32_t) {
     return h * 32u + code;
   }
