@@ -514,6 +514,17 @@ int swx_last_stage_ms(const swx_ctx *ctx, double *ms, int cap);
  * blocks > 2^20 or bad gaps. */
 int swx_lane_probe(swx_ctx *ctx, int32_t bits, int64_t columns, int64_t blocks, int32_t gap_open,
                    int32_t gap_extend, uint32_t *best, double *ms);
+/* Check of the hardware fact the batched fill's 16-bit lanes rely on (method
+ * section: narrow saturating lanes): H, the largest of diagonal + score, E
+ * and F, is taken with one packed f16 three-way maximum, which equals the
+ * unsigned maximum only while every 16-bit pattern is below 0x7C00.  Runs
+ * that operation (the fill's own lane helper) on the device over every pair
+ * (a, b) below 0x7C00 with c from a fixed set of 8 values, in both halves,
+ * and over 2^31 pseudo-random triples; *mismatches (host) receives the
+ * number of results that differ from the unsigned maximum (0 expected) and
+ * *checked the number of results compared.  Errors: SWX_EINVAL for null
+ * arguments, SWX_EDEVICE on a device failure. */
+int swx_check_max3(swx_ctx *ctx, uint64_t *mismatches, uint64_t *checked);
 
 #ifdef __cplusplus
 }

@@ -162,6 +162,8 @@ _SIGS = {
     "swx_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxServerStats)]),
     "swx_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "swx_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SwxTuning)]),
+    "swx_check_max3": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64),
+                                      ctypes.POINTER(ctypes.c_uint64)]),
     "swx_lane_probe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                       ctypes.POINTER(ctypes.c_double)]),
@@ -421,6 +423,12 @@ class Context:
                                     ctypes.byref(ms)), "swx_lane_probe")
         cells = n * 16 * columns
         return best, ms.value, cells / (ms.value * 1e-3) / 1e9
+
+    def check_max3(self):
+        """swx_check_max3: (mismatches, results compared)."""
+        bad, n = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().swx_check_max3(self.handle, ctypes.byref(bad), ctypes.byref(n)), "swx_check_max3")
+        return bad.value, n.value
 
     def stage_ms(self):
         return swx_last_stage_ms(self.handle)

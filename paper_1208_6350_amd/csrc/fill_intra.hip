@@ -421,7 +421,9 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
 // row), built from the packed H with v_perm, so the max array has the same
 // layout as the 32-bit pass with kbits = 16.  Hand-over rows hold the 16-bit
 // values in 32-bit words, one row per job as in the 32-bit pass.
-template <int RL>
+// M3: every lane value of the launch stays below 0x7C00 (score bound plus
+// bias), so H is taken with one packed three-way maximum.
+template <int RL, bool M3>
 __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill16(IntraArgs a) {
   extern __shared__ uint4 s_dyn[];            // per wave and job: [(n + 1) symbols][64 lanes][RL bytes]
   __shared__ int8_t s_mat[32 * 32];
@@ -595,12 +597,17 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill16(IntraArgs a) {
 
       uint32_t cmA = 0u, cmB = 0u;
       auto score_of = [&](int r) -> V16 { return T::from(perm(XB[r >> 2], XA[r >> 2], T::sel_const(r & 3))); };
-      V16 u_next = T::max(T::add(hup_prev, score_of(0)), E[0]);
+      V16 u_next = M3 ? T::add(hup_prev, score_of(0)) : T::max(T::add(hup_prev, score_of(0)), E[0]);
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const V16 u = u_next;
-        if (r + 1 < RL) u_next = T::max(T::add(H[r], score_of(r + 1)), E[r + 1]);
-        const V16 hb = T::max(u, F);
+        if (r + 1 < RL) {
+          u_next = T::add(H[r], score_of(r + 1));
+          if constexpr (!M3) u_next = T::max(u_next, E[r + 1]);
+        }
+        V16 hb;
+        if constexpr (M3) hb = T::max3(u, E[r], F);
+        else hb = T::max(u, F);
         const V16 hn = T::subs(hb, vbias);
         H[r] = hn;
         const uint32_t kc = (uint32_t)(RL - 1 - r);
@@ -850,20 +857,21 @@ hipError_t intra_sync_init(IntraSync *sync, int64_t njobs, hipStream_t st) {
 }
 
 template <int RL>
-static void launch_rl16(const IntraArgs &a, int waves, hipStream_t st) {
+static void launch_rl16(const IntraArgs &a, int waves, bool m3, hipStream_t st) {
   const dim3 g((unsigned)(a.njobs / 2)), b(64 * waves);
   const size_t lds = intra_lds_bytes16(a.n, RL) * waves;
-  hipLaunchKernelGGL((k_intra_fill16<RL>), g, b, lds, st, a);
+  if (m3) hipLaunchKernelGGL((k_intra_fill16<RL, true>), g, b, lds, st, a);
+  else hipLaunchKernelGGL((k_intra_fill16<RL, false>), g, b, lds, st, a);
 }
 
-hipError_t intra_fill16(const IntraArgs &a, int RL, int waves, hipStream_t st) {
+hipError_t intra_fill16(const IntraArgs &a, int RL, int waves, bool m3, hipStream_t st) {
   if (a.njobs == 0) return hipSuccess;
   if (waves < 1 || waves > kMaxWaves || (a.njobs & 1)) return hipErrorInvalidValue;
   switch (RL) {
-    case 4: launch_rl16<4>(a, waves, st); break;
-    case 8: launch_rl16<8>(a, waves, st); break;
-    case 16: launch_rl16<16>(a, waves, st); break;
-    case 32: launch_rl16<32>(a, waves, st); break;
+    case 4: launch_rl16<4>(a, waves, m3, st); break;
+    case 8: launch_rl16<8>(a, waves, m3, st); break;
+    case 16: launch_rl16<16>(a, waves, m3, st); break;
+    case 32: launch_rl16<32>(a, waves, m3, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -128,7 +128,70 @@ __global__ __launch_bounds__(256) void k_lane_probe(int64_t cols, int32_t o, int
   for (int k = 0; k < PL; ++k) best[t * PL + k] = (cmax >> (BITS * k)) & ((1u << BITS) - 1u);
 }
 
+// Check of VT<u16x2>::max3 (the batched fill's packed three-way maximum)
+// against the unsigned maximum: block a tests every b below lim with c from a
+// fixed set, in both halves; the pseudo-random part draws triples from a
+// 64-bit mix (splitmix64's finaliser) of the thread index.
+__device__ __forceinline__ uint32_t max3_bits(uint32_t a, uint32_t b, uint32_t c) {
+  return VT<u16x2>::bits(VT<u16x2>::max3(VT<u16x2>::from(a), VT<u16x2>::from(b), VT<u16x2>::from(c)));
+}
+
+__device__ __forceinline__ uint32_t umax2(uint32_t a, uint32_t b) { return a > b ? a : b; }
+
+__device__ __forceinline__ uint64_t half_mismatches(uint32_t r, uint32_t lo_a, uint32_t lo_b,
+                                                    uint32_t lo_c, uint32_t hi_a, uint32_t hi_b,
+                                                    uint32_t hi_c) {
+  return (uint64_t)((r & 0xFFFFu) != umax2(umax2(lo_a, lo_b), lo_c)) +
+         (uint64_t)((r >> 16) != umax2(umax2(hi_a, hi_b), hi_c));
+}
+
+__global__ __launch_bounds__(256) void k_max3_pairs(uint32_t lim, unsigned long long *bad) {
+  const uint32_t a = blockIdx.x;
+  if (a >= lim) return;
+  const uint32_t cs[8] = {0u, 1u, 0x3FFu, 0x400u, 0x401u, 0x7FFu, 0x123u, lim - 1};
+  uint64_t nb = 0;
+  for (uint32_t b = threadIdx.x; b < lim; b += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t c = cs[k];
+      nb += half_mismatches(max3_bits(a | (b << 16), b | (c << 16), c | (a << 16)), a, b, c, b, c, a);
+    }
+  }
+  if (nb) atomicAdd(bad, (unsigned long long)nb);
+}
+
+__global__ __launch_bounds__(256) void k_max3_random(uint32_t lim, uint64_t n,
+                                                     unsigned long long *bad) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t x = i * 0x9E3779B97F4A7C15ull;
+  uint64_t nb = 0;
+  for (int it = 0; it < 16; ++it) {
+    x += 0x9E3779B97F4A7C15ull;
+    uint64_t z = x;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const uint32_t v0 = (uint32_t)(z % lim), v1 = (uint32_t)((z >> 15) % lim);
+    const uint32_t v2 = (uint32_t)((z >> 30) % lim), v3 = (uint32_t)((z >> 45) % lim);
+    const uint32_t v4 = (uint32_t)((z >> 7) & 63u), v5 = (uint32_t)((z >> 22) % 1100u);
+    nb += half_mismatches(max3_bits(v0 | (v3 << 16), v1 | (v4 << 16), v2 | (v5 << 16)), v0, v1, v2,
+                          v3, v4, v5);
+  }
+  if (nb) atomicAdd(bad, (unsigned long long)nb);
+}
+
 }  // namespace
+
+hipError_t max3_check(unsigned long long *bad, uint64_t *checked, hipStream_t st) {
+  constexpr uint32_t kLim = 0x7C00u;             // the finite non-negative f16 patterns
+  constexpr uint64_t kRandom = uint64_t(1) << 26;   // threads of the random part
+  hipLaunchKernelGGL(k_max3_pairs, dim3(kLim), dim3(256), 0, st, kLim, bad);
+  hipLaunchKernelGGL(k_max3_random, dim3((unsigned)(kRandom / 256)), dim3(256), 0, st, kLim,
+                     kRandom, bad);
+  *checked = (uint64_t)kLim * kLim * 16 + kRandom * 32;
+  return hipGetLastError();
+}
 
 hipError_t lane_probe(int bits, int64_t cols, int64_t blocks, int32_t o, int32_t e,
                       uint32_t *best, hipStream_t st) {

@@ -922,6 +922,10 @@ static bool intra_fits16(const Scoring &sc, int64_t Lq, int64_t Lr, int RL) {
   return bound + sc.bias <= 32766 && round_up(Lq, 64 * RL) <= 65536;
 }
 
+// Largest 16-bit lane value for which the packed f16 three-way maximum is the
+// unsigned maximum (0x7C00 and above are f16 infinities and NaNs).
+static constexpr int64_t kMax3Lane = 0x7BFF;
+
 // 16-bit waves per compute unit from which the automatic choice takes them.
 static constexpr int64_t kIntra16MinWavesPerCu = 4;
 
@@ -985,7 +989,8 @@ typedef std::map<std::pair<int, int64_t>, std::vector<IntraJob>> Jobs16;
 
 // Upload the 16-bit jobs (each key's list padded to an even count with an
 // empty job) and launch them, a pair of jobs per workgroup.
-static int launch_intra16_jobs(swx_ctx *ctx, const Jobs16 &jobs, IntraArgs a, const Scoring &sc) {
+static int launch_intra16_jobs(swx_ctx *ctx, const Jobs16 &jobs, IntraArgs a, const Scoring &sc,
+                               bool m3) {
   if (jobs.empty()) return SWX_OK;
   std::vector<IntraJob> all;
   std::vector<std::pair<int64_t, int64_t>> span;   // per key: first job, count
@@ -1008,7 +1013,7 @@ static int launch_intra16_jobs(swx_ctx *ctx, const Jobs16 &jobs, IntraArgs a, co
     const int RL = kv.first.first;
     a.jobs = dj + span[k].first;
     a.njobs = span[k].second;
-    HIP_TRY(intra_fill16(a, RL, intra_waves16(kv.first.second, sc.n, RL), ctx->stream));
+    HIP_TRY(intra_fill16(a, RL, intra_waves16(kv.first.second, sc.n, RL), m3, ctx->stream));
     ++k;
   }
   HIP_TRY(hipStreamSynchronize(ctx->stream));   // the host job table must outlive the copy
@@ -1092,6 +1097,7 @@ static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
   }
   IntraGroups groups;
   int64_t mc_words = 0, bnd_words = 0;
+  bool m3 = true;   // every 16-bit pair's lane values below 0x7C00
   for (int64_t k = 0; k < lp.nlong; ++k) {
     const int64_t p = lp.ids[k], Lq = lp.info[6 * k], Lr = lp.info[6 * k + 1];
     const bool w16 = is16[k];
@@ -1107,6 +1113,7 @@ static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
     if (kb > 30 || bound >= (int64_t(1) << (32 - kb)))
       return fail(SWX_EOVERFLOW, "long pair: score range and query length exceed the max-array word");
     (w16 ? ids16 : ids32).push_back(p);
+    if (w16 && bound + sc.bias > kMax3Lane) m3 = false;
     IntraPair ip{p, mc_words, kb, (int32_t)SH};
     lp.pairs.push_back(ip);
     if (Lr > 0) {
@@ -1150,7 +1157,7 @@ static int run_intra_forward(swx_ctx *ctx, const Scoring &sc, LongPath &lp, cons
   if (!a.bnd) return fail(SWX_ENOMEM, "device pool exhausted (hand-over rows)");
   int rc;
   if ((rc = launch_intra_jobs(ctx, groups, a, bnd_words, false))) return rc;
-  if ((rc = launch_intra16_jobs(ctx, jobs16, a, sc))) return rc;
+  if ((rc = launch_intra16_jobs(ctx, jobs16, a, sc, m3))) return rc;
   // lane widths of the long pairs (diagnostic)
   for (int w = 0; w < 2; ++w) {
     const std::vector<int64_t> &ids = w ? ids32 : ids16;
@@ -2157,6 +2164,23 @@ int swx_lane_probe(swx_ctx *ctx, int32_t bits, int64_t columns, int64_t blocks, 
   float t = 0;
   HIP_TRY(hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[1]));
   *ms = t;
+  return SWX_OK;
+}
+
+int swx_check_max3(swx_ctx *ctx, uint64_t *mismatches, uint64_t *checked) {
+  if (!ctx || !mismatches || !checked) return fail(SWX_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(SWX_EDEVICE, "hipSetDevice failed");
+  ctx->arena.reset();
+  unsigned long long *d = ctx->arena.get<unsigned long long>(1);
+  if (!d) return fail(SWX_ENOMEM, "device pool exhausted (check)");
+  hipStream_t st = ctx->stream;
+  HIP_TRY(hipMemsetAsync(d, 0, sizeof(*d), st));
+  HIP_TRY(max3_check(d, checked, st));
+  unsigned long long h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *mismatches = h;
   return SWX_OK;
 }
 

@@ -190,6 +190,9 @@ hipError_t fill_u8(int64_t n, uint8_t *p, uint8_t v, hipStream_t st);
 hipError_t fill_i64(int64_t n, int64_t *p, int64_t v, hipStream_t st);
 // lane-width probe: blocks x 256 threads, each 32/bits synthetic pairs of 16
 // rows x cols columns; best[pair] = the pair's best score
+// adds to *bad the results of VT<u16x2>::max3 that differ from the unsigned
+// maximum over the check's operand set; *checked: the number of lane results
+hipError_t max3_check(unsigned long long *bad, uint64_t *checked, hipStream_t st);
 hipError_t lane_probe(int bits, int64_t cols, int64_t blocks, int32_t o, int32_t e, uint32_t *best,
                       hipStream_t st);
 hipError_t class_ranges(const int64_t *counts, int64_t *ranges, hipStream_t st);
@@ -234,7 +237,9 @@ hipError_t intra_fill(const IntraArgs &a, int RL, int waves, bool rev, hipStream
 hipError_t intra_sync_init(IntraSync *sync, int64_t njobs, hipStream_t st);
 // forward pass on packed 16-bit lanes: jobs[2b] and jobs[2b + 1] (same padded
 // height; pair -1: none) share workgroup b; a.njobs even
-hipError_t intra_fill16(const IntraArgs &a, int RL, int waves, hipStream_t st);
+// m3: every pair's score bound plus bias is below 0x7C00 (one packed
+// three-way maximum per row instead of two maxima)
+hipError_t intra_fill16(const IntraArgs &a, int RL, int waves, bool m3, hipStream_t st);
 size_t intra_lds_bytes16(int n, int RL);
 int intra_max_strips();
 int intra_max_waves();

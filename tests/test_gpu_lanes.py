@@ -50,3 +50,17 @@ def test_probe_rejects_bad_widths():
                 ctx.lane_probe(bits, columns=8, blocks=1)
     finally:
         ctx.close()
+
+
+def test_packed_max3_is_exact_below_0x7c00():
+    """The batched fill takes H as one packed f16 three-way maximum; on every
+    16-bit pattern below 0x7C00 it must equal the unsigned maximum (checked on
+    the device over every pair of such values with 8 third operands, and
+    2^31 pseudo-random triples)."""
+    ctx = swx.Context(0)
+    try:
+        bad, n = ctx.check_max3()
+    finally:
+        ctx.close()
+    assert n == 0x7C00 * 0x7C00 * 16 + (1 << 26) * 32
+    assert bad == 0
