@@ -47,6 +47,29 @@ __device__ __forceinline__ uint32_t push_code(uint32_t acc, int32_t diag, int32_
 __device__ __forceinline__ uint32_t code_src(uint32_t c) {
   return (c & kCodeNotM) ? ((c & kCodeF) ? 2u : 1u) : 0u;
 }
+// The walk's moves (rule T3) by state (0 H, 1 E, 2 F) and choice code:
+// nibble c of walk_moves(state) = next state << 2 | row up << 1 | column
+// left.  In H the code names H's source: the diagonal (M, up and left) or a
+// gap state; in E a D move left, staying in E while E extends; in F an I move
+// up, staying in F while F extends.
+constexpr uint64_t walk_moves(int state) {
+  uint64_t t = 0;
+  for (uint32_t c = 0; c < 16; ++c) {
+    uint32_t v;
+    if (state == 0) {
+      const uint32_t src = (c & kCodeNotM) ? ((c & kCodeF) ? 2u : 1u) : 0u;
+      v = src == 0 ? 3u : (src << 2);
+    } else if (state == 1) {
+      v = ((c & kCodeEExt) ? 1u : 0u) << 2 | 1u;
+    } else {
+      v = ((c & kCodeFExt) ? 2u : 0u) << 2 | 2u;
+    }
+    t |= (uint64_t)v << (4 * c);
+  }
+  return t;
+}
+constexpr uint64_t kMovesH = walk_moves(0), kMovesE = walk_moves(1), kMovesF = walk_moves(2);
+
 // row 0 of the global DP: reached from the left by one deletion run
 __device__ __forceinline__ uint32_t row0_code(int64_t j, int32_t o, int32_t e) {
   return (j == 0) ? 0u : (kCodeNotM | ((j == 1 || o <= e) ? 0u : kCodeEExt));
@@ -150,7 +173,7 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
   __shared__ int8_t s_mat[32 * 32];
   __shared__ uint32_t s_lut4[32];   // LUT4: scores of query symbol x against reference 0..3
   constexpr int kRunSlots = 16;     // CIGAR runs per thread kept in LDS during the walk
-  __shared__ uint32_t s_runs[kRunSlots * 256];
+  __shared__ uint32_t s_runs[(kRunSlots + 1) * 256];
   for (int k = threadIdx.x; k < a.n * a.n; k += blockDim.x) s_mat[k] = a.matrix[k];
   if (LUT4 && (int)threadIdx.x < a.n) {
     uint32_t l = 0;
@@ -332,8 +355,10 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
   int32_t nruns = 0;
   int32_t i = m32, j = w32;   // 32-bit walk state
   int state = 0;
-  uint32_t cur_op = 0xFF, cur_len = 0;
-  bool walking = true, bad = false, full = false;
+  uint32_t cur_op = 3, cur_len = 0;   // 3: no run yet
+  // flags as 0/1 integers: lane booleans that live across the walk loop
+  // would be kept as lane masks, merged with scalar instructions per move
+  uint32_t walking = 1, bad = 0, full = 0;
   uint32_t pend = 0;
   // (a masked OR rather than a select chain, which the compiler would turn
   // into an indexed load from a private copy of the ring)
@@ -380,32 +405,39 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
 #pragma unroll
     for (int u = 0; u < kWP; ++u) {   // no early exit: every step issues the same loads
       const int32_t row = m32 - (t0 + u);
-      // the moves inside this row: D moves, then one M or I out of it
+      // the moves inside this row: D moves, then one M or I out of it.  One
+      // move per iteration, in lane arithmetic rather than branches (the lanes
+      // of a wave sit in different states): the move comes from walk_moves, the
+      // run bookkeeping from 0/1 integers, and the finished run is stored
+      // unconditionally into the next free slot (slot kRunSlots takes the
+      // stores that end no run).
       for (int g = 0; g < 2 * BW + 4 && row >= 0 && walking; ++g) {
         const int32_t k = j - i - dlo32;
-        if (k < 0 || k >= BW || i != row) { bad = true; walking = false; break; }
-        bool up;
-        const uint32_t op = move(code_at(ring[u], k), up);
-        if (op != 0xFF) {
-          if (op == cur_op) ++cur_len;
-          else {
-            if (cur_len) {
-              const uint32_t run = (cur_len << 4) | cur_op;
-              if (nruns == kRunSlots) {   // no slot left: finish on the plain walk
-                pend = run;
-                full = true;
-                walking = false;
-              } else {
-                s_runs[nruns * 256 + threadIdx.x] = run;
-                ++nruns;
-              }
-            }
-            cur_op = op;
-            cur_len = 1;
-          }
-        }
-        if ((i == 0 && j == 0) || full) { walking = false; break; }
-        if (up) break;
+        const uint32_t ok = (uint32_t)(((k | (BW - 1 - k)) >= 0) & (i == row));
+        const uint32_t c = code_at(ring[u], k);   // k out of range matches no word
+        const uint64_t moves = state == 0 ? kMovesH : (state == 1 ? kMovesE : kMovesF);
+        const uint32_t r = (uint32_t)(moves >> (4 * c)) & 15u;
+        const uint32_t step = (r & 3u) * ok;          // 2 * (row up) + (column left)
+        const uint32_t op = 3u - step;                // M 0, I 1, D 2; 3: no move
+        const uint32_t moved = step != 0u;
+        const uint32_t same = op == cur_op;
+        const uint32_t ends = moved & (same ^ 1u) & (cur_len != 0u);
+        const uint32_t run = (cur_len << 4) | cur_op;
+        s_runs[nruns * 256 + threadIdx.x] = run;
+        const uint32_t room = nruns < kRunSlots;
+        nruns += ends & room;
+        const uint32_t spill = ends & (room ^ 1u);   // no slot left: finish on the plain walk
+        pend = spill ? run : pend;
+        full |= spill;
+        cur_len = moved ? (same ? cur_len + 1 : 1u) : cur_len;
+        cur_op = moved ? op : cur_op;
+        i -= (int32_t)(step >> 1);
+        j -= (int32_t)(step & 1u);
+        state = ok ? (int)(r >> 2) : state;
+        bad |= ok ^ 1u;
+        const uint32_t stop = (ok ^ 1u) | (uint32_t)((i | j) == 0) | full;
+        walking &= stop ^ 1u;
+        if (stop | (step >> 1)) break;   // the move went up a row
       }
       load_row(row - kWP, ring[u]);   // the slot is free again: kWP rows up
     }
