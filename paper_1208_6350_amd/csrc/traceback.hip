@@ -865,7 +865,7 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
   // (32-bit walk state: a strip task spans well under 2^31 code dwords)
   int32_t i = (int32_t)m, j = (int32_t)w;
   int state = 0;
-  uint32_t cur_op = 0xFF, cur_len = 0;
+  uint32_t cur_op = 3, cur_len = 0;   // 3: no run yet
   int64_t guard = 2 * (m + w) + 4;
   uint32_t *cache = s_walk + ((threadIdx.x >> 6) * 64 + slot * LP) * kCU;   // [g][kCU]
   int32_t cache_s = -1, cache_j = -1;
@@ -930,22 +930,14 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
       const uint32_t dwv = cache[gk * kCU + (top2 - (t >> 1))];
       c = (dwv >> (16 * (t & 1) + 4 * (RL - 1 - k % RL))) & 0xFu;
     }
-    uint32_t op = 0xFF;
-    if (state == 0) {
-      const uint32_t src = code_src(c);
-      if (src == 0 && i > 0 && j > 0) { op = 0; --i; --j; }
-      else if (src == 1) state = 1;
-      else state = 2;
-    } else if (state == 1) {
-      op = 2;
-      state = (c & kCodeEExt) ? 1 : 0;
-      --j;
-    } else {
-      op = 1;
-      state = (c & kCodeFExt) ? 2 : 0;
-      --i;
-    }
-    if (op != 0xFF) {
+    // the move from the per-state table (M 0, I 1, D 2; 3: a change of state)
+    const uint64_t moves = state == 0 ? kMovesH : (state == 1 ? kMovesE : kMovesF);
+    const uint32_t r = (uint32_t)(moves >> (4 * c)) & 15u;
+    const uint32_t step = r & 3u, op = 3u - step;
+    i -= (int32_t)(step >> 1);
+    j -= (int32_t)(step & 1u);
+    state = (int)(r >> 2);
+    if (step) {
       if (op == cur_op) ++cur_len;
       else {
         if (cur_len && g == 0) out[nruns] = (cur_len << 4) | cur_op;
