@@ -300,83 +300,107 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
       if (hand_over) publish((int32_t)(col + 1 - clo), false);
     };
 
+    // Steps go in blocks of 64: the block's start reads the symbols and the
+    // row above for its 64 columns, its step 62 completes the output queues
+    // of 64 columns (flushed there from the second block on), and step 63
+    // takes its next symbol from the next block's lanes; so the steps in
+    // between carry no per-step tests beyond the reversed pass's target.
+    bool stop = false;
 #pragma unroll 1
-    for (int64_t t = 0; t < nsteps; ++t) {
-      const int tm = (int)(t & 63);
-      if (tm == 0) {
-        if (REV && t >= 63 &&
-            (unsigned long long)(clo + t - 63) >= __hip_atomic_load(s_best, __ATOMIC_RELAXED, SCOPE)) {
-          cdone = clo + t - 63;   // an earlier strip already reached the target at or before here
-          break;
-        }
-        if (t > 0) {
-          symbuf = symnext;
-          symnext = symbols(clo + t + 64);
-        }
-        // inputs of lane 0 for the next 64 steps
-        const int64_t cend = (clo + t + 64 < phi) ? clo + t + 64 : phi;
+    for (int64_t t0 = 0; t0 < nsteps; t0 += 64) {
+      if (REV && t0 >= 63 &&
+          (unsigned long long)(clo + t0 - 63) >= __hip_atomic_load(s_best, __ATOMIC_RELAXED, SCOPE)) {
+        cdone = clo + t0 - 63;   // an earlier strip already reached the target at or before here
+        break;
+      }
+      if (t0 > 0) {
+        symbuf = symnext;
+        symnext = symbols(clo + t0 + 64);
+      }
+      {   // inputs of lane 0 for the next 64 steps
+        const int64_t cend = (clo + t0 + 64 < phi) ? clo + t0 + 64 : phi;
         if (s > 0 && cend > plo) wait_for((int32_t)(cend - plo));
-        const int64_t c = clo + t + lane;
+        const int64_t c = clo + t0 + lane;
         const bool prev = c < chi && s > 0 && c >= plo && c < plo + avail && c < phi;
         // read past the CU's L1 (another wave wrote them)
         hbuf = prev ? __hip_atomic_load(&inH[c - jb.cw], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
         fbuf = prev ? __hip_atomic_load(&inF[c - jb.cw], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
       }
-      const uint32_t hup = from_above(hout, lane_value(hbuf, tm));
-      uint32_t F = from_above(fout, lane_value(fbuf, tm));
-      const uint32_t cmin = from_above(cmout, 0u);
-      // next step's symbol and profile row
-      const uint32_t symn = from_above(sym, lane_value(tm == 63 ? symnext : symbuf, (tm + 1) & 63));
-      uint32_t Xn[RL / 4];
-      lds_load_words<RL>(s_prof + ((int64_t)symn * 64 + lane) * RL, Xn);
+      // step t0 + tm; the next step's symbol is lane `nl` of `nsym`.  Returns
+      // true when the reversed pass has reached its target (outputs flushed).
+      auto step = [&](int tm, uint32_t nsym, int nl) -> bool {
+        const uint32_t hup = from_above(hout, lane_value(hbuf, tm));
+        uint32_t F = from_above(fout, lane_value(fbuf, tm));
+        const uint32_t cmin = from_above(cmout, 0u);
+        // next step's symbol and profile row
+        const uint32_t symn = from_above(sym, lane_value(nsym, nl));
+        uint32_t Xn[RL / 4];
+        lds_load_words<RL>(s_prof + ((int64_t)symn * 64 + lane) * RL, Xn);
 
-      uint32_t cm = 0u;
-      uint32_t u_next = T::max(hup_prev + __builtin_amdgcn_ubfe(X[0], 0, 8), E[0]);
+        uint32_t cm = 0u;
+        uint32_t u_next = T::max(hup_prev + __builtin_amdgcn_ubfe(X[0], 0, 8), E[0]);
 #pragma unroll
-      for (int r = 0; r < RL; ++r) {
-        const uint32_t u = u_next;
-        if (r + 1 < RL)
-          u_next = T::max(H[r] + __builtin_amdgcn_ubfe(X[(r + 1) >> 2], 8 * ((r + 1) & 3), 8), E[r + 1]);
-        const uint32_t hb = T::max(u, F);
-        const uint32_t hn = T::subs(hb, vbias);
-        H[r] = hn;
-        const uint32_t enc = (hn << kb) + (uint32_t)(RL - 1 - r);
-        cm = cm > enc ? cm : enc;
-        const uint32_t ho = T::subs(hb, vo);
-        E[r] = T::max(T::subs(E[r], ve), ho);
-        F = T::max(T::subs(F, ve), ho);
-      }
-      hup_prev = hup;
-      hout = H[RL - 1];
-      fout = F;
-      const uint32_t cml = cm + DL;
-      cmout = cmin > cml ? cmin : cml;
-      sym = symn;
+        for (int r = 0; r < RL; ++r) {
+          const uint32_t u = u_next;
+          if (r + 1 < RL)
+            u_next = T::max(H[r] + __builtin_amdgcn_ubfe(X[(r + 1) >> 2], 8 * ((r + 1) & 3), 8), E[r + 1]);
+          const uint32_t hb = T::max(u, F);
+          const uint32_t hn = T::subs(hb, vbias);
+          H[r] = hn;
+          const uint32_t enc = (hn << kb) + (uint32_t)(RL - 1 - r);
+          cm = cm > enc ? cm : enc;
+          const uint32_t ho = T::subs(hb, vo);
+          E[r] = T::max(T::subs(E[r], ve), ho);
+          F = T::max(T::subs(F, ve), ho);
+        }
+        hup_prev = hup;
+        hout = H[RL - 1];
+        fout = F;
+        const uint32_t cml = cm + DL;
+        cmout = cmin > cml ? cmin : cml;
+        sym = symn;
 #pragma unroll
-      for (int k = 0; k < RL / 4; ++k) X[k] = Xn[k];
+        for (int k = 0; k < RL / 4; ++k) X[k] = Xn[k];
 
-      // lane 63's outputs enter at lane 63 while the collected ones move one
-      // lane down: after 64 steps lane k holds the k-th column of the chunk
-      obH = shift_in(obH, hout);
-      obF = shift_in(obF, fout);
-      obC = shift_in(obC, cmout);
-      if (t >= 63) {
-        const int j = (int)((t - 63) & 63);
-        const int64_t col = clo + t - 63;
-        if (REV) {
-          const uint32_t oc = lane_value(cmout, 63);
-          if (tgt > 0 && (int32_t)(oc >> kb) >= tgt) {
-            flush(col, j);
-            cdone = col + 1;
-            if (lane == 0) {
-              s_rcol[s] = col;
-              s_rrow[s] = (int32_t)(M - (oc & M));
-              atomicMin(s_best, (unsigned long long)col);
+        // lane 63's outputs enter at lane 63 while the collected ones move one
+        // lane down: after 64 steps lane k holds the k-th column of the chunk
+        obH = shift_in(obH, hout);
+        obF = shift_in(obF, fout);
+        obC = shift_in(obC, cmout);
+        if constexpr (REV) {
+          const int64_t t = t0 + tm;
+          if (t >= 63) {
+            const uint32_t oc = lane_value(cmout, 63);
+            if (tgt > 0 && (int32_t)(oc >> kb) >= tgt) {
+              const int64_t col = clo + t - 63;
+              flush(col, (int)((t - 63) & 63));
+              cdone = col + 1;
+              if (lane == 0) {
+                s_rcol[s] = col;
+                s_rrow[s] = (int32_t)(M - (oc & M));
+                atomicMin(s_best, (unsigned long long)col);
+              }
+              return true;
             }
-            break;
           }
         }
-        if (j == 63 || t == nsteps - 1) flush(col, j);
+        return false;
+      };
+      const int tn = (int)(nsteps - t0 < 64 ? nsteps - t0 : 64);
+      const int ta = tn < 62 ? tn : 62;
+#pragma unroll 1
+      for (int tm = 0; tm < ta; ++tm)
+        if (step(tm, symbuf, tm + 1)) { stop = true; break; }
+      if (stop) break;
+      if (tn > 62) {
+        if (step(62, symbuf, 63)) break;
+        if (t0 >= 64) flush(clo + t0 - 1, 63);   // step t0 + 62 ends columns ..t0 - 1 + clo
+      }
+      if (tn > 63 && step(63, symnext, 0)) break;
+      if (t0 + tn == nsteps) {   // the strip's last step: the rest of its outputs
+        const int64_t t = nsteps - 1;
+        const int j = (int)((t - 63) & 63);
+        if (t >= 63 && j != 63) flush(clo + t - 63, j);
       }
     }
     publish((int32_t)(cdone - clo), true);
