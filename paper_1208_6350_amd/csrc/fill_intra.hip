@@ -590,18 +590,17 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill16(IntraArgs a) {
       if (hand_over) publish((int32_t)(o + 1), false);
     };
 
+    // steps in blocks of 64, as in the 32-bit pass
 #pragma unroll 1
-    for (int64_t t = 0; t < nsteps; ++t) {
-      const int tm = (int)(t & 63);
-      if (tm == 0) {
-        if (t > 0) {
-          symbuf = symnext;
-          symnext = symbols(t + 64);
-        }
-        // inputs of lane 0 for the next 64 steps, both jobs
-        const int64_t cend = (t + 64 < width) ? t + 64 : width;
+    for (int64_t t0 = 0; t0 < nsteps; t0 += 64) {
+      if (t0 > 0) {
+        symbuf = symnext;
+        symnext = symbols(t0 + 64);
+      }
+      {   // inputs of lane 0 for the next 64 steps, both jobs
+        const int64_t cend = (t0 + 64 < width) ? t0 + 64 : width;
         if (s > 0 && cend > 0) wait_for((int32_t)cend);
-        const int64_t off = t + lane;
+        const int64_t off = t0 + lane;
         const bool inA = off < widthA, inB = hasB && off < widthB;
         const bool prev = s > 0 && off < avail;
         const uint32_t ha = (prev && inA) ? __hip_atomic_load(&iHA[off], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
@@ -611,54 +610,67 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill16(IntraArgs a) {
         hbuf = perm(hb, ha, 0x05040100u);   // A in the low half, B in the high half
         fbuf = perm(fb, fa, 0x05040100u);
       }
-      const V16 hup = T::from(from_above(T::bits(hout), lane_value(hbuf, tm)));
-      V16 F = T::from(from_above(T::bits(fout), lane_value(fbuf, tm)));
-      const uint32_t cminA = from_above(cmoutA, 0u), cminB = from_above(cmoutB, 0u);
-      const uint32_t symn = from_above(sym, lane_value(tm == 63 ? symnext : symbuf, (tm + 1) & 63));
-      uint32_t XnA[RL / 4], XnB[RL / 4];
-      lds_load_words<RL>(s_profA + ((int64_t)(symn & 0xFFu) * 64 + lane) * RL, XnA);
-      lds_load_words<RL>(s_profB + ((int64_t)((symn >> 8) & 0xFFu) * 64 + lane) * RL, XnB);
+      // step t0 + tm; the next step's symbols are lane `nl` of `nsym`
+      auto step = [&](int tm, uint32_t nsym, int nl) {
+        const V16 hup = T::from(from_above(T::bits(hout), lane_value(hbuf, tm)));
+        V16 F = T::from(from_above(T::bits(fout), lane_value(fbuf, tm)));
+        const uint32_t cminA = from_above(cmoutA, 0u), cminB = from_above(cmoutB, 0u);
+        const uint32_t symn = from_above(sym, lane_value(nsym, nl));
+        uint32_t XnA[RL / 4], XnB[RL / 4];
+        lds_load_words<RL>(s_profA + ((int64_t)(symn & 0xFFu) * 64 + lane) * RL, XnA);
+        lds_load_words<RL>(s_profB + ((int64_t)((symn >> 8) & 0xFFu) * 64 + lane) * RL, XnB);
 
-      uint32_t cmA = 0u, cmB = 0u;
-      auto score_of = [&](int r) -> V16 { return T::from(perm(XB[r >> 2], XA[r >> 2], T::sel_const(r & 3))); };
-      V16 u_next = M3 ? T::add(hup_prev, score_of(0)) : T::max(T::add(hup_prev, score_of(0)), E[0]);
+        uint32_t cmA = 0u, cmB = 0u;
+        auto score_of = [&](int r) -> V16 { return T::from(perm(XB[r >> 2], XA[r >> 2], T::sel_const(r & 3))); };
+        V16 u_next = M3 ? T::add(hup_prev, score_of(0)) : T::max(T::add(hup_prev, score_of(0)), E[0]);
 #pragma unroll
-      for (int r = 0; r < RL; ++r) {
-        const V16 u = u_next;
-        if (r + 1 < RL) {
-          u_next = T::add(H[r], score_of(r + 1));
-          if constexpr (!M3) u_next = T::max(u_next, E[r + 1]);
+        for (int r = 0; r < RL; ++r) {
+          const V16 u = u_next;
+          if (r + 1 < RL) {
+            u_next = T::add(H[r], score_of(r + 1));
+            if constexpr (!M3) u_next = T::max(u_next, E[r + 1]);
+          }
+          V16 hb;
+          if constexpr (M3) hb = T::max3(u, E[r], F);
+          else hb = T::max(u, F);
+          const V16 hn = T::subs(hb, vbias);
+          H[r] = hn;
+          const uint32_t kc = (uint32_t)(RL - 1 - r);
+          const uint32_t wa = perm(T::bits(hn), kc, selA), wb = perm(T::bits(hn), kc, selB);
+          cmA = cmA > wa ? cmA : wa;
+          cmB = cmB > wb ? cmB : wb;
+          const V16 ho = T::subs(hb, vo);
+          E[r] = T::max(T::subs(E[r], ve), ho);
+          F = T::max(T::subs(F, ve), ho);
         }
-        V16 hb;
-        if constexpr (M3) hb = T::max3(u, E[r], F);
-        else hb = T::max(u, F);
-        const V16 hn = T::subs(hb, vbias);
-        H[r] = hn;
-        const uint32_t kc = (uint32_t)(RL - 1 - r);
-        const uint32_t wa = perm(T::bits(hn), kc, selA), wb = perm(T::bits(hn), kc, selB);
-        cmA = cmA > wa ? cmA : wa;
-        cmB = cmB > wb ? cmB : wb;
-        const V16 ho = T::subs(hb, vo);
-        E[r] = T::max(T::subs(E[r], ve), ho);
-        F = T::max(T::subs(F, ve), ho);
-      }
-      hup_prev = hup;
-      hout = H[RL - 1];
-      fout = F;
-      const uint32_t cmlA = cmA + DL, cmlB = cmB + DL;
-      cmoutA = cminA > cmlA ? cminA : cmlA;
-      cmoutB = cminB > cmlB ? cminB : cmlB;
-      sym = symn;
+        hup_prev = hup;
+        hout = H[RL - 1];
+        fout = F;
+        const uint32_t cmlA = cmA + DL, cmlB = cmB + DL;
+        cmoutA = cminA > cmlA ? cminA : cmlA;
+        cmoutB = cminB > cmlB ? cminB : cmlB;
+        sym = symn;
 #pragma unroll
-      for (int k = 0; k < RL / 4; ++k) { XA[k] = XnA[k]; XB[k] = XnB[k]; }
+        for (int k = 0; k < RL / 4; ++k) { XA[k] = XnA[k]; XB[k] = XnB[k]; }
 
-      obH = shift_in(obH, T::bits(hout));
-      obF = shift_in(obF, T::bits(fout));
-      obCA = shift_in(obCA, cmoutA);
-      obCB = shift_in(obCB, cmoutB);
-      if (t >= 63) {
+        obH = shift_in(obH, T::bits(hout));
+        obF = shift_in(obF, T::bits(fout));
+        obCA = shift_in(obCA, cmoutA);
+        obCB = shift_in(obCB, cmoutB);
+      };
+      const int tn = (int)(nsteps - t0 < 64 ? nsteps - t0 : 64);
+      const int ta = tn < 62 ? tn : 62;
+#pragma unroll 1
+      for (int tm = 0; tm < ta; ++tm) step(tm, symbuf, tm + 1);
+      if (tn > 62) {
+        step(62, symbuf, 63);
+        if (t0 >= 64) flush(t0 - 1, 63);   // step t0 + 62 ends offsets ..t0 - 1
+      }
+      if (tn > 63) step(63, symnext, 0);
+      if (t0 + tn == nsteps) {   // the last step: the rest of the outputs
+        const int64_t t = nsteps - 1;
         const int j = (int)((t - 63) & 63);
-        if (j == 63 || t == nsteps - 1) flush(t - 63, j);
+        if (t >= 63 && j != 63) flush(t - 63, j);
       }
     }
     publish((int32_t)width, true);

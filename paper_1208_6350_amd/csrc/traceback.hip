@@ -1151,70 +1151,92 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
     uint32_t sym = (uint32_t)tb_from_above(n, __builtin_amdgcn_readlane(symbuf, 0));
     uint32_t X[RL / 4];
     tb_prof_load<RL>(s_prof + ((int64_t)sym * 64 + lane) * RL, X);
+    // Steps in blocks of 64: the block's start reads the symbols and the row
+    // above for its 64 columns; step t gathers lane 63's H and F of column
+    // clo + t - 63 into lane (t - 63) mod 64 (from step 63 on), and step 62
+    // of every block after the first completes 64 such columns.
 #pragma unroll 1
-    for (int64_t t = 0; t < nsteps; ++t) {
-      const int tm = (int)(t & 63);
-      if (tm == 0) {
-        if (t > 0) {
-          symbuf = symnext;
-          symnext = symbols(clo + t + 64);
-        }
-        const int64_t cend = (clo + t + 64 < phi) ? clo + t + 64 : phi;
+    for (int64_t t0 = 0; t0 < nsteps; t0 += 64) {
+      if (t0 > 0) {
+        symbuf = symnext;
+        symnext = symbols(clo + t0 + 64);
+      }
+      {
+        const int64_t cend = (clo + t0 + 64 < phi) ? clo + t0 + 64 : phi;
         if (cend > plo) wait_for((int32_t)(cend - plo));
-        const int64_t c = clo + t + lane;
+        const int64_t c = clo + t0 + lane;
         const bool prev = c < chi && c >= plo && c < phi && c < plo + avail;
         hbuf = prev ? rd(&inH[c]) : kNeg;
         fbuf = prev ? rd(&inF[c]) : kNeg;
       }
-      const int32_t hup = tb_from_above(hout, __builtin_amdgcn_readlane(hbuf, tm));
-      int32_t fup = tb_from_above(fout, __builtin_amdgcn_readlane(fbuf, tm));
-      const uint32_t symn = (uint32_t)tb_from_above(
-          (int32_t)sym, __builtin_amdgcn_readlane(tm == 63 ? symnext : symbuf, (tm + 1) & 63));
-      uint32_t Xn[RL / 4];
-      tb_prof_load<RL>(s_prof + ((int64_t)symn * 64 + lane) * RL, Xn);
-      int32_t hdiag = hup_prev;
-      int32_t hcur = hup;
-      uint32_t dw[(RL + 7) / 8];
+      // step t0 + tm; the next step's symbol is lane `nl` of `nsym`; gather:
+      // the step has a column to hand over (t >= 63)
+      auto step = [&](int tm, int32_t nsym, int nl, bool gather) {
+        const int64_t t = t0 + tm;
+        const int32_t hup = tb_from_above(hout, __builtin_amdgcn_readlane(hbuf, tm));
+        int32_t fup = tb_from_above(fout, __builtin_amdgcn_readlane(fbuf, tm));
+        const uint32_t symn = (uint32_t)tb_from_above((int32_t)sym, __builtin_amdgcn_readlane(nsym, nl));
+        uint32_t Xn[RL / 4];
+        tb_prof_load<RL>(s_prof + ((int64_t)symn * 64 + lane) * RL, Xn);
+        int32_t hdiag = hup_prev;
+        int32_t hcur = hup;
+        uint32_t dw[(RL + 7) / 8];
 #pragma unroll
-      for (int k = 0; k < (RL + 7) / 8; ++k) dw[k] = 0u;
+        for (int k = 0; k < (RL + 7) / 8; ++k) dw[k] = 0u;
 #pragma unroll
-      for (int k = 0; k < RL; ++k) {
-        const int32_t sc = __builtin_amdgcn_sbfe((int32_t)X[k >> 2], 8 * (k & 3), 8);
-        const int32_t diag = hdiag + sc;
-        const int32_t fo = hcur - o, fx = fup - e;
-        const int32_t fij = fo > fx ? fo : fx;
-        const int32_t eo = H[k] - o, ex = E[k] - e;
-        const int32_t eij = eo > ex ? eo : ex;
-        int32_t h = diag > eij ? diag : eij;
-        h = h > fij ? h : fij;
-        // row k: nibble 7 - k % 8 of dword k / 8 (the first row on top)
-        dw[k >> 3] = push_code(dw[k >> 3], diag, h, eij, fij, eo, ex, fo, fx);
-        hdiag = H[k];
-        H[k] = h;
-        E[k] = eij;
-        hcur = h;
-        fup = fij;
-      }
-      hup_prev = hup;
-      hout = H[RL - 1];
-      fout = fup;
-      sym = symn;
-#pragma unroll
-      for (int k = 0; k < RL / 4; ++k) X[k] = Xn[k];
-      if constexpr (RL == 16) reinterpret_cast<uint2 *>(dstrip)[t * 64 + lane] = make_uint2(dw[0], dw[1]);
-      else if constexpr (RL == 8) reinterpret_cast<uint32_t *>(dstrip)[t * 64 + lane] = dw[0];
-      else reinterpret_cast<uint16_t *>(dstrip)[t * 64 + lane] = (uint16_t)dw[0];
-      if (hand_over && t >= 63) {
-        const int jj = (int)((t - 63) & 63);
-        const int32_t vh = __builtin_amdgcn_readlane(hout, 63);
-        const int32_t vf = __builtin_amdgcn_readlane(fout, 63);
-        obH = (lane == jj) ? vh : obH;
-        obF = (lane == jj) ? vf : obF;
-        if (jj == 63 || t == nsteps - 1) {
-          const int64_t cb = clo + (t - 63) - jj;
-          if (lane <= jj) { outH[cb + lane] = obH; outF[cb + lane] = obF; }
-          publish((int32_t)(cb + jj + 1 - clo), false);
+        for (int k = 0; k < RL; ++k) {
+          const int32_t sc = __builtin_amdgcn_sbfe((int32_t)X[k >> 2], 8 * (k & 3), 8);
+          const int32_t diag = hdiag + sc;
+          const int32_t fo = hcur - o, fx = fup - e;
+          const int32_t fij = fo > fx ? fo : fx;
+          const int32_t eo = H[k] - o, ex = E[k] - e;
+          const int32_t eij = eo > ex ? eo : ex;
+          int32_t h = diag > eij ? diag : eij;
+          h = h > fij ? h : fij;
+          // row k: nibble 7 - k % 8 of dword k / 8 (the first row on top)
+          dw[k >> 3] = push_code(dw[k >> 3], diag, h, eij, fij, eo, ex, fo, fx);
+          hdiag = H[k];
+          H[k] = h;
+          E[k] = eij;
+          hcur = h;
+          fup = fij;
         }
+        hup_prev = hup;
+        hout = H[RL - 1];
+        fout = fup;
+        sym = symn;
+#pragma unroll
+        for (int k = 0; k < RL / 4; ++k) X[k] = Xn[k];
+        if constexpr (RL == 16) reinterpret_cast<uint2 *>(dstrip)[t * 64 + lane] = make_uint2(dw[0], dw[1]);
+        else if constexpr (RL == 8) reinterpret_cast<uint32_t *>(dstrip)[t * 64 + lane] = dw[0];
+        else reinterpret_cast<uint16_t *>(dstrip)[t * 64 + lane] = (uint16_t)dw[0];
+        if (hand_over && gather) {
+          const int jj = (tm + 1) & 63;   // (t - 63) mod 64
+          const int32_t vh = __builtin_amdgcn_readlane(hout, 63);
+          const int32_t vf = __builtin_amdgcn_readlane(fout, 63);
+          obH = (lane == jj) ? vh : obH;
+          obF = (lane == jj) ? vf : obF;
+        }
+      };
+      // columns [cb, cb + jj] are complete: store and publish them
+      auto hand = [&](int64_t cb, int jj) {
+        if (lane <= jj) { outH[cb + lane] = obH; outF[cb + lane] = obF; }
+        publish((int32_t)(cb + jj + 1 - clo), false);
+      };
+      const bool later = t0 >= 64;
+      const int tn = (int)(nsteps - t0 < 64 ? nsteps - t0 : 64);
+      const int ta = tn < 62 ? tn : 62;
+#pragma unroll 1
+      for (int tm = 0; tm < ta; ++tm) step(tm, symbuf, tm + 1, later);
+      if (tn > 62) {
+        step(62, symbuf, 63, later);
+        if (hand_over && later) hand(clo + t0 - 64, 63);
+      }
+      if (tn > 63) step(63, symnext, 0, true);
+      if (hand_over && t0 + tn == nsteps) {   // the strip's last step
+        const int64_t t = nsteps - 1;
+        const int jj = (int)((t - 63) & 63);
+        if (t >= 63 && jj != 63) hand(clo + (t - 63) - jj, jj);
       }
     }
     publish((int32_t)(chi - clo), true);
