@@ -1598,6 +1598,13 @@ struct GraphState {
   void *tb_sort_tmp = nullptr;
   size_t tb_sort_bytes = 0;
   FixedTb tb[6];
+  // one-pair graphs: the pair's traceback on the wave kernel, its job planned
+  // on the device (instead of the class, sort and task kernels of a batch)
+  bool tbw1 = false;
+  int tbw_rl = 4, tbw_waves = 1;
+  TbWaveJob *tbw_job = nullptr;
+  uint8_t *tbw_dir = nullptr;
+  int32_t *tbw_bnd = nullptr;
   uint32_t *cscr = nullptr;
   // intra route: every pair spread over a wave (one job per pair)
   bool intra = false;
@@ -1799,6 +1806,10 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
     ta.wave_cells = INT64_MAX;   // no host-planned wave traceback in a graph
     ta.cig = g.cscr;
     ta.cig_off = g.coff;
+    if (g.tbw1) {
+      HIP_TRY(tb_wave_job1(ta, g.tbw_job, g.coff, st));
+      HIP_TRY(tb_wave(ta, g.tbw_job, 1, g.tbw_rl, g.tbw_waves, 1, nullptr, g.tbw_dir, g.tbw_bnd, st));
+    } else {
     HIP_TRY(fill_i64(1, g.ccap + B, 0, st));
     HIP_TRY(fill_i64(8, g.counts, 0, st));
     HIP_TRY(tb_classify(ta, B, g.cls, g.tk0, g.tv0, g.ccap, st));
@@ -1832,6 +1843,7 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
       tc.dir = t.dir;
       HIP_TRY(tb_strip(tc, tasks, t.cap_tasks, g.tb_sorted, t.bnd, st));
     }
+    }
     HIP_TRY(fill_i64(1, g.len64 + B, 0, st));
     HIP_TRY(lens_to_i64(B, g.cig_len, g.len64, st));
     if ((rc = fixed_scan(g, g.len64, g.cig_off_final, B + 1, st))) return rc;
@@ -1862,6 +1874,9 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
   HIP_TRY(launch_any_flag(B, g.err, g.status, st));
   return SWX_OK;
 }
+
+// Code bytes up to which a one-pair graph traces its pair on the wave kernel.
+static constexpr int64_t kGraphWaveTbBytes = int64_t(64) << 20;
 
 static int graph_alloc(GraphState &g) {
   DevArena &A = g.A;
@@ -1976,6 +1991,22 @@ static int graph_alloc(GraphState &g) {
     t.bnd = A.get<int32_t>(capW * 2 * (g.RM + 1) * kTbwSlots);
     if (!t.tasks || !t.dsz || !t.doff || !t.bsz || !t.boff || !t.dir || !t.bnd)
       return fail(SWX_ENOMEM, "device pool exhausted (graph traceback)");
+  }
+  if (B == 1) {
+    // codes of at most QM rows over at most RM + 1 columns per strip
+    const int RL = 4;
+    const int64_t dbytes = tb_wave_dir_bytes(g.QM, g.RM, RL);
+    const int64_t nstrips = (g.QM + 64 * RL - 1) / (64 * RL);
+    if (dbytes <= kGraphWaveTbBytes && nstrips <= tb_wave_max_strips()) {
+      g.tbw_rl = RL;
+      g.tbw_waves = tb_wave_waves(g.QM, g.sc.n, RL);
+      g.tbw_job = A.get<TbWaveJob>(1);
+      g.tbw_dir = A.get<uint8_t>(dbytes);
+      g.tbw_bnd = A.get<int32_t>(2 * (g.RM + 1) * (nstrips + 1));
+      if (!g.tbw_job || !g.tbw_dir || !g.tbw_bnd)
+        return fail(SWX_ENOMEM, "device pool exhausted (graph wave traceback)");
+      g.tbw1 = true;
+    }
   }
   size_t sb = 0;
   HIP_TRY(sort_keys(B, g.tk0, g.tk1, g.tv0, g.tv1, nullptr, &sb, &g.tb_sorted, nullptr, kTbKeyBits));

@@ -180,6 +180,11 @@ hipError_t tbw_offsets(int64_t ntasks, TbwTask *tasks, const int64_t *doff, cons
                        hipStream_t st);
 hipError_t tb_strip(const TbArgs &a, const TbwTask *tasks, int64_t ntasks, const int64_t *sorted,
                     int32_t *bndbuf, hipStream_t st);
+// One-pair graphs: pair 0's wave job planned on the device (m = 0 when it has
+// no alignment; its CIGAR scratch offset cig_off[0] = 0), and an upper bound
+// of the code bytes of a pair of at most m rows and w columns
+hipError_t tb_wave_job1(const TbArgs &a, TbWaveJob *job, int64_t *cig_off, hipStream_t st);
+int64_t tb_wave_dir_bytes(int64_t m, int64_t w, int RL);
 // segs > 1: each pair's strips spread over that many workgroups (sync: one
 // record per pair), then a walk kernel; else the fill and the walk in one
 hipError_t tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, int RL, int waves,

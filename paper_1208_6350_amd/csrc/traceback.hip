@@ -55,7 +55,7 @@ __device__ __forceinline__ uint32_t code_src(uint32_t c) {
 constexpr uint64_t walk_moves(int state) {
   uint64_t t = 0;
   for (uint32_t c = 0; c < 16; ++c) {
-    uint32_t v;
+    uint32_t v = 0;
     if (state == 0) {
       const uint32_t src = (c & kCodeNotM) ? ((c & kCodeF) ? 2u : 1u) : 0u;
       v = src == 0 ? 3u : (src << 2);
@@ -1030,6 +1030,7 @@ __global__ __launch_bounds__(64 * kTbMaxWaves) void k_tb_wave(TbArgs a, const Tb
   int32_t *s_prog = SPREAD ? sync[jix].prog : l_prog;
   int32_t *s_done = SPREAD ? sync[jix].done : l_done;
   const TbWaveJob jb = jobs[jix];
+  if (jb.m <= 0) return;   // a job without an alignment (one-pair graphs plan it on the device)
   const int64_t p = jb.pair, m = jb.m, w = jb.w;
   const int n = a.n;
   const int32_t o = a.o, e = a.e;
@@ -1255,6 +1256,7 @@ template <int RL>
 __global__ __launch_bounds__(64) void k_tb_walk(TbArgs a, const TbWaveJob *jobs, uint8_t *dirw) {
   __shared__ uint4 s_tile[kTbTileBytes / 16];
   const TbWaveJob jb = jobs[blockIdx.x];
+  if (jb.m <= 0) return;
   tb_wave_walk<RL>(a, jb, dirw + jb.dir_off, s_tile, (int)(threadIdx.x & 63));
 }
 
@@ -1452,6 +1454,37 @@ hipError_t tb_wave(const TbArgs &a, const TbWaveJob *jobs, int64_t njobs, int RL
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// The wave job of pair 0 of a one-pair graph, planned on the device: the
+// rectangle and safe band of its alignment, codes and hand-over rows at the
+// start of their buffers (m = 0: no alignment, nothing to trace), and its
+// CIGAR scratch at offset 0.
+__global__ void k_tb_wave_job1(TbArgs a, TbWaveJob *job, int64_t *cig_off) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  TbWaveJob jb{};
+  jb.pair = 0;
+  if (a.score[0] > 0) {
+    if (tb_coords_ok(a, 0)) {
+      jb.m = a.qend[0] - a.qbeg[0] + 1;
+      jb.w = a.rend[0] - a.rbeg[0] + 1;
+      safe_band(jb.m, jb.w, a.score[0], a.smax, a.o, a.e, &jb.dlo, &jb.bw);
+    } else {
+      a.err[0] = 1;
+    }
+  }
+  *job = jb;
+  cig_off[0] = 0;
+}
+
+hipError_t tb_wave_job1(const TbArgs &a, TbWaveJob *job, int64_t *cig_off, hipStream_t st) {
+  hipLaunchKernelGGL(k_tb_wave_job1, dim3(1), dim3(64), 0, st, a, job, cig_off);
+  return hipGetLastError();
+}
+
+int64_t tb_wave_dir_bytes(int64_t m, int64_t w, int RL) {
+  const int64_t SH = 64 * RL, nstrips = (m + SH - 1) / SH;
+  return nstrips * (w + 1 + 63) * 64 * (RL / 2);
 }
 
 hipError_t tbw_tasks(int64_t n0, int64_t n1, const int64_t *sorted, const TbArgs &a,
