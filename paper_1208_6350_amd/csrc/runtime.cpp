@@ -1938,7 +1938,9 @@ static int graph_alloc(GraphState &g) {
     int64_t wcap = g.RM;
     if (g.sc.e > 0) {
       wcap = g.QM + std::max<int64_t>((int64_t)g.sc.smax * g.QM - g.sc.o, 0) / g.sc.e + 1;
-      const int64_t C = std::max<int64_t>(256, (wcap + 1) / 2);
+      // (a one-pair graph is latency-bound: its chunks only need to fill a
+      // few compute units, so it takes the most of them)
+      const int64_t C = B == 1 ? 128 : std::max<int64_t>(256, (wcap + 1) / 2);
       const int64_t nc = std::min<int64_t>(kGraphMaxChunks, (g.RM + C - 1) / C);
       if (nc > 1) {
         g.nc = (int32_t)nc;
