@@ -625,6 +625,52 @@ hipError_t launch_band_tb(const BandArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// the CIGAR of pair 0 of a one-pair call: its final offsets (0 and its
+// length) and its words, in one launch
+__global__ void k_cigar_one(const uint32_t *src, const int64_t *src_off, const int32_t *len,
+                            int64_t *dst_off, uint32_t *dst) {
+  const int32_t n = len[0];
+  if (threadIdx.x == 0) {
+    dst_off[0] = 0;
+    dst_off[1] = n;
+  }
+  const int64_t so = src_off[0];
+  for (int32_t k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[so + k];
+}
+
+hipError_t cigar_one(const uint32_t *src, const int64_t *src_off, const int32_t *len,
+                     int64_t *dst_off, uint32_t *dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_cigar_one, dim3(1), dim3(256), 0, st, src, src_off, len, dst_off, dst);
+  return hipGetLastError();
+}
+
+// Clears of many buffers in one launch (graph capture records no memset):
+// entry k sets f.n[k] elements of f.size[k] bytes at f.p[k] to f.v[k].
+__global__ void k_fill_set(FillSet f) {
+  const int64_t gs = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int k = 0; k < f.count; ++k) {
+    const int64_t n = f.n[k];
+    if (f.size[k] == 1) {
+      uint8_t *q = static_cast<uint8_t *>(f.p[k]);
+      for (int64_t i = gt; i < n; i += gs) q[i] = (uint8_t)f.v[k];
+    } else if (f.size[k] == 4) {
+      uint32_t *q = static_cast<uint32_t *>(f.p[k]);
+      for (int64_t i = gt; i < n; i += gs) q[i] = (uint32_t)f.v[k];
+    } else {
+      int64_t *q = static_cast<int64_t *>(f.p[k]);
+      for (int64_t i = gt; i < n; i += gs) q[i] = f.v[k];
+    }
+  }
+}
+
+hipError_t fill_set(const FillSet &f, hipStream_t st) {
+  if (f.count < 0 || f.count > kFillSetMax) return hipErrorInvalidValue;
+  if (f.count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_set, dim3(64), dim3(256), 0, st, f);
+  return hipGetLastError();
+}
+
 hipError_t launch_cigar_compact(int64_t npairs, const uint32_t *src, const int64_t *src_off,
                                 const int32_t *len, const int64_t *dst_off, uint32_t *dst,
                                 hipStream_t st) {

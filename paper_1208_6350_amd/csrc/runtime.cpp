@@ -1719,10 +1719,26 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
   const int64_t B = g.B;
   const uint32_t flags = g.cfg.flags & (SWX_CIGAR | SWX_SCORE2) ? (g.cfg.flags | SWX_BEGIN) : g.cfg.flags;
   int rc;
-  HIP_TRY(fill_u8(4, (uint8_t *)g.bad, 0, st));
-  HIP_TRY(fill_i64(1, g.status, 0, st));
-  HIP_TRY(fill_u8(B, g.err, 0, st));
-  HIP_TRY(fill_u8(B, g.lanebits, 16, st));
+  if (g.intra) {
+    // the intra route clears all its per-call buffers in one launch (the
+    // lanes are 32-bit throughout)
+    FillSet fs{};
+    fs.add(g.bad, 1, 4, 0);
+    fs.add(g.status, 1, 8, 0);
+    fs.add(g.err, B, 1, 0);
+    fs.add(g.lanebits, B, 1, 32);
+    fs.add(g.maxcol, B * g.RM, 4, 0);
+    fs.add(g.rsc, B, 4, 0);
+    fs.add(g.cig_len, B, 4, 0);
+    fs.add(g.cig_off_final, B + 1, 8, 0);
+    fs.add(g.len64 + B, 1, 8, 0);
+    HIP_TRY(fill_set(fs, st));
+  } else {
+    HIP_TRY(fill_u8(4, (uint8_t *)g.bad, 0, st));
+    HIP_TRY(fill_i64(1, g.status, 0, st));
+    HIP_TRY(fill_u8(B, g.err, 0, st));
+    HIP_TRY(fill_u8(B, g.lanebits, 16, st));
+  }
   ValidateArgs va{g.qcat, g.cfg.qcat_cap, g.qoff, g.cfg.nq_cap, g.rcat, g.cfg.rcat_cap, g.roff,
                   g.cfg.nr_cap, g.pair_q, g.pair_r, B, g.sc.n, g.bad};
   HIP_TRY(launch_validate(va, st));
@@ -1736,7 +1752,6 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
   FillOut fout{g.score, g.qend, g.rend, g.ovf, g.err};
   IntraArgs ia{};
   if (g.intra) {
-    HIP_TRY(fill_u8(4 * B * g.RM, (uint8_t *)g.maxcol, 0, st));
     HIP_TRY(intra_jobs_chunked(B, g.nc, g.chunk, g.qlen, g.rlen, g.sc.smax, g.sc.o, g.sc.e,
                                g.kbits, g.sh, g.RM, g.fbnd_stride, g.jobs, g.ipairs, st));
     ia.jobs = g.jobs; ia.njobs = B * g.nc; ia.view = fview; ia.matrix = g.sc.dmat;
@@ -1748,7 +1763,6 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
     e.score = g.score; e.qend = g.qend; e.rend = g.rend; e.overflow = g.ovf;
     e.part_v = g.part_v; e.part_j = g.part_j;
     HIP_TRY(intra_end(e, B, st));
-    HIP_TRY(fill_u8(B, g.lanebits, 32, st));
   } else if ((rc = fixed_fill(g, g.p16, nullptr, nullptr, g.qlen, g.rlen, nullptr, nullptr, fview, false,
                               nullptr, fout, st))) {
     return rc;
@@ -1766,7 +1780,7 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
                              g.rql, g.rrs, g.rrl, g.tgt, g.err, st));
     HIP_TRY(rev_prepare(B, g.score, g.qend, g.rend, g.lanebits, g.sc.smax, g.sc.o, g.sc.e, g.band,
                         g.band_q, g.f16, g.f32, st));
-    HIP_TRY(fill_u8(4 * B, (uint8_t *)g.rsc, 0, st));
+    if (!g.intra) HIP_TRY(fill_u8(4 * B, (uint8_t *)g.rsc, 0, st));
     PairView rview{g.rqs, g.rrs, g.rql, g.rrl, g.qcat, g.rcat, 1};
     FillOut rout{g.rsc, g.rqe, g.rre, g.rov, g.err};
     if (g.intra) {
@@ -1794,8 +1808,10 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
     }
     HIP_TRY(launch_begins(B, g.score, g.qend, g.rend, g.rsc, g.rqe, g.rre, g.qbeg, g.rbeg, g.err, st));
   }
-  HIP_TRY(fill_u8(4 * B, (uint8_t *)g.cig_len, 0, st));
-  HIP_TRY(fill_i64(B + 1, g.cig_off_final, 0, st));
+  if (!g.intra) {
+    HIP_TRY(fill_u8(4 * B, (uint8_t *)g.cig_len, 0, st));
+    HIP_TRY(fill_i64(B + 1, g.cig_off_final, 0, st));
+  }
   if (flags & SWX_CIGAR) {
     TbArgs ta{};
     ta.score = g.score; ta.qbeg = g.qbeg; ta.qend = g.qend; ta.rbeg = g.rbeg; ta.rend = g.rend;
@@ -1844,10 +1860,14 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
       HIP_TRY(tb_strip(tc, tasks, t.cap_tasks, g.tb_sorted, t.bnd, st));
     }
     }
-    HIP_TRY(fill_i64(1, g.len64 + B, 0, st));
-    HIP_TRY(lens_to_i64(B, g.cig_len, g.len64, st));
-    if ((rc = fixed_scan(g, g.len64, g.cig_off_final, B + 1, st))) return rc;
-    HIP_TRY(launch_cigar_compact(B, g.cscr, g.coff, g.cig_len, g.cig_off_final, g.cigar, st));
+    if (B == 1) {
+      HIP_TRY(cigar_one(g.cscr, g.coff, g.cig_len, g.cig_off_final, g.cigar, st));
+    } else {
+      if (!g.intra) HIP_TRY(fill_i64(1, g.len64 + B, 0, st));
+      HIP_TRY(lens_to_i64(B, g.cig_len, g.len64, st));
+      if ((rc = fixed_scan(g, g.len64, g.cig_off_final, B + 1, st))) return rc;
+      HIP_TRY(launch_cigar_compact(B, g.cscr, g.coff, g.cig_len, g.cig_off_final, g.cigar, st));
+    }
   }
   if ((flags & SWX_SCORE2) && g.intra) {
     IntraPairArgs e{};

@@ -301,6 +301,23 @@ hipError_t launch_band_sizes(int64_t npairs, const int32_t *score, const int32_t
                              int32_t smax, int32_t o, int32_t e, int64_t *dir_size,
                              int64_t *cig_cap, int64_t *row_cap, hipStream_t st);
 hipError_t launch_band_tb(const BandArgs &a, hipStream_t st);
+// one launch for many clears: entry k sets n[k] elements of size[k] bytes
+// (1, 4 or 8) at p[k] to v[k]
+constexpr int kFillSetMax = 12;
+struct FillSet {
+  void *p[kFillSetMax];
+  int64_t n[kFillSetMax];
+  int64_t v[kFillSetMax];
+  int32_t size[kFillSetMax];
+  int32_t count;
+  void add(void *ptr, int64_t count_, int32_t bytes, int64_t value) {
+    p[count] = ptr; n[count] = count_; size[count] = bytes; v[count] = value; ++count;
+  }
+};
+hipError_t fill_set(const FillSet &f, hipStream_t st);
+// pair 0's CIGAR words and final offsets {0, length} (one-pair calls)
+hipError_t cigar_one(const uint32_t *src, const int64_t *src_off, const int32_t *len,
+                     int64_t *dst_off, uint32_t *dst, hipStream_t st);
 hipError_t launch_cigar_compact(int64_t npairs, const uint32_t *src, const int64_t *src_off,
                                 const int32_t *len, const int64_t *dst_off, uint32_t *dst,
                                 hipStream_t st);
