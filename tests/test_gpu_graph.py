@@ -193,3 +193,45 @@ def test_graph_rejects_bad_contents(ctx):
         _check_oracle(a, recs, cig)
     finally:
         g.close()
+
+
+@pytest.mark.parametrize("route", ROUTES)
+def test_one_pair_graph_replays(ctx, route):
+    """A graph of capacity one (its traceback planned on the device for the
+    wave kernel): single pairs of every kind loaded and replayed in turn --
+    planted hits, random pairs, an empty reference, a one-symbol query -- each
+    equal to the oracle, and every replay equal to the graph's eager run."""
+    g0 = np.random.Generator(np.random.PCG64(917))
+    dna = W.dna_matrix()
+    cases = []
+    for k in range(10):
+        lq = int(g0.integers(1, 160))
+        lr = int(g0.integers(0, 500))
+        r = g0.integers(0, 4, lr).astype(np.int8)
+        q = g0.integers(0, 4, lq).astype(np.int8)
+        if k % 2 == 0 and lr >= lq:   # a planted copy with a few substitutions
+            p0 = int(g0.integers(0, lr - lq + 1))
+            q = r[p0:p0 + lq].copy()
+            flip = g0.random(lq) < 0.05
+            q[flip] = (q[flip] + 1) % 4
+        cases.append((q, r))
+    cases.append((np.array([2], np.int8), np.zeros(0, np.int8)))
+    cases.append((np.array([1], np.int8), np.array([1, 1, 3], np.int8)))
+    b = W.from_lists("one-pair-graph", dna, 3, 1, [c[0] for c in cases], [c[1] for c in cases])
+    g = swx.Graph(ctx, b.matrix, b.gap_open, b.gap_extend, max_pairs=1, max_qlen=160,
+                  max_rlen=512, qcat_cap=256, rcat_cap=640, nq_cap=2, nr_cap=3, route=route)
+    try:
+        for p in range(b.npairs):
+            pb = b.subset(np.array([p]))
+            g.load(pb.qcat, pb.qoff, pb.rcat, pb.roff, pb.pair_q, pb.pair_r)
+            g.run(eager=True)
+            recs_e, cig_e = g.read()
+            _check_oracle(pb, recs_e, cig_e)
+            for k in range(2):
+                g.run()
+                recs_g, cig_g = g.read()
+                assert recs_g.tobytes() == recs_e.tobytes(), (p, k)
+                assert np.array_equal(cig_g, cig_e), (p, k)
+        _say(f"[graph] one-pair route {route}: {b.npairs} pairs")
+    finally:
+        g.close()
