@@ -235,3 +235,33 @@ def test_one_pair_graph_replays(ctx, route):
         _say(f"[graph] one-pair route {route}: {b.npairs} pairs")
     finally:
         g.close()
+
+
+@pytest.mark.parametrize("route", ROUTES)
+def test_one_pair_graph_multi_strip(ctx, route):
+    """A one-pair graph whose pairs are taller than one strip of the wave
+    traceback (hand-over rows between strips inside the graph): planted
+    near-copies with indels and a random pair, equal to the oracle."""
+    g0 = np.random.Generator(np.random.PCG64(929))
+    qs, rs = [], []
+    for k in range(4):
+        r = g0.integers(0, 4, 1600).astype(np.int8)
+        lq = int(g0.integers(600, 900))
+        p0 = int(g0.integers(0, 1600 - lq))
+        src = r[p0:p0 + lq]
+        q, _ = W.mutate_many(g0, src, np.array([0, lq]), 0.03, 0.01, 0.01, 3)
+        qs.append(q if k < 3 else g0.integers(0, 4, lq).astype(np.int8))
+        rs.append(r)
+    b = W.from_lists("one-pair-graph-tall", W.dna_matrix(), 3, 1, qs, rs)
+    g = swx.Graph(ctx, b.matrix, b.gap_open, b.gap_extend, max_pairs=1, max_qlen=1024,
+                  max_rlen=1600, qcat_cap=1100, rcat_cap=1700, nq_cap=2, nr_cap=3, route=route)
+    try:
+        for p in range(b.npairs):
+            pb = b.subset(np.array([p]))
+            g.load(pb.qcat, pb.qoff, pb.rcat, pb.roff, pb.pair_q, pb.pair_r)
+            g.run()
+            recs, cig = g.read()
+            _check_oracle(pb, recs, cig)
+            _say(f"[graph] tall one-pair route {route} pair {p}: score {recs['score1'][0]}")
+    finally:
+        g.close()
