@@ -17,16 +17,21 @@
 // Each lane walks the matrix in strips of R rows.  For each column of a strip
 // the lane keeps H and E of its R rows in registers and receives H and F of
 // the row above from the boundary planes written by the previous strip; the
-// cell update is 11 saturating 16-bit-pair instructions plus two for the
+// cell update is 9 saturating 16-bit-pair instructions plus two for the
 // column max with the row code (value * 32 + code, so that a max over the
-// strip also names the first row reaching it).  Boundary planes and the
-// reference symbols (packed per task by k_inter_rsym, padding included) move
-// in groups of 4 columns: one 16-byte word per lane and plane.
+// strip also names the first row reaching it; one and a half when rows go in
+// pairs, see kColPair), one fewer when the bias is the gap open penalty.
+// Boundary planes and the reference symbols (packed per task by k_inter_rsym,
+// padding included) move in groups of 4 columns: one 16-byte word per lane
+// and plane.
 //
 // Scores live in a biased domain: the substitution term arrives as
-// S + bias >= 0 (bias = -min S), E and F are kept as E + bias and F + bias
+// S + bias >= 0 (bias >= -min S), E and F are kept as E + bias and F + bias
 // floored at 0 by saturating subtraction, and H is recovered with one
 // saturating subtraction of the bias, which also applies the zero floor.
+// When the bias equals o, that same subtraction is the H - o that opens a
+// gap (a candidate below zero is raised to zero, i.e. to -bias: gap values
+// at or below zero never decide a cell, whose H is at least zero).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -94,14 +99,26 @@ struct CoopShared {
 constexpr int32_t kStripDone = (int32_t)0x80000000u;
 constexpr int64_t kCoopSpinLimit = int64_t(1) << 26;
 
+// How a 16-bit fill keeps a column's maximum (value * 32 + row code): one
+// max per row, the same after clamping the value to the field's top (scores
+// of the launch may pass it), or one packed three-way maximum per two rows
+// (every encoded value of the launch below 0x7C00).  32-bit lanes use the
+// first.
+enum : int { kColPlain = 0, kColClamp = 1, kColPair = 2 };
+// Form of a fill kernel: the column maximum's form, plus kFormHo when the
+// launch's bias equals o (H and H - o are then one value).
+constexpr int kFormHo = 4;
+
 // One task (up to 64 or 128 pairs) on one wave: every strip, column group by
 // column group.  tid is uniform across the wave, so the task and everything
 // derived from it (bounds, plane addresses) live in SGPRs.
-template <class V, int R, uint32_t MODE, bool CLAMP, bool REV, bool COOP>
+template <class V, int R, uint32_t MODE, int FORM, bool REV, bool COOP>
 __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid,
                                            const uint32_t *s_lut, CoopShared *cs, int wave) {
   using T = VT<V>;
   constexpr int NH = T::kHalves;
+  constexpr int COL = FORM & 3;
+  constexpr bool HO = (FORM & kFormHo) != 0;
   const int lane = threadIdx.x & 63;
   const InterTask tk = a.tasks[tid];
   if (tk.nslots == 0) return;   // an empty task of a fixed-capacity plan (uniform per workgroup)
@@ -428,6 +445,7 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
           // (diagonal + substitution) is computed one row ahead
           hdtop = hup;
           V cm = T::zero();
+          V enc0 = T::zero();   // paired column maximum: the pair's first row
           V ho = T::zero();
           auto score_of = [&](int r) -> V {
             uint32_t sraw;
@@ -436,6 +454,7 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
             return T::from(sraw);
           };
           V u_next = T::add(hdiag_in, score_of(0));
+          static_assert(NR % 2 == 0, "rows come in pairs");
   #pragma unroll
           for (int r = 0; r < NR; ++r) {
             const V u = u_next;
@@ -449,8 +468,17 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
             // scores past the 11-bit value field enter the code as the field's
             // top (the pass is then flagged and re-run wider)
             // (32-bit lanes hold any score beside the code)
-            cm = T::max(cm, T::enc_nosat((CLAMP && NH == 2) ? T::min(hn, vtop) : hn, code, mul32));
-            ho = T::subs(hb, vo);
+            const V enc = T::enc_nosat((COL == kColClamp && NH == 2) ? T::min(hn, vtop) : hn, code, mul32);
+            if constexpr (COL == kColPair && NH == 2) {
+              // rows in pairs, one packed three-way maximum per pair: every
+              // encoded value is below 0x7C00 here (scores of the launch are
+              // at most kInter16PairLimit), where it is the unsigned maximum
+              if (r & 1) cm = T::max3(cm, enc0, enc);
+              else enc0 = enc;
+            } else {
+              cm = T::max(cm, enc);
+            }
+            ho = HO ? hn : T::subs(hb, vo);
             E[r] = T::max(T::subs(E[r], ve), ho);
             F = T::max(T::subs(F, ve), ho);   // F of the next row
           }
@@ -579,7 +607,7 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
 // them largest first, 2 keeps a grid of resident waves that take tasks
 // largest first from a device counter (a work queue: one 64-bit atomic per
 // task) until it runs past the last task.
-template <class V, int R, uint32_t MODE, bool CLAMP, bool REV, bool COOP>
+template <class V, int R, uint32_t MODE, int FORM, bool REV, bool COOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fill_waves<R>()))) void k_inter_fill(
     InterArgs a) {
   struct NoShared {};
@@ -609,7 +637,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fill_waves<
       k = (int64_t)(((uint64_t)hi << 32) | lo);
     }
     if (k >= a.ntasks) return;   // uniform per workgroup in the cooperative mode
-    inter_task<V, R, MODE, CLAMP, REV, COOP>(a, a.sched == 0 ? k : a.ntasks - 1 - k, s_lut, csp,
+    inter_task<V, R, MODE, FORM, REV, COOP>(a, a.sched == 0 ? k : a.ntasks - 1 - k, s_lut, csp,
                                              wave);
     if (!queued) return;
   }
@@ -724,6 +752,18 @@ __global__ __launch_bounds__(256) void k_inter_prof(PackArgs a) {
 }
 
 // ---- host-side launchers ------------------------------------------------
+template <class V, int R, uint32_t MODE, int FORM>
+static void launch_form(const InterArgs &a, dim3 g, dim3 b, hipStream_t st) {
+  const bool coop = a.coop > 1;
+  if (a.rev) {
+    if (coop) hipLaunchKernelGGL((k_inter_fill<V, R, MODE, FORM, true, true>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_inter_fill<V, R, MODE, FORM, true, false>), g, b, 0, st, a);
+  } else {
+    if (coop) hipLaunchKernelGGL((k_inter_fill<V, R, MODE, FORM, false, true>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_inter_fill<V, R, MODE, FORM, false, false>), g, b, 0, st, a);
+  }
+}
+
 template <class V, int R, uint32_t MODE>
 static hipError_t launch_fill(const InterArgs &a, hipStream_t st) {
   const int waves_per_block = 4;
@@ -738,22 +778,22 @@ static hipError_t launch_fill(const InterArgs &a, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, st, a.queue);
   }
   const dim3 g((unsigned)blocks), b(64 * waves_per_block);
-  const bool coop = a.coop > 1;
-  if (a.rev) {
-    if (a.clamp) {
-      if (coop) hipLaunchKernelGGL((k_inter_fill<V, R, MODE, true, true, true>), g, b, 0, st, a);
-      else hipLaunchKernelGGL((k_inter_fill<V, R, MODE, true, true, false>), g, b, 0, st, a);
-    } else {
-      if (coop) hipLaunchKernelGGL((k_inter_fill<V, R, MODE, false, true, true>), g, b, 0, st, a);
-      else hipLaunchKernelGGL((k_inter_fill<V, R, MODE, false, true, false>), g, b, 0, st, a);
-    }
+  // 32-bit lanes: one form (their values hold any score beside the code);
+  // 16-bit strips other than 32 rows (tuning choices): no pairs, no merged H - o
+  if constexpr (VT<V>::kHalves == 1) {
+    launch_form<V, R, MODE, kColPlain>(a, g, b, st);
+  } else if constexpr (R != 32) {
+    if (a.clamp) launch_form<V, R, MODE, kColClamp>(a, g, b, st);
+    else launch_form<V, R, MODE, kColPlain>(a, g, b, st);
   } else {
-    if (a.clamp) {
-      if (coop) hipLaunchKernelGGL((k_inter_fill<V, R, MODE, true, false, true>), g, b, 0, st, a);
-      else hipLaunchKernelGGL((k_inter_fill<V, R, MODE, true, false, false>), g, b, 0, st, a);
-    } else {
-      if (coop) hipLaunchKernelGGL((k_inter_fill<V, R, MODE, false, false, true>), g, b, 0, st, a);
-      else hipLaunchKernelGGL((k_inter_fill<V, R, MODE, false, false, false>), g, b, 0, st, a);
+    const int col = a.clamp ? kColClamp : (a.pair3 ? kColPair : kColPlain);
+    switch (col | (a.bias == a.o ? kFormHo : 0)) {
+      case kColPlain: launch_form<V, R, MODE, kColPlain>(a, g, b, st); break;
+      case kColClamp: launch_form<V, R, MODE, kColClamp>(a, g, b, st); break;
+      case kColPair: launch_form<V, R, MODE, kColPair>(a, g, b, st); break;
+      case kColPlain | kFormHo: launch_form<V, R, MODE, kColPlain | kFormHo>(a, g, b, st); break;
+      case kColClamp | kFormHo: launch_form<V, R, MODE, kColClamp | kFormHo>(a, g, b, st); break;
+      default: launch_form<V, R, MODE, kColPair | kFormHo>(a, g, b, st); break;
     }
   }
   return hipGetLastError();

@@ -238,7 +238,12 @@ static int make_scoring(const int8_t *mat, int32_t n, int32_t o, int32_t e, Scor
   sc->n = n;
   sc->o = o;
   sc->e = e;
+  // the fills' bias: at least -min S, so that every biased score S + bias is
+  // a byte >= 0; the gap open penalty where that qualifies, since the fill's
+  // saturating H = hb - bias is then also its H - o (one instruction fewer
+  // per cell)
   sc->bias = mn < 0 ? -mn : 0;
+  if (o >= sc->bias && o + mx <= 255) sc->bias = o;
   sc->smax = mx;
   sc->qsel = (n <= 4);
   // QSEL column LUTs: lut[r] holds, for query symbols a = 0..3, the biased
@@ -408,6 +413,7 @@ static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &v
   // without a possible score above the 16-bit value field the row code needs
   // no saturation (scores are at most smax * min(qlen, rlen))
   a.clamp = score_bound > kInter16Limit - 1 ? 1 : 0;
+  a.pair3 = score_bound <= kInter16PairLimit ? 1 : 0;
   a.code_top = pl.R - 1;
   a.dummy = sc.dmat;   // any readable device bytes
   a.target = d_target;
@@ -1573,7 +1579,7 @@ struct GraphState {
   Scoring sc{};
   DevArena A;
   int64_t B = 0, QM = 0, RM = 0;
-  bool clamp = false, need32 = false;
+  bool clamp = false, need32 = false, pair3 = false;
   // inputs / outputs
   int8_t *qcat = nullptr, *rcat = nullptr;
   int64_t *qoff = nullptr, *roff = nullptr, *pair_q = nullptr, *pair_r = nullptr;
@@ -1693,6 +1699,7 @@ static int fixed_fill(GraphState &g, FixedPlan &pl, const int64_t *ids, const in
   a.n = g.sc.n; a.o = g.sc.o; a.e = g.sc.e; a.bias = g.sc.bias;
   a.rev = rev ? 1 : 0;
   a.clamp = g.clamp ? 1 : 0;
+  a.pair3 = g.pair3 ? 1 : 0;
   a.code_top = pl.R - 1;
   a.dummy = g.sc.dmat;
   a.target = target;
@@ -2598,6 +2605,7 @@ int swx_graph_create(swx_ctx *ctx, const swx_graph_cfg *cfg, swx_graph **out, sw
   const int64_t bound = (int64_t)std::max(g.sc.smax, 0) * std::min<int64_t>(g.QM, g.RM);
   if (bound >= (1 << 26) - 1) { delete gr; return fail(SWX_EOVERFLOW, "scores could exceed the lane range"); }
   g.clamp = bound > kInter16Limit - 1;
+  g.pair3 = bound <= kInter16PairLimit;
   g.need32 = bound >= kInter16Limit;
   g.intra = cfg->route == SWX_ROUTE_INTRA;
   g.fill_sched = ctx->fill_sched;

@@ -86,6 +86,8 @@ struct InterArgs {
   int32_t n, o, e, bias;
   int32_t rev;                // reversed pass: stop at target, band window, no CM plane
   int32_t clamp;              // scores may exceed the 16-bit value field: saturate the code
+  int32_t pair3;              // 16-bit lanes, scores at most kInter16PairLimit: the column
+                              // maximum takes two rows per packed three-way maximum
   int32_t code_top;           // row code of the first strip row (strip height - 1)
   const int8_t *dummy;        // readable bytes for empty slots
   const int32_t *target;      // reversed pass: per pair score to reach
@@ -119,6 +121,10 @@ constexpr int kCoopWaves = 4;
 // Largest score the 16-bit inter path represents exactly together with its
 // 5-bit row code (value * 32 + code <= 65535).
 constexpr int kInter16Limit = 2047;
+// Largest score whose encoded form (value * 32 + code <= 0x7BFF) stays below
+// 0x7C00, the range where the packed f16 maximum orders 16-bit patterns as
+// unsigned integers.
+constexpr int kInter16PairLimit = 991;
 
 // ---- intra-sequence fill (long pairs) ------------------------------------
 // One wave per job.  Lane k holds rows [k*RL, (k+1)*RL) of a strip of 64*RL

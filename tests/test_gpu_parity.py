@@ -150,6 +150,39 @@ def test_lane_width_threshold(ctx):
         assert set(recs["lane_bits"]) == {16, 32}
 
 
+@pytest.mark.parametrize("match,o,e,L", [
+    (1, 2, 1, 991),    # bias = o; a-priori bound 991: column max over row pairs, at its limit
+    (1, 2, 1, 992),    # bias = o; bound 992: one max per row
+    (2, 1, 1, 495),    # o below the worst mismatch (bias = 2, not o); paired rows
+    (2, 1, 1, 600),    # neither
+])
+def test_column_max_forms(ctx, match, o, e, L):
+    """The 16-bit fill's forms on either side of their conditions: the column
+    maximum over pairs of rows (only when every score of the batch is at most
+    991, so that value * 32 + row code stays below 0x7C00) and H - o taken as
+    H itself (only when the bias can be the gap open penalty).  Planted exact
+    copies reach the a-priori bound (smax times the longest query) itself,
+    mutated copies and random pairs give ends and begins in every row of a
+    strip."""
+    g = np.random.Generator(np.random.PCG64(1000 + L + 7 * o))
+    mat = W.dna_matrix(match, -match)
+    qs, rs = [], []
+    for k in range(10):
+        ref = g.integers(0, 4, size=L + 120).astype(np.int8)
+        q = ref[40 + k:40 + k + L].copy()
+        if k >= 2:   # mutated copies
+            flip = g.random(L) < 0.02 * k
+            q[flip] = (q[flip] + g.integers(1, 4, size=int(flip.sum()))) % 4
+        qs.append(q)
+        rs.append(ref)
+    for k in range(20):   # short random pairs beside them
+        qs.append(g.integers(0, 4, size=int(g.integers(1, 80))).astype(np.int8))
+        rs.append(g.integers(0, 4, size=int(g.integers(1, 300))).astype(np.int8))
+    b = W.from_lists(f"forms-{match}-{o}-{L}", mat, o, e, qs, rs)
+    recs = assert_parity(ctx, b)
+    assert int(recs["score1"].max()) == match * L
+
+
 def test_many_tasks_ragged(ctx):
     b = W.random_pairs(404, 700, (1, 200), (1, 500))
     assert_parity(ctx, b)
