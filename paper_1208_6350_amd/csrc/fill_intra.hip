@@ -20,7 +20,8 @@
 //
 // All lanes are 32-bit, biased like the inter-sequence kernel: scores arrive
 // as S + bias >= 0, E and F are kept biased and floored at 0, and one
-// saturating subtraction of the bias yields H with its zero floor.
+// saturating subtraction of the bias yields H with its zero floor (and, when
+// the bias is the gap open penalty, also the H - o that opens a gap).
 #include <hip/hip_runtime.h>
 
 #include "lanes.h"
@@ -109,7 +110,7 @@ __device__ __forceinline__ void lds_wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <int RL, bool REV, bool SPREAD>
+template <int RL, bool REV, bool SPREAD, bool HO>
 __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
   extern __shared__ uint4 s_dyn[];            // per wave: [(n + 1) symbols][64 lanes][RL bytes]
   __shared__ int8_t s_mat[32 * 32];
@@ -349,7 +350,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
           H[r] = hn;
           const uint32_t enc = (hn << kb) + (uint32_t)(RL - 1 - r);
           cm = cm > enc ? cm : enc;
-          const uint32_t ho = T::subs(hb, vo);
+          const uint32_t ho = HO ? hn : T::subs(hb, vo);   // HO: bias == o
           E[r] = T::max(T::subs(E[r], ve), ho);
           F = T::max(T::subs(F, ve), ho);
         }
@@ -447,7 +448,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill(IntraArgs a) {
 // values in 32-bit words, one row per job as in the 32-bit pass.
 // M3: every lane value of the launch stays below 0x7C00 (score bound plus
 // bias), so H is taken with one packed three-way maximum.
-template <int RL, bool M3>
+template <int RL, bool M3, bool HO>
 __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill16(IntraArgs a) {
   extern __shared__ uint4 s_dyn[];            // per wave and job: [(n + 1) symbols][64 lanes][RL bytes]
   __shared__ int8_t s_mat[32 * 32];
@@ -639,7 +640,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_intra_fill16(IntraArgs a) {
           const uint32_t wa = perm(T::bits(hn), kc, selA), wb = perm(T::bits(hn), kc, selB);
           cmA = cmA > wa ? cmA : wa;
           cmB = cmB > wb ? cmB : wb;
-          const V16 ho = T::subs(hb, vo);
+          const V16 ho = HO ? hn : T::subs(hb, vo);   // HO: bias == o
           E[r] = T::max(T::subs(E[r], ve), ho);
           F = T::max(T::subs(F, ve), ho);
         }
@@ -854,19 +855,26 @@ hipError_t intra_rev_jobs_fixed(int64_t B, const int32_t *score, const int64_t *
 // ---- launchers ----------------------------------------------------------------
 size_t intra_lds_bytes(int n, int RL) { return (size_t)(n + 1) * 64 * RL; }
 
-template <int RL>
-static void launch_rl(const IntraArgs &a, int waves, bool rev, hipStream_t st) {
+template <int RL, bool HO>
+static void launch_rl_ho(const IntraArgs &a, int waves, bool rev, hipStream_t st) {
   const dim3 b(64 * waves);
   const size_t lds = intra_lds_bytes(a.n, RL) * waves;
   if (a.segs > 1) {
     const dim3 g((unsigned)(8 * a.segs * ((a.njobs + 7) / 8)));
-    if (rev) hipLaunchKernelGGL((k_intra_fill<RL, true, true>), g, b, lds, st, a);
-    else hipLaunchKernelGGL((k_intra_fill<RL, false, true>), g, b, lds, st, a);
+    if (rev) hipLaunchKernelGGL((k_intra_fill<RL, true, true, HO>), g, b, lds, st, a);
+    else hipLaunchKernelGGL((k_intra_fill<RL, false, true, HO>), g, b, lds, st, a);
     return;
   }
   const dim3 g((unsigned)a.njobs);
-  if (rev) hipLaunchKernelGGL((k_intra_fill<RL, true, false>), g, b, lds, st, a);
-  else hipLaunchKernelGGL((k_intra_fill<RL, false, false>), g, b, lds, st, a);
+  if (rev) hipLaunchKernelGGL((k_intra_fill<RL, true, false, HO>), g, b, lds, st, a);
+  else hipLaunchKernelGGL((k_intra_fill<RL, false, false, HO>), g, b, lds, st, a);
+}
+
+// the bias is the gap open penalty: H and H - o are one value
+template <int RL>
+static void launch_rl(const IntraArgs &a, int waves, bool rev, hipStream_t st) {
+  if (a.bias == a.o) launch_rl_ho<RL, true>(a, waves, rev, st);
+  else launch_rl_ho<RL, false>(a, waves, rev, st);
 }
 
 __global__ void k_intra_sync_init(IntraSync *sync, int64_t njobs) {
@@ -896,8 +904,13 @@ template <int RL>
 static void launch_rl16(const IntraArgs &a, int waves, bool m3, hipStream_t st) {
   const dim3 g((unsigned)(a.njobs / 2)), b(64 * waves);
   const size_t lds = intra_lds_bytes16(a.n, RL) * waves;
-  if (m3) hipLaunchKernelGGL((k_intra_fill16<RL, true>), g, b, lds, st, a);
-  else hipLaunchKernelGGL((k_intra_fill16<RL, false>), g, b, lds, st, a);
+  if (a.bias == a.o) {   // H and H - o are one value
+    if (m3) hipLaunchKernelGGL((k_intra_fill16<RL, true, true>), g, b, lds, st, a);
+    else hipLaunchKernelGGL((k_intra_fill16<RL, false, true>), g, b, lds, st, a);
+  } else {
+    if (m3) hipLaunchKernelGGL((k_intra_fill16<RL, true, false>), g, b, lds, st, a);
+    else hipLaunchKernelGGL((k_intra_fill16<RL, false, false>), g, b, lds, st, a);
+  }
 }
 
 hipError_t intra_fill16(const IntraArgs &a, int RL, int waves, bool m3, hipStream_t st) {
