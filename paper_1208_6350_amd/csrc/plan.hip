@@ -186,6 +186,25 @@ __global__ void k_rev_prepare(int64_t n, const int32_t *score, const int32_t *qe
 
 static inline unsigned nb(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Eager sorts go by digit passes (onesweep) at every size: rocprim's default
+// sorts up to 2^20 items by block sorts and about ten merge passes instead,
+// which took ~0.2 ms per sort of 10^6 pairs (two kernels per merge pass).
+// Both are stable, so the order is the same.  Sorts recorded into a graph
+// take the merge form at every size: onesweep clears its lookback states with
+// a memset, which must not become a graph node.
+using OnesweepConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                                  rocprim::default_config, 0>;
+using MergeConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                               rocprim::default_config, SIZE_MAX>;
+
+template <class K, class V>
+static hipError_t radix_pairs(bool graph, void *tmp, size_t &bytes, rocprim::double_buffer<K> &kb,
+                              rocprim::double_buffer<V> &vb, size_t n, unsigned end_bit,
+                              hipStream_t st) {
+  if (graph) return rocprim::radix_sort_pairs<MergeConfig>(tmp, bytes, kb, vb, n, 0u, end_bit, st);
+  return rocprim::radix_sort_pairs<OnesweepConfig>(tmp, bytes, kb, vb, n, 0u, end_bit, st);
+}
+
 hipError_t count_classes(int64_t n, const uint8_t *cls, int64_t *counts, hipStream_t st) {
   if (!n) return hipSuccess;
   unsigned blocks = nb(n, 256);
@@ -196,10 +215,10 @@ hipError_t count_classes(int64_t n, const uint8_t *cls, int64_t *counts, hipStre
 
 hipError_t sort_keys(int64_t n, uint64_t *keys, uint64_t *keys_alt, int64_t *vals,
                      int64_t *vals_alt, void *tmp, size_t *tmp_bytes, int64_t **sorted_out,
-                     hipStream_t st, int end_bit) {
+                     hipStream_t st, int end_bit, bool graph) {
   rocprim::double_buffer<uint64_t> kb(keys, keys_alt);
   rocprim::double_buffer<int64_t> vb(vals, vals_alt);
-  hipError_t e = rocprim::radix_sort_pairs(tmp, *tmp_bytes, kb, vb, (size_t)n, 0u, (unsigned)end_bit, st);
+  hipError_t e = radix_pairs(graph, tmp, *tmp_bytes, kb, vb, (size_t)n, (unsigned)end_bit, st);
   if (tmp) *sorted_out = vb.current();
   return e;
 }
@@ -217,7 +236,7 @@ hipError_t rev_prepare(int64_t npairs, const int32_t *score, const int32_t *qend
 hipError_t plan_sort(int64_t n, const int64_t *n_dev, const int64_t *ids, const int32_t *qlen,
                      const int64_t *rlen, const int32_t *band, int32_t R, uint64_t *keys,
                      uint64_t *keys_alt, int64_t *vals, int64_t *vals_alt, void *tmp,
-                     size_t *tmp_bytes, int64_t **sorted_out, hipStream_t st) {
+                     size_t *tmp_bytes, int64_t **sorted_out, hipStream_t st, bool graph) {
   // without a band the top field is zero: sort the low 44 bits only.  The
   // size query covers both bit ranges, so one buffer serves either pass.
   const int end_bit = band ? 64 : 44;
@@ -225,8 +244,8 @@ hipError_t plan_sort(int64_t n, const int64_t *n_dev, const int64_t *ids, const 
     rocprim::double_buffer<uint64_t> kb(keys, keys_alt);
     rocprim::double_buffer<int64_t> vb(vals, vals_alt);
     size_t b44 = 0, b64 = 0;
-    hipError_t e = rocprim::radix_sort_pairs(nullptr, b44, kb, vb, (size_t)n, 0u, 44u, st);
-    if (e == hipSuccess) e = rocprim::radix_sort_pairs(nullptr, b64, kb, vb, (size_t)n, 0u, 64u, st);
+    hipError_t e = radix_pairs(graph, nullptr, b44, kb, vb, (size_t)n, 44u, st);
+    if (e == hipSuccess) e = radix_pairs(graph, nullptr, b64, kb, vb, (size_t)n, 64u, st);
     *tmp_bytes = b44 > b64 ? b44 : b64;
     return e;
   }
@@ -237,7 +256,7 @@ hipError_t plan_sort(int64_t n, const int64_t *n_dev, const int64_t *ids, const 
   if (e != hipSuccess) return e;
   rocprim::double_buffer<uint64_t> kb(keys, keys_alt);
   rocprim::double_buffer<int64_t> vb(vals, vals_alt);
-  e = rocprim::radix_sort_pairs(tmp, *tmp_bytes, kb, vb, (size_t)n, 0u, (unsigned)end_bit, st);
+  e = radix_pairs(graph, tmp, *tmp_bytes, kb, vb, (size_t)n, (unsigned)end_bit, st);
   *sorted_out = vb.current();
   return e;
 }

@@ -1660,7 +1660,7 @@ static int fixed_plan_alloc(GraphState &g, FixedPlan &pl, int lane_bits, int R) 
   if (!g.sc.qsel) pl.prof = A.get<uint8_t>(pl.ntasks * qp_cap * (g.sc.n + 1) * halves * 64 + 16);
   size_t sb = 0;
   HIP_TRY(plan_sort(g.B, nullptr, nullptr, nullptr, nullptr, nullptr, R, pl.k0, pl.k1, pl.v0, pl.v1,
-                    nullptr, &sb, nullptr, nullptr));
+                    nullptr, &sb, nullptr, nullptr, true));
   pl.sort_bytes = sb;
   pl.sort_tmp = A.alloc(sb);
   if (!pl.k0 || !pl.k1 || !pl.v0 || !pl.v1 || !pl.tasks || !pl.bsz || !pl.boff || !pl.qsz ||
@@ -1676,7 +1676,7 @@ static int fixed_fill(GraphState &g, FixedPlan &pl, const int64_t *ids, const in
                       const int32_t *target, FillOut out, hipStream_t st) {
   size_t sb = pl.sort_bytes;
   HIP_TRY(plan_sort(pl.cap_n, n_dev, ids, qlen, rlen, band, pl.R, pl.k0, pl.k1, pl.v0, pl.v1,
-                    pl.sort_tmp, &sb, &pl.sorted, st));
+                    pl.sort_tmp, &sb, &pl.sorted, st, true));
   const int halves = pl.lane_bits == 16 ? 2 : 1;
   const int64_t per_row = g.sc.qsel ? 0 : (int64_t)(g.sc.n + 1) * halves * 64;
   HIP_TRY(plan_tasks_dev(   // also clears bsz[ntasks], qsz[ntasks]
@@ -1839,7 +1839,8 @@ static int fixed_issue(GraphState &g, hipStream_t st) {
     if ((rc = fixed_scan(g, g.ccap, g.coff, B + 1, st))) return rc;
     HIP_TRY(count_classes(B, g.cls, g.counts, st));
     size_t sb = g.tb_sort_bytes;
-    HIP_TRY(sort_keys(B, g.tk0, g.tk1, g.tv0, g.tv1, g.tb_sort_tmp, &sb, &g.tb_sorted, st, kTbKeyBits));
+    HIP_TRY(sort_keys(B, g.tk0, g.tk1, g.tv0, g.tv1, g.tb_sort_tmp, &sb, &g.tb_sorted, st, kTbKeyBits,
+                      true));
     HIP_TRY(class_ranges(g.counts, g.ranges, st));
     for (int c = 1; c <= 3; ++c) {
       FixedTb &t = g.tb[c];
@@ -2038,7 +2039,8 @@ static int graph_alloc(GraphState &g) {
     }
   }
   size_t sb = 0;
-  HIP_TRY(sort_keys(B, g.tk0, g.tk1, g.tv0, g.tv1, nullptr, &sb, &g.tb_sorted, nullptr, kTbKeyBits));
+  HIP_TRY(sort_keys(B, g.tk0, g.tk1, g.tv0, g.tv1, nullptr, &sb, &g.tb_sorted, nullptr, kTbKeyBits,
+                    true));
   g.tb_sort_bytes = sb;
   g.tb_sort_tmp = A.alloc(sb);
   // scan scratch: the largest scan is over B + 1 elements

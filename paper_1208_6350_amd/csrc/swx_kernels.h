@@ -202,9 +202,10 @@ hipError_t lane_probe(int bits, int64_t cols, int64_t blocks, int32_t o, int32_t
                       hipStream_t st);
 hipError_t class_ranges(const int64_t *counts, int64_t *ranges, hipStream_t st);
 hipError_t count_classes(int64_t n, const uint8_t *cls, int64_t *counts, hipStream_t st);
+// graph: the sort is recorded into a HIP graph (a form that issues no memset)
 hipError_t sort_keys(int64_t n, uint64_t *keys, uint64_t *keys_alt, int64_t *vals,
                      int64_t *vals_alt, void *tmp, size_t *tmp_bytes, int64_t **sorted_out,
-                     hipStream_t st, int end_bit = 64);
+                     hipStream_t st, int end_bit = 64, bool graph = false);
 hipError_t rev_prepare(int64_t npairs, const int32_t *score, const int32_t *qend,
                        const int64_t *rend, const uint8_t *lanebits, int32_t smax, int32_t o,
                        int32_t e, int32_t *band, int32_t *band_q, uint8_t *f16, uint8_t *f32,
@@ -355,7 +356,7 @@ hipError_t launch_begins(int64_t npairs, const int32_t *score1, const int32_t *q
 hipError_t plan_sort(int64_t n, const int64_t *n_dev, const int64_t *ids, const int32_t *qlen, const int64_t *rlen,
                      const int32_t *band, int32_t R, uint64_t *keys, uint64_t *keys_alt,
                      int64_t *vals, int64_t *vals_alt, void *tmp, size_t *tmp_bytes,
-                     int64_t **sorted_out, hipStream_t st);
+                     int64_t **sorted_out, hipStream_t st, bool graph = false);
 hipError_t plan_tasks_dev(int64_t n, const int64_t *n_dev, int64_t ntasks, int32_t slots, int32_t R,
                           int64_t qdata_per_row, const int64_t *sorted, const int32_t *qlen,
                           const int64_t *rlen, const int32_t *band, const int32_t *band_q,
