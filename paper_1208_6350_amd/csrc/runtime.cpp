@@ -361,6 +361,66 @@ static int plan_pass(swx_ctx *ctx, const Scoring &sc, const int64_t *ids, int64_
   return SWX_OK;
 }
 
+// Runs independent launches side by side: each goes to a side stream that
+// first waits for everything queued on the main stream, and the main stream
+// then waits for all of them.  Launches come with a cost estimate (an
+// estimated run time alone on the device) and are placed longest first on the
+// least loaded of two side streams (the device gives a process few hardware
+// queues; more streams would share them).  A `lead` launch (one whose few,
+// long waves leave most of the device to others) goes first, alone, and its
+// stream is charged only kLeadShare of its cost: the launches beside it run
+// mostly in its shadow.
+struct SideLaunch {
+  double cost;
+  std::function<hipError_t(hipStream_t)> fn;
+  bool lead = false;
+};
+constexpr double kLeadShare = 0.2;
+
+static int run_side_by_side(swx_ctx *ctx, std::vector<SideLaunch> &ls) {
+  if (ls.empty()) return SWX_OK;
+  if (ls.size() == 1 || !ctx->side_streams) {
+    for (auto &l : ls) HIP_TRY(l.fn(ctx->stream));
+    return SWX_OK;
+  }
+  constexpr int na = swx_ctx::kAux;
+  // side streams are made on first use, so a context that never needs them
+  // (short pairs only) holds a single stream and a single hardware queue
+  bool have = true;
+  for (int k = 0; k < na; ++k)
+    if (!ctx->aux[k] && hipStreamCreate(&ctx->aux[k]) != hipSuccess) {
+      ctx->aux[k] = nullptr;
+      have = false;
+    }
+  if (!have) {   // no side streams: one after the other on the main stream
+    for (auto &l : ls) HIP_TRY(l.fn(ctx->stream));
+    return SWX_OK;
+  }
+  std::stable_sort(ls.begin(), ls.end(), [](const SideLaunch &x, const SideLaunch &y) {
+    return x.lead != y.lead ? x.lead : x.cost > y.cost;
+  });
+  HIP_TRY(hipEventRecord(ctx->fork_ev, ctx->stream));
+  for (int k = 0; k < na; ++k) HIP_TRY(hipStreamWaitEvent(ctx->aux[k], ctx->fork_ev, 0));
+  // place every launch first, then submit stream by stream: the lead's
+  // stream is filled before the other one starts (measured: interleaved
+  // submission lets the other stream's first kernel take the device first)
+  double load[na] = {0, 0};
+  std::vector<int> where(ls.size());
+  for (size_t x = 0; x < ls.size(); ++x) {
+    const int k = load[0] <= load[1] ? 0 : 1;
+    load[k] += ls[x].lead ? kLeadShare * ls[x].cost : ls[x].cost;
+    where[x] = k;
+  }
+  for (int k = 0; k < na; ++k)
+    for (size_t x = 0; x < ls.size(); ++x)
+      if (where[x] == k) HIP_TRY(ls[x].fn(ctx->aux[k]));
+  for (int k = 0; k < na; ++k) {
+    HIP_TRY(hipEventRecord(ctx->join_ev[k], ctx->aux[k]));
+    HIP_TRY(hipStreamWaitEvent(ctx->stream, ctx->join_ev[k], 0));
+  }
+  return SWX_OK;
+}
+
 // profile (general alphabets) + fill for one plan; when mark_fill >= 0,
 // events mark_fill and mark_fill + 1 bracket the fill kernel alone
 static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &view, bool rev,
@@ -424,6 +484,29 @@ static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &v
   a.anchor = anchor;
   a.lastcol = lastcol;
   a.coop = coop_waves(ctx->fill_coop, pl.ntasks, ctx->cus);
+  // A reversed pass over many tasks: its largest tasks (full rectangles of
+  // weak alignments, no early exit) each take the four waves of a workgroup,
+  // launched first beside the rest.  On one wave each they start first and
+  // end last: on the benchmark workload the ~50 largest of 7,800 tasks ran
+  // 2.0-3.1 ms against 2.1 ms of work per wave slot (the stage went 3.5 ->
+  // 3.3 ms with the split).
+  const int64_t nsplit = (rev && a.coop == 1 && ctx->fill_coop == 0 && ctx->side_streams &&
+                          pl.ntasks >= (int64_t)ctx->cus * 8)
+                             ? std::min<int64_t>(pl.ntasks / 16, ctx->cus / 2)
+                             : 0;
+  if (nsplit > 0 && mark_fill < 0) {
+    InterArgs big = a, rest = a;
+    big.tasks = pl.d_tasks + (pl.ntasks - nsplit);   // tasks are sorted, largest last
+    big.ntasks = nsplit;
+    big.coop = kCoopWaves;
+    big.sched = 1;   // a grid of its own, all resident: no device queue
+    rest.ntasks = pl.ntasks - nsplit;
+    const int lb = pl.lane_bits, R = pl.R;
+    std::vector<SideLaunch> ls;
+    ls.push_back({2.0, [=](hipStream_t s_) { return inter_fill(big, lb, R, s_); }, true});
+    ls.push_back({1.0, [=](hipStream_t s_) { return inter_fill(rest, lb, R, s_); }});
+    return run_side_by_side(ctx, ls);
+  }
   if (mark_fill >= 0) HIP_TRY(hipEventRecord(ctx->ev[mark_fill], st));
   HIP_TRY(inter_fill(a, pl.lane_bits, pl.R, st));
   if (mark_fill >= 0) HIP_TRY(hipEventRecord(ctx->ev[mark_fill + 1], st));
@@ -481,66 +564,6 @@ struct DeviceBatch {
   const int64_t *qoff, *roff, *pair_q, *pair_r;
   int64_t qcat_len, rcat_len, nq, nr, npairs;
 };
-
-// Runs independent launches side by side: each goes to a side stream that
-// first waits for everything queued on the main stream, and the main stream
-// then waits for all of them.  Launches come with a cost estimate (an
-// estimated run time alone on the device) and are placed longest first on the
-// least loaded of two side streams (the device gives a process few hardware
-// queues; more streams would share them).  A `lead` launch (one whose few,
-// long waves leave most of the device to others) goes first, alone, and its
-// stream is charged only kLeadShare of its cost: the launches beside it run
-// mostly in its shadow.
-struct SideLaunch {
-  double cost;
-  std::function<hipError_t(hipStream_t)> fn;
-  bool lead = false;
-};
-constexpr double kLeadShare = 0.2;
-
-static int run_side_by_side(swx_ctx *ctx, std::vector<SideLaunch> &ls) {
-  if (ls.empty()) return SWX_OK;
-  if (ls.size() == 1 || !ctx->side_streams) {
-    for (auto &l : ls) HIP_TRY(l.fn(ctx->stream));
-    return SWX_OK;
-  }
-  constexpr int na = swx_ctx::kAux;
-  // side streams are made on first use, so a context that never needs them
-  // (short pairs only) holds a single stream and a single hardware queue
-  bool have = true;
-  for (int k = 0; k < na; ++k)
-    if (!ctx->aux[k] && hipStreamCreate(&ctx->aux[k]) != hipSuccess) {
-      ctx->aux[k] = nullptr;
-      have = false;
-    }
-  if (!have) {   // no side streams: one after the other on the main stream
-    for (auto &l : ls) HIP_TRY(l.fn(ctx->stream));
-    return SWX_OK;
-  }
-  std::stable_sort(ls.begin(), ls.end(), [](const SideLaunch &x, const SideLaunch &y) {
-    return x.lead != y.lead ? x.lead : x.cost > y.cost;
-  });
-  HIP_TRY(hipEventRecord(ctx->fork_ev, ctx->stream));
-  for (int k = 0; k < na; ++k) HIP_TRY(hipStreamWaitEvent(ctx->aux[k], ctx->fork_ev, 0));
-  // place every launch first, then submit stream by stream: the lead's
-  // stream is filled before the other one starts (measured: interleaved
-  // submission lets the other stream's first kernel take the device first)
-  double load[na] = {0, 0};
-  std::vector<int> where(ls.size());
-  for (size_t x = 0; x < ls.size(); ++x) {
-    const int k = load[0] <= load[1] ? 0 : 1;
-    load[k] += ls[x].lead ? kLeadShare * ls[x].cost : ls[x].cost;
-    where[x] = k;
-  }
-  for (int k = 0; k < na; ++k)
-    for (size_t x = 0; x < ls.size(); ++x)
-      if (where[x] == k) HIP_TRY(ls[x].fn(ctx->aux[k]));
-  for (int k = 0; k < na; ++k) {
-    HIP_TRY(hipEventRecord(ctx->join_ev[k], ctx->aux[k]));
-    HIP_TRY(hipStreamWaitEvent(ctx->stream, ctx->join_ev[k], 0));
-  }
-  return SWX_OK;
-}
 
 static int gather_info(swx_ctx *ctx, int64_t n, const int64_t *d_ids, const int32_t *qlen,
                        const int64_t *rlen, const int32_t *score, const int32_t *qend,
