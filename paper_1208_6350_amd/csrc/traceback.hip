@@ -182,8 +182,11 @@ __global__ __launch_bounds__(256) void k_tb_band(TbArgs a, const TbTask *tasks, 
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int64_t tid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (tid >= ntasks) return;
+  // tasks are sorted by rows, ascending: the largest go first, so that the
+  // launch does not end on its longest tasks
+  const int64_t k_ = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (k_ >= ntasks) return;
+  const int64_t tid = ntasks - 1 - k_;
   const TbTask tk = tasks[tid];
   if (tk.nslots == 0) return;
   const bool live = lane < tk.nslots;
@@ -647,8 +650,10 @@ __global__ __launch_bounds__(256) void k_tb_strip(TbArgs a, const TbwTask *tasks
   const int lane = threadIdx.x & 63;
   const int g = lane & (LP - 1);        // row group of this lane
   const int slot = lane / LP;           // pair slot of the task
-  const int64_t tid = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (tid >= ntasks) return;
+  // tasks are sorted by rows and band, ascending: the largest go first
+  const int64_t k_ = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (k_ >= ntasks) return;
+  const int64_t tid = ntasks - 1 - k_;
   const TbwTask tk = tasks[tid];
   if (tk.nslots == 0) return;
   const bool live = slot < tk.nslots;
