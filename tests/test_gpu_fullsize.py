@@ -69,6 +69,24 @@ def test_batched_dna_full_size_device_resident(tuning):
     assert bad["pairs_bad"] == 0, bad
 
 
+def test_batched_dna_reversed_pass_split():
+    """263,000 pairs of the batched-DNA workload: 2,055 tasks of 128 pairs,
+    just above the 8 tasks per compute unit of a 256-CU device from which the
+    reversed pass runs its largest tasks four waves each on a side launch
+    beside the rest.  Every pair against the oracle."""
+    b = W.config4(npairs=263_000)
+    _say(f"[fullsize] config4 {b.npairs} pairs (reversed-pass split)")
+    ctx = swx.Context(0)
+    try:
+        recs, cig = _device_run(ctx, b)
+    finally:
+        ctx.close()
+    ref, rcig, rcoff = _oracle(b)
+    bad = mismatches(recs, cig, ref, rcig, rcoff)
+    _say(f"[fullsize] config4 263k mismatches {bad}")
+    assert bad["pairs_bad"] == 0, bad
+
+
 def test_protein_search_full_size_device_resident():
     b = W.config3()
     _say(f"[fullsize] config3 {b.npairs} targets")
