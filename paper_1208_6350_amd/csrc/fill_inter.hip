@@ -603,10 +603,10 @@ __device__ __forceinline__ void inter_task(const InterArgs &a, const int64_t tid
 }
 
 // Task order: tasks are sorted by (band, strips, columns) ascending, so the
-// largest come last.  sched 0 runs task blockIdx-order ascending, 1 runs
-// them largest first, 2 keeps a grid of resident waves that take tasks
-// largest first from a device counter (a work queue: one 64-bit atomic per
-// task) until it runs past the last task.
+// largest come last, or (order) listed by ascending area.  sched 0 runs
+// them in that order, 1 largest first, 2 keeps a grid of resident waves that
+// take tasks largest first from a device counter (a work queue: one 64-bit
+// atomic per task) until it runs past the last task.
 template <class V, int R, uint32_t MODE, int FORM, bool REV, bool COOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fill_waves<R>()))) void k_inter_fill(
     InterArgs a) {
@@ -637,10 +637,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fill_waves<
       k = (int64_t)(((uint64_t)hi << 32) | lo);
     }
     if (k >= a.ntasks) return;   // uniform per workgroup in the cooperative mode
-    inter_task<V, R, MODE, FORM, REV, COOP>(a, a.sched == 0 ? k : a.ntasks - 1 - k, s_lut, csp,
-                                             wave);
+    const int64_t tix = a.sched == 0 ? k : a.ntasks - 1 - k;
+    inter_task<V, R, MODE, FORM, REV, COOP>(a, a.order ? a.order[tix] : tix, s_lut, csp, wave);
     if (!queued) return;
   }
+}
+
+__global__ void k_area_keys(const InterTask *tasks, int64_t ntasks, uint64_t *keys,
+                            int64_t *vals) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntasks) return;
+  keys[t] = (uint64_t)(uint32_t)tasks[t].qp * (uint64_t)(uint32_t)tasks[t].rp;
+  vals[t] = t;
 }
 
 __global__ void k_zero_queue(unsigned long long *q) {
@@ -816,6 +824,14 @@ hipError_t inter_fill(const InterArgs &a, int lane_bits, int R, hipStream_t st) 
     if (R == 16) return qsel ? launch_fill<uint32_t, 16, kQSel>(a, st) : launch_fill<uint32_t, 16, kQGen>(a, st);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t inter_area_keys(const InterTask *tasks, int64_t ntasks, uint64_t *keys, int64_t *vals,
+                           hipStream_t st) {
+  if (ntasks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_area_keys, dim3((unsigned)((ntasks + 255) / 256)), dim3(256), 0, st, tasks,
+                     ntasks, keys, vals);
+  return hipGetLastError();
 }
 
 hipError_t inter_pack_ref(const PackArgs &a, hipStream_t st) {

@@ -484,6 +484,24 @@ static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &v
   a.anchor = anchor;
   a.lastcol = lastcol;
   a.coop = coop_waves(ctx->fill_coop, pl.ntasks, ctx->cus);
+  // A forward pass runs its tasks by area (padded rows x columns, its cost),
+  // largest first: the plan's order (by height, then width) leaves
+  // mid-sized tasks of short, wide pairs for the end of the launch.
+  if (!rev && pl.ntasks > 1) {
+    DevArena &A = ctx->arena;
+    const int64_t nt = pl.ntasks;
+    uint64_t *k0 = A.get<uint64_t>(nt), *k1 = A.get<uint64_t>(nt);
+    int64_t *v0 = A.get<int64_t>(nt), *v1 = A.get<int64_t>(nt);
+    if (!k0 || !k1 || !v0 || !v1) return fail(SWX_ENOMEM, "device pool exhausted (task order)");
+    HIP_TRY(inter_area_keys(pl.d_tasks, nt, k0, v0, st));
+    size_t tb = 0;
+    int64_t *order = nullptr;
+    HIP_TRY(sort_keys(nt, k0, k1, v0, v1, nullptr, &tb, &order, st, 48));
+    void *tmp = A.alloc(tb);
+    if (!tmp) return fail(SWX_ENOMEM, "device pool exhausted (task order)");
+    HIP_TRY(sort_keys(nt, k0, k1, v0, v1, tmp, &tb, &order, st, 48));
+    a.order = order;
+  }
   // A reversed pass over many tasks: its largest tasks (full rectangles of
   // weak alignments, no early exit) each take the four waves of a workgroup,
   // launched first beside the rest.  On one wave each they start first and

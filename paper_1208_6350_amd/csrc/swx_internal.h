@@ -108,6 +108,9 @@ struct InterArgs {
   int64_t qprof_row;          // bytes per symbol row
   int64_t qprof_copy;         // reversed: bytes per shifted copy
   int32_t qprof_qlen;         // the query's length
+  const int64_t *order;       // the tasks by ascending area (padded rows x columns), run from
+                              // the end (largest first); null: the plan's order (by height,
+                              // then width)
   int32_t coop;               // 1: one wave per task; 4: the four waves of a workgroup share
                               // a task, wave w taking strips w, w + 4, ... (a strip starts on
                               // a column group once the strip above has stored it)
