@@ -647,7 +647,10 @@ __global__ void k_area_keys(const InterTask *tasks, int64_t ntasks, uint64_t *ke
                             int64_t *vals) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ntasks) return;
-  keys[t] = (uint64_t)(uint32_t)tasks[t].qp * (uint64_t)(uint32_t)tasks[t].rp;
+  // in units of 256 cells, clamped to 24 bits (tasks above 2^32 cells share
+  // the top key: only the order of their launch depends on it)
+  const uint64_t k = ((uint64_t)(uint32_t)tasks[t].qp * (uint64_t)(uint32_t)tasks[t].rp) >> 8;
+  keys[t] = k < 0xFFFFFFull ? k : 0xFFFFFFull;
   vals[t] = t;
 }
 

@@ -496,10 +496,10 @@ static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &v
     HIP_TRY(inter_area_keys(pl.d_tasks, nt, k0, v0, st));
     size_t tb = 0;
     int64_t *order = nullptr;
-    HIP_TRY(sort_keys(nt, k0, k1, v0, v1, nullptr, &tb, &order, st, 48));
+    HIP_TRY(sort_keys(nt, k0, k1, v0, v1, nullptr, &tb, &order, st, 24));
     void *tmp = A.alloc(tb);
     if (!tmp) return fail(SWX_ENOMEM, "device pool exhausted (task order)");
-    HIP_TRY(sort_keys(nt, k0, k1, v0, v1, tmp, &tb, &order, st, 48));
+    HIP_TRY(sort_keys(nt, k0, k1, v0, v1, tmp, &tb, &order, st, 24));
     a.order = order;
   }
   // A reversed pass over many tasks: its largest tasks (full rectangles of
