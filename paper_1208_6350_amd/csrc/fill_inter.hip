@@ -643,13 +643,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fill_waves<
   }
 }
 
-__global__ void k_area_keys(const InterTask *tasks, int64_t ntasks, uint64_t *keys,
+__global__ void k_area_keys(const InterTask *tasks, int64_t ntasks, int32_t R, uint64_t *keys,
                             int64_t *vals) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ntasks) return;
+  const InterTask tk = tasks[t];
+  // a banded (reversed) task's strips sweep windows of R + band_q + band columns
+  uint64_t w = (uint32_t)tk.rp;
+  if (tk.band >= 0) {
+    const uint64_t win = (uint64_t)R + (uint32_t)tk.band_q + (uint32_t)tk.band + 4;
+    w = win < w ? win : w;
+  }
   // in units of 256 cells, clamped to 24 bits (tasks above 2^32 cells share
   // the top key: only the order of their launch depends on it)
-  const uint64_t k = ((uint64_t)(uint32_t)tasks[t].qp * (uint64_t)(uint32_t)tasks[t].rp) >> 8;
+  const uint64_t k = ((uint64_t)(uint32_t)tk.qp * w) >> 8;
   keys[t] = k < 0xFFFFFFull ? k : 0xFFFFFFull;
   vals[t] = t;
 }
@@ -829,11 +836,11 @@ hipError_t inter_fill(const InterArgs &a, int lane_bits, int R, hipStream_t st) 
   return hipErrorInvalidValue;
 }
 
-hipError_t inter_area_keys(const InterTask *tasks, int64_t ntasks, uint64_t *keys, int64_t *vals,
-                           hipStream_t st) {
+hipError_t inter_area_keys(const InterTask *tasks, int64_t ntasks, int32_t R, uint64_t *keys,
+                           int64_t *vals, hipStream_t st) {
   if (ntasks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_area_keys, dim3((unsigned)((ntasks + 255) / 256)), dim3(256), 0, st, tasks,
-                     ntasks, keys, vals);
+                     ntasks, R, keys, vals);
   return hipGetLastError();
 }
 

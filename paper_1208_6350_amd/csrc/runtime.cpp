@@ -484,16 +484,16 @@ static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &v
   a.anchor = anchor;
   a.lastcol = lastcol;
   a.coop = coop_waves(ctx->fill_coop, pl.ntasks, ctx->cus);
-  // A forward pass runs its tasks by area (padded rows x columns, its cost),
-  // largest first: the plan's order (by height, then width) leaves
+  // A pass runs its tasks by area (padded rows x swept columns, its cost),
+  // largest first: the plan's order (by band, height, then width) leaves
   // mid-sized tasks of short, wide pairs for the end of the launch.
-  if (!rev && pl.ntasks > 1) {
+  if (pl.ntasks > 1) {
     DevArena &A = ctx->arena;
     const int64_t nt = pl.ntasks;
     uint64_t *k0 = A.get<uint64_t>(nt), *k1 = A.get<uint64_t>(nt);
     int64_t *v0 = A.get<int64_t>(nt), *v1 = A.get<int64_t>(nt);
     if (!k0 || !k1 || !v0 || !v1) return fail(SWX_ENOMEM, "device pool exhausted (task order)");
-    HIP_TRY(inter_area_keys(pl.d_tasks, nt, k0, v0, st));
+    HIP_TRY(inter_area_keys(pl.d_tasks, nt, pl.R, k0, v0, st));
     size_t tb = 0;
     int64_t *order = nullptr;
     HIP_TRY(sort_keys(nt, k0, k1, v0, v1, nullptr, &tb, &order, st, 24));
@@ -514,7 +514,7 @@ static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &v
                              : 0;
   if (nsplit > 0 && mark_fill < 0) {
     InterArgs big = a, rest = a;
-    big.tasks = pl.d_tasks + (pl.ntasks - nsplit);   // tasks are sorted, largest last
+    big.order = a.order + (pl.ntasks - nsplit);   // the order lists the largest last
     big.ntasks = nsplit;
     big.coop = kCoopWaves;
     big.sched = 1;   // a grid of its own, all resident: no device queue

@@ -212,10 +212,11 @@ hipError_t rev_prepare(int64_t npairs, const int32_t *score, const int32_t *qend
                        hipStream_t st);
 
 hipError_t inter_fill(const InterArgs &a, int lane_bits, int R, hipStream_t st);
-// keys[t] = padded rows x columns of task t / 256, vals[t] = t (for InterArgs::order;
-// sorted on 24 key bits)
-hipError_t inter_area_keys(const InterTask *tasks, int64_t ntasks, uint64_t *keys, int64_t *vals,
-                           hipStream_t st);
+// keys[t] = padded rows x swept columns of task t (a banded task's window of R +
+// band_q + band columns per strip) / 256, vals[t] = t (for InterArgs::order; sorted on
+// 24 key bits)
+hipError_t inter_area_keys(const InterTask *tasks, int64_t ntasks, int32_t R, uint64_t *keys,
+                           int64_t *vals, hipStream_t st);
 
 // intra-sequence path (long pairs)
 struct IntraPair {         // one long pair's forward max array
