@@ -486,8 +486,10 @@ static int run_fill(swx_ctx *ctx, Plan &pl, const Scoring &sc, const PairView &v
   a.coop = coop_waves(ctx->fill_coop, pl.ntasks, ctx->cus);
   // A pass runs its tasks by area (padded rows x swept columns, its cost),
   // largest first: the plan's order (by band, height, then width) leaves
-  // mid-sized tasks of short, wide pairs for the end of the launch.
-  if (pl.ntasks > 1) {
+  // mid-sized tasks of short, wide pairs for the end of the launch.  Passes
+  // whose tasks all start at once (at most two per compute unit) keep the
+  // plan's order and save the sort's launches.
+  if (pl.ntasks > 2 * (int64_t)std::max(ctx->cus, 1)) {
     DevArena &A = ctx->arena;
     const int64_t nt = pl.ntasks;
     uint64_t *k0 = A.get<uint64_t>(nt), *k1 = A.get<uint64_t>(nt);
