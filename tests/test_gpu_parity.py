@@ -183,6 +183,17 @@ def test_column_max_forms(ctx, match, o, e, L):
     assert int(recs["score1"].max()) == match * L
 
 
+@pytest.mark.parametrize("o", [253, 254])
+def test_bias_byte_limit(ctx, o):
+    """The fills' bias becomes the gap open penalty when every biased score
+    S + o still fits a byte: with +2/-2 scores, o = 253 takes bias = o (the
+    largest biased score is exactly 255), o = 254 keeps bias = 2.  Either way
+    every result equals the oracle's."""
+    b = W.random_pairs(1300 + o, 200, (1, 90), (1, 260), o=o, e=1)
+    recs = assert_parity(ctx, b)
+    assert (recs["score1"] > 0).sum() > 100
+
+
 def test_many_tasks_ragged(ctx):
     b = W.random_pairs(404, 700, (1, 200), (1, 500))
     assert_parity(ctx, b)
