@@ -378,6 +378,20 @@ struct SideLaunch {
 };
 constexpr double kLeadShare = 0.2;
 
+// Side streams are made on first use, so a context that never needs them
+// (short pairs only) holds a single stream and a single hardware queue.
+// False when side streams are off or could not be made.
+static bool have_side_streams(swx_ctx *ctx) {
+  if (!ctx->side_streams) return false;
+  bool have = true;
+  for (int k = 0; k < swx_ctx::kAux; ++k)
+    if (!ctx->aux[k] && hipStreamCreate(&ctx->aux[k]) != hipSuccess) {
+      ctx->aux[k] = nullptr;
+      have = false;
+    }
+  return have;
+}
+
 static int run_side_by_side(swx_ctx *ctx, std::vector<SideLaunch> &ls) {
   if (ls.empty()) return SWX_OK;
   if (ls.size() == 1 || !ctx->side_streams) {
@@ -385,15 +399,7 @@ static int run_side_by_side(swx_ctx *ctx, std::vector<SideLaunch> &ls) {
     return SWX_OK;
   }
   constexpr int na = swx_ctx::kAux;
-  // side streams are made on first use, so a context that never needs them
-  // (short pairs only) holds a single stream and a single hardware queue
-  bool have = true;
-  for (int k = 0; k < na; ++k)
-    if (!ctx->aux[k] && hipStreamCreate(&ctx->aux[k]) != hipSuccess) {
-      ctx->aux[k] = nullptr;
-      have = false;
-    }
-  if (!have) {   // no side streams: one after the other on the main stream
+  if (!have_side_streams(ctx)) {   // no side streams: one after the other on the main stream
     for (auto &l : ls) HIP_TRY(l.fn(ctx->stream));
     return SWX_OK;
   }
@@ -1374,9 +1380,27 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
   Plan p16, p32;
   if ((rc = plan_pass(ctx, sc, lp.d_short, lp.nshort, qlen, rlen, nullptr, nullptr, 16, R, p16, sp)))
     return rc;
+  // With both kinds of pairs, the long pairs' pass runs on a side stream
+  // beside the batched one (each ends on its own largest tasks, the other
+  // fills the device meanwhile; the outputs are disjoint).
+  const bool beside = lp.nlong > 0 && p16.ntasks > 0 && have_side_streams(ctx);
+  if (beside) {
+    HIP_TRY(hipEventRecord(ctx->fork_ev, st));
+    HIP_TRY(hipStreamWaitEvent(ctx->aux[0], ctx->fork_ev, 0));
+  }
   if ((rc = run_fill(ctx, p16, sc, fview, false, nullptr, fout, score_bound, 1, 0, 0, sp))) return rc;
   if (lp.nlong > 0) {
-    if ((rc = run_intra_forward(ctx, sc, lp, fview, fout, err, lanebits))) return rc;
+    if (beside) {
+      {
+        StreamScope on_side(ctx, ctx->aux[0]);   // the pass's launches and waits go there
+        rc = run_intra_forward(ctx, sc, lp, fview, fout, err, lanebits);
+      }
+      if (rc) return rc;
+      HIP_TRY(hipEventRecord(ctx->join_ev[0], ctx->aux[0]));
+      HIP_TRY(hipStreamWaitEvent(st, ctx->join_ev[0], 0));
+    } else if ((rc = run_intra_forward(ctx, sc, lp, fview, fout, err, lanebits))) {
+      return rc;
+    }
     HIP_TRY(hipEventRecord(ctx->ev[2], st));
   }
 
