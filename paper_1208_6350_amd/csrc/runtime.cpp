@@ -1395,7 +1395,10 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
         StreamScope on_side(ctx, ctx->aux[0]);   // the pass's launches and waits go there
         rc = run_intra_forward(ctx, sc, lp, fview, fout, err, lanebits);
       }
-      if (rc) return rc;
+      if (rc) {   // nothing of the call may still run when it returns
+        (void)hipStreamSynchronize(ctx->aux[0]);
+        return rc;
+      }
       HIP_TRY(hipEventRecord(ctx->join_ev[0], ctx->aux[0]));
       HIP_TRY(hipStreamWaitEvent(st, ctx->join_ev[0], 0));
     } else if ((rc = run_intra_forward(ctx, sc, lp, fview, fout, err, lanebits))) {
