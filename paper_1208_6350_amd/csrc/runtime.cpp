@@ -1446,17 +1446,40 @@ static int run_pipeline(swx_ctx *ctx, const Scoring &sc, const DeviceBatch &b, u
       HIP_TRY(hipMemcpyAsync(rc2 + k, rcd[k], sizeof(int64_t), hipMemcpyDeviceToDevice, st));
     }
     if ((rc = read_i64(ctx, rc2, rcnt, 2))) return rc;
+    // as in the forward pass, the long pairs' reversed pass runs on a side
+    // stream beside the batched one (16-bit lanes)
+    const bool beside = lp.nlong > 0 && rcnt[0] > 0 && have_side_streams(ctx);
+    bool long_done = false;
     for (int k = 0; k < 2; ++k) {
       if (rcnt[k] == 0) continue;
       Plan pr;
       if ((rc = plan_pass(ctx, sc, rids[k], rcnt[k], rql, rrl, band, band_q, k == 0 ? 16 : 32, R, pr,
                           sp)))
         return rc;
+      if (k == 0 && beside) {
+        HIP_TRY(hipEventRecord(ctx->fork_ev, st));
+        HIP_TRY(hipStreamWaitEvent(ctx->aux[0], ctx->fork_ev, 0));
+      }
       if ((rc = run_fill(ctx, pr, sc, rview, true, tgt, rout, score_bound, -1, 0, 0, sp))) return rc;
+      if (k == 0 && beside) {
+        {
+          StreamScope on_side(ctx, ctx->aux[0]);
+          rc = run_intra_reverse(ctx, sc, lp, rview, score, qend, rend, band, tgt, rout, err);
+        }
+        if (rc) {   // nothing of the call may still run when it returns
+          (void)hipStreamSynchronize(ctx->aux[0]);
+          return rc;
+        }
+        HIP_TRY(hipEventRecord(ctx->join_ev[0], ctx->aux[0]));
+        long_done = true;
+      }
     }
-    if (lp.nlong > 0 &&
-        (rc = run_intra_reverse(ctx, sc, lp, rview, score, qend, rend, band, tgt, rout, err)))
+    if (long_done) {
+      HIP_TRY(hipStreamWaitEvent(st, ctx->join_ev[0], 0));
+    } else if (lp.nlong > 0 &&
+               (rc = run_intra_reverse(ctx, sc, lp, rview, score, qend, rend, band, tgt, rout, err))) {
       return rc;
+    }
     HIP_TRY(launch_begins(np, score, qend, rend, rsc, rqe, rre, qbeg, rbeg, err, st));
   }
   HIP_TRY(hipEventRecord(ctx->ev[4], st));
